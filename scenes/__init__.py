@@ -1,0 +1,525 @@
+"""Seeded synthetic scenes and photon bundles.
+
+This module is the only code shared by the FP64 reference tracer under
+``oracle/`` and the HIP library.  It builds *inputs*: volume descriptors (a
+role from the paper's set of lens / mirror / focal surface / obscuration,
+§2.1, and a shape from §2.2) and photon bundles (position plus direction,
+§2.1).  It contains no tracing arithmetic: no intersection, no interaction
+physics, no random draws made during tracing.
+
+Every stand-in telescope follows the optics the paper applies ROBAST to (§3):
+a single spherical mirror, a Davies-Cotton segmented dish, a two-mirror
+Schwarzschild-Couder telescope with segmented aspheric mirrors, and an array
+of hexagonal Bezier-profile light concentrators behind a PMMA window.  The
+paper prints no design tables, so the layouts are synthetic and every
+number below is stated where it is chosen.
+
+Conventions
+-----------
+* A volume's local frame is ``x_l = Q (x - c)`` (rows of ``Q`` are the local
+  axes in world coordinates).
+* Each face has a *front* side.  Mirrors reflect on the front, focal
+  surfaces detect on the front; both absorb on the back.  Closed solids
+  (box, cylinder) have the front outside, hexagonal cone walls inside.
+* For single-precision scenes every descriptor and ray value is rounded to
+  float32 here, so the reference tracer and the GPU read identical numbers.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Callable, Dict, List, Optional
+
+import numpy as np
+
+# ---------------------------------------------------------------- codes
+ROLE_MIRROR, ROLE_LENS, ROLE_FOCAL, ROLE_OBSCURATION = 1, 2, 3, 4
+SHAPE_PLANE, SHAPE_SPHERE, SHAPE_ASPHERE, SHAPE_CYLINDER, SHAPE_BOX, SHAPE_HEXCONE = 1, 2, 3, 4, 5, 6
+OUTLINE_NONE, OUTLINE_DISC, OUTLINE_ANNULUS, OUTLINE_RECT, OUTLINE_HEX, OUTLINE_SECTOR = 0, 1, 2, 3, 4, 5
+FATE_NONE, FATE_FOCUSED, FATE_ABSORBED, FATE_EXITED, FATE_SUSPENDED, FATE_FAILED = 0, 1, 2, 3, 4, 5
+
+VOLUME_DTYPE = np.dtype([
+    ("role", "<i4"), ("shape", "<i4"), ("outline", "<i4"),
+    ("shape_param", "<i4"), ("tilt_param", "<i4"), ("flags", "<i4"),
+    ("Q", "<f8", (9,)), ("c", "<f8", (3,)),
+    ("p", "<f8", (16,)), ("o", "<f8", (4,)),
+    ("reflectivity", "<f8"), ("n_inside", "<f8"),
+    # untilted frame, pivot and the two tilt axes (world); used only by
+    # volumes with tilt parameters: the effective frame is the untilted one
+    # rotated about `pivot` by R = Rot(e2, beta) Rot(e1, alpha).
+    ("Q0", "<f8", (9,)), ("c0", "<f8", (3,)),
+    ("pivot", "<f8", (3,)), ("e1", "<f8", (3,)), ("e2", "<f8", (3,)),
+])
+
+SEED_BASE = 150807803
+
+
+def _q(x, precision):
+    """Round to the kernel precision (float32 values kept in float64)."""
+    a = np.asarray(x, dtype=np.float64)
+    if precision == 32:
+        return a.astype(np.float32).astype(np.float64)
+    return a
+
+
+def rot(axis, angle):
+    """Rotation matrix about a unit axis (Rodrigues)."""
+    e = np.asarray(axis, dtype=np.float64)
+    e = e / np.linalg.norm(e)
+    k = np.array([[0.0, -e[2], e[1]], [e[2], 0.0, -e[0]], [-e[1], e[0], 0.0]])
+    return np.cos(angle) * np.eye(3) + np.sin(angle) * k + (1.0 - np.cos(angle)) * np.outer(e, e)
+
+
+def frame_from_axes(z_axis, x_hint=(1.0, 0.0, 0.0)):
+    """Rows (x_l, y_l, z_l): z_l along `z_axis`, x_l the projection of x_hint."""
+    z = np.asarray(z_axis, dtype=np.float64)
+    z = z / np.linalg.norm(z)
+    xh = np.asarray(x_hint, dtype=np.float64)
+    x = xh - np.dot(xh, z) * z
+    if np.linalg.norm(x) < 1e-9:
+        xh = np.array([0.0, 1.0, 0.0])
+        x = xh - np.dot(xh, z) * z
+    x = x / np.linalg.norm(x)
+    y = np.cross(z, x)
+    return np.stack([x, y, z])
+
+
+def tilted_frame(Q0, c0, pivot, e1, e2, alpha, beta):
+    """Frame of a rigid body rotated about `pivot` by Rot(e2,beta) Rot(e1,alpha)."""
+    R = rot(e2, beta) @ rot(e1, alpha)
+    Q = np.asarray(Q0) @ R.T
+    c = np.asarray(pivot) - R @ (np.asarray(pivot) - np.asarray(c0))
+    return Q, c
+
+
+def new_volume(role, shape, outline=OUTLINE_NONE, Q=None, c=(0, 0, 0), p=(), o=(),
+               reflectivity=1.0, n_inside=1.0, shape_param=-1, tilt_param=-1):
+    v = np.zeros((), dtype=VOLUME_DTYPE)
+    v["role"], v["shape"], v["outline"] = role, shape, outline
+    v["shape_param"], v["tilt_param"] = shape_param, tilt_param
+    Qm = np.eye(3) if Q is None else np.asarray(Q, dtype=np.float64)
+    v["Q"] = Qm.reshape(9)
+    v["c"] = c
+    pp = np.zeros(16); pp[:len(p)] = p
+    oo = np.zeros(4); oo[:len(o)] = o
+    v["p"], v["o"] = pp, oo
+    v["reflectivity"], v["n_inside"] = reflectivity, n_inside
+    v["Q0"], v["c0"] = Qm.reshape(9), c
+    return v
+
+
+@dataclasses.dataclass
+class Scene:
+    name: str
+    volumes: np.ndarray                 # VOLUME_DTYPE[n]
+    params: np.ndarray                  # float64[n_params] differentiable parameters
+    param_names: List[str]
+    precision: int                      # 32 or 64
+    max_events: int
+    seed: int
+    l_ref: float                        # length scale for tolerances
+    groups: np.ndarray                  # per-group field / incidence angle (rad)
+    ray_maker: Callable = None          # (scene, n_per_group, seed, groups) -> rays
+    meta: Dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def n_volumes(self):
+        return int(self.volumes.shape[0])
+
+    @property
+    def n_groups(self):
+        return int(len(self.groups))
+
+    def rays(self, n_per_group, seed=None, groups=None):
+        """Seeded photon bundle, float64 arrays already rounded to the precision."""
+        s = self.seed if seed is None else seed
+        g = np.arange(self.n_groups) if groups is None else np.asarray(groups)
+        return self.ray_maker(self, int(n_per_group), s, g)
+
+
+def _finish(name, vols, params, names, precision, max_events, seed, l_ref, groups, ray_maker, **meta):
+    arr = np.array(vols, dtype=VOLUME_DTYPE)
+    if precision == 32:
+        for f in ("Q", "c", "p", "o", "Q0", "c0", "pivot", "e1", "e2"):
+            arr[f] = _q(arr[f], 32)
+        params = _q(params, 32)
+    return Scene(name, arr, np.asarray(params, dtype=np.float64), list(names), precision,
+                 max_events, seed, l_ref, np.asarray(groups, dtype=np.float64), ray_maker, dict(meta))
+
+
+def make_rays(precision, ox, oy, oz, dx, dy, dz, group, lam=400e-9):
+    """Photon bundle from explicit arrays (rounded to the precision)."""
+    return _pack_rays(precision, ox, oy, oz, dx, dy, dz, group, lam)
+
+
+def _pack_rays(precision, ox, oy, oz, dx, dy, dz, group, lam=400e-9):
+    n = len(ox)
+    out = {k: _q(v, precision) for k, v in
+           dict(ox=ox, oy=oy, oz=oz, dx=dx, dy=dy, dz=dz).items()}
+    out["lam"] = _q(np.full(n, lam), precision)
+    out["group"] = np.asarray(group, dtype=np.uint32)
+    return out
+
+
+# ================================================================ C1
+def single_mirror(seed=SEED_BASE + 0):
+    """Spherical mirror R=16 m, 4 m aperture, focal disc r=0.5 m at z=8 m, FP64.
+
+    The focal disc faces the mirror, so rays at r < 0.5 m meet its back on the
+    way in and are absorbed (the camera shadow).  Parameter 0 is the mirror's
+    radius of curvature.
+    """
+    R = 16.0
+    vols = [
+        new_volume(ROLE_MIRROR, SHAPE_SPHERE, OUTLINE_DISC, p=[1.0 / R], o=[2.0],
+                   reflectivity=1.0, shape_param=0),
+        new_volume(ROLE_FOCAL, SHAPE_PLANE, OUTLINE_DISC,
+                   Q=np.diag([1.0, -1.0, -1.0]), c=(0.0, 0.0, 8.0), o=[0.5]),
+    ]
+
+    def rays(scene, n, s, groups):
+        rng = np.random.default_rng(s)
+        out = []
+        for g in groups:
+            u1, u2 = rng.random(n), rng.random(n)
+            r, ph = 2.0 * np.sqrt(u1), 2.0 * np.pi * u2
+            out.append((r * np.cos(ph), r * np.sin(ph), np.full(n, 20.0),
+                        np.zeros(n), np.zeros(n), -np.ones(n), np.full(n, g)))
+        cols = [np.concatenate(c) for c in zip(*out)]
+        return _pack_rays(scene.precision, *cols)
+
+    return _finish("single_mirror", vols, [R], ["R_mirror"], 64, 16, seed, 8.0, [0.0], rays,
+                   radius=R, aperture=2.0, focal_z=8.0)
+
+
+# ================================================================ C2
+def davies_cotton(seed=SEED_BASE + 1, sigma_tilt=1e-4, fields_deg=(0.0, 0.5, 1.0, 1.5, 2.0),
+                  radius_scale=None, tilts=None, precision=32):
+    """Davies-Cotton dish, f = 28 m, 198 hexagonal spherical facets.
+
+    Facet centres: hex lattice of pitch 1.55 m (4 cm gaps between 1.51 m
+    flat-to-flat facets) inside an 11.5 m circle, origin removed -> 198
+    facets on the sphere z = f - sqrt(f^2 - r^2).  Each facet is a sphere of
+    radius 2f aimed at (0, 0, 2f), with a hexagonal outline in the plane
+    normal to its axis, then tilted by two Gaussian angles (sigma 0.1 mrad)
+    about its local x then y axes.  Camera: a 3 m x 3 m focal plane at
+    z = f facing the dish, closed by 5 absorbing rectangles (1 m deep).
+    Four absorbing masts (r = 0.1 m) from the dish rim to the camera corners.
+    Parameters: 198 facet radii, then 2 tilts per facet.
+    """
+    f, pitch, rmax, half_flat = 28.0, 1.55, 11.5, 0.755
+    rng = np.random.default_rng(seed)
+    centres = []
+    for i in range(-10, 11):
+        for j in range(-10, 11):
+            x = pitch * (i + 0.5 * j)
+            y = pitch * (math.sqrt(3.0) / 2.0) * j
+            r = math.hypot(x, y)
+            if r <= rmax and (i, j) != (0, 0):
+                centres.append((r, math.atan2(y, x), x, y))
+    centres.sort()
+    assert len(centres) == 198
+    nf = len(centres)
+    if tilts is None:
+        tilts = rng.normal(0.0, sigma_tilt, size=(nf, 2))
+    radii = np.full(nf, 2.0 * f) if radius_scale is None else 2.0 * f * np.asarray(radius_scale)
+    vols, params, names = [], [], []
+    params.extend(radii); names.extend([f"facet{k}_R" for k in range(nf)])
+    for k in range(nf):
+        params.extend(tilts[k]); names.extend([f"facet{k}_tilt_x", f"facet{k}_tilt_y"])
+    for k, (r, _, x, y) in enumerate(centres):
+        cz = f - math.sqrt(f * f - r * r)
+        cen = np.array([x, y, cz])
+        axis = np.array([0.0, 0.0, 2.0 * f]) - cen
+        Q0 = frame_from_axes(axis)
+        e1, e2 = Q0[0].copy(), Q0[1].copy()
+        Q, c = tilted_frame(Q0, cen, cen, e1, e2, tilts[k][0], tilts[k][1])
+        v = new_volume(ROLE_MIRROR, SHAPE_SPHERE, OUTLINE_HEX, Q=Q, c=c, p=[1.0 / radii[k]],
+                       o=[half_flat], reflectivity=0.9, shape_param=k, tilt_param=nf + 2 * k)
+        v["Q0"], v["c0"], v["pivot"], v["e1"], v["e2"] = Q0.reshape(9), cen, cen, e1, e2
+        vols.append(v)
+    flip = np.diag([1.0, -1.0, -1.0])
+    # camera: focal plane (front towards the dish) + absorbing walls and lid
+    vols.append(new_volume(ROLE_FOCAL, SHAPE_PLANE, OUTLINE_RECT, Q=flip, c=(0, 0, f), o=[1.5, 1.5]))
+    vols.append(new_volume(ROLE_OBSCURATION, SHAPE_PLANE, OUTLINE_RECT, c=(0, 0, f + 1.0), o=[1.5, 1.5]))
+    for sx in (1.0, -1.0):
+        Q = frame_from_axes((sx, 0, 0), x_hint=(0, 0, 1))
+        vols.append(new_volume(ROLE_OBSCURATION, SHAPE_PLANE, OUTLINE_RECT, Q=Q,
+                               c=(1.5 * sx, 0, f + 0.5), o=[0.5, 1.5]))
+    for sy in (1.0, -1.0):
+        Q = frame_from_axes((0, sy, 0), x_hint=(0, 0, 1))
+        vols.append(new_volume(ROLE_OBSCURATION, SHAPE_PLANE, OUTLINE_RECT, Q=Q,
+                               c=(0, 1.5 * sy, f + 0.5), o=[0.5, 1.5]))
+    zrim = f - math.sqrt(f * f - rmax * rmax)
+    for kk in range(4):
+        ph = math.radians(45.0 + 90.0 * kk)
+        base = np.array([rmax * math.cos(ph), rmax * math.sin(ph), zrim])
+        top = np.array([1.5 * np.sign(math.cos(ph)), 1.5 * np.sign(math.sin(ph)), f])
+        ax = top - base
+        vols.append(new_volume(ROLE_OBSCURATION, SHAPE_CYLINDER, Q=frame_from_axes(ax), c=base,
+                               p=[0.1, float(np.linalg.norm(ax))]))
+    groups = np.radians(np.asarray(fields_deg, dtype=np.float64))
+
+    def rays(scene, n, s, gsel):
+        rng2 = np.random.default_rng(s)
+        out = []
+        for g in gsel:
+            th = scene.groups[g]
+            d = np.array([math.sin(th), 0.0, -math.cos(th)])
+            e1v = np.array([math.cos(th), 0.0, math.sin(th)])
+            e2v = np.array([0.0, 1.0, 0.0])
+            u1, u2 = rng2.random(n), rng2.random(n)
+            r, ph = 12.0 * np.sqrt(u1), 2.0 * np.pi * u2
+            px, py = r * np.cos(ph), r * np.sin(ph)
+            o = -40.0 * d[None, :] + px[:, None] * e1v[None, :] + py[:, None] * e2v[None, :]
+            out.append((o[:, 0], o[:, 1], o[:, 2], np.full(n, d[0]), np.full(n, d[1]),
+                        np.full(n, d[2]), np.full(n, g)))
+        cols = [np.concatenate(c) for c in zip(*out)]
+        return _pack_rays(scene.precision, *cols)
+
+    return _finish("davies_cotton", vols, params, names, precision, 16, seed, 28.0, groups, rays,
+                   n_facets=nf, focal_length=f)
+
+
+# ================================================================ C3
+SC_PRIMARY = dict(R=38.0958, k=-1.4980, rn=4.83, r_in=2.19, r_out=4.83, z=0.0)
+SC_SECONDARY = dict(R=8.8680, k=-3.1648, rn=2.7, r_in=0.0, r_out=2.7, z=8.4)
+SC_FOCAL_Z = 5.3257
+
+
+def conic_taylor(R, k, rn, n=8):
+    """Coefficients b_i of z = sum b_i u^i, u = (r/rn)^2, for the conic (R, k)."""
+    c = 1.0 / R
+    return np.array([math.comb(2 * i, i) / (4.0 ** i * (2 * i - 1)) * (1.0 + k) ** (i - 1)
+                     * c ** (2 * i - 1) * rn ** (2 * i) for i in range(1, n + 1)])
+
+
+def _ring_panels(r_in, r_out, r_split, n_inner, n_outer):
+    out = []
+    for (a, b, n) in ((r_in, r_split, n_inner), (r_split, r_out, n_outer)):
+        dphi = 2.0 * math.pi / n
+        for s in range(n):
+            out.append((a, b, s * dphi, (s + 1) * dphi))
+    return out
+
+
+def schwarzschild_couder(seed=SEED_BASE + 2, sigma_tilt=5e-5, n_fields=16, max_field_deg=4.0,
+                         coeff_scale=None, tilts=None, precision=32):
+    """Two-mirror Schwarzschild-Couder telescope with segmented aspheric mirrors.
+
+    Sag z = sum_{i=1..8} b_i u^i with u = (r/rn)^2 (normalised form; the
+    monomial a_i = b_i / rn^(2i) would span 1e-2 .. 1e-28).  Baseline b_i are
+    the Taylor coefficients of the conics (R1 = 38.0958 m, k1 = -1.4980) and
+    (R2 = 8.8680 m, k2 = -3.1648), primary vertex at z = 0 concave up,
+    secondary vertex at z = 8.4 m concave down.  Panels: primary 16 + 32
+    (r 2.19-3.3127-4.83 m), secondary 8 + 16 (r 0-1.5588-2.7 m), each the
+    parent surface restricted to its (r, phi) sector and rotated about its
+    sector-centroid point by two Gaussian angles (sigma 0.05 mrad) about the
+    radial and tangential axes.  Focal surface: a spherical cap of radius
+    1 m, vertex at z = 5.3257 m, centre of curvature below, aperture 0.6 m.
+    Parameters: 8 primary b_i, 8 secondary b_i, 2 tilts per panel (144).
+    """
+    rng = np.random.default_rng(seed)
+    pri, sec = SC_PRIMARY, SC_SECONDARY
+    bp = conic_taylor(pri["R"], pri["k"], pri["rn"])
+    bs = conic_taylor(sec["R"], sec["k"], sec["rn"])
+    if coeff_scale is not None:
+        cs = np.asarray(coeff_scale)
+        bp, bs = bp * cs[:8], bs * cs[8:]
+    pan_p = _ring_panels(pri["r_in"], pri["r_out"], 3.3127, 16, 32)
+    pan_s = _ring_panels(sec["r_in"], sec["r_out"], 1.5588, 8, 16)
+    npan = len(pan_p) + len(pan_s)
+    if tilts is None:
+        tilts = rng.normal(0.0, sigma_tilt, size=(npan, 2))
+    params = list(bp) + list(bs)
+    names = [f"primary_b{i}" for i in range(1, 9)] + [f"secondary_b{i}" for i in range(1, 9)]
+    for k in range(npan):
+        params.extend(tilts[k]); names.extend([f"panel{k}_tilt_r", f"panel{k}_tilt_t"])
+    vols = []
+    k = 0
+    for mirror, pans, b, off, Q0 in ((pri, pan_p, bp, 0, np.eye(3)),
+                                     (sec, pan_s, bs, 8, np.diag([1.0, -1.0, -1.0]))):
+        c0 = np.array([0.0, 0.0, mirror["z"]])
+        for (ra, rb, pa, pb) in pans:
+            phm = 0.5 * (pa + pb)
+            half = 0.5 * (pb - pa)
+            rc = (2.0 / 3.0) * (rb ** 3 - ra ** 3) / (rb ** 2 - ra ** 2) * math.sin(half) / half
+            u = (rc / mirror["rn"]) ** 2
+            zc = sum(b[i] * u ** (i + 1) for i in range(8))
+            piv_l = np.array([rc * math.cos(phm), rc * math.sin(phm), zc])
+            pivot = c0 + Q0.T @ piv_l
+            e1 = Q0.T @ np.array([math.cos(phm), math.sin(phm), 0.0])
+            e2 = Q0.T @ np.array([-math.sin(phm), math.cos(phm), 0.0])
+            Q, c = tilted_frame(Q0, c0, pivot, e1, e2, tilts[k][0], tilts[k][1])
+            v = new_volume(ROLE_MIRROR, SHAPE_ASPHERE, OUTLINE_SECTOR, Q=Q, c=c,
+                           p=[mirror["rn"]] + list(b), o=[ra, rb, pa, pb], reflectivity=1.0,
+                           shape_param=off, tilt_param=16 + 2 * k)
+            v["Q0"], v["c0"], v["pivot"], v["e1"], v["e2"] = Q0.reshape(9), c0, pivot, e1, e2
+            vols.append(v)
+            k += 1
+    vols.append(new_volume(ROLE_FOCAL, SHAPE_SPHERE, OUTLINE_DISC, c=(0.0, 0.0, SC_FOCAL_Z),
+                           p=[-1.0], o=[0.6]))
+    groups = np.radians(np.linspace(0.0, max_field_deg, n_fields))
+
+    def rays(scene, n, s, gsel):
+        rng2 = np.random.default_rng(s)
+        out = []
+        for g in gsel:
+            th = scene.groups[g]
+            d = np.array([math.sin(th), 0.0, -math.cos(th)])
+            u1, u2 = rng2.random(n), rng2.random(n)
+            r = np.sqrt(pri["r_in"] ** 2 + u1 * (pri["r_out"] ** 2 - pri["r_in"] ** 2))
+            ph = 2.0 * np.pi * u2
+            o = np.stack([r * np.cos(ph), r * np.sin(ph), np.zeros(n)], 1) - 12.0 * d[None, :]
+            out.append((o[:, 0], o[:, 1], o[:, 2], np.full(n, d[0]), np.full(n, d[1]),
+                        np.full(n, d[2]), np.full(n, g)))
+        cols = [np.concatenate(c) for c in zip(*out)]
+        return _pack_rays(scene.precision, *cols)
+
+    return _finish("schwarzschild_couder", vols, params, names, precision, 16, seed, 5.6, groups, rays,
+                   n_panels=npan, focal_z=SC_FOCAL_Z)
+
+
+# ================================================================ C4
+def cpc_bezier(a=25.0, theta_c_deg=30.0):
+    """Cubic Bezier control points of the compound parabolic concentrator.
+
+    The CPC wall is a parabola with focus at the opposite exit edge and axis
+    tilted by the cut-off angle; as a quadratic Bezier its control points are
+    the exit edge, the intersection of the end tangents and the entrance
+    edge; degree elevation gives the cubic.  Returns [(rho, z)] x 4 (mm).
+    """
+    th = math.radians(theta_c_deg)
+    ap = a * math.sin(th)                       # exit half-width
+    L = (a + ap) / math.tan(th)                 # length
+    # tangent at the exit edge: direction of the parabola at (ap, 0)
+    # parabola in the (rho, z) plane, focus F = (-ap, 0), axis direction
+    # w = (sin th, -cos th) (pointing from the vertex away from the opening)
+    P0 = np.array([ap, 0.0]); P2 = np.array([a, L])
+    F = np.array([-ap, 0.0]); w = np.array([math.sin(th), -math.cos(th)])
+
+    def tangent(P):
+        # for a parabola the tangent bisects the focal radius and the axis line
+        r = (P - F) / np.linalg.norm(P - F)
+        t = r - w
+        return t / np.linalg.norm(t)
+    t0, t2 = tangent(P0), tangent(P2)
+    # P1 = P0 + s t0 = P2 + q t2
+    A = np.stack([t0, -t2], 1)
+    s, _ = np.linalg.solve(A, P2 - P0)
+    P1 = P0 + s * t0
+    Q1 = P0 + 2.0 / 3.0 * (P1 - P0)
+    Q2 = P2 + 2.0 / 3.0 * (P1 - P2)
+    return [tuple(P0), tuple(Q1), tuple(Q2), tuple(P2)], L
+
+
+def hex_concentrator(seed=SEED_BASE + 3, n_rows=8, n_cols=8, reflectivity=0.92,
+                     angles_deg=None, control=None, window=True, precision=32):
+    """8 x 8 array of hexagonal cones with a cubic Bezier CPC profile (mm).
+
+    Cone cross-section at height z is a regular hexagon of inradius rho(z):
+    12.5 mm at the exit (z = 0), 25 mm at the entrance (z = L = 64.95 mm);
+    the baseline profile is the degree-elevated ideal CPC for a 30 deg
+    cut-off.  Walls are zero-thickness mirrors (front inside, R = 0.92).
+    Cones sit on a hex lattice of 50 mm pitch, alternate rows offset 25 mm.
+    A 2 mm PMMA window (n = 1.49) with its bottom 1 mm above the entrance
+    covers the array; each exit hexagon is a focal surface and the rest of
+    the z = 0 plane absorbs.  Parameters: the interior control points
+    (rho1, z1, rho2, z2), shared by every cone.
+    """
+    ctrl, L = cpc_bezier()
+    if control is not None:
+        c4 = list(control)
+        ctrl = [ctrl[0], (c4[0], c4[1]), (c4[2], c4[3]), ctrl[3]]
+    pitch = 50.0
+    row = pitch * math.sqrt(3.0) / 2.0
+    cells = []
+    for j in range(n_rows):
+        for i in range(n_cols):
+            cells.append((pitch * i + 0.5 * pitch * (j % 2), row * j))
+    cells = np.array(cells)
+    cells -= cells.mean(axis=0)
+    vols = []
+    flat_ctrl = [v for pt in ctrl for v in pt]
+    for (x, y) in cells:
+        vols.append(new_volume(ROLE_MIRROR, SHAPE_HEXCONE, c=(x, y, 0.0), p=flat_ctrl,
+                               reflectivity=reflectivity, shape_param=0))
+    for (x, y) in cells:
+        vols.append(new_volume(ROLE_FOCAL, SHAPE_PLANE, OUTLINE_HEX, c=(x, y, 0.0), o=[ctrl[0][0]]))
+    span = float(np.abs(cells).max()) + 2 * pitch
+    vols.append(new_volume(ROLE_OBSCURATION, SHAPE_PLANE, OUTLINE_RECT, c=(0.0, 0.0, 0.0),
+                           o=[span, span]))
+    if window:
+        vols.append(new_volume(ROLE_LENS, SHAPE_BOX, c=(0.0, 0.0, L + 2.0), p=[span, span, 1.0],
+                               n_inside=1.49))
+    params = [ctrl[1][0], ctrl[1][1], ctrl[2][0], ctrl[2][1]]
+    names = ["rho1", "z1", "rho2", "z2"]
+    if angles_deg is None:
+        angles_deg = np.arange(0.0, 45.0 + 1e-9, 0.5)
+    groups = np.radians(np.asarray(angles_deg, dtype=np.float64))
+    z_launch = L + 8.0
+    a_in = ctrl[3][0]
+
+    def rays(scene, n, s, gsel, phi_fixed=None):
+        rng2 = np.random.default_rng(s)
+        out = []
+        for g in gsel:
+            th = scene.groups[g]
+            k = rng2.integers(0, len(cells), size=n)
+            # uniform point in a hexagon of inradius a_in (flats normal to x)
+            pts = np.empty((n, 2)); filled = 0
+            R = a_in * 2.0 / math.sqrt(3.0)
+            while filled < n:
+                m = 2 * (n - filled) + 16
+                cand = (rng2.random((m, 2)) * 2.0 - 1.0) * np.array([a_in, R])
+                ok = np.ones(m, bool)
+                for ang in (0.0, math.pi / 3.0, 2.0 * math.pi / 3.0):
+                    ok &= np.abs(cand[:, 0] * math.cos(ang) + cand[:, 1] * math.sin(ang)) <= a_in
+                cand = cand[ok][: n - filled]
+                pts[filled:filled + len(cand)] = cand
+                filled += len(cand)
+            ph = rng2.random(n) * 2.0 * np.pi if phi_fixed is None else np.full(n, phi_fixed)
+            d = np.stack([math.sin(th) * np.cos(ph), math.sin(th) * np.sin(ph),
+                          np.full(n, -math.cos(th))], 1)
+            P = np.stack([cells[k, 0] + pts[:, 0], cells[k, 1] + pts[:, 1], np.full(n, L)], 1)
+            sdist = (z_launch - L) / (-d[:, 2])
+            o = P - sdist[:, None] * d
+            out.append((o[:, 0], o[:, 1], o[:, 2], d[:, 0], d[:, 1], d[:, 2], np.full(n, g)))
+        cols = [np.concatenate(c) for c in zip(*out)]
+        return _pack_rays(scene.precision, *cols)
+
+    return _finish("hex_concentrator", vols, params, names, precision, 32, seed, L, groups, rays,
+                   n_cones=len(cells), length=L, control=ctrl, cells=cells, z_launch=z_launch)
+
+
+# ================================================================ small test scenes
+def empty_scene(precision=64):
+    """No volumes: every photon leaves the scene."""
+    def rays(scene, n, s, groups):
+        rng = np.random.default_rng(s)
+        v = rng.normal(size=(n, 3)); v /= np.linalg.norm(v, axis=1)[:, None]
+        return _pack_rays(scene.precision, *rng.normal(size=(3, n)), v[:, 0], v[:, 1], v[:, 2],
+                          np.zeros(n))
+    return Scene("empty", np.zeros(0, dtype=VOLUME_DTYPE), np.zeros(0), [], precision, 16,
+                 SEED_BASE, 1.0, np.array([0.0]), rays)
+
+
+def window_slab(n_index=1.49, thickness=2.0, precision=64, seed=SEED_BASE + 7):
+    """A lone lens slab with normal-incidence photons (Fresnel statistics)."""
+    vols = [new_volume(ROLE_LENS, SHAPE_BOX, c=(0, 0, 0), p=[100.0, 100.0, thickness / 2],
+                       n_inside=n_index)]
+
+    def rays(scene, n, s, groups):
+        rng = np.random.default_rng(s)
+        x, y = rng.uniform(-10, 10, size=(2, n))
+        return _pack_rays(scene.precision, x, y, np.full(n, 10.0), np.zeros(n), np.zeros(n),
+                          -np.ones(n), np.zeros(n))
+    return _finish("window_slab", vols, [], [], precision, 64, seed, thickness, [0.0], rays)
+
+
+ALL = {
+    "single_mirror": single_mirror,
+    "davies_cotton": davies_cotton,
+    "schwarzschild_couder": schwarzschild_couder,
+    "hex_concentrator": hex_concentrator,
+}
