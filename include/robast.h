@@ -1,0 +1,186 @@
+/* robast.h -- C ABI of the MI355X non-sequential photon tracer.
+ *
+ * The interface follows the paper's statement of the problem (Okumura, Noda,
+ * Rulten, ROBAST, ICRC 2015):
+ *   - a scene is a set of volumes, each with an optical role -- lens, mirror,
+ *     focal surface, or absorbing obscuration (§2.1) -- and a shape: plane,
+ *     sphere cap, cylinder, box, aspheric disc, or a hexagonal cone whose wall
+ *     profile is a Bezier curve (the Winston / Okumura cones, §2.2);
+ *   - photons are given by position and momentum direction (§2.1);
+ *   - the trace is non-sequential: no surface order is fixed in advance, so
+ *     multiple reflections on segmented mirrors and inside concentrators
+ *     arise by themselves (§1, §2.1, §3);
+ *   - each photon leaves with an exit state: detected on a focal surface,
+ *     absorbed, or escaped, plus its exit position and direction.
+ * On top of the paper's forward trace the library returns gradients of the
+ * focal-plane figures of §3 (spot RMS per field angle, cosine-weighted
+ * collection per incidence angle) with respect to the scene's parameters,
+ * by reverse mode along each photon's fixed surface sequence.
+ *
+ * Conventions
+ *   - Every function returns robast_status (0 = OK, < 0 = error) and never
+ *     throws.  robast_last_error() gives a thread-local message.
+ *   - Host pointers are marked [host]; device pointers [device].  The caller
+ *     allocates and owns every ray, hit, sum and gradient buffer; the library
+ *     never frees them.  A scene owns its device tables until
+ *     robast_destroy_scene.
+ *   - Calls that take a stream validate on the host, enqueue on that HIP
+ *     stream (NULL = the null stream) and return without waiting.  A device
+ *     fault surfaces at the caller's next synchronisation.
+ *   - Floating-point ray/hit arrays are float (precision 32) or double
+ *     (precision 64), matching the scene.
+ */
+#ifndef ROBAST_H
+#define ROBAST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ROBAST_OK = 0,
+  ROBAST_EINVAL = -1,       /* invalid argument; nothing was launched */
+  ROBAST_ENOMEM = -2,       /* device allocation failed */
+  ROBAST_EHIP = -3,         /* a HIP runtime call failed (message in robast_last_error) */
+  ROBAST_EUNSUPPORTED = -4, /* valid request with no kernel for it */
+  ROBAST_EMISMATCH = -5     /* inconsistent inputs (e.g. buffer sizes of two calls) */
+} robast_status;
+
+/* optical roles (§2.1) */
+enum { ROBAST_MIRROR = 1, ROBAST_LENS = 2, ROBAST_FOCAL = 3, ROBAST_OBSCURATION = 4 };
+
+/* shapes (§2.2).  Each face has a front side: plane / sphere / asphere front
+ * is local +z; cylinder and box front is outside; cone walls front inside.
+ *   PLANE    z_l = 0, bounded by the outline
+ *   SPHERE   z_l = c r^2 / (1 + sqrt(1 - c^2 r^2)), p[0] = c = 1/R (signed)
+ *   ASPHERE  z_l = sum_{i=1..8} b_i u^i, u = r^2/rn^2; p[0] = rn, p[1..8] = b_i
+ *   CYLINDER x_l^2 + y_l^2 = p[0]^2, 0 <= z_l <= p[1] (lateral surface)
+ *   BOX      |x_l| <= p[0], |y_l| <= p[1], |z_l| <= p[2]; six faces,
+ *            face k = 2*axis + (negative side)
+ *   HEXCONE  six walls k = 0..5 with outward direction n_k = (cos k60, sin k60):
+ *            {rho(s) n_k + v m_k + z(s) e_z : 0<=s<=1, |v| <= rho(s)/sqrt(3)},
+ *            (rho, z)(s) the cubic Bezier with control points
+ *            p[0..7] = rho0 z0 rho1 z1 rho2 z2 rho3 z3                       */
+enum { ROBAST_PLANE = 1, ROBAST_SPHERE = 2, ROBAST_ASPHERE = 3, ROBAST_CYLINDER = 4,
+       ROBAST_BOX = 5, ROBAST_HEXCONE = 6 };
+
+/* outlines of plane / sphere / asphere faces, on local (x, y):
+ *   DISC r <= o[0];  ANNULUS o[0] <= r <= o[1];  RECT |x| <= o[0], |y| <= o[1];
+ *   HEX |x cos a + y sin a| <= o[0] for a = 0, 60, 120 deg;
+ *   SECTOR o[0] <= r <= o[1], o[2] <= phi <= o[3] (o[3] - o[2] <= 2 pi)       */
+enum { ROBAST_OUTLINE_NONE = 0, ROBAST_DISC = 1, ROBAST_ANNULUS = 2, ROBAST_RECT = 3,
+       ROBAST_HEX = 4, ROBAST_SECTOR = 5 };
+
+/* photon fates */
+enum { ROBAST_FOCUSED = 1, ROBAST_ABSORBED = 2, ROBAST_EXITED = 3, ROBAST_SUSPENDED = 4,
+       ROBAST_FAILED = 5 };
+
+/* One volume.  Local frame x_l = Q (x - c), Q row-major.  Differentiable
+ * parameters: shape_param indexes the first of the shape's parameters in the
+ * scene's parameter vector (SPHERE: radius R; ASPHERE: b_1..b_8; HEXCONE:
+ * rho1 z1 rho2 z2), tilt_param the two tilt angles (alpha, beta) of a body
+ * whose frame is the untilted (Q0, c0) rotated about `pivot` by
+ * Rot(e2, beta) Rot(e1, alpha); -1 = none.  Layout: 6 int32 then 55 double
+ * (464 bytes), identical to a packed C struct on x86-64. */
+typedef struct {
+  int32_t role, shape, outline, shape_param, tilt_param, flags;
+  double Q[9], c[3];
+  double p[16], o[4];
+  double reflectivity; /* mirrors: absorb iff Philox word >= floor(R 2^32) */
+  double n_inside;     /* lenses: refractive index inside, 1 outside */
+  double Q0[9], c0[3], pivot[3], e1[3], e2[3];
+} robast_volume_desc;
+
+typedef struct {
+  const robast_volume_desc* volumes; /* [host] n_volumes entries */
+  int32_t n_volumes;                 /* 0 .. 65535 */
+  int32_t precision;                 /* 32 (float) or 64 (double) */
+  int32_t max_events;                /* 1 .. 255; photons still alive after it: SUSPENDED */
+  int32_t n_groups;                  /* 1 .. 4096 photon groups (field angles) */
+  uint64_t seed;                     /* Philox4x32-10 key */
+  double l_ref;                      /* scene length scale (> 0), sets self-hit epsilons */
+} robast_scene_desc;
+
+/* Structure-of-arrays photon bundle.  Photon i has id id_base + i: its
+ * random draws are Philox4x32-10 with key = seed and counter =
+ * (id lo, id hi, event >> 2, 1), word event & 3 -- so a photon's result never
+ * depends on launch shape or on which other photons share the launch. */
+typedef struct {
+  const void *ox, *oy, *oz, *dx, *dy, *dz; /* [device] n each, float or double */
+  const uint32_t* group;                   /* [device] n, < n_groups; NULL = all group 0 */
+  uint64_t id_base;
+} robast_rays;
+
+/* Per-photon exit records; any pointer may be NULL (not written).
+ * group_sums [device] n_groups * ROBAST_GROUP_STRIDE doubles, ACCUMULATED
+ * (+=): per group {launched, focused, sum x, sum y, sum x^2, sum y^2,
+ * sum |u_z|, 0} over FOCUSED photons (x, y world focal-surface coordinates,
+ * u_z the exit direction's z component). */
+#define ROBAST_GROUP_STRIDE 8
+typedef struct {
+  uint8_t* fate;     /* [device] n */
+  uint8_t* n_events; /* [device] n, interactions including the terminal one */
+  int32_t* last_vol; /* [device] n, volume of the last interaction or -1 */
+  void *x, *y, *z;   /* [device] exit position (focal hit, absorption point, last point) */
+  void *ux, *uy, *uz;/* [device] exit direction */
+  void* opl;         /* [device] optical path length sum n_medium * segment */
+  uint64_t* seq_hash;/* [device] hash of the (volume, face, side) sequence: h0 =
+                        0xcbf29ce484222325, h = (h ^ (vol<<4 | face<<1 | back)) *
+                        0x100000001b3 per interaction */
+  double* group_sums;
+} robast_hits;
+
+/* Figures per group (§3: spot diagrams, collection efficiency), 8 doubles:
+ * {launched, focused, centroid x, centroid y, RMS spot radius, efficiency
+ *  focused/launched, weighted collection sum|u_z|/launched, 0}. */
+#define ROBAST_FIGURE_STRIDE 8
+
+typedef struct robast_scene robast_scene;
+
+/* Validate the descriptors, compile the device tables (volume records, an XY
+ * uniform grid with per-cell volume lists for the non-sequential candidate
+ * search) and upload them.  `params` [host] n_params values of the
+ * differentiable parameters (may be NULL if n_params == 0); every
+ * shape_param/tilt_param index must lie inside it.  EINVAL on: NULL desc or
+ * out, n_volumes out of range, unknown role / shape / outline, non-finite
+ * values, non-positive sizes, a sphere whose aperture passes its equator,
+ * precision not 32/64, max_events outside 1..255, n_groups outside 1..4096,
+ * l_ref <= 0, a parameter index out of range.  Synchronous. */
+int robast_build_scene(const robast_scene_desc* desc, const double* params, int64_t n_params,
+                       robast_scene** out);
+
+/* Trace photons [0, n).  rays/hits as above; n == 0 is a no-op.  EINVAL on
+ * NULL scene/rays/hits, n < 0, a NULL ray coordinate array. */
+int robast_trace(robast_scene* scene, const robast_rays* rays, int64_t n, const robast_hits* hits,
+                 uint32_t flags, void* hip_stream);
+
+/* Figures from accumulated group sums (device -> device, n_groups * 8 doubles). */
+int robast_figures(robast_scene* scene, const double* d_group_sums, double* d_figures,
+                   void* hip_stream);
+
+/* Reverse mode along each photon's fixed surface sequence (pathwise
+ * gradient; fates and sequences are re-derived with the same draws, so they
+ * equal the forward ones).  The objective is
+ *   L = sum_g ( w_rms[g] * RMS_g + w_eff[g] * effw_g )
+ * with d_cot [device] n_groups * 2 doubles {w_rms, w_eff} per group and
+ * d_group_sums [device] the forward sums of the same photons.
+ * d_grad [device] n_params doubles, ACCUMULATED (+=). */
+int robast_trace_backward(robast_scene* scene, const robast_rays* rays, int64_t n,
+                          const double* d_group_sums, const double* d_cot, double* d_grad,
+                          void* hip_stream);
+
+/* Replace the differentiable parameters (host vector, n_params) and rebuild
+ * the affected device records.  Synchronous. */
+int robast_update_params(robast_scene* scene, const double* params, int64_t n_params);
+
+void robast_destroy_scene(robast_scene* scene);
+const char* robast_status_string(int status);
+const char* robast_last_error(void);
+int robast_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ROBAST_H */

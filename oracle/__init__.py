@@ -111,7 +111,8 @@ def trace(scene, rays, id_base=0, log=False, nthreads=None, culled=True, volumes
     lg = None
     if log:
         lg = dict(vol=np.full((n, me), -1, np.int32), face=np.full((n, me), -1, np.int32),
-                  act=np.full((n, me), -1, np.int32), t=np.zeros((n, me)), s=np.zeros((n, me)))
+                  act=np.full((n, me), -1, np.int32), t=np.zeros((n, me)), s=np.zeros((n, me)),
+                  diag=np.full((n, me, 5), np.inf))
     nth = nthreads or os.cpu_count() or 1
     rc = L.oracle_trace(ctypes.c_int(len(vols)), _p(vi), _p(vd), ctypes.c_int(me),
                         ctypes.c_uint64(scene.seed), ctypes.c_double(scene.l_ref),
@@ -120,13 +121,29 @@ def trace(scene, rays, id_base=0, log=False, nthreads=None, culled=True, volumes
                         _p(out["dir"]), _p(out["opl"]), _p(out["seq_hash"]),
                         _p(lg["vol"]) if lg else None, _p(lg["face"]) if lg else None,
                         _p(lg["act"]) if lg else None, _p(lg["t"]) if lg else None,
-                        _p(lg["s"]) if lg else None, ctypes.c_int(nth), ctypes.c_int(1 if culled else 0))
+                        _p(lg["s"]) if lg else None, _p(lg["diag"]) if lg else None,
+                        ctypes.c_int(nth), ctypes.c_int(1 if culled else 0))
     if rc != 0:
         raise ValueError("oracle_trace rejected its input")
     out["group"] = np.asarray(rays["group"])
     if log:
         out["log"] = lg
     return out
+
+
+def grazing(rec, l_ref, tol_len=1e-5, tol_cos=1e-4, tol_draw=1e-5):
+    """Photons whose oracle path is ill-conditioned: at some interaction two
+    candidate surfaces lie within tol_len * l_ref, the hit or a rejected root
+    nearer than it lies within tol_len * l_ref of a face boundary, the ray
+    meets the surface with |d . n| < tol_cos, or the random draw lies within
+    tol_draw of its threshold.  Needs a trace with log=True."""
+    dg = rec["log"]["diag"]
+    ne = rec["n_events"].astype(np.int64)
+    live = np.arange(dg.shape[1])[None, :] <= np.minimum(ne, dg.shape[1] - 1)[:, None]
+    L = tol_len * l_ref
+    bad = ((dg[:, :, 0] < L) | (dg[:, :, 1] < L) | (dg[:, :, 2] < L) | (dg[:, :, 3] < tol_cos) |
+           (dg[:, :, 4] < tol_draw)) & live
+    return bad.any(axis=1)
 
 
 def timed_trace(scene, rays, nthreads=None, **kw):

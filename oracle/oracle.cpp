@@ -288,9 +288,42 @@ double outline_radius(const Vol& v) {
 }
 
 // ------------------------------------------------------------------ root enumeration (double)
-struct Hit { double t; int face; double s; };
+// A root of a face: t, face, curve parameter, whether it lies inside the
+// face bounds, and its distance to the nearest face boundary (diagnostic).
+struct Hit { double t; int face; double s; bool ok; double bd; };
 
-void push_root(std::vector<Hit>& out, double t, int face, double s = 0.0) { out.push_back({t, face, s}); }
+void push_root(std::vector<Hit>& out, double t, int face, double s, bool ok, double bd) {
+  out.push_back({t, face, s, ok, bd});
+}
+
+// unsigned distance from (x, y) to the boundary of the outline (diagnostic only)
+double outline_bdist(const Vol& v, double x, double y) {
+  const double* o = v.o;
+  double r = std::hypot(x, y);
+  switch (v.outline) {
+    case OL_DISC: return std::fabs(r - o[0]);
+    case OL_ANNULUS: return std::min(std::fabs(r - o[0]), std::fabs(r - o[1]));
+    case OL_RECT: {
+      double ex = std::fabs(x) - o[0], ey = std::fabs(y) - o[1];
+      if (ex <= 0 && ey <= 0) return std::min(-ex, -ey);
+      return std::hypot(std::max(ex, 0.0), std::max(ey, 0.0));
+    }
+    case OL_HEX: {
+      double m = -1e300;
+      for (int k = 0; k < 3; ++k) {
+        double a = k * PI / 3.0;
+        m = std::max(m, std::fabs(x * std::cos(a) + y * std::sin(a)) - o[0]);
+      }
+      return std::fabs(m);
+    }
+    case OL_SECTOR: {
+      double d = std::min(std::fabs(r - o[0]), std::fabs(r - o[1]));
+      for (int e = 2; e <= 3; ++e) d = std::min(d, std::fabs(x * std::sin(o[e]) - y * std::cos(o[e])));
+      return d;
+    }
+  }
+  return 1e300;
+}
 
 void quad_roots(double a, double b, double c, double r[2], int& n) {
   n = 0;
@@ -370,7 +403,7 @@ void volume_hits(const Vol& v, V3<double> ow, V3<double> dw, double l_ref, std::
       if (d.z == 0.0) return;
       double t = -o.z / d.z;
       V3<double> x = o + t * d;
-      if (inside_outline(v, x.x, x.y)) push_root(out, t, 0);
+      push_root(out, t, 0, 0.0, inside_outline(v, x.x, x.y), outline_bdist(v, x.x, x.y));
       return;
     }
     case SH_SPHERE: {
@@ -381,7 +414,7 @@ void volume_hits(const Vol& v, V3<double> ow, V3<double> dw, double l_ref, std::
       for (int i = 0; i < n; ++i) {
         V3<double> x = o + r[i] * d;
         if (1.0 - cv * x.z < 0.0) continue;            // far hemisphere: not the cap
-        if (inside_outline(v, x.x, x.y)) push_root(out, r[i], 0);
+        push_root(out, r[i], 0, 0.0, inside_outline(v, x.x, x.y), outline_bdist(v, x.x, x.y));
       }
       return;
     }
@@ -411,7 +444,7 @@ void volume_hits(const Vol& v, V3<double> ow, V3<double> dw, double l_ref, std::
       if (ta < tb) asphere_roots(p, o.x, o.y, o.z, d.x, d.y, d.z, ta, tb, 1e-9 * l_ref, roots);
       for (double t : roots) {
         V3<double> x = o + t * d;
-        if (inside_outline(v, x.x, x.y)) push_root(out, t, 0);
+        push_root(out, t, 0, 0.0, inside_outline(v, x.x, x.y), outline_bdist(v, x.x, x.y));
       }
       return;
     }
@@ -422,7 +455,7 @@ void volume_hits(const Vol& v, V3<double> ow, V3<double> dw, double l_ref, std::
       quad_roots(a, b, c, r, n);
       for (int i = 0; i < n; ++i) {
         double z = o.z + r[i] * d.z;
-        if (z >= 0.0 && z <= p[1]) push_root(out, r[i], 0);
+        push_root(out, r[i], 0, 0.0, z >= 0.0 && z <= p[1], std::min(std::fabs(z), std::fabs(p[1] - z)));
       }
       return;
     }
@@ -435,8 +468,13 @@ void volume_hits(const Vol& v, V3<double> ow, V3<double> dw, double l_ref, std::
         V3<double> x = o + t * d;
         double xs[3] = {x.x, x.y, x.z};
         bool ok = true;
-        for (int k = 0; k < 3; ++k) if (k != ax && std::fabs(xs[k]) > p[k]) ok = false;
-        if (ok) push_root(out, t, f);
+        double bd = 1e300;
+        for (int k = 0; k < 3; ++k)
+          if (k != ax) {
+            if (std::fabs(xs[k]) > p[k]) ok = false;
+            bd = std::min(bd, std::fabs(p[k] - std::fabs(xs[k])));
+          }
+        push_root(out, t, f, 0.0, ok, bd);
       }
       return;
     }
@@ -457,7 +495,9 @@ void volume_hits(const Vol& v, V3<double> ow, V3<double> dw, double l_ref, std::
           double t = std::fabs(d.z) >= std::fabs(du) ? (z - o.z) / d.z : (rho - u0) / du;
           V3<double> x = o + t * d;
           double vt = -x.x * ny + x.y * nx;
-          if (std::fabs(vt) <= rho / std::sqrt(3.0)) push_root(out, t, f, s);
+          double arc = std::hypot(drho, dz);
+          double bd = std::min(std::fabs(rho / std::sqrt(3.0) - std::fabs(vt)), std::min(s, 1.0 - s) * arc);
+          push_root(out, t, f, s, std::fabs(vt) <= rho / std::sqrt(3.0), bd);
         }
       }
       return;
@@ -567,12 +607,20 @@ struct Scn {
   int max_events; uint64_t seed; double l_ref;
 };
 
+// Per-event diagnostics (NDIAG doubles), used only to classify photons whose
+// path is ill-conditioned: [0] gap to the next candidate surface (or the hit
+// distance when the face just left is met again), [1] distance of the hit to
+// its face boundary, [2] smallest boundary distance of a root rejected by the
+// bounds nearer than the hit, [3] |d . n|, [4] distance of the random draw
+// from its reflect / absorb threshold.
+constexpr int NDIAG = 5;
+
 Rec trace_one(const Scn& S, V3<double> o, V3<double> d, uint64_t id, int culled,
-              int32_t* lv, int32_t* lf, int32_t* la, double* lt, double* ls) {
+              int32_t* lv, int32_t* lf, int32_t* la, double* lt, double* ls, double* ldiag) {
   Rec r{};
   r.hash = HASH0; r.last_vol = -1;
   double ncur = 1.0;
-  int prev_v = -1, prev_f = -1;
+  int prev_v = -1, prev_f = -1, prev_side = 0;
   const double eps_self = 1e-9 * S.l_ref, eps_tie = 1e-12 * S.l_ref;
   std::vector<Hit> hits;
   if (!(std::isfinite(o.x) && std::isfinite(o.y) && std::isfinite(o.z) && std::isfinite(d.x) &&
@@ -582,20 +630,46 @@ Rec trace_one(const Scn& S, V3<double> o, V3<double> d, uint64_t id, int culled,
   int k = 0;
   while (!r.fate) {
     if (k == S.max_events) { r.fate = F_SUSPENDED; break; }
-    double bt = std::numeric_limits<double>::infinity(), bs = 0.0;
+    const double INF = std::numeric_limits<double>::infinity();
+    double bt = INF, bs = 0.0, bbd = INF;
     int bv = -1, bf = -1;
+    std::vector<std::pair<double, double>> rejected;   // (t, boundary distance)
+    std::vector<std::pair<double, long>> valid;        // (t, vol * 8 + face)
     for (int vi = 0; vi < (int)S.v.size(); ++vi) {
       const Vol& v = S.v[vi];
       if (culled && !sphere_may_hit(v, o, d, 0.0)) continue;
       hits.clear();
       volume_hits(v, o, d, S.l_ref, hits);
       for (const Hit& h : hits) {
-        double tlo = (vi == prev_v && h.face == prev_f) ? eps_self : 0.0;
+        bool self = vi == prev_v && h.face == prev_f;
+        double tlo = self ? eps_self : 0.0;
         if (!(h.t > tlo)) continue;
+        if (self) {
+          // the face just left is met again only from the side the photon is on
+          Geo<double> gs = geometry<double>(v, nullptr);
+          V3<double> ns = front_normal(v, gs, h.face, to_local_p(gs, o + h.t * d), h.s);
+          if ((dot(d, ns) < 0.0) != (prev_side == 0)) continue;
+        }
+        if (!h.ok) { if (ldiag) rejected.push_back({h.t, h.bd}); continue; }
+        if (ldiag) valid.push_back({h.t, (long)vi * 8 + h.face});
         bool better = h.t < bt - eps_tie ||
                       (std::fabs(h.t - bt) <= eps_tie && (vi < bv || (vi == bv && h.face < bf)));
-        if (better) { bt = h.t; bv = vi; bf = h.face; bs = h.s; }
+        if (better) { bt = h.t; bv = vi; bf = h.face; bs = h.s; bbd = h.bd; }
       }
+    }
+    if (ldiag) {
+      double* dg = ldiag + NDIAG * k;
+      double gap = INF, miss = INF;
+      // exact ties (coincident surfaces) are settled by volume id on any
+      // tracer and are not ill-conditioned
+      for (auto& c : valid)
+        if (c.second != (long)bv * 8 + bf && std::fabs(c.first - bt) > eps_tie)
+          gap = std::min(gap, std::fabs(c.first - bt));
+      if (bv >= 0 && bv == prev_v && bf == prev_f) gap = std::min(gap, bt);
+      double tcut = (bv >= 0 ? bt : INF) + 1e-5 * S.l_ref;
+      for (auto& c : rejected)
+        if (c.first <= tcut) miss = std::min(miss, c.second);
+      dg[0] = gap; dg[1] = bbd; dg[2] = miss; dg[3] = INF; dg[4] = INF;
     }
     if (bv < 0) { r.fate = F_EXITED; break; }
     const Vol& v = S.v[bv];
@@ -605,6 +679,7 @@ Rec trace_one(const Scn& S, V3<double> o, V3<double> d, uint64_t id, int culled,
     V3<double> n = front_normal(v, g, bf, to_local_p(g, X), bs);
     double dn = dot(d, n);
     int back = dn < 0.0 ? 0 : 1;
+    if (ldiag) ldiag[NDIAG * k + 3] = std::fabs(dn);
     uint32_t code = ((uint32_t)bv << 4) | ((uint32_t)bf << 1) | (uint32_t)back;
     r.hash = (r.hash ^ code) * HASHP;
     r.last_vol = bv;
@@ -620,6 +695,7 @@ Rec trace_one(const Scn& S, V3<double> o, V3<double> d, uint64_t id, int culled,
         double R = std::min(std::max(v.refl, 0.0), 1.0);
         uint64_t thr = (uint64_t)std::floor(R * 4294967296.0);
         uint32_t u = draw(S.seed, id, k);
+        if (ldiag && R < 1.0) ldiag[NDIAG * k + 4] = std::fabs((double)u / 4294967296.0 - R);
         if ((uint64_t)u >= thr) r.fate = F_ABSORBED;
         else { d = d - (2.0 * dn) * n; act = ACT_REFLECT; }
       }
@@ -629,6 +705,7 @@ Rec trace_one(const Scn& S, V3<double> o, V3<double> d, uint64_t id, int culled,
       double cos_i = -dot(d, no), cos_t;
       double R = fresnel(cos_i, n1, n2, cos_t);
       uint32_t u = draw(S.seed, id, k);
+      if (ldiag) ldiag[NDIAG * k + 4] = std::fabs((double)(u >> 8) * (1.0 / 16777216.0) - R);
       if ((double)(u >> 8) * (1.0 / 16777216.0) < R) { d = d - (2.0 * dot(d, no)) * no; act = ACT_REFLECT; }
       else {
         double eta = n1 / n2;
@@ -640,6 +717,7 @@ Rec trace_one(const Scn& S, V3<double> o, V3<double> d, uint64_t id, int culled,
     }
     if (lv) { lv[k] = bv; lf[k] = bf; la[k] = act; lt[k] = bt; ls[k] = bs; }
     prev_v = bv; prev_f = bf;
+    prev_side = back ^ (act == ACT_REFRACT ? 1 : 0);
     ++k;
     if (!(std::isfinite(d.x) && std::isfinite(d.y) && std::isfinite(d.z))) r.fate = F_FAILED;
   }
@@ -766,7 +844,8 @@ int oracle_trace(int nv, const int32_t* vi, const double* vd, int max_events, ui
                  const double* dx, const double* dy, const double* dz, uint64_t id_base,
                  uint8_t* fate, uint8_t* nev, int32_t* last_vol, double* pos, double* dir,
                  double* opl, uint64_t* hash, int32_t* log_vol, int32_t* log_face,
-                 int32_t* log_act, double* log_t, double* log_s, int nthreads, int culled) {
+                 int32_t* log_act, double* log_t, double* log_s, double* log_diag, int nthreads,
+                 int culled) {
   if (nv < 0 || n < 0 || max_events < 1 || max_events > 255) return -1;
   Scn S;
   S.v = unpack(nv, vi, vd);
@@ -777,7 +856,7 @@ int oracle_trace(int nv, const int32_t* vi, const double* vd, int max_events, ui
       Rec r = trace_one(S, mk(ox[i], oy[i], oz[i]), mk(dx[i], dy[i], dz[i]), id_base + (uint64_t)i,
                         culled, log_vol ? log_vol + lo : nullptr, log_face ? log_face + lo : nullptr,
                         log_act ? log_act + lo : nullptr, log_t ? log_t + lo : nullptr,
-                        log_s ? log_s + lo : nullptr);
+                        log_s ? log_s + lo : nullptr, log_diag ? log_diag + lo * NDIAG : nullptr);
       fate[i] = r.fate; nev[i] = r.nev; last_vol[i] = r.last_vol;
       for (int k = 0; k < 3; ++k) { pos[3 * i + k] = r.pos[k]; dir[3 * i + k] = r.dir[k]; }
       opl[i] = r.opl; hash[i] = r.hash;

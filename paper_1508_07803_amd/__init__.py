@@ -1,0 +1,264 @@
+"""Python binding of librobast (MI355X non-sequential photon tracer).
+
+Argument marshalling only: every step of the trace, the figures and the
+adjoint runs in the HIP library behind the C ABI declared in
+``include/robast.h``.  PyTorch supplies device memory and the stream.  There
+is no CPU fallback: if the library is missing this module raises on import.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librobast.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, EMISMATCH = 0, -1, -2, -3, -4, -5
+GROUP_STRIDE = 8
+FIGURE_STRIDE = 8
+
+SYMBOLS = ["robast_build_scene", "robast_trace", "robast_figures", "robast_trace_backward",
+           "robast_update_params", "robast_destroy_scene", "robast_status_string",
+           "robast_last_error", "robast_abi_version"]
+
+
+class VolumeDesc(ctypes.Structure):
+    _fields_ = [("role", ctypes.c_int32), ("shape", ctypes.c_int32), ("outline", ctypes.c_int32),
+                ("shape_param", ctypes.c_int32), ("tilt_param", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("Q", ctypes.c_double * 9), ("c", ctypes.c_double * 3), ("p", ctypes.c_double * 16),
+                ("o", ctypes.c_double * 4), ("reflectivity", ctypes.c_double), ("n_inside", ctypes.c_double),
+                ("Q0", ctypes.c_double * 9), ("c0", ctypes.c_double * 3), ("pivot", ctypes.c_double * 3),
+                ("e1", ctypes.c_double * 3), ("e2", ctypes.c_double * 3)]
+
+
+class SceneDesc(ctypes.Structure):
+    _fields_ = [("volumes", ctypes.c_void_p), ("n_volumes", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("max_events", ctypes.c_int32), ("n_groups", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("l_ref", ctypes.c_double)]
+
+
+class Rays(ctypes.Structure):
+    _fields_ = [("ox", ctypes.c_void_p), ("oy", ctypes.c_void_p), ("oz", ctypes.c_void_p),
+                ("dx", ctypes.c_void_p), ("dy", ctypes.c_void_p), ("dz", ctypes.c_void_p),
+                ("group", ctypes.c_void_p), ("id_base", ctypes.c_uint64)]
+
+
+class Hits(ctypes.Structure):
+    _fields_ = [("fate", ctypes.c_void_p), ("n_events", ctypes.c_void_p), ("last_vol", ctypes.c_void_p),
+                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("ux", ctypes.c_void_p), ("uy", ctypes.c_void_p), ("uz", ctypes.c_void_p),
+                ("opl", ctypes.c_void_p), ("seq_hash", ctypes.c_void_p), ("group_sums", ctypes.c_void_p)]
+
+
+assert ctypes.sizeof(VolumeDesc) == 464
+
+_lib.robast_build_scene.argtypes = [ctypes.POINTER(SceneDesc), ctypes.c_void_p, ctypes.c_int64,
+                                    ctypes.POINTER(ctypes.c_void_p)]
+_lib.robast_trace.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ctypes.c_int64, ctypes.POINTER(Hits),
+                              ctypes.c_uint32, ctypes.c_void_p]
+_lib.robast_figures.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+_lib.robast_trace_backward.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ctypes.c_int64, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+_lib.robast_update_params.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+_lib.robast_destroy_scene.argtypes = [ctypes.c_void_p]
+_lib.robast_destroy_scene.restype = None
+_lib.robast_status_string.argtypes = [ctypes.c_int]
+_lib.robast_status_string.restype = ctypes.c_char_p
+_lib.robast_last_error.restype = ctypes.c_char_p
+for _name in ("robast_build_scene", "robast_trace", "robast_figures", "robast_trace_backward",
+              "robast_update_params", "robast_abi_version"):
+    getattr(_lib, _name).restype = ctypes.c_int
+
+
+class RobastError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        msg = _lib.robast_last_error().decode()
+        super().__init__(f"{what}: {_lib.robast_status_string(status).decode()} ({status}): {msg}")
+
+
+def _check(status, what):
+    if status != OK:
+        raise RobastError(status, what)
+
+
+def lib():
+    return _lib
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr()) if hasattr(t, "data_ptr") else t
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def build_scene_raw(volumes, precision, max_events, n_groups, seed, l_ref, params):
+    """Call robast_build_scene on a VOLUME_DTYPE array; returns (status, handle)."""
+    vols = np.ascontiguousarray(volumes)
+    assert vols.dtype.itemsize == 464 or len(vols) == 0
+    P = np.ascontiguousarray(params, dtype=np.float64)
+    desc = SceneDesc(vols.ctypes.data if len(vols) else None, len(vols), precision, max_events, n_groups,
+                     seed, l_ref)
+    h = ctypes.c_void_p()
+    st = _lib.robast_build_scene(ctypes.byref(desc), P.ctypes.data if len(P) else None, len(P),
+                                 ctypes.byref(h))
+    return st, h
+
+
+class Scene:
+    """A compiled scene on the current HIP device."""
+
+    def __init__(self, scene):
+        self.src = scene
+        self.precision = scene.precision
+        self.n_groups = scene.n_groups
+        self.n_params = len(scene.params)
+        self.params = np.array(scene.params, dtype=np.float64)
+        st, h = build_scene_raw(scene.volumes, scene.precision, scene.max_events, scene.n_groups,
+                                scene.seed, scene.l_ref, scene.params)
+        _check(st, "robast_build_scene")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.robast_destroy_scene(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- tensors
+    @property
+    def dtype(self):
+        import torch
+        return torch.float32 if self.precision == 32 else torch.float64
+
+    def upload_rays(self, rays, device="cuda"):
+        """Host ray dict (numpy, from `scenes`) -> dict of device tensors."""
+        import torch
+        out = {k: torch.from_numpy(np.ascontiguousarray(rays[k])).to(device=device, dtype=self.dtype)
+               for k in ("ox", "oy", "oz", "dx", "dy", "dz")}
+        out["group"] = torch.from_numpy(np.ascontiguousarray(rays["group"]).astype(np.int32)).to(device)
+        return out
+
+    def alloc_hits(self, n, device="cuda", sums=False):
+        import torch
+        h = dict(fate=torch.zeros(n, dtype=torch.uint8, device=device),
+                 n_events=torch.zeros(n, dtype=torch.uint8, device=device),
+                 last_vol=torch.zeros(n, dtype=torch.int32, device=device),
+                 opl=torch.zeros(n, dtype=self.dtype, device=device),
+                 seq_hash=torch.zeros(n, dtype=torch.int64, device=device))
+        for k in ("x", "y", "z", "ux", "uy", "uz"):
+            h[k] = torch.zeros(n, dtype=self.dtype, device=device)
+        if sums:
+            h["group_sums"] = self.new_sums(device)
+        return h
+
+    def new_sums(self, device="cuda"):
+        import torch
+        return torch.zeros(self.n_groups * GROUP_STRIDE, dtype=torch.float64, device=device)
+
+    @staticmethod
+    def _rays_struct(rays, id_base=0, offset=0):
+        def p(k):
+            t = rays[k]
+            return ctypes.c_void_p(t.data_ptr() + offset * t.element_size())
+        g = rays.get("group")
+        return Rays(p("ox").value, p("oy").value, p("oz").value, p("dx").value, p("dy").value, p("dz").value,
+                    (g.data_ptr() + offset * g.element_size()) if g is not None else None, id_base + offset)
+
+    # -------------------------------------------------------------- calls
+    def trace(self, rays, n=None, hits=None, sums=None, id_base=0, stream=None):
+        """Trace n photons; writes the given hit tensors and/or accumulates sums."""
+        n = int(rays["ox"].numel()) if n is None else int(n)
+        hits = hits or {}
+        H = Hits(*[(_ptr(hits.get(k)).value if hits.get(k) is not None else None)
+                   for k in ("fate", "n_events", "last_vol", "x", "y", "z", "ux", "uy", "uz", "opl",
+                             "seq_hash")],
+                 _ptr(sums).value if sums is not None else None)
+        R = self._rays_struct(rays, id_base)
+        _check(_lib.robast_trace(self._h, ctypes.byref(R), n, ctypes.byref(H), 0, _stream(stream)),
+               "robast_trace")
+        return hits
+
+    def figures(self, sums, stream=None):
+        import torch
+        fig = torch.zeros(self.n_groups * FIGURE_STRIDE, dtype=torch.float64, device=sums.device)
+        _check(_lib.robast_figures(self._h, _ptr(sums), _ptr(fig), _stream(stream)), "robast_figures")
+        return fig.view(self.n_groups, FIGURE_STRIDE)
+
+    def backward(self, rays, sums, cot, grad, n=None, id_base=0, stream=None):
+        """Accumulate dL/dparams into grad for L = sum_g cot[g,0] RMS_g + cot[g,1] effw_g."""
+        n = int(rays["ox"].numel()) if n is None else int(n)
+        R = self._rays_struct(rays, id_base)
+        _check(_lib.robast_trace_backward(self._h, ctypes.byref(R), n, _ptr(sums), _ptr(cot), _ptr(grad),
+                                          _stream(stream)), "robast_trace_backward")
+        return grad
+
+    def update_params(self, params):
+        P = np.ascontiguousarray(params, dtype=np.float64)
+        _check(_lib.robast_update_params(self._h, P.ctypes.data if len(P) else None, len(P)),
+               "robast_update_params")
+        self.params = P.copy()
+
+
+def _autograd():
+    import torch
+
+    class RobastTrace(torch.autograd.Function):
+        """figures (n_groups x 8) = trace(params); backward via robast_trace_backward.
+
+        Gradients flow from the RMS spot radius (column 4) and the weighted
+        collection (column 6); the other figure columns are counts and means
+        whose pathwise derivative is not propagated.
+        """
+
+        @staticmethod
+        def forward(ctx, params, scene, rays):
+            p = params.detach().cpu().numpy()
+            if not np.array_equal(p, scene.params):
+                scene.update_params(p)
+            sums = scene.new_sums(rays["ox"].device)
+            scene.trace(rays, sums=sums)
+            fig = scene.figures(sums)
+            ctx.scene, ctx.rays = scene, rays
+            ctx.save_for_backward(sums)
+            return fig
+
+        @staticmethod
+        def backward(ctx, gfig):
+            (sums,) = ctx.saved_tensors
+            scene = ctx.scene
+            cot = torch.stack([gfig[:, 4], gfig[:, 6]], 1).contiguous().to(torch.float64)
+            grad = torch.zeros(scene.n_params, dtype=torch.float64, device=sums.device)
+            scene.backward(ctx.rays, sums, cot, grad)
+            return grad.to("cpu"), None, None
+
+    return RobastTrace
+
+
+def __getattr__(name):
+    if name == "RobastTrace":
+        return _autograd()
+    raise AttributeError(name)

@@ -1,0 +1,670 @@
+// Device-side photon transport for gfx950: Philox draws, per-shape exact
+// intersections, the non-sequential nearest-surface search and the
+// interaction physics.  All arithmetic is in the scene precision T (float or
+// double); group sums are accumulated in double by the kernels.
+//
+// Physics follows the paper's roles (§2.1): mirrors reflect (absorbing with
+// probability 1 - R, and on their back), lenses refract by Snell's law with
+// unpolarised Fresnel reflection, focal surfaces detect (front) or absorb
+// (back), obscurations absorb.  Shapes follow §2.2.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "scene_layout.hpp"
+
+namespace robast {
+
+template <typename T> struct V3 { T x, y, z; };
+template <typename T> __device__ __forceinline__ V3<T> mk3(T a, T b, T c) { return V3<T>{a, b, c}; }
+template <typename T> __device__ __forceinline__ V3<T> add(V3<T> a, V3<T> b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <typename T> __device__ __forceinline__ V3<T> sub(V3<T> a, V3<T> b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <typename T> __device__ __forceinline__ V3<T> scl(T s, V3<T> a) { return {s * a.x, s * a.y, s * a.z}; }
+template <typename T> __device__ __forceinline__ V3<T> fma3(T s, V3<T> a, V3<T> b) {
+  return {s * a.x + b.x, s * a.y + b.y, s * a.z + b.z};
+}
+template <typename T> __device__ __forceinline__ T dot(V3<T> a, V3<T> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <typename T> __device__ __forceinline__ V3<T> cross(V3<T> a, V3<T> b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+
+__device__ __forceinline__ float dsqrt(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ double dsqrt(double x) { return __builtin_sqrt(x); }
+__device__ __forceinline__ float dabs(float x) { return __builtin_fabsf(x); }
+__device__ __forceinline__ double dabs(double x) { return __builtin_fabs(x); }
+__device__ __forceinline__ float dmin(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ double dmin(double a, double b) { return __builtin_fmin(a, b); }
+__device__ __forceinline__ float dmax(float a, float b) { return __builtin_fmaxf(a, b); }
+__device__ __forceinline__ double dmax(double a, double b) { return __builtin_fmax(a, b); }
+__device__ __forceinline__ float dfloor(float a) { return __builtin_floorf(a); }
+__device__ __forceinline__ double dfloor(double a) { return __builtin_floor(a); }
+__device__ __forceinline__ float dcopysign(float a, float b) { return __builtin_copysignf(a, b); }
+__device__ __forceinline__ double dcopysign(double a, double b) { return __builtin_copysign(a, b); }
+template <typename T> __device__ __forceinline__ T tinf() { return T(__builtin_huge_valf()); }
+template <typename T> __device__ __forceinline__ bool finite3(V3<T> a) {
+  return __builtin_isfinite(a.x) && __builtin_isfinite(a.y) && __builtin_isfinite(a.z);
+}
+
+// ------------------------------------------------------------------ Philox4x32-10
+// Salmon, Moraes, Dror, Shaw (SC'11): 10 rounds of two 32x32->64 multiplies
+// with Weyl-sequence key bumps.  Counter (id lo, id hi, event>>2, tag=1).
+__device__ __forceinline__ uint32_t philox_word(uint64_t seed, uint64_t id, int event) {
+  uint32_t c0 = (uint32_t)id, c1 = (uint32_t)(id >> 32), c2 = (uint32_t)(event >> 2), c3 = 1u;
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+  }
+  int w = event & 3;
+  return w == 0 ? c0 : w == 1 ? c1 : w == 2 ? c2 : c3;
+}
+
+// ------------------------------------------------------------------ frames and outlines
+template <typename T> __device__ __forceinline__ V3<T> loc_p(const DVol<T>& v, V3<T> x) {
+  T rx = x.x - v.c[0], ry = x.y - v.c[1], rz = x.z - v.c[2];
+  return {v.Q[0] * rx + v.Q[1] * ry + v.Q[2] * rz, v.Q[3] * rx + v.Q[4] * ry + v.Q[5] * rz,
+          v.Q[6] * rx + v.Q[7] * ry + v.Q[8] * rz};
+}
+template <typename T> __device__ __forceinline__ V3<T> loc_d(const DVol<T>& v, V3<T> d) {
+  return {v.Q[0] * d.x + v.Q[1] * d.y + v.Q[2] * d.z, v.Q[3] * d.x + v.Q[4] * d.y + v.Q[5] * d.z,
+          v.Q[6] * d.x + v.Q[7] * d.y + v.Q[8] * d.z};
+}
+// Local coordinates of a world point kept in double: the offset from the
+// volume origin is formed in double and only then rounded to T, so the local
+// point carries the precision of the local scale, not of the world scale.
+template <typename T> __device__ __forceinline__ V3<T> loc_pd(const DVol<T>& v, V3<double> x) {
+  T rx = (T)(x.x - (double)v.c[0]), ry = (T)(x.y - (double)v.c[1]), rz = (T)(x.z - (double)v.c[2]);
+  return {v.Q[0] * rx + v.Q[1] * ry + v.Q[2] * rz, v.Q[3] * rx + v.Q[4] * ry + v.Q[5] * rz,
+          v.Q[6] * rx + v.Q[7] * ry + v.Q[8] * rz};
+}
+template <typename T> __device__ __forceinline__ V3<double> adv(V3<double> o, T t, V3<T> d) {
+  return {o.x + (double)t * (double)d.x, o.y + (double)t * (double)d.y, o.z + (double)t * (double)d.z};
+}
+template <typename T> __device__ __forceinline__ V3<T> to_t(V3<double> a) { return {(T)a.x, (T)a.y, (T)a.z}; }
+
+// Q^T n, normalised (world normal of a local gradient)
+template <typename T> __device__ __forceinline__ V3<T> world_n(const DVol<T>& v, V3<T> n) {
+  V3<T> w = {v.Q[0] * n.x + v.Q[3] * n.y + v.Q[6] * n.z, v.Q[1] * n.x + v.Q[4] * n.y + v.Q[7] * n.z,
+             v.Q[2] * n.x + v.Q[5] * n.y + v.Q[8] * n.z};
+  T s = T(1) / dsqrt(dot(w, w));
+  return scl(s, w);
+}
+
+template <typename T> __device__ __forceinline__ bool inside_outline(const DVol<T>& v, T x, T y) {
+  const T* o = v.o;
+  switch (v.outline) {
+    case OL_NONE: return true;
+    case OL_DISC: return x * x + y * y <= o[0];
+    case OL_ANNULUS: { T r2 = x * x + y * y; return r2 >= o[0] && r2 <= o[1]; }
+    case OL_RECT: return dabs(x) <= o[0] && dabs(y) <= o[1];
+    case OL_HEX: {
+      const T h = T(0.8660254037844386);
+      return dabs(x) <= o[0] && dabs(T(0.5) * x + h * y) <= o[0] && dabs(T(-0.5) * x + h * y) <= o[0];
+    }
+    case OL_SECTOR: {
+      T r2 = x * x + y * y;
+      if (r2 < o[0] || r2 > o[1]) return false;
+      T c0 = o[2] * y - o[3] * x;   // cross(e0, p) >= 0
+      T c1 = x * o[5] - y * o[4];   // cross(p, e1) >= 0
+      if (o[6] > T(0)) return !(c0 < T(0) && c1 < T(0));  // sector wider than pi
+      return c0 >= T(0) && c1 >= T(0);
+    }
+  }
+  return false;
+}
+
+// ------------------------------------------------------------------ candidate bookkeeping
+// Nearest candidate so far: t (precision T) orders the candidates; tp is the
+// same parameter formed in double from the box-entry shift and the local
+// root, used for the hit point.
+template <typename T> struct Best {
+  T t, s;
+  double tp;
+  int vol, face;
+};
+
+template <typename T> __device__ __forceinline__ void offer(Best<T>& b, T t, int vol, int face, T s, double tp) {
+  bool better = t < b.t || (t == b.t && (vol < b.vol || (vol == b.vol && face < b.face)));
+  if (better) { b.t = t; b.vol = vol; b.face = face; b.s = s; b.tp = tp; }
+}
+
+__device__ __forceinline__ void wall_dir(int k, float& nx, float& ny);
+__device__ __forceinline__ void wall_dir(int k, double& nx, double& ny);
+template <typename C, typename P> __device__ __forceinline__ void sag_eval(const P* p, C u, C& S, C& dS);
+template <typename C, typename P> __device__ __forceinline__ void bez_eval(const P* p, C s, C& rho, C& z, C& drho, C& dz);
+
+// Gradient of the face's implicit function at local point x, computed in C
+// from the record's parameters: it points to the front side (un-normalised).
+template <typename C, typename T> __device__ __forceinline__ V3<C> local_grad(const DVol<T>& v, int face, V3<C> x, C s) {
+  switch (v.shape) {
+    case PLANE: return {C(0), C(0), C(1)};
+    case SPHERE: {
+      C c = (C)v.p[0];
+      return {-c * x.x, -c * x.y, C(1) - c * x.z};
+    }
+    case ASPHERE: {
+      C ir = (C)v.p[9];
+      C u = (x.x * x.x + x.y * x.y) * ir;
+      C S, dS;
+      sag_eval(v.p, u, S, dS);
+      C k = dS * C(2) * ir;
+      return {-k * x.x, -k * x.y, C(1)};
+    }
+    case CYLINDER: return {x.x, x.y, C(0)};
+    case BOX: {
+      int ax = face >> 1;
+      C sg = (face & 1) ? C(-1) : C(1);
+      return {ax == 0 ? sg : C(0), ax == 1 ? sg : C(0), ax == 2 ? sg : C(0)};
+    }
+    default: {
+      C rho, z, dr, dz;
+      bez_eval(v.p, s, rho, z, dr, dz);
+      C nx, ny;
+      wall_dir(face, nx, ny);
+      return {-dz * nx, -dz * ny, dr};
+    }
+  }
+}
+
+// The face just left may be met again only beyond eps and only from the side
+// the photon is on (side 0: front, 1: back); a root that fails this is the
+// departure point itself, displaced by rounding.
+struct SelfRule {
+  int face;   // face of this volume the photon just left, or -1
+  int side;   // side of that face the photon is on
+};
+template <typename T> __device__ __forceinline__ bool self_ok(const DVol<T>& v, const SelfRule& sr, int face,
+                                                             T tt, T eps, V3<T> x, V3<T> d, T s) {
+  if (face != sr.face) return tt > T(0);
+  if (!(tt > eps)) return false;
+  T sd = dot(d, local_grad(v, face, x, s));
+  return (sd < T(0)) == (sr.side == 0);
+}
+
+// ------------------------------------------------------------------ narrow phase
+// Each function receives the local ray (o, d) already advanced by t0 and offers
+// roots t' + t0 in (0, b.t] that pass the self rule.
+
+template <typename T> __device__ __forceinline__ void quad2(T a, T b, T c, T& r0, T& r1, int& n) {
+  n = 0;
+  if (a == T(0)) {
+    if (b != T(0)) { r0 = -c / b; n = 1; }
+    return;
+  }
+  T disc = b * b - T(4) * a * c;
+  if (disc < T(0)) return;
+  T q = T(-0.5) * (b + dcopysign(dsqrt(disc), b));
+  if (q == T(0)) { r0 = T(0); n = 1; return; }
+  r0 = q / a; r1 = c / q; n = 2;
+}
+
+template <typename T> __device__ __forceinline__ void nf_plane(const DVol<T>& v, int vid, V3<T> o, V3<T> d,
+                                                               T t0, T eps, SelfRule sr, Best<T>& b) {
+  if (d.z == T(0)) return;
+  T t = -o.z / d.z;
+  T tt = t + t0;
+  if (tt > b.t) return;
+  V3<T> x = fma3(t, d, o);
+  if (!self_ok(v, sr, 0, tt, eps, x, d, T(0))) return;
+  if (inside_outline(v, x.x, x.y)) offer(b, tt, vid, 0, T(0), (double)t0 + (double)t);
+}
+
+template <typename T> __device__ __forceinline__ void nf_sphere(const DVol<T>& v, int vid, V3<T> o, V3<T> d,
+                                                                T t0, T eps, SelfRule sr, Best<T>& b) {
+  T cv = v.p[0];
+  T a = T(-0.5) * cv * dot(d, d), bb = d.z - cv * dot(o, d), c = o.z - T(0.5) * cv * dot(o, o);
+  T r[2]; int n;
+  quad2(a, bb, c, r[0], r[1], n);
+  for (int i = 0; i < n; ++i) {
+    T tt = r[i] + t0;
+    if (tt > b.t) continue;
+    V3<T> x = fma3(r[i], d, o);
+    if (T(1) - cv * x.z < T(0)) continue;
+    if (!self_ok(v, sr, 0, tt, eps, x, d, T(0))) continue;
+    if (inside_outline(v, x.x, x.y)) offer(b, tt, vid, 0, T(0), (double)t0 + (double)r[i]);
+  }
+}
+
+template <typename C, typename P> __device__ __forceinline__ void sag_eval(const P* p, C u, C& S, C& dS) {
+  // S = sum_{i=1..8} b_i u^i, dS = dS/du ; p[1..8] = b_i
+  C s = (C)p[8], ds = C(8) * (C)p[8];
+#pragma unroll
+  for (int i = 7; i >= 1; --i) { s = s * u + (C)p[i]; ds = ds * u + C(i) * (C)p[i]; }
+  S = s * u; dS = ds;
+}
+
+// g(t) = z(t) - S(u(t)), u = (x^2 + y^2)/rn^2
+template <typename T> __device__ __forceinline__ void asph_g(const DVol<T>& v, V3<T> o, V3<T> d, T t, T& g, T& gp) {
+  T x = o.x + t * d.x, y = o.y + t * d.y, z = o.z + t * d.z;
+  T u = (x * x + y * y) * v.p[9];
+  T S, dS;
+  sag_eval(v.p, u, S, dS);
+  g = z - S;
+  gp = d.z - dS * T(2) * v.p[9] * (x * d.x + y * d.y);
+}
+
+template <typename T> __device__ __forceinline__ void nf_asphere(const DVol<T>& v, int vid, V3<T> o, V3<T> d,
+                                                                 T t0, T eps, SelfRule sr, Best<T>& b) {
+  // bracket: local z-slab of the surface and the cylinder r <= rout
+  T tlo = sr.face == 0 ? eps : T(0);
+  T ta = tlo - t0, tb = b.t - t0;
+  if (d.z != T(0)) {
+    T t1 = (v.lo[2] - o.z) / d.z, t2 = (v.hi[2] - o.z) / d.z;
+    ta = dmax(ta, dmin(t1, t2)); tb = dmin(tb, dmax(t1, t2));
+  } else if (o.z < v.lo[2] || o.z > v.hi[2]) {
+    return;
+  }
+  T A = d.x * d.x + d.y * d.y, B = T(2) * (o.x * d.x + o.y * d.y), C = o.x * o.x + o.y * o.y - v.rout * v.rout;
+  if (A > T(0)) {
+    T r0, r1; int n;
+    quad2(A, B, C, r0, r1, n);
+    if (n < 2) return;
+    ta = dmax(ta, dmin(r0, r1)); tb = dmin(tb, dmax(r0, r1));
+  } else if (C > T(0)) {
+    return;
+  }
+  if (!(ta <= tb)) return;
+  T ga, gpa, gb, gpb;
+  asph_g(v, o, d, ta, ga, gpa);
+  asph_g(v, o, d, tb, gb, gpb);
+  if ((ga > T(0)) == (gb > T(0))) {
+    // no sign change; with |d_z| > slope |d_xy| g is monotone, so no root
+    if (dabs(d.z) > v.slope * dsqrt(A)) return;
+    // grazing ray: first sign change on a uniform subdivision
+    const int K = 16;
+    T h = (tb - ta) / T(K), tp = ta, gprev = ga;
+    bool found = false;
+    for (int k = 1; k <= K; ++k) {
+      T tk = k == K ? tb : ta + h * T(k);
+      T gk, gpk;
+      asph_g(v, o, d, tk, gk, gpk);
+      if ((gk > T(0)) != (gprev > T(0))) { ta = tp; tb = tk; ga = gprev; gb = gk; found = true; break; }
+      tp = tk; gprev = gk;
+    }
+    if (!found) return;
+  }
+  // safeguarded Newton on [ta, tb]
+  T a = ta, bnd = tb, ga_ = ga;
+  T t = (gb - ga) != T(0) ? ta - ga * (tb - ta) / (gb - ga) : T(0.5) * (ta + tb);
+  const T tol = sizeof(T) == 4 ? T(2e-7) : T(1e-15);
+  for (int it = 0; it < 24; ++it) {
+    T g, gp;
+    asph_g(v, o, d, t, g, gp);
+    if (g == T(0)) break;
+    if ((g > T(0)) == (ga_ > T(0))) { a = t; ga_ = g; } else { bnd = t; }
+    T tn = gp != T(0) ? t - g / gp : T(0.5) * (a + bnd);
+    if (!(tn > dmin(a, bnd) && tn < dmax(a, bnd))) tn = T(0.5) * (a + bnd);
+    T dt = tn - t;
+    t = tn;
+    if (dabs(dt) <= tol * (dabs(t) + dabs(t0) + T(1e-30))) break;
+  }
+  T tt = t + t0;
+  if (tt > b.t) return;
+  V3<T> x = fma3(t, d, o);
+  if (!self_ok(v, sr, 0, tt, eps, x, d, T(0))) return;
+  if (inside_outline(v, x.x, x.y)) offer(b, tt, vid, 0, T(0), (double)t0 + (double)t);
+}
+
+template <typename T> __device__ __forceinline__ void nf_cylinder(const DVol<T>& v, int vid, V3<T> o, V3<T> d,
+                                                                  T t0, T eps, SelfRule sr, Best<T>& b) {
+  T A = d.x * d.x + d.y * d.y;
+  if (A == T(0)) return;
+  T B = T(2) * (o.x * d.x + o.y * d.y), C = o.x * o.x + o.y * o.y - v.p[0] * v.p[0];
+  T r[2]; int n;
+  quad2(A, B, C, r[0], r[1], n);
+  for (int i = 0; i < n; ++i) {
+    T tt = r[i] + t0;
+    if (tt > b.t) continue;
+    V3<T> x = fma3(r[i], d, o);
+    if (!self_ok(v, sr, 0, tt, eps, x, d, T(0))) continue;
+    if (x.z >= T(0) && x.z <= v.p[1]) offer(b, tt, vid, 0, T(0), (double)t0 + (double)r[i]);
+  }
+}
+
+template <typename T> __device__ __forceinline__ void nf_box(const DVol<T>& v, int vid, V3<T> o, V3<T> d,
+                                                             T t0, T eps, SelfRule sr, Best<T>& b) {
+  const T oa[3] = {o.x, o.y, o.z}, da[3] = {d.x, d.y, d.z};
+  for (int f = 0; f < 6; ++f) {
+    int ax = f >> 1;
+    T sgn = (f & 1) ? T(-1) : T(1);
+    if (da[ax] == T(0)) continue;
+    T t = (sgn * v.p[ax] - oa[ax]) / da[ax];
+    T tt = t + t0;
+    if (tt > b.t) continue;
+    if (!self_ok(v, sr, f, tt, eps, fma3(t, d, o), d, T(0))) continue;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      if (k != ax && dabs(oa[k] + t * da[k]) > v.p[k]) ok = false;
+    if (ok) offer(b, tt, vid, f, T(0), (double)t0 + (double)t);
+  }
+}
+
+template <typename C, typename P> __device__ __forceinline__ void bez_eval(const P* pp, C s, C& rho, C& z, C& drho, C& dz) {
+  C p[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) p[i] = (C)pp[i];
+  C a = C(1) - s;
+  C b0 = a * a * a, b1 = C(3) * a * a * s, b2 = C(3) * a * s * s, b3 = s * s * s;
+  rho = b0 * p[0] + b1 * p[2] + b2 * p[4] + b3 * p[6];
+  z = b0 * p[1] + b1 * p[3] + b2 * p[5] + b3 * p[7];
+  C d0 = C(3) * a * a, d1 = C(6) * a * s, d2 = C(3) * s * s;
+  drho = d0 * (p[2] - p[0]) + d1 * (p[4] - p[2]) + d2 * (p[6] - p[4]);
+  dz = d0 * (p[3] - p[1]) + d1 * (p[5] - p[3]) + d2 * (p[7] - p[5]);
+}
+
+__device__ __forceinline__ void wall_dir(int k, float& nx, float& ny) {
+  const float cs[6] = {1.f, 0.5f, -0.5f, -1.f, -0.5f, 0.5f};
+  const float sn[6] = {0.f, 0.8660254037844386f, 0.8660254037844386f, 0.f, -0.8660254037844386f, -0.8660254037844386f};
+  nx = cs[k]; ny = sn[k];
+}
+__device__ __forceinline__ void wall_dir(int k, double& nx, double& ny) {
+  const double cs[6] = {1.0, 0.5, -0.5, -1.0, -0.5, 0.5};
+  const double sn[6] = {0.0, 0.8660254037844386, 0.8660254037844386, 0.0, -0.8660254037844386, -0.8660254037844386};
+  nx = cs[k]; ny = sn[k];
+}
+
+// root of the cubic (power basis) on the monotone piece [a, b] with a sign change
+// Cubic in Bernstein form, F(s) = sum_k w_k B_k(s), and its derivative.  The
+// Bernstein form keeps the value accurate near s = 0 and s = 1 (the exit and
+// entrance rims), where the power-basis coefficients cancel.
+template <typename T> __device__ __forceinline__ void bern3(const T* w, T s, T& f, T& fp) {
+  T a = T(1) - s;
+  T b0 = a * a, b1 = T(2) * a * s, b2 = s * s;
+  f = a * (b0 * w[0] + T(3) * a * s * w[1]) + s * (T(3) * a * s * w[2] + b2 * w[3]);
+  fp = T(3) * (b0 * (w[1] - w[0]) + b1 * (w[2] - w[1]) + b2 * (w[3] - w[2]));
+}
+
+// root of F on the monotone piece [a, b] with a sign change, safeguarded Newton
+template <typename T> __device__ __forceinline__ T cubic_root_piece(const T* w, T a, T b, T fa) {
+  T s = T(0.5) * (a + b);
+  for (int it = 0; it < 40; ++it) {
+    T f, fp;
+    bern3(w, s, f, fp);
+    if (f == T(0)) break;
+    if ((f > T(0)) == (fa > T(0))) { a = s; fa = f; } else { b = s; }
+    T sn = fp != T(0) ? s - f / fp : T(0.5) * (a + b);
+    if (!(sn > a && sn < b)) sn = T(0.5) * (a + b);
+    T ds = sn - s;
+    s = sn;
+    if (dabs(ds) <= (sizeof(T) == 4 ? T(1e-7) : T(1e-16))) break;
+  }
+  return s;
+}
+
+template <typename T> __device__ __forceinline__ void nf_hexcone(const DVol<T>& v, int vid, V3<T> o, V3<T> d,
+                                                                 T t0, T eps, SelfRule sr, Best<T>& b) {
+  const T* p = v.p;
+  const T inv_sqrt3 = T(0.5773502691896258);
+  for (int f = 0; f < 6; ++f) {
+    T nx, ny;
+    wall_dir(f, nx, ny);
+    T u0 = o.x * nx + o.y * ny, du = d.x * nx + d.y * ny;
+    T w0 = (p[0] - u0) * d.z - (p[1] - o.z) * du;
+    T w1 = (p[2] - u0) * d.z - (p[3] - o.z) * du;
+    T w2 = (p[4] - u0) * d.z - (p[5] - o.z) * du;
+    T w3 = (p[6] - u0) * d.z - (p[7] - o.z) * du;
+    if (w0 == T(0) && w1 == T(0) && w2 == T(0) && w3 == T(0)) continue;
+    const T wv[4] = {w0, w1, w2, w3};
+    // power-basis coefficients, used only to split [0, 1] at the critical points
+    T c[4] = {w0, T(3) * (w1 - w0), T(3) * (w0 - T(2) * w1 + w2), w3 - T(3) * w2 + T(3) * w1 - w0};
+    // monotone pieces split at the critical points in (0, 1)
+    T br[4]; int nb = 0;
+    br[nb++] = T(0);
+    T q0, q1; int nq;
+    quad2(T(3) * c[3], T(2) * c[2], c[1], q0, q1, nq);
+    if (nq == 2 && q0 > q1) { T tq = q0; q0 = q1; q1 = tq; }
+    if (nq >= 1 && q0 > T(0) && q0 < T(1)) br[nb++] = q0;
+    if (nq == 2 && q1 > T(0) && q1 < T(1)) br[nb++] = q1;
+    br[nb++] = T(1);
+    T fa = c[0];
+    for (int i = 0; i + 1 < nb; ++i) {
+      T a = br[i], bb = br[i + 1];
+      T fb, fpb;
+      bern3(wv, bb, fb, fpb);
+      T s;
+      if (fa == T(0)) s = a;
+      else if (fb == T(0) && i + 2 == nb) s = bb;
+      else if ((fa > T(0)) != (fb > T(0))) s = cubic_root_piece(wv, a, bb, fa);
+      else { fa = fb; continue; }
+      fa = fb;
+      T rho, z, dr, dzs;
+      bez_eval(p, s, rho, z, dr, dzs);
+      T t = dabs(d.z) >= dabs(du) ? (z - o.z) / d.z : (rho - u0) / du;
+      T tt = t + t0;
+      if (tt > b.t) continue;
+      V3<T> xh = fma3(t, d, o);
+      if (!self_ok(v, sr, f, tt, eps, xh, d, s)) continue;
+      T vt = -xh.x * ny + xh.y * nx;
+      if (dabs(vt) <= rho * inv_sqrt3) offer(b, tt, vid, f, s, (double)t0 + (double)t);
+    }
+  }
+}
+
+// world AABB slab test: entry parameter, or -1 if the box is missed in (0, tmax]
+template <typename T> __device__ __forceinline__ bool aabb(const DVol<T>& v, V3<T> o, V3<T> inv, T tmax, T& tin) {
+  T t1 = (v.bmin[0] - o.x) * inv.x, t2 = (v.bmax[0] - o.x) * inv.x;
+  T lo = dmin(t1, t2), hi = dmax(t1, t2);
+  t1 = (v.bmin[1] - o.y) * inv.y; t2 = (v.bmax[1] - o.y) * inv.y;
+  lo = dmax(lo, dmin(t1, t2)); hi = dmin(hi, dmax(t1, t2));
+  t1 = (v.bmin[2] - o.z) * inv.z; t2 = (v.bmax[2] - o.z) * inv.z;
+  lo = dmax(lo, dmin(t1, t2)); hi = dmin(hi, dmax(t1, t2));
+  tin = dmax(lo, T(0));
+  return hi >= tin && tin <= tmax;
+}
+
+// Exact test of one volume; offers its nearest valid face root to b.
+// The photon position O is kept in double (world scale); of and inv are its
+// rounding and the inverse direction in T for the box tests.
+template <typename T> __device__ __forceinline__ void test_volume(const DVol<T>& v, int vid, V3<double> O, V3<T> of,
+                                                                  V3<T> d, V3<T> inv, int prev_vol, int prev_face,
+                                                                  int prev_side, T eps, Best<T>& b) {
+  T tin;
+  if (!aabb(v, of, inv, b.t, tin)) return;
+  // advance to the box entry to keep the local quadratic well conditioned;
+  // planes are not advanced, so coincident planes with the same z-row give
+  // bit-identical t and the tie goes to the lower volume id
+  T t0 = v.shape == PLANE ? T(0) : tin;
+  V3<T> ol = loc_pd(v, adv(O, t0, d)), dl = loc_d(v, d);
+  SelfRule sr{vid == prev_vol ? prev_face : -1, prev_side};
+  switch (v.shape) {
+    case PLANE: nf_plane(v, vid, ol, dl, t0, eps, sr, b); break;
+    case SPHERE: nf_sphere(v, vid, ol, dl, t0, eps, sr, b); break;
+    case ASPHERE: nf_asphere(v, vid, ol, dl, t0, eps, sr, b); break;
+    case CYLINDER: nf_cylinder(v, vid, ol, dl, t0, eps, sr, b); break;
+    case BOX: nf_box(v, vid, ol, dl, t0, eps, sr, b); break;
+    case HEXCONE: nf_hexcone(v, vid, ol, dl, t0, eps, sr, b); break;
+  }
+}
+
+template <typename T> __device__ __forceinline__ V3<T> inv_dir(V3<T> d) {
+  return {T(1) / d.x, T(1) / d.y, T(1) / d.z};
+}
+
+// Non-sequential search: nearest face over the always-list and the grid
+// cells crossed by the ray's XY projection.
+// Recently tested volumes: a volume listed in several grid cells crossed by
+// one ray is tested once per search.
+struct Mailbox {
+  int m0, m1, m2, m3;
+  __device__ __forceinline__ bool seen(int v) const { return v == m0 || v == m1 || v == m2 || v == m3; }
+  __device__ __forceinline__ void put(int v) { m3 = m2; m2 = m1; m1 = m0; m0 = v; }
+};
+
+template <typename T> __device__ void find_nearest(const SceneView<T>& S, V3<double> O, V3<T> d, int prev_vol,
+                                                   int prev_face, int prev_side, Best<T>& b) {
+  b.t = tinf<T>(); b.vol = -1; b.face = -1; b.s = T(0); b.tp = 0.0;
+  Mailbox mb{prev_vol, -1, -1, -1};
+  V3<T> inv = inv_dir(d);
+  const V3<T> o = to_t<T>(O);
+  // the volume just left first: photons bouncing inside a cone or between
+  // facets usually meet it (or its neighbour) next, which tightens b.t early
+  if (prev_vol >= 0)
+    test_volume(S.vol[prev_vol], prev_vol, O, o, d, inv, prev_vol, prev_face, prev_side, S.eps_self, b);
+  for (int i = 0; i < S.n_always; ++i) {
+    int vid = S.always[i];
+    if (vid != prev_vol) test_volume(S.vol[vid], vid, O, o, d, inv, prev_vol, prev_face, prev_side, S.eps_self, b);
+  }
+  if (S.nx == 0) return;
+  // clip the XY projection to the grid rectangle
+  T gx1 = S.gx0 + T(S.nx) * S.cell, gy1 = S.gy0 + T(S.ny) * S.cell;
+  T ta = T(0), tb = tinf<T>();
+  if (d.x != T(0)) {
+    T t1 = (S.gx0 - o.x) * inv.x, t2 = (gx1 - o.x) * inv.x;
+    ta = dmax(ta, dmin(t1, t2)); tb = dmin(tb, dmax(t1, t2));
+  } else if (o.x < S.gx0 || o.x > gx1) return;
+  if (d.y != T(0)) {
+    T t1 = (S.gy0 - o.y) * inv.y, t2 = (gy1 - o.y) * inv.y;
+    ta = dmax(ta, dmin(t1, t2)); tb = dmin(tb, dmax(t1, t2));
+  } else if (o.y < S.gy0 || o.y > gy1) return;
+  if (!(ta <= tb)) return;
+  T px = o.x + ta * d.x, py = o.y + ta * d.y;
+  int ix = (int)dfloor((px - S.gx0) * S.inv_cell), iy = (int)dfloor((py - S.gy0) * S.inv_cell);
+  ix = ix < 0 ? 0 : (ix >= S.nx ? S.nx - 1 : ix);
+  iy = iy < 0 ? 0 : (iy >= S.ny ? S.ny - 1 : iy);
+  int sx = d.x > T(0) ? 1 : -1, sy = d.y > T(0) ? 1 : -1;
+  T tmx = d.x != T(0) ? (S.gx0 + T(ix + (d.x > T(0) ? 1 : 0)) * S.cell - o.x) * inv.x : tinf<T>();
+  T tmy = d.y != T(0) ? (S.gy0 + T(iy + (d.y > T(0) ? 1 : 0)) * S.cell - o.y) * inv.y : tinf<T>();
+  T tdx = d.x != T(0) ? S.cell * dabs(inv.x) : tinf<T>();
+  T tdy = d.y != T(0) ? S.cell * dabs(inv.y) : tinf<T>();
+  int guard = S.nx + S.ny + 2;
+  while (guard-- > 0) {
+    int cell = iy * S.nx + ix;
+    uint32_t i0 = S.cell_start[cell], i1 = S.cell_start[cell + 1];
+    for (uint32_t k = i0; k < i1; ++k) {
+      int vid = S.items[k];
+      if (!mb.seen(vid)) {
+        mb.put(vid);
+        test_volume(S.vol[vid], vid, O, o, d, inv, prev_vol, prev_face, prev_side, S.eps_self, b);
+      }
+    }
+    T tn = dmin(tmx, tmy);
+    if (tn > tb || tn >= b.t) break;
+    if (tmx < tmy) { ix += sx; tmx += tdx; if (ix < 0 || ix >= S.nx) break; }
+    else { iy += sy; tmy += tdy; if (iy < 0 || iy >= S.ny) break; }
+  }
+}
+
+// front normal (world) of the face hit, at world point X
+// Front normal (world, double) of the face hit at world point X (double):
+// local point, gradient and normalisation in double from the record.
+template <typename T> __device__ __forceinline__ V3<double> front_normal(const DVol<T>& v, int face, V3<double> X,
+                                                                        double s) {
+  double rx = X.x - (double)v.c[0], ry = X.y - (double)v.c[1], rz = X.z - (double)v.c[2];
+  double Q[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Q[i] = (double)v.Q[i];
+  V3<double> x = {Q[0] * rx + Q[1] * ry + Q[2] * rz, Q[3] * rx + Q[4] * ry + Q[5] * rz,
+                  Q[6] * rx + Q[7] * ry + Q[8] * rz};
+  V3<double> g = local_grad<double>(v, face, x, s);
+  V3<double> w = {Q[0] * g.x + Q[3] * g.y + Q[6] * g.z, Q[1] * g.x + Q[4] * g.y + Q[7] * g.z,
+                  Q[2] * g.x + Q[5] * g.y + Q[8] * g.z};
+  return scl(1.0 / dsqrt(dot(w, w)), w);
+}
+
+template <typename T> __device__ __forceinline__ T fresnel_R(T cos_i, T n1, T n2, T& cos_t) {
+  T eta = n1 / n2;
+  T s2 = eta * eta * (T(1) - cos_i * cos_i);
+  if (s2 >= T(1)) { cos_t = T(0); return T(1); }
+  cos_t = dsqrt(T(1) - s2);
+  T rs = (n1 * cos_i - n2 * cos_t) / (n1 * cos_i + n2 * cos_t);
+  T rp = (n2 * cos_i - n1 * cos_t) / (n2 * cos_i + n1 * cos_t);
+  return T(0.5) * (rs * rs + rp * rp);
+}
+
+enum { ACT_REFLECT = 0, ACT_REFRACT = 1, ACT_STOP = 2 };
+
+// Apply the interaction of the event at X on (vol, face).  Updates d, ncur,
+// fate; returns the action.  `back` is set from the side the photon came from.
+template <typename C, typename T> __device__ __forceinline__ int interact(const DVol<T>& v, V3<C> n, V3<C>& d,
+                                                                          C& ncur, int& fate, int& back,
+                                                                          uint64_t seed, uint64_t id, int k) {
+  C dn = dot(d, n);
+  back = dn < C(0) ? 0 : 1;
+  switch (v.role) {
+    case FOCAL: fate = back ? ABSORBED : FOCUSED; return ACT_STOP;
+    case OBSCURATION: fate = ABSORBED; return ACT_STOP;
+    case MIRROR: {
+      if (back) { fate = ABSORBED; return ACT_STOP; }
+      if (!v.always_reflect) {
+        uint32_t u = philox_word(seed, id, k);
+        if (u >= v.thr) { fate = ABSORBED; return ACT_STOP; }
+      }
+      d = fma3(C(-2) * dn, n, d);
+      return ACT_REFLECT;
+    }
+    case LENS: {
+      C nin = (C)v.n_in;
+      C n1 = back ? nin : C(1), n2 = back ? C(1) : nin;
+      V3<C> no = back ? scl(C(-1), n) : n;
+      C cos_i = -dot(d, no), cos_t;
+      C R = fresnel_R(cos_i, n1, n2, cos_t);
+      uint32_t u = philox_word(seed, id, k);
+      if (C(u >> 8) * C(1.0 / 16777216.0) < R) {
+        d = fma3(C(-2) * dot(d, no), no, d);
+        return ACT_REFLECT;
+      }
+      C eta = n1 / n2;
+      d = fma3(eta * cos_i - cos_t, no, scl(eta, d));
+      ncur = n2;
+      return ACT_REFRACT;
+    }
+  }
+  fate = FAILED;
+  return ACT_STOP;
+}
+
+template <typename T> struct PhotonOut {
+  int fate, nev, last_vol;
+  V3<T> pos, dir;
+  T opl;
+  uint64_t hash;
+};
+
+// Full non-sequential transport of one photon.  If `codes` is non-null the
+// event sequence (vol << 8 | face << 4 | action) is written to it.
+template <typename T, int MAXLOG>
+__device__ __forceinline__ PhotonOut<T> trace_photon(const SceneView<T>& S, V3<T> o_in, V3<T> d, uint64_t id,
+                                                     uint32_t* codes) {
+  V3<double> o = {(double)o_in.x, (double)o_in.y, (double)o_in.z};
+  // direction state in double; the search uses its rounding to T
+  V3<double> dd = {(double)d.x, (double)d.y, (double)d.z};
+  PhotonOut<T> r;
+  r.fate = 0; r.last_vol = -1; r.opl = T(0); r.hash = 0xcbf29ce484222325ull;
+  double ncur = 1.0, opl = 0.0;
+  int prev_v = -1, prev_f = -1, prev_side = 0;
+  int k = 0;
+  if (!finite3(o_in) || !finite3(d) || dot(d, d) == T(0)) r.fate = FAILED;
+  while (!r.fate) {
+    if (k == S.max_events) { r.fate = SUSPENDED; break; }
+    Best<T> b;
+    find_nearest(S, o, d, prev_v, prev_f, prev_side, b);
+    if (b.vol < 0) { r.fate = EXITED; break; }
+    const DVol<T>& v = S.vol[b.vol];
+    V3<double> X = {o.x + b.tp * dd.x, o.y + b.tp * dd.y, o.z + b.tp * dd.z};
+    opl += ncur * b.tp;
+    V3<double> n = front_normal(v, b.face, X, (double)b.s);
+    int back, fate = 0;
+    int act = interact<double>(v, n, dd, ncur, fate, back, S.seed, id, k);
+    d = to_t<T>(dd);
+    r.hash = (r.hash ^ (((uint64_t)b.vol << 4) | ((uint64_t)b.face << 1) | (uint64_t)back)) * 0x100000001b3ull;
+    r.last_vol = b.vol;
+    if (codes && k < MAXLOG) codes[k] = ((uint32_t)b.vol << 8) | ((uint32_t)b.face << 4) | (uint32_t)act;
+    o = X;
+    prev_v = b.vol; prev_f = b.face;
+    // side of the face just left: reflection keeps the photon on the side it
+    // came from, refraction moves it across
+    prev_side = back ^ (act == ACT_REFRACT ? 1 : 0);
+    ++k;
+    if (fate) { r.fate = fate; break; }
+    if (!finite3(dd)) { r.fate = FAILED; break; }
+  }
+  r.nev = k; r.pos = to_t<T>(o); r.dir = to_t<T>(dd); r.opl = (T)opl;
+  return r;
+}
+
+}  // namespace robast

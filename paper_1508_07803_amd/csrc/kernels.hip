@@ -1,0 +1,201 @@
+// Forward trace kernels and the figures kernel (gfx950, wave64).
+//
+// One lane traces one photon at a time, start to finish (the event loop of
+// the non-sequential trace, §2.1), over a persistent grid-stride loop.  Each
+// workgroup stages the scene blob (volume records + candidate grid) into LDS
+// once and reuses it for every photon it traces.  Per-group figure sums are
+// kept per lane in FP64 registers, flushed wave-synchronously into LDS when
+// any lane's group changes, and added to global memory once per workgroup.
+#include <hip/hip_runtime.h>
+
+#include "device_trace.hpp"
+#include "kernels.hpp"
+
+namespace robast {
+
+constexpr int kBlock = 256;
+constexpr int kNSum = 7;  // launched, focused, x, y, x^2, y^2, |u_z|
+
+// With USE_LDS the scene pointers are derived from the LDS array only, so the
+// compiler addresses them as LDS (ds_read) rather than through flat loads.
+template <typename T, bool USE_LDS>
+__device__ __forceinline__ void stage_scene(const SceneView<T>& S, SceneView<T>& L, char* lds) {
+  L = S;
+  if (!USE_LDS) return;
+  const uint4* src = reinterpret_cast<const uint4*>(S.blob);
+  uint4* dst = reinterpret_cast<uint4*>(lds);
+  uint32_t n16 = S.blob_bytes / 16u;
+  for (uint32_t i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
+  const char* base = S.blob;
+  L.vol = reinterpret_cast<const DVol<T>*>(lds);
+  L.always = reinterpret_cast<const uint16_t*>(lds + (reinterpret_cast<const char*>(S.always) - base));
+  L.cell_start = reinterpret_cast<const uint32_t*>(lds + (reinterpret_cast<const char*>(S.cell_start) - base));
+  L.items = reinterpret_cast<const uint16_t*>(lds + (reinterpret_cast<const char*>(S.items) - base));
+}
+
+__device__ __forceinline__ void flush_lane(double* acc_lds, int g, const double* a) {
+  if (g < 0) return;
+#pragma unroll
+  for (int k = 0; k < kNSum; ++k)
+    if (a[k] != 0.0) atomicAdd(acc_lds + g * 8 + k, a[k]);
+}
+
+template <typename T, bool RECORD, bool SUMS, bool USE_LDS>
+__global__ void __launch_bounds__(kBlock) k_trace(SceneView<T> S, RaysView<T> R, int64_t n, HitsView<T> H,
+                                                  int sums_in_lds) {
+  extern __shared__ __align__(16) char lds[];
+  SceneView<T> L;
+  stage_scene<T, USE_LDS>(S, L, lds);
+  double* acc = reinterpret_cast<double*>(lds + (USE_LDS ? ((S.blob_bytes + 15u) & ~15u) : 0u));
+  if (SUMS && sums_in_lds) {
+    for (int i = threadIdx.x; i < S.n_groups * 8; i += blockDim.x) acc[i] = 0.0;
+  }
+  __syncthreads();
+
+  double a[kNSum];
+#pragma unroll
+  for (int k = 0; k < kNSum; ++k) a[k] = 0.0;
+  int ag = -1;
+  double* acc_target = (SUMS && sums_in_lds) ? acc : H.sums;
+
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // all lanes of a wave run the same number of iterations (wave-uniform loop
+  // bound), so the wave-synchronous flush below is well defined
+  const int64_t wave_first = first - (threadIdx.x & 63);
+  const int64_t iters = wave_first < n ? (n - wave_first + stride - 1) / stride : 0;
+  for (int64_t it = 0; it < iters; ++it) {
+    int64_t i = first + it * stride;
+    bool live = i < n;
+    int g = -1;
+    PhotonOut<T> r;
+    if (live) {
+      V3<T> o = {R.ox[i], R.oy[i], R.oz[i]};
+      V3<T> d = {R.dx[i], R.dy[i], R.dz[i]};
+      g = R.group ? (int)R.group[i] : 0;
+      // a group id outside [0, n_groups) is traced but never accumulated
+      if ((unsigned)g >= (unsigned)S.n_groups) g = -1;
+      r = trace_photon<T, 0>(L, o, d, R.id_base + (uint64_t)i, nullptr);
+      if (RECORD) {
+        if (H.fate) H.fate[i] = (uint8_t)r.fate;
+        if (H.nev) H.nev[i] = (uint8_t)r.nev;
+        if (H.last_vol) H.last_vol[i] = r.last_vol;
+        if (H.x) { H.x[i] = r.pos.x; H.y[i] = r.pos.y; H.z[i] = r.pos.z; }
+        if (H.ux) { H.ux[i] = r.dir.x; H.uy[i] = r.dir.y; H.uz[i] = r.dir.z; }
+        if (H.opl) H.opl[i] = r.opl;
+        if (H.hash) H.hash[i] = r.hash;
+      }
+    }
+    if (SUMS) {
+      // wave-uniform flush when any lane's group changes
+      bool change = live && g >= 0 && g != ag && ag >= 0;
+      if (__any(change)) {
+        flush_lane(acc_target, ag, a);
+#pragma unroll
+        for (int k = 0; k < kNSum; ++k) a[k] = 0.0;
+        ag = -1;
+      }
+      if (live && g >= 0) {
+        ag = g;
+        a[0] += 1.0;
+        if (r.fate == FOCUSED) {
+          double x = (double)r.pos.x, y = (double)r.pos.y;
+          a[1] += 1.0; a[2] += x; a[3] += y; a[4] += x * x; a[5] += y * y;
+          a[6] += (double)dabs(r.dir.z);
+        }
+      }
+    }
+  }
+  if (SUMS) {
+    flush_lane(acc_target, ag, a);
+    if (sums_in_lds) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < S.n_groups * 8; i += blockDim.x)
+        if (acc[i] != 0.0) atomicAdd(H.sums + i, acc[i]);
+    }
+  }
+}
+
+// Figures per group from the accumulated sums (§3: spot RMS, efficiency).
+__global__ void k_figures(const double* sums, double* fig, int n_groups) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_groups) return;
+  const double* s = sums + g * 8;
+  double nl = s[0], nf = s[1];
+  double cx = nf > 0 ? s[2] / nf : 0.0, cy = nf > 0 ? s[3] / nf : 0.0;
+  double var = nf > 0 ? (s[4] / nf - cx * cx) + (s[5] / nf - cy * cy) : 0.0;
+  double* f = fig + g * 8;
+  f[0] = nl; f[1] = nf; f[2] = cx; f[3] = cy;
+  f[4] = var > 0 ? sqrt(var) : 0.0;
+  f[5] = nl > 0 ? nf / nl : 0.0;
+  f[6] = nl > 0 ? s[6] / nl : 0.0;
+  f[7] = 0.0;
+}
+
+// ------------------------------------------------------------------ launchers
+static int g_num_cu = 0;
+
+static hipError_t device_cus(int& ncu) {
+  if (g_num_cu == 0) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&g_num_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+  }
+  ncu = g_num_cu;
+  return hipSuccess;
+}
+
+template <typename T, bool RECORD, bool SUMS, bool USE_LDS>
+static hipError_t launch_one_l(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const HitsView<T>& H,
+                             const LaunchCfg& cfg, hipStream_t st) {
+  int ncu = 0;
+  hipError_t e = device_cus(ncu);
+  if (e != hipSuccess) return e;
+  const bool use_lds = USE_LDS;
+  size_t sums_bytes = (size_t)S.n_groups * 8 * sizeof(double);
+  bool sums_lds = SUMS && sums_bytes <= 16384;
+  size_t shmem = (use_lds ? ((S.blob_bytes + 15u) & ~15u) : 0u) + (sums_lds ? sums_bytes : 0);
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace<T, RECORD, SUMS, USE_LDS>, kBlock, shmem);
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
+  int64_t want = (n + kBlock - 1) / kBlock;
+  int64_t cap = (int64_t)ncu * per_cu * (cfg.waves_mult > 0 ? cfg.waves_mult : 1);
+  if (cfg.max_blocks > 0) cap = std::min<int64_t>(cap, cfg.max_blocks);
+  int blocks = (int)std::max<int64_t>(1, std::min(want, cap));
+  hipLaunchKernelGGL((k_trace<T, RECORD, SUMS, USE_LDS>), dim3(blocks), dim3(kBlock), shmem, st, S, R, n, H,
+                     sums_lds ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <typename T, bool RECORD, bool SUMS>
+static hipError_t launch_one(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const HitsView<T>& H,
+                             const LaunchCfg& cfg, hipStream_t st) {
+  bool use_lds = cfg.lds_cap > 0 && S.blob_bytes <= (uint32_t)cfg.lds_cap;
+  if (use_lds) return launch_one_l<T, RECORD, SUMS, true>(S, R, n, H, cfg, st);
+  return launch_one_l<T, RECORD, SUMS, false>(S, R, n, H, cfg, st);
+}
+
+template <typename T>
+hipError_t launch_trace(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const HitsView<T>& H,
+                        const LaunchCfg& cfg, hipStream_t st) {
+  bool rec = H.fate || H.nev || H.last_vol || H.x || H.ux || H.opl || H.hash;
+  bool sums = H.sums != nullptr;
+  if (rec && sums) return launch_one<T, true, true>(S, R, n, H, cfg, st);
+  if (rec) return launch_one<T, true, false>(S, R, n, H, cfg, st);
+  if (sums) return launch_one<T, false, true>(S, R, n, H, cfg, st);
+  return launch_one<T, true, false>(S, R, n, H, cfg, st);
+}
+
+hipError_t launch_figures(const double* sums, double* fig, int n_groups, hipStream_t st) {
+  hipLaunchKernelGGL(k_figures, dim3((n_groups + 63) / 64), dim3(64), 0, st, sums, fig, n_groups);
+  return hipGetLastError();
+}
+
+template hipError_t launch_trace<float>(const SceneView<float>&, const RaysView<float>&, int64_t,
+                                        const HitsView<float>&, const LaunchCfg&, hipStream_t);
+template hipError_t launch_trace<double>(const SceneView<double>&, const RaysView<double>&, int64_t,
+                                         const HitsView<double>&, const LaunchCfg&, hipStream_t);
+
+}  // namespace robast

@@ -1,0 +1,60 @@
+// Device scene layout shared by the host scene compiler and the kernels.
+//
+// A compiled scene is one contiguous blob (staged into LDS by each workgroup
+// when it fits):
+//   [DVol<T> x n_vol] [u16 always-list] [u32 cell_start x (ncell + 1)] [u16 cell items]
+// The XY uniform grid lists, per cell, every volume whose world AABB overlaps
+// the cell's column; volumes too large for the grid go on the always-list and
+// are tested for every photon.  The grid is only a candidate filter: a
+// volume's exact intersection is always computed in its own frame.
+#pragma once
+#include <cstdint>
+
+namespace robast {
+
+enum Role { MIRROR = 1, LENS = 2, FOCAL = 3, OBSCURATION = 4 };
+enum Shape { PLANE = 1, SPHERE = 2, ASPHERE = 3, CYLINDER = 4, BOX = 5, HEXCONE = 6 };
+enum Outline { OL_NONE = 0, OL_DISC = 1, OL_ANNULUS = 2, OL_RECT = 3, OL_HEX = 4, OL_SECTOR = 5 };
+enum Fate { FOCUSED = 1, ABSORBED = 2, EXITED = 3, SUSPENDED = 4, FAILED = 5 };
+
+// Per-volume record, precision T.
+//   p (shape, derived): SPHERE {c}; ASPHERE {rn, b1..b8, 1/rn^2}; CYLINDER {rho, h};
+//     BOX {hx, hy, hz}; HEXCONE {rho0 z0 rho1 z1 rho2 z2 rho3 z3}
+//   o (outline, derived): DISC {r^2}; ANNULUS {rin^2, rout^2}; RECT {hx, hy};
+//     HEX {a}; SECTOR {rin^2, rout^2, cos phi0, sin phi0, cos phi1, sin phi1, wide}
+//   lo/hi: local-frame box of the surface (asphere z-slab for bracketing)
+//   bmin/bmax: world AABB; slope: max |grad sag| of a sag surface on its outline
+template <typename T> struct alignas(16) DVol {
+  T bmin[3], bmax[3];    // world AABB first: the candidate test reads only these and `shape`
+  int32_t shape, role;
+  int32_t outline, nfaces, sparam, tparam, always_reflect;
+  uint32_t thr;          // mirrors: absorb iff draw >= thr (unless always_reflect)
+  T Q[9];
+  T c[3];
+  T p[12];
+  T o[8];
+  T lo[3], hi[3];
+  T n_in, slope, rout, pad;
+};
+
+// Tilt data used only by the adjoint: pivot and the two world rotation axes
+// a1 = Rot(e2, beta) e1, a2 = e2 of the current tilt.
+struct DTilt {
+  double pivot[3], a1[3], a2[3];
+};
+
+template <typename T> struct SceneView {
+  const DVol<T>* vol;
+  const uint16_t* always;
+  const uint32_t* cell_start;
+  const uint16_t* items;
+  int32_t n_vol, n_always, nx, ny;
+  T gx0, gy0, inv_cell, cell;      // grid origin and cell size (world XY)
+  int32_t max_events, n_groups;
+  uint64_t seed;
+  T eps_self;                      // self-intersection guard for the face just left
+  uint32_t blob_bytes;             // size of the blob (for LDS staging)
+  const char* blob;                // start of the blob (== vol)
+};
+
+}  // namespace robast

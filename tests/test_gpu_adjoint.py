@@ -1,0 +1,165 @@
+"""Reverse-mode gradients of the HIP library against the FP64 oracle.
+
+The oracle's gradient is the pathwise (fixed-sequence) derivative by dual
+numbers along each photon's recorded surface sequence; its dual numbers are
+themselves pinned to central finite differences of forced sequences and to a
+closed-form derivative (tests/test_oracle_pins.py).  Bar per component:
+|g_gpu - g_ref| <= 1e-3 * max(|g_ref|, floor * max|g_ref|), with floor 1e-3
+for FP64 scenes and 1e-2 for FP32 scenes, whose focal positions carry FP32
+rounding into the centroid-subtracted cotangents of small components.
+"""
+import numpy as np
+import pytest
+
+import scenes
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rb():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1508_07803_amd as rb
+    return rb
+
+
+def gpu_grad(rb, sc, r, w_rms=None, w_eff=None, id_base=0):
+    dev = rb.Scene(sc)
+    rays = dev.upload_rays(r)
+    sums = dev.new_sums()
+    dev.trace(rays, sums=sums, id_base=id_base)
+    cot = torch.zeros(sc.n_groups, 2, dtype=torch.float64, device="cuda")
+    if w_rms is not None:
+        cot[:, 0] = torch.as_tensor(w_rms, dtype=torch.float64)
+    if w_eff is not None:
+        cot[:, 1] = torch.as_tensor(w_eff, dtype=torch.float64)
+    grad = torch.zeros(len(sc.params), dtype=torch.float64, device="cuda")
+    dev.backward(rays, sums, cot, grad, id_base=id_base)
+    torch.cuda.synchronize()
+    out = grad.cpu().numpy()
+    dev.close()
+    return out
+
+
+def check(g, ref, floor, names):
+    scale = np.abs(ref).max()
+    assert scale > 0
+    err = np.abs(g - ref) / np.maximum(np.abs(ref), floor * scale)
+    worst = int(np.argmax(err))
+    assert err.max() <= 1e-3, f"{names[worst]}: gpu {g[worst]:.6e} ref {ref[worst]:.6e} (rel {err.max():.2e})"
+    return err.max()
+
+
+def test_single_mirror_radius_fp64(rb):
+    import oracle
+    sc = scenes.single_mirror()
+    r = sc.rays(50000)
+    g = gpu_grad(rb, sc, r, w_rms=[1.0])
+    rec = oracle.trace(sc, r, log=True)
+    ref = oracle.gradient_rms(sc, r, rec, [1.0])
+    assert abs(g[0] - ref[0]) <= 1e-9 * abs(ref[0])
+
+
+@pytest.mark.parametrize("precision,n_per,floor", [(32, 3000, 1e-2), (64, 1000, 1e-3)])
+def test_sc_rms_gradient(rb, precision, n_per, floor):
+    import oracle
+    sc = scenes.schwarzschild_couder(precision=precision)
+    r = sc.rays(n_per)
+    w = np.full(sc.n_groups, 1.0 / sc.n_groups)
+    g = gpu_grad(rb, sc, r, w_rms=w)
+    rec = oracle.trace(sc, r, log=True)
+    ref = oracle.gradient_rms(sc, r, rec, w)
+    e = check(g, ref, floor, sc.param_names)
+    print(f"SC fp{precision}: 160 params, worst rel {e:.2e}")
+
+
+@pytest.mark.parametrize("precision,n_per,floor", [(32, 10000, 1e-2), (64, 2000, 1e-3)])
+def test_dc_rms_gradient(rb, precision, n_per, floor):
+    import oracle
+    sc = scenes.davies_cotton(precision=precision)
+    r = sc.rays(n_per)
+    w = np.full(sc.n_groups, 1.0 / sc.n_groups)
+    g = gpu_grad(rb, sc, r, w_rms=w)
+    rec = oracle.trace(sc, r, log=True)
+    ref = oracle.gradient_rms(sc, r, rec, w)
+    e = check(g, ref, floor, sc.param_names)
+    print(f"DC fp{precision}: 594 params, worst rel {e:.2e}")
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_concentrator_weighted_collection_gradient(rb, precision):
+    import oracle
+    sc = scenes.hex_concentrator(precision=precision)
+    r = sc.rays(300)
+    w = np.full(sc.n_groups, 1.0 / sc.n_groups)
+    g = gpu_grad(rb, sc, r, w_eff=w)
+    rec = oracle.trace(sc, r, log=True)
+    ref = oracle.gradient_eff_w(sc, r, rec, w)
+    e = check(g, ref, 1e-3, sc.param_names)
+    print(f"cone fp{precision}: 4 control scalars, worst rel {e:.2e}")
+
+
+def test_gradient_matches_central_fd_of_forced_sequences(rb):
+    """GPU adjoint vs central finite differences of the oracle's forced
+    sequences (same photons, fates frozen) for a sample of parameters."""
+    import oracle
+    sc = scenes.schwarzschild_couder(precision=64)
+    r = sc.rays(500)
+    w = np.full(sc.n_groups, 1.0 / sc.n_groups)
+    g = gpu_grad(rb, sc, r, w_rms=w)
+    rec = oracle.trace(sc, r, log=True)
+    foc = rec["fate"] == scenes.FATE_FOCUSED
+    grp = rec["group"].astype(int)
+
+    def loss(P):
+        pos, _, st = oracle.forced(sc, r, rec, P)
+        tot = 0.0
+        for k in range(sc.n_groups):
+            m = foc & (grp == k)
+            x, y = pos[m, 0], pos[m, 1]
+            tot += w[k] * np.sqrt(np.mean((x - x.mean()) ** 2 + (y - y.mean()) ** 2))
+        return tot
+
+    for j in (0, 2, 8, 11, 16, 40, 100, 159):
+        h = 1e-7 if "tilt" in sc.param_names[j] else 1e-6 * abs(sc.params[j])
+        P1, P2 = sc.params.copy(), sc.params.copy()
+        P1[j] += h; P2[j] -= h
+        fd = (loss(P1) - loss(P2)) / (2 * h)
+        assert abs(g[j] - fd) <= 1e-3 * max(abs(fd), 1e-3 * np.abs(g).max()), sc.param_names[j]
+
+
+def test_backward_split_launches_add_up(rb):
+    """Gradients accumulate (+=): two launches over halves equal one launch."""
+    sc = scenes.schwarzschild_couder()
+    r = sc.rays(2000)
+    dev = rb.Scene(sc)
+    rays = dev.upload_rays(r)
+    n = len(r["ox"])
+    sums = dev.new_sums()
+    dev.trace(rays, sums=sums)
+    cot = torch.zeros(sc.n_groups, 2, dtype=torch.float64, device="cuda")
+    cot[:, 0] = 1.0 / sc.n_groups
+    g1 = torch.zeros(len(sc.params), dtype=torch.float64, device="cuda")
+    dev.backward(rays, sums, cot, g1)
+    g2 = torch.zeros_like(g1)
+    h = n // 3
+    dev.backward({k: v[:h] for k, v in rays.items()}, sums, cot, g2, n=h)
+    dev.backward({k: v[h:] for k, v in rays.items()}, sums, cot, g2, n=n - h, id_base=h)
+    torch.cuda.synchronize()
+    assert torch.allclose(g1, g2, rtol=1e-9, atol=1e-12 * float(g1.abs().max()))
+
+
+def test_autograd_function(rb):
+    """torch.autograd through RobastTrace: d(mean RMS)/d(params)."""
+    sc = scenes.schwarzschild_couder()
+    r = sc.rays(1000)
+    dev = rb.Scene(sc)
+    rays = dev.upload_rays(r)
+    params = torch.tensor(sc.params, dtype=torch.float64, requires_grad=True)
+    fig = rb.RobastTrace.apply(params, dev, rays)
+    loss = fig[:, 4].mean()
+    loss.backward()
+    ref = gpu_grad(rb, sc, r, w_rms=np.full(sc.n_groups, 1.0 / sc.n_groups))
+    assert np.allclose(params.grad.numpy(), ref, rtol=1e-9, atol=1e-12 * np.abs(ref).max())
