@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -339,6 +340,224 @@ template <typename T> void align_to(std::vector<char>& b, size_t a) {
   while (b.size() % a) b.push_back(0);
 }
 
+// Points on a volume's surface (world), spaced about h apart.
+void surface_samples(const robast_volume_desc& v, double h, std::vector<std::array<double, 3>>& out) {
+  double I[9];
+  inv3(v.Q, I);
+  auto emit = [&](double x, double y, double z) {
+    std::array<double, 3> w;
+    for (int i = 0; i < 3; ++i) w[i] = v.c[i] + I[3 * i] * x + I[3 * i + 1] * y + I[3 * i + 2] * z;
+    out.push_back(w);
+  };
+  double slope;
+  Box3 lb = local_bounds(v, slope);
+  switch (v.shape) {
+    case ROBAST_PLANE: case ROBAST_SPHERE: case ROBAST_ASPHERE: {
+      const double* o = v.o;
+      auto inside = [&](double x, double y) {
+        double r = std::hypot(x, y);
+        switch (v.outline) {
+          case ROBAST_DISC: return r <= o[0] + h;
+          case ROBAST_ANNULUS: return r >= o[0] - h && r <= o[1] + h;
+          case ROBAST_RECT: return std::fabs(x) <= o[0] + h && std::fabs(y) <= o[1] + h;
+          case ROBAST_HEX:
+            for (int k = 0; k < 3; ++k)
+              if (std::fabs(x * std::cos(k * M_PI / 3) + y * std::sin(k * M_PI / 3)) > o[0] + h) return false;
+            return true;
+          case ROBAST_SECTOR: {
+            if (r < o[0] - h || r > o[1] + h) return false;
+            if (o[3] - o[2] >= 2 * M_PI - 1e-12) return true;
+            double ph = std::atan2(y, x) - o[2];
+            ph = std::fmod(ph, 2 * M_PI);
+            if (ph < 0) ph += 2 * M_PI;
+            double tol = r > h ? h / r : M_PI;
+            return ph <= o[3] - o[2] + tol || ph >= 2 * M_PI - tol;
+          }
+        }
+        return true;
+      };
+      auto sag = [&](double x, double y) {
+        double r2 = x * x + y * y;
+        if (v.shape == ROBAST_SPHERE) {
+          double c = v.p[0], q = 1.0 - c * c * r2;
+          return q > 0 ? c * r2 / (1.0 + std::sqrt(q)) : 1.0 / c;
+        }
+        if (v.shape == ROBAST_ASPHERE) return sag_asph(v.p + 1, r2 / (v.p[0] * v.p[0]));
+        return 0.0;
+      };
+      for (double x = lb.lo[0]; x <= lb.hi[0] + h; x += h)
+        for (double y = lb.lo[1]; y <= lb.hi[1] + h; y += h) {
+          double xx = std::min(x, lb.hi[0]), yy = std::min(y, lb.hi[1]);
+          if (inside(xx, yy)) emit(xx, yy, sag(xx, yy));
+        }
+      break;
+    }
+    case ROBAST_CYLINDER: {
+      int nt = std::max(8, (int)std::ceil(2 * M_PI * v.p[0] / h));
+      for (int i = 0; i < nt; ++i)
+        for (double z = 0; z <= v.p[1] + h; z += h)
+          emit(v.p[0] * std::cos(2 * M_PI * i / nt), v.p[0] * std::sin(2 * M_PI * i / nt), std::min(z, v.p[1]));
+      break;
+    }
+    case ROBAST_BOX: case ROBAST_HEXCONE: default: {
+      // the local box (conservative: its points cover the surface's projection)
+      for (double x = lb.lo[0]; x <= lb.hi[0] + h; x += h)
+        for (double y = lb.lo[1]; y <= lb.hi[1] + h; y += h)
+          for (int zz = 0; zz < 2; ++zz)
+            emit(std::min(x, lb.hi[0]), std::min(y, lb.hi[1]), zz ? lb.hi[2] : lb.lo[2]);
+      break;
+    }
+  }
+}
+
+struct GroupBuild {
+  double Q[9], c[3];
+  std::vector<int> members;
+  double zmin = 1e300, zmax = -1e300, x0 = 1e300, y0 = 1e300, x1 = -1e300, y1 = -1e300, cell = 1.0;
+  int nx = 0, ny = 0;
+  std::vector<std::vector<uint16_t>> cells;
+};
+
+void to_group(const GroupBuild& g, const double* w, double* x) {
+  double r[3] = {w[0] - g.c[0], w[1] - g.c[1], w[2] - g.c[2]};
+  for (int i = 0; i < 3; ++i) x[i] = g.Q[3 * i] * r[0] + g.Q[3 * i + 1] * r[1] + g.Q[3 * i + 2] * r[2];
+}
+
+// Partition the volumes into the always-list and candidate groups and
+// rasterise each group's members onto its grid.
+void build_groups(const robast_scene& s, const std::vector<Box3>& wb, std::vector<uint16_t>& always,
+                  std::vector<GroupBuild>& groups) {
+  int nv = s.n_vol;
+  always.clear();
+  groups.clear();
+  if (nv <= 4) {
+    for (int i = 0; i < nv; ++i) always.push_back((uint16_t)i);
+    return;
+  }
+  double ux0 = 1e300, uy0 = 1e300, uz0 = 1e300, ux1 = -1e300, uy1 = -1e300, uz1 = -1e300;
+  for (int i = 0; i < nv; ++i) {
+    ux0 = std::min(ux0, wb[i].lo[0]); uy0 = std::min(uy0, wb[i].lo[1]); uz0 = std::min(uz0, wb[i].lo[2]);
+    ux1 = std::max(ux1, wb[i].hi[0]); uy1 = std::max(uy1, wb[i].hi[1]); uz1 = std::max(uz1, wb[i].hi[2]);
+  }
+  double uarea = (ux1 - ux0) * (uy1 - uy0), uz = uz1 - uz0;
+  std::vector<double> fa(nv);
+  for (int i = 0; i < nv; ++i) fa[i] = (wb[i].hi[0] - wb[i].lo[0]) * (wb[i].hi[1] - wb[i].lo[1]);
+  std::vector<double> fs = fa;
+  std::nth_element(fs.begin(), fs.begin() + nv / 2, fs.end());
+  double fmed = fs[nv / 2];
+  std::vector<int> rest;
+  std::vector<char> placed(nv, 0);
+  // always-list: volumes covering much of the scene, and long slanted ones
+  // (struts) that would merge separate z-layers
+  for (int i = 0; i < nv; ++i) {
+    double z = wb[i].hi[2] - wb[i].lo[2];
+    if (fa[i] > 0.2 * uarea || (uz > 0 && z > 0.5 * uz && fa[i] > 10.0 * fmed)) {
+      always.push_back((uint16_t)i);
+      placed[i] = 1;
+    }
+  }
+  // panels sharing one untilted frame: a group in that frame
+  for (int i = 0; i < nv; ++i) {
+    const robast_volume_desc& v = s.desc[i];
+    if (placed[i] || v.tilt_param < 0) continue;
+    GroupBuild g;
+    std::memcpy(g.Q, v.Q0, sizeof g.Q);
+    std::memcpy(g.c, v.c0, sizeof g.c);
+    for (int j = i; j < nv; ++j) {
+      const robast_volume_desc& u = s.desc[j];
+      if (placed[j] || u.tilt_param < 0) continue;
+      if (std::memcmp(u.Q0, v.Q0, sizeof u.Q0) == 0 && std::memcmp(u.c0, v.c0, sizeof u.c0) == 0) {
+        g.members.push_back(j);
+        placed[j] = 1;
+      }
+    }
+    if (g.members.size() >= 2) groups.push_back(g);
+    else for (int j : g.members) placed[j] = 0;
+    if (g.members.size() < 2) rest.push_back(i), placed[i] = 1;
+  }
+  for (int i = 0; i < nv; ++i)
+    if (!placed[i]) rest.push_back(i);
+  // world-frame layers of overlapping z-extent
+  std::sort(rest.begin(), rest.end(), [&](int a, int b) { return wb[a].lo[2] < wb[b].lo[2]; });
+  for (size_t k = 0; k < rest.size();) {
+    GroupBuild g;
+    const double I[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    std::memcpy(g.Q, I, sizeof g.Q);
+    g.c[0] = g.c[1] = g.c[2] = 0.0;
+    double top = wb[rest[k]].hi[2];
+    size_t j = k;
+    while (j < rest.size() && wb[rest[j]].lo[2] <= top) {
+      top = std::max(top, wb[rest[j]].hi[2]);
+      g.members.push_back(rest[j]);
+      ++j;
+    }
+    k = j;
+    if (g.members.size() >= 2) groups.push_back(g);
+    else always.push_back((uint16_t)g.members[0]);
+  }
+  // rasterise
+  for (GroupBuild& g : groups) {
+    std::vector<double> areas;
+    for (int m : g.members) {
+      double slope;
+      Box3 lb = local_bounds(s.desc[m], slope);
+      double I[9];
+      inv3(s.desc[m].Q, I);
+      double mx0 = 1e300, my0 = 1e300, mx1 = -1e300, my1 = -1e300;
+      for (int cc = 0; cc < 8; ++cc) {
+        double xl[3] = {(cc & 1) ? lb.hi[0] : lb.lo[0], (cc & 2) ? lb.hi[1] : lb.lo[1], (cc & 4) ? lb.hi[2] : lb.lo[2]};
+        double w[3], x[3];
+        for (int i = 0; i < 3; ++i)
+          w[i] = s.desc[m].c[i] + I[3 * i] * xl[0] + I[3 * i + 1] * xl[1] + I[3 * i + 2] * xl[2];
+        to_group(g, w, x);
+        g.zmin = std::min(g.zmin, x[2]); g.zmax = std::max(g.zmax, x[2]);
+        mx0 = std::min(mx0, x[0]); mx1 = std::max(mx1, x[0]); my0 = std::min(my0, x[1]); my1 = std::max(my1, x[1]);
+      }
+      g.x0 = std::min(g.x0, mx0); g.x1 = std::max(g.x1, mx1); g.y0 = std::min(g.y0, my0); g.y1 = std::max(g.y1, my1);
+      areas.push_back(std::max((mx1 - mx0) * (my1 - my0), 1e-30));
+    }
+    double zp = 1e-5 * (g.zmax - g.zmin + s.l_ref);
+    g.zmin -= zp; g.zmax += zp;
+    double xp = 1e-5 * (g.x1 - g.x0 + g.y1 - g.y0 + s.l_ref);
+    g.x0 -= xp; g.y0 -= xp; g.x1 += xp; g.y1 += xp;
+    // cell from the median footprint of the members that have one (walls
+    // seen edge-on have none), at least 1/256 of the group's extent
+    double W = g.x1 - g.x0, H = g.y1 - g.y0;
+    std::vector<double> real;
+    for (double a : areas)
+      if (a > 1e-4 * W * H) real.push_back(a);
+    if (real.empty()) real.push_back(W * H / 16.0);
+    std::nth_element(real.begin(), real.begin() + real.size() / 2, real.end());
+    g.cell = 0.5 * std::sqrt(real[real.size() / 2]);
+    g.cell = std::max(g.cell, std::max(W, H) / 256.0);
+    g.nx = std::max(1, (int)std::ceil((g.x1 - g.x0) / g.cell));
+    g.ny = std::max(1, (int)std::ceil((g.y1 - g.y0) / g.cell));
+    g.cells.assign((size_t)g.nx * g.ny, {});
+    std::vector<std::array<double, 3>> pts;
+    std::vector<int> mark((size_t)g.nx * g.ny, -1);
+    for (int m : g.members) {
+      double slope;
+      Box3 lb = local_bounds(s.desc[m], slope);
+      double ext = std::max(std::max(lb.hi[0] - lb.lo[0], lb.hi[1] - lb.lo[1]), lb.hi[2] - lb.lo[2]);
+      double h = std::max(g.cell / 6.0, ext / 256.0);
+      pts.clear();
+      surface_samples(s.desc[m], h, pts);
+      double pad = h + 1e-5 * s.l_ref;
+      for (auto& w : pts) {
+        double x[3];
+        to_group(g, w.data(), x);
+        for (int q = 0; q < 5; ++q) {
+          double px = x[0] + (q == 1 ? pad : q == 2 ? -pad : 0.0), py = x[1] + (q == 3 ? pad : q == 4 ? -pad : 0.0);
+          int ix = (int)std::floor((px - g.x0) / g.cell), iy = (int)std::floor((py - g.y0) / g.cell);
+          if (ix < 0 || iy < 0 || ix >= g.nx || iy >= g.ny) continue;
+          size_t ci = (size_t)iy * g.nx + ix;
+          if (mark[ci] != m) { mark[ci] = m; g.cells[ci].push_back((uint16_t)m); }
+        }
+      }
+    }
+  }
+}
+
 // Build the blob for precision T and fill the view offsets (host addresses
 // are rebased to the device allocation by the caller).
 template <typename T>
@@ -347,67 +566,51 @@ void compile_blob(const robast_scene& s, std::vector<char>& blob, SceneView<T>& 
   std::vector<DVol<T>> recs(nv);
   std::vector<Box3> wb(nv);
   for (int i = 0; i < nv; ++i) fill_record<T>(recs[i], s.desc[i], wb[i], s.l_ref);
-  // grid over the XY footprints
   std::vector<uint16_t> always;
-  std::vector<int> gridv;
-  double ux0 = 1e300, uy0 = 1e300, ux1 = -1e300, uy1 = -1e300;
-  std::vector<double> areas;
-  for (int i = 0; i < nv; ++i) {
-    ux0 = std::min(ux0, wb[i].lo[0]); uy0 = std::min(uy0, wb[i].lo[1]);
-    ux1 = std::max(ux1, wb[i].hi[0]); uy1 = std::max(uy1, wb[i].hi[1]);
-    areas.push_back((wb[i].hi[0] - wb[i].lo[0]) * (wb[i].hi[1] - wb[i].lo[1]));
+  std::vector<GroupBuild> groups;
+  build_groups(s, wb, always, groups);
+  std::vector<GroupRec<T>> grecs(groups.size());
+  std::vector<uint32_t> starts;
+  std::vector<uint16_t> items;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const GroupBuild& g = groups[gi];
+    GroupRec<T>& r = grecs[gi];
+    std::memset(&r, 0, sizeof r);
+    for (int i = 0; i < 9; ++i) r.Q[i] = q<T>(g.Q[i]);
+    for (int i = 0; i < 3; ++i) r.c[i] = q<T>(g.c[i]);
+    r.zmin = std::nextafter(q<T>(g.zmin), (T)-INFINITY); r.zmax = std::nextafter(q<T>(g.zmax), (T)INFINITY);
+    r.x0 = std::nextafter(q<T>(g.x0), (T)-INFINITY); r.y0 = std::nextafter(q<T>(g.y0), (T)-INFINITY);
+    r.cell = q<T>(g.cell); r.inv_cell = q<T>(1.0 / (double)r.cell);
+    r.nx = g.nx; r.ny = g.ny;
+    r.start = (uint32_t)starts.size();
+    for (auto& c : g.cells) { starts.push_back((uint32_t)items.size()); items.insert(items.end(), c.begin(), c.end()); }
   }
-  int nx = 0, ny = 0;
-  double cell = 1.0;
-  if (nv > 8) {
-    std::vector<double> a2 = areas;
-    std::nth_element(a2.begin(), a2.begin() + a2.size() / 2, a2.end());
-    cell = std::sqrt(std::max(a2[a2.size() / 2], 1e-30));
-    double W = ux1 - ux0, H = uy1 - uy0;
-    cell = std::max(cell, std::max(W, H) / 256.0);
-    nx = std::max(1, (int)std::ceil(W / cell));
-    ny = std::max(1, (int)std::ceil(H / cell));
-  }
-  std::vector<std::vector<uint16_t>> cells((size_t)nx * ny);
-  for (int i = 0; i < nv; ++i) {
-    if (nx == 0) { always.push_back((uint16_t)i); continue; }
-    int ix0 = (int)std::floor((wb[i].lo[0] - ux0) / cell), ix1 = (int)std::floor((wb[i].hi[0] - ux0) / cell);
-    int iy0 = (int)std::floor((wb[i].lo[1] - uy0) / cell), iy1 = (int)std::floor((wb[i].hi[1] - uy0) / cell);
-    ix0 = std::max(0, ix0); iy0 = std::max(0, iy0);
-    ix1 = std::min(nx - 1, ix1); iy1 = std::min(ny - 1, iy1);
-    long span = (long)(ix1 - ix0 + 1) * (iy1 - iy0 + 1);
-    if (span > 64 || span > (long)nx * ny / 4) { always.push_back((uint16_t)i); continue; }
-    for (int iy = iy0; iy <= iy1; ++iy)
-      for (int ix = ix0; ix <= ix1; ++ix) cells[(size_t)iy * nx + ix].push_back((uint16_t)i);
-  }
-  // layout
+  starts.push_back((uint32_t)items.size());
+  // layout: volumes | groups | always | cell_start | items
   blob.clear();
-  offs.assign(4, 0);
-  offs[0] = 0;
+  offs.assign(5, 0);
   blob.resize(sizeof(DVol<T>) * nv);
   if (nv) std::memcpy(blob.data(), recs.data(), sizeof(DVol<T>) * nv);
+  align_to<T>(blob, 16);
+  offs[4] = blob.size();
+  size_t p0 = blob.size();
+  blob.resize(p0 + sizeof(GroupRec<T>) * grecs.size());
+  if (!grecs.empty()) std::memcpy(blob.data() + p0, grecs.data(), sizeof(GroupRec<T>) * grecs.size());
   align_to<T>(blob, 16);
   offs[1] = blob.size();
   for (uint16_t a : always) { blob.push_back((char)(a & 0xff)); blob.push_back((char)(a >> 8)); }
   align_to<T>(blob, 16);
   offs[2] = blob.size();
-  uint32_t acc = 0;
-  std::vector<uint32_t> starts;
-  for (auto& c : cells) { starts.push_back(acc); acc += (uint32_t)c.size(); }
-  starts.push_back(acc);
-  size_t p0 = blob.size();
+  p0 = blob.size();
   blob.resize(p0 + 4 * starts.size());
   std::memcpy(blob.data() + p0, starts.data(), 4 * starts.size());
   align_to<T>(blob, 16);
   offs[3] = blob.size();
-  for (auto& c : cells)
-    for (uint16_t a : c) { blob.push_back((char)(a & 0xff)); blob.push_back((char)(a >> 8)); }
+  for (uint16_t a : items) { blob.push_back((char)(a & 0xff)); blob.push_back((char)(a >> 8)); }
   align_to<T>(blob, 16);
   V.n_vol = nv;
   V.n_always = (int)always.size();
-  V.nx = nx; V.ny = ny;
-  V.gx0 = q<T>(ux0); V.gy0 = q<T>(uy0);
-  V.cell = q<T>(cell); V.inv_cell = q<T>(1.0 / (double)q<T>(cell));
+  V.n_grp = (int)grecs.size();
   V.max_events = s.max_events;
   V.n_groups = s.n_groups;
   V.seed = s.seed;
@@ -418,6 +621,7 @@ void compile_blob(const robast_scene& s, std::vector<char>& blob, SceneView<T>& 
 template <typename T> void rebase(SceneView<T>& V, const std::vector<size_t>& offs, const char* base) {
   V.blob = base;
   V.vol = reinterpret_cast<const DVol<T>*>(base + offs[0]);
+  V.groups = reinterpret_cast<const GroupRec<T>*>(base + offs[4]);
   V.always = reinterpret_cast<const uint16_t*>(base + offs[1]);
   V.cell_start = reinterpret_cast<const uint32_t*>(base + offs[2]);
   V.items = reinterpret_cast<const uint16_t*>(base + offs[3]);

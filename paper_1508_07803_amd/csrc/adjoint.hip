@@ -53,6 +53,7 @@ __global__ void __launch_bounds__(kBlockAdj) k_backward(SceneView<T> S, RaysView
     L.always = reinterpret_cast<const uint16_t*>(lds + (reinterpret_cast<const char*>(S.always) - base));
     L.cell_start = reinterpret_cast<const uint32_t*>(lds + (reinterpret_cast<const char*>(S.cell_start) - base));
     L.items = reinterpret_cast<const uint16_t*>(lds + (reinterpret_cast<const char*>(S.items) - base));
+  L.groups = reinterpret_cast<const GroupRec<T>*>(lds + (reinterpret_cast<const char*>(S.groups) - base));
   }
   double* gacc = reinterpret_cast<double*>(lds + (USE_LDS ? ((S.blob_bytes + 15u) & ~15u) : 0u));
   if (grad_in_lds)

@@ -41,6 +41,19 @@ __device__ __forceinline__ double dfloor(double a) { return __builtin_floor(a); 
 __device__ __forceinline__ float dcopysign(float a, float b) { return __builtin_copysignf(a, b); }
 __device__ __forceinline__ double dcopysign(double a, double b) { return __builtin_copysign(a, b); }
 template <typename T> __device__ __forceinline__ T tinf() { return T(__builtin_huge_valf()); }
+// Reciprocal for the search arithmetic: the hardware reciprocal (1 ulp) in
+// FP32, exact division in FP64.  Roots found with it differ from correctly
+// rounded division by a few ulp, far inside the tracer's tolerances.
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+template <typename T> __device__ __forceinline__ T fdiv(T a, T b) { return a * frcp(b); }
+// 1/sqrt(x) in double from the hardware estimate and two Newton steps
+__device__ __forceinline__ double rsqrt_d(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y;
+}
 template <typename T> __device__ __forceinline__ bool finite3(V3<T> a) {
   return __builtin_isfinite(a.x) && __builtin_isfinite(a.y) && __builtin_isfinite(a.z);
 }
@@ -192,20 +205,20 @@ template <typename T> __device__ __forceinline__ bool self_ok(const DVol<T>& v, 
 template <typename T> __device__ __forceinline__ void quad2(T a, T b, T c, T& r0, T& r1, int& n) {
   n = 0;
   if (a == T(0)) {
-    if (b != T(0)) { r0 = -c / b; n = 1; }
+    if (b != T(0)) { r0 = -fdiv(c, b); n = 1; }
     return;
   }
   T disc = b * b - T(4) * a * c;
   if (disc < T(0)) return;
   T q = T(-0.5) * (b + dcopysign(dsqrt(disc), b));
   if (q == T(0)) { r0 = T(0); n = 1; return; }
-  r0 = q / a; r1 = c / q; n = 2;
+  r0 = fdiv(q, a); r1 = fdiv(c, q); n = 2;
 }
 
 template <typename T> __device__ __forceinline__ void nf_plane(const DVol<T>& v, int vid, V3<T> o, V3<T> d,
                                                                T t0, T eps, SelfRule sr, Best<T>& b) {
   if (d.z == T(0)) return;
-  T t = -o.z / d.z;
+  T t = -fdiv(o.z, d.z);
   T tt = t + t0;
   if (tt > b.t) return;
   V3<T> x = fma3(t, d, o);
@@ -253,7 +266,8 @@ template <typename T> __device__ __forceinline__ void nf_asphere(const DVol<T>& 
   T tlo = sr.face == 0 ? eps : T(0);
   T ta = tlo - t0, tb = b.t - t0;
   if (d.z != T(0)) {
-    T t1 = (v.lo[2] - o.z) / d.z, t2 = (v.hi[2] - o.z) / d.z;
+    T iz = frcp(d.z);
+    T t1 = (v.lo[2] - o.z) * iz, t2 = (v.hi[2] - o.z) * iz;
     ta = dmax(ta, dmin(t1, t2)); tb = dmin(tb, dmax(t1, t2));
   } else if (o.z < v.lo[2] || o.z > v.hi[2]) {
     return;
@@ -289,14 +303,14 @@ template <typename T> __device__ __forceinline__ void nf_asphere(const DVol<T>& 
   }
   // safeguarded Newton on [ta, tb]
   T a = ta, bnd = tb, ga_ = ga;
-  T t = (gb - ga) != T(0) ? ta - ga * (tb - ta) / (gb - ga) : T(0.5) * (ta + tb);
+  T t = (gb - ga) != T(0) ? ta - ga * fdiv(tb - ta, gb - ga) : T(0.5) * (ta + tb);
   const T tol = sizeof(T) == 4 ? T(2e-7) : T(1e-15);
   for (int it = 0; it < 24; ++it) {
     T g, gp;
     asph_g(v, o, d, t, g, gp);
     if (g == T(0)) break;
     if ((g > T(0)) == (ga_ > T(0))) { a = t; ga_ = g; } else { bnd = t; }
-    T tn = gp != T(0) ? t - g / gp : T(0.5) * (a + bnd);
+    T tn = gp != T(0) ? t - fdiv(g, gp) : T(0.5) * (a + bnd);
     if (!(tn > dmin(a, bnd) && tn < dmax(a, bnd))) tn = T(0.5) * (a + bnd);
     T dt = tn - t;
     t = tn;
@@ -332,7 +346,7 @@ template <typename T> __device__ __forceinline__ void nf_box(const DVol<T>& v, i
     int ax = f >> 1;
     T sgn = (f & 1) ? T(-1) : T(1);
     if (da[ax] == T(0)) continue;
-    T t = (sgn * v.p[ax] - oa[ax]) / da[ax];
+    T t = fdiv(sgn * v.p[ax] - oa[ax], da[ax]);
     T tt = t + t0;
     if (tt > b.t) continue;
     if (!self_ok(v, sr, f, tt, eps, fma3(t, d, o), d, T(0))) continue;
@@ -387,7 +401,7 @@ template <typename T> __device__ __forceinline__ T cubic_root_piece(const T* w, 
     bern3(w, s, f, fp);
     if (f == T(0)) break;
     if ((f > T(0)) == (fa > T(0))) { a = s; fa = f; } else { b = s; }
-    T sn = fp != T(0) ? s - f / fp : T(0.5) * (a + b);
+    T sn = fp != T(0) ? s - fdiv(f, fp) : T(0.5) * (a + b);
     if (!(sn > a && sn < b)) sn = T(0.5) * (a + b);
     T ds = sn - s;
     s = sn;
@@ -400,6 +414,33 @@ template <typename T> __device__ __forceinline__ void nf_hexcone(const DVol<T>& 
                                                                  T t0, T eps, SelfRule sr, Best<T>& b) {
   const T* p = v.p;
   const T inv_sqrt3 = T(0.5773502691896258);
+  {
+    // the walls lie inside the hexagonal prism |x . n_k| <= rho_max,
+    // z in [lo, hi]: skip the cone unless the ray crosses it before b.t
+    T rm = dmax(dmax(p[0], p[2]), dmax(p[4], p[6]));
+    T ta = -t0, tb = b.t - t0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      T nx, ny;
+      wall_dir(k, nx, ny);
+      T u0 = o.x * nx + o.y * ny, du = d.x * nx + d.y * ny;
+      if (du != T(0)) {
+        T iu = frcp(du);
+        T t1 = (-rm - u0) * iu, t2 = (rm - u0) * iu;
+        ta = dmax(ta, dmin(t1, t2)); tb = dmin(tb, dmax(t1, t2));
+      } else if (dabs(u0) > rm) {
+        return;
+      }
+    }
+    if (d.z != T(0)) {
+      T iz = frcp(d.z);
+      T t1 = (v.lo[2] - o.z) * iz, t2 = (v.hi[2] - o.z) * iz;
+      ta = dmax(ta, dmin(t1, t2)); tb = dmin(tb, dmax(t1, t2));
+    } else if (o.z < v.lo[2] || o.z > v.hi[2]) {
+      return;
+    }
+    if (!(ta <= tb)) return;
+  }
   for (int f = 0; f < 6; ++f) {
     T nx, ny;
     wall_dir(f, nx, ny);
@@ -434,7 +475,7 @@ template <typename T> __device__ __forceinline__ void nf_hexcone(const DVol<T>& 
       fa = fb;
       T rho, z, dr, dzs;
       bez_eval(p, s, rho, z, dr, dzs);
-      T t = dabs(d.z) >= dabs(du) ? (z - o.z) / d.z : (rho - u0) / du;
+      T t = dabs(d.z) >= dabs(du) ? fdiv(z - o.z, d.z) : fdiv(rho - u0, du);
       T tt = t + t0;
       if (tt > b.t) continue;
       V3<T> xh = fma3(t, d, o);
@@ -460,11 +501,9 @@ template <typename T> __device__ __forceinline__ bool aabb(const DVol<T>& v, V3<
 // Exact test of one volume; offers its nearest valid face root to b.
 // The photon position O is kept in double (world scale); of and inv are its
 // rounding and the inverse direction in T for the box tests.
-template <typename T> __device__ __forceinline__ void test_volume(const DVol<T>& v, int vid, V3<double> O, V3<T> of,
-                                                                  V3<T> d, V3<T> inv, int prev_vol, int prev_face,
-                                                                  int prev_side, T eps, Best<T>& b) {
-  T tin;
-  if (!aabb(v, of, inv, b.t, tin)) return;
+template <typename T> __device__ __forceinline__ void narrow(const DVol<T>& v, int vid, V3<double> O, V3<T> d,
+                                                             T tin, int prev_vol, int prev_face, int prev_side,
+                                                             T eps, Best<T>& b) {
   // advance to the box entry to keep the local quadratic well conditioned;
   // planes are not advanced, so coincident planes with the same z-row give
   // bit-identical t and the tie goes to the lower volume id
@@ -481,8 +520,16 @@ template <typename T> __device__ __forceinline__ void test_volume(const DVol<T>&
   }
 }
 
+template <typename T> __device__ __forceinline__ void test_volume(const DVol<T>& v, int vid, V3<double> O, V3<T> of,
+                                                                  V3<T> d, V3<T> inv, int prev_vol, int prev_face,
+                                                                  int prev_side, T eps, Best<T>& b) {
+  T tin;
+  if (!aabb(v, of, inv, b.t, tin)) return;
+  narrow(v, vid, O, d, tin, prev_vol, prev_face, prev_side, eps, b);
+}
+
 template <typename T> __device__ __forceinline__ V3<T> inv_dir(V3<T> d) {
-  return {T(1) / d.x, T(1) / d.y, T(1) / d.z};
+  return {frcp(d.x), frcp(d.y), frcp(d.z)};
 }
 
 // Non-sequential search: nearest face over the always-list and the grid
@@ -495,61 +542,129 @@ struct Mailbox {
   __device__ __forceinline__ void put(int v) { m3 = m2; m2 = m1; m1 = m0; m0 = v; }
 };
 
+// Candidates of one search, gathered before any exact test so that every
+// lane of a wave runs the exact tests in one loop at one code site, nearest
+// box entry first.  The arrays are only indexed through unrolled selects, so
+// they stay in VGPRs.
+template <typename T> struct Cands {
+  static constexpr int K = 6;
+  int vid[K];
+  T tin[K];
+  int n;
+};
+
+template <typename T>
+__device__ __forceinline__ void run_cands(const SceneView<T>& S, Cands<T>& c, V3<double> O, V3<T> d, int prev_vol,
+                                          int prev_face, int prev_side, Best<T>& b) {
+#pragma unroll 1
+  for (int it = 0; it < c.n; ++it) {
+    int vid = -1, sel = 0;
+    T tin = tinf<T>();
+#pragma unroll
+    for (int j = 0; j < Cands<T>::K; ++j)
+      if (j < c.n && c.tin[j] < tin) { tin = c.tin[j]; vid = c.vid[j]; sel = j; }
+#pragma unroll
+    for (int j = 0; j < Cands<T>::K; ++j)
+      if (j == sel) c.tin[j] = tinf<T>();
+    if (vid < 0 || tin > b.t) break;
+    narrow(S.vol[vid], vid, O, d, tin, prev_vol, prev_face, prev_side, S.eps_self, b);
+  }
+  c.n = 0;
+}
+
+template <typename T>
+__device__ __forceinline__ void gather(const SceneView<T>& S, Cands<T>& c, int vid, V3<T> o, V3<T> inv, V3<double> O,
+                                       V3<T> d, int prev_vol, int prev_face, int prev_side, Best<T>& b) {
+  T tin;
+  if (!aabb(S.vol[vid], o, inv, b.t, tin)) return;
+  if (c.n == Cands<T>::K) run_cands(S, c, O, d, prev_vol, prev_face, prev_side, b);
+#pragma unroll
+  for (int j = 0; j < Cands<T>::K; ++j)
+    if (j == c.n) { c.vid[j] = vid; c.tin[j] = tin; }
+  ++c.n;
+}
+
+// Non-sequential search: nearest face over the volume just left, the
+// always-list and the candidate groups crossed by the ray.
 template <typename T> __device__ void find_nearest(const SceneView<T>& S, V3<double> O, V3<T> d, int prev_vol,
                                                    int prev_face, int prev_side, Best<T>& b) {
   b.t = tinf<T>(); b.vol = -1; b.face = -1; b.s = T(0); b.tp = 0.0;
   Mailbox mb{prev_vol, -1, -1, -1};
   V3<T> inv = inv_dir(d);
   const V3<T> o = to_t<T>(O);
+  Cands<T> c;
+  c.n = 0;
   // the volume just left first: photons bouncing inside a cone or between
-  // facets usually meet it (or its neighbour) next, which tightens b.t early
-  if (prev_vol >= 0)
-    test_volume(S.vol[prev_vol], prev_vol, O, o, d, inv, prev_vol, prev_face, prev_side, S.eps_self, b);
+  // facets usually meet it (or its neighbour) next
+  if (prev_vol >= 0) gather(S, c, prev_vol, o, inv, O, d, prev_vol, prev_face, prev_side, b);
   for (int i = 0; i < S.n_always; ++i) {
     int vid = S.always[i];
-    if (vid != prev_vol) test_volume(S.vol[vid], vid, O, o, d, inv, prev_vol, prev_face, prev_side, S.eps_self, b);
+    if (vid != prev_vol) gather(S, c, vid, o, inv, O, d, prev_vol, prev_face, prev_side, b);
   }
-  if (S.nx == 0) return;
-  // clip the XY projection to the grid rectangle
-  T gx1 = S.gx0 + T(S.nx) * S.cell, gy1 = S.gy0 + T(S.ny) * S.cell;
-  T ta = T(0), tb = tinf<T>();
-  if (d.x != T(0)) {
-    T t1 = (S.gx0 - o.x) * inv.x, t2 = (gx1 - o.x) * inv.x;
-    ta = dmax(ta, dmin(t1, t2)); tb = dmin(tb, dmax(t1, t2));
-  } else if (o.x < S.gx0 || o.x > gx1) return;
-  if (d.y != T(0)) {
-    T t1 = (S.gy0 - o.y) * inv.y, t2 = (gy1 - o.y) * inv.y;
-    ta = dmax(ta, dmin(t1, t2)); tb = dmin(tb, dmax(t1, t2));
-  } else if (o.y < S.gy0 || o.y > gy1) return;
-  if (!(ta <= tb)) return;
-  T px = o.x + ta * d.x, py = o.y + ta * d.y;
-  int ix = (int)dfloor((px - S.gx0) * S.inv_cell), iy = (int)dfloor((py - S.gy0) * S.inv_cell);
-  ix = ix < 0 ? 0 : (ix >= S.nx ? S.nx - 1 : ix);
-  iy = iy < 0 ? 0 : (iy >= S.ny ? S.ny - 1 : iy);
-  int sx = d.x > T(0) ? 1 : -1, sy = d.y > T(0) ? 1 : -1;
-  T tmx = d.x != T(0) ? (S.gx0 + T(ix + (d.x > T(0) ? 1 : 0)) * S.cell - o.x) * inv.x : tinf<T>();
-  T tmy = d.y != T(0) ? (S.gy0 + T(iy + (d.y > T(0) ? 1 : 0)) * S.cell - o.y) * inv.y : tinf<T>();
-  T tdx = d.x != T(0) ? S.cell * dabs(inv.x) : tinf<T>();
-  T tdy = d.y != T(0) ? S.cell * dabs(inv.y) : tinf<T>();
-  int guard = S.nx + S.ny + 2;
-  while (guard-- > 0) {
-    int cell = iy * S.nx + ix;
-    uint32_t i0 = S.cell_start[cell], i1 = S.cell_start[cell + 1];
-    for (uint32_t k = i0; k < i1; ++k) {
-      int vid = S.items[k];
-      if (!mb.seen(vid)) {
-        mb.put(vid);
-        test_volume(S.vol[vid], vid, O, o, d, inv, prev_vol, prev_face, prev_side, S.eps_self, b);
-      }
+  // candidate groups: walk each group's grid over the stretch of the ray that
+  // lies inside the group's z-slab (in the group frame)
+  for (int gi = 0; gi < S.n_grp; ++gi) {
+    const GroupRec<T>& G = S.groups[gi];
+    T rx = (T)(O.x - (double)G.c[0]), ry = (T)(O.y - (double)G.c[1]), rz = (T)(O.z - (double)G.c[2]);
+    // the slab first: most searches cross only some groups' slabs
+    T goz = G.Q[6] * rx + G.Q[7] * ry + G.Q[8] * rz, gdz = G.Q[6] * d.x + G.Q[7] * d.y + G.Q[8] * d.z;
+    T ta = T(0), tb = b.t;
+    if (gdz != T(0)) {
+      T iz = frcp(gdz);
+      T t1 = (G.zmin - goz) * iz, t2 = (G.zmax - goz) * iz;
+      ta = dmax(ta, dmin(t1, t2)); tb = dmin(tb, dmax(t1, t2));
+    } else if (goz < G.zmin || goz > G.zmax) {
+      continue;
     }
-    T tn = dmin(tmx, tmy);
-    if (tn > tb || tn >= b.t) break;
-    if (tmx < tmy) { ix += sx; tmx += tdx; if (ix < 0 || ix >= S.nx) break; }
-    else { iy += sy; tmy += tdy; if (iy < 0 || iy >= S.ny) break; }
+    if (!(ta <= tb)) continue;
+    V3<T> go = {G.Q[0] * rx + G.Q[1] * ry + G.Q[2] * rz, G.Q[3] * rx + G.Q[4] * ry + G.Q[5] * rz, goz};
+    V3<T> gd = {G.Q[0] * d.x + G.Q[1] * d.y + G.Q[2] * d.z, G.Q[3] * d.x + G.Q[4] * d.y + G.Q[5] * d.z, gdz};
+    T gx1 = G.x0 + T(G.nx) * G.cell, gy1 = G.y0 + T(G.ny) * G.cell;
+    T ix_ = T(0), iy_ = T(0);
+    if (gd.x != T(0)) {
+      ix_ = frcp(gd.x);
+      T t1 = (G.x0 - go.x) * ix_, t2 = (gx1 - go.x) * ix_;
+      ta = dmax(ta, dmin(t1, t2)); tb = dmin(tb, dmax(t1, t2));
+    } else if (go.x < G.x0 || go.x > gx1) {
+      continue;
+    }
+    if (gd.y != T(0)) {
+      iy_ = frcp(gd.y);
+      T t1 = (G.y0 - go.y) * iy_, t2 = (gy1 - go.y) * iy_;
+      ta = dmax(ta, dmin(t1, t2)); tb = dmin(tb, dmax(t1, t2));
+    } else if (go.y < G.y0 || go.y > gy1) {
+      continue;
+    }
+    if (!(ta <= tb)) continue;
+    T px = go.x + ta * gd.x, py = go.y + ta * gd.y;
+    int ix = (int)dfloor((px - G.x0) * G.inv_cell), iy = (int)dfloor((py - G.y0) * G.inv_cell);
+    ix = ix < 0 ? 0 : (ix >= G.nx ? G.nx - 1 : ix);
+    iy = iy < 0 ? 0 : (iy >= G.ny ? G.ny - 1 : iy);
+    int sx = gd.x > T(0) ? 1 : -1, sy = gd.y > T(0) ? 1 : -1;
+    T tmx = gd.x != T(0) ? (G.x0 + T(ix + (gd.x > T(0) ? 1 : 0)) * G.cell - go.x) * ix_ : tinf<T>();
+    T tmy = gd.y != T(0) ? (G.y0 + T(iy + (gd.y > T(0) ? 1 : 0)) * G.cell - go.y) * iy_ : tinf<T>();
+    T tdx = gd.x != T(0) ? G.cell * dabs(ix_) : tinf<T>();
+    T tdy = gd.y != T(0) ? G.cell * dabs(iy_) : tinf<T>();
+    int guard = G.nx + G.ny + 2;
+    while (guard-- > 0) {
+      uint32_t cell = G.start + (uint32_t)(iy * G.nx + ix);
+      uint32_t i0 = S.cell_start[cell], i1 = S.cell_start[cell + 1];
+      for (uint32_t k = i0; k < i1; ++k) {
+        int vid = S.items[k];
+        if (!mb.seen(vid)) {
+          mb.put(vid);
+          gather(S, c, vid, o, inv, O, d, prev_vol, prev_face, prev_side, b);
+        }
+      }
+      T tn = dmin(tmx, tmy);
+      if (tn > tb || tn >= b.t) break;
+      if (tmx < tmy) { ix += sx; tmx += tdx; if (ix < 0 || ix >= G.nx) break; }
+      else { iy += sy; tmy += tdy; if (iy < 0 || iy >= G.ny) break; }
+    }
   }
+  run_cands(S, c, O, d, prev_vol, prev_face, prev_side, b);
 }
 
-// front normal (world) of the face hit, at world point X
 // Front normal (world, double) of the face hit at world point X (double):
 // local point, gradient and normalisation in double from the record.
 template <typename T> __device__ __forceinline__ V3<double> front_normal(const DVol<T>& v, int face, V3<double> X,
@@ -563,7 +678,7 @@ template <typename T> __device__ __forceinline__ V3<double> front_normal(const D
   V3<double> g = local_grad<double>(v, face, x, s);
   V3<double> w = {Q[0] * g.x + Q[3] * g.y + Q[6] * g.z, Q[1] * g.x + Q[4] * g.y + Q[7] * g.z,
                   Q[2] * g.x + Q[5] * g.y + Q[8] * g.z};
-  return scl(1.0 / dsqrt(dot(w, w)), w);
+  return scl(rsqrt_d(dot(w, w)), w);
 }
 
 template <typename T> __device__ __forceinline__ T fresnel_R(T cos_i, T n1, T n2, T& cos_t) {
@@ -625,46 +740,71 @@ template <typename T> struct PhotonOut {
   uint64_t hash;
 };
 
-// Full non-sequential transport of one photon.  If `codes` is non-null the
-// event sequence (vol << 8 | face << 4 | action) is written to it.
-template <typename T, int MAXLOG>
-__device__ __forceinline__ PhotonOut<T> trace_photon(const SceneView<T>& S, V3<T> o_in, V3<T> d, uint64_t id,
-                                                     uint32_t* codes) {
-  V3<double> o = {(double)o_in.x, (double)o_in.y, (double)o_in.z};
-  // direction state in double; the search uses its rounding to T
-  V3<double> dd = {(double)d.x, (double)d.y, (double)d.z};
+// State of a photon between interactions.  Position and direction are kept
+// in double; every search uses their rounding to T.
+struct PhotonState {
+  V3<double> o, d;
+  double ncur, opl;
+  uint64_t hash, id;
+  int k, prev_v, prev_f, prev_side, fate, last_vol;
+};
+
+template <typename T> __device__ __forceinline__ void photon_init(PhotonState& p, V3<T> o, V3<T> d, uint64_t id) {
+  p.o = {(double)o.x, (double)o.y, (double)o.z};
+  p.d = {(double)d.x, (double)d.y, (double)d.z};
+  p.ncur = 1.0; p.opl = 0.0; p.hash = 0xcbf29ce484222325ull; p.id = id;
+  p.k = 0; p.prev_v = -1; p.prev_f = -1; p.prev_side = 0; p.fate = 0; p.last_vol = -1;
+  if (!finite3(o) || !finite3(d) || dot(d, d) == T(0)) p.fate = FAILED;
+}
+
+// One interaction of the non-sequential transport: nearest surface, then the
+// role of its volume.  Returns the event code (vol << 8 | face << 4 | action)
+// of the interaction, or 0xffffffff when the photon ends without one.
+template <typename T> __device__ __forceinline__ uint32_t photon_step(const SceneView<T>& S, PhotonState& p) {
+  if (p.k == S.max_events) { p.fate = SUSPENDED; return 0xffffffffu; }
+  Best<T> b;
+  find_nearest(S, p.o, to_t<T>(p.d), p.prev_v, p.prev_f, p.prev_side, b);
+  if (b.vol < 0) { p.fate = EXITED; return 0xffffffffu; }
+  const DVol<T>& v = S.vol[b.vol];
+  V3<double> X = {p.o.x + b.tp * p.d.x, p.o.y + b.tp * p.d.y, p.o.z + b.tp * p.d.z};
+  p.opl += p.ncur * b.tp;
+  V3<double> n = front_normal(v, b.face, X, (double)b.s);
+  int back, fate = 0;
+  int act = interact<double>(v, n, p.d, p.ncur, fate, back, S.seed, p.id, p.k);
+  p.hash = (p.hash ^ (((uint64_t)b.vol << 4) | ((uint64_t)b.face << 1) | (uint64_t)back)) * 0x100000001b3ull;
+  p.last_vol = b.vol;
+  uint32_t code = ((uint32_t)b.vol << 8) | ((uint32_t)b.face << 4) | (uint32_t)act;
+  p.o = X;
+  p.prev_v = b.vol; p.prev_f = b.face;
+  // side of the face just left: reflection keeps the photon on the side it
+  // came from, refraction moves it across
+  p.prev_side = back ^ (act == ACT_REFRACT ? 1 : 0);
+  ++p.k;
+  if (fate) p.fate = fate;
+  else if (!finite3(p.d)) p.fate = FAILED;
+  return code;
+}
+
+template <typename T> __device__ __forceinline__ PhotonOut<T> photon_out(const PhotonState& p) {
   PhotonOut<T> r;
-  r.fate = 0; r.last_vol = -1; r.opl = T(0); r.hash = 0xcbf29ce484222325ull;
-  double ncur = 1.0, opl = 0.0;
-  int prev_v = -1, prev_f = -1, prev_side = 0;
-  int k = 0;
-  if (!finite3(o_in) || !finite3(d) || dot(d, d) == T(0)) r.fate = FAILED;
-  while (!r.fate) {
-    if (k == S.max_events) { r.fate = SUSPENDED; break; }
-    Best<T> b;
-    find_nearest(S, o, d, prev_v, prev_f, prev_side, b);
-    if (b.vol < 0) { r.fate = EXITED; break; }
-    const DVol<T>& v = S.vol[b.vol];
-    V3<double> X = {o.x + b.tp * dd.x, o.y + b.tp * dd.y, o.z + b.tp * dd.z};
-    opl += ncur * b.tp;
-    V3<double> n = front_normal(v, b.face, X, (double)b.s);
-    int back, fate = 0;
-    int act = interact<double>(v, n, dd, ncur, fate, back, S.seed, id, k);
-    d = to_t<T>(dd);
-    r.hash = (r.hash ^ (((uint64_t)b.vol << 4) | ((uint64_t)b.face << 1) | (uint64_t)back)) * 0x100000001b3ull;
-    r.last_vol = b.vol;
-    if (codes && k < MAXLOG) codes[k] = ((uint32_t)b.vol << 8) | ((uint32_t)b.face << 4) | (uint32_t)act;
-    o = X;
-    prev_v = b.vol; prev_f = b.face;
-    // side of the face just left: reflection keeps the photon on the side it
-    // came from, refraction moves it across
-    prev_side = back ^ (act == ACT_REFRACT ? 1 : 0);
-    ++k;
-    if (fate) { r.fate = fate; break; }
-    if (!finite3(dd)) { r.fate = FAILED; break; }
-  }
-  r.nev = k; r.pos = to_t<T>(o); r.dir = to_t<T>(dd); r.opl = (T)opl;
+  r.fate = p.fate; r.nev = p.k; r.last_vol = p.last_vol;
+  r.pos = to_t<T>(p.o); r.dir = to_t<T>(p.d); r.opl = (T)p.opl; r.hash = p.hash;
   return r;
+}
+
+// Full non-sequential transport of one photon.  If `codes` is non-null the
+// event codes are written to it (at most MAXLOG).
+template <typename T, int MAXLOG>
+__device__ __forceinline__ PhotonOut<T> trace_photon(const SceneView<T>& S, V3<T> o, V3<T> d, uint64_t id,
+                                                     uint32_t* codes) {
+  PhotonState p;
+  photon_init(p, o, d, id);
+  while (!p.fate) {
+    int k = p.k;
+    uint32_t code = photon_step(S, p);
+    if (codes && code != 0xffffffffu && k < MAXLOG) codes[k] = code;
+  }
+  return photon_out<T>(p);
 }
 
 }  // namespace robast

@@ -31,6 +31,7 @@ __device__ __forceinline__ void stage_scene(const SceneView<T>& S, SceneView<T>&
   L.always = reinterpret_cast<const uint16_t*>(lds + (reinterpret_cast<const char*>(S.always) - base));
   L.cell_start = reinterpret_cast<const uint32_t*>(lds + (reinterpret_cast<const char*>(S.cell_start) - base));
   L.items = reinterpret_cast<const uint16_t*>(lds + (reinterpret_cast<const char*>(S.items) - base));
+  L.groups = reinterpret_cast<const GroupRec<T>*>(lds + (reinterpret_cast<const char*>(S.groups) - base));
 }
 
 __device__ __forceinline__ void flush_lane(double* acc_lds, int g, const double* a) {
@@ -58,51 +59,63 @@ __global__ void __launch_bounds__(kBlock) k_trace(SceneView<T> S, RaysView<T> R,
   int ag = -1;
   double* acc_target = (SUMS && sums_in_lds) ? acc : H.sums;
 
+  // Event-level refill: every iteration each lane performs one interaction
+  // of its current photon; a lane whose photon has ended takes its next photon
+  // (grid-stride order) at the top of the iteration, so the wave keeps
+  // running the same per-event code instead of idling behind long photons.
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  // all lanes of a wave run the same number of iterations (wave-uniform loop
-  // bound), so the wave-synchronous flush below is well defined
-  const int64_t wave_first = first - (threadIdx.x & 63);
-  const int64_t iters = wave_first < n ? (n - wave_first + stride - 1) / stride : 0;
-  for (int64_t it = 0; it < iters; ++it) {
-    int64_t i = first + it * stride;
-    bool live = i < n;
-    int g = -1;
-    PhotonOut<T> r;
-    if (live) {
-      V3<T> o = {R.ox[i], R.oy[i], R.oz[i]};
-      V3<T> d = {R.dx[i], R.dy[i], R.dz[i]};
-      g = R.group ? (int)R.group[i] : 0;
+  int64_t next = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t cur = -1;
+  int g = -1;
+  PhotonState ps;
+  ps.fate = 1;
+  while (true) {
+    bool started = false;
+    if (cur < 0 && next < n) {
+      cur = next;
+      next += stride;
+      V3<T> o = {R.ox[cur], R.oy[cur], R.oz[cur]};
+      V3<T> d = {R.dx[cur], R.dy[cur], R.dz[cur]};
+      g = R.group ? (int)R.group[cur] : 0;
       // a group id outside [0, n_groups) is traced but never accumulated
       if ((unsigned)g >= (unsigned)S.n_groups) g = -1;
-      r = trace_photon<T, 0>(L, o, d, R.id_base + (uint64_t)i, nullptr);
-      if (RECORD) {
-        if (H.fate) H.fate[i] = (uint8_t)r.fate;
-        if (H.nev) H.nev[i] = (uint8_t)r.nev;
-        if (H.last_vol) H.last_vol[i] = r.last_vol;
-        if (H.x) { H.x[i] = r.pos.x; H.y[i] = r.pos.y; H.z[i] = r.pos.z; }
-        if (H.ux) { H.ux[i] = r.dir.x; H.uy[i] = r.dir.y; H.uz[i] = r.dir.z; }
-        if (H.opl) H.opl[i] = r.opl;
-        if (H.hash) H.hash[i] = r.hash;
-      }
+      photon_init(ps, o, d, R.id_base + (uint64_t)cur);
+      started = true;
     }
+    if (!__any(cur >= 0)) break;
     if (SUMS) {
-      // wave-uniform flush when any lane's group changes
-      bool change = live && g >= 0 && g != ag && ag >= 0;
+      // wave-uniform flush when a lane starts a photon of another group
+      bool change = started && g >= 0 && g != ag && ag >= 0;
       if (__any(change)) {
         flush_lane(acc_target, ag, a);
 #pragma unroll
         for (int k = 0; k < kNSum; ++k) a[k] = 0.0;
         ag = -1;
       }
-      if (live && g >= 0) {
-        ag = g;
-        a[0] += 1.0;
-        if (r.fate == FOCUSED) {
-          double x = (double)r.pos.x, y = (double)r.pos.y;
-          a[1] += 1.0; a[2] += x; a[3] += y; a[4] += x * x; a[5] += y * y;
-          a[6] += (double)dabs(r.dir.z);
+    }
+    if (cur >= 0) {
+      if (!ps.fate) photon_step(L, ps);
+      if (ps.fate) {
+        PhotonOut<T> r = photon_out<T>(ps);
+        if (RECORD) {
+          if (H.fate) H.fate[cur] = (uint8_t)r.fate;
+          if (H.nev) H.nev[cur] = (uint8_t)r.nev;
+          if (H.last_vol) H.last_vol[cur] = r.last_vol;
+          if (H.x) { H.x[cur] = r.pos.x; H.y[cur] = r.pos.y; H.z[cur] = r.pos.z; }
+          if (H.ux) { H.ux[cur] = r.dir.x; H.uy[cur] = r.dir.y; H.uz[cur] = r.dir.z; }
+          if (H.opl) H.opl[cur] = r.opl;
+          if (H.hash) H.hash[cur] = r.hash;
         }
+        if (SUMS && g >= 0) {
+          ag = g;
+          a[0] += 1.0;
+          if (r.fate == FOCUSED) {
+            double x = (double)r.pos.x, y = (double)r.pos.y;
+            a[1] += 1.0; a[2] += x; a[3] += y; a[4] += x * x; a[5] += y * y;
+            a[6] += (double)dabs(r.dir.z);
+          }
+        }
+        cur = -1;
       }
     }
   }

@@ -43,13 +43,28 @@ struct DTilt {
   double pivot[3], a1[3], a2[3];
 };
 
+// A candidate group: volumes whose surfaces lie in the slab zmin <= z <= zmax
+// of the group frame (x_g = Q (x - c)), with a uniform grid over (x_g, y_g)
+// listing per cell the members whose surface projects into that cell.
+// Groups are formed by the scene compiler: panels sharing one untilted frame
+// (a segmented mirror) form a group in that frame; the remaining volumes are
+// split into world-frame layers by their z extent.
+template <typename T> struct alignas(16) GroupRec {
+  T Q[9];
+  T c[3];
+  T zmin, zmax, x0, y0, cell, inv_cell;
+  int32_t nx, ny;
+  uint32_t start;   // index of this group's first cell in cell_start
+  uint32_t pad;
+};
+
 template <typename T> struct SceneView {
   const DVol<T>* vol;
   const uint16_t* always;
   const uint32_t* cell_start;
   const uint16_t* items;
-  int32_t n_vol, n_always, nx, ny;
-  T gx0, gy0, inv_cell, cell;      // grid origin and cell size (world XY)
+  const GroupRec<T>* groups;
+  int32_t n_vol, n_always, n_grp, pad0;
   int32_t max_events, n_groups;
   uint64_t seed;
   T eps_self;                      // self-intersection guard for the face just left
