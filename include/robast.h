@@ -176,6 +176,57 @@ int robast_trace_backward(robast_scene* scene, const robast_rays* rays, int64_t 
 int robast_update_params(robast_scene* scene, const double* params, int64_t n_params);
 
 void robast_destroy_scene(robast_scene* scene);
+
+/* ---- batched design sweeps --------------------------------------------
+ * Many design variants (scenes of one precision) traced in one persistent
+ * launch (the event loop of §2.1 run over a parameter sweep of the kind used
+ * for the designs of §3).  The photons of variant v are rays
+ * [offsets[v], offsets[v+1]) of one concatenated bundle and are numbered from
+ * offsets[v] (photon id = rays->id_base + index - offsets[v]), so every
+ * photon's result equals that of robast_trace on variant v alone with the
+ * same id_base.  The work is cut into items of at most `chunk` photons,
+ * sorted by variant, which persistent workgroups pull from a device-side
+ * counter; a workgroup stages a variant's tables into LDS only when its next
+ * item belongs to another variant.
+ * Concatenated layouts, in variant order: group sums n_groups_v * 8 doubles,
+ * cotangents n_groups_v * 2, figures n_groups_v * 8, gradient n_params_v.
+ * The work list is fixed at build time and the calls make no host-device
+ * copies or allocations, so they can be captured in a HIP graph; parameter
+ * updates of member scenes (robast_update_params, outside any capture) are
+ * seen by later calls and replays.  The scenes must outlive the batch; a
+ * scene may belong to several batches.  Calls on one batch that overlap in
+ * time (two streams) race on its work counters.
+ * Errors: EINVAL on NULL arguments, n_scenes < 1, offsets not
+ * non-decreasing from 0, chunk == 0 or > 2^30, scenes of different precision;
+ * EUNSUPPORTED for FP64 scenes (batches are built for FP32, the precision of
+ * the sweeps); ENOMEM when the device tables cannot be allocated. */
+typedef struct robast_batch robast_batch;
+
+/* scenes: [host] n_scenes handles (a scene may appear more than once);
+ * offsets: [host] n_scenes + 1 photon offsets, offsets[0] == 0;
+ * chunk: photons per work item (a few thousand: large enough to amortise
+ * the item fetch, small enough to balance the tail). */
+int robast_build_batch(robast_scene* const* scenes, int32_t n_scenes, const int64_t* offsets, uint32_t chunk,
+                       robast_batch** out);
+
+/* Forward trace of the whole bundle: hits as for robast_trace, indexed by the
+ * global photon index; hits->group_sums is the concatenated sums (+=). */
+int robast_trace_batch(robast_batch* batch, const robast_rays* rays, const robast_hits* hits, void* hip_stream);
+
+/* Figures of every variant's groups from concatenated sums (as robast_figures). */
+int robast_figures_batch(robast_batch* batch, const double* d_group_sums, double* d_figures, void* hip_stream);
+
+/* Adjoint of the whole bundle (as robast_trace_backward per variant):
+ * d_group_sums and d_cot concatenated, d_grad concatenated and accumulated
+ * (+=).  EUNSUPPORTED when a variant has max_events > 32. */
+int robast_trace_backward_batch(robast_batch* batch, const robast_rays* rays, const double* d_group_sums,
+                                const double* d_cot, double* d_grad, void* hip_stream);
+
+/* Totals of the concatenated layouts: photons, groups, parameters. */
+int robast_batch_sizes(const robast_batch* batch, int64_t* n_photons, int64_t* n_groups, int64_t* n_params);
+
+void robast_destroy_batch(robast_batch* batch);
+
 const char* robast_status_string(int status);
 const char* robast_last_error(void);
 int robast_abi_version(void);

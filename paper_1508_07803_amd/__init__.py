@@ -26,7 +26,8 @@ FIGURE_STRIDE = 8
 
 SYMBOLS = ["robast_build_scene", "robast_trace", "robast_figures", "robast_trace_backward",
            "robast_update_params", "robast_destroy_scene", "robast_status_string",
-           "robast_last_error", "robast_abi_version"]
+           "robast_last_error", "robast_abi_version", "robast_build_batch", "robast_trace_batch",
+           "robast_figures_batch", "robast_trace_backward_batch", "robast_batch_sizes", "robast_destroy_batch"]
 
 
 class VolumeDesc(ctypes.Structure):
@@ -72,8 +73,18 @@ _lib.robast_destroy_scene.restype = None
 _lib.robast_status_string.argtypes = [ctypes.c_int]
 _lib.robast_status_string.restype = ctypes.c_char_p
 _lib.robast_last_error.restype = ctypes.c_char_p
+_lib.robast_build_batch.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_uint32,
+                                    ctypes.POINTER(ctypes.c_void_p)]
+_lib.robast_trace_batch.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ctypes.POINTER(Hits), ctypes.c_void_p]
+_lib.robast_figures_batch.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+_lib.robast_trace_backward_batch.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+_lib.robast_batch_sizes.argtypes = [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int64)] * 3
+_lib.robast_destroy_batch.argtypes = [ctypes.c_void_p]
+_lib.robast_destroy_batch.restype = None
 for _name in ("robast_build_scene", "robast_trace", "robast_figures", "robast_trace_backward",
-              "robast_update_params", "robast_abi_version"):
+              "robast_update_params", "robast_abi_version", "robast_build_batch", "robast_trace_batch",
+              "robast_figures_batch", "robast_trace_backward_batch", "robast_batch_sizes"):
     getattr(_lib, _name).restype = ctypes.c_int
 
 
@@ -117,6 +128,24 @@ def build_scene_raw(volumes, precision, max_events, n_groups, seed, l_ref, param
     st = _lib.robast_build_scene(ctypes.byref(desc), P.ctypes.data if len(P) else None, len(P),
                                  ctypes.byref(h))
     return st, h
+
+
+_HIT_KEYS = ("fate", "n_events", "last_vol", "x", "y", "z", "ux", "uy", "uz", "opl", "seq_hash")
+
+
+def _rays_struct(rays, id_base=0, offset=0):
+    def p(k):
+        t = rays[k]
+        return t.data_ptr() + offset * t.element_size()
+    g = rays.get("group")
+    return Rays(p("ox"), p("oy"), p("oz"), p("dx"), p("dy"), p("dz"),
+                (g.data_ptr() + offset * g.element_size()) if g is not None else None, id_base + offset)
+
+
+def _hits_struct(hits, sums):
+    hits = hits or {}
+    return Hits(*[(hits[k].data_ptr() if hits.get(k) is not None else None) for k in _HIT_KEYS],
+                sums.data_ptr() if sums is not None else None)
 
 
 class Scene:
@@ -181,22 +210,14 @@ class Scene:
 
     @staticmethod
     def _rays_struct(rays, id_base=0, offset=0):
-        def p(k):
-            t = rays[k]
-            return ctypes.c_void_p(t.data_ptr() + offset * t.element_size())
-        g = rays.get("group")
-        return Rays(p("ox").value, p("oy").value, p("oz").value, p("dx").value, p("dy").value, p("dz").value,
-                    (g.data_ptr() + offset * g.element_size()) if g is not None else None, id_base + offset)
+        return _rays_struct(rays, id_base, offset)
 
     # -------------------------------------------------------------- calls
     def trace(self, rays, n=None, hits=None, sums=None, id_base=0, stream=None):
         """Trace n photons; writes the given hit tensors and/or accumulates sums."""
         n = int(rays["ox"].numel()) if n is None else int(n)
         hits = hits or {}
-        H = Hits(*[(_ptr(hits.get(k)).value if hits.get(k) is not None else None)
-                   for k in ("fate", "n_events", "last_vol", "x", "y", "z", "ux", "uy", "uz", "opl",
-                             "seq_hash")],
-                 _ptr(sums).value if sums is not None else None)
+        H = _hits_struct(hits, sums)
         R = self._rays_struct(rays, id_base)
         _check(_lib.robast_trace(self._h, ctypes.byref(R), n, ctypes.byref(H), 0, _stream(stream)),
                "robast_trace")
@@ -221,6 +242,90 @@ class Scene:
         _check(_lib.robast_update_params(self._h, P.ctypes.data if len(P) else None, len(P)),
                "robast_update_params")
         self.params = P.copy()
+
+
+class Batch:
+    """Scene variants traced together: one persistent launch per call.
+
+    ``counts[v]`` photons of variant ``v`` occupy rays
+    ``[offsets[v], offsets[v+1])`` of one concatenated bundle and are
+    numbered from ``offsets[v]``; sums, cotangents, figures and gradients are
+    concatenated per variant (``goff`` / ``poff`` give each variant's first
+    group / parameter).  The member scenes are kept alive by the batch.
+    """
+
+    def __init__(self, scenes, counts, chunk=8192):
+        self.scenes = list(scenes)
+        precisions = {s.precision for s in self.scenes}
+        self.precision = self.scenes[0].precision if len(precisions) == 1 else None
+        counts = np.asarray(counts, dtype=np.int64)
+        self.offsets = np.zeros(len(self.scenes) + 1, dtype=np.int64)
+        self.offsets[1:] = np.cumsum(counts) if len(counts) else []
+        self.goff = np.concatenate([[0], np.cumsum([s.n_groups for s in self.scenes])]).astype(np.int64)
+        self.poff = np.concatenate([[0], np.cumsum([s.n_params for s in self.scenes])]).astype(np.int64)
+        handles = (ctypes.c_void_p * max(1, len(self.scenes)))(*[s.handle.value for s in self.scenes])
+        offs = np.ascontiguousarray(self.offsets)
+        h = ctypes.c_void_p()
+        _check(_lib.robast_build_batch(handles, len(self.scenes), offs.ctypes.data, int(chunk), ctypes.byref(h)),
+               "robast_build_batch")
+        self._h = h
+        n = [ctypes.c_int64() for _ in range(3)]
+        _check(_lib.robast_batch_sizes(h, *[ctypes.byref(x) for x in n]), "robast_batch_sizes")
+        self.n_photons, self.n_groups, self.n_params = (int(x.value) for x in n)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.robast_destroy_batch(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def new_sums(self, device="cuda"):
+        import torch
+        return torch.zeros(self.n_groups * GROUP_STRIDE, dtype=torch.float64, device=device)
+
+    def _check_sizes(self, rays, hits=None, sums=None, grad=None, cot=None):
+        # the C ABI takes plain pointers: the extents are checked here
+        for k in ("ox", "oy", "oz", "dx", "dy", "dz", "group"):
+            if rays.get(k) is not None and rays[k].numel() < self.n_photons:
+                raise ValueError(f"rays[{k!r}] holds {rays[k].numel()} < {self.n_photons} photons")
+        for k, t in (hits or {}).items():
+            if t is not None and k in _HIT_KEYS and t.numel() < self.n_photons:
+                raise ValueError(f"hits[{k!r}] holds {t.numel()} < {self.n_photons} photons")
+        for name, t, need in (("sums", sums, self.n_groups * GROUP_STRIDE), ("grad", grad, self.n_params),
+                              ("cot", cot, self.n_groups * 2)):
+            if t is not None and t.numel() < need:
+                raise ValueError(f"{name} holds {t.numel()} < {need} values")
+
+    def trace(self, rays, hits=None, sums=None, id_base=0, stream=None):
+        self._check_sizes(rays, hits, sums)
+        H = _hits_struct(hits, sums)
+        R = _rays_struct(rays, id_base)
+        _check(_lib.robast_trace_batch(self._h, ctypes.byref(R), ctypes.byref(H), _stream(stream)),
+               "robast_trace_batch")
+        return hits
+
+    def figures(self, sums, fig=None, stream=None):
+        import torch
+        if fig is None:
+            fig = torch.zeros(self.n_groups * FIGURE_STRIDE, dtype=torch.float64, device=sums.device)
+        _check(_lib.robast_figures_batch(self._h, _ptr(sums), _ptr(fig), _stream(stream)), "robast_figures_batch")
+        return fig.view(self.n_groups, FIGURE_STRIDE)
+
+    def backward(self, rays, sums, cot, grad, id_base=0, stream=None):
+        self._check_sizes(rays, None, sums, grad, cot)
+        R = _rays_struct(rays, id_base)
+        _check(_lib.robast_trace_backward_batch(self._h, ctypes.byref(R), _ptr(sums), _ptr(cot), _ptr(grad),
+                                                _stream(stream)), "robast_trace_backward_batch")
+        return grad
 
 
 def _autograd():

@@ -8,12 +8,14 @@
 
 #include <algorithm>
 #include <array>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
 
 #include "../../include/robast.h"
+#include "batch.hpp"
 #include "kernels.hpp"
 #include "scene_layout.hpp"
 
@@ -160,9 +162,26 @@ struct robast_scene {
   size_t blob_bytes = 0;
   DTilt* d_tilt = nullptr;
   double* d_coef = nullptr;    // n_groups * 4 backward coefficients
+  void* d_view = nullptr;      // device copy of sf / sd, read by batched launches
   SceneView<float> sf{};
   SceneView<double> sd{};
   LaunchCfg cfg{};
+};
+
+// LDS a workgroup may use for a scene's tables: three workgroups of four
+// waves (the trace kernel's occupancy) share the 160 KiB of a CU.
+constexpr int kLdsCap = (160 * 1024 / 3) & ~15;
+
+struct robast_batch {
+  int precision = 32;
+  std::vector<robast_scene*> scenes;
+  int64_t n_photons = 0, n_groups = 0, n_params = 0;
+  int max_events = 0, max_params = 0, n_items = 0;
+  uint32_t blob_cap = 0;
+  void* d_vars = nullptr;          // BatchVariant<T>[n_scenes]
+  BatchItem* d_items = nullptr;    // n_items
+  uint32_t* d_queue = nullptr;     // 2 counters
+  double* d_coef = nullptr;        // n_groups * 4
 };
 
 namespace {
@@ -673,7 +692,62 @@ int upload(robast_scene* s) {
   }
   if (s->precision == 32) rebase(s->sf, offs, (const char*)s->d_blob);
   else rebase(s->sd, offs, (const char*)s->d_blob);
+  if (!s->d_view) {
+    e = hipMalloc(&s->d_view, sizeof(SceneView<double>));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc view");
+  }
+  if (s->precision == 32) e = hipMemcpy(s->d_view, &s->sf, sizeof(SceneView<float>), hipMemcpyHostToDevice);
+  else e = hipMemcpy(s->d_view, &s->sd, sizeof(SceneView<double>), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy view");
   return ROBAST_OK;
+}
+
+template <typename T> RaysView<T> rays_view(const robast_rays* r) {
+  return RaysView<T>{(const T*)r->ox, (const T*)r->oy, (const T*)r->oz, (const T*)r->dx, (const T*)r->dy,
+                     (const T*)r->dz, r->group, r->id_base};
+}
+
+template <typename T> HitsView<T> hits_view(const robast_hits* h) {
+  return HitsView<T>{h->fate, h->n_events, h->last_vol, (T*)h->x, (T*)h->y, (T*)h->z, (T*)h->ux, (T*)h->uy,
+                     (T*)h->uz, (T*)h->opl, h->seq_hash, h->group_sums};
+}
+
+int check_rays(const robast_rays* rays) {
+  if (!rays->ox || !rays->oy || !rays->oz || !rays->dx || !rays->dy || !rays->dz)
+    return fail(ROBAST_EINVAL, "NULL ray coordinate array");
+  return ROBAST_OK;
+}
+
+int check_hits(const robast_hits* hits) {
+  if (hits->x && (!hits->y || !hits->z)) return fail(ROBAST_EINVAL, "x given without y, z");
+  if (hits->ux && (!hits->uy || !hits->uz)) return fail(ROBAST_EINVAL, "ux given without uy, uz");
+  return ROBAST_OK;
+}
+
+template <typename T> BatchView<T> batch_view(const robast_batch* b) {
+  return BatchView<T>{(const BatchVariant<T>*)b->d_vars, b->d_items, b->d_queue, b->n_items, b->max_events,
+                      b->max_params, b->blob_cap};
+}
+
+template <typename T> std::vector<BatchVariant<T>> variant_table(const robast_batch& b, const int64_t* offsets) {
+  std::vector<BatchVariant<T>> t(b.scenes.size());
+  int64_t goff = 0, poff = 0;
+  for (size_t v = 0; v < b.scenes.size(); ++v) {
+    const robast_scene* s = b.scenes[v];
+    t[v] = BatchVariant<T>{(const SceneView<T>*)s->d_view, s->d_tilt, offsets[v], (int32_t)goff, (int32_t)poff,
+                           (int32_t)s->params.size(), 0};
+    goff += s->n_groups;
+    poff += (int64_t)s->params.size();
+  }
+  return t;
+}
+
+void free_batch(robast_batch* b) {
+  if (b->d_vars) (void)hipFree(b->d_vars);
+  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_queue) (void)hipFree(b->d_queue);
+  if (b->d_coef) (void)hipFree(b->d_coef);
+  delete b;
 }
 
 }  // namespace
@@ -711,7 +785,7 @@ int robast_build_scene(const robast_scene_desc* desc, const double* params, int6
   s->l_ref = desc->l_ref;
   s->desc.assign(desc->volumes, desc->volumes + desc->n_volumes);
   s->params.assign(params, params + n_params);
-  s->cfg.lds_cap = 48 * 1024;
+  s->cfg.lds_cap = kLdsCap;
   s->cfg.waves_mult = 1;
   s->cfg.max_blocks = 0;
   rc = upload(s);
@@ -737,6 +811,7 @@ void robast_destroy_scene(robast_scene* s) {
   if (s->d_blob) (void)hipFree(s->d_blob);
   if (s->d_tilt) (void)hipFree(s->d_tilt);
   if (s->d_coef) (void)hipFree(s->d_coef);
+  if (s->d_view) (void)hipFree(s->d_view);
   delete s;
 }
 
@@ -746,29 +821,13 @@ int robast_trace(robast_scene* s, const robast_rays* rays, int64_t n, const roba
   if (!s || !rays || !hits) return fail(ROBAST_EINVAL, "NULL scene, rays or hits");
   if (n < 0) return fail(ROBAST_EINVAL, "n < 0");
   if (n == 0) return ROBAST_OK;
-  if (!rays->ox || !rays->oy || !rays->oz || !rays->dx || !rays->dy || !rays->dz)
-    return fail(ROBAST_EINVAL, "NULL ray coordinate array");
-  if (hits->x && (!hits->y || !hits->z)) return fail(ROBAST_EINVAL, "x given without y, z");
-  if (hits->ux && (!hits->uy || !hits->uz)) return fail(ROBAST_EINVAL, "ux given without uy, uz");
+  int rc = check_rays(rays);
+  if (!rc) rc = check_hits(hits);
+  if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;
-  if (s->precision == 32) {
-    RaysView<float> R{(const float*)rays->ox, (const float*)rays->oy, (const float*)rays->oz,
-                      (const float*)rays->dx, (const float*)rays->dy, (const float*)rays->dz, rays->group,
-                      rays->id_base};
-    HitsView<float> H{hits->fate, hits->n_events, hits->last_vol, (float*)hits->x, (float*)hits->y,
-                      (float*)hits->z, (float*)hits->ux, (float*)hits->uy, (float*)hits->uz,
-                      (float*)hits->opl, hits->seq_hash, hits->group_sums};
-    e = launch_trace<float>(s->sf, R, n, H, s->cfg, st);
-  } else {
-    RaysView<double> R{(const double*)rays->ox, (const double*)rays->oy, (const double*)rays->oz,
-                       (const double*)rays->dx, (const double*)rays->dy, (const double*)rays->dz, rays->group,
-                       rays->id_base};
-    HitsView<double> H{hits->fate, hits->n_events, hits->last_vol, (double*)hits->x, (double*)hits->y,
-                       (double*)hits->z, (double*)hits->ux, (double*)hits->uy, (double*)hits->uz,
-                       (double*)hits->opl, hits->seq_hash, hits->group_sums};
-    e = launch_trace<double>(s->sd, R, n, H, s->cfg, st);
-  }
+  if (s->precision == 32) e = launch_trace<float>(s->sf, rays_view<float>(rays), n, hits_view<float>(hits), s->cfg, st);
+  else e = launch_trace<double>(s->sd, rays_view<double>(rays), n, hits_view<double>(hits), s->cfg, st);
   if (e != hipSuccess) return hip_fail(e, "trace launch");
   return ROBAST_OK;
 }
@@ -785,26 +844,129 @@ int robast_trace_backward(robast_scene* s, const robast_rays* rays, int64_t n, c
   if (!s || !rays || !sums || !cot || !grad) return fail(ROBAST_EINVAL, "NULL scene, rays, sums, cot or grad");
   if (n < 0) return fail(ROBAST_EINVAL, "n < 0");
   if (n == 0) return ROBAST_OK;
-  if (!rays->ox || !rays->oy || !rays->oz || !rays->dx || !rays->dy || !rays->dz)
-    return fail(ROBAST_EINVAL, "NULL ray coordinate array");
+  int rc = check_rays(rays);
+  if (rc) return rc;
   if (s->max_events > 64) return fail(ROBAST_EUNSUPPORTED, "backward supports max_events <= 64");
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = launch_adj_coef(sums, cot, s->d_coef, s->n_groups, st);
   if (e != hipSuccess) return hip_fail(e, "coefficient launch");
   AdjView A{s->d_coef, grad, s->d_tilt, (int)s->params.size()};
-  if (s->precision == 32) {
-    RaysView<float> R{(const float*)rays->ox, (const float*)rays->oy, (const float*)rays->oz,
-                      (const float*)rays->dx, (const float*)rays->dy, (const float*)rays->dz, rays->group,
-                      rays->id_base};
-    e = launch_backward<float>(s->sf, R, n, A, s->cfg, st);
-  } else {
-    RaysView<double> R{(const double*)rays->ox, (const double*)rays->oy, (const double*)rays->oz,
-                       (const double*)rays->dx, (const double*)rays->dy, (const double*)rays->dz, rays->group,
-                       rays->id_base};
-    e = launch_backward<double>(s->sd, R, n, A, s->cfg, st);
-  }
+  if (s->precision == 32) e = launch_backward<float>(s->sf, rays_view<float>(rays), n, A, s->cfg, st);
+  else e = launch_backward<double>(s->sd, rays_view<double>(rays), n, A, s->cfg, st);
   if (e != hipSuccess) return hip_fail(e, "backward launch");
   return ROBAST_OK;
+}
+
+// ---- batched design sweeps
+
+int robast_build_batch(robast_scene* const* scenes, int32_t n_scenes, const int64_t* offsets, uint32_t chunk,
+                       robast_batch** out) {
+  if (!out) return fail(ROBAST_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!scenes || !offsets) return fail(ROBAST_EINVAL, "NULL scenes or offsets");
+  if (n_scenes < 1) return fail(ROBAST_EINVAL, "n_scenes < 1");
+  if (chunk == 0 || chunk > (1u << 30)) return fail(ROBAST_EINVAL, "chunk must be in [1, 2^30]");
+  if (offsets[0] != 0) return fail(ROBAST_EINVAL, "offsets[0] != 0");
+  for (int v = 0; v < n_scenes; ++v) {
+    if (!scenes[v]) return fail(ROBAST_EINVAL, "NULL scene in batch");
+    if (offsets[v + 1] < offsets[v]) return fail(ROBAST_EINVAL, "offsets decrease");
+    if (scenes[v]->precision != scenes[0]->precision) return fail(ROBAST_EINVAL, "scenes of different precision");
+  }
+  if (scenes[0]->precision != 32) return fail(ROBAST_EUNSUPPORTED, "batches are built for FP32 scenes");
+  std::vector<BatchItem> items;
+  for (int v = 0; v < n_scenes; ++v)
+    for (int64_t st = offsets[v]; st < offsets[v + 1]; st += chunk)
+      items.push_back(BatchItem{st, (int32_t)std::min<int64_t>(chunk, offsets[v + 1] - st), v});
+  if (items.size() > (size_t)INT32_MAX - 65536) return fail(ROBAST_EINVAL, "too many work items: raise chunk");
+  robast_batch* b = new robast_batch();
+  b->precision = scenes[0]->precision;
+  b->scenes.assign(scenes, scenes + n_scenes);
+  b->n_photons = offsets[n_scenes];
+  b->n_items = (int)items.size();
+  size_t max_blob = 0;
+  for (robast_scene* s : b->scenes) {
+    b->n_groups += s->n_groups;
+    b->n_params += (int64_t)s->params.size();
+    b->max_events = std::max(b->max_events, s->max_events);
+    b->max_params = std::max(b->max_params, (int)s->params.size());
+    max_blob = std::max(max_blob, s->blob_bytes);
+  }
+  if (b->n_groups > INT32_MAX || b->n_params > INT32_MAX) {
+    free_batch(b);
+    return fail(ROBAST_EINVAL, "too many groups or parameters");
+  }
+  // LDS reserved per workgroup for a variant's tables, with room for the
+  // tables to grow under parameter updates; a variant that outgrows it is
+  // read from global memory instead.
+  const size_t lds_cap = (size_t)scenes[0]->cfg.lds_cap;
+  if (max_blob <= lds_cap) b->blob_cap = (uint32_t)std::min(lds_cap, ((max_blob * 3 / 2) + 15) & ~(size_t)15);
+  const size_t vbytes = sizeof(BatchVariant<float>);
+  hipError_t e = hipMalloc(&b->d_vars, vbytes * n_scenes);
+  if (e == hipSuccess) e = hipMalloc(&b->d_items, sizeof(BatchItem) * std::max<size_t>(1, items.size()));
+  if (e == hipSuccess) e = hipMalloc(&b->d_queue, kQueueCounters * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc(&b->d_coef, sizeof(double) * 4 * std::max<int64_t>(1, b->n_groups));
+  if (e != hipSuccess) {
+    free_batch(b);
+    return fail(ROBAST_ENOMEM, "hipMalloc batch tables");
+  }
+  {
+    auto t = variant_table<float>(*b, offsets);
+    e = hipMemcpy(b->d_vars, t.data(), vbytes * n_scenes, hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess && !items.empty())
+    e = hipMemcpy(b->d_items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_batch(b);
+    return hip_fail(e, "hipMemcpy batch tables");
+  }
+  *out = b;
+  return ROBAST_OK;
+}
+
+int robast_trace_batch(robast_batch* b, const robast_rays* rays, const robast_hits* hits, void* stream) {
+  if (!b || !rays || !hits) return fail(ROBAST_EINVAL, "NULL batch, rays or hits");
+  if (b->n_photons == 0) return ROBAST_OK;
+  int rc = check_rays(rays);
+  if (!rc) rc = check_hits(hits);
+  if (rc) return rc;
+  hipError_t e = launch_trace_batch(batch_view<float>(b), rays_view<float>(rays), hits_view<float>(hits),
+                                    (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "batched trace launch");
+  return ROBAST_OK;
+}
+
+int robast_figures_batch(robast_batch* b, const double* sums, double* fig, void* stream) {
+  if (!b || !sums || !fig) return fail(ROBAST_EINVAL, "NULL batch, sums or figures");
+  hipError_t e = launch_figures(sums, fig, (int)b->n_groups, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "figures launch");
+  return ROBAST_OK;
+}
+
+int robast_trace_backward_batch(robast_batch* b, const robast_rays* rays, const double* sums, const double* cot,
+                                double* grad, void* stream) {
+  if (!b || !rays || !sums || !cot || !grad) return fail(ROBAST_EINVAL, "NULL batch, rays, sums, cot or grad");
+  if (b->n_photons == 0) return ROBAST_OK;
+  int rc = check_rays(rays);
+  if (rc) return rc;
+  if (b->max_events > 32) return fail(ROBAST_EUNSUPPORTED, "batched backward supports max_events <= 32");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = launch_adj_coef(sums, cot, b->d_coef, (int)b->n_groups, st);
+  if (e != hipSuccess) return hip_fail(e, "coefficient launch");
+  e = launch_backward_batch(batch_view<float>(b), rays_view<float>(rays), b->d_coef, grad, st);
+  if (e != hipSuccess) return hip_fail(e, "batched backward launch");
+  return ROBAST_OK;
+}
+
+int robast_batch_sizes(const robast_batch* b, int64_t* n_photons, int64_t* n_groups, int64_t* n_params) {
+  if (!b) return fail(ROBAST_EINVAL, "NULL batch");
+  if (n_photons) *n_photons = b->n_photons;
+  if (n_groups) *n_groups = b->n_groups;
+  if (n_params) *n_params = b->n_params;
+  return ROBAST_OK;
+}
+
+void robast_destroy_batch(robast_batch* b) {
+  if (b) free_batch(b);
 }
 
 }  // extern "C"

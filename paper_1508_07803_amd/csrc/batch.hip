@@ -1,0 +1,194 @@
+// Batched forward trace: many scene variants in one persistent launch.
+//
+// Inside a work item the lanes trace with event-level refill exactly like
+// the single-scene kernel and number photons from the variant's first
+// photon, so every photon's result equals that of a single-scene call on its
+// variant.  Per-lane FP64 figure sums are reduced across the wave per group
+// before one atomic per wave and sum.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "batch_device.hpp"
+#include "device_trace.hpp"
+#include "kernels.hpp"
+
+namespace robast {
+
+constexpr int kNSumB = 7;   // launched, focused, x, y, x^2, y^2, |u_z|
+
+__global__ void k_batch_reset(uint32_t* q, int first, int count) {
+  if ((int)threadIdx.x < count) q[first + threadIdx.x] = 0u;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Adds each lane's sums (group ag, values a) into target[group * 8 + k]: the
+// lanes holding the group of the lowest holding lane reduce across the wave
+// and that lane issues the atomics; repeated until no lane holds sums.  Must
+// be reached by the whole wave.
+__device__ __forceinline__ void wave_flush(double* target, int& ag, double* a) {
+  while (true) {
+    const unsigned long long m = __ballot(ag >= 0);
+    if (m == 0ull) break;
+    const int lead = __ffsll((unsigned long long)m) - 1;
+    const int gsel = __shfl(ag, lead, 64);
+    const bool mine = ag == gsel;
+#pragma unroll
+    for (int k = 0; k < kNSumB; ++k) {
+      const double v = wave_sum(mine ? a[k] : 0.0);
+      if ((int)(threadIdx.x & 63) == lead && v != 0.0) atomicAdd(target + gsel * 8 + k, v);
+    }
+    if (mine) {
+#pragma unroll
+      for (int k = 0; k < kNSumB; ++k) a[k] = 0.0;
+      ag = -1;
+    }
+  }
+}
+
+// Traces photons [start, end) of one variant whose first photon is `off`.
+// Reached by the whole workgroup.
+template <bool RECORD>
+__device__ __forceinline__ void trace_item(const SceneView<float>& L, int64_t start, int64_t end, int64_t off,
+                                           const RaysView<float>& R, const HitsView<float>& H, double* target,
+                                           int& ag, double* a) {
+  int64_t next = start + threadIdx.x;
+  int64_t cur = -1;
+  int g = -1;
+  PhotonState ps;
+  ps.fate = 1;
+  while (true) {
+    bool started = false;
+    if (cur < 0 && next < end) {
+      cur = next;
+      next += blockDim.x;
+      V3<float> o = {R.ox[cur], R.oy[cur], R.oz[cur]};
+      V3<float> d = {R.dx[cur], R.dy[cur], R.dz[cur]};
+      g = R.group ? (int)R.group[cur] : 0;
+      if ((unsigned)g >= (unsigned)L.n_groups) g = -1;
+      photon_init(ps, o, d, R.id_base + (uint64_t)(cur - off));
+      started = true;
+    }
+    if (!__any(cur >= 0)) break;
+    if (target && __any(started && g >= 0 && ag >= 0 && g != ag)) wave_flush(target, ag, a);
+    if (cur >= 0) {
+      if (!ps.fate) photon_step(L, ps);
+      if (ps.fate) {
+        PhotonOut<float> r = photon_out<float>(ps);
+        if (RECORD) {
+          if (H.fate) H.fate[cur] = (uint8_t)r.fate;
+          if (H.nev) H.nev[cur] = (uint8_t)r.nev;
+          if (H.last_vol) H.last_vol[cur] = r.last_vol;
+          if (H.x) { H.x[cur] = r.pos.x; H.y[cur] = r.pos.y; H.z[cur] = r.pos.z; }
+          if (H.ux) { H.ux[cur] = r.dir.x; H.uy[cur] = r.dir.y; H.uz[cur] = r.dir.z; }
+          if (H.opl) H.opl[cur] = r.opl;
+          if (H.hash) H.hash[cur] = r.hash;
+        }
+        if (target && g >= 0) {
+          ag = g;
+          a[0] += 1.0;
+          if (r.fate == FOCUSED) {
+            double x = (double)r.pos.x, y = (double)r.pos.y;
+            a[1] += 1.0; a[2] += x; a[3] += y; a[4] += x * x; a[5] += y * y;
+            a[6] += (double)dabs(r.dir.z);
+          }
+        }
+        cur = -1;
+      }
+    }
+  }
+}
+
+// USE_LDS: the items of variants that fit the LDS reservation; otherwise the
+// items of the others.  The LDS form is held to 3 waves per SIMD (<= 168
+// VGPRs), which the search needs to hide its LDS latency.
+template <bool USE_LDS, bool RECORD>
+__global__ void __launch_bounds__(kBlockB) __attribute__((amdgpu_waves_per_eu(USE_LDS ? 3 : 1, USE_LDS ? 3 : 8)))
+k_trace_batch(const BatchVariant<float>* vars, const BatchItem* items, int n_items, uint32_t* queue,
+              uint32_t blob_cap, RaysView<float> R, HitsView<float> H) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ int s_item;
+  SceneView<float> S = {};
+  SceneView<float> L;
+  lds_view(L, lds);
+  bool mine = false;
+  int cur_v = -1;
+  int64_t off = 0;
+  double* target = nullptr;
+  double a[kNSumB];
+#pragma unroll
+  for (int k = 0; k < kNSumB; ++k) a[k] = 0.0;
+  int ag = -1;
+  uint32_t* counter = queue + (USE_LDS ? 0 : 1);
+  while (true) {
+    const int item = next_item(counter, &s_item);
+    if (item >= n_items) break;
+    const BatchItem it = items[item];
+    if (it.v != cur_v) {
+      if (target) wave_flush(target, ag, a);
+      const BatchVariant<float> bv = vars[it.v];
+      S = *bv.S;
+      mine = fits_lds(S, blob_cap) == USE_LDS;
+      if (USE_LDS && mine) stage_variant<float>(S, L, lds);
+      target = H.sums ? H.sums + (int64_t)bv.goff * 8 : nullptr;
+      off = bv.off;
+      cur_v = it.v;
+      __syncthreads();
+    }
+    if (!mine) continue;
+    trace_item<RECORD>(USE_LDS ? L : S, it.start, it.start + it.count, off, R, H, target, ag, a);
+    // a change of variant overwrites LDS: every wave must be done with it
+    __syncthreads();
+  }
+  if (target) wave_flush(target, ag, a);
+}
+
+// ------------------------------------------------------------------ launcher
+static hipError_t cu_count(int& ncu) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  return hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+}
+
+template <bool USE_LDS, bool RECORD>
+static hipError_t trace_batch_k(const BatchView<float>& B, const RaysView<float>& R, const HitsView<float>& H,
+                                int ncu, hipStream_t st) {
+  const size_t shmem = USE_LDS ? B.blob_cap : 0;
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace_batch<USE_LDS, RECORD>, kBlockB,
+                                                              shmem);
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
+  const int blocks = std::max(1, std::min(B.n_items, ncu * per_cu));
+  hipLaunchKernelGGL((k_trace_batch<USE_LDS, RECORD>), dim3(blocks), dim3(kBlockB), shmem, st, B.vars, B.items,
+                     B.n_items, B.queue, B.blob_cap, R, H);
+  return hipGetLastError();
+}
+
+template <bool RECORD>
+static hipError_t trace_batch_r(const BatchView<float>& B, const RaysView<float>& R, const HitsView<float>& H,
+                                int ncu, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  if (B.blob_cap > 0) e = trace_batch_k<true, RECORD>(B, R, H, ncu, st);
+  if (e == hipSuccess) e = trace_batch_k<false, RECORD>(B, R, H, ncu, st);
+  return e;
+}
+
+hipError_t launch_trace_batch(const BatchView<float>& B, const RaysView<float>& R, const HitsView<float>& H,
+                              hipStream_t st) {
+  int ncu = 0;
+  hipError_t e = cu_count(ncu);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, B.queue, 0, 2);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const bool rec = H.fate || H.nev || H.last_vol || H.x || H.ux || H.opl || H.hash;
+  return rec ? trace_batch_r<true>(B, R, H, ncu, st) : trace_batch_r<false>(B, R, H, ncu, st);
+}
+
+}  // namespace robast

@@ -278,7 +278,7 @@ def davies_cotton(seed=SEED_BASE + 1, sigma_tilt=1e-4, fields_deg=(0.0, 0.5, 1.0
         return _pack_rays(scene.precision, *cols)
 
     return _finish("davies_cotton", vols, params, names, precision, 16, seed, 28.0, groups, rays,
-                   n_facets=nf, focal_length=f)
+                   n_facets=nf, focal_length=f, beam=dict(kind="disc_perp", r_in=0.0, r_out=12.0, back=40.0))
 
 
 # ================================================================ C3
@@ -304,7 +304,7 @@ def _ring_panels(r_in, r_out, r_split, n_inner, n_outer):
 
 
 def schwarzschild_couder(seed=SEED_BASE + 2, sigma_tilt=5e-5, n_fields=16, max_field_deg=4.0,
-                         coeff_scale=None, tilts=None, precision=32):
+                         coeff_scale=None, tilts=None, precision=32, fields_deg=None):
     """Two-mirror Schwarzschild-Couder telescope with segmented aspheric mirrors.
 
     Sag z = sum_{i=1..8} b_i u^i with u = (r/rn)^2 (normalised form; the
@@ -318,6 +318,8 @@ def schwarzschild_couder(seed=SEED_BASE + 2, sigma_tilt=5e-5, n_fields=16, max_f
     radial and tangential axes.  Focal surface: a spherical cap of radius
     1 m, vertex at z = 5.3257 m, centre of curvature below, aperture 0.6 m.
     Parameters: 8 primary b_i, 8 secondary b_i, 2 tilts per panel (144).
+    Fields: n_fields angles evenly spaced in [0, max_field_deg], or the
+    explicit list fields_deg.
     """
     rng = np.random.default_rng(seed)
     pri, sec = SC_PRIMARY, SC_SECONDARY
@@ -359,7 +361,10 @@ def schwarzschild_couder(seed=SEED_BASE + 2, sigma_tilt=5e-5, n_fields=16, max_f
             k += 1
     vols.append(new_volume(ROLE_FOCAL, SHAPE_SPHERE, OUTLINE_DISC, c=(0.0, 0.0, SC_FOCAL_Z),
                            p=[-1.0], o=[0.6]))
-    groups = np.radians(np.linspace(0.0, max_field_deg, n_fields))
+    if fields_deg is None:
+        groups = np.radians(np.linspace(0.0, max_field_deg, n_fields))
+    else:
+        groups = np.radians(np.asarray(fields_deg, dtype=np.float64))
 
     def rays(scene, n, s, gsel):
         rng2 = np.random.default_rng(s)
@@ -377,7 +382,71 @@ def schwarzschild_couder(seed=SEED_BASE + 2, sigma_tilt=5e-5, n_fields=16, max_f
         return _pack_rays(scene.precision, *cols)
 
     return _finish("schwarzschild_couder", vols, params, names, precision, 16, seed, 5.6, groups, rays,
-                   n_panels=npan, focal_z=SC_FOCAL_Z)
+                   n_panels=npan, focal_z=SC_FOCAL_Z,
+                   beam=dict(kind="annulus_z0", r_in=pri["r_in"], r_out=pri["r_out"], back=12.0))
+
+
+# ================================================================ C5
+def sweep(seed=SEED_BASE + 5, n_dc=128, n_sc=128, field_deg=1.0, log10_n=(5.0, 7.0), precision=32):
+    """Batched design sweep: seeded variants of the Davies-Cotton and
+    Schwarzschild-Couder scenes at one field angle.
+
+    Each variant perturbs its family's baseline: facet radii and aspheric
+    coefficients times (1 + N(0, 1e-3)), tilts drawn with the family's sigma
+    (0.1 mrad DC, 0.05 mrad SC).  Photon counts are round(10^U(lo, hi)).
+    Returns (list of Scene, int64 counts); DC variants first.
+    """
+    rng = np.random.default_rng(seed)
+    variants = []
+    for v in range(n_dc):
+        rs = 1.0 + rng.normal(0.0, 1e-3, 198)
+        tl = rng.normal(0.0, 1e-4, (198, 2))
+        variants.append(davies_cotton(seed=seed + 1 + v, fields_deg=(field_deg,), radius_scale=rs, tilts=tl,
+                                      precision=precision))
+    for v in range(n_sc):
+        cs = 1.0 + rng.normal(0.0, 1e-3, 16)
+        tl = rng.normal(0.0, 5e-5, (72, 2))
+        variants.append(schwarzschild_couder(seed=seed + 1 + n_dc + v, fields_deg=(field_deg,), coeff_scale=cs,
+                                             tilts=tl, precision=precision))
+    counts = np.rint(10.0 ** rng.uniform(log10_n[0], log10_n[1], n_dc + n_sc)).astype(np.int64)
+    return variants, counts
+
+
+def device_rays(scene, n, seed, group=0, device="cuda"):
+    """Parallel beam of n photons for one field of a telescope scene,
+    generated on the device with torch's seeded generator (the same beam
+    geometry as Scene.rays, a different random stream).  Returns a dict of
+    device tensors in the scene precision plus int32 groups."""
+    import torch
+    b = scene.meta["beam"]
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
+    f64 = torch.float64
+    u1 = torch.rand(n, generator=gen, device=device, dtype=f64)
+    u2 = torch.rand(n, generator=gen, device=device, dtype=f64)
+    th = float(scene.groups[group])
+    d = (math.sin(th), 0.0, -math.cos(th))
+    ph = (2.0 * math.pi) * u2
+    if b["kind"] == "disc_perp":
+        r = b["r_out"] * torch.sqrt(u1)
+        px, py = r * torch.cos(ph), r * torch.sin(ph)
+        e1 = (math.cos(th), 0.0, math.sin(th))
+        ox = -b["back"] * d[0] + px * e1[0]
+        oy = py
+        oz = -b["back"] * d[2] + px * e1[2]
+    elif b["kind"] == "annulus_z0":
+        r = torch.sqrt(b["r_in"] ** 2 + u1 * (b["r_out"] ** 2 - b["r_in"] ** 2))
+        ox = r * torch.cos(ph) - b["back"] * d[0]
+        oy = r * torch.sin(ph)
+        oz = torch.full_like(u1, -b["back"] * d[2])
+    else:
+        raise ValueError(f"no device beam for {b['kind']}")
+    dt = torch.float32 if scene.precision == 32 else torch.float64
+    out = dict(ox=ox.to(dt), oy=oy.to(dt), oz=oz.to(dt))
+    for k, val in zip(("dx", "dy", "dz"), d):
+        out[k] = torch.full((n,), val, dtype=dt, device=device)
+    out["group"] = torch.full((n,), int(group), dtype=torch.int32, device=device)
+    return out
 
 
 # ================================================================ C4

@@ -81,3 +81,23 @@ def test_null_arguments_rejected(rb):
     assert lib.robast_figures(None, None, None, None) == rb.EINVAL
     assert b"NULL" in lib.robast_last_error()
     assert lib.robast_status_string(rb.EINVAL) == b"invalid argument"
+
+
+def test_batch_arguments_rejected(rb):
+    """Batch entry points validate before touching a device."""
+    import ctypes
+    lib = rb.lib()
+    h = ctypes.c_void_p()
+    offs = (ctypes.c_int64 * 3)(0, 10, 5)
+    scenes_null = (ctypes.c_void_p * 2)(None, None)
+    assert lib.robast_build_batch(None, 1, offs, 64, None) == rb.EINVAL
+    assert lib.robast_build_batch(None, 1, offs, 64, ctypes.byref(h)) == rb.EINVAL
+    assert lib.robast_build_batch(scenes_null, 0, offs, 64, ctypes.byref(h)) == rb.EINVAL
+    assert lib.robast_build_batch(scenes_null, 2, offs, 0, ctypes.byref(h)) == rb.EINVAL
+    assert lib.robast_build_batch(scenes_null, 2, offs, 64, ctypes.byref(h)) == rb.EINVAL
+    assert h.value is None
+    assert lib.robast_trace_batch(None, None, None, None) == rb.EINVAL
+    assert lib.robast_figures_batch(None, None, None, None) == rb.EINVAL
+    assert lib.robast_trace_backward_batch(None, None, None, None, None, None) == rb.EINVAL
+    assert lib.robast_batch_sizes(None, None, None, None) == rb.EINVAL
+    lib.robast_destroy_batch(None)

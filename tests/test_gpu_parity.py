@@ -72,8 +72,9 @@ def _perturbed(sc, r, idx, k, eps_pos, eps_dir):
     return oracle.trace(sc, sub, id_base=0, volumes=None)["seq_hash"], sub
 
 
-def grazing(sc, r, idx, ref_hash):
-    """True where the oracle's own sequence is not stable under 1e-5 nudges."""
+def grazing(sc, r, idx, ref_hash, id_base=0):
+    """True where the oracle's own sequence is not stable under 1e-5 nudges
+    (photon r[i] has id id_base + i)."""
     import oracle
     idx = np.asarray(idx)
     if len(idx) == 0:
@@ -84,13 +85,13 @@ def grazing(sc, r, idx, ref_hash):
         for j, i in enumerate(idx):
             sub = {key: np.asarray(v)[[i]].copy() for key, v in r.items()}
             h, moved = _perturbed(sc, sub, [0], k, 1e-5 * sc.l_ref, 1e-5)
-            hh = oracle.trace(sc, moved, id_base=int(i))["seq_hash"][0]
+            hh = oracle.trace(sc, moved, id_base=id_base + int(i))["seq_hash"][0]
             if hh != ref_hash[j]:
                 g[j] = True
     return g
 
 
-def compare(sc, r, got, ref, pos_tol, dir_tol, max_rate=1e-5):
+def compare(sc, r, got, ref, pos_tol, dir_tol, max_rate=1e-5, id_base=0):
     n = len(r["ox"])
     same = ((got["fate"] == ref["fate"]) & (got["n_events"] == ref["n_events"]) &
             (got["last_vol"] == ref["last_vol"]) & (got["seq_hash"] == ref["seq_hash"]))
@@ -100,7 +101,7 @@ def compare(sc, r, got, ref, pos_tol, dir_tol, max_rate=1e-5):
         import oracle
         g = oracle.grazing(ref, sc.l_ref)[bad] if "log" in ref else np.zeros(len(bad), bool)
         if not g.all():
-            g[~g] = grazing(sc, r, bad[~g], ref["seq_hash"][bad[~g]])
+            g[~g] = grazing(sc, r, bad[~g], ref["seq_hash"][bad[~g]], id_base)
         assert g.all(), f"non-grazing mismatches at {bad[~g][:10]}"
     foc = same & (ref["fate"] == scenes.FATE_FOCUSED)
     assert foc.sum() > 0
