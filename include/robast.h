@@ -152,7 +152,14 @@ int robast_build_scene(const robast_scene_desc* desc, const double* params, int6
                        robast_scene** out);
 
 /* Trace photons [0, n).  rays/hits as above; n == 0 is a no-op.  EINVAL on
- * NULL scene/rays/hits, n < 0, a NULL ray coordinate array. */
+ * NULL scene/rays/hits, n < 0, a NULL ray coordinate array.  `flags` is
+ * reserved (pass 0).
+ * Calls on one scene (trace, backward, update) must not overlap in time:
+ * they share the scene's photon counter and binning workspace, so issue them
+ * on one stream or order them.  With binning on (robast_tuning), a call with
+ * more photons than any before it on the scene grows the workspace
+ * (hipMalloc, 40 bytes per photon in FP32, 72 in FP64): capture a call in a HIP graph only
+ * after an eager call of at least the same size. */
 int robast_trace(robast_scene* scene, const robast_rays* rays, int64_t n, const robast_hits* hits,
                  uint32_t flags, void* hip_stream);
 
@@ -170,6 +177,34 @@ int robast_figures(robast_scene* scene, const double* d_group_sums, double* d_fi
 int robast_trace_backward(robast_scene* scene, const robast_rays* rays, int64_t n,
                           const double* d_group_sums, const double* d_cot, double* d_grad,
                           void* hip_stream);
+
+/* ---- launch tuning ------------------------------------------------------
+ * Per-scene launch parameters.  They change the order in which photons are
+ * processed, never a photon's result (each photon keeps its id, draws and
+ * search); group sums and gradients change only in FP64 summation order. */
+typedef struct robast_tuning {
+  /* nonzero: before each trace / backward call of at least 32768 photons
+   * (and at most 2^32 - 1), order the photons by group and by the cell of a
+   * square grid where their line crosses the scene's entrance plane (the
+   * lowest z of its mirrors and lenses), by a counting sort into scene-owned
+   * workspace, so that the photons of one wave take similar paths */
+  uint32_t bin_photons;
+  uint32_t bin_target;   /* photons per cell aimed at when sizing that grid, 1..65536 */
+  uint32_t wave_chunk;   /* photons a wave takes from the call's counter at a time, 64..65536 */
+  uint32_t waves_mult;   /* workgroups launched per resident workgroup slot, 1..8 */
+} robast_tuning;
+
+/* Defaults: bin_photons 1, bin_target 128, wave_chunk 256, waves_mult 1. */
+int robast_get_tuning(const robast_scene* scene, robast_tuning* out);
+/* EINVAL on NULL arguments or a field out of range. */
+int robast_set_tuning(robast_scene* scene, const robast_tuning* tuning);
+
+/* Autotuner: traces photons [0, n) of `rays` (group sums only, into its own
+ * scratch) under a set of candidate tunings, times each with HIP events on
+ * the stream, keeps the fastest in the scene and returns it in *best (may be
+ * NULL).  Synchronous; allocates; EINVAL as robast_trace or n < 1. */
+int robast_autotune(robast_scene* scene, const robast_rays* rays, int64_t n, robast_tuning* best,
+                    void* hip_stream);
 
 /* Replace the differentiable parameters (host vector, n_params) and rebuild
  * the affected device records.  Synchronous. */

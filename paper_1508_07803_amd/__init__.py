@@ -27,7 +27,8 @@ FIGURE_STRIDE = 8
 SYMBOLS = ["robast_build_scene", "robast_trace", "robast_figures", "robast_trace_backward",
            "robast_update_params", "robast_destroy_scene", "robast_status_string",
            "robast_last_error", "robast_abi_version", "robast_build_batch", "robast_trace_batch",
-           "robast_figures_batch", "robast_trace_backward_batch", "robast_batch_sizes", "robast_destroy_batch"]
+           "robast_figures_batch", "robast_trace_backward_batch", "robast_batch_sizes", "robast_destroy_batch",
+           "robast_get_tuning", "robast_set_tuning", "robast_autotune"]
 
 
 class VolumeDesc(ctypes.Structure):
@@ -58,6 +59,14 @@ class Hits(ctypes.Structure):
                 ("opl", ctypes.c_void_p), ("seq_hash", ctypes.c_void_p), ("group_sums", ctypes.c_void_p)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("bin_photons", ctypes.c_uint32), ("bin_target", ctypes.c_uint32),
+                ("wave_chunk", ctypes.c_uint32), ("waves_mult", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 assert ctypes.sizeof(VolumeDesc) == 464
 
 _lib.robast_build_scene.argtypes = [ctypes.POINTER(SceneDesc), ctypes.c_void_p, ctypes.c_int64,
@@ -80,11 +89,16 @@ _lib.robast_figures_batch.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c
 _lib.robast_trace_backward_batch.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
 _lib.robast_batch_sizes.argtypes = [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int64)] * 3
+_lib.robast_get_tuning.argtypes = [ctypes.c_void_p, ctypes.POINTER(Tuning)]
+_lib.robast_set_tuning.argtypes = [ctypes.c_void_p, ctypes.POINTER(Tuning)]
+_lib.robast_autotune.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ctypes.c_int64, ctypes.POINTER(Tuning),
+                                 ctypes.c_void_p]
 _lib.robast_destroy_batch.argtypes = [ctypes.c_void_p]
 _lib.robast_destroy_batch.restype = None
 for _name in ("robast_build_scene", "robast_trace", "robast_figures", "robast_trace_backward",
               "robast_update_params", "robast_abi_version", "robast_build_batch", "robast_trace_batch",
-              "robast_figures_batch", "robast_trace_backward_batch", "robast_batch_sizes"):
+              "robast_figures_batch", "robast_trace_backward_batch", "robast_batch_sizes", "robast_get_tuning",
+              "robast_set_tuning", "robast_autotune"):
     getattr(_lib, _name).restype = ctypes.c_int
 
 
@@ -236,6 +250,32 @@ class Scene:
         _check(_lib.robast_trace_backward(self._h, ctypes.byref(R), n, _ptr(sums), _ptr(cot), _ptr(grad),
                                           _stream(stream)), "robast_trace_backward")
         return grad
+
+    @property
+    def tuning(self):
+        t = Tuning()
+        _check(_lib.robast_get_tuning(self._h, ctypes.byref(t)), "robast_get_tuning")
+        return t.as_dict()
+
+    def set_tuning(self, **fields):
+        """Change launch parameters (bin_photons, bin_target, wave_chunk, waves_mult)."""
+        cur = self.tuning
+        unknown = set(fields) - set(cur)
+        if unknown:
+            raise KeyError(f"unknown tuning fields {sorted(unknown)}")
+        cur.update(fields)
+        t = Tuning(**cur)
+        _check(_lib.robast_set_tuning(self._h, ctypes.byref(t)), "robast_set_tuning")
+        return self.tuning
+
+    def autotune(self, rays, n=None, stream=None):
+        """Time candidate launch parameters on these photons; keeps and returns the fastest."""
+        n = int(rays["ox"].numel()) if n is None else int(n)
+        R = self._rays_struct(rays, 0)
+        t = Tuning()
+        _check(_lib.robast_autotune(self._h, ctypes.byref(R), n, ctypes.byref(t), _stream(stream)),
+               "robast_autotune")
+        return t.as_dict()
 
     def update_params(self, params):
         P = np.ascontiguousarray(params, dtype=np.float64)

@@ -16,6 +16,7 @@
 
 #include "../../include/robast.h"
 #include "batch.hpp"
+#include "binning.hpp"
 #include "kernels.hpp"
 #include "scene_layout.hpp"
 
@@ -166,6 +167,12 @@ struct robast_scene {
   SceneView<float> sf{};
   SceneView<double> sd{};
   LaunchCfg cfg{};
+  robast_tuning tuning{};
+  // photon binning: plane z = bin_z, square of side bin_side from (bin_x0, bin_y0)
+  double bin_z = 0.0, bin_x0 = 0.0, bin_y0 = 0.0, bin_side = 1.0;
+  unsigned long long* d_counter = nullptr;   // photon counter of the running call
+  void* d_work = nullptr;                    // binning workspace
+  size_t work_bytes = 0;
 };
 
 // LDS a workgroup may use for a scene's tables: three workgroups of four
@@ -579,12 +586,36 @@ void build_groups(const robast_scene& s, const std::vector<Box3>& wb, std::vecto
 
 // Build the blob for precision T and fill the view offsets (host addresses
 // are rebased to the device allocation by the caller).
+// Binning frame: the xy extent of the mirrors and lenses (of every volume
+// if there are none) on the plane through their lowest point.
+void set_bin_frame(robast_scene& s, const std::vector<Box3>& wb) {
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int pass = 0; pass < 2 && !(lo[0] <= hi[0]); ++pass)
+    for (int i = 0; i < s.n_vol; ++i) {
+      const int role = s.desc[i].role;
+      if (pass == 0 && role != ROBAST_MIRROR && role != ROBAST_LENS) continue;
+      for (int k = 0; k < 3; ++k) {
+        lo[k] = std::min(lo[k], wb[i].lo[k]);
+        hi[k] = std::max(hi[k], wb[i].hi[k]);
+      }
+    }
+  if (!(lo[0] <= hi[0]) || !std::isfinite(lo[0] + lo[1] + lo[2] + hi[0] + hi[1])) {
+    s.bin_z = 0.0; s.bin_x0 = -1.0; s.bin_y0 = -1.0; s.bin_side = 2.0;
+    return;
+  }
+  s.bin_z = lo[2];
+  s.bin_side = std::max({hi[0] - lo[0], hi[1] - lo[1], 1e-9 * s.l_ref});
+  s.bin_x0 = 0.5 * (lo[0] + hi[0]) - 0.5 * s.bin_side;
+  s.bin_y0 = 0.5 * (lo[1] + hi[1]) - 0.5 * s.bin_side;
+}
+
 template <typename T>
-void compile_blob(const robast_scene& s, std::vector<char>& blob, SceneView<T>& V, std::vector<size_t>& offs) {
+void compile_blob(robast_scene& s, std::vector<char>& blob, SceneView<T>& V, std::vector<size_t>& offs) {
   int nv = s.n_vol;
   std::vector<DVol<T>> recs(nv);
   std::vector<Box3> wb(nv);
   for (int i = 0; i < nv; ++i) fill_record<T>(recs[i], s.desc[i], wb[i], s.l_ref);
+  set_bin_frame(s, wb);
   std::vector<uint16_t> always;
   std::vector<GroupBuild> groups;
   build_groups(s, wb, always, groups);
@@ -742,6 +773,81 @@ template <typename T> std::vector<BatchVariant<T>> variant_table(const robast_ba
   return t;
 }
 
+constexpr int64_t kBinMin = 32768;
+constexpr int64_t kBinsMax = int64_t(1) << 22;
+
+void apply_tuning(robast_scene* s) {
+  s->cfg.wave_chunk = (int)s->tuning.wave_chunk;
+  s->cfg.waves_mult = (int)s->tuning.waves_mult;
+}
+
+int tuning_valid(const robast_tuning& t) {
+  return t.bin_target >= 1 && t.bin_target <= 65536 && t.wave_chunk >= 64 && t.wave_chunk <= 65536 &&
+         t.waves_mult >= 1 && t.waves_mult <= 8;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// The view of the photons a launch reads: the caller's arrays, or their
+// binned copy (with the permutation back to the caller's order).
+template <typename T>
+int binned_view(robast_scene* s, const robast_rays* rays, int64_t n, hipStream_t st, RaysView<T>& out) {
+  const RaysView<T> R = rays_view<T>(rays);
+  out = R;
+  if (!s->tuning.bin_photons || n < kBinMin || n > (int64_t)UINT32_MAX) return ROBAST_OK;
+  const int G = s->n_groups;
+  const double per_cell = (double)n / ((double)G * (double)s->tuning.bin_target);
+  int nc = (int)std::floor(std::sqrt(std::max(1.0, per_cell)));
+  const int nc_max = (int)std::floor(std::sqrt((double)kBinsMax / G));
+  nc = std::max(1, std::min({nc, 1024, nc_max}));
+  const int64_t bins = (int64_t)G * nc * nc, parts = bin_scan_parts(bins);
+  const size_t un = align256((size_t)n * 4), rn = align256((size_t)n * sizeof(BinRecord<T>));
+  const size_t need = 2 * un + rn + align256((size_t)bins * 4) + align256((size_t)parts * 4);
+  if (need > s->work_bytes) {
+    if (s->d_work) (void)hipFree(s->d_work);
+    s->d_work = nullptr;
+    s->work_bytes = 0;
+    hipError_t e = hipMalloc(&s->d_work, need);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(ROBAST_ENOMEM, "hipMalloc binning workspace")
+                                                         : hip_fail(e, "hipMalloc binning workspace");
+    s->work_bytes = need;
+  }
+  char* p = (char*)s->d_work;
+  BinWork<T> W{};
+  W.out = (BinRecord<T>*)p; p += rn;
+  W.key = (uint32_t*)p; p += un;
+  W.rank = (uint32_t*)p; p += un;
+  W.hist = (uint32_t*)p; p += align256((size_t)bins * 4);
+  W.part = (uint32_t*)p;
+  const BinGeom geo{s->bin_z, s->bin_x0, s->bin_y0, (double)nc / s->bin_side, nc, G};
+  hipError_t e = launch_binning<T>(R, n, geo, W, st);
+  if (e != hipSuccess) return hip_fail(e, "binning launch");
+  out = binned_rays<T>(W.out, rays->group != nullptr, rays->id_base);
+  return ROBAST_OK;
+}
+
+template <typename T>
+int trace_t(robast_scene* s, const SceneView<T>& V, const robast_rays* rays, int64_t n, const robast_hits* hits,
+            hipStream_t st) {
+  RaysView<T> R;
+  int rc = binned_view<T>(s, rays, n, st, R);
+  if (rc) return rc;
+  hipError_t e = launch_trace<T>(V, R, n, hits_view<T>(hits), s->cfg, s->d_counter, st);
+  if (e != hipSuccess) return hip_fail(e, "trace launch");
+  return ROBAST_OK;
+}
+
+template <typename T>
+int backward_t(robast_scene* s, const SceneView<T>& V, const robast_rays* rays, int64_t n, const AdjView& A,
+               hipStream_t st) {
+  RaysView<T> R;
+  int rc = binned_view<T>(s, rays, n, st, R);
+  if (rc) return rc;
+  hipError_t e = launch_backward<T>(V, R, n, A, s->cfg, st);
+  if (e != hipSuccess) return hip_fail(e, "backward launch");
+  return ROBAST_OK;
+}
+
 void free_batch(robast_batch* b) {
   if (b->d_vars) (void)hipFree(b->d_vars);
   if (b->d_items) (void)hipFree(b->d_items);
@@ -786,9 +892,14 @@ int robast_build_scene(const robast_scene_desc* desc, const double* params, int6
   s->desc.assign(desc->volumes, desc->volumes + desc->n_volumes);
   s->params.assign(params, params + n_params);
   s->cfg.lds_cap = kLdsCap;
-  s->cfg.waves_mult = 1;
   s->cfg.max_blocks = 0;
+  s->tuning = robast_tuning{1u, 128u, 256u, 1u};
+  apply_tuning(s);
   rc = upload(s);
+  if (!rc) {
+    hipError_t e = hipMalloc(&s->d_counter, sizeof(unsigned long long));
+    if (e != hipSuccess) rc = hip_fail(e, "hipMalloc counter");
+  }
   if (rc) {
     robast_destroy_scene(s);
     return rc;
@@ -812,6 +923,8 @@ void robast_destroy_scene(robast_scene* s) {
   if (s->d_tilt) (void)hipFree(s->d_tilt);
   if (s->d_coef) (void)hipFree(s->d_coef);
   if (s->d_view) (void)hipFree(s->d_view);
+  if (s->d_counter) (void)hipFree(s->d_counter);
+  if (s->d_work) (void)hipFree(s->d_work);
   delete s;
 }
 
@@ -825,11 +938,8 @@ int robast_trace(robast_scene* s, const robast_rays* rays, int64_t n, const roba
   if (!rc) rc = check_hits(hits);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e;
-  if (s->precision == 32) e = launch_trace<float>(s->sf, rays_view<float>(rays), n, hits_view<float>(hits), s->cfg, st);
-  else e = launch_trace<double>(s->sd, rays_view<double>(rays), n, hits_view<double>(hits), s->cfg, st);
-  if (e != hipSuccess) return hip_fail(e, "trace launch");
-  return ROBAST_OK;
+  if (s->precision == 32) return trace_t<float>(s, s->sf, rays, n, hits, st);
+  return trace_t<double>(s, s->sd, rays, n, hits, st);
 }
 
 int robast_figures(robast_scene* s, const double* sums, double* fig, void* stream) {
@@ -851,9 +961,68 @@ int robast_trace_backward(robast_scene* s, const robast_rays* rays, int64_t n, c
   hipError_t e = launch_adj_coef(sums, cot, s->d_coef, s->n_groups, st);
   if (e != hipSuccess) return hip_fail(e, "coefficient launch");
   AdjView A{s->d_coef, grad, s->d_tilt, (int)s->params.size()};
-  if (s->precision == 32) e = launch_backward<float>(s->sf, rays_view<float>(rays), n, A, s->cfg, st);
-  else e = launch_backward<double>(s->sd, rays_view<double>(rays), n, A, s->cfg, st);
-  if (e != hipSuccess) return hip_fail(e, "backward launch");
+  if (s->precision == 32) return backward_t<float>(s, s->sf, rays, n, A, st);
+  return backward_t<double>(s, s->sd, rays, n, A, st);
+}
+
+int robast_get_tuning(const robast_scene* s, robast_tuning* out) {
+  if (!s || !out) return fail(ROBAST_EINVAL, "NULL scene or tuning");
+  *out = s->tuning;
+  return ROBAST_OK;
+}
+
+int robast_set_tuning(robast_scene* s, const robast_tuning* t) {
+  if (!s || !t) return fail(ROBAST_EINVAL, "NULL scene or tuning");
+  if (!tuning_valid(*t)) return fail(ROBAST_EINVAL, "tuning field out of range");
+  s->tuning = *t;
+  apply_tuning(s);
+  return ROBAST_OK;
+}
+
+int robast_autotune(robast_scene* s, const robast_rays* rays, int64_t n, robast_tuning* best, void* stream) {
+  if (!s || !rays) return fail(ROBAST_EINVAL, "NULL scene or rays");
+  if (n < 1) return fail(ROBAST_EINVAL, "n < 1");
+  int rc = check_rays(rays);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  double* sums = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc(&sums, sizeof(double) * 8 * s->n_groups);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  const robast_tuning saved = s->tuning;
+  robast_tuning win = saved;
+  float win_ms = INFINITY;
+  robast_hits hits{};
+  hits.group_sums = sums;
+  for (uint32_t bin = 0; bin < 2 && e == hipSuccess && !rc; ++bin)
+    for (uint32_t chunk : {128u, 256u, 1024u})
+      for (uint32_t mult : {1u, 2u}) {
+        if (e != hipSuccess || rc) break;
+        s->tuning = robast_tuning{bin, saved.bin_target, chunk, mult};
+        apply_tuning(s);
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2 && e == hipSuccess && !rc; ++rep) {   // first run warms up
+          e = hipMemsetAsync(sums, 0, sizeof(double) * 8 * s->n_groups, st);
+          if (e == hipSuccess) e = hipEventRecord(e0, st);
+          if (e == hipSuccess) rc = robast_trace(s, rays, n, &hits, 0, stream);
+          if (e == hipSuccess && !rc) e = hipEventRecord(e1, st);
+          if (e == hipSuccess && !rc) e = hipEventSynchronize(e1);
+          if (e == hipSuccess && !rc) e = hipEventElapsedTime(&ms, e0, e1);
+        }
+        if (e == hipSuccess && !rc && ms < win_ms) {
+          win_ms = ms;
+          win = s->tuning;
+        }
+      }
+  s->tuning = (e == hipSuccess && !rc) ? win : saved;
+  apply_tuning(s);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (sums) (void)hipFree(sums);
+  if (rc) return rc;
+  if (e != hipSuccess) return hip_fail(e, "autotune");
+  if (best) *best = win;
   return ROBAST_OK;
 }
 

@@ -263,14 +263,16 @@ template <typename T, int MAXE>
 __device__ __forceinline__ void adjoint_photon(const SceneView<T>& L, const RaysView<T>& R, int64_t i,
                                                const AdjView& A, GradSink& gs) {
   do {
-      int g = R.group ? (int)R.group[i] : 0;
+      int g = R.grp(i);
       if ((unsigned)g >= (unsigned)L.n_groups) return;
       const double* cf = A.coef + 4 * g;
       T ca = (T)cf[0], cb = (T)cf[3];
       if (ca == T(0) && cb == T(0)) return;
-      V3<T> o0 = {R.ox[i], R.oy[i], R.oz[i]};
-      V3<T> d0 = {R.dx[i], R.dy[i], R.dz[i]};
-      uint64_t id = R.id_base + (uint64_t)i;
+      T oa[3], da[3];
+      R.load(i, oa, da);
+      V3<T> o0 = {oa[0], oa[1], oa[2]};
+      V3<T> d0 = {da[0], da[1], da[2]};
+      uint64_t id = R.id_base + (uint64_t)R.src(i);
       uint32_t codes[MAXE];
       PhotonOut<T> r = trace_photon<T, MAXE>(L, o0, d0, id, codes);
       if (r.fate != FOCUSED || r.nev > MAXE) return;

@@ -67,9 +67,11 @@ __device__ __forceinline__ void trace_item(const SceneView<float>& L, int64_t st
     if (cur < 0 && next < end) {
       cur = next;
       next += blockDim.x;
-      V3<float> o = {R.ox[cur], R.oy[cur], R.oz[cur]};
-      V3<float> d = {R.dx[cur], R.dy[cur], R.dz[cur]};
-      g = R.group ? (int)R.group[cur] : 0;
+      float oa[3], da[3];
+      R.load(cur, oa, da);
+      V3<float> o = {oa[0], oa[1], oa[2]};
+      V3<float> d = {da[0], da[1], da[2]};
+      g = R.grp(cur);
       if ((unsigned)g >= (unsigned)L.n_groups) g = -1;
       photon_init(ps, o, d, R.id_base + (uint64_t)(cur - off));
       started = true;

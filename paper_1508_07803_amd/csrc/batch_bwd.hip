@@ -61,9 +61,10 @@ k_backward_batch(const BatchVariant<float>* vars, const BatchItem* items, int n_
       // the variant's photons, indexed and numbered from its first photon
       off = bv.off;
       Rv = R;
-      Rv.ox = R.ox + off; Rv.oy = R.oy + off; Rv.oz = R.oz + off;
-      Rv.dx = R.dx + off; Rv.dy = R.dy + off; Rv.dz = R.dz + off;
-      Rv.group = R.group ? R.group + off : nullptr;
+      const int64_t k = off * R.stride, u = off * R.ustride;
+      Rv.ox = R.ox + k; Rv.oy = R.oy + k; Rv.oz = R.oz + k;
+      Rv.dx = R.dx + k; Rv.dy = R.dy + k; Rv.dz = R.dz + k;
+      Rv.group = R.group ? R.group + u : nullptr;
       cur_v = it.v;
       __syncthreads();
     }

@@ -1,0 +1,49 @@
+// Spatial binning of photon bundles (ordering for wave coherence).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace robast {
+
+// Bin geometry: an nc x nc grid of cells of size 1 / inv_cell from (x0, y0)
+// on the plane z = z_ref, per photon group.
+struct BinGeom {
+  double z_ref, x0, y0, inv_cell;
+  int nc, n_groups;
+};
+
+// Binned photons, one record per photon: 6 coordinates (ox, oy, oz, dx, dy,
+// dz), then the group and the photon's index in the caller's bundle (uint32),
+// padded to 32 bytes (FP32) or 64 bytes (FP64) so that a photon is written
+// with whole 16-byte stores.
+template <typename T> struct BinRecord;
+template <> struct alignas(16) BinRecord<float> { float c[6]; uint32_t group, src; };
+template <> struct alignas(16) BinRecord<double> { double c[6]; uint32_t group, src, pad[2]; };
+
+template <typename T> struct BinWork {
+  uint32_t* key;         // n
+  uint32_t* rank;        // n
+  uint32_t* hist;        // bins: counts, then offsets
+  uint32_t* part;        // bin_scan_parts(bins)
+  BinRecord<T>* out;     // n
+};
+
+// The view of binned records as photon arrays.
+template <typename T> RaysView<T> binned_rays(const BinRecord<T>* rec, bool has_group, uint64_t id_base) {
+  const T* c = rec->c;
+  const uint32_t* u = &rec->group;
+  RaysView<T> R{c, c + 1, c + 2, c + 3, c + 4, c + 5, has_group ? u : nullptr, id_base, u + 1};
+  R.stride = (int64_t)(sizeof(BinRecord<T>) / sizeof(T));
+  R.ustride = (int64_t)(sizeof(BinRecord<T>) / sizeof(uint32_t));
+  return R;
+}
+
+int64_t bin_scan_parts(int64_t bins);
+
+template <typename T>
+hipError_t launch_binning(const RaysView<T>& R, int64_t n, const BinGeom& geo, const BinWork<T>& W,
+                          hipStream_t st);
+
+}  // namespace robast

@@ -11,6 +11,22 @@ template <typename T> struct RaysView {
   const T *ox, *oy, *oz, *dx, *dy, *dz;
   const uint32_t* group;
   uint64_t id_base;
+  // When set, photon i of these arrays is photon perm[i] of the caller's
+  // bundle: it is numbered id_base + perm[i] and its results go to perm[i].
+  const uint32_t* perm = nullptr;
+  // Elements between consecutive photons: 1 for the caller's separate
+  // arrays; binned copies interleave each photon into one record.
+  int64_t stride = 1;    // in T
+  int64_t ustride = 1;   // in uint32_t (group, perm)
+
+  __device__ __forceinline__ void load(int64_t i, T o[3], T d[3]) const {
+    const int64_t k = i * stride;
+    o[0] = ox[k]; o[1] = oy[k]; o[2] = oz[k];
+    d[0] = dx[k]; d[1] = dy[k]; d[2] = dz[k];
+  }
+  __device__ __forceinline__ int grp(int64_t i) const { return group ? (int)group[i * ustride] : 0; }
+  // index of photon i in the caller's bundle
+  __device__ __forceinline__ int64_t src(int64_t i) const { return perm ? (int64_t)perm[i * ustride] : i; }
 };
 
 template <typename T> struct HitsView {
@@ -26,6 +42,7 @@ struct LaunchCfg {
   int lds_cap;      // stage the scene blob in LDS when it is at most this many bytes
   int waves_mult;   // persistent grid = CUs x resident blocks per CU x waves_mult
   int max_blocks;   // 0 = no cap
+  int wave_chunk;   // photons a wave takes from the launch's photon counter at a time
 };
 
 // Backward-pass inputs: per-group cotangent coefficients of the objective
@@ -37,9 +54,10 @@ struct AdjView {
   int n_params;
 };
 
+// counter: device int64, the launch's photon counter (reset by the launch)
 template <typename T>
 hipError_t launch_trace(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const HitsView<T>& H,
-                        const LaunchCfg& cfg, hipStream_t st);
+                        const LaunchCfg& cfg, unsigned long long* counter, hipStream_t st);
 hipError_t launch_figures(const double* sums, double* fig, int n_groups, hipStream_t st);
 hipError_t launch_adj_coef(const double* sums, const double* cot, double* coef, int n_groups,
                            hipStream_t st);

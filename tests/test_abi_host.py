@@ -101,3 +101,12 @@ def test_batch_arguments_rejected(rb):
     assert lib.robast_trace_backward_batch(None, None, None, None, None, None) == rb.EINVAL
     assert lib.robast_batch_sizes(None, None, None, None) == rb.EINVAL
     lib.robast_destroy_batch(None)
+
+
+def test_tuning_arguments_rejected(rb):
+    import ctypes
+    lib = rb.lib()
+    t = rb.Tuning(1, 128, 256, 1)
+    assert lib.robast_get_tuning(None, ctypes.byref(t)) == rb.EINVAL
+    assert lib.robast_set_tuning(None, ctypes.byref(t)) == rb.EINVAL
+    assert lib.robast_autotune(None, None, 10, None, None) == rb.EINVAL

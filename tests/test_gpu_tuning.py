@@ -1,0 +1,100 @@
+"""Launch tuning never changes a photon's result.
+
+Photon binning (counting sort by entrance cell), the per-wave chunk size and
+the grid size only change which lane traces which photon and in which
+order: every per-photon record must be bit-identical across tunings, group
+sums and gradients equal up to FP64 summation order (1e-12 / 1e-9
+relative).  The binned path is also what the parity tests against the
+oracle exercise (their bundles exceed the binning threshold).
+"""
+import numpy as np
+import pytest
+
+import scenes
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TUNINGS = [dict(bin_photons=0, wave_chunk=256, waves_mult=1),
+           dict(bin_photons=1, wave_chunk=256, waves_mult=1),
+           dict(bin_photons=1, wave_chunk=64, waves_mult=2),
+           dict(bin_photons=1, wave_chunk=4096, waves_mult=1, bin_target=16)]
+
+
+@pytest.fixture(scope="module")
+def rb():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1508_07803_amd as rb
+    return rb
+
+
+@pytest.mark.parametrize("name,n_per", [("schwarzschild_couder", 2500), ("davies_cotton", 8000),
+                                        ("hex_concentrator", 400)])
+def test_tunings_give_identical_photons(rb, name, n_per):
+    sc = getattr(scenes, name)()
+    r = sc.rays(n_per)
+    dev = rb.Scene(sc)
+    rays = dev.upload_rays(r)
+    n = int(rays["ox"].numel())
+    assert n >= 32768   # above the binning threshold
+    runs = []
+    for t in TUNINGS:
+        dev.set_tuning(**t)
+        hits = dev.alloc_hits(n)
+        sums = dev.new_sums()
+        dev.trace(rays, hits=hits, sums=sums, id_base=5)
+        torch.cuda.synchronize()
+        runs.append((hits, sums))
+    h0, s0 = runs[0]
+    for t, (h, s) in zip(TUNINGS[1:], runs[1:]):
+        for k in h0:
+            assert torch.equal(h0[k], h[k]), f"{t}: {k} differs"
+        assert torch.allclose(s0, s, rtol=1e-12, atol=1e-12 * float(s0.abs().max())), t
+
+
+def test_tunings_give_identical_gradients(rb):
+    sc = scenes.schwarzschild_couder()
+    r = sc.rays(2500)
+    dev = rb.Scene(sc)
+    rays = dev.upload_rays(r)
+    cot = torch.zeros(sc.n_groups, 2, dtype=torch.float64, device="cuda")
+    cot[:, 0] = 1.0 / sc.n_groups
+    grads = []
+    for t in TUNINGS[:3]:
+        dev.set_tuning(**t)
+        sums = dev.new_sums()
+        dev.trace(rays, sums=sums)
+        g = torch.zeros(len(sc.params), dtype=torch.float64, device="cuda")
+        dev.backward(rays, sums, cot, g)
+        torch.cuda.synchronize()
+        grads.append(g)
+    for g in grads[1:]:
+        assert torch.allclose(grads[0], g, rtol=1e-9, atol=1e-12 * float(grads[0].abs().max()))
+
+
+def test_autotune_keeps_results(rb):
+    sc = scenes.davies_cotton()
+    r = sc.rays(10000)
+    dev = rb.Scene(sc)
+    rays = dev.upload_rays(r)
+    n = int(rays["ox"].numel())
+    ref = dev.alloc_hits(n)
+    dev.trace(rays, hits=ref)
+    best = dev.autotune(rays)
+    assert best == dev.tuning
+    assert best["wave_chunk"] >= 64 and best["waves_mult"] >= 1
+    hits = dev.alloc_hits(n)
+    dev.trace(rays, hits=hits)
+    torch.cuda.synchronize()
+    for k in ref:
+        assert torch.equal(ref[k], hits[k]), k
+
+
+def test_tuning_rejects_out_of_range(rb):
+    dev = rb.Scene(scenes.single_mirror())
+    for bad in (dict(wave_chunk=32), dict(wave_chunk=1 << 20), dict(waves_mult=0), dict(waves_mult=9),
+                dict(bin_target=0)):
+        with pytest.raises(rb.RobastError):
+            dev.set_tuning(**bad)
+    assert dev.tuning == dict(bin_photons=1, bin_target=128, wave_chunk=256, waves_mult=1)
