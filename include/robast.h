@@ -151,9 +151,18 @@ typedef struct robast_scene robast_scene;
 int robast_build_scene(const robast_scene_desc* desc, const double* params, int64_t n_params,
                        robast_scene** out);
 
+/* robast_trace flag: keep the binned photon order this call used (see
+ * robast_tuning) for the next calls on the scene.  A kept order is used,
+ * instead of binning again, by a trace or backward call given the same ray
+ * pointers, id_base and n; the caller guarantees that the photon arrays were
+ * not written in between.  It stays kept after a trace call with this flag
+ * and is dropped by any other call that bins, by a backward call that used
+ * it, by a parameter update and by the autotuner. */
+#define ROBAST_TRACE_KEEP_ORDER 1u
+
 /* Trace photons [0, n).  rays/hits as above; n == 0 is a no-op.  EINVAL on
- * NULL scene/rays/hits, n < 0, a NULL ray coordinate array.  `flags` is
- * reserved (pass 0).
+ * NULL scene/rays/hits, n < 0, a NULL ray coordinate array, an unknown flag
+ * (flags: 0 or ROBAST_TRACE_KEEP_ORDER).
  * Calls on one scene (trace, backward, update) must not overlap in time:
  * they share the scene's photon counter and binning workspace, so issue them
  * on one stream or order them.  With binning on (robast_tuning), a call with
@@ -177,6 +186,12 @@ int robast_figures(robast_scene* scene, const double* d_group_sums, double* d_fi
 int robast_trace_backward(robast_scene* scene, const robast_rays* rays, int64_t n,
                           const double* d_group_sums, const double* d_cot, double* d_grad,
                           void* hip_stream);
+
+/* Bin photons [0, n) now and keep the order, as a trace call with
+ * ROBAST_TRACE_KEEP_ORDER would (a no-op when binning is off or n is outside
+ * the binning range).  Lets a caller time the binning apart from the trace,
+ * or bin once for a forward and a backward call.  EINVAL as robast_trace. */
+int robast_bin_photons(robast_scene* scene, const robast_rays* rays, int64_t n, void* hip_stream);
 
 /* ---- launch tuning ------------------------------------------------------
  * Per-scene launch parameters.  They change the order in which photons are
@@ -245,8 +260,14 @@ int robast_build_batch(robast_scene* const* scenes, int32_t n_scenes, const int6
                        robast_batch** out);
 
 /* Forward trace of the whole bundle: hits as for robast_trace, indexed by the
- * global photon index; hits->group_sums is the concatenated sums (+=). */
-int robast_trace_batch(robast_batch* batch, const robast_rays* rays, const robast_hits* hits, void* hip_stream);
+ * global photon index; hits->group_sums is the concatenated sums (+=).
+ * Photon binning (per variant, within its range) follows the tuning of the
+ * first scene at build time; its workspace (40 bytes per photon) is
+ * allocated by robast_build_batch, so calls allocate nothing.  flags: 0 or
+ * ROBAST_TRACE_KEEP_ORDER, with the meaning it has for robast_trace (the kept
+ * order belongs to the batch). */
+int robast_trace_batch(robast_batch* batch, const robast_rays* rays, const robast_hits* hits, uint32_t flags,
+                       void* hip_stream);
 
 /* Figures of every variant's groups from concatenated sums (as robast_figures). */
 int robast_figures_batch(robast_batch* batch, const double* d_group_sums, double* d_figures, void* hip_stream);

@@ -23,12 +23,13 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, EMISMATCH = 0, -1, -2, -3, -4, -5
 GROUP_STRIDE = 8
 FIGURE_STRIDE = 8
+TRACE_KEEP_ORDER = 1
 
 SYMBOLS = ["robast_build_scene", "robast_trace", "robast_figures", "robast_trace_backward",
            "robast_update_params", "robast_destroy_scene", "robast_status_string",
            "robast_last_error", "robast_abi_version", "robast_build_batch", "robast_trace_batch",
            "robast_figures_batch", "robast_trace_backward_batch", "robast_batch_sizes", "robast_destroy_batch",
-           "robast_get_tuning", "robast_set_tuning", "robast_autotune"]
+           "robast_get_tuning", "robast_set_tuning", "robast_autotune", "robast_bin_photons"]
 
 
 class VolumeDesc(ctypes.Structure):
@@ -84,7 +85,8 @@ _lib.robast_status_string.restype = ctypes.c_char_p
 _lib.robast_last_error.restype = ctypes.c_char_p
 _lib.robast_build_batch.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_uint32,
                                     ctypes.POINTER(ctypes.c_void_p)]
-_lib.robast_trace_batch.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ctypes.POINTER(Hits), ctypes.c_void_p]
+_lib.robast_trace_batch.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ctypes.POINTER(Hits), ctypes.c_uint32,
+                                    ctypes.c_void_p]
 _lib.robast_figures_batch.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
 _lib.robast_trace_backward_batch.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
@@ -93,12 +95,13 @@ _lib.robast_get_tuning.argtypes = [ctypes.c_void_p, ctypes.POINTER(Tuning)]
 _lib.robast_set_tuning.argtypes = [ctypes.c_void_p, ctypes.POINTER(Tuning)]
 _lib.robast_autotune.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ctypes.c_int64, ctypes.POINTER(Tuning),
                                  ctypes.c_void_p]
+_lib.robast_bin_photons.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ctypes.c_int64, ctypes.c_void_p]
 _lib.robast_destroy_batch.argtypes = [ctypes.c_void_p]
 _lib.robast_destroy_batch.restype = None
 for _name in ("robast_build_scene", "robast_trace", "robast_figures", "robast_trace_backward",
               "robast_update_params", "robast_abi_version", "robast_build_batch", "robast_trace_batch",
               "robast_figures_batch", "robast_trace_backward_batch", "robast_batch_sizes", "robast_get_tuning",
-              "robast_set_tuning", "robast_autotune"):
+              "robast_set_tuning", "robast_autotune", "robast_bin_photons"):
     getattr(_lib, _name).restype = ctypes.c_int
 
 
@@ -227,15 +230,26 @@ class Scene:
         return _rays_struct(rays, id_base, offset)
 
     # -------------------------------------------------------------- calls
-    def trace(self, rays, n=None, hits=None, sums=None, id_base=0, stream=None):
-        """Trace n photons; writes the given hit tensors and/or accumulates sums."""
+    def trace(self, rays, n=None, hits=None, sums=None, id_base=0, stream=None, keep_order=False):
+        """Trace n photons; writes the given hit tensors and/or accumulates sums.
+
+        keep_order: keep the binned photon order for the next backward call
+        on the same photon tensors (which must not be modified in between).
+        """
         n = int(rays["ox"].numel()) if n is None else int(n)
         hits = hits or {}
         H = _hits_struct(hits, sums)
         R = self._rays_struct(rays, id_base)
-        _check(_lib.robast_trace(self._h, ctypes.byref(R), n, ctypes.byref(H), 0, _stream(stream)),
+        flags = TRACE_KEEP_ORDER if keep_order else 0
+        _check(_lib.robast_trace(self._h, ctypes.byref(R), n, ctypes.byref(H), flags, _stream(stream)),
                "robast_trace")
         return hits
+
+    def bin_photons(self, rays, n=None, id_base=0, stream=None):
+        """Bin the photons now and keep the order for the next trace / backward calls."""
+        n = int(rays["ox"].numel()) if n is None else int(n)
+        R = self._rays_struct(rays, id_base)
+        _check(_lib.robast_bin_photons(self._h, ctypes.byref(R), n, _stream(stream)), "robast_bin_photons")
 
     def figures(self, sums, stream=None):
         import torch
@@ -345,11 +359,12 @@ class Batch:
             if t is not None and t.numel() < need:
                 raise ValueError(f"{name} holds {t.numel()} < {need} values")
 
-    def trace(self, rays, hits=None, sums=None, id_base=0, stream=None):
+    def trace(self, rays, hits=None, sums=None, id_base=0, stream=None, keep_order=False):
         self._check_sizes(rays, hits, sums)
         H = _hits_struct(hits, sums)
         R = _rays_struct(rays, id_base)
-        _check(_lib.robast_trace_batch(self._h, ctypes.byref(R), ctypes.byref(H), _stream(stream)),
+        flags = TRACE_KEEP_ORDER if keep_order else 0
+        _check(_lib.robast_trace_batch(self._h, ctypes.byref(R), ctypes.byref(H), flags, _stream(stream)),
                "robast_trace_batch")
         return hits
 
@@ -385,7 +400,7 @@ def _autograd():
             if not np.array_equal(p, scene.params):
                 scene.update_params(p)
             sums = scene.new_sums(rays["ox"].device)
-            scene.trace(rays, sums=sums)
+            scene.trace(rays, sums=sums, keep_order=True)
             fig = scene.figures(sums)
             ctx.scene, ctx.rays = scene, rays
             ctx.save_for_backward(sums)

@@ -173,6 +173,11 @@ struct robast_scene {
   unsigned long long* d_counter = nullptr;   // photon counter of the running call
   void* d_work = nullptr;                    // binning workspace
   size_t work_bytes = 0;
+  // the binned order kept by a trace call for the next backward call
+  bool kept = false;
+  robast_rays kept_rays{};
+  int64_t kept_n = 0;
+  void* kept_records = nullptr;
 };
 
 // LDS a workgroup may use for a scene's tables: three workgroups of four
@@ -187,8 +192,16 @@ struct robast_batch {
   uint32_t blob_cap = 0;
   void* d_vars = nullptr;          // BatchVariant<T>[n_scenes]
   BatchItem* d_items = nullptr;    // n_items
-  uint32_t* d_queue = nullptr;     // 2 counters
+  uint32_t* d_queue = nullptr;     // kQueueCounters counters
   double* d_coef = nullptr;        // n_groups * 4
+  // photon binning per variant (fixed at build: geometry, bins, workspace)
+  bool bin = false;
+  int64_t bins = 0;
+  int64_t* d_offsets = nullptr;    // n_scenes + 1
+  BinGeom* d_geo = nullptr;        // n_scenes
+  void* d_work = nullptr;
+  bool kept = false;
+  robast_rays kept_rays{};
 };
 
 namespace {
@@ -790,11 +803,25 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // The view of the photons a launch reads: the caller's arrays, or their
 // binned copy (with the permutation back to the caller's order).
+bool same_rays(const robast_rays& a, const robast_rays& b) {
+  return a.ox == b.ox && a.oy == b.oy && a.oz == b.oz && a.dx == b.dx && a.dy == b.dy && a.dz == b.dz &&
+         a.group == b.group && a.id_base == b.id_base;
+}
+
+// The kept binned order is used by any call given the same arrays and n;
+// afterwards it stays kept only if `keep` (a backward call passes false).
 template <typename T>
-int binned_view(robast_scene* s, const robast_rays* rays, int64_t n, hipStream_t st, RaysView<T>& out) {
+int binned_view(robast_scene* s, const robast_rays* rays, int64_t n, hipStream_t st, RaysView<T>& out,
+                bool keep) {
   const RaysView<T> R = rays_view<T>(rays);
   out = R;
   if (!s->tuning.bin_photons || n < kBinMin || n > (int64_t)UINT32_MAX) return ROBAST_OK;
+  if (s->kept && s->kept_n == n && same_rays(s->kept_rays, *rays)) {
+    s->kept = keep;
+    out = binned_rays<T>((const BinRecord<T>*)s->kept_records, rays->group != nullptr, rays->id_base);
+    return ROBAST_OK;
+  }
+  s->kept = false;   // the workspace is about to be overwritten
   const int G = s->n_groups;
   const double per_cell = (double)n / ((double)G * (double)s->tuning.bin_target);
   int nc = (int)std::floor(std::sqrt(std::max(1.0, per_cell)));
@@ -819,18 +846,24 @@ int binned_view(robast_scene* s, const robast_rays* rays, int64_t n, hipStream_t
   W.rank = (uint32_t*)p; p += un;
   W.hist = (uint32_t*)p; p += align256((size_t)bins * 4);
   W.part = (uint32_t*)p;
-  const BinGeom geo{s->bin_z, s->bin_x0, s->bin_y0, (double)nc / s->bin_side, nc, G};
-  hipError_t e = launch_binning<T>(R, n, geo, W, st);
+  const BinGeom geo{s->bin_z, s->bin_x0, s->bin_y0, (double)nc / s->bin_side, nc, G, 0u, 0u};
+  hipError_t e = launch_binning<T>(R, n, geo, BinMulti{nullptr, nullptr, 0}, bins, W, st);
   if (e != hipSuccess) return hip_fail(e, "binning launch");
   out = binned_rays<T>(W.out, rays->group != nullptr, rays->id_base);
+  if (keep) {
+    s->kept = true;
+    s->kept_rays = *rays;
+    s->kept_n = n;
+    s->kept_records = W.out;
+  }
   return ROBAST_OK;
 }
 
 template <typename T>
 int trace_t(robast_scene* s, const SceneView<T>& V, const robast_rays* rays, int64_t n, const robast_hits* hits,
-            hipStream_t st) {
+            bool keep, hipStream_t st) {
   RaysView<T> R;
-  int rc = binned_view<T>(s, rays, n, st, R);
+  int rc = binned_view<T>(s, rays, n, st, R, keep);
   if (rc) return rc;
   hipError_t e = launch_trace<T>(V, R, n, hits_view<T>(hits), s->cfg, s->d_counter, st);
   if (e != hipSuccess) return hip_fail(e, "trace launch");
@@ -841,10 +874,50 @@ template <typename T>
 int backward_t(robast_scene* s, const SceneView<T>& V, const robast_rays* rays, int64_t n, const AdjView& A,
                hipStream_t st) {
   RaysView<T> R;
-  int rc = binned_view<T>(s, rays, n, st, R);
+  int rc = binned_view<T>(s, rays, n, st, R, false);
   if (rc) return rc;
   hipError_t e = launch_backward<T>(V, R, n, A, s->cfg, st);
   if (e != hipSuccess) return hip_fail(e, "backward launch");
+  return ROBAST_OK;
+}
+
+struct BatchBinLayout {
+  size_t un, rn, hist, parts_bytes, total;
+  int64_t parts;
+};
+
+BatchBinLayout batch_bin_layout(int64_t n, int64_t bins) {
+  BatchBinLayout L{};
+  L.un = align256((size_t)n * 4);
+  L.rn = align256((size_t)n * sizeof(BinRecord<float>));
+  L.hist = align256((size_t)bins * 4);
+  L.parts = bin_scan_parts(bins);
+  L.parts_bytes = align256((size_t)L.parts * 4);
+  L.total = L.rn + 2 * L.un + L.hist + L.parts_bytes;
+  return L;
+}
+
+// The photons a batched launch reads: the caller's arrays or their binned
+// copy (kept order reused when given the same arrays).
+int batch_binned_view(robast_batch* b, const robast_rays* rays, hipStream_t st, bool keep, RaysView<float>& out) {
+  out = rays_view<float>(rays);
+  if (!b->bin) return ROBAST_OK;
+  const BatchBinLayout L = batch_bin_layout(b->n_photons, b->bins);
+  char* p = (char*)b->d_work;
+  BinWork<float> W{};
+  W.out = (BinRecord<float>*)p; p += L.rn;
+  W.key = (uint32_t*)p; p += L.un;
+  W.rank = (uint32_t*)p; p += L.un;
+  W.hist = (uint32_t*)p; p += L.hist;
+  W.part = (uint32_t*)p;
+  if (!(b->kept && same_rays(b->kept_rays, *rays))) {
+    const BinMulti multi{b->d_offsets, b->d_geo, (int)b->scenes.size()};
+    hipError_t e = launch_binning<float>(out, b->n_photons, BinGeom{}, multi, b->bins, W, st);
+    if (e != hipSuccess) return hip_fail(e, "batched binning launch");
+  }
+  b->kept = keep;
+  b->kept_rays = *rays;
+  out = binned_rays<float>(W.out, rays->group != nullptr, rays->id_base);
   return ROBAST_OK;
 }
 
@@ -853,6 +926,9 @@ void free_batch(robast_batch* b) {
   if (b->d_items) (void)hipFree(b->d_items);
   if (b->d_queue) (void)hipFree(b->d_queue);
   if (b->d_coef) (void)hipFree(b->d_coef);
+  if (b->d_offsets) (void)hipFree(b->d_offsets);
+  if (b->d_geo) (void)hipFree(b->d_geo);
+  if (b->d_work) (void)hipFree(b->d_work);
   delete b;
 }
 
@@ -914,6 +990,7 @@ int robast_update_params(robast_scene* s, const double* params, int64_t n_params
   if (!finite_all(params, (int)n_params)) return fail(ROBAST_EINVAL, "non-finite parameter");
   s->params.assign(params, params + n_params);
   for (auto& v : s->desc) apply_params(v, s->params);
+  s->kept = false;
   return upload(s);
 }
 
@@ -930,16 +1007,17 @@ void robast_destroy_scene(robast_scene* s) {
 
 int robast_trace(robast_scene* s, const robast_rays* rays, int64_t n, const robast_hits* hits, uint32_t flags,
                  void* stream) {
-  (void)flags;
   if (!s || !rays || !hits) return fail(ROBAST_EINVAL, "NULL scene, rays or hits");
+  if (flags & ~(uint32_t)ROBAST_TRACE_KEEP_ORDER) return fail(ROBAST_EINVAL, "unknown trace flag");
   if (n < 0) return fail(ROBAST_EINVAL, "n < 0");
   if (n == 0) return ROBAST_OK;
   int rc = check_rays(rays);
   if (!rc) rc = check_hits(hits);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
-  if (s->precision == 32) return trace_t<float>(s, s->sf, rays, n, hits, st);
-  return trace_t<double>(s, s->sd, rays, n, hits, st);
+  const bool keep = (flags & ROBAST_TRACE_KEEP_ORDER) != 0;
+  if (s->precision == 32) return trace_t<float>(s, s->sf, rays, n, hits, keep, st);
+  return trace_t<double>(s, s->sd, rays, n, hits, keep, st);
 }
 
 int robast_figures(robast_scene* s, const double* sums, double* fig, void* stream) {
@@ -965,6 +1043,22 @@ int robast_trace_backward(robast_scene* s, const robast_rays* rays, int64_t n, c
   return backward_t<double>(s, s->sd, rays, n, A, st);
 }
 
+int robast_bin_photons(robast_scene* s, const robast_rays* rays, int64_t n, void* stream) {
+  if (!s || !rays) return fail(ROBAST_EINVAL, "NULL scene or rays");
+  if (n < 0) return fail(ROBAST_EINVAL, "n < 0");
+  if (n == 0) return ROBAST_OK;
+  int rc = check_rays(rays);
+  if (rc) return rc;
+  s->kept = false;
+  hipStream_t st = (hipStream_t)stream;
+  if (s->precision == 32) {
+    RaysView<float> R;
+    return binned_view<float>(s, rays, n, st, R, true);
+  }
+  RaysView<double> R;
+  return binned_view<double>(s, rays, n, st, R, true);
+}
+
 int robast_get_tuning(const robast_scene* s, robast_tuning* out) {
   if (!s || !out) return fail(ROBAST_EINVAL, "NULL scene or tuning");
   *out = s->tuning;
@@ -985,6 +1079,7 @@ int robast_autotune(robast_scene* s, const robast_rays* rays, int64_t n, robast_
   int rc = check_rays(rays);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
+  s->kept = false;
   double* sums = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipMalloc(&sums, sizeof(double) * 8 * s->n_groups);
@@ -1088,18 +1183,53 @@ int robast_build_batch(robast_scene* const* scenes, int32_t n_scenes, const int6
     free_batch(b);
     return hip_fail(e, "hipMemcpy batch tables");
   }
+  // per-variant photon binning, sized from the variant photon counts
+  if (scenes[0]->tuning.bin_photons && b->n_photons >= kBinMin && b->n_photons <= (int64_t)UINT32_MAX) {
+    std::vector<BinGeom> geo(n_scenes);
+    int64_t base = 0;
+    for (int v = 0; v < n_scenes; ++v) {
+      const robast_scene* sv = scenes[v];
+      const int64_t cnt = offsets[v + 1] - offsets[v];
+      const int G = sv->n_groups;
+      const double per_cell = (double)std::max<int64_t>(cnt, 1) / ((double)G * (double)sv->tuning.bin_target);
+      int nc = (int)std::floor(std::sqrt(std::max(1.0, per_cell)));
+      nc = std::max(1, std::min(nc, 1024));
+      geo[v] = BinGeom{sv->bin_z, sv->bin_x0, sv->bin_y0, (double)nc / sv->bin_side, nc, G, (uint32_t)base, 0u};
+      base += (int64_t)G * nc * nc;
+    }
+    if (base <= (int64_t)1 << 28) {
+      b->bins = base;
+      const BatchBinLayout L = batch_bin_layout(b->n_photons, b->bins);
+      e = hipMalloc(&b->d_offsets, sizeof(int64_t) * (n_scenes + 1));
+      if (e == hipSuccess) e = hipMalloc(&b->d_geo, sizeof(BinGeom) * n_scenes);
+      if (e == hipSuccess) e = hipMalloc(&b->d_work, L.total);
+      if (e == hipSuccess)
+        e = hipMemcpy(b->d_offsets, offsets, sizeof(int64_t) * (n_scenes + 1), hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(b->d_geo, geo.data(), sizeof(BinGeom) * n_scenes, hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        free_batch(b);
+        return e == hipErrorOutOfMemory ? fail(ROBAST_ENOMEM, "hipMalloc batch binning workspace")
+                                        : hip_fail(e, "batch binning tables");
+      }
+      b->bin = true;
+    }
+  }
   *out = b;
   return ROBAST_OK;
 }
 
-int robast_trace_batch(robast_batch* b, const robast_rays* rays, const robast_hits* hits, void* stream) {
+int robast_trace_batch(robast_batch* b, const robast_rays* rays, const robast_hits* hits, uint32_t flags,
+                       void* stream) {
   if (!b || !rays || !hits) return fail(ROBAST_EINVAL, "NULL batch, rays or hits");
+  if (flags & ~(uint32_t)ROBAST_TRACE_KEEP_ORDER) return fail(ROBAST_EINVAL, "unknown trace flag");
   if (b->n_photons == 0) return ROBAST_OK;
   int rc = check_rays(rays);
   if (!rc) rc = check_hits(hits);
   if (rc) return rc;
-  hipError_t e = launch_trace_batch(batch_view<float>(b), rays_view<float>(rays), hits_view<float>(hits),
-                                    (hipStream_t)stream);
+  RaysView<float> R;
+  rc = batch_binned_view(b, rays, (hipStream_t)stream, (flags & ROBAST_TRACE_KEEP_ORDER) != 0, R);
+  if (rc) return rc;
+  hipError_t e = launch_trace_batch(batch_view<float>(b), R, hits_view<float>(hits), (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "batched trace launch");
   return ROBAST_OK;
 }
@@ -1121,7 +1251,10 @@ int robast_trace_backward_batch(robast_batch* b, const robast_rays* rays, const 
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = launch_adj_coef(sums, cot, b->d_coef, (int)b->n_groups, st);
   if (e != hipSuccess) return hip_fail(e, "coefficient launch");
-  e = launch_backward_batch(batch_view<float>(b), rays_view<float>(rays), b->d_coef, grad, st);
+  RaysView<float> R;
+  rc = batch_binned_view(b, rays, st, false, R);
+  if (rc) return rc;
+  e = launch_backward_batch(batch_view<float>(b), R, b->d_coef, grad, st);
   if (e != hipSuccess) return hip_fail(e, "batched backward launch");
   return ROBAST_OK;
 }

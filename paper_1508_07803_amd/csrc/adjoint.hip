@@ -38,8 +38,11 @@ __global__ void k_adj_coef(const double* sums, const double* cot, double* coef, 
   coef[4 * g + 0] = a; coef[4 * g + 1] = cx; coef[4 * g + 2] = cy; coef[4 * g + 3] = b;
 }
 
+// FP32 kernels with up to 16 events are held to 3 waves per SIMD (<= 168
+// VGPRs, no spills; the unconstrained allocation gives 2).
 template <typename T, int MAXE, bool USE_LDS>
-__global__ void __launch_bounds__(kBlockAdj) k_backward(SceneView<T> S, RaysView<T> R, int64_t n, AdjView A,
+__global__ void __launch_bounds__(kBlockAdj)
+__attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && MAXE <= 16) ? 3 : 1, 8))) k_backward(SceneView<T> S, RaysView<T> R, int64_t n, AdjView A,
                                                          int grad_in_lds) {
   extern __shared__ __align__(16) char lds[];
   SceneView<T> L;

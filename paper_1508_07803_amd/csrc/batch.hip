@@ -73,7 +73,7 @@ __device__ __forceinline__ void trace_item(const SceneView<float>& L, int64_t st
       V3<float> d = {da[0], da[1], da[2]};
       g = R.grp(cur);
       if ((unsigned)g >= (unsigned)L.n_groups) g = -1;
-      photon_init(ps, o, d, R.id_base + (uint64_t)(cur - off));
+      photon_init(ps, o, d, R.id_base + (uint64_t)(R.src(cur) - off));
       started = true;
     }
     if (!__any(cur >= 0)) break;
@@ -83,13 +83,14 @@ __device__ __forceinline__ void trace_item(const SceneView<float>& L, int64_t st
       if (ps.fate) {
         PhotonOut<float> r = photon_out<float>(ps);
         if (RECORD) {
-          if (H.fate) H.fate[cur] = (uint8_t)r.fate;
-          if (H.nev) H.nev[cur] = (uint8_t)r.nev;
-          if (H.last_vol) H.last_vol[cur] = r.last_vol;
-          if (H.x) { H.x[cur] = r.pos.x; H.y[cur] = r.pos.y; H.z[cur] = r.pos.z; }
-          if (H.ux) { H.ux[cur] = r.dir.x; H.uy[cur] = r.dir.y; H.uz[cur] = r.dir.z; }
-          if (H.opl) H.opl[cur] = r.opl;
-          if (H.hash) H.hash[cur] = r.hash;
+          const int64_t q = R.src(cur);
+          if (H.fate) H.fate[q] = (uint8_t)r.fate;
+          if (H.nev) H.nev[q] = (uint8_t)r.nev;
+          if (H.last_vol) H.last_vol[q] = r.last_vol;
+          if (H.x) { H.x[q] = r.pos.x; H.y[q] = r.pos.y; H.z[q] = r.pos.z; }
+          if (H.ux) { H.ux[q] = r.dir.x; H.uy[q] = r.dir.y; H.uz[q] = r.dir.z; }
+          if (H.opl) H.opl[q] = r.opl;
+          if (H.hash) H.hash[q] = r.hash;
         }
         if (target && g >= 0) {
           ag = g;

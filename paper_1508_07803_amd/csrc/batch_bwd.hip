@@ -21,7 +21,7 @@ namespace robast {
 constexpr uint32_t kGradLdsMax = 16384;
 
 template <bool USE_LDS, int MAXE>
-__global__ void __launch_bounds__(kBlockB)
+__global__ void __launch_bounds__(kBlockB) __attribute__((amdgpu_waves_per_eu(MAXE <= 16 ? 3 : 1, 8)))
 k_backward_batch(const BatchVariant<float>* vars, const BatchItem* items, int n_items, uint32_t* queue,
                  uint32_t blob_cap, int grad_in_lds, RaysView<float> R, const double* coef, double* grad) {
   extern __shared__ __align__(16) char lds[];
@@ -65,6 +65,12 @@ k_backward_batch(const BatchVariant<float>* vars, const BatchItem* items, int n_
       Rv.ox = R.ox + k; Rv.oy = R.oy + k; Rv.oz = R.oz + k;
       Rv.dx = R.dx + k; Rv.dy = R.dy + k; Rv.dz = R.dz + k;
       Rv.group = R.group ? R.group + u : nullptr;
+      // binned photons carry their index in the whole bundle: number them
+      // from the variant's first photon
+      if (R.perm) {
+        Rv.perm = R.perm + u;
+        Rv.id_base = R.id_base - (uint64_t)off;
+      }
       cur_v = it.v;
       __syncthreads();
     }

@@ -27,10 +27,21 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
     p[i] = v;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kBinBlock) k_bin_count(RaysView<T> R, int64_t n, BinGeom geo, uint32_t* key,
-                                                         uint32_t* rank, uint32_t* hist) {
+// bundle of photon i: the last v with offsets[v] <= i (offsets ascending)
+__device__ __forceinline__ int bundle_of(const int64_t* offsets, int n_var, int64_t i) {
+  int lo = 0, hi = n_var - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (offsets[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T, bool MULTI>
+__global__ void __launch_bounds__(kBinBlock) k_bin_count(RaysView<T> R, int64_t n, BinGeom geo1, BinMulti multi,
+                                                         uint32_t* key, uint32_t* rank, uint32_t* hist) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const BinGeom geo = MULTI ? multi.geo[bundle_of(multi.offsets, multi.n_var, i)] : geo1;
     T o[3], d[3];
     R.load(i, o, d);
     double ox = (double)o[0], oy = (double)o[1];
@@ -47,7 +58,7 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_count(RaysView<T> R, int64_t 
     const double fx = (ox - geo.x0) * geo.inv_cell, fy = (oy - geo.y0) * geo.inv_cell;
     const int ix = (int)fmin(fmax(fx, 0.0), (double)(geo.nc - 1));
     const int iy = (int)fmin(fmax(fy, 0.0), (double)(geo.nc - 1));
-    const uint32_t k = (g * (uint32_t)geo.nc + (uint32_t)iy) * (uint32_t)geo.nc + (uint32_t)ix;
+    const uint32_t k = geo.base + (g * (uint32_t)geo.nc + (uint32_t)iy) * (uint32_t)geo.nc + (uint32_t)ix;
     key[i] = k;
     rank[i] = atomicAdd(hist + k, 1u);
   }
@@ -138,12 +149,16 @@ static int grid_for(int64_t n) {
 int64_t bin_scan_parts(int64_t bins) { return (bins + kScanTile - 1) / kScanTile; }
 
 template <typename T>
-hipError_t launch_binning(const RaysView<T>& R, int64_t n, const BinGeom& geo, const BinWork<T>& W,
-                          hipStream_t st) {
-  const int64_t bins = (int64_t)geo.n_groups * geo.nc * geo.nc;
+hipError_t launch_binning(const RaysView<T>& R, int64_t n, const BinGeom& geo, const BinMulti& multi,
+                          int64_t bins, const BinWork<T>& W, hipStream_t st) {
   const int64_t parts = bin_scan_parts(bins);
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(bins)), dim3(kBinBlock), 0, st, W.hist, bins, 0u);
-  hipLaunchKernelGGL(k_bin_count<T>, dim3(grid_for(n)), dim3(kBinBlock), 0, st, R, n, geo, W.key, W.rank, W.hist);
+  if (multi.n_var > 0)
+    hipLaunchKernelGGL((k_bin_count<T, true>), dim3(grid_for(n)), dim3(kBinBlock), 0, st, R, n, geo, multi, W.key,
+                       W.rank, W.hist);
+  else
+    hipLaunchKernelGGL((k_bin_count<T, false>), dim3(grid_for(n)), dim3(kBinBlock), 0, st, R, n, geo, multi, W.key,
+                       W.rank, W.hist);
   hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)parts), dim3(kBinBlock), 0, st, W.hist, bins, W.part);
   hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kBinBlock), 0, st, W.part, (int)parts);
   hipLaunchKernelGGL(k_scan_add, dim3((unsigned)parts), dim3(kBinBlock), 0, st, W.hist, bins, W.part);
@@ -152,9 +167,9 @@ hipError_t launch_binning(const RaysView<T>& R, int64_t n, const BinGeom& geo, c
   return hipGetLastError();
 }
 
-template hipError_t launch_binning<float>(const RaysView<float>&, int64_t, const BinGeom&, const BinWork<float>&,
-                                          hipStream_t);
-template hipError_t launch_binning<double>(const RaysView<double>&, int64_t, const BinGeom&,
-                                           const BinWork<double>&, hipStream_t);
+template hipError_t launch_binning<float>(const RaysView<float>&, int64_t, const BinGeom&, const BinMulti&, int64_t,
+                                          const BinWork<float>&, hipStream_t);
+template hipError_t launch_binning<double>(const RaysView<double>&, int64_t, const BinGeom&, const BinMulti&,
+                                           int64_t, const BinWork<double>&, hipStream_t);
 
 }  // namespace robast

@@ -8,10 +8,21 @@
 namespace robast {
 
 // Bin geometry: an nc x nc grid of cells of size 1 / inv_cell from (x0, y0)
-// on the plane z = z_ref, per photon group.
+// on the plane z = z_ref, per photon group; the bins are numbered from base.
 struct BinGeom {
   double z_ref, x0, y0, inv_cell;
   int nc, n_groups;
+  uint32_t base, pad;
+};
+
+// Photons of several bundles binned together (a batch of scene variants):
+// bundle v holds photons [offsets[v], offsets[v+1]) and is binned with
+// geo[v], whose bins follow those of bundle v - 1, so every photon stays in
+// its bundle's range.
+struct BinMulti {
+  const int64_t* offsets;   // device, n_var + 1
+  const BinGeom* geo;       // device, n_var
+  int n_var;
 };
 
 // Binned photons, one record per photon: 6 coordinates (ox, oy, oz, dx, dy,
@@ -42,8 +53,9 @@ template <typename T> RaysView<T> binned_rays(const BinRecord<T>* rec, bool has_
 
 int64_t bin_scan_parts(int64_t bins);
 
+// One bundle (geo) or several (multi.n_var > 0); bins = total bin count.
 template <typename T>
-hipError_t launch_binning(const RaysView<T>& R, int64_t n, const BinGeom& geo, const BinWork<T>& W,
-                          hipStream_t st);
+hipError_t launch_binning(const RaysView<T>& R, int64_t n, const BinGeom& geo, const BinMulti& multi,
+                          int64_t bins, const BinWork<T>& W, hipStream_t st);
 
 }  // namespace robast

@@ -48,8 +48,11 @@ __global__ void k_reset_counter(unsigned long long* c) {
   if (threadIdx.x == 0) *c = 0ull;
 }
 
+// FP32 kernels are held to 4 waves per SIMD (<= 128 VGPRs, a few spills):
+// measured faster than the 3 waves the unconstrained allocation gives, as
+// the extra wave hides LDS and memory latency of the search.
 template <typename T, bool RECORD, bool SUMS, bool USE_LDS>
-__global__ void __launch_bounds__(kBlock) k_trace(SceneView<T> S, RaysView<T> R, int64_t n, HitsView<T> H,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1, 8))) k_trace(SceneView<T> S, RaysView<T> R, int64_t n, HitsView<T> H,
                                                   int sums_in_lds, unsigned long long* counter, int chunk) {
   extern __shared__ __align__(16) char lds[];
   SceneView<T> L;

@@ -96,7 +96,7 @@ def test_batch_arguments_rejected(rb):
     assert lib.robast_build_batch(scenes_null, 2, offs, 0, ctypes.byref(h)) == rb.EINVAL
     assert lib.robast_build_batch(scenes_null, 2, offs, 64, ctypes.byref(h)) == rb.EINVAL
     assert h.value is None
-    assert lib.robast_trace_batch(None, None, None, None) == rb.EINVAL
+    assert lib.robast_trace_batch(None, None, None, 0, None) == rb.EINVAL
     assert lib.robast_figures_batch(None, None, None, None) == rb.EINVAL
     assert lib.robast_trace_backward_batch(None, None, None, None, None, None) == rb.EINVAL
     assert lib.robast_batch_sizes(None, None, None, None) == rb.EINVAL

@@ -55,12 +55,17 @@ def as_numpy(hits, sl):
     return out
 
 
-def test_batch_equals_per_variant_bitwise(rb):
+# small bundles run unbinned; above 32768 photons the batch bins per variant
+COUNTS = {"unbinned": [3001, 0, 1, 2048, 4097], "binned": [40000, 0, 1, 30000, 50001]}
+
+
+@pytest.mark.parametrize("kind", sorted(COUNTS))
+def test_batch_equals_per_variant_bitwise(rb, kind):
     """Ragged counts (0, 1, chunk multiples and tails), chunk smaller than a
     variant, mixed DC / SC variants: every photon identical to the plain call."""
     variants = small_sweep()
     devs = [rb.Scene(v) for v in variants]
-    counts = [3001, 0, 1, 2048, 4097]
+    counts = COUNTS[kind]
     chunk = 1024
     rays, parts = concat_rays(rb, devs, counts)
     batch = rb.Batch(devs, counts, chunk=chunk)
@@ -90,14 +95,17 @@ def test_batch_equals_per_variant_bitwise(rb):
     assert torch.count_nonzero(sums[g * 8:(g + 1) * 8]) == 0
 
 
-def test_batch_backward_equals_per_variant(rb):
+@pytest.mark.parametrize("counts,keep", [([5000, 2500, 1, 0, 7000], False), ([40000, 2500, 1, 0, 35000], False),
+                                         ([40000, 2500, 1, 0, 35000], True)])
+def test_batch_backward_equals_per_variant(rb, counts, keep):
+    """Adjoint of the batch against per-variant adjoint calls; also with the
+    binned order kept from the forward call."""
     variants = small_sweep(seed=scenes.SEED_BASE + 56)
     devs = [rb.Scene(v) for v in variants]
-    counts = [5000, 2500, 1, 0, 7000]
     rays, parts = concat_rays(rb, devs, counts, seed0=21)
     batch = rb.Batch(devs, counts, chunk=2048)
     sums = batch.new_sums()
-    batch.trace(rays, sums=sums)
+    batch.trace(rays, sums=sums, keep_order=keep)
     cot = torch.zeros(batch.n_groups, 2, dtype=torch.float64, device="cuda")
     cot[:, 0] = 1.0
     cot[:, 1] = 0.25
@@ -141,12 +149,13 @@ def test_batch_photons_match_oracle(rb):
         off += c
 
 
-def test_batch_graph_capture_replays(rb):
+@pytest.mark.parametrize("counts", [[4000, 3000, 5000], [40000, 3000, 50000]])
+def test_batch_graph_capture_replays(rb, counts):
     """Captured step (zero sums, trace, figures, adjoint) replayed 3 times with
-    eager work and a parameter update in between; each replay equals eager."""
+    eager work and a parameter update in between; each replay equals eager.
+    The second case bins (the binning kernels are part of the graph)."""
     variants = small_sweep(n_dc=1, n_sc=2, seed=scenes.SEED_BASE + 58)
     devs = [rb.Scene(v) for v in variants]
-    counts = [4000, 3000, 5000]
     rays, _ = concat_rays(rb, devs, counts, seed0=41)
     batch = rb.Batch(devs, counts, chunk=1024)
     sums = batch.new_sums()
@@ -158,7 +167,7 @@ def test_batch_graph_capture_replays(rb):
     def step(stream=None):
         sums.zero_()
         grad.zero_()
-        batch.trace(rays, sums=sums, stream=stream)
+        batch.trace(rays, sums=sums, stream=stream, keep_order=True)
         batch.figures(sums, fig=fig, stream=stream)
         batch.backward(rays, sums, cot, grad, stream=stream)
 

@@ -98,3 +98,49 @@ def test_tuning_rejects_out_of_range(rb):
         with pytest.raises(rb.RobastError):
             dev.set_tuning(**bad)
     assert dev.tuning == dict(bin_photons=1, bin_target=128, wave_chunk=256, waves_mult=1)
+
+
+def test_kept_order_reused_by_backward(rb):
+    """trace(keep_order) + backward, and bin_photons + trace + backward, give
+    the photons and gradients of independent calls."""
+    sc = scenes.schwarzschild_couder()
+    r = sc.rays(2500)
+    dev = rb.Scene(sc)
+    rays = dev.upload_rays(r)
+    n = int(rays["ox"].numel())
+    cot = torch.zeros(sc.n_groups, 2, dtype=torch.float64, device="cuda")
+    cot[:, 0] = 1.0 / sc.n_groups
+
+    def run(mode):
+        hits = dev.alloc_hits(n)
+        sums = dev.new_sums()
+        if mode == "bin_first":
+            dev.bin_photons(rays)
+        dev.trace(rays, hits=hits, sums=sums, keep_order=(mode != "plain"))
+        g = torch.zeros(len(sc.params), dtype=torch.float64, device="cuda")
+        dev.backward(rays, sums, cot, g)
+        torch.cuda.synchronize()
+        return hits, sums, g
+
+    ref = run("plain")
+    for mode in ("keep", "bin_first"):
+        hits, sums, g = run(mode)
+        for k in ref[0]:
+            assert torch.equal(ref[0][k], hits[k]), (mode, k)
+        assert torch.allclose(ref[1], sums, rtol=1e-12, atol=1e-12 * float(ref[1].abs().max()))
+        assert torch.allclose(ref[2], g, rtol=1e-9, atol=1e-12 * float(ref[2].abs().max())), mode
+    # a kept order is not used for other photon arrays
+    dev.trace(rays, sums=dev.new_sums(), keep_order=True)
+    other = {k: v.clone() for k, v in rays.items()}
+    other["ox"] += 0.01
+    g1 = torch.zeros(len(sc.params), dtype=torch.float64, device="cuda")
+    s1 = dev.new_sums()
+    dev.trace(other, sums=s1)
+    dev.backward(other, s1, cot, g1)
+    dev.set_tuning(bin_photons=0)
+    g2 = torch.zeros(len(sc.params), dtype=torch.float64, device="cuda")
+    s2 = dev.new_sums()
+    dev.trace(other, sums=s2)
+    dev.backward(other, s2, cot, g2)
+    torch.cuda.synchronize()
+    assert torch.allclose(g1, g2, rtol=1e-9, atol=1e-12 * float(g2.abs().max()))
