@@ -1,21 +1,30 @@
-"""Benchmark: traced photons/s on the two-mirror Schwarzschild-Couder telescope.
+"""Benchmark: traced photons/s on the two-mirror Schwarzschild-Couder telescope,
+and the batched forward + adjoint design sweep against plain per-variant calls.
 
-Workload: 16 field angles (0..4 deg) x 1e7 photons = 1.6e8 photons per step,
-FP32, synthetic scene and photon bundles (seeded), inputs resident in HBM
-before timing starts.  One step is the whole hot path: forward trace with
-per-field figure sums, the figures (centroid, RMS spot radius, efficiency),
-and the reverse-mode gradient of the mean RMS with respect to the 160 scene
-parameters (16 aspheric coefficients, 144 panel tilts).
+Workload (one step): 16 field angles (0..4 deg) x 1e7 photons = 1.6e8 photons,
+FP32, synthetic seeded scene and photon bundles generated on the device before
+timing starts.  A step is the whole hot path: photon binning, forward trace
+with per-field figure sums, the figures (centroid, RMS spot radius,
+efficiency), and the reverse-mode gradient of the mean RMS with respect to the
+160 scene parameters (16 aspheric coefficients, 144 panel tilts).
 
-Prints one JSON line (rank 0).  Also reported:
-  roofline      the trace kernel's algorithmic VALU operations per second
-                against the MI355X VALU issue rate (256 CU x 64 lanes x 2.4 GHz);
+Prints one JSON line.  Besides the contract fields:
+  kernels       per-launch durations (HIP events on the launch stream) of
+                the binning, trace and adjoint phases of the step;
+  roofline      the dominant kernel's algorithmic VALU operations per second
+                against the MI355X VALU issue rate (256 CU x 64 lanes x
+                2.4 GHz); roofline_kernels gives it for both kernels;
+  sweep         256 Davies-Cotton / Schwarzschild-Couder variants with
+                log-uniform photon counts: one batched forward + adjoint step
+                (captured in a HIP graph) against 256 plain per-variant calls,
+                over a few gradient-descent steps;
   cpu_baseline  the FP64 reference tracer on a bounded sample on the host.
 """
 import argparse
+import hashlib
 import json
-import math
 import os
+import re
 import sys
 import time
 
@@ -27,7 +36,8 @@ sys.path.insert(0, ROOT)
 VALU_PEAK_OPS = 256 * 64 * 2.4e9        # lane-operations per second (non-packed)
 
 # Algorithmic VALU cost per interaction, in lane-op slots (quarter-rate ops --
-# sqrt, reciprocal, 32-bit integer multiply -- count 4): the exact
+# sqrt, reciprocal, 32-bit integer multiply -- count 4; FP64 ops count 1, the
+# MI355X FP64 vector rate equals its non-packed FP32 rate): the exact
 # intersection of the surface that is hit, its normal and the interaction.
 # Acceleration-structure overhead (box tests of other candidates, grid walk)
 # is not counted, so the figure is a lower bound of the work done.
@@ -45,33 +55,202 @@ COST = {
     "draw": 90,           # Philox4x32-10: 20 32-bit multiplies (x4) + xors/adds
     "hash": 20,
 }
+# Reverse sweep, per event of a FOCUSED photon (FP64): pull-back through the
+# interaction, the normal (with the surface Hessian), the hit point and the
+# implicit root to the shape and tilt parameters.
+PULLBACK = {"plane": 150, "sphere": 300, "asphere": 420, "cylinder": 250, "box": 200, "hexcone": 600}
 SHAPE_NAME = {1: "plane", 2: "sphere", 3: "asphere", 4: "cylinder", 5: "box", 6: "hexcone"}
+
+TRACE_SOURCES = ["device_trace.hpp", "kernels.hip", "kernels.hpp", "scene_layout.hpp"]
+
+
+def event_cost(scene, v, a):
+    """Forward cost of events at volumes v with actions a (arrays)."""
+    shapes = scene.volumes["shape"][v]
+    roles = scene.volumes["role"][v]
+    refl = scene.volumes["reflectivity"][v]
+    c = np.zeros(len(v))
+    for sh, name in SHAPE_NAME.items():
+        c += (shapes == sh) * (COST["frame"] + COST[name] + COST["normal"] + COST["hash"])
+    c += COST["reflect"] * (a == 0) + COST["refract"] * (a == 1)
+    c += COST["draw"] * (((roles == 1) & (refl < 1.0)) | (roles == 2))
+    return c
 
 
 def ops_per_photon(scene, rec):
-    """Algorithmic VALU ops per photon from the reference tracer's event log."""
+    """Algorithmic VALU ops per photon of the forward trace and of the adjoint,
+    from the reference tracer's event log."""
     lg = rec["log"]
     vol, act = lg["vol"], lg["act"]
     n = len(rec["fate"])
-    total = 0.0
-    shapes = scene.volumes["shape"]
-    roles = scene.volumes["role"]
-    refl = scene.volumes["reflectivity"]
+    fwd = np.zeros(n)
+    per_event = np.zeros(vol.shape)
     for k in range(vol.shape[1]):
         m = vol[:, k] >= 0
+        if m.any():
+            per_event[m, k] = event_cost(scene, vol[m, k], act[m, k])
+    fwd = per_event.sum(axis=1) + COST["frame"] * (rec["fate"] == 3)
+    # adjoint: the forward search again, then for event e of a FOCUSED photon
+    # the replay of events 0..e (exact intersections, no search) and the
+    # pull-back of event e
+    adj = fwd.copy()
+    foc = rec["fate"] == 1
+    shapes = scene.volumes["shape"]
+    for e in range(vol.shape[1]):
+        m = foc & (vol[:, e] >= 0)
         if not m.any():
             continue
-        v = vol[m, k]
-        a = act[m, k]
-        for sh in np.unique(shapes[v]):
-            total += (COST["frame"] + COST[SHAPE_NAME[int(sh)]] + COST["normal"] + COST["hash"]) * \
-                np.count_nonzero(shapes[v] == sh)
-        total += COST["reflect"] * np.count_nonzero(a == 0) + COST["refract"] * np.count_nonzero(a == 1)
-        lens = roles[v] == 2
-        total += COST["draw"] * np.count_nonzero(((roles[v] == 1) & (refl[v] < 1.0)) | lens)
-    # the final search that finds nothing (EXITED) still costs one frame test
-    total += COST["frame"] * np.count_nonzero(rec["fate"] == 3)
-    return total / n
+        adj[m] += per_event[m, :e + 1].sum(axis=1)
+        for sh, name in SHAPE_NAME.items():
+            adj[m] += PULLBACK[name] * (shapes[vol[m, e]] == sh)
+    return float(fwd.mean()), float(adj.mean())
+
+
+def sources_digest(names):
+    h = hashlib.sha256()
+    for nm in names:
+        with open(os.path.join(ROOT, "paper_1508_07803_amd", "csrc", nm), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per trace launch from the committed counter summary, if the
+    trace sources are the ones the counters were taken on."""
+    path = os.path.join(ROOT, "profiles", "k_trace_sc_16x1e7_traffic.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"sources_sha256_16:\s*([0-9a-f]{16})", text)
+    b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not b or m.group(1) != sources_digest(TRACE_SOURCES):
+        return None
+    return float(b.group(1))
+
+
+def ev(torch):
+    return torch.cuda.Event(enable_timing=True)
+
+
+def host_cores():
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return min(cores, 16)
+
+
+def c3_bundle(scenes, torch, sc, npf):
+    """16 fields x npf photons, generated on the device, field-major."""
+    parts = [scenes.device_rays(sc, npf, seed=sc.seed + 1000 * g, group=g) for g in range(sc.n_groups)]
+    rays = {k: torch.cat([p[k] for p in parts]) for k in parts[0]}
+    return rays
+
+
+def run_sweep(args, torch, rb, scenes):
+    """Batched (one persistent forward + adjoint launch, HIP graph) against
+    plain per-variant calls on 256 variants, over a few GD steps."""
+    t0 = time.time()
+    variants, counts = scenes.sweep()
+    devs = [rb.Scene(v) for v in variants]
+    parts = [scenes.device_rays(v, int(c), seed=v.seed + 17, group=0) for v, c in zip(variants, counts)]
+    rays = {k: torch.cat([p[k] for p in parts]) for k in parts[0]}
+    del parts
+    n = int(counts.sum())
+    offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    batch = rb.Batch(devs, counts, chunk=args.sweep_chunk)
+    sums = batch.new_sums()
+    fig = torch.zeros(batch.n_groups * rb.FIGURE_STRIDE, dtype=torch.float64, device="cuda")
+    cot = torch.zeros(batch.n_groups, 2, dtype=torch.float64, device="cuda")
+    cot[:, 0] = 1.0                                    # each variant: its own RMS at 1 deg
+    grad = torch.zeros(batch.n_params, dtype=torch.float64, device="cuda")
+    go, po = batch.goff, batch.poff
+    sub = [{k: t[offs[v]:offs[v + 1]] for k, t in rays.items()} for v in range(len(devs))]
+    print(f"[bench] sweep: {len(devs)} variants, {n:.3e} photons, ready in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+
+    def batched_step():
+        sums.zero_()
+        grad.zero_()
+        batch.trace(rays, sums=sums, keep_order=True)
+        batch.figures(sums, fig=fig)
+        batch.backward(rays, sums, cot, grad)
+
+    def plain_step():
+        sums.zero_()
+        grad.zero_()
+        for v, d in enumerate(devs):
+            s_v = sums[go[v] * 8:go[v + 1] * 8]
+            d.trace(sub[v], sums=s_v, keep_order=True)
+            d.figures(s_v, fig=fig[go[v] * 8:go[v + 1] * 8])
+            d.backward(sub[v], s_v, cot[go[v]:go[v + 1]], grad[po[v]:po[v + 1]])
+
+    # warm both paths, then capture the batched step
+    batched_step()
+    plain_step()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        batched_step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batched_step()
+    torch.cuda.synchronize()
+
+    # fixed GD step per family and parameter class, set from the first gradient
+    lr = None
+    t_b, t_p, losses, diffs = [], [], [], []
+    for step in range(args.sweep_steps):
+        a, b = ev(torch), ev(torch)
+        a.record()
+        graph.replay()
+        b.record()
+        torch.cuda.synchronize()
+        t_b.append(a.elapsed_time(b))
+        sums_b, grad_b = sums.clone(), grad.clone()
+        rms = fig.view(-1, rb.FIGURE_STRIDE)[:, 4].cpu().numpy()
+        losses.append(float(rms.mean()))
+        a, b = ev(torch), ev(torch)
+        a.record()
+        plain_step()
+        b.record()
+        torch.cuda.synchronize()
+        t_p.append(a.elapsed_time(b))
+        # same photons, same results: sums and gradients equal up to FP64 order
+        rel_s = float(((sums - sums_b).abs() / sums_b.abs().clamp_min(1e-300)).max())
+        rel_g = float((grad - grad_b).abs().max() / grad_b.abs().max().clamp_min(1e-300))
+        diffs.append(max(rel_s, rel_g))
+        g = grad_b.cpu().numpy()
+        if lr is None:
+            lr = []
+            for v, d in enumerate(devs):
+                gv = g[po[v]:po[v + 1]]
+                names = d.src.param_names
+                tilt = np.array(["tilt" in nm for nm in names])
+                sig = 1e-4 if d.src.name == "davies_cotton" else 5e-5
+                lt = 0.2 * sig / max(np.abs(gv[tilt]).max(), 1e-300)
+                ls = 2e-4 * np.abs(d.params[~tilt]).max() / max(np.abs(gv[~tilt]).max(), 1e-300)
+                lr.append(np.where(tilt, lt, ls))
+        for v, d in enumerate(devs):
+            d.update_params(d.params - lr[v] * g[po[v]:po[v + 1]])
+        print(f"[bench] sweep step {step}: batched {t_b[-1]:.1f} ms, plain {t_p[-1]:.1f} ms, "
+              f"mean RMS {losses[-1] * 1e3:.4f} mm", file=sys.stderr, flush=True)
+    tb, tp = float(np.mean(t_b)), float(np.mean(t_p))
+    return {
+        "workload": "256 variants (128 Davies-Cotton, 128 Schwarzschild-Couder) at 1 deg, perturbed radii / "
+                    "coefficients / tilts, photons per variant round(10^U(5,7)); one step = forward trace + "
+                    "figures + adjoint of each variant's RMS, then a gradient-descent update",
+        "photons_per_step": n, "variants": len(devs), "steps": args.sweep_steps, "chunk": args.sweep_chunk,
+        "batched_ms_per_step": tb, "plain_ms_per_step": tp, "speedup": tp / tb,
+        "batched_photons_per_s": n / (tb / 1e3), "plain_photons_per_s": n / (tp / 1e3),
+        "batched": "one binning + forward launch and one adjoint launch, replayed from a HIP graph",
+        "plain": f"{len(devs)} x (binning + trace + figures + coefficients + adjoint) launches",
+        "max_rel_diff_batched_vs_plain": float(max(diffs)),
+        "mean_rms_m_per_step": losses,
+    }
 
 
 def main():
@@ -80,12 +259,17 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--photons-per-field", type=int, default=10_000_000)
-    ap.add_argument("--cpu-sample-per-field", type=int, default=20_000)
+    ap.add_argument("--cpu-sample-per-field", type=int, default=60_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--sweep-steps", type=int, default=4)
+    ap.add_argument("--sweep-chunk", type=int, default=8192)
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
+                    help="copy this many GiB device to device first (a known-size kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
     import torch
@@ -93,96 +277,98 @@ def main():
     import scenes
 
     assert torch.cuda.is_available(), "needs a HIP device"
+    if args.calibrate_copy_gib > 0:
+        nel = int(args.calibrate_copy_gib * (1 << 30)) // 4
+        src = torch.ones(nel, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {nel * 4} bytes done", file=sys.stderr, flush=True)
+        del src, dst
     sc = scenes.schwarzschild_couder()
     dev = rb.Scene(sc)
     npf = args.photons_per_field
     n = npf * sc.n_groups
-    # photon bundle, generated per field on the host and uploaded (untimed)
-    rays = {k: torch.empty(n, dtype=torch.float32, device="cuda") for k in ("ox", "oy", "oz", "dx", "dy", "dz")}
-    rays["group"] = torch.empty(n, dtype=torch.int32, device="cuda")
     t0 = time.time()
-    for g in range(sc.n_groups):
-        r = sc.rays(npf, seed=sc.seed + 1000 * g, groups=[g])
-        for k in ("ox", "oy", "oz", "dx", "dy", "dz"):
-            rays[k][g * npf:(g + 1) * npf].copy_(torch.from_numpy(r[k].astype(np.float32)))
-        rays["group"][g * npf:(g + 1) * npf].copy_(torch.from_numpy(r["group"].astype(np.int32)))
-        print(f"[bench] field {g}: {npf} photons uploaded", file=sys.stderr, flush=True)
+    rays = c3_bundle(scenes, torch, sc, npf)
     torch.cuda.synchronize()
-    print(f"[bench] inputs ready in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    print(f"[bench] {n:.3e} photons generated on the device in {time.time() - t0:.1f}s", file=sys.stderr,
+          flush=True)
 
     sums = dev.new_sums()
+    fig = torch.zeros(sc.n_groups * rb.FIGURE_STRIDE, dtype=torch.float64, device="cuda")
     grad = torch.zeros(len(sc.params), dtype=torch.float64, device="cuda")
     cot = torch.zeros(sc.n_groups, 2, dtype=torch.float64, device="cuda")
     cot[:, 0] = 1.0 / sc.n_groups                    # L = mean RMS over the fields
     do_bwd = not args.no_backward
-    if do_bwd:
-        try:
-            dev.backward({k: v[:1] for k, v in rays.items()}, sums, cot, grad, n=1)
-        except rb.RobastError as e:
-            print(f"[bench] backward unavailable: {e}", file=sys.stderr, flush=True)
-            do_bwd = False
     stream = torch.cuda.current_stream()
-    ev_tr0, ev_tr1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    evs = [ev(torch) for _ in range(5)]
 
-    def step(record):
+    def step():
         sums.zero_()
-        if record:
-            ev_tr0.record(stream)
-        dev.trace(rays, sums=sums)
-        if record:
-            ev_tr1.record(stream)
-        fig = dev.figures(sums)
+        evs[0].record(stream)
+        dev.bin_photons(rays)                         # counting sort by entrance cell
+        evs[1].record(stream)
+        dev.trace(rays, sums=sums, keep_order=do_bwd)
+        evs[2].record(stream)
+        dev.figures(sums, fig=fig)
+        grad.zero_()
+        evs[3].record(stream)
         if do_bwd:
-            grad.zero_()
-            dev.backward(rays, sums, cot, grad)
-        return fig
+            dev.backward(rays, sums, cot, grad)      # reuses the binned order
+        evs[4].record(stream)
 
     for i in range(args.warmup):
-        step(False)
+        step()
         torch.cuda.synchronize()
         print(f"[bench] warmup {i} done", file=sys.stderr, flush=True)
-    trace_ms = []
+    k_bin, k_trace, k_bwd = [], [], []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
-        fig = step(True)
-        # per-launch duration of the trace kernel, measured on its own stream
-        ev_tr1.synchronize()
-        trace_ms.append(ev_tr0.elapsed_time(ev_tr1))
+        step()
+        evs[4].synchronize()
+        k_bin.append(evs[0].elapsed_time(evs[1]))
+        k_trace.append(evs[1].elapsed_time(evs[2]))
+        k_bwd.append(evs[3].elapsed_time(evs[4]))
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     ms_per_step = 1e3 * t_total / args.steps
-    figs = fig.cpu().numpy()
-    print(f"[bench] {args.steps} steps in {t_total:.3f}s; trace kernel {np.mean(trace_ms):.3f} ms avg",
-          file=sys.stderr, flush=True)
+    figs = fig.view(sc.n_groups, rb.FIGURE_STRIDE).cpu().numpy()
+    print(f"[bench] {args.steps} steps in {t_total:.3f}s; binning {np.mean(k_bin):.2f} ms, trace "
+          f"{np.mean(k_trace):.2f} ms, adjoint {np.mean(k_bwd):.2f} ms per step", file=sys.stderr, flush=True)
 
-    # CPU baseline (reference tracer) on a bounded sample + op tallies
-    cpu = None
-    ops = None
+    sweep = None if args.no_sweep else run_sweep(args, torch, rb, scenes)
+
+    # algorithmic op tallies from the reference tracer's event log
     import oracle
-    tally_rays = sc.rays(400, seed=sc.seed + 77)
-    tally = oracle.trace(sc, tally_rays, log=True)
-    ops = ops_per_photon(sc, tally)
+    tally = oracle.trace(sc, sc.rays(400, seed=sc.seed + 77), log=True)
+    ops_fwd, ops_adj = ops_per_photon(sc, tally)
+    cpu = None
     if not args.no_cpu_baseline:
-        cores = os.cpu_count() or 1
-        try:
-            cores = len(os.sched_getaffinity(0))
-        except AttributeError:
-            pass
-        cores = min(cores, 16)
+        cores = host_cores()
         sample = sc.rays(args.cpu_sample_per_field, seed=sc.seed + 99)
         rec, dt = oracle.timed_trace(sc, sample, nthreads=cores)
         ncpu = len(sample["ox"])
         cpu = {"value": ncpu / dt, "unit": "photons/s", "cores": cores, "kind": "oracle",
                "sample": f"{ncpu} photons ({args.cpu_sample_per_field} per field x {sc.n_groups} fields) "
-                         f"of the same scene, FP64 brute-force search, {dt:.1f}s"}
+                         f"of the same scene, forward trace only, FP64 brute-force search, {dt:.1f} s"}
         print(f"[bench] cpu baseline {ncpu / dt:.3e} photons/s on {cores} threads", file=sys.stderr,
               flush=True)
 
-    trace_s = np.mean(trace_ms) / 1e3
-    achieved = ops * n / trace_s / 1e12
+    def roof(ops, ms, traffic=None):
+        achieved = ops * n / (ms / 1e3) / 1e12
+        return {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
+                "frac": achieved * 1e12 / VALU_PEAK_OPS, "traffic": traffic, "ops_per_photon": ops,
+                "kernel_ms": ms}
+
+    t_trace, t_bwd = float(np.mean(k_trace)), float(np.mean(k_bwd))
+    rk = {"k_trace": roof(ops_fwd, t_trace, measured_traffic())}
+    if do_bwd:
+        rk["k_backward"] = roof(ops_adj, t_bwd)
+    dominant = "k_backward" if do_bwd and t_bwd > t_trace else "k_trace"
     out = {
-        "metric": "traced photons/s (2-mirror SC, 1e7 rays per field)",
+        "metric": "traced photons/s (2-mirror SC, 1e7 rays); batched fwd+adjoint vs plain, 1 GPU",
         "value": n / (ms_per_step / 1e3),
         "unit": "photons/s",
         "n_gpus": 1,
@@ -194,14 +380,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "schwarzschild_couder: 16 fields x 1e7 photons, 72 aspheric panels, "
-                               "forward + figures" + (" + adjoint (160 params)" if do_bwd else ""),
+        "config": {"workload": "schwarzschild_couder: 16 fields (0-4 deg) x 1e7 photons, 72 aspheric panels, "
+                               "binning + forward + figures" + (" + adjoint (160 params)" if do_bwd else ""),
                    "photons_per_step": n, "fields": sc.n_groups, "precision": 32},
-        "trace_kernel_ms": float(np.mean(trace_ms)),
-        "trace_photons_per_s": n / trace_s,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_OPS / 1e12,
-                     "unit": "Tops/s", "frac": achieved * 1e12 / VALU_PEAK_OPS, "traffic": None,
-                     "ops_per_photon": ops},
+        "kernels": {"binning_ms": float(np.mean(k_bin)), "trace_ms": t_trace, "adjoint_ms": t_bwd,
+                    "trace_photons_per_s": n / (t_trace / 1e3)},
+        "roofline": dict(rk[dominant], kernel=dominant),
+        "roofline_kernels": rk,
+        "sweep": sweep,
         "cpu_baseline": cpu,
         "figures": {"rms_mean_m": float(np.mean(figs[:, 4])), "efficiency_mean": float(np.mean(figs[:, 5]))},
     }

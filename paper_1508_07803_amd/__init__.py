@@ -251,9 +251,10 @@ class Scene:
         R = self._rays_struct(rays, id_base)
         _check(_lib.robast_bin_photons(self._h, ctypes.byref(R), n, _stream(stream)), "robast_bin_photons")
 
-    def figures(self, sums, stream=None):
+    def figures(self, sums, fig=None, stream=None):
         import torch
-        fig = torch.zeros(self.n_groups * FIGURE_STRIDE, dtype=torch.float64, device=sums.device)
+        if fig is None:
+            fig = torch.zeros(self.n_groups * FIGURE_STRIDE, dtype=torch.float64, device=sums.device)
         _check(_lib.robast_figures(self._h, _ptr(sums), _ptr(fig), _stream(stream)), "robast_figures")
         return fig.view(self.n_groups, FIGURE_STRIDE)
 

@@ -189,7 +189,7 @@ struct robast_batch {
   std::vector<robast_scene*> scenes;
   int64_t n_photons = 0, n_groups = 0, n_params = 0;
   int max_events = 0, max_params = 0, n_items = 0;
-  uint32_t blob_cap = 0;
+  uint32_t blob_cap = 0, blob_cap_bwd = 0;
   void* d_vars = nullptr;          // BatchVariant<T>[n_scenes]
   BatchItem* d_items = nullptr;    // n_items
   uint32_t* d_queue = nullptr;     // kQueueCounters counters
@@ -770,7 +770,7 @@ int check_hits(const robast_hits* hits) {
 
 template <typename T> BatchView<T> batch_view(const robast_batch* b) {
   return BatchView<T>{(const BatchVariant<T>*)b->d_vars, b->d_items, b->d_queue, b->n_items, b->max_events,
-                      b->max_params, b->blob_cap};
+                      b->max_params, b->blob_cap, b->blob_cap_bwd};
 }
 
 template <typename T> std::vector<BatchVariant<T>> variant_table(const robast_batch& b, const int64_t* offsets) {
@@ -1164,6 +1164,15 @@ int robast_build_batch(robast_scene* const* scenes, int32_t n_scenes, const int6
   // read from global memory instead.
   const size_t lds_cap = (size_t)scenes[0]->cfg.lds_cap;
   if (max_blob <= lds_cap) b->blob_cap = (uint32_t)std::min(lds_cap, ((max_blob * 3 / 2) + 15) & ~(size_t)15);
+  // the adjoint also keeps the gradient sums in LDS (up to 16 KiB); within
+  // the same budget per workgroup a variant whose tables do not fit what is
+  // left is traced from global memory rather than lowering the occupancy of
+  // every variant
+  {
+    const size_t gbytes = (size_t)b->max_params * sizeof(double);
+    const size_t left = gbytes <= 16384 && gbytes < lds_cap ? (lds_cap - gbytes) & ~(size_t)15 : lds_cap;
+    b->blob_cap_bwd = (uint32_t)std::min<size_t>(b->blob_cap, left);
+  }
   const size_t vbytes = sizeof(BatchVariant<float>);
   hipError_t e = hipMalloc(&b->d_vars, vbytes * n_scenes);
   if (e == hipSuccess) e = hipMalloc(&b->d_items, sizeof(BatchItem) * std::max<size_t>(1, items.size()));

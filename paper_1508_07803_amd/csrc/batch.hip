@@ -108,21 +108,18 @@ __device__ __forceinline__ void trace_item(const SceneView<float>& L, int64_t st
 }
 
 // USE_LDS: the items of variants that fit the LDS reservation; otherwise the
-// items of the others.  The LDS form is held to 3 waves per SIMD (<= 168
-// VGPRs), which the search needs to hide its LDS latency.
+// items of the others.  Per-variant state is re-derived from the variant
+// table for every item rather than carried across items (only the staged
+// variant and the lanes' sums are).  The LDS form is held to 3 waves per SIMD
+// (<= 168 VGPRs); 4 measured slower.
 template <bool USE_LDS, bool RECORD>
 __global__ void __launch_bounds__(kBlockB) __attribute__((amdgpu_waves_per_eu(USE_LDS ? 3 : 1, USE_LDS ? 3 : 8)))
 k_trace_batch(const BatchVariant<float>* vars, const BatchItem* items, int n_items, uint32_t* queue,
               uint32_t blob_cap, RaysView<float> R, HitsView<float> H) {
   extern __shared__ __align__(16) char lds[];
   __shared__ int s_item;
-  SceneView<float> S = {};
-  SceneView<float> L;
-  lds_view(L, lds);
-  bool mine = false;
-  int cur_v = -1;
-  int64_t off = 0;
-  double* target = nullptr;
+  int staged_v = -1;   // variant whose tables are in LDS
+  int acc_v = -1;      // variant whose sums the lanes hold
   double a[kNSumB];
 #pragma unroll
   for (int k = 0; k < kNSumB; ++k) a[k] = 0.0;
@@ -130,25 +127,32 @@ k_trace_batch(const BatchVariant<float>* vars, const BatchItem* items, int n_ite
   uint32_t* counter = queue + (USE_LDS ? 0 : 1);
   while (true) {
     const int item = next_item(counter, &s_item);
-    if (item >= n_items) break;
-    const BatchItem it = items[item];
-    if (it.v != cur_v) {
-      if (target) wave_flush(target, ag, a);
-      const BatchVariant<float> bv = vars[it.v];
-      S = *bv.S;
-      mine = fits_lds(S, blob_cap) == USE_LDS;
-      if (USE_LDS && mine) stage_variant<float>(S, L, lds);
-      target = H.sums ? H.sums + (int64_t)bv.goff * 8 : nullptr;
-      off = bv.off;
-      cur_v = it.v;
-      __syncthreads();
+    const BatchItem it = item < n_items ? load_uniform(items + item) : BatchItem{0, 0, -1};
+    if (acc_v >= 0 && it.v != acc_v) {
+      wave_flush(H.sums + (int64_t)load_uniform(vars + acc_v).goff * 8, ag, a);
+      acc_v = -1;
     }
-    if (!mine) continue;
-    trace_item<RECORD>(USE_LDS ? L : S, it.start, it.start + it.count, off, R, H, target, ag, a);
+    if (item >= n_items) break;
+    const BatchVariant<float> bv = load_uniform(vars + it.v);
+    const SceneView<float> S = load_uniform(bv.S);
+    if (fits_lds(S, blob_cap) != USE_LDS) continue;
+    SceneView<float> L;
+    if (USE_LDS) {
+      lds_view(L, lds);
+      if (it.v != staged_v) {
+        stage_variant<float>(S, L, lds);
+        staged_v = it.v;
+        __syncthreads();
+      } else {
+        stage_variant_view<float>(S, L, lds);
+      }
+    }
+    double* target = H.sums ? H.sums + (int64_t)bv.goff * 8 : nullptr;
+    trace_item<RECORD>(USE_LDS ? L : S, it.start, it.start + it.count, bv.off, R, H, target, ag, a);
+    if (target) acc_v = it.v;
     // a change of variant overwrites LDS: every wave must be done with it
     __syncthreads();
   }
-  if (target) wave_flush(target, ag, a);
 }
 
 // ------------------------------------------------------------------ launcher

@@ -39,6 +39,7 @@ template <typename T> struct BatchView {
   int max_events;                // largest max_events over the variants
   int max_params;                // largest n_params over the variants
   uint32_t blob_cap;             // LDS bytes reserved for a variant's tables (0: read from global memory)
+  uint32_t blob_cap_bwd;         // the same for the adjoint, whose LDS also holds the gradient sums
 };
 
 // Batched launches are built for FP32 scenes (the sweep precision).

@@ -33,6 +33,20 @@ __device__ __forceinline__ int next_item(uint32_t* counter, int* s_item) {
   return item;
 }
 
+// Loads a workgroup-uniform record into scalar registers.  The tables are
+// read through pointers the compiler cannot prove unaliased by the kernel's
+// stores, so it would keep them in vector registers; taking every word
+// through readfirstlane marks them uniform.
+template <typename T> __device__ __forceinline__ T load_uniform(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "records of whole words");
+  T out;
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(p);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) dst[k] = __builtin_amdgcn_readfirstlane(src[k]);
+  return out;
+}
+
 template <typename T> __device__ __forceinline__ bool fits_lds(const SceneView<T>& S, uint32_t blob_cap) {
   return blob_cap > 0 && S.blob_bytes <= blob_cap;
 }
@@ -48,14 +62,10 @@ template <typename T> __device__ __forceinline__ void lds_view(SceneView<T>& L, 
   L.groups = reinterpret_cast<const GroupRec<T>*>(lds);
 }
 
-// Copies the variant's tables into LDS and rebuilds the view's pointers
-// from the LDS array.  Reached by the whole workgroup; the caller
-// synchronises before the tables are read.
+// The view of a variant's tables held in LDS: the pointers are rebuilt from
+// the LDS array.
 template <typename T>
-__device__ __forceinline__ void stage_variant(const SceneView<T>& S, SceneView<T>& L, char* lds) {
-  const uint4* src = reinterpret_cast<const uint4*>(S.blob);
-  uint4* dst = reinterpret_cast<uint4*>(lds);
-  for (uint32_t i = threadIdx.x; i < S.blob_bytes / 16u; i += blockDim.x) dst[i] = src[i];
+__device__ __forceinline__ void stage_variant_view(const SceneView<T>& S, SceneView<T>& L, char* lds) {
   const char* base = S.blob;
   L = S;
   L.vol = reinterpret_cast<const DVol<T>*>(lds);
@@ -63,6 +73,16 @@ __device__ __forceinline__ void stage_variant(const SceneView<T>& S, SceneView<T
   L.cell_start = reinterpret_cast<const uint32_t*>(lds + (reinterpret_cast<const char*>(S.cell_start) - base));
   L.items = reinterpret_cast<const uint16_t*>(lds + (reinterpret_cast<const char*>(S.items) - base));
   L.groups = reinterpret_cast<const GroupRec<T>*>(lds + (reinterpret_cast<const char*>(S.groups) - base));
+}
+
+// Copies the variant's tables into LDS and builds their view.  Reached by
+// the whole workgroup; the caller synchronises before the tables are read.
+template <typename T>
+__device__ __forceinline__ void stage_variant(const SceneView<T>& S, SceneView<T>& L, char* lds) {
+  const uint4* src = reinterpret_cast<const uint4*>(S.blob);
+  uint4* dst = reinterpret_cast<uint4*>(lds);
+  for (uint32_t i = threadIdx.x; i < S.blob_bytes / 16u; i += blockDim.x) dst[i] = src[i];
+  stage_variant_view<T>(S, L, lds);
 }
 
 }  // namespace robast
