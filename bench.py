@@ -61,7 +61,12 @@ COST = {
 PULLBACK = {"plane": 150, "sphere": 300, "asphere": 420, "cylinder": 250, "box": 200, "hexcone": 600}
 SHAPE_NAME = {1: "plane", 2: "sphere", 3: "asphere", 4: "cylinder", 5: "box", 6: "hexcone"}
 
-TRACE_SOURCES = ["device_trace.hpp", "kernels.hip", "kernels.hpp", "scene_layout.hpp"]
+# sources each kernel is built from (its counters go stale when they change)
+KERNEL_SOURCES = {
+    "k_trace": ["device_trace.hpp", "kernels.hip", "kernels.hpp", "scene_layout.hpp"],
+    "k_backward": ["device_trace.hpp", "adjoint_device.hpp", "adjoint.hip", "kernels.hpp", "scene_layout.hpp"],
+}
+TRAFFIC_SUMMARY = os.path.join("profiles", "k_trace_k_backward_sc_16x1e7_hbm_traffic.md")
 
 
 def event_cost(scene, v, a):
@@ -114,18 +119,17 @@ def sources_digest(names):
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per trace launch from the committed counter summary, if the
-    trace sources are the ones the counters were taken on."""
-    path = os.path.join(ROOT, "profiles", "k_trace_sc_16x1e7_traffic.md")
+def measured_traffic(kernel):
+    """Calibrated HBM bytes per launch of `kernel` from the committed counter
+    summary, if its sources are the ones the counters were taken on."""
+    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
     if not os.path.exists(path):
         return None
-    text = open(path).read()
-    m = re.search(r"sources_sha256_16:\s*([0-9a-f]{16})", text)
-    b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m or not b or m.group(1) != sources_digest(TRACE_SOURCES):
+    m = re.search(kernel + r"\s+traffic_bytes_per_launch:\s*([0-9.eE+]+)\s+sources_sha256_16:\s*([0-9a-f]{16})",
+                  open(path).read())
+    if not m or m.group(2) != sources_digest(KERNEL_SOURCES[kernel]):
         return None
-    return float(b.group(1))
+    return float(m.group(1))
 
 
 def ev(torch):
@@ -363,9 +367,9 @@ def main():
                 "kernel_ms": ms}
 
     t_trace, t_bwd = float(np.mean(k_trace)), float(np.mean(k_bwd))
-    rk = {"k_trace": roof(ops_fwd, t_trace, measured_traffic())}
+    rk = {"k_trace": roof(ops_fwd, t_trace, measured_traffic("k_trace"))}
     if do_bwd:
-        rk["k_backward"] = roof(ops_adj, t_bwd)
+        rk["k_backward"] = roof(ops_adj, t_bwd, measured_traffic("k_backward"))
     dominant = "k_backward" if do_bwd and t_bwd > t_trace else "k_trace"
     out = {
         "metric": "traced photons/s (2-mirror SC, 1e7 rays); batched fwd+adjoint vs plain, 1 GPU",
