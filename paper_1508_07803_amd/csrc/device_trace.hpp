@@ -130,6 +130,43 @@ template <typename T> __device__ __forceinline__ bool inside_outline(const DVol<
   return false;
 }
 
+// Conservative test of a straight segment (xa, ya)-(xb, yb) of the local xy
+// plane against the outline: false only if no point of the segment can pass
+// inside_outline.  Each test is against a convex set (a half-plane, a slab,
+// the inside of a circle), for which both endpoints outside means the whole
+// segment outside; r^2 along a segment is convex, so both endpoints inside
+// the hole means the whole segment is.  Padded by 1e-5 of the outline size
+// against rounding of the hit point.
+template <typename T>
+__device__ __forceinline__ bool segment_may_meet_outline(const DVol<T>& v, T xa, T ya, T xb, T yb) {
+  const T* o = v.o;
+  switch (v.outline) {
+    case OL_ANNULUS: {
+      const T hole = o[0] * T(1 - 2e-5);
+      return !(xa * xa + ya * ya < hole && xb * xb + yb * yb < hole);
+    }
+    case OL_SECTOR: {
+      const T hole = o[0] * T(1 - 2e-5);
+      if (xa * xa + ya * ya < hole && xb * xb + yb * yb < hole) return false;
+      if (o[6] > T(0)) return true;
+      const T pad = T(1e-5) * v.rout;
+      if (o[2] * ya - o[3] * xa < -pad && o[2] * yb - o[3] * xb < -pad) return false;
+      if (xa * o[5] - ya * o[4] < -pad && xb * o[5] - yb * o[4] < -pad) return false;
+      return true;
+    }
+    case OL_HEX: {
+      const T h = T(0.8660254037844386), lim = o[0] * T(1 + 1e-5);
+      const T pa[3] = {xa, T(0.5) * xa + h * ya, T(-0.5) * xa + h * ya};
+      const T pb[3] = {xb, T(0.5) * xb + h * yb, T(-0.5) * xb + h * yb};
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        if ((pa[k] > lim && pb[k] > lim) || (pa[k] < -lim && pb[k] < -lim)) return false;
+      return true;
+    }
+    default: return true;
+  }
+}
+
 // ------------------------------------------------------------------ candidate bookkeeping
 // Nearest candidate so far: t (precision T) orders the candidates; tp is the
 // same parameter formed in double from the box-entry shift and the local
@@ -282,6 +319,9 @@ template <typename T> __device__ __forceinline__ void nf_asphere(const DVol<T>& 
     return;
   }
   if (!(ta <= tb)) return;
+  // the hit lies on [ta, tb]; skip the solve if that piece of the ray misses
+  // the outline (a neighbouring segment of a segmented mirror)
+  if (!segment_may_meet_outline(v, o.x + ta * d.x, o.y + ta * d.y, o.x + tb * d.x, o.y + tb * d.y)) return;
   T ga, gpa, gb, gpb;
   asph_g(v, o, d, ta, ga, gpa);
   asph_g(v, o, d, tb, gb, gpb);
