@@ -167,7 +167,7 @@ int robast_build_scene(const robast_scene_desc* desc, const double* params, int6
  * they share the scene's photon counter and binning workspace, so issue them
  * on one stream or order them.  With binning on (robast_tuning), a call with
  * more photons than any before it on the scene grows the workspace
- * (hipMalloc, 40 bytes per photon in FP32, 72 in FP64): capture a call in a HIP graph only
+ * (hipMalloc, 72 bytes per photon in FP32, 136 in FP64): capture a call in a HIP graph only
  * after an eager call of at least the same size. */
 int robast_trace(robast_scene* scene, const robast_rays* rays, int64_t n, const robast_hits* hits,
                  uint32_t flags, void* hip_stream);
@@ -262,7 +262,7 @@ int robast_build_batch(robast_scene* const* scenes, int32_t n_scenes, const int6
 /* Forward trace of the whole bundle: hits as for robast_trace, indexed by the
  * global photon index; hits->group_sums is the concatenated sums (+=).
  * Photon binning (per variant, within its range) follows the tuning of the
- * first scene at build time; its workspace (40 bytes per photon) is
+ * first scene at build time; its workspace (72 bytes per photon) is
  * allocated by robast_build_batch, so calls allocate nothing.  flags: 0 or
  * ROBAST_TRACE_KEEP_ORDER, with the meaning it has for robast_trace (the kept
  * order belongs to the batch). */

@@ -787,7 +787,6 @@ template <typename T> std::vector<BatchVariant<T>> variant_table(const robast_ba
 }
 
 constexpr int64_t kBinMin = 32768;
-constexpr int64_t kBinsMax = int64_t(1) << 22;
 
 void apply_tuning(robast_scene* s) {
   s->cfg.wave_chunk = (int)s->tuning.wave_chunk;
@@ -827,27 +826,20 @@ int binned_view(robast_scene* s, const robast_rays* rays, int64_t n, hipStream_t
   int nc = (int)std::floor(std::sqrt(std::max(1.0, per_cell)));
   const int nc_max = (int)std::floor(std::sqrt((double)kBinsMax / G));
   nc = std::max(1, std::min({nc, 1024, nc_max}));
-  const int64_t bins = (int64_t)G * nc * nc, parts = bin_scan_parts(bins);
-  const size_t un = align256((size_t)n * 4), rn = align256((size_t)n * sizeof(BinRecord<T>));
-  const size_t need = 2 * un + rn + align256((size_t)bins * 4) + align256((size_t)parts * 4);
-  if (need > s->work_bytes) {
+  const int64_t bins = (int64_t)G * nc * nc;
+  const BinPlan plan = bin_plan<T>(n, bins);
+  if (plan.bytes > s->work_bytes) {
     if (s->d_work) (void)hipFree(s->d_work);
     s->d_work = nullptr;
     s->work_bytes = 0;
-    hipError_t e = hipMalloc(&s->d_work, need);
+    hipError_t e = hipMalloc(&s->d_work, plan.bytes);
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(ROBAST_ENOMEM, "hipMalloc binning workspace")
                                                          : hip_fail(e, "hipMalloc binning workspace");
-    s->work_bytes = need;
+    s->work_bytes = plan.bytes;
   }
-  char* p = (char*)s->d_work;
-  BinWork<T> W{};
-  W.out = (BinRecord<T>*)p; p += rn;
-  W.key = (uint32_t*)p; p += un;
-  W.rank = (uint32_t*)p; p += un;
-  W.hist = (uint32_t*)p; p += align256((size_t)bins * 4);
-  W.part = (uint32_t*)p;
+  const BinWork<T> W = bin_carve<T>(plan, s->d_work);
   const BinGeom geo{s->bin_z, s->bin_x0, s->bin_y0, (double)nc / s->bin_side, nc, G, 0u, 0u};
-  hipError_t e = launch_binning<T>(R, n, geo, BinMulti{nullptr, nullptr, 0}, bins, W, st);
+  hipError_t e = launch_binning<T>(R, n, geo, BinMulti{nullptr, nullptr, 0}, plan, W, st);
   if (e != hipSuccess) return hip_fail(e, "binning launch");
   out = binned_rays<T>(W.out, rays->group != nullptr, rays->id_base);
   if (keep) {
@@ -881,38 +873,16 @@ int backward_t(robast_scene* s, const SceneView<T>& V, const robast_rays* rays, 
   return ROBAST_OK;
 }
 
-struct BatchBinLayout {
-  size_t un, rn, hist, parts_bytes, total;
-  int64_t parts;
-};
-
-BatchBinLayout batch_bin_layout(int64_t n, int64_t bins) {
-  BatchBinLayout L{};
-  L.un = align256((size_t)n * 4);
-  L.rn = align256((size_t)n * sizeof(BinRecord<float>));
-  L.hist = align256((size_t)bins * 4);
-  L.parts = bin_scan_parts(bins);
-  L.parts_bytes = align256((size_t)L.parts * 4);
-  L.total = L.rn + 2 * L.un + L.hist + L.parts_bytes;
-  return L;
-}
-
 // The photons a batched launch reads: the caller's arrays or their binned
 // copy (kept order reused when given the same arrays).
 int batch_binned_view(robast_batch* b, const robast_rays* rays, hipStream_t st, bool keep, RaysView<float>& out) {
   out = rays_view<float>(rays);
   if (!b->bin) return ROBAST_OK;
-  const BatchBinLayout L = batch_bin_layout(b->n_photons, b->bins);
-  char* p = (char*)b->d_work;
-  BinWork<float> W{};
-  W.out = (BinRecord<float>*)p; p += L.rn;
-  W.key = (uint32_t*)p; p += L.un;
-  W.rank = (uint32_t*)p; p += L.un;
-  W.hist = (uint32_t*)p; p += L.hist;
-  W.part = (uint32_t*)p;
+  const BinPlan plan = bin_plan<float>(b->n_photons, b->bins);
+  const BinWork<float> W = bin_carve<float>(plan, b->d_work);
   if (!(b->kept && same_rays(b->kept_rays, *rays))) {
     const BinMulti multi{b->d_offsets, b->d_geo, (int)b->scenes.size()};
-    hipError_t e = launch_binning<float>(out, b->n_photons, BinGeom{}, multi, b->bins, W, st);
+    hipError_t e = launch_binning<float>(out, b->n_photons, BinGeom{}, multi, plan, W, st);
     if (e != hipSuccess) return hip_fail(e, "batched binning launch");
   }
   b->kept = keep;
@@ -1206,12 +1176,12 @@ int robast_build_batch(robast_scene* const* scenes, int32_t n_scenes, const int6
       geo[v] = BinGeom{sv->bin_z, sv->bin_x0, sv->bin_y0, (double)nc / sv->bin_side, nc, G, (uint32_t)base, 0u};
       base += (int64_t)G * nc * nc;
     }
-    if (base <= (int64_t)1 << 28) {
+    if (base <= kBinsMax) {
       b->bins = base;
-      const BatchBinLayout L = batch_bin_layout(b->n_photons, b->bins);
+      const BinPlan plan = bin_plan<float>(b->n_photons, b->bins);
       e = hipMalloc(&b->d_offsets, sizeof(int64_t) * (n_scenes + 1));
       if (e == hipSuccess) e = hipMalloc(&b->d_geo, sizeof(BinGeom) * n_scenes);
-      if (e == hipSuccess) e = hipMalloc(&b->d_work, L.total);
+      if (e == hipSuccess) e = hipMalloc(&b->d_work, plan.bytes);
       if (e == hipSuccess)
         e = hipMemcpy(b->d_offsets, offsets, sizeof(int64_t) * (n_scenes + 1), hipMemcpyHostToDevice);
       if (e == hipSuccess) e = hipMemcpy(b->d_geo, geo.data(), sizeof(BinGeom) * n_scenes, hipMemcpyHostToDevice);

@@ -5,11 +5,19 @@
 // diverges far less than a wave of photons drawn at random over the
 // aperture.  The bundle is ordered by a key made of the photon's group and
 // the cell (row-major in a square grid) where its line crosses a reference
-// plane z = z_ref, by a counting sort: count per bin (the atomic's return
-// value is the photon's rank inside its bin), exclusive scan of the counts,
-// scatter.  The permutation is kept: the trace numbers each photon by its
-// original index (its random draws and its result do not depend on the
+// plane z = z_ref.  The permutation is kept: the trace numbers each photon by
+// its original index (its random draws and its result do not depend on the
 // order) and writes per-photon results back at that index.
+//
+// The sort is a two-level counting sort that needs no per-photon global
+// atomics: (1) each tile of photons counts its keys' coarse digits in LDS and
+// writes one count per (coarse bucket, tile); (2) an exclusive scan of those
+// counts, bucket-major, gives every (bucket, tile) its output range, and the
+// tile scatters its photons there (LDS cursors); (3) one workgroup per coarse
+// bucket counts the fine digits in LDS, scans them and scatters the bucket's
+// photons into key order.  Order within a (bucket, tile) or within a bin is
+// whatever the LDS atomics give: it changes only which lane traces which
+// photon.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,12 +28,10 @@ namespace robast {
 
 constexpr int kBinBlock = 256;
 constexpr int kScanPerThread = 4;
-constexpr int kScanTile = kBinBlock * kScanPerThread;   // bins per scan block
-
-__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = v;
-}
+constexpr int kScanTile = kBinBlock * kScanPerThread;   // entries per scan block
+constexpr int kMaxCoarse = 2048;                        // LDS counters of the coarse pass
+constexpr int kMaxFineShift = 13;                       // LDS counters of the fine pass: 2^13
+constexpr int64_t kTile = 131072;                       // photons per tile of the coarse pass
 
 // bundle of photon i: the last v with offsets[v] <= i (offsets ascending)
 __device__ __forceinline__ int bundle_of(const int64_t* offsets, int n_var, int64_t i) {
@@ -38,29 +44,111 @@ __device__ __forceinline__ int bundle_of(const int64_t* offsets, int n_var, int6
 }
 
 template <typename T, bool MULTI>
-__global__ void __launch_bounds__(kBinBlock) k_bin_count(RaysView<T> R, int64_t n, BinGeom geo1, BinMulti multi,
-                                                         uint32_t* key, uint32_t* rank, uint32_t* hist) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const BinGeom geo = MULTI ? multi.geo[bundle_of(multi.offsets, multi.n_var, i)] : geo1;
-    T o[3], d[3];
-    R.load(i, o, d);
-    double ox = (double)o[0], oy = (double)o[1];
-    const double oz = (double)o[2], dx = (double)d[0], dy = (double)d[1], dz = (double)d[2];
-    // where the line crosses the reference plane (the origin itself for
-    // lines nearly parallel to it)
-    if (fabs(dz) > 1e-3) {
-      const double s = (geo.z_ref - oz) / dz;
-      ox += s * dx;
-      oy += s * dy;
-    }
-    uint32_t g = (uint32_t)R.grp(i);
-    if (g >= (uint32_t)geo.n_groups) g = 0u;
-    const double fx = (ox - geo.x0) * geo.inv_cell, fy = (oy - geo.y0) * geo.inv_cell;
-    const int ix = (int)fmin(fmax(fx, 0.0), (double)(geo.nc - 1));
-    const int iy = (int)fmin(fmax(fy, 0.0), (double)(geo.nc - 1));
-    const uint32_t k = geo.base + (g * (uint32_t)geo.nc + (uint32_t)iy) * (uint32_t)geo.nc + (uint32_t)ix;
+__device__ __forceinline__ uint32_t photon_key(const RaysView<T>& R, int64_t i, const BinGeom& geo1,
+                                               const BinMulti& multi) {
+  const BinGeom geo = MULTI ? multi.geo[bundle_of(multi.offsets, multi.n_var, i)] : geo1;
+  T o[3], d[3];
+  R.load(i, o, d);
+  double ox = (double)o[0], oy = (double)o[1];
+  const double oz = (double)o[2], dx = (double)d[0], dy = (double)d[1], dz = (double)d[2];
+  // where the line crosses the reference plane (the origin itself for lines
+  // nearly parallel to it)
+  if (fabs(dz) > 1e-3) {
+    const double s = (geo.z_ref - oz) / dz;
+    ox += s * dx;
+    oy += s * dy;
+  }
+  uint32_t g = (uint32_t)R.grp(i);
+  if (g >= (uint32_t)geo.n_groups) g = 0u;
+  const double fx = (ox - geo.x0) * geo.inv_cell, fy = (oy - geo.y0) * geo.inv_cell;
+  const int ix = (int)fmin(fmax(fx, 0.0), (double)(geo.nc - 1));
+  const int iy = (int)fmin(fmax(fy, 0.0), (double)(geo.nc - 1));
+  return geo.base + (g * (uint32_t)geo.nc + (uint32_t)iy) * (uint32_t)geo.nc + (uint32_t)ix;
+}
+
+// (1) keys and per-tile coarse counts; cnt is bucket-major: cnt[c * n_tiles + tile]
+template <typename T, bool MULTI>
+__global__ void __launch_bounds__(kBinBlock) k_bin_keys(RaysView<T> R, int64_t n, BinGeom geo1, BinMulti multi,
+                                                        int shift, int n_coarse, int n_tiles, uint32_t* key,
+                                                        uint32_t* cnt) {
+  extern __shared__ uint32_t hist[];
+  for (int c = threadIdx.x; c < n_coarse; c += blockDim.x) hist[c] = 0u;
+  __syncthreads();
+  const int64_t lo = (int64_t)blockIdx.x * kTile, hi = lo + kTile < n ? lo + kTile : n;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const uint32_t k = photon_key<T, MULTI>(R, i, geo1, multi);
     key[i] = k;
-    rank[i] = atomicAdd(hist + k, 1u);
+    atomicAdd(hist + (k >> shift), 1u);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < n_coarse; c += blockDim.x) cnt[(int64_t)c * n_tiles + blockIdx.x] = hist[c];
+}
+
+// (2) each tile scatters its photons to its range of every coarse bucket
+template <typename T>
+__global__ void __launch_bounds__(kBinBlock) k_bin_coarse(RaysView<T> R, int64_t n, int shift, int n_coarse,
+                                                          int n_tiles, const uint32_t* key, const uint32_t* offs,
+                                                          uint32_t* tkey, BinRecord<T>* tmp) {
+  static_assert(sizeof(BinRecord<T>) % 16 == 0, "records are written as 16-byte words");
+  extern __shared__ uint32_t cursor[];
+  for (int c = threadIdx.x; c < n_coarse; c += blockDim.x) cursor[c] = offs[(int64_t)c * n_tiles + blockIdx.x];
+  __syncthreads();
+  const int64_t lo = (int64_t)blockIdx.x * kTile, hi = lo + kTile < n ? lo + kTile : n;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const uint32_t k = key[i];
+    const uint32_t pos = atomicAdd(cursor + (k >> shift), 1u);
+    BinRecord<T> r{};
+    R.load(i, r.c, r.c + 3);
+    r.group = (uint32_t)R.grp(i);
+    r.src = (uint32_t)i;
+    const uint4* from = reinterpret_cast<const uint4*>(&r);
+    uint4* to = reinterpret_cast<uint4*>(tmp + pos);
+#pragma unroll
+    for (int w = 0; w < (int)(sizeof(BinRecord<T>) / 16); ++w) to[w] = from[w];
+    tkey[pos] = k;
+  }
+}
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t& total);
+
+// (3) one workgroup per coarse bucket: fine counting sort into key order
+template <typename T>
+__global__ void __launch_bounds__(kBinBlock) k_bin_fine(int64_t n, int shift, int n_coarse, int n_tiles,
+                                                        const uint32_t* offs, const uint32_t* tkey,
+                                                        const BinRecord<T>* tmp, BinRecord<T>* out) {
+  extern __shared__ uint32_t fine[];
+  __shared__ uint32_t sh[kBinBlock];
+  const int c = blockIdx.x;
+  const int nf = 1 << shift;
+  const uint32_t mask = (uint32_t)nf - 1u;
+  const int64_t start = offs[(int64_t)c * n_tiles];
+  const int64_t end = c + 1 < n_coarse ? (int64_t)offs[(int64_t)(c + 1) * n_tiles] : n;
+  for (int f = threadIdx.x; f < nf; f += blockDim.x) fine[f] = 0u;
+  __syncthreads();
+  for (int64_t i = start + threadIdx.x; i < end; i += blockDim.x) atomicAdd(fine + (tkey[i] & mask), 1u);
+  __syncthreads();
+  // exclusive scan of the fine counts: contiguous runs per thread, then the
+  // run totals across the workgroup
+  const int per = (nf + kBinBlock - 1) / kBinBlock;
+  const int f0 = threadIdx.x * per;
+  uint32_t run = 0;
+  for (int k = 0; k < per; ++k)
+    if (f0 + k < nf) run += fine[f0 + k];
+  uint32_t total;
+  uint32_t acc = block_exclusive_scan(run, sh, total);
+  for (int k = 0; k < per; ++k)
+    if (f0 + k < nf) {
+      const uint32_t v = fine[f0 + k];
+      fine[f0 + k] = acc;
+      acc += v;
+    }
+  __syncthreads();
+  for (int64_t i = start + threadIdx.x; i < end; i += blockDim.x) {
+    const uint32_t pos = (uint32_t)start + atomicAdd(fine + (tkey[i] & mask), 1u);
+    const uint4* from = reinterpret_cast<const uint4*>(tmp + i);
+    uint4* to = reinterpret_cast<uint4*>(out + pos);
+#pragma unroll
+    for (int w = 0; w < (int)(sizeof(BinRecord<T>) / 16); ++w) to[w] = from[w];
   }
 }
 
@@ -124,52 +212,72 @@ __global__ void __launch_bounds__(kBinBlock) k_scan_add(uint32_t* hist, int64_t 
     if (base + k < bins) hist[base + k] += add;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kBinBlock) k_bin_scatter(RaysView<T> R, int64_t n, const uint32_t* key,
-                                                           const uint32_t* rank, const uint32_t* offs,
-                                                           BinRecord<T>* out) {
-  static_assert(sizeof(BinRecord<T>) % 16 == 0, "records are written as 16-byte words");
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    BinRecord<T> r{};
-    R.load(i, r.c, r.c + 3);
-    r.group = (uint32_t)R.grp(i);
-    r.src = (uint32_t)i;
-    const uint32_t slot = offs[key[i]] + rank[i];
-    const uint4* from = reinterpret_cast<const uint4*>(&r);
-    uint4* to = reinterpret_cast<uint4*>(out + slot);
-#pragma unroll
-    for (int k = 0; k < (int)(sizeof(BinRecord<T>) / 16); ++k) to[k] = from[k];
-  }
-}
-
 static int grid_for(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>((n + kBinBlock - 1) / kBinBlock, 8192));
 }
 
-int64_t bin_scan_parts(int64_t bins) { return (bins + kScanTile - 1) / kScanTile; }
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+template <typename T> BinPlan bin_plan(int64_t n, int64_t bins) {
+  BinPlan p{};
+  int shift = 0;
+  while ((bins + (int64_t(1) << shift) - 1) >> shift > kMaxCoarse) ++shift;
+  p.shift = shift;
+  p.n_coarse = (int)((bins + (int64_t(1) << shift) - 1) >> shift);
+  p.n_tiles = (int)((n + kTile - 1) / kTile);
+  p.cnt_entries = (int64_t)p.n_coarse * p.n_tiles;
+  p.parts = (p.cnt_entries + kScanTile - 1) / kScanTile;
+  size_t off = 0;
+  p.key_off = off; off += align256((size_t)n * 4);
+  p.tkey_off = off; off += align256((size_t)n * 4);
+  p.tmp_off = off; off += align256((size_t)n * sizeof(BinRecord<T>));
+  p.out_off = off; off += align256((size_t)n * sizeof(BinRecord<T>));
+  p.cnt_off = off; off += align256((size_t)p.cnt_entries * 4);
+  p.part_off = off; off += align256((size_t)p.parts * 4);
+  p.bytes = off;
+  return p;
+}
+
+template <typename T> BinWork<T> bin_carve(const BinPlan& p, void* base) {
+  char* b = (char*)base;
+  BinWork<T> W;
+  W.key = (uint32_t*)(b + p.key_off);
+  W.tkey = (uint32_t*)(b + p.tkey_off);
+  W.tmp = (BinRecord<T>*)(b + p.tmp_off);
+  W.out = (BinRecord<T>*)(b + p.out_off);
+  W.cnt = (uint32_t*)(b + p.cnt_off);
+  W.part = (uint32_t*)(b + p.part_off);
+  return W;
+}
 
 template <typename T>
 hipError_t launch_binning(const RaysView<T>& R, int64_t n, const BinGeom& geo, const BinMulti& multi,
-                          int64_t bins, const BinWork<T>& W, hipStream_t st) {
-  const int64_t parts = bin_scan_parts(bins);
-  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(bins)), dim3(kBinBlock), 0, st, W.hist, bins, 0u);
+                          const BinPlan& p, const BinWork<T>& W, hipStream_t st) {
+  if (p.shift > kMaxFineShift || p.n_coarse > kMaxCoarse) return hipErrorInvalidValue;
+  const size_t coarse_lds = (size_t)p.n_coarse * 4, fine_lds = ((size_t)1 << p.shift) * 4;
   if (multi.n_var > 0)
-    hipLaunchKernelGGL((k_bin_count<T, true>), dim3(grid_for(n)), dim3(kBinBlock), 0, st, R, n, geo, multi, W.key,
-                       W.rank, W.hist);
+    hipLaunchKernelGGL((k_bin_keys<T, true>), dim3(p.n_tiles), dim3(kBinBlock), coarse_lds, st, R, n, geo, multi,
+                       p.shift, p.n_coarse, p.n_tiles, W.key, W.cnt);
   else
-    hipLaunchKernelGGL((k_bin_count<T, false>), dim3(grid_for(n)), dim3(kBinBlock), 0, st, R, n, geo, multi, W.key,
-                       W.rank, W.hist);
-  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)parts), dim3(kBinBlock), 0, st, W.hist, bins, W.part);
-  hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kBinBlock), 0, st, W.part, (int)parts);
-  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)parts), dim3(kBinBlock), 0, st, W.hist, bins, W.part);
-  hipLaunchKernelGGL(k_bin_scatter<T>, dim3(grid_for(n)), dim3(kBinBlock), 0, st, R, n, W.key, W.rank, W.hist,
-                     W.out);
+    hipLaunchKernelGGL((k_bin_keys<T, false>), dim3(p.n_tiles), dim3(kBinBlock), coarse_lds, st, R, n, geo, multi,
+                       p.shift, p.n_coarse, p.n_tiles, W.key, W.cnt);
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)p.parts), dim3(kBinBlock), 0, st, W.cnt, p.cnt_entries, W.part);
+  hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kBinBlock), 0, st, W.part, (int)p.parts);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)p.parts), dim3(kBinBlock), 0, st, W.cnt, p.cnt_entries, W.part);
+  hipLaunchKernelGGL(k_bin_coarse<T>, dim3(p.n_tiles), dim3(kBinBlock), coarse_lds, st, R, n, p.shift, p.n_coarse,
+                     p.n_tiles, W.key, W.cnt, W.tkey, W.tmp);
+  hipLaunchKernelGGL(k_bin_fine<T>, dim3(p.n_coarse), dim3(kBinBlock), fine_lds, st, n, p.shift, p.n_coarse,
+                     p.n_tiles, W.cnt, W.tkey, W.tmp, W.out);
   return hipGetLastError();
 }
 
-template hipError_t launch_binning<float>(const RaysView<float>&, int64_t, const BinGeom&, const BinMulti&, int64_t,
-                                          const BinWork<float>&, hipStream_t);
+template BinPlan bin_plan<float>(int64_t, int64_t);
+template BinPlan bin_plan<double>(int64_t, int64_t);
+template BinWork<float> bin_carve<float>(const BinPlan&, void*);
+template BinWork<double> bin_carve<double>(const BinPlan&, void*);
+template hipError_t launch_binning<float>(const RaysView<float>&, int64_t, const BinGeom&, const BinMulti&,
+                                          const BinPlan&, const BinWork<float>&, hipStream_t);
 template hipError_t launch_binning<double>(const RaysView<double>&, int64_t, const BinGeom&, const BinMulti&,
-                                           int64_t, const BinWork<double>&, hipStream_t);
+                                           const BinPlan&, const BinWork<double>&, hipStream_t);
 
 }  // namespace robast

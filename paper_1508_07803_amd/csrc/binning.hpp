@@ -33,13 +33,33 @@ template <typename T> struct BinRecord;
 template <> struct alignas(16) BinRecord<float> { float c[6]; uint32_t group, src; };
 template <> struct alignas(16) BinRecord<double> { double c[6]; uint32_t group, src, pad[2]; };
 
-template <typename T> struct BinWork {
-  uint32_t* key;         // n
-  uint32_t* rank;        // n
-  uint32_t* hist;        // bins: counts, then offsets
-  uint32_t* part;        // bin_scan_parts(bins)
-  BinRecord<T>* out;     // n
+// Workspace of one binning (two-level counting sort, see binning.hip).
+struct BinPlan {
+  int shift;            // fine digit = key & ((1 << shift) - 1), coarse = key >> shift
+  int n_coarse;         // coarse buckets
+  int n_tiles;          // photon tiles of the coarse pass
+  int64_t cnt_entries;  // n_coarse * n_tiles per-tile counts
+  int64_t parts;        // scan partials
+  size_t key_off, tkey_off, tmp_off, out_off, cnt_off, part_off, bytes;
 };
+
+// Largest bin count a binning supports (keys are 32-bit; the coarse pass
+// keeps one LDS counter per coarse bucket and the fine pass one per bin of a
+// bucket).
+constexpr int64_t kBinsMax = int64_t(1) << 24;
+
+template <typename T> BinPlan bin_plan(int64_t n, int64_t bins);
+
+template <typename T> struct BinWork {
+  uint32_t* key;         // n: key per photon (caller order)
+  uint32_t* tkey;        // n: key per photon (coarse order)
+  BinRecord<T>* tmp;     // n: records in coarse order
+  BinRecord<T>* out;     // n: records in key order (the result)
+  uint32_t* cnt;         // cnt_entries: per (coarse bucket, tile) counts, then offsets
+  uint32_t* part;        // scan partials
+};
+
+template <typename T> BinWork<T> bin_carve(const BinPlan& plan, void* base);
 
 // The view of binned records as photon arrays.
 template <typename T> RaysView<T> binned_rays(const BinRecord<T>* rec, bool has_group, uint64_t id_base) {
@@ -51,11 +71,10 @@ template <typename T> RaysView<T> binned_rays(const BinRecord<T>* rec, bool has_
   return R;
 }
 
-int64_t bin_scan_parts(int64_t bins);
-
-// One bundle (geo) or several (multi.n_var > 0); bins = total bin count.
+// One bundle (geo) or several (multi.n_var > 0); bins = total bin count
+// (<= kBinsMax), n <= 2^32 - 1; plan = bin_plan<T>(n, bins).
 template <typename T>
 hipError_t launch_binning(const RaysView<T>& R, int64_t n, const BinGeom& geo, const BinMulti& multi,
-                          int64_t bins, const BinWork<T>& W, hipStream_t st);
+                          const BinPlan& plan, const BinWork<T>& W, hipStream_t st);
 
 }  // namespace robast
