@@ -62,10 +62,10 @@ class Hits(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("bin_photons", ctypes.c_uint32), ("bin_target", ctypes.c_uint32),
-                ("wave_chunk", ctypes.c_uint32), ("waves_mult", ctypes.c_uint32)]
+                ("waves_mult", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
     def as_dict(self):
-        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
 
 
 assert ctypes.sizeof(VolumeDesc) == 464
@@ -273,7 +273,7 @@ class Scene:
         return t.as_dict()
 
     def set_tuning(self, **fields):
-        """Change launch parameters (bin_photons, bin_target, wave_chunk, waves_mult)."""
+        """Change launch parameters (bin_photons, bin_target, waves_mult)."""
         cur = self.tuning
         unknown = set(fields) - set(cur)
         if unknown:

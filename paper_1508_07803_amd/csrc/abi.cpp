@@ -170,7 +170,6 @@ struct robast_scene {
   robast_tuning tuning{};
   // photon binning: plane z = bin_z, square of side bin_side from (bin_x0, bin_y0)
   double bin_z = 0.0, bin_x0 = 0.0, bin_y0 = 0.0, bin_side = 1.0;
-  unsigned long long* d_counter = nullptr;   // photon counter of the running call
   void* d_work = nullptr;                    // binning workspace
   size_t work_bytes = 0;
   // the binned order kept by a trace call for the next backward call
@@ -788,14 +787,10 @@ template <typename T> std::vector<BatchVariant<T>> variant_table(const robast_ba
 
 constexpr int64_t kBinMin = 32768;
 
-void apply_tuning(robast_scene* s) {
-  s->cfg.wave_chunk = (int)s->tuning.wave_chunk;
-  s->cfg.waves_mult = (int)s->tuning.waves_mult;
-}
+void apply_tuning(robast_scene* s) { s->cfg.waves_mult = (int)s->tuning.waves_mult; }
 
 int tuning_valid(const robast_tuning& t) {
-  return t.bin_target >= 1 && t.bin_target <= 65536 && t.wave_chunk >= 64 && t.wave_chunk <= 65536 &&
-         t.waves_mult >= 1 && t.waves_mult <= 8;
+  return t.bin_target >= 1 && t.bin_target <= 65536 && t.waves_mult >= 1 && t.waves_mult <= 8;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -857,7 +852,7 @@ int trace_t(robast_scene* s, const SceneView<T>& V, const robast_rays* rays, int
   RaysView<T> R;
   int rc = binned_view<T>(s, rays, n, st, R, keep);
   if (rc) return rc;
-  hipError_t e = launch_trace<T>(V, R, n, hits_view<T>(hits), s->cfg, s->d_counter, st);
+  hipError_t e = launch_trace<T>(V, R, n, hits_view<T>(hits), s->cfg, st);
   if (e != hipSuccess) return hip_fail(e, "trace launch");
   return ROBAST_OK;
 }
@@ -939,13 +934,9 @@ int robast_build_scene(const robast_scene_desc* desc, const double* params, int6
   s->params.assign(params, params + n_params);
   s->cfg.lds_cap = kLdsCap;
   s->cfg.max_blocks = 0;
-  s->tuning = robast_tuning{1u, 128u, 256u, 1u};
+  s->tuning = robast_tuning{1u, 128u, 1u, 0u};
   apply_tuning(s);
   rc = upload(s);
-  if (!rc) {
-    hipError_t e = hipMalloc(&s->d_counter, sizeof(unsigned long long));
-    if (e != hipSuccess) rc = hip_fail(e, "hipMalloc counter");
-  }
   if (rc) {
     robast_destroy_scene(s);
     return rc;
@@ -970,7 +961,6 @@ void robast_destroy_scene(robast_scene* s) {
   if (s->d_tilt) (void)hipFree(s->d_tilt);
   if (s->d_coef) (void)hipFree(s->d_coef);
   if (s->d_view) (void)hipFree(s->d_view);
-  if (s->d_counter) (void)hipFree(s->d_counter);
   if (s->d_work) (void)hipFree(s->d_work);
   delete s;
 }
@@ -1061,10 +1051,10 @@ int robast_autotune(robast_scene* s, const robast_rays* rays, int64_t n, robast_
   robast_hits hits{};
   hits.group_sums = sums;
   for (uint32_t bin = 0; bin < 2 && e == hipSuccess && !rc; ++bin)
-    for (uint32_t chunk : {128u, 256u, 1024u})
+    for (uint32_t target : {32u, 128u, 512u})
       for (uint32_t mult : {1u, 2u}) {
-        if (e != hipSuccess || rc) break;
-        s->tuning = robast_tuning{bin, saved.bin_target, chunk, mult};
+        if (e != hipSuccess || rc || (!bin && target != 128u)) continue;
+        s->tuning = robast_tuning{bin, target, mult, 0u};
         apply_tuning(s);
         float ms = 0.0f;
         for (int rep = 0; rep < 2 && e == hipSuccess && !rc; ++rep) {   // first run warms up

@@ -41,19 +41,12 @@ __device__ __forceinline__ void flush_lane(double* acc_lds, int g, const double*
     if (a[k] != 0.0) atomicAdd(acc_lds + g * 8 + k, a[k]);
 }
 
-// Photons are handed out in contiguous chunks per wave from one counter per
-// launch: a wave's lanes take consecutive photons of the (binned) bundle, so
-// they stay spatially close, and waves that finish early take more chunks.
-__global__ void k_reset_counter(unsigned long long* c) {
-  if (threadIdx.x == 0) *c = 0ull;
-}
-
 // FP32 kernels are held to 4 waves per SIMD (<= 128 VGPRs, a few spills):
 // measured faster than the 3 waves the unconstrained allocation gives, as
 // the extra wave hides LDS and memory latency of the search.
 template <typename T, bool RECORD, bool SUMS, bool USE_LDS>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1, 8))) k_trace(SceneView<T> S, RaysView<T> R, int64_t n, HitsView<T> H,
-                                                  int sums_in_lds, unsigned long long* counter, int chunk) {
+                                                  int sums_in_lds) {
   extern __shared__ __align__(16) char lds[];
   SceneView<T> L;
   stage_scene<T, USE_LDS>(S, L, lds);
@@ -69,81 +62,42 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
   int ag = -1;
   double* acc_target = (SUMS && sums_in_lds) ? acc : H.sums;
 
-  // Event-level refill: every iteration each lane performs one interaction
-  // of its current photon; lanes whose photon has ended take the next photons
-  // of the wave's chunk at the top of the iteration, so the wave keeps
-  // running the same per-event code instead of idling behind long photons.
-  const int lane = (int)(threadIdx.x & 63);
-  const unsigned long long below = (1ull << lane) - 1ull;
-  int64_t wnext = 0, wend = 0;   // the wave's chunk [wnext, wend)
-  bool drained = false;
-  int64_t cur = -1;
-  int g = -1;
-  PhotonState ps;
-  ps.fate = 1;
-  while (true) {
-    bool started = false;
-    // two passes: the chunk may run out part-way through a refill
-    for (int pass = 0; pass < 2 && !drained; ++pass) {
-      const unsigned long long need = __ballot(cur < 0);
-      if (need == 0ull) break;
-      if (wnext >= wend) {
-        unsigned long long c0 = 0ull;
-        if (lane == 0) c0 = atomicAdd(counter, (unsigned long long)chunk);
-        const int64_t c = (int64_t)__shfl(c0, 0, 64);
-        if (c >= n) { drained = true; break; }
-        wnext = c;
-        wend = c + chunk < n ? c + chunk : n;
-      }
-      const int64_t idx = wnext + (int64_t)__popcll(need & below);
-      if (cur < 0 && idx < wend) {
-        cur = idx;
-        T oa[3], da[3];
-        R.load(cur, oa, da);
-        g = R.grp(cur);
-        // a group id outside [0, n_groups) is traced but never accumulated
-        if ((unsigned)g >= (unsigned)S.n_groups) g = -1;
-        photon_init(ps, V3<T>{oa[0], oa[1], oa[2]}, V3<T>{da[0], da[1], da[2]}, R.id_base + (uint64_t)R.src(cur));
-        started = true;
-      }
-      const int64_t took = (int64_t)__popcll(need);
-      wnext = wnext + took < wend ? wnext + took : wend;
+  // One lane traces one photon start to finish (the event loop, §2.1), over
+  // a persistent grid-stride walk of the (binned) bundle: consecutive lanes
+  // take consecutive photons, which binning makes spatially close, so a
+  // wave's photons follow similar paths and finish at similar times.
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t cur = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; cur < n; cur += stride) {
+    T oa[3], da[3];
+    R.load(cur, oa, da);
+    int g = R.grp(cur);
+    if ((unsigned)g >= (unsigned)S.n_groups) g = -1;
+    PhotonState ps;
+    photon_init(ps, V3<T>{oa[0], oa[1], oa[2]}, V3<T>{da[0], da[1], da[2]}, R.id_base + (uint64_t)R.src(cur));
+    while (!ps.fate) photon_step(L, ps);
+    PhotonOut<T> r = photon_out<T>(ps);
+    if (RECORD) {
+      const int64_t o = R.src(cur);
+      if (H.fate) H.fate[o] = (uint8_t)r.fate;
+      if (H.nev) H.nev[o] = (uint8_t)r.nev;
+      if (H.last_vol) H.last_vol[o] = r.last_vol;
+      if (H.x) { H.x[o] = r.pos.x; H.y[o] = r.pos.y; H.z[o] = r.pos.z; }
+      if (H.ux) { H.ux[o] = r.dir.x; H.uy[o] = r.dir.y; H.uz[o] = r.dir.z; }
+      if (H.opl) H.opl[o] = r.opl;
+      if (H.hash) H.hash[o] = r.hash;
     }
-    if (!__any(cur >= 0)) break;
-    if (SUMS) {
-      // wave-uniform flush when a lane starts a photon of another group
-      bool change = started && g >= 0 && g != ag && ag >= 0;
-      if (__any(change)) {
+    if (SUMS && g >= 0) {
+      if (g != ag && ag >= 0) {
         flush_lane(acc_target, ag, a);
 #pragma unroll
         for (int k = 0; k < kNSum; ++k) a[k] = 0.0;
-        ag = -1;
       }
-    }
-    if (cur >= 0) {
-      if (!ps.fate) photon_step(L, ps);
-      if (ps.fate) {
-        PhotonOut<T> r = photon_out<T>(ps);
-        if (RECORD) {
-          const int64_t o = R.src(cur);
-          if (H.fate) H.fate[o] = (uint8_t)r.fate;
-          if (H.nev) H.nev[o] = (uint8_t)r.nev;
-          if (H.last_vol) H.last_vol[o] = r.last_vol;
-          if (H.x) { H.x[o] = r.pos.x; H.y[o] = r.pos.y; H.z[o] = r.pos.z; }
-          if (H.ux) { H.ux[o] = r.dir.x; H.uy[o] = r.dir.y; H.uz[o] = r.dir.z; }
-          if (H.opl) H.opl[o] = r.opl;
-          if (H.hash) H.hash[o] = r.hash;
-        }
-        if (SUMS && g >= 0) {
-          ag = g;
-          a[0] += 1.0;
-          if (r.fate == FOCUSED) {
-            double x = (double)r.pos.x, y = (double)r.pos.y;
-            a[1] += 1.0; a[2] += x; a[3] += y; a[4] += x * x; a[5] += y * y;
-            a[6] += (double)dabs(r.dir.z);
-          }
-        }
-        cur = -1;
+      ag = g;
+      a[0] += 1.0;
+      if (r.fate == FOCUSED) {
+        double x = (double)r.pos.x, y = (double)r.pos.y;
+        a[1] += 1.0; a[2] += x; a[3] += y; a[4] += x * x; a[5] += y * y;
+        a[6] += (double)dabs(r.dir.z);
       }
     }
   }
@@ -190,7 +144,7 @@ static hipError_t device_cus(int& ncu) {
 
 template <typename T, bool RECORD, bool SUMS, bool USE_LDS>
 static hipError_t launch_one_l(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const HitsView<T>& H,
-                             const LaunchCfg& cfg, unsigned long long* counter, hipStream_t st) {
+                             const LaunchCfg& cfg, hipStream_t st) {
   int ncu = 0;
   hipError_t e = device_cus(ncu);
   if (e != hipSuccess) return e;
@@ -201,34 +155,32 @@ static hipError_t launch_one_l(const SceneView<T>& S, const RaysView<T>& R, int6
   int per_cu = 0;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace<T, RECORD, SUMS, USE_LDS>, kBlock, shmem);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
-  const int chunk = std::max(64, cfg.wave_chunk);
-  int64_t want = (n + chunk * (kBlock / 64) - 1) / (chunk * (kBlock / 64));
+  int64_t want = (n + kBlock - 1) / kBlock;
   int64_t cap = (int64_t)ncu * per_cu * (cfg.waves_mult > 0 ? cfg.waves_mult : 1);
   if (cfg.max_blocks > 0) cap = std::min<int64_t>(cap, cfg.max_blocks);
   int blocks = (int)std::max<int64_t>(1, std::min(want, cap));
-  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
   hipLaunchKernelGGL((k_trace<T, RECORD, SUMS, USE_LDS>), dim3(blocks), dim3(kBlock), shmem, st, S, R, n, H,
-                     sums_lds ? 1 : 0, counter, chunk);
+                     sums_lds ? 1 : 0);
   return hipGetLastError();
 }
 
 template <typename T, bool RECORD, bool SUMS>
 static hipError_t launch_one(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const HitsView<T>& H,
-                             const LaunchCfg& cfg, unsigned long long* counter, hipStream_t st) {
+                             const LaunchCfg& cfg, hipStream_t st) {
   bool use_lds = cfg.lds_cap > 0 && S.blob_bytes <= (uint32_t)cfg.lds_cap;
-  if (use_lds) return launch_one_l<T, RECORD, SUMS, true>(S, R, n, H, cfg, counter, st);
-  return launch_one_l<T, RECORD, SUMS, false>(S, R, n, H, cfg, counter, st);
+  if (use_lds) return launch_one_l<T, RECORD, SUMS, true>(S, R, n, H, cfg, st);
+  return launch_one_l<T, RECORD, SUMS, false>(S, R, n, H, cfg, st);
 }
 
 template <typename T>
 hipError_t launch_trace(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const HitsView<T>& H,
-                        const LaunchCfg& cfg, unsigned long long* counter, hipStream_t st) {
+                        const LaunchCfg& cfg, hipStream_t st) {
   bool rec = H.fate || H.nev || H.last_vol || H.x || H.ux || H.opl || H.hash;
   bool sums = H.sums != nullptr;
-  if (rec && sums) return launch_one<T, true, true>(S, R, n, H, cfg, counter, st);
-  if (rec) return launch_one<T, true, false>(S, R, n, H, cfg, counter, st);
-  if (sums) return launch_one<T, false, true>(S, R, n, H, cfg, counter, st);
-  return launch_one<T, true, false>(S, R, n, H, cfg, counter, st);
+  if (rec && sums) return launch_one<T, true, true>(S, R, n, H, cfg, st);
+  if (rec) return launch_one<T, true, false>(S, R, n, H, cfg, st);
+  if (sums) return launch_one<T, false, true>(S, R, n, H, cfg, st);
+  return launch_one<T, true, false>(S, R, n, H, cfg, st);
 }
 
 hipError_t launch_figures(const double* sums, double* fig, int n_groups, hipStream_t st) {
@@ -237,9 +189,8 @@ hipError_t launch_figures(const double* sums, double* fig, int n_groups, hipStre
 }
 
 template hipError_t launch_trace<float>(const SceneView<float>&, const RaysView<float>&, int64_t,
-                                        const HitsView<float>&, const LaunchCfg&, unsigned long long*, hipStream_t);
+                                        const HitsView<float>&, const LaunchCfg&, hipStream_t);
 template hipError_t launch_trace<double>(const SceneView<double>&, const RaysView<double>&, int64_t,
-                                         const HitsView<double>&, const LaunchCfg&, unsigned long long*,
-                                         hipStream_t);
+                                         const HitsView<double>&, const LaunchCfg&, hipStream_t);
 
 }  // namespace robast

@@ -42,7 +42,6 @@ struct LaunchCfg {
   int lds_cap;      // stage the scene blob in LDS when it is at most this many bytes
   int waves_mult;   // persistent grid = CUs x resident blocks per CU x waves_mult
   int max_blocks;   // 0 = no cap
-  int wave_chunk;   // photons a wave takes from the launch's photon counter at a time
 };
 
 // Backward-pass inputs: per-group cotangent coefficients of the objective
@@ -54,10 +53,9 @@ struct AdjView {
   int n_params;
 };
 
-// counter: device int64, the launch's photon counter (reset by the launch)
 template <typename T>
 hipError_t launch_trace(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const HitsView<T>& H,
-                        const LaunchCfg& cfg, unsigned long long* counter, hipStream_t st);
+                        const LaunchCfg& cfg, hipStream_t st);
 hipError_t launch_figures(const double* sums, double* fig, int n_groups, hipStream_t st);
 hipError_t launch_adj_coef(const double* sums, const double* cot, double* coef, int n_groups,
                            hipStream_t st);

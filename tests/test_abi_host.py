@@ -106,7 +106,7 @@ def test_batch_arguments_rejected(rb):
 def test_tuning_arguments_rejected(rb):
     import ctypes
     lib = rb.lib()
-    t = rb.Tuning(1, 128, 256, 1)
+    t = rb.Tuning(1, 128, 1, 0)
     assert lib.robast_get_tuning(None, ctypes.byref(t)) == rb.EINVAL
     assert lib.robast_set_tuning(None, ctypes.byref(t)) == rb.EINVAL
     assert lib.robast_autotune(None, None, 10, None, None) == rb.EINVAL

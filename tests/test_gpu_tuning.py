@@ -1,7 +1,7 @@
 """Launch tuning never changes a photon's result.
 
-Photon binning (counting sort by entrance cell), the per-wave chunk size and
-the grid size only change which lane traces which photon and in which
+Photon binning (counting sort by entrance cell), the cell size and the grid
+size only change which lane traces which photon and in which
 order: every per-photon record must be bit-identical across tunings, group
 sums and gradients equal up to FP64 summation order (1e-12 / 1e-9
 relative).  The binned path is also what the parity tests against the
@@ -15,10 +15,10 @@ import scenes
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-TUNINGS = [dict(bin_photons=0, wave_chunk=256, waves_mult=1),
-           dict(bin_photons=1, wave_chunk=256, waves_mult=1),
-           dict(bin_photons=1, wave_chunk=64, waves_mult=2),
-           dict(bin_photons=1, wave_chunk=4096, waves_mult=1, bin_target=16)]
+TUNINGS = [dict(bin_photons=0, waves_mult=1),
+           dict(bin_photons=1, waves_mult=1),
+           dict(bin_photons=1, waves_mult=2, bin_target=512),
+           dict(bin_photons=1, waves_mult=1, bin_target=16)]
 
 
 @pytest.fixture(scope="module")
@@ -83,7 +83,7 @@ def test_autotune_keeps_results(rb):
     dev.trace(rays, hits=ref)
     best = dev.autotune(rays)
     assert best == dev.tuning
-    assert best["wave_chunk"] >= 64 and best["waves_mult"] >= 1
+    assert best["bin_target"] >= 1 and best["waves_mult"] >= 1
     hits = dev.alloc_hits(n)
     dev.trace(rays, hits=hits)
     torch.cuda.synchronize()
@@ -93,11 +93,10 @@ def test_autotune_keeps_results(rb):
 
 def test_tuning_rejects_out_of_range(rb):
     dev = rb.Scene(scenes.single_mirror())
-    for bad in (dict(wave_chunk=32), dict(wave_chunk=1 << 20), dict(waves_mult=0), dict(waves_mult=9),
-                dict(bin_target=0)):
+    for bad in (dict(bin_target=1 << 20), dict(waves_mult=0), dict(waves_mult=9), dict(bin_target=0)):
         with pytest.raises(rb.RobastError):
             dev.set_tuning(**bad)
-    assert dev.tuning == dict(bin_photons=1, bin_target=128, wave_chunk=256, waves_mult=1)
+    assert dev.tuning == dict(bin_photons=1, bin_target=128, waves_mult=1)
 
 
 def test_kept_order_reused_by_backward(rb):
