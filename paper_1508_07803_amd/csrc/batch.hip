@@ -51,57 +51,49 @@ __device__ __forceinline__ void wave_flush(double* target, int& ag, double* a) {
   }
 }
 
-// Traces photons [start, end) of one variant whose first photon is `off`.
-// Reached by the whole workgroup.
+// Traces photons [start, end) of one variant whose first photon is `off`, a
+// whole photon per lane (consecutive lanes, consecutive binned photons).
+// The lanes' sums stay in registers across items of one group; a lane whose
+// next photon is of another group adds its sums directly.  Reached by the
+// whole workgroup.
 template <bool RECORD>
 __device__ __forceinline__ void trace_item(const SceneView<float>& L, int64_t start, int64_t end, int64_t off,
                                            const RaysView<float>& R, const HitsView<float>& H, double* target,
                                            int& ag, double* a) {
-  int64_t next = start + threadIdx.x;
-  int64_t cur = -1;
-  int g = -1;
-  PhotonState ps;
-  ps.fate = 1;
-  while (true) {
-    bool started = false;
-    if (cur < 0 && next < end) {
-      cur = next;
-      next += blockDim.x;
-      float oa[3], da[3];
-      R.load(cur, oa, da);
-      V3<float> o = {oa[0], oa[1], oa[2]};
-      V3<float> d = {da[0], da[1], da[2]};
-      g = R.grp(cur);
-      if ((unsigned)g >= (unsigned)L.n_groups) g = -1;
-      photon_init(ps, o, d, R.id_base + (uint64_t)(R.src(cur) - off));
-      started = true;
+  for (int64_t cur = start + threadIdx.x; cur < end; cur += blockDim.x) {
+    float oa[3], da[3];
+    R.load(cur, oa, da);
+    int g = R.grp(cur);
+    if ((unsigned)g >= (unsigned)L.n_groups) g = -1;
+    PhotonState ps;
+    photon_init(ps, V3<float>{oa[0], oa[1], oa[2]}, V3<float>{da[0], da[1], da[2]},
+                R.id_base + (uint64_t)(R.src(cur) - off));
+    while (!ps.fate) photon_step(L, ps);
+    PhotonOut<float> r = photon_out<float>(ps);
+    if (RECORD) {
+      const int64_t q = R.src(cur);
+      if (H.fate) H.fate[q] = (uint8_t)r.fate;
+      if (H.nev) H.nev[q] = (uint8_t)r.nev;
+      if (H.last_vol) H.last_vol[q] = r.last_vol;
+      if (H.x) { H.x[q] = r.pos.x; H.y[q] = r.pos.y; H.z[q] = r.pos.z; }
+      if (H.ux) { H.ux[q] = r.dir.x; H.uy[q] = r.dir.y; H.uz[q] = r.dir.z; }
+      if (H.opl) H.opl[q] = r.opl;
+      if (H.hash) H.hash[q] = r.hash;
     }
-    if (!__any(cur >= 0)) break;
-    if (target && __any(started && g >= 0 && ag >= 0 && g != ag)) wave_flush(target, ag, a);
-    if (cur >= 0) {
-      if (!ps.fate) photon_step(L, ps);
-      if (ps.fate) {
-        PhotonOut<float> r = photon_out<float>(ps);
-        if (RECORD) {
-          const int64_t q = R.src(cur);
-          if (H.fate) H.fate[q] = (uint8_t)r.fate;
-          if (H.nev) H.nev[q] = (uint8_t)r.nev;
-          if (H.last_vol) H.last_vol[q] = r.last_vol;
-          if (H.x) { H.x[q] = r.pos.x; H.y[q] = r.pos.y; H.z[q] = r.pos.z; }
-          if (H.ux) { H.ux[q] = r.dir.x; H.uy[q] = r.dir.y; H.uz[q] = r.dir.z; }
-          if (H.opl) H.opl[q] = r.opl;
-          if (H.hash) H.hash[q] = r.hash;
+    if (target && g >= 0) {
+      if (ag >= 0 && g != ag) {
+#pragma unroll
+        for (int k = 0; k < kNSumB; ++k) {
+          if (a[k] != 0.0) atomicAdd(target + ag * 8 + k, a[k]);
+          a[k] = 0.0;
         }
-        if (target && g >= 0) {
-          ag = g;
-          a[0] += 1.0;
-          if (r.fate == FOCUSED) {
-            double x = (double)r.pos.x, y = (double)r.pos.y;
-            a[1] += 1.0; a[2] += x; a[3] += y; a[4] += x * x; a[5] += y * y;
-            a[6] += (double)dabs(r.dir.z);
-          }
-        }
-        cur = -1;
+      }
+      ag = g;
+      a[0] += 1.0;
+      if (r.fate == FOCUSED) {
+        double x = (double)r.pos.x, y = (double)r.pos.y;
+        a[1] += 1.0; a[2] += x; a[3] += y; a[4] += x * x; a[5] += y * y;
+        a[6] += (double)dabs(r.dir.z);
       }
     }
   }

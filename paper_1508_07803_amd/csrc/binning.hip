@@ -31,7 +31,9 @@ constexpr int kScanPerThread = 4;
 constexpr int kScanTile = kBinBlock * kScanPerThread;   // entries per scan block
 constexpr int kMaxCoarse = 2048;                        // LDS counters of the coarse pass
 constexpr int kMaxFineShift = 13;                       // LDS counters of the fine pass: 2^13
-constexpr int64_t kTile = 131072;                       // photons per tile of the coarse pass
+constexpr int64_t kTileMax = 131072;                    // photons per tile of the coarse pass, at most
+constexpr int64_t kTileMin = 4096;                      // and at least
+constexpr int64_t kTilesWanted = 1024;                  // enough workgroups to fill the chip
 
 // bundle of photon i: the last v with offsets[v] <= i (offsets ascending)
 __device__ __forceinline__ int bundle_of(const int64_t* offsets, int n_var, int64_t i) {
@@ -69,12 +71,12 @@ __device__ __forceinline__ uint32_t photon_key(const RaysView<T>& R, int64_t i, 
 // (1) keys and per-tile coarse counts; cnt is bucket-major: cnt[c * n_tiles + tile]
 template <typename T, bool MULTI>
 __global__ void __launch_bounds__(kBinBlock) k_bin_keys(RaysView<T> R, int64_t n, BinGeom geo1, BinMulti multi,
-                                                        int shift, int n_coarse, int n_tiles, uint32_t* key,
-                                                        uint32_t* cnt) {
+                                                        int shift, int n_coarse, int n_tiles, int64_t tile,
+                                                        uint32_t* key, uint32_t* cnt) {
   extern __shared__ uint32_t hist[];
   for (int c = threadIdx.x; c < n_coarse; c += blockDim.x) hist[c] = 0u;
   __syncthreads();
-  const int64_t lo = (int64_t)blockIdx.x * kTile, hi = lo + kTile < n ? lo + kTile : n;
+  const int64_t lo = (int64_t)blockIdx.x * tile, hi = lo + tile < n ? lo + tile : n;
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
     const uint32_t k = photon_key<T, MULTI>(R, i, geo1, multi);
     key[i] = k;
@@ -87,13 +89,13 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_keys(RaysView<T> R, int64_t n
 // (2) each tile scatters its photons to its range of every coarse bucket
 template <typename T>
 __global__ void __launch_bounds__(kBinBlock) k_bin_coarse(RaysView<T> R, int64_t n, int shift, int n_coarse,
-                                                          int n_tiles, const uint32_t* key, const uint32_t* offs,
-                                                          uint32_t* tkey, BinRecord<T>* tmp) {
+                                                          int n_tiles, int64_t tile, const uint32_t* key,
+                                                          const uint32_t* offs, uint32_t* tkey, BinRecord<T>* tmp) {
   static_assert(sizeof(BinRecord<T>) % 16 == 0, "records are written as 16-byte words");
   extern __shared__ uint32_t cursor[];
   for (int c = threadIdx.x; c < n_coarse; c += blockDim.x) cursor[c] = offs[(int64_t)c * n_tiles + blockIdx.x];
   __syncthreads();
-  const int64_t lo = (int64_t)blockIdx.x * kTile, hi = lo + kTile < n ? lo + kTile : n;
+  const int64_t lo = (int64_t)blockIdx.x * tile, hi = lo + tile < n ? lo + tile : n;
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
     const uint32_t k = key[i];
     const uint32_t pos = atomicAdd(cursor + (k >> shift), 1u);
@@ -224,7 +226,8 @@ template <typename T> BinPlan bin_plan(int64_t n, int64_t bins) {
   while ((bins + (int64_t(1) << shift) - 1) >> shift > kMaxCoarse) ++shift;
   p.shift = shift;
   p.n_coarse = (int)((bins + (int64_t(1) << shift) - 1) >> shift);
-  p.n_tiles = (int)((n + kTile - 1) / kTile);
+  p.tile = std::min(kTileMax, std::max(kTileMin, ((n + kTilesWanted - 1) / kTilesWanted + 255) / 256 * 256));
+  p.n_tiles = (int)((n + p.tile - 1) / p.tile);
   p.cnt_entries = (int64_t)p.n_coarse * p.n_tiles;
   p.parts = (p.cnt_entries + kScanTile - 1) / kScanTile;
   size_t off = 0;
@@ -257,15 +260,15 @@ hipError_t launch_binning(const RaysView<T>& R, int64_t n, const BinGeom& geo, c
   const size_t coarse_lds = (size_t)p.n_coarse * 4, fine_lds = ((size_t)1 << p.shift) * 4;
   if (multi.n_var > 0)
     hipLaunchKernelGGL((k_bin_keys<T, true>), dim3(p.n_tiles), dim3(kBinBlock), coarse_lds, st, R, n, geo, multi,
-                       p.shift, p.n_coarse, p.n_tiles, W.key, W.cnt);
+                       p.shift, p.n_coarse, p.n_tiles, p.tile, W.key, W.cnt);
   else
     hipLaunchKernelGGL((k_bin_keys<T, false>), dim3(p.n_tiles), dim3(kBinBlock), coarse_lds, st, R, n, geo, multi,
-                       p.shift, p.n_coarse, p.n_tiles, W.key, W.cnt);
+                       p.shift, p.n_coarse, p.n_tiles, p.tile, W.key, W.cnt);
   hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)p.parts), dim3(kBinBlock), 0, st, W.cnt, p.cnt_entries, W.part);
   hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kBinBlock), 0, st, W.part, (int)p.parts);
   hipLaunchKernelGGL(k_scan_add, dim3((unsigned)p.parts), dim3(kBinBlock), 0, st, W.cnt, p.cnt_entries, W.part);
   hipLaunchKernelGGL(k_bin_coarse<T>, dim3(p.n_tiles), dim3(kBinBlock), coarse_lds, st, R, n, p.shift, p.n_coarse,
-                     p.n_tiles, W.key, W.cnt, W.tkey, W.tmp);
+                     p.n_tiles, p.tile, W.key, W.cnt, W.tkey, W.tmp);
   hipLaunchKernelGGL(k_bin_fine<T>, dim3(p.n_coarse), dim3(kBinBlock), fine_lds, st, n, p.shift, p.n_coarse,
                      p.n_tiles, W.cnt, W.tkey, W.tmp, W.out);
   return hipGetLastError();

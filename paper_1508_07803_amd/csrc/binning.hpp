@@ -38,6 +38,7 @@ struct BinPlan {
   int shift;            // fine digit = key & ((1 << shift) - 1), coarse = key >> shift
   int n_coarse;         // coarse buckets
   int n_tiles;          // photon tiles of the coarse pass
+  int64_t tile;         // photons per tile
   int64_t cnt_entries;  // n_coarse * n_tiles per-tile counts
   int64_t parts;        // scan partials
   size_t key_off, tkey_off, tmp_off, out_off, cnt_off, part_off, bytes;
