@@ -1,0 +1,192 @@
+"""Full benchmark sizes, in the launch configuration bench.py times.
+
+The workloads at their real sizes (Schwarzschild-Couder 16 fields x 1e7,
+Davies-Cotton 5 x 1e7, hex-cone array 91 x 1e6) are traced with binning on,
+exactly as the benchmark does.  The oracle cannot trace them whole, so:
+  * blocks of consecutive photons (start, middle, end of every field) are
+    recomputed by the oracle with their photon ids and compared photon by
+    photon (the parity bar of test_gpu_parity);
+  * properties that hold at any size are checked on the whole bundle: the
+    per-group sums of the perf-mode launch (the benchmark's kernel) equal the
+    sums formed from the per-photon records, and the launched counts are
+    exact;
+  * the adjoint: the gradient of the full-size objective restricted to
+    sampled photons (cotangents from the full-size sums) against the oracle's
+    dual-number gradient of the same photons, and the full-size gradient
+    against the sum of the gradients of two halves.
+"""
+import numpy as np
+import pytest
+
+import scenes
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rb():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1508_07803_amd as rb
+    return rb
+
+
+def device_bundle(sc, npf):
+    parts = [scenes.device_rays(sc, npf, seed=sc.seed + 1000 * g, group=g) for g in range(sc.n_groups)]
+    rays = {k: torch.cat([p[k] for p in parts]) for k in parts[0]}
+    return rays
+
+
+def host_block(rays, start, count):
+    sl = slice(start, start + count)
+    host = {k: rays[k][sl].double().cpu().numpy() for k in ("ox", "oy", "oz", "dx", "dy", "dz")}
+    host["group"] = rays["group"][sl].cpu().numpy().astype(np.uint32)
+    return host
+
+
+def as_numpy(hits, sl):
+    out = {k: hits[k][sl].cpu().numpy() for k in hits}
+    out["seq_hash"] = out["seq_hash"].view(np.uint64)
+    out["pos"] = np.stack([out["x"], out["y"], out["z"]], 1).astype(np.float64)
+    out["dir"] = np.stack([out["ux"], out["uy"], out["uz"]], 1).astype(np.float64)
+    return out
+
+
+def full_trace(rb, sc, rays):
+    n = int(rays["ox"].numel())
+    dev = rb.Scene(sc)
+    hits = {k: torch.empty(n, dtype=dev.dtype, device="cuda") for k in ("x", "y", "z", "ux", "uy", "uz")}
+    hits["fate"] = torch.empty(n, dtype=torch.uint8, device="cuda")
+    hits["n_events"] = torch.empty(n, dtype=torch.uint8, device="cuda")
+    hits["last_vol"] = torch.empty(n, dtype=torch.int32, device="cuda")
+    hits["seq_hash"] = torch.empty(n, dtype=torch.int64, device="cuda")
+    dev.trace(rays, hits=hits)
+    sums = dev.new_sums()
+    dev.trace(rays, sums=sums)          # the perf-mode launch of the benchmark
+    torch.cuda.synchronize()
+    return dev, hits, sums
+
+
+def check_sums_against_records(sc, rays, hits, sums, npf):
+    g = rays["group"].long()
+    foc = hits["fate"] == scenes.FATE_FOCUSED
+    s = sums.view(sc.n_groups, 8).cpu().numpy()
+    assert np.all(s[:, 0] == npf)
+    x, y = hits["x"].double(), hits["y"].double()
+    for k in range(sc.n_groups):
+        m = foc & (g == k)
+        ref = [float(m.sum()), float(x[m].sum()), float(y[m].sum()), float((x[m] ** 2).sum()),
+               float((y[m] ** 2).sum()), float(hits["uz"][m].double().abs().sum())]
+        got = s[k, 1:7]
+        assert got[0] == ref[0], (k, got[0], ref[0])
+        scale = np.maximum(np.abs(ref), 1.0)
+        assert np.all(np.abs(got - ref) <= 1e-9 * scale), (k, got, ref)
+
+
+def sampled_parity(sc, rays, hits, npf, rate):
+    """Blocks of 1000 photons at the start, middle and end of every group;
+    every mismatch must be grazing (checked per block) and their total at
+    most max(3, rate x photons sampled)."""
+    import oracle
+    from test_gpu_parity import compare
+    total_bad = total = 0
+    for g in range(sc.n_groups):
+        for start in (g * npf, g * npf + npf // 2, (g + 1) * npf - 1000):
+            host = host_block(rays, start, 1000)
+            rec = oracle.trace(sc, host, id_base=start, log=True)
+            tol = 1e-5 * sc.l_ref
+            # beyond a concentrator's cut-off angle a block may have no FOCUSED photon
+            nbad, _, _ = compare(sc, host, as_numpy(hits, slice(start, start + 1000)), rec, tol, 1e-5,
+                                 max_rate=1.0, id_base=start, require_focused=False)
+            total_bad += nbad
+            total += 1000
+    print(f"{sc.name}: sampled {total} photons, {total_bad} grazing mismatches")
+    assert total_bad <= max(3, rate * total), f"{total_bad} mismatches of {total}"
+
+
+def test_sc_full_size(rb):
+    sc = scenes.schwarzschild_couder()
+    npf = 10_000_000
+    rays = device_bundle(sc, npf)
+    dev, hits, sums = full_trace(rb, sc, rays)
+    check_sums_against_records(sc, rays, hits, sums, npf)
+    sampled_parity(sc, rays, hits, npf, 1e-5)
+
+
+def test_dc_full_size(rb):
+    sc = scenes.davies_cotton()
+    npf = 10_000_000
+    rays = device_bundle(sc, npf)
+    dev, hits, sums = full_trace(rb, sc, rays)
+    check_sums_against_records(sc, rays, hits, sums, npf)
+    sampled_parity(sc, rays, hits, npf, 1e-5)
+
+
+def test_concentrator_full_size(rb):
+    """91 incidence angles x 1e6 photons (host-generated, the same recipe as
+    the parity tests), up to 32 events, window and walls."""
+    sc = scenes.hex_concentrator()
+    npf = 1_000_000
+    dev0 = rb.Scene(sc)
+    parts = []
+    for g in range(sc.n_groups):
+        parts.append(dev0.upload_rays(sc.rays(npf, seed=sc.seed + 1000 * g, groups=[g])))
+    rays = {k: torch.cat([p[k] for p in parts]) for k in parts[0]}
+    del parts
+    dev, hits, sums = full_trace(rb, sc, rays)
+    check_sums_against_records(sc, rays, hits, sums, npf)
+    # the FP32 cone rims (see test_gpu_parity): grazing mismatches up to 5e-4
+    sampled_parity(sc, rays, hits, npf, 5e-4)
+
+
+def test_sc_full_size_adjoint(rb):
+    """Gradient of the mean RMS over 16 fields x 1e7 photons: restricted to
+    sampled photons against the oracle's dual numbers, and additive over the
+    two halves of the bundle."""
+    import oracle
+    sc = scenes.schwarzschild_couder()
+    npf = 10_000_000
+    rays = device_bundle(sc, npf)
+    n = int(rays["ox"].numel())
+    dev = rb.Scene(sc)
+    sums = dev.new_sums()
+    dev.trace(rays, sums=sums, keep_order=True)
+    cot = torch.zeros(sc.n_groups, 2, dtype=torch.float64, device="cuda")
+    cot[:, 0] = 1.0 / sc.n_groups
+    g_full = torch.zeros(len(sc.params), dtype=torch.float64, device="cuda")
+    dev.backward(rays, sums, cot, g_full)
+    h = n // 2 + 12345
+    g_halves = torch.zeros_like(g_full)
+    dev.backward({k: v[:h] for k, v in rays.items()}, sums, cot, g_halves, n=h)
+    dev.backward({k: v[h:] for k, v in rays.items()}, sums, cot, g_halves, n=n - h, id_base=h)
+    torch.cuda.synchronize()
+    scale = float(g_full.abs().max())
+    assert torch.allclose(g_full, g_halves, rtol=1e-9, atol=1e-12 * scale)
+
+    # sampled photons, cotangents from the full-size figures
+    fig = dev.figures(sums).cpu().numpy()
+    s = sums.view(sc.n_groups, 8).cpu().numpy()
+    nf, cx, cy, rms = s[:, 1], fig[:, 2], fig[:, 3], fig[:, 4]
+    a = (1.0 / sc.n_groups) / (nf * rms)
+    g_gpu = torch.zeros_like(g_full)
+    g_ref = np.zeros(len(sc.params))
+    for g in range(sc.n_groups):
+        start = g * npf + npf // 3
+        sub = {k: v[start:start + 400] for k, v in rays.items()}
+        dev.backward(sub, sums, cot, g_gpu, n=400, id_base=start)
+        host = host_block(rays, start, 400)
+        rec = oracle.trace(sc, host, id_base=start, log=True)
+        foc = rec["fate"] == scenes.FATE_FOCUSED
+        grp = rec["group"].astype(int)
+        cotp = np.stack([a[grp] * (rec["pos"][:, 0] - cx[grp]), a[grp] * (rec["pos"][:, 1] - cy[grp])], 1)
+        for p0 in range(0, len(sc.params), 8):
+            cnt = min(8, len(sc.params) - p0)
+            dpos, _, st = oracle.forced_jac(sc, host, rec, sc.params, p0, cnt)
+            m = foc & (st == 0)
+            g_ref[p0:p0 + cnt] += np.einsum("nk,nkj->j", cotp[m], dpos[m][:, :2, :])
+    torch.cuda.synchronize()
+    got = g_gpu.cpu().numpy()
+    big = np.abs(g_ref).max()
+    err = np.abs(got - g_ref) / np.maximum(np.abs(g_ref), 1e-2 * big)
+    assert err.max() <= 1e-3, (int(np.argmax(err)), got[np.argmax(err)], g_ref[np.argmax(err)])

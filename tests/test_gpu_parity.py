@@ -91,7 +91,7 @@ def grazing(sc, r, idx, ref_hash, id_base=0):
     return g
 
 
-def compare(sc, r, got, ref, pos_tol, dir_tol, max_rate=1e-5, id_base=0):
+def compare(sc, r, got, ref, pos_tol, dir_tol, max_rate=1e-5, id_base=0, require_focused=True):
     n = len(r["ox"])
     same = ((got["fate"] == ref["fate"]) & (got["n_events"] == ref["n_events"]) &
             (got["last_vol"] == ref["last_vol"]) & (got["seq_hash"] == ref["seq_hash"]))
@@ -104,7 +104,7 @@ def compare(sc, r, got, ref, pos_tol, dir_tol, max_rate=1e-5, id_base=0):
             g[~g] = grazing(sc, r, bad[~g], ref["seq_hash"][bad[~g]], id_base)
         assert g.all(), f"non-grazing mismatches at {bad[~g][:10]}"
     foc = same & (ref["fate"] == scenes.FATE_FOCUSED)
-    assert foc.sum() > 0
+    assert foc.sum() > 0 or not require_focused
     # A reflection at incidence |d.n| multiplies the effect of a hit-point
     # error on the exit direction by ~1/|d.n|: paths with a glancing
     # interaction (|d.n| < 0.05) are held to 100x the tolerance.
