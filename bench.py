@@ -64,7 +64,7 @@ SHAPE_NAME = {1: "plane", 2: "sphere", 3: "asphere", 4: "cylinder", 5: "box", 6:
 # sources each kernel is built from (its counters go stale when they change)
 KERNEL_SOURCES = {
     "k_trace": ["device_trace.hpp", "kernels.hip", "kernels.hpp", "scene_layout.hpp"],
-    "k_backward": ["device_trace.hpp", "adjoint_device.hpp", "adjoint.hip", "kernels.hpp", "scene_layout.hpp"],
+    "k_backward_path": ["device_trace.hpp", "adjoint_device.hpp", "adjoint.hip", "kernels.hpp", "scene_layout.hpp"],
 }
 TRAFFIC_SUMMARY = os.path.join("profiles", "k_trace_k_backward_sc_16x1e7_hbm_traffic.md")
 
@@ -95,17 +95,17 @@ def ops_per_photon(scene, rec):
         if m.any():
             per_event[m, k] = event_cost(scene, vol[m, k], act[m, k])
     fwd = per_event.sum(axis=1) + COST["frame"] * (rec["fate"] == 3)
-    # adjoint: the forward search again, then for event e of a FOCUSED photon
-    # the replay of events 0..e (exact intersections, no search) and the
-    # pull-back of event e
-    adj = fwd.copy()
+    # adjoint along the recorded sequence of a FOCUSED photon: each event's
+    # exact intersection, normal and interaction once (the state entering
+    # it) and its pull-back; other photons need nothing
+    adj = np.zeros(n)
     foc = rec["fate"] == 1
     shapes = scene.volumes["shape"]
     for e in range(vol.shape[1]):
         m = foc & (vol[:, e] >= 0)
         if not m.any():
             continue
-        adj[m] += per_event[m, :e + 1].sum(axis=1)
+        adj[m] += per_event[m, e]
         for sh, name in SHAPE_NAME.items():
             adj[m] += PULLBACK[name] * (shapes[vol[m, e]] == sh)
     return float(fwd.mean()), float(adj.mean())
@@ -313,13 +313,13 @@ def main():
         evs[0].record(stream)
         dev.bin_photons(rays)                         # counting sort by entrance cell
         evs[1].record(stream)
-        dev.trace(rays, sums=sums, keep_order=do_bwd)
+        dev.trace(rays, sums=sums, keep_order=do_bwd)    # + path records for the adjoint
         evs[2].record(stream)
         dev.figures(sums, fig=fig)
         grad.zero_()
         evs[3].record(stream)
         if do_bwd:
-            dev.backward(rays, sums, cot, grad)      # reuses the binned order
+            dev.backward(rays, sums, cot, grad)      # binned order and paths of the trace
         evs[4].record(stream)
 
     for i in range(args.warmup):
@@ -369,8 +369,8 @@ def main():
     t_trace, t_bwd = float(np.mean(k_trace)), float(np.mean(k_bwd))
     rk = {"k_trace": roof(ops_fwd, t_trace, measured_traffic("k_trace"))}
     if do_bwd:
-        rk["k_backward"] = roof(ops_adj, t_bwd, measured_traffic("k_backward"))
-    dominant = "k_backward" if do_bwd and t_bwd > t_trace else "k_trace"
+        rk["k_backward_path"] = roof(ops_adj, t_bwd, measured_traffic("k_backward_path"))
+    dominant = "k_backward_path" if do_bwd and t_bwd > t_trace else "k_trace"
     out = {
         "metric": "traced photons/s (2-mirror SC, 1e7 rays); batched fwd+adjoint vs plain, 1 GPU",
         "value": n / (ms_per_step / 1e3),

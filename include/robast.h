@@ -157,7 +157,15 @@ int robast_build_scene(const robast_scene_desc* desc, const double* params, int6
  * pointers, id_base and n; the caller guarantees that the photon arrays were
  * not written in between.  It stays kept after a trace call with this flag
  * and is dropped by any other call that bins, by a backward call that used
- * it, by a parameter update and by the autotuner. */
+ * it, by a parameter update and by the autotuner.
+ * The call also records each photon's path (its surface sequence, when
+ * FOCUSED with at most 4 events; 20 bytes per photon of scene-owned memory,
+ * grown by hipMalloc like the binning workspace, n < 2^32).  The next
+ * backward call, if it is the next call on the scene after this trace and is
+ * given the same arrays, id_base and n, replays the recorded sequences
+ * instead of searching for them again (longer sequences are still found by
+ * a search).  Any other call drops the record: trace, bin, update, tuning,
+ * autotune, and the backward call that used it. */
 #define ROBAST_TRACE_KEEP_ORDER 1u
 
 /* Trace photons [0, n).  rays/hits as above; n == 0 is a no-op.  EINVAL on
@@ -178,7 +186,9 @@ int robast_figures(robast_scene* scene, const double* d_group_sums, double* d_fi
 
 /* Reverse mode along each photon's fixed surface sequence (pathwise
  * gradient; fates and sequences are re-derived with the same draws, so they
- * equal the forward ones).  The objective is
+ * equal the forward ones, or read from the path record of the preceding
+ * ROBAST_TRACE_KEEP_ORDER trace; the gradient is the same either way up to
+ * FP64 summation order).  The objective is
  *   L = sum_g ( w_rms[g] * RMS_g + w_eff[g] * effw_g )
  * with d_cot [device] n_groups * 2 doubles {w_rms, w_eff} per group and
  * d_group_sums [device] the forward sums of the same photons.

@@ -233,8 +233,10 @@ class Scene:
     def trace(self, rays, n=None, hits=None, sums=None, id_base=0, stream=None, keep_order=False):
         """Trace n photons; writes the given hit tensors and/or accumulates sums.
 
-        keep_order: keep the binned photon order for the next backward call
-        on the same photon tensors (which must not be modified in between).
+        keep_order: keep the binned photon order, and each photon's path
+        record, for the next backward call on the same photon tensors (which
+        must not be modified in between): that call then replays the
+        recorded surface sequences instead of searching for them again.
         """
         n = int(rays["ox"].numel()) if n is None else int(n)
         hits = hits or {}

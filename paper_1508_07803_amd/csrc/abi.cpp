@@ -177,6 +177,13 @@ struct robast_scene {
   robast_rays kept_rays{};
   int64_t kept_n = 0;
   void* kept_records = nullptr;
+  // path records of the last trace that kept its order (one-shot, like the
+  // order): kPathSlots words per photon, then the long-record list and count
+  void* d_path = nullptr;
+  int64_t path_cap = 0;
+  bool path_ok = false, path_binned = false;
+  robast_rays path_rays{};
+  int64_t path_n = 0;
 };
 
 // LDS a workgroup may use for a scene's tables: three workgroups of four
@@ -806,12 +813,14 @@ bool same_rays(const robast_rays& a, const robast_rays& b) {
 // afterwards it stays kept only if `keep` (a backward call passes false).
 template <typename T>
 int binned_view(robast_scene* s, const robast_rays* rays, int64_t n, hipStream_t st, RaysView<T>& out,
-                bool keep) {
+                bool keep, bool* reused = nullptr) {
   const RaysView<T> R = rays_view<T>(rays);
   out = R;
+  if (reused) *reused = false;
   if (!s->tuning.bin_photons || n < kBinMin || n > (int64_t)UINT32_MAX) return ROBAST_OK;
   if (s->kept && s->kept_n == n && same_rays(s->kept_rays, *rays)) {
     s->kept = keep;
+    if (reused) *reused = true;
     out = binned_rays<T>((const BinRecord<T>*)s->kept_records, rays->group != nullptr, rays->id_base);
     return ROBAST_OK;
   }
@@ -846,24 +855,70 @@ int binned_view(robast_scene* s, const robast_rays* rays, int64_t n, hipStream_t
   return ROBAST_OK;
 }
 
-template <typename T>
-int trace_t(robast_scene* s, const SceneView<T>& V, const robast_rays* rays, int64_t n, const robast_hits* hits,
-            bool keep, hipStream_t st) {
-  RaysView<T> R;
-  int rc = binned_view<T>(s, rays, n, st, R, keep);
-  if (rc) return rc;
-  hipError_t e = launch_trace<T>(V, R, n, hits_view<T>(hits), s->cfg, st);
-  if (e != hipSuccess) return hip_fail(e, "trace launch");
+// Path-record buffer for n photons: records, long-record list, count.
+size_t path_bytes(int64_t n) {
+  return align256((size_t)n * kPathSlots * 4) + align256((size_t)n * 4) + 256;
+}
+
+PathView path_view(const robast_scene* s) {
+  char* base = (char*)s->d_path;
+  const size_t rec = align256((size_t)s->path_cap * kPathSlots * 4);
+  const size_t list = align256((size_t)s->path_cap * 4);
+  return PathView{(const uint32_t*)base, (uint32_t*)(base + rec), (uint32_t*)(base + rec + list)};
+}
+
+int ensure_path(robast_scene* s, int64_t n) {
+  if (n <= s->path_cap) return ROBAST_OK;
+  if (s->d_path) (void)hipFree(s->d_path);
+  s->d_path = nullptr;
+  s->path_cap = 0;
+  hipError_t e = hipMalloc(&s->d_path, path_bytes(n));
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(ROBAST_ENOMEM, "hipMalloc path records")
+                                                       : hip_fail(e, "hipMalloc path records");
+  s->path_cap = n;
   return ROBAST_OK;
 }
 
 template <typename T>
+int trace_t(robast_scene* s, const SceneView<T>& V, const robast_rays* rays, int64_t n, const robast_hits* hits,
+            bool keep, hipStream_t st) {
+  s->path_ok = false;
+  RaysView<T> R;
+  int rc = binned_view<T>(s, rays, n, st, R, keep);
+  if (rc) return rc;
+  HitsView<T> H = hits_view<T>(hits);
+  if (keep && n <= (int64_t)UINT32_MAX) {
+    rc = ensure_path(s, n);
+    if (rc) return rc;
+    H.path = const_cast<uint32_t*>(path_view(s).rec);
+  }
+  hipError_t e = launch_trace<T>(V, R, n, H, s->cfg, st);
+  if (e != hipSuccess) return hip_fail(e, "trace launch");
+  if (H.path) {
+    s->path_ok = true;
+    s->path_binned = R.perm != nullptr;
+    s->path_rays = *rays;
+    s->path_n = n;
+  }
+  return ROBAST_OK;
+}
+
+// The backward call replays the path records of the preceding trace when
+// that trace kept its order for the same arrays (and the photons are read
+// in that same order); otherwise it traces the photons again.
+template <typename T>
 int backward_t(robast_scene* s, const SceneView<T>& V, const robast_rays* rays, int64_t n, const AdjView& A,
                hipStream_t st) {
   RaysView<T> R;
-  int rc = binned_view<T>(s, rays, n, st, R, false);
+  bool reused = false;
+  int rc = binned_view<T>(s, rays, n, st, R, false, &reused);
   if (rc) return rc;
-  hipError_t e = launch_backward<T>(V, R, n, A, s->cfg, st);
+  const bool binned = R.perm != nullptr;
+  const bool use_path = s->path_ok && s->path_n == n && same_rays(s->path_rays, *rays) &&
+                        binned == s->path_binned && (!binned || reused);
+  s->path_ok = false;
+  const PathView P = use_path ? path_view(s) : PathView{};
+  hipError_t e = launch_backward<T>(V, R, n, A, s->cfg, st, use_path ? &P : nullptr);
   if (e != hipSuccess) return hip_fail(e, "backward launch");
   return ROBAST_OK;
 }
@@ -952,6 +1007,7 @@ int robast_update_params(robast_scene* s, const double* params, int64_t n_params
   s->params.assign(params, params + n_params);
   for (auto& v : s->desc) apply_params(v, s->params);
   s->kept = false;
+  s->path_ok = false;
   return upload(s);
 }
 
@@ -962,6 +1018,7 @@ void robast_destroy_scene(robast_scene* s) {
   if (s->d_coef) (void)hipFree(s->d_coef);
   if (s->d_view) (void)hipFree(s->d_view);
   if (s->d_work) (void)hipFree(s->d_work);
+  if (s->d_path) (void)hipFree(s->d_path);
   delete s;
 }
 
@@ -1010,6 +1067,7 @@ int robast_bin_photons(robast_scene* s, const robast_rays* rays, int64_t n, void
   int rc = check_rays(rays);
   if (rc) return rc;
   s->kept = false;
+  s->path_ok = false;
   hipStream_t st = (hipStream_t)stream;
   if (s->precision == 32) {
     RaysView<float> R;
@@ -1030,6 +1088,7 @@ int robast_set_tuning(robast_scene* s, const robast_tuning* t) {
   if (!tuning_valid(*t)) return fail(ROBAST_EINVAL, "tuning field out of range");
   s->tuning = *t;
   apply_tuning(s);
+  s->path_ok = false;
   return ROBAST_OK;
 }
 
@@ -1040,6 +1099,7 @@ int robast_autotune(robast_scene* s, const robast_rays* rays, int64_t n, robast_
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   s->kept = false;
+  s->path_ok = false;
   double* sums = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipMalloc(&sums, sizeof(double) * 8 * s->n_groups);

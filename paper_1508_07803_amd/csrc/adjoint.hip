@@ -38,89 +38,181 @@ __global__ void k_adj_coef(const double* sums, const double* cot, double* coef, 
   coef[4 * g + 0] = a; coef[4 * g + 1] = cx; coef[4 * g + 2] = cy; coef[4 * g + 3] = b;
 }
 
-// FP32 kernels with up to 16 events are held to 3 waves per SIMD (<= 168
-// VGPRs, no spills; the unconstrained allocation gives 2).
-template <typename T, int MAXE, bool USE_LDS>
-__global__ void __launch_bounds__(kBlockAdj)
-__attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && MAXE <= 16) ? 3 : 1, 8))) k_backward(SceneView<T> S, RaysView<T> R, int64_t n, AdjView A,
-                                                         int grad_in_lds) {
-  extern __shared__ __align__(16) char lds[];
-  SceneView<T> L;
+// Stages the scene blob into LDS (when USE_LDS) and returns the view of it.
+template <typename T, bool USE_LDS>
+__device__ __forceinline__ void stage_adj_scene(const SceneView<T>& S, SceneView<T>& L, char* lds) {
   L = S;
-  if (USE_LDS) {
-    const uint4* src = reinterpret_cast<const uint4*>(S.blob);
-    uint4* dst = reinterpret_cast<uint4*>(lds);
-    for (uint32_t i = threadIdx.x; i < S.blob_bytes / 16u; i += blockDim.x) dst[i] = src[i];
-    const char* base = S.blob;
-    L.vol = reinterpret_cast<const DVol<T>*>(lds);
-    L.always = reinterpret_cast<const uint16_t*>(lds + (reinterpret_cast<const char*>(S.always) - base));
-    L.cell_start = reinterpret_cast<const uint32_t*>(lds + (reinterpret_cast<const char*>(S.cell_start) - base));
-    L.items = reinterpret_cast<const uint16_t*>(lds + (reinterpret_cast<const char*>(S.items) - base));
+  if (!USE_LDS) return;
+  const uint4* src = reinterpret_cast<const uint4*>(S.blob);
+  uint4* dst = reinterpret_cast<uint4*>(lds);
+  for (uint32_t i = threadIdx.x; i < S.blob_bytes / 16u; i += blockDim.x) dst[i] = src[i];
+  const char* base = S.blob;
+  L.vol = reinterpret_cast<const DVol<T>*>(lds);
+  L.always = reinterpret_cast<const uint16_t*>(lds + (reinterpret_cast<const char*>(S.always) - base));
+  L.cell_start = reinterpret_cast<const uint32_t*>(lds + (reinterpret_cast<const char*>(S.cell_start) - base));
+  L.items = reinterpret_cast<const uint16_t*>(lds + (reinterpret_cast<const char*>(S.items) - base));
   L.groups = reinterpret_cast<const GroupRec<T>*>(lds + (reinterpret_cast<const char*>(S.groups) - base));
-  }
-  double* gacc = reinterpret_cast<double*>(lds + (USE_LDS ? ((S.blob_bytes + 15u) & ~15u) : 0u));
-  if (grad_in_lds)
-    for (int i = threadIdx.x; i < A.n_params; i += blockDim.x) gacc[i] = 0.0;
-  __syncthreads();
-  GradSink gs{grad_in_lds ? gacc : A.grad};
+}
 
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    adjoint_photon<T, MAXE>(L, R, i, A, gs);
-  }
-  if (grad_in_lds) {
-    __syncthreads();
-    for (int i = threadIdx.x; i < A.n_params; i += blockDim.x)
-      if (gacc[i] != 0.0) atomicAdd(A.grad + i, gacc[i]);
+// Gradient partials of a workgroup are summed in LDS in `copies` (a power of
+// two) interleaved copies of the parameter vector, `pstride` doubles apart:
+// lane l adds to copy l mod copies, so lanes of a wave that hit the same
+// surface (the common case once photons are binned) contend for one address
+// copies times less.  copies == 0: partials go straight to global memory.
+struct GradLds {
+  int copies, pstride;
+};
+
+__device__ __forceinline__ GradSink grad_begin(double* gacc, const GradLds& G, const AdjView& A) {
+  if (G.copies > 0)
+    for (int i = threadIdx.x; i < G.copies * G.pstride; i += blockDim.x) gacc[i] = 0.0;
+  __syncthreads();
+  return GradSink{G.copies > 0 ? gacc + (threadIdx.x & (G.copies - 1)) * G.pstride : A.grad};
+}
+
+__device__ __forceinline__ void grad_end(const double* gacc, const GradLds& G, const AdjView& A) {
+  if (G.copies == 0) return;
+  __syncthreads();
+  for (int i = threadIdx.x; i < A.n_params; i += blockDim.x) {
+    double v = 0.0;
+    for (int c = 0; c < G.copies; ++c) v += gacc[c * G.pstride + i];
+    if (v != 0.0) atomicAdd(A.grad + i, v);
   }
 }
+
+// FP32 kernels with up to 16 events are held to 3 waves per SIMD (<= 168
+// VGPRs, no spills; the unconstrained allocation gives 2).  With `list` the
+// kernel takes only the photons at the positions list[0 .. *count) (those
+// whose path record was too long); otherwise every photon of the bundle.
+template <typename T, int MAXE, bool USE_LDS>
+__global__ void __launch_bounds__(kBlockAdj)
+__attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && MAXE <= 16) ? 3 : 1, 8)))
+k_backward(SceneView<T> S, RaysView<T> R, int64_t n, AdjView A, GradLds G, const uint32_t* list,
+           const uint32_t* count) {
+  extern __shared__ __align__(16) char lds[];
+  SceneView<T> L;
+  stage_adj_scene<T, USE_LDS>(S, L, lds);
+  double* gacc = reinterpret_cast<double*>(lds + (USE_LDS ? ((S.blob_bytes + 15u) & ~15u) : 0u));
+  GradSink gs = grad_begin(gacc, G, A);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t m = list ? (int64_t)*count : n;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) {
+    const int64_t i = list ? (int64_t)list[j] : j;
+    adjoint_photon<T, MAXE>(L, R, i, A, gs);
+  }
+  grad_end(gacc, G, A);
+}
+
+// Adjoint from the forward trace's path records: photons with a record of
+// their sequence are swept without a search; those whose record is too long
+// are appended to a list (one atomic per wave) for k_backward.
+template <typename T, bool USE_LDS>
+__global__ void __launch_bounds__(kBlockAdj)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1, 8)))
+k_backward_path(SceneView<T> S, RaysView<T> R, int64_t n, AdjView A, GradLds G, PathView P) {
+  extern __shared__ __align__(16) char lds[];
+  SceneView<T> L;
+  stage_adj_scene<T, USE_LDS>(S, L, lds);
+  double* gacc = reinterpret_cast<double*>(lds + (USE_LDS ? ((S.blob_bytes + 15u) & ~15u) : 0u));
+  GradSink gs = grad_begin(gacc, G, A);
+  const uint4* rec = reinterpret_cast<const uint4*>(P.rec);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const uint4 w = rec[i];
+    const bool is_long = w.x == kPathLong;
+    const uint64_t mask = __ballot(is_long);
+    if (mask) {
+      const int leader = __ffsll((unsigned long long)mask) - 1;
+      uint32_t base = 0;
+      if ((int)__lane_id() == leader) base = atomicAdd(P.count, (uint32_t)__popcll(mask));
+      base = __shfl(base, leader);
+      const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+      if (is_long) P.list[base + below] = (uint32_t)i;
+    }
+    if (w.x >= kPathLong) continue;
+    adjoint_photon_path<T>(L, R, i, A, gs, w);
+  }
+  grad_end(gacc, G, A);
+}
+
+__global__ void k_clear_u32(uint32_t* p) { *p = 0u; }
 
 hipError_t launch_adj_coef(const double* sums, const double* cot, double* coef, int n_groups, hipStream_t st) {
   hipLaunchKernelGGL(k_adj_coef, dim3((n_groups + 63) / 64), dim3(64), 0, st, sums, cot, coef, n_groups);
   return hipGetLastError();
 }
 
-template <typename T, int MAXE, bool USE_LDS>
-static hipError_t launch_bwd_l(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const AdjView& A,
-                               const LaunchCfg& cfg, hipStream_t st) {
+// LDS bytes of a launch: the scene blob (when staged) and the gradient
+// copies, as many (up to 16) as fit beside the blob within the LDS cap, at
+// least one while the parameter vector is at most 16 KiB.
+static size_t grad_layout(size_t blob_lds, int n_params, int lds_cap, GradLds& G) {
+  G.pstride = n_params | 1;   // odd: the copies start in different banks
+  const size_t one = (size_t)G.pstride * sizeof(double);
+  G.copies = 0;
+  if ((size_t)n_params * sizeof(double) <= 16384) {
+    G.copies = 1;
+    while (G.copies < 16 && blob_lds + 2 * G.copies * one <= (size_t)lds_cap) G.copies *= 2;
+  }
+  return blob_lds + (size_t)G.copies * one;
+}
+
+template <typename K>
+static hipError_t grid_for(K kernel, size_t shmem, int64_t n, const LaunchCfg& cfg, int& blocks) {
   int dev = 0, ncu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  const bool use_lds = USE_LDS;
-  size_t gbytes = (size_t)A.n_params * sizeof(double);
-  bool grad_lds = gbytes <= 16384;
-  size_t shmem = (use_lds ? ((S.blob_bytes + 15u) & ~15u) : 0u) + (grad_lds ? gbytes : 0);
   int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_backward<T, MAXE, USE_LDS>, kBlockAdj, shmem);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlockAdj, shmem);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
-  int64_t want = (n + kBlockAdj - 1) / kBlockAdj;
-  int64_t cap = (int64_t)ncu * per_cu * (cfg.waves_mult > 0 ? cfg.waves_mult : 1);
-  int blocks = (int)std::max<int64_t>(1, std::min(want, cap));
-  hipLaunchKernelGGL((k_backward<T, MAXE, USE_LDS>), dim3(blocks), dim3(kBlockAdj), shmem, st, S, R, n, A,
-                     grad_lds ? 1 : 0);
+  const int64_t want = (n + kBlockAdj - 1) / kBlockAdj;
+  const int64_t cap = (int64_t)ncu * per_cu * (cfg.waves_mult > 0 ? cfg.waves_mult : 1);
+  blocks = (int)std::max<int64_t>(1, std::min(want, cap));
+  return hipSuccess;
+}
+
+template <typename T, int MAXE, bool USE_LDS>
+static hipError_t launch_bwd_l(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const AdjView& A,
+                               const LaunchCfg& cfg, hipStream_t st, const PathView* P) {
+  GradLds G;
+  const size_t shmem = grad_layout(USE_LDS ? ((S.blob_bytes + 15u) & ~15u) : 0u, A.n_params, cfg.lds_cap, G);
+  int blocks = 0;
+  hipError_t e;
+  if (P) {
+    hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(1), 0, st, P->count);
+    e = grid_for(k_backward_path<T, USE_LDS>, shmem, n, cfg, blocks);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_backward_path<T, USE_LDS>), dim3(blocks), dim3(kBlockAdj), shmem, st, S, R, n, A, G, *P);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  e = grid_for(k_backward<T, MAXE, USE_LDS>, shmem, n, cfg, blocks);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_backward<T, MAXE, USE_LDS>), dim3(blocks), dim3(kBlockAdj), shmem, st, S, R, n, A, G,
+                     P ? P->list : nullptr, P ? P->count : nullptr);
   return hipGetLastError();
 }
 
 template <typename T, int MAXE>
 static hipError_t launch_bwd(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const AdjView& A,
-                             const LaunchCfg& cfg, hipStream_t st) {
-  if (cfg.lds_cap > 0 && S.blob_bytes <= (uint32_t)cfg.lds_cap) return launch_bwd_l<T, MAXE, true>(S, R, n, A, cfg, st);
-  return launch_bwd_l<T, MAXE, false>(S, R, n, A, cfg, st);
+                             const LaunchCfg& cfg, hipStream_t st, const PathView* P) {
+  if (cfg.lds_cap > 0 && S.blob_bytes <= (uint32_t)cfg.lds_cap)
+    return launch_bwd_l<T, MAXE, true>(S, R, n, A, cfg, st, P);
+  return launch_bwd_l<T, MAXE, false>(S, R, n, A, cfg, st, P);
 }
 
 template <typename T>
 hipError_t launch_backward(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const AdjView& A,
-                           const LaunchCfg& cfg, hipStream_t st) {
-  if (S.max_events <= 16) return launch_bwd<T, 16>(S, R, n, A, cfg, st);
-  if (S.max_events <= 32) return launch_bwd<T, 32>(S, R, n, A, cfg, st);
-  return launch_bwd<T, 64>(S, R, n, A, cfg, st);
+                           const LaunchCfg& cfg, hipStream_t st, const PathView* P) {
+  if (S.max_events <= 16) return launch_bwd<T, 16>(S, R, n, A, cfg, st, P);
+  if (S.max_events <= 32) return launch_bwd<T, 32>(S, R, n, A, cfg, st, P);
+  return launch_bwd<T, 64>(S, R, n, A, cfg, st, P);
 }
 
 template hipError_t launch_backward<float>(const SceneView<float>&, const RaysView<float>&, int64_t,
-                                           const AdjView&, const LaunchCfg&, hipStream_t);
+                                           const AdjView&, const LaunchCfg&, hipStream_t, const PathView*);
 template hipError_t launch_backward<double>(const SceneView<double>&, const RaysView<double>&, int64_t,
-                                            const AdjView&, const LaunchCfg&, hipStream_t);
+                                            const AdjView&, const LaunchCfg&, hipStream_t, const PathView*);
 
 }  // namespace robast

@@ -256,59 +256,159 @@ __device__ __forceinline__ void event_adjoint(const DVol<T>& v, const DTilt* til
   db = dbar;
 }
 
-// Reverse sweep of one photon: replays its forward search (same draws) to
-// record its sequence, then pulls the objective's cotangents back to the
-// parameters.  Returns without effect for photons that are not FOCUSED.
+// Reverse sweep along a photon's recorded sequence of `nev` events (codes
+// vol << 8 | face << 4 | action) from its initial ray.  The state entering
+// event e is recomputed by replaying events 0..e-1 (one exact intersection
+// each, no search).  The objective's cotangents start at the last event:
+// those of the final position (rounded to T like the photon's record) and of
+// the sign of its final direction.  Returns false if a replayed intersection
+// no longer yields the recorded (volume, face), which an unchanged scene
+// cannot produce; the photon then adds nothing further.
+template <typename T>
+__device__ __forceinline__ bool reverse_sweep(const SceneView<T>& L, const AdjView& A, GradSink& gs,
+                                              const double* cf, V3<T> o0, V3<T> d0, const uint32_t* codes,
+                                              int nev) {
+  const V3<double> O0 = {(double)o0.x, (double)o0.y, (double)o0.z};
+  const V3<double> D0 = {(double)d0.x, (double)d0.y, (double)d0.z};
+  V3<double> Xb = {0.0, 0.0, 0.0}, db = {0.0, 0.0, 0.0};
+  for (int e = nev - 1; e >= 0; --e) {
+    // state entering event e, replayed along the recorded sequence
+    V3<double> O = O0;
+    V3<double> d = D0;
+    int pv = -1, pf = -1, ps = 0;
+    for (int j = 0; j < e; ++j) {
+      const int vid = (int)(codes[j] >> 8), face = (int)((codes[j] >> 4) & 15u), act = (int)(codes[j] & 15u);
+      double t, s;
+      if (!replay_root(L, vid, face, O, d, pv, pf, ps, t, s)) return false;
+      const DVol<T>& v = L.vol[vid];
+      V3<double> X = {O.x + t * d.x, O.y + t * d.y, O.z + t * d.z};
+      V3<double> nrm = front_normal(v, face, X, s);
+      int back;
+      apply_action(v, nrm, act, d, back);
+      O = X; pv = vid; pf = face; ps = back ^ (act == ACT_REFRACT ? 1 : 0);
+    }
+    const int vid = (int)(codes[e] >> 8), face = (int)((codes[e] >> 4) & 15u), act = (int)(codes[e] & 15u);
+    double t, s;
+    if (!replay_root(L, vid, face, O, d, pv, pf, ps, t, s)) return false;
+    if (e == nev - 1) {
+      const V3<double> X = {O.x + t * d.x, O.y + t * d.y, O.z + t * d.z};
+      V3<double> dout = d;
+      if (act == ACT_REFLECT || act == ACT_REFRACT) {
+        int back;
+        apply_action(L.vol[vid], front_normal(L.vol[vid], face, X, s), act, dout, back);
+      }
+      Xb = {cf[0] * ((double)(T)X.x - cf[1]), cf[0] * ((double)(T)X.y - cf[2]), 0.0};
+      db = {0.0, 0.0, (T)dout.z >= T(0) ? cf[3] : -cf[3]};
+    }
+    // the pull-back runs in FP64 from the replayed state: the per-photon
+    // partials are summed with cancellation (centroid-subtracted
+    // cotangents), which FP32 arithmetic would not resolve
+    DVol<double> vd = promote(L.vol[vid]);
+    event_adjoint<double>(vd, A.tilt + vid, face, act, O, d, t, s, Xb, db, gs);
+  }
+  return true;
+}
+
+// Adjoint of one photon whose sequence is not recorded: its forward search
+// is run again with the same draws (so its fate and sequence equal the
+// forward ones) and the sequence is swept in reverse.  Photons that are not
+// FOCUSED add nothing.
 template <typename T, int MAXE>
 __device__ __forceinline__ void adjoint_photon(const SceneView<T>& L, const RaysView<T>& R, int64_t i,
                                                const AdjView& A, GradSink& gs) {
-  do {
-      int g = R.grp(i);
-      if ((unsigned)g >= (unsigned)L.n_groups) return;
-      const double* cf = A.coef + 4 * g;
-      T ca = (T)cf[0], cb = (T)cf[3];
-      if (ca == T(0) && cb == T(0)) return;
-      T oa[3], da[3];
-      R.load(i, oa, da);
-      V3<T> o0 = {oa[0], oa[1], oa[2]};
-      V3<T> d0 = {da[0], da[1], da[2]};
-      uint64_t id = R.id_base + (uint64_t)R.src(i);
-      uint32_t codes[MAXE];
-      PhotonOut<T> r = trace_photon<T, MAXE>(L, o0, d0, id, codes);
-      if (r.fate != FOCUSED || r.nev > MAXE) return;
-      V3<double> Xb = {cf[0] * ((double)r.pos.x - cf[1]), cf[0] * ((double)r.pos.y - cf[2]), 0.0};
-      V3<double> db = {0.0, 0.0, r.dir.z >= T(0) ? cf[3] : -cf[3]};
-      const V3<double> O0 = {(double)o0.x, (double)o0.y, (double)o0.z};
-      const V3<double> D0 = {(double)d0.x, (double)d0.y, (double)d0.z};
-      for (int e = r.nev - 1; e >= 0; --e) {
-        // state entering event e, replayed along the recorded sequence
-        V3<double> O = O0;
-        V3<double> d = D0;
-        int pv = -1, pf = -1, ps = 0;
-        bool ok = true;
-        for (int j = 0; j < e && ok; ++j) {
-          int vid = (int)(codes[j] >> 8), face = (int)((codes[j] >> 4) & 15u), act = (int)(codes[j] & 15u);
-          double t, s;
-          ok = replay_root(L, vid, face, O, d, pv, pf, ps, t, s);
-          if (!ok) break;
-          const DVol<T>& v = L.vol[vid];
-          V3<double> X = {O.x + t * d.x, O.y + t * d.y, O.z + t * d.z};
-          V3<double> nrm = front_normal(v, face, X, s);
-          int back;
-          apply_action(v, nrm, act, d, back);
-          O = X; pv = vid; pf = face; ps = back ^ (act == ACT_REFRACT ? 1 : 0);
-        }
-        int vid = (int)(codes[e] >> 8), face = (int)((codes[e] >> 4) & 15u), act = (int)(codes[e] & 15u);
-        double t, s;
-        if (!ok || !replay_root(L, vid, face, O, d, pv, pf, ps, t, s)) break;
-        // the pull-back runs in FP64 from the replayed state: the per-photon
-        // partials are summed with cancellation (centroid-subtracted
-        // cotangents), which FP32 arithmetic would not resolve
-        DVol<double> vd = promote(L.vol[vid]);
-        event_adjoint<double>(vd, A.tilt + vid, face, act, O, d, t, s, Xb, db, gs);
+  const int g = R.grp(i);
+  if ((unsigned)g >= (unsigned)L.n_groups) return;
+  const double* cf = A.coef + 4 * g;
+  if ((T)cf[0] == T(0) && (T)cf[3] == T(0)) return;
+  T oa[3], da[3];
+  R.load(i, oa, da);
+  const V3<T> o0 = {oa[0], oa[1], oa[2]};
+  const V3<T> d0 = {da[0], da[1], da[2]};
+  uint32_t codes[MAXE];
+  PhotonOut<T> r = trace_photon<T, MAXE>(L, o0, d0, R.id_base + (uint64_t)R.src(i), codes);
+  if (r.fate != FOCUSED || r.nev > MAXE) return;
+  (void)reverse_sweep<T>(L, A, gs, cf, o0, d0, codes, r.nev);
+}
+
+#ifndef ROBAST_PATH_SWEEP
+#define ROBAST_PATH_SWEEP 1
+#endif
+
+// State entering an event of a recorded path: origin, direction, and the
+// root (distance, cone wall parameter) of the event's intersection.
+struct PathState {
+  V3<double> O, d;
+  double t, s;
+};
+
+// Adjoint of one photon from its path record (see kPathSlots): no search.
+// The states entering the (at most kPathSlots) events are replayed once,
+// forward, and kept in registers; the reverse sweep then reads them back.
+template <typename T>
+__device__ __forceinline__ void adjoint_photon_path(const SceneView<T>& L, const RaysView<T>& R, int64_t i,
+                                                    const AdjView& A, GradSink& gs, uint4 w) {
+  const int g = R.grp(i);
+  if ((unsigned)g >= (unsigned)L.n_groups) return;
+  const double* cf = A.coef + 4 * g;
+  if ((T)cf[0] == T(0) && (T)cf[3] == T(0)) return;
+  T oa[3], da[3];
+  R.load(i, oa, da);
+  const uint32_t codes[kPathSlots] = {w.x, w.y, w.z, w.w};
+  const int nev = w.y == kPathEnd ? 1 : w.z == kPathEnd ? 2 : w.w == kPathEnd ? 3 : 4;
+#if ROBAST_PATH_SWEEP == 0
+  (void)reverse_sweep<T>(L, A, gs, cf, V3<T>{oa[0], oa[1], oa[2]}, V3<T>{da[0], da[1], da[2]}, codes, nev);
+#else
+  PathState st[kPathSlots];
+  V3<double> O = {(double)oa[0], (double)oa[1], (double)oa[2]};
+  V3<double> d = {(double)da[0], (double)da[1], (double)da[2]};
+  int pv = -1, pf = -1, ps = 0;
+#pragma unroll
+  for (int e = 0; e < kPathSlots; ++e) {
+    if (e < nev) {
+      const int vid = (int)(codes[e] >> 8), face = (int)((codes[e] >> 4) & 15u), act = (int)(codes[e] & 15u);
+      double t, s;
+      // a replayed intersection that no longer yields the recorded face
+      // (impossible for an unchanged scene): the photon adds nothing
+      if (!replay_root(L, vid, face, O, d, pv, pf, ps, t, s)) return;
+      st[e] = PathState{O, d, t, s};
+      const DVol<T>& v = L.vol[vid];
+      const V3<double> X = {O.x + t * d.x, O.y + t * d.y, O.z + t * d.z};
+      if (act == ACT_REFLECT || act == ACT_REFRACT) {
+        int back;
+        apply_action(v, front_normal(v, face, X, s), act, d, back);
+        ps = back ^ (act == ACT_REFRACT ? 1 : 0);
+      } else {
+        ps = dot(d, front_normal(v, face, X, s)) < 0.0 ? 0 : 1;
       }
-  
-  } while (false);
+      O = X; pv = vid; pf = face;
+    }
+  }
+  // cotangents of the final position (rounded to T like the photon's record)
+  // and of the sign of the final direction
+  V3<double> Xb = {cf[0] * ((double)(T)O.x - cf[1]), cf[0] * ((double)(T)O.y - cf[2]), 0.0};
+  V3<double> db = {0.0, 0.0, (T)d.z >= T(0) ? cf[3] : -cf[3]};
+#if ROBAST_PATH_SWEEP == 1
+#pragma unroll
+  for (int e = kPathSlots - 1; e >= 0; --e) {
+    if (e < nev) {
+      const int vid = (int)(codes[e] >> 8), face = (int)((codes[e] >> 4) & 15u), act = (int)(codes[e] & 15u);
+      DVol<double> vd = promote(L.vol[vid]);
+      event_adjoint<double>(vd, A.tilt + vid, face, act, st[e].O, st[e].d, st[e].t, st[e].s, Xb, db, gs);
+    }
+  }
+#else
+  for (int e = nev - 1; e >= 0; --e) {
+    PathState c = st[0];
+#pragma unroll
+    for (int k = 1; k < kPathSlots; ++k)
+      if (e == k) c = st[k];
+    const uint32_t code = e == 0 ? codes[0] : e == 1 ? codes[1] : e == 2 ? codes[2] : codes[3];
+    const int vid = (int)(code >> 8), face = (int)((code >> 4) & 15u), act = (int)(code & 15u);
+    DVol<double> vd = promote(L.vol[vid]);
+    event_adjoint<double>(vd, A.tilt + vid, face, act, c.O, c.d, c.t, c.s, Xb, db, gs);
+  }
+#endif
+#endif
 }
 
 }  // namespace robast

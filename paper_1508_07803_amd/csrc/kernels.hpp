@@ -29,6 +29,17 @@ template <typename T> struct RaysView {
   __device__ __forceinline__ int64_t src(int64_t i) const { return perm ? (int64_t)perm[i * ustride] : i; }
 };
 
+// Path record of a photon, written by a forward trace for the adjoint that
+// follows it: four words per photon, indexed by the photon's position in the
+// traced order.  A FOCUSED photon with at most kPathSlots events stores its
+// event codes (vol << 8 | face << 4 | action) followed by kPathEnd; any other
+// photon stores kPathSkip (not FOCUSED: no gradient) or kPathLong (FOCUSED
+// with more events: its sequence is found again by a full trace) in word 0.
+constexpr int kPathSlots = 4;
+constexpr uint32_t kPathEnd = 0xffffffffu;
+constexpr uint32_t kPathSkip = 0xfffffffeu;
+constexpr uint32_t kPathLong = 0xfffffffdu;
+
 template <typename T> struct HitsView {
   uint8_t* fate;
   uint8_t* nev;
@@ -36,6 +47,7 @@ template <typename T> struct HitsView {
   T *x, *y, *z, *ux, *uy, *uz, *opl;
   uint64_t* hash;
   double* sums;
+  uint32_t* path;   // kPathSlots words per photon, or null
 };
 
 struct LaunchCfg {
@@ -53,14 +65,25 @@ struct AdjView {
   int n_params;
 };
 
+// Path records of the forward trace for the adjoint, and the list of the
+// photons whose record is kPathLong (positions in the traced order, with
+// their count; the count is cleared by the backward launch).
+struct PathView {
+  const uint32_t* rec;
+  uint32_t* list;
+  uint32_t* count;
+};
+
 template <typename T>
 hipError_t launch_trace(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const HitsView<T>& H,
                         const LaunchCfg& cfg, hipStream_t st);
 hipError_t launch_figures(const double* sums, double* fig, int n_groups, hipStream_t st);
 hipError_t launch_adj_coef(const double* sums, const double* cot, double* coef, int n_groups,
                            hipStream_t st);
+// With `P` (non-null) the photons' sequences are read from the forward
+// trace's path records instead of being found again by a search.
 template <typename T>
 hipError_t launch_backward(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const AdjView& A,
-                           const LaunchCfg& cfg, hipStream_t st);
+                           const LaunchCfg& cfg, hipStream_t st, const PathView* P = nullptr);
 
 }  // namespace robast

@@ -26,21 +26,29 @@ def rb():
 
 
 def gpu_grad(rb, sc, r, w_rms=None, w_eff=None, id_base=0):
+    """Gradient by both backward modes: after a plain trace (sequences found
+    again by a search) and after a trace that keeps its order (sequences
+    replayed from the path records).  They must agree to FP64 summation
+    order; the path-record gradient is returned."""
     dev = rb.Scene(sc)
     rays = dev.upload_rays(r)
-    sums = dev.new_sums()
-    dev.trace(rays, sums=sums, id_base=id_base)
     cot = torch.zeros(sc.n_groups, 2, dtype=torch.float64, device="cuda")
     if w_rms is not None:
         cot[:, 0] = torch.as_tensor(w_rms, dtype=torch.float64)
     if w_eff is not None:
         cot[:, 1] = torch.as_tensor(w_eff, dtype=torch.float64)
-    grad = torch.zeros(len(sc.params), dtype=torch.float64, device="cuda")
-    dev.backward(rays, sums, cot, grad, id_base=id_base)
-    torch.cuda.synchronize()
-    out = grad.cpu().numpy()
+    out = []
+    for keep in (False, True):
+        sums = dev.new_sums()
+        dev.trace(rays, sums=sums, id_base=id_base, keep_order=keep)
+        grad = torch.zeros(len(sc.params), dtype=torch.float64, device="cuda")
+        dev.backward(rays, sums, cot, grad, id_base=id_base)
+        torch.cuda.synchronize()
+        out.append(grad.cpu().numpy())
     dev.close()
-    return out
+    scale = np.abs(out[0]).max()
+    assert np.allclose(out[1], out[0], rtol=1e-9, atol=1e-12 * scale), np.abs(out[1] - out[0]).max() / scale
+    return out[1]
 
 
 def check(g, ref, floor, names):
