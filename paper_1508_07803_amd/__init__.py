@@ -159,6 +159,42 @@ def _rays_struct(rays, id_base=0, offset=0):
                 (g.data_ptr() + offset * g.element_size()) if g is not None else None, id_base + offset)
 
 
+_HIT_ITEM = {"fate": 1, "n_events": 1, "last_vol": 4, "seq_hash": 8}
+
+
+def _check_extents(n, dtype, rays=None, hits=None, f64=()):
+    """The C ABI takes plain pointers: extents and element types of the
+    tensors a call reads or writes are checked here, before any launch."""
+    import torch
+    if rays is not None:
+        for k in ("ox", "oy", "oz", "dx", "dy", "dz"):
+            t = rays[k]
+            if t.dtype != dtype:
+                raise ValueError(f"rays[{k!r}] is {t.dtype}, the scene computes in {dtype}")
+            if t.numel() < n:
+                raise ValueError(f"rays[{k!r}] holds {t.numel()} < {n} photons")
+        g = rays.get("group")
+        if g is not None and (g.element_size() != 4 or g.dtype.is_floating_point or g.numel() < n):
+            raise ValueError(f"rays['group'] must hold >= {n} 32-bit integers")
+    for k, t in (hits or {}).items():
+        if t is None or k not in _HIT_KEYS:
+            continue
+        if k in _HIT_ITEM:
+            if t.element_size() != _HIT_ITEM[k] or t.dtype.is_floating_point:
+                raise ValueError(f"hits[{k!r}] must be {8 * _HIT_ITEM[k]}-bit integers")
+        elif t.dtype != dtype:
+            raise ValueError(f"hits[{k!r}] is {t.dtype}, the scene computes in {dtype}")
+        if t.numel() < n:
+            raise ValueError(f"hits[{k!r}] holds {t.numel()} < {n} photons")
+    for name, t, need in f64:     # FP64 buffers: (name, tensor, values needed)
+        if t is None:
+            continue
+        if t.dtype != torch.float64:
+            raise ValueError(f"{name} must be float64")
+        if t.numel() < need:
+            raise ValueError(f"{name} holds {t.numel()} < {need} values")
+
+
 def _hits_struct(hits, sums):
     hits = hits or {}
     return Hits(*[(hits[k].data_ptr() if hits.get(k) is not None else None) for k in _HIT_KEYS],
@@ -240,6 +276,7 @@ class Scene:
         """
         n = int(rays["ox"].numel()) if n is None else int(n)
         hits = hits or {}
+        _check_extents(n, self.dtype, rays, hits, [("sums", sums, self.n_groups * GROUP_STRIDE)])
         H = _hits_struct(hits, sums)
         R = self._rays_struct(rays, id_base)
         flags = TRACE_KEEP_ORDER if keep_order else 0
@@ -250,6 +287,7 @@ class Scene:
     def bin_photons(self, rays, n=None, id_base=0, stream=None):
         """Bin the photons now and keep the order for the next trace / backward calls."""
         n = int(rays["ox"].numel()) if n is None else int(n)
+        _check_extents(n, self.dtype, rays)
         R = self._rays_struct(rays, id_base)
         _check(_lib.robast_bin_photons(self._h, ctypes.byref(R), n, _stream(stream)), "robast_bin_photons")
 
@@ -257,12 +295,16 @@ class Scene:
         import torch
         if fig is None:
             fig = torch.zeros(self.n_groups * FIGURE_STRIDE, dtype=torch.float64, device=sums.device)
+        _check_extents(0, None, f64=[("sums", sums, self.n_groups * GROUP_STRIDE),
+                                     ("fig", fig, self.n_groups * FIGURE_STRIDE)])
         _check(_lib.robast_figures(self._h, _ptr(sums), _ptr(fig), _stream(stream)), "robast_figures")
         return fig.view(self.n_groups, FIGURE_STRIDE)
 
     def backward(self, rays, sums, cot, grad, n=None, id_base=0, stream=None):
         """Accumulate dL/dparams into grad for L = sum_g cot[g,0] RMS_g + cot[g,1] effw_g."""
         n = int(rays["ox"].numel()) if n is None else int(n)
+        _check_extents(n, self.dtype, rays, f64=[("sums", sums, self.n_groups * GROUP_STRIDE),
+                                                 ("cot", cot, self.n_groups * 2), ("grad", grad, self.n_params)])
         R = self._rays_struct(rays, id_base)
         _check(_lib.robast_trace_backward(self._h, ctypes.byref(R), n, _ptr(sums), _ptr(cot), _ptr(grad),
                                           _stream(stream)), "robast_trace_backward")
@@ -288,6 +330,7 @@ class Scene:
     def autotune(self, rays, n=None, stream=None):
         """Time candidate launch parameters on these photons; keeps and returns the fastest."""
         n = int(rays["ox"].numel()) if n is None else int(n)
+        _check_extents(n, self.dtype, rays)
         R = self._rays_struct(rays, 0)
         t = Tuning()
         _check(_lib.robast_autotune(self._h, ctypes.byref(R), n, ctypes.byref(t), _stream(stream)),
@@ -350,17 +393,10 @@ class Batch:
         return torch.zeros(self.n_groups * GROUP_STRIDE, dtype=torch.float64, device=device)
 
     def _check_sizes(self, rays, hits=None, sums=None, grad=None, cot=None):
-        # the C ABI takes plain pointers: the extents are checked here
-        for k in ("ox", "oy", "oz", "dx", "dy", "dz", "group"):
-            if rays.get(k) is not None and rays[k].numel() < self.n_photons:
-                raise ValueError(f"rays[{k!r}] holds {rays[k].numel()} < {self.n_photons} photons")
-        for k, t in (hits or {}).items():
-            if t is not None and k in _HIT_KEYS and t.numel() < self.n_photons:
-                raise ValueError(f"hits[{k!r}] holds {t.numel()} < {self.n_photons} photons")
-        for name, t, need in (("sums", sums, self.n_groups * GROUP_STRIDE), ("grad", grad, self.n_params),
-                              ("cot", cot, self.n_groups * 2)):
-            if t is not None and t.numel() < need:
-                raise ValueError(f"{name} holds {t.numel()} < {need} values")
+        import torch
+        _check_extents(self.n_photons, torch.float32, rays, hits,
+                       [("sums", sums, self.n_groups * GROUP_STRIDE), ("cot", cot, self.n_groups * 2),
+                        ("grad", grad, self.n_params)])
 
     def trace(self, rays, hits=None, sums=None, id_base=0, stream=None, keep_order=False):
         self._check_sizes(rays, hits, sums)
@@ -375,6 +411,8 @@ class Batch:
         import torch
         if fig is None:
             fig = torch.zeros(self.n_groups * FIGURE_STRIDE, dtype=torch.float64, device=sums.device)
+        _check_extents(0, None, f64=[("sums", sums, self.n_groups * GROUP_STRIDE),
+                                     ("fig", fig, self.n_groups * FIGURE_STRIDE)])
         _check(_lib.robast_figures_batch(self._h, _ptr(sums), _ptr(fig), _stream(stream)), "robast_figures_batch")
         return fig.view(self.n_groups, FIGURE_STRIDE)
 

@@ -208,6 +208,10 @@ struct robast_batch {
   void* d_work = nullptr;
   bool kept = false;
   robast_rays kept_rays{};
+  // path records of the last forward launch that kept its order (one-shot)
+  uint32_t* d_path = nullptr;
+  bool path_ok = false;
+  robast_rays path_rays{};
 };
 
 namespace {
@@ -925,11 +929,14 @@ int backward_t(robast_scene* s, const SceneView<T>& V, const robast_rays* rays, 
 
 // The photons a batched launch reads: the caller's arrays or their binned
 // copy (kept order reused when given the same arrays).
-int batch_binned_view(robast_batch* b, const robast_rays* rays, hipStream_t st, bool keep, RaysView<float>& out) {
+int batch_binned_view(robast_batch* b, const robast_rays* rays, hipStream_t st, bool keep, RaysView<float>& out,
+                      bool* reused = nullptr) {
   out = rays_view<float>(rays);
+  if (reused) *reused = false;
   if (!b->bin) return ROBAST_OK;
   const BinPlan plan = bin_plan<float>(b->n_photons, b->bins);
   const BinWork<float> W = bin_carve<float>(plan, b->d_work);
+  if (reused) *reused = b->kept && same_rays(b->kept_rays, *rays);
   if (!(b->kept && same_rays(b->kept_rays, *rays))) {
     const BinMulti multi{b->d_offsets, b->d_geo, (int)b->scenes.size()};
     hipError_t e = launch_binning<float>(out, b->n_photons, BinGeom{}, multi, plan, W, st);
@@ -949,6 +956,7 @@ void free_batch(robast_batch* b) {
   if (b->d_offsets) (void)hipFree(b->d_offsets);
   if (b->d_geo) (void)hipFree(b->d_geo);
   if (b->d_work) (void)hipFree(b->d_work);
+  if (b->d_path) (void)hipFree(b->d_path);
   delete b;
 }
 
@@ -1198,6 +1206,8 @@ int robast_build_batch(robast_scene* const* scenes, int32_t n_scenes, const int6
   if (e == hipSuccess) e = hipMalloc(&b->d_items, sizeof(BatchItem) * std::max<size_t>(1, items.size()));
   if (e == hipSuccess) e = hipMalloc(&b->d_queue, kQueueCounters * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMalloc(&b->d_coef, sizeof(double) * 4 * std::max<int64_t>(1, b->n_groups));
+  if (e == hipSuccess && b->n_photons <= (int64_t)UINT32_MAX)
+    e = hipMalloc(&b->d_path, (size_t)std::max<int64_t>(1, b->n_photons) * kPathSlots * sizeof(uint32_t));
   if (e != hipSuccess) {
     free_batch(b);
     return fail(ROBAST_ENOMEM, "hipMalloc batch tables");
@@ -1255,11 +1265,19 @@ int robast_trace_batch(robast_batch* b, const robast_rays* rays, const robast_hi
   int rc = check_rays(rays);
   if (!rc) rc = check_hits(hits);
   if (rc) return rc;
+  const bool keep = (flags & ROBAST_TRACE_KEEP_ORDER) != 0;
+  b->path_ok = false;
   RaysView<float> R;
-  rc = batch_binned_view(b, rays, (hipStream_t)stream, (flags & ROBAST_TRACE_KEEP_ORDER) != 0, R);
+  rc = batch_binned_view(b, rays, (hipStream_t)stream, keep, R);
   if (rc) return rc;
-  hipError_t e = launch_trace_batch(batch_view<float>(b), R, hits_view<float>(hits), (hipStream_t)stream);
+  HitsView<float> H = hits_view<float>(hits);
+  if (keep) H.path = b->d_path;
+  hipError_t e = launch_trace_batch(batch_view<float>(b), R, H, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "batched trace launch");
+  if (H.path) {
+    b->path_ok = true;
+    b->path_rays = *rays;
+  }
   return ROBAST_OK;
 }
 
@@ -1281,9 +1299,14 @@ int robast_trace_backward_batch(robast_batch* b, const robast_rays* rays, const 
   hipError_t e = launch_adj_coef(sums, cot, b->d_coef, (int)b->n_groups, st);
   if (e != hipSuccess) return hip_fail(e, "coefficient launch");
   RaysView<float> R;
-  rc = batch_binned_view(b, rays, st, false, R);
+  bool reused = false;
+  rc = batch_binned_view(b, rays, st, false, R, &reused);
   if (rc) return rc;
-  e = launch_backward_batch(batch_view<float>(b), R, b->d_coef, grad, st);
+  // replay the path records of the preceding forward launch if it kept its
+  // order for these arrays (and the photons are read in that order)
+  const bool use_path = b->path_ok && same_rays(b->path_rays, *rays) && (!b->bin || reused);
+  b->path_ok = false;
+  e = launch_backward_batch(batch_view<float>(b), R, b->d_coef, grad, st, use_path ? b->d_path : nullptr);
   if (e != hipSuccess) return hip_fail(e, "batched backward launch");
   return ROBAST_OK;
 }

@@ -1,9 +1,9 @@
 // Batched forward trace: many scene variants in one persistent launch.
 //
-// Inside a work item the lanes trace with event-level refill exactly like
-// the single-scene kernel and number photons from the variant's first
-// photon, so every photon's result equals that of a single-scene call on its
-// variant.  Per-lane FP64 figure sums are reduced across the wave per group
+// Inside a work item each lane traces whole photons exactly like the
+// single-scene kernel and numbers them from the variant's first photon, so
+// every photon's result (and path record) equals that of a single-scene call
+// on its variant.  Per-lane FP64 figure sums are reduced across the wave per group
 // before one atomic per wave and sum.
 #include <hip/hip_runtime.h>
 
@@ -59,7 +59,7 @@ __device__ __forceinline__ void wave_flush(double* target, int& ag, double* a) {
 template <bool RECORD>
 __device__ __forceinline__ void trace_item(const SceneView<float>& L, int64_t start, int64_t end, int64_t off,
                                            const RaysView<float>& R, const HitsView<float>& H, double* target,
-                                           int& ag, double* a) {
+                                           int& ag, double* a, uint32_t* long_flag) {
   for (int64_t cur = start + threadIdx.x; cur < end; cur += blockDim.x) {
     float oa[3], da[3];
     R.load(cur, oa, da);
@@ -68,8 +68,22 @@ __device__ __forceinline__ void trace_item(const SceneView<float>& L, int64_t st
     PhotonState ps;
     photon_init(ps, V3<float>{oa[0], oa[1], oa[2]}, V3<float>{da[0], da[1], da[2]},
                 R.id_base + (uint64_t)(R.src(cur) - off));
-    while (!ps.fate) photon_step(L, ps);
+    while (!ps.fate) {
+      const int k = ps.k;
+      const uint32_t code = photon_step(L, ps);
+      if (H.path && k < kPathSlots) H.path[cur * kPathSlots + k] = code;
+    }
     PhotonOut<float> r = photon_out<float>(ps);
+    if (H.path) {
+      uint32_t* w = H.path + cur * kPathSlots;
+      const bool is_long = r.fate == FOCUSED && r.nev > kPathSlots;
+      if (r.fate != FOCUSED) w[0] = kPathSkip;
+      else if (is_long) w[0] = kPathLong;
+      else
+        for (int k = r.nev; k < kPathSlots; ++k) w[k] = kPathEnd;
+      const unsigned long long m = __ballot(is_long);
+      if (m && (int)__lane_id() == __ffsll(m) - 1) atomicOr(long_flag, 1u);
+    }
     if (RECORD) {
       const int64_t q = R.src(cur);
       if (H.fate) H.fate[q] = (uint8_t)r.fate;
@@ -116,7 +130,7 @@ k_trace_batch(const BatchVariant<float>* vars, const BatchItem* items, int n_ite
 #pragma unroll
   for (int k = 0; k < kNSumB; ++k) a[k] = 0.0;
   int ag = -1;
-  uint32_t* counter = queue + (USE_LDS ? 0 : 1);
+  uint32_t* counter = queue + (USE_LDS ? kQFwdLds : kQFwdGlobal);
   while (true) {
     const int item = next_item(counter, &s_item);
     const BatchItem it = item < n_items ? load_uniform(items + item) : BatchItem{0, 0, -1};
@@ -140,7 +154,8 @@ k_trace_batch(const BatchVariant<float>* vars, const BatchItem* items, int n_ite
       }
     }
     double* target = H.sums ? H.sums + (int64_t)bv.goff * 8 : nullptr;
-    trace_item<RECORD>(USE_LDS ? L : S, it.start, it.start + it.count, bv.off, R, H, target, ag, a);
+    trace_item<RECORD>(USE_LDS ? L : S, it.start, it.start + it.count, bv.off, R, H, target, ag, a,
+                       queue + kQLongFlag);
     if (target) acc_v = it.v;
     // a change of variant overwrites LDS: every wave must be done with it
     __syncthreads();
@@ -183,7 +198,7 @@ hipError_t launch_trace_batch(const BatchView<float>& B, const RaysView<float>& 
   int ncu = 0;
   hipError_t e = cu_count(ncu);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, B.queue, 0, 2);
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, B.queue, kQFwdLds, kQLongFlag - kQFwdLds + 1);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const bool rec = H.fate || H.nev || H.last_vol || H.x || H.ux || H.opl || H.hash;

@@ -28,8 +28,14 @@ struct BatchItem {
   int32_t v;
 };
 
-// Work counters: forward (LDS kernel, global kernel), adjoint (LDS, global).
-constexpr int kQueueCounters = 4;
+// Device counters of a batch: work queues of the forward kernels (LDS,
+// global), a flag set by the forward launch when some photon's path record
+// is too long (kPathLong), and the work queues of the adjoint kernels (LDS,
+// global) and of its pass over the long records (LDS, global).  The forward
+// launch clears [kQFwdLds, kQLongFlag], the adjoint [kQBwdLds, kQLongGlobal].
+constexpr int kQFwdLds = 0, kQFwdGlobal = 1, kQLongFlag = 2;
+constexpr int kQBwdLds = 3, kQBwdGlobal = 4, kQLongLds = 5, kQLongGlobal = 6;
+constexpr int kQueueCounters = 8;
 
 template <typename T> struct BatchView {
   const BatchVariant<T>* vars;   // device
@@ -45,7 +51,10 @@ template <typename T> struct BatchView {
 // Batched launches are built for FP32 scenes (the sweep precision).
 hipError_t launch_trace_batch(const BatchView<float>& B, const RaysView<float>& R, const HitsView<float>& H,
                               hipStream_t st);
+// With `path` (the forward launch's path records, non-null) the sequences
+// are replayed from the records; photons whose record is too long are
+// found again by a search.
 hipError_t launch_backward_batch(const BatchView<float>& B, const RaysView<float>& R, const double* coef,
-                                 double* grad, hipStream_t st);
+                                 double* grad, hipStream_t st, const uint32_t* path = nullptr);
 
 }  // namespace robast

@@ -1,11 +1,12 @@
 // Batched adjoint: the reverse sweep of many scene variants in one
 // persistent launch.
 //
-// Each photon is processed exactly as by the single-scene adjoint kernel
-// (forward search replayed with the same draws, reverse sweep along the
-// recorded sequence), with the variant's photons indexed and numbered from
-// its first photon.  Gradients are summed per workgroup in LDS (FP64) and
-// added to the variant's slice of the concatenated gradient when the
+// Each photon is processed exactly as by the single-scene adjoint kernels
+// (replayed from the forward launch's path record, or its forward search
+// run again with the same draws, then the reverse sweep along the sequence),
+// with the variant's photons indexed and numbered from its first photon.
+// Gradients are summed per workgroup in LDS (FP64) and added to the
+// variant's slice of the concatenated gradient when the
 // workgroup moves to another variant.
 #include <hip/hip_runtime.h>
 
@@ -20,18 +21,28 @@ namespace robast {
 
 constexpr uint32_t kGradLdsMax = 16384;   // gradient sums kept in LDS up to this size
 
+// Photon selection of a batched adjoint launch: every photon, searched
+// again (kSearchAll); only the photons whose path record is kPathLong,
+// searched again (kSearchLong; the launch ends at once when the forward
+// launch flagged none); every photon with a path record, replayed from it
+// (kReplay).
+constexpr int kSearchAll = 0, kSearchLong = 1, kReplay = 2;
+
 // Per-variant state (view, tilt table, slices) is re-derived from the
 // variant table for every item rather than carried across items, which
 // keeps it out of the registers the adjoint itself needs.
-template <bool USE_LDS, int MAXE>
+template <bool USE_LDS, int MAXE, int MODE>
 __global__ void __launch_bounds__(kBlockB) __attribute__((amdgpu_waves_per_eu(MAXE <= 16 ? 3 : 1, 8)))
 k_backward_batch(const BatchVariant<float>* vars, const BatchItem* items, int n_items, uint32_t* queue,
-                 uint32_t blob_cap, int grad_in_lds, RaysView<float> R, const double* coef, double* grad) {
+                 uint32_t blob_cap, int grad_in_lds, RaysView<float> R, const double* coef, double* grad,
+                 const uint32_t* path) {
   extern __shared__ __align__(16) char lds[];
   __shared__ int s_item;
+  if (MODE == kSearchLong && queue[kQLongFlag] == 0u) return;
   double* gacc = reinterpret_cast<double*>(lds + (USE_LDS ? blob_cap : 0u));
   int cur_v = -1;   // variant whose partial gradient sits in gacc (-1: none)
-  uint32_t* counter = queue + (USE_LDS ? 2 : 3);
+  uint32_t* counter = queue + (MODE == kSearchLong ? (USE_LDS ? kQLongLds : kQLongGlobal)
+                                                   : (USE_LDS ? kQBwdLds : kQBwdGlobal));
   while (true) {
     const int item = next_item(counter, &s_item);
     const BatchItem it = item < n_items ? load_uniform(items + item) : BatchItem{0, 0, -1};
@@ -74,51 +85,67 @@ k_backward_batch(const BatchVariant<float>* vars, const BatchItem* items, int n_
       Rv.id_base = R.id_base - (uint64_t)off;
     }
     const int64_t lo = it.start - off, hi = it.start - off + it.count;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x)
-      adjoint_photon<float, MAXE>(USE_LDS ? L : S, Rv, i, A, gs);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+      // path records are indexed by position in the whole bundle
+      if (MODE == kReplay) {
+        const uint4 w = reinterpret_cast<const uint4*>(path)[off + i];
+        if (w.x < kPathLong) adjoint_photon_path<float>(USE_LDS ? L : S, Rv, i, A, gs, w);
+      } else if (MODE == kSearchAll || path[(off + i) * kPathSlots] == kPathLong) {
+        adjoint_photon<float, MAXE>(USE_LDS ? L : S, Rv, i, A, gs);
+      }
+    }
     // a change of variant overwrites LDS: every wave must be done with it
     __syncthreads();
   }
 }
 
 // ------------------------------------------------------------------ launcher
-template <bool USE_LDS, int MAXE>
+template <bool USE_LDS, int MAXE, int MODE>
 static hipError_t backward_batch_k(const BatchView<float>& B, const RaysView<float>& R, const double* coef,
-                                   double* grad, int ncu, hipStream_t st) {
+                                   double* grad, int ncu, hipStream_t st, const uint32_t* path) {
   const size_t gbytes = (size_t)B.max_params * sizeof(double);
   const bool grad_lds = gbytes <= kGradLdsMax;
   const size_t shmem = (USE_LDS ? B.blob_cap_bwd : 0) + (grad_lds ? gbytes : 0);
   int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_backward_batch<USE_LDS, MAXE>, kBlockB,
-                                                              shmem);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_backward_batch<USE_LDS, MAXE, MODE>,
+                                                              kBlockB, shmem);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
   const int blocks = std::max(1, std::min(B.n_items, ncu * per_cu));
-  hipLaunchKernelGGL((k_backward_batch<USE_LDS, MAXE>), dim3(blocks), dim3(kBlockB), shmem, st, B.vars, B.items,
-                     B.n_items, B.queue, B.blob_cap_bwd, grad_lds ? 1 : 0, R, coef, grad);
+  hipLaunchKernelGGL((k_backward_batch<USE_LDS, MAXE, MODE>), dim3(blocks), dim3(kBlockB), shmem, st, B.vars,
+                     B.items, B.n_items, B.queue, B.blob_cap_bwd, grad_lds ? 1 : 0, R, coef, grad, path);
   return hipGetLastError();
 }
 
-template <int MAXE>
+template <int MAXE, int MODE>
 static hipError_t backward_batch_e(const BatchView<float>& B, const RaysView<float>& R, const double* coef,
-                                   double* grad, int ncu, hipStream_t st) {
+                                   double* grad, int ncu, hipStream_t st, const uint32_t* path) {
   hipError_t e = hipSuccess;
-  if (B.blob_cap_bwd > 0) e = backward_batch_k<true, MAXE>(B, R, coef, grad, ncu, st);
-  if (e == hipSuccess) e = backward_batch_k<false, MAXE>(B, R, coef, grad, ncu, st);
+  if (B.blob_cap_bwd > 0) e = backward_batch_k<true, MAXE, MODE>(B, R, coef, grad, ncu, st, path);
+  if (e == hipSuccess) e = backward_batch_k<false, MAXE, MODE>(B, R, coef, grad, ncu, st, path);
+  return e;
+}
+
+template <int MAXE>
+static hipError_t backward_batch_m(const BatchView<float>& B, const RaysView<float>& R, const double* coef,
+                                   double* grad, int ncu, hipStream_t st, const uint32_t* path) {
+  if (!path) return backward_batch_e<MAXE, kSearchAll>(B, R, coef, grad, ncu, st, nullptr);
+  hipError_t e = backward_batch_e<16, kReplay>(B, R, coef, grad, ncu, st, path);
+  if (e == hipSuccess) e = backward_batch_e<MAXE, kSearchLong>(B, R, coef, grad, ncu, st, path);
   return e;
 }
 
 hipError_t launch_backward_batch(const BatchView<float>& B, const RaysView<float>& R, const double* coef,
-                                 double* grad, hipStream_t st) {
+                                 double* grad, hipStream_t st, const uint32_t* path) {
   int dev = 0, ncu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
   if (B.max_events > 32) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, B.queue, 2, 2);
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, B.queue, kQBwdLds, kQLongGlobal - kQBwdLds + 1);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (B.max_events <= 16) return backward_batch_e<16>(B, R, coef, grad, ncu, st);
-  return backward_batch_e<32>(B, R, coef, grad, ncu, st);
+  if (B.max_events <= 16) return backward_batch_m<16>(B, R, coef, grad, ncu, st, path);
+  return backward_batch_m<32>(B, R, coef, grad, ncu, st, path);
 }
 
 }  // namespace robast

@@ -110,3 +110,34 @@ def test_tuning_arguments_rejected(rb):
     assert lib.robast_get_tuning(None, ctypes.byref(t)) == rb.EINVAL
     assert lib.robast_set_tuning(None, ctypes.byref(t)) == rb.EINVAL
     assert lib.robast_autotune(None, None, 10, None, None) == rb.EINVAL
+
+
+def test_binding_checks_extents_before_launch(rb):
+    """The C ABI takes plain pointers, so the binding checks every tensor a
+    call reads or writes against the photon count and the scene sizes
+    (CPU tensors: the checks run before anything reaches the library)."""
+    import torch
+    f32 = torch.float32
+    n = 100
+    rays = {k: torch.zeros(n, dtype=f32) for k in ("ox", "oy", "oz", "dx", "dy", "dz")}
+    rays["group"] = torch.zeros(n, dtype=torch.int32)
+    hits = {"fate": torch.zeros(n, dtype=torch.uint8), "x": torch.zeros(n, dtype=f32),
+            "seq_hash": torch.zeros(n, dtype=torch.int64)}
+    sums = torch.zeros(16, dtype=torch.float64)
+    rb._check_extents(n, f32, rays, hits, [("sums", sums, 16)])          # consistent: no error
+    bad_cases = [
+        dict(n=n + 1),                                                   # more photons than the arrays hold
+        dict(rays={**rays, "dz": torch.zeros(n - 1, dtype=f32)}),
+        dict(rays={**rays, "ox": torch.zeros(n, dtype=torch.float64)}),   # wrong precision
+        dict(rays={**rays, "group": torch.zeros(n, dtype=torch.int64)}),
+        dict(hits={**hits, "x": torch.zeros(n - 1, dtype=f32)}),
+        dict(hits={**hits, "fate": torch.zeros(n, dtype=torch.int32)}),
+        dict(hits={**hits, "seq_hash": torch.zeros(n, dtype=torch.float64)}),
+        dict(f64=[("sums", sums, 17)]),
+        dict(f64=[("sums", sums.float(), 16)]),
+    ]
+    for case in bad_cases:
+        args = dict(n=n, rays=rays, hits=hits, f64=[("sums", sums, 16)])
+        args.update(case)
+        with pytest.raises(ValueError):
+            rb._check_extents(args["n"], f32, args["rays"], args["hits"], args["f64"])

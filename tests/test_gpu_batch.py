@@ -96,7 +96,7 @@ def test_batch_equals_per_variant_bitwise(rb, kind):
 
 
 @pytest.mark.parametrize("counts,keep", [([5000, 2500, 1, 0, 7000], False), ([40000, 2500, 1, 0, 35000], False),
-                                         ([40000, 2500, 1, 0, 35000], True)])
+                                         ([5000, 2500, 1, 0, 7000], True), ([40000, 2500, 1, 0, 35000], True)])
 def test_batch_backward_equals_per_variant(rb, counts, keep):
     """Adjoint of the batch against per-variant adjoint calls; also with the
     binned order kept from the forward call."""
@@ -125,6 +125,45 @@ def test_batch_backward_equals_per_variant(rb, counts, keep):
         torch.cuda.synchronize()
         scale = float(g1.abs().max())
         assert torch.allclose(grad[p0:p1], g1, rtol=1e-9, atol=1e-12 * max(scale, 1e-300)), v
+
+
+@pytest.mark.parametrize("n_per", [[30, 200], [400, 2500]])
+def test_batch_backward_long_paths(rb, n_per):
+    """A batch holding the hex-cone concentrator, whose collected photons
+    often take more events than a path record holds: after a forward launch
+    that keeps its order, the adjoint replays the short records and searches
+    the long ones again; the gradient equals that of per-variant calls that
+    search every photon.  Both variants have several groups (n_per photons
+    per group; the larger case is binned)."""
+    devs = [rb.Scene(scenes.hex_concentrator()), rb.Scene(scenes.schwarzschild_couder())]
+    parts = [d.upload_rays(d.src.rays(k, seed=31 + v)) for v, (d, k) in enumerate(zip(devs, n_per))]
+    counts = [int(p["ox"].numel()) for p in parts]
+    rays = {k: torch.cat([p[k] for p in parts]) for k in parts[0]}
+    batch = rb.Batch(devs, counts, chunk=2048)
+    cot = torch.zeros(batch.n_groups, 2, dtype=torch.float64, device="cuda")
+    cot[:, 0] = 1.0
+    cot[:, 1] = 0.5
+    grads = []
+    for keep in (False, True):
+        sums = batch.new_sums()
+        batch.trace(rays, sums=sums, keep_order=keep)
+        grad = torch.zeros(batch.n_params, dtype=torch.float64, device="cuda")
+        batch.backward(rays, sums, cot, grad)
+        torch.cuda.synchronize()
+        grads.append(grad)
+    for v, d in enumerate(devs):
+        s1 = d.new_sums()
+        d.trace(parts[v], sums=s1)
+        g1 = torch.zeros(d.n_params, dtype=torch.float64, device="cuda")
+        d.backward(parts[v], s1, cot[batch.goff[v]:batch.goff[v + 1]].contiguous(), g1)
+        torch.cuda.synchronize()
+        p0, p1 = batch.poff[v], batch.poff[v + 1]
+        scale = float(g1.abs().max())
+        assert scale > 0
+        for keep, grad in zip((False, True), grads):
+            err = float((grad[p0:p1] - g1).abs().max()) / scale
+            print(f"variant {v} keep={keep}: max diff {err:.2e} of max |g|")
+            assert torch.allclose(grad[p0:p1], g1, rtol=1e-9, atol=1e-12 * scale), (v, keep, err)
 
 
 def test_batch_photons_match_oracle(rb):
