@@ -27,13 +27,21 @@
 namespace robast {
 
 constexpr int kBinBlock = 256;
+// The scatters run one large workgroup per CU (the LDS request below keeps a
+// second one off the CU): fewer output streams open at once per XCD, so more
+// of the partially written lines are completed in L2 before write-back.
+constexpr int kCoarseBlock = 1024;                      // threads of a keys / coarse-pass workgroup
+constexpr int kFineBlock = 1024;                        // threads of a fine-pass workgroup
+constexpr size_t kScatterLds = 90 * 1024;               // LDS requested by each scatter workgroup
+constexpr int kUnroll = 4;                              // photons in flight per thread in the scatters
+                                                        // (the fine pass is written out for 4)
 constexpr int kScanPerThread = 4;
 constexpr int kScanTile = kBinBlock * kScanPerThread;   // entries per scan block
 constexpr int kMaxCoarse = 2048;                        // LDS counters of the coarse pass
 constexpr int kMaxFineShift = 13;                       // LDS counters of the fine pass: 2^13
-constexpr int64_t kTileMax = 131072;                    // photons per tile of the coarse pass, at most
+constexpr int64_t kTileMax = int64_t(1) << 21;          // photons per tile of the coarse pass, at most
 constexpr int64_t kTileMin = 4096;                      // and at least
-constexpr int64_t kTilesWanted = 1024;                  // enough workgroups to fill the chip
+constexpr int64_t kTilesWanted = 256;                   // one workgroup per CU
 
 // bundle of photon i: the last v with offsets[v] <= i (offsets ascending)
 __device__ __forceinline__ int bundle_of(const int64_t* offsets, int n_var, int64_t i) {
@@ -70,7 +78,7 @@ __device__ __forceinline__ uint32_t photon_key(const RaysView<T>& R, int64_t i, 
 
 // (1) keys and per-tile coarse counts; cnt is bucket-major: cnt[c * n_tiles + tile]
 template <typename T, bool MULTI>
-__global__ void __launch_bounds__(kBinBlock) k_bin_keys(RaysView<T> R, int64_t n, BinGeom geo1, BinMulti multi,
+__global__ void __launch_bounds__(kCoarseBlock) k_bin_keys(RaysView<T> R, int64_t n, BinGeom geo1, BinMulti multi,
                                                         int shift, int n_coarse, int n_tiles, int64_t tile,
                                                         uint32_t* key, uint32_t* cnt) {
   extern __shared__ uint32_t hist[];
@@ -88,7 +96,7 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_keys(RaysView<T> R, int64_t n
 
 // (2) each tile scatters its photons to its range of every coarse bucket
 template <typename T>
-__global__ void __launch_bounds__(kBinBlock) k_bin_coarse(RaysView<T> R, int64_t n, int shift, int n_coarse,
+__global__ void __launch_bounds__(kCoarseBlock) k_bin_coarse(RaysView<T> R, int64_t n, int shift, int n_coarse,
                                                           int n_tiles, int64_t tile, const uint32_t* key,
                                                           const uint32_t* offs, uint32_t* tkey, BinRecord<T>* tmp) {
   static_assert(sizeof(BinRecord<T>) % 16 == 0, "records are written as 16-byte words");
@@ -96,30 +104,46 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_coarse(RaysView<T> R, int64_t
   for (int c = threadIdx.x; c < n_coarse; c += blockDim.x) cursor[c] = offs[(int64_t)c * n_tiles + blockIdx.x];
   __syncthreads();
   const int64_t lo = (int64_t)blockIdx.x * tile, hi = lo + tile < n ? lo + tile : n;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    const uint32_t k = key[i];
-    const uint32_t pos = atomicAdd(cursor + (k >> shift), 1u);
-    BinRecord<T> r{};
-    R.load(i, r.c, r.c + 3);
-    r.group = (uint32_t)R.grp(i);
-    r.src = (uint32_t)i;
-    const uint4* from = reinterpret_cast<const uint4*>(&r);
-    uint4* to = reinterpret_cast<uint4*>(tmp + pos);
+  // kUnroll photons per thread at a time: all their loads are issued before
+  // the first store, so that each thread keeps several in flight
+  for (int64_t base = lo + threadIdx.x; base < hi; base += (int64_t)blockDim.x * kUnroll) {
+    uint32_t k[kUnroll], pos[kUnroll];
+    BinRecord<T> r[kUnroll];
 #pragma unroll
-    for (int w = 0; w < (int)(sizeof(BinRecord<T>) / 16); ++w) to[w] = from[w];
-    tkey[pos] = k;
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t i = base + (int64_t)u * blockDim.x;
+      if (i < hi) {
+        k[u] = key[i];
+        R.load(i, r[u].c, r[u].c + 3);
+        r[u].group = (uint32_t)R.grp(i);
+        r[u].src = (uint32_t)i;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      if (base + (int64_t)u * blockDim.x < hi) pos[u] = atomicAdd(cursor + (k[u] >> shift), 1u);
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (base + (int64_t)u * blockDim.x < hi) {
+        const uint4* from = reinterpret_cast<const uint4*>(&r[u]);
+        uint4* to = reinterpret_cast<uint4*>(tmp + pos[u]);
+#pragma unroll
+        for (int w = 0; w < (int)(sizeof(BinRecord<T>) / 16); ++w) to[w] = from[w];
+        tkey[pos[u]] = k[u];
+      }
+    }
   }
 }
 
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t& total);
+template <int NT> __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t& total);
 
 // (3) one workgroup per coarse bucket: fine counting sort into key order
 template <typename T>
-__global__ void __launch_bounds__(kBinBlock) k_bin_fine(int64_t n, int shift, int n_coarse, int n_tiles,
-                                                        const uint32_t* offs, const uint32_t* tkey,
-                                                        const BinRecord<T>* tmp, BinRecord<T>* out) {
+__global__ void __launch_bounds__(kFineBlock) k_bin_fine(int64_t n, int shift, int n_coarse, int n_tiles,
+                                                         const uint32_t* offs, const uint32_t* tkey,
+                                                         const BinRecord<T>* tmp, BinRecord<T>* out) {
   extern __shared__ uint32_t fine[];
-  __shared__ uint32_t sh[kBinBlock];
+  __shared__ uint32_t sh[kFineBlock];
   const int c = blockIdx.x;
   const int nf = 1 << shift;
   const uint32_t mask = (uint32_t)nf - 1u;
@@ -127,17 +151,25 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_fine(int64_t n, int shift, in
   const int64_t end = c + 1 < n_coarse ? (int64_t)offs[(int64_t)(c + 1) * n_tiles] : n;
   for (int f = threadIdx.x; f < nf; f += blockDim.x) fine[f] = 0u;
   __syncthreads();
-  for (int64_t i = start + threadIdx.x; i < end; i += blockDim.x) atomicAdd(fine + (tkey[i] & mask), 1u);
+  for (int64_t base = start + threadIdx.x; base < end; base += (int64_t)blockDim.x * kUnroll) {
+    uint32_t k[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      if (base + (int64_t)u * blockDim.x < end) k[u] = tkey[base + (int64_t)u * blockDim.x];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      if (base + (int64_t)u * blockDim.x < end) atomicAdd(fine + (k[u] & mask), 1u);
+  }
   __syncthreads();
   // exclusive scan of the fine counts: contiguous runs per thread, then the
   // run totals across the workgroup
-  const int per = (nf + kBinBlock - 1) / kBinBlock;
+  const int per = (nf + kFineBlock - 1) / kFineBlock;
   const int f0 = threadIdx.x * per;
   uint32_t run = 0;
   for (int k = 0; k < per; ++k)
     if (f0 + k < nf) run += fine[f0 + k];
   uint32_t total;
-  uint32_t acc = block_exclusive_scan(run, sh, total);
+  uint32_t acc = block_exclusive_scan<kFineBlock>(run, sh, total);
   for (int k = 0; k < per; ++k)
     if (f0 + k < nf) {
       const uint32_t v = fine[f0 + k];
@@ -145,34 +177,68 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_fine(int64_t n, int shift, in
       acc += v;
     }
   __syncthreads();
-  for (int64_t i = start + threadIdx.x; i < end; i += blockDim.x) {
-    const uint32_t pos = (uint32_t)start + atomicAdd(fine + (tkey[i] & mask), 1u);
-    const uint4* from = reinterpret_cast<const uint4*>(tmp + i);
-    uint4* to = reinterpret_cast<uint4*>(out + pos);
+  // FP32 records: kUnroll photons per thread at a time, all loads issued
+  // before the first store, their 16-byte words in named registers (past
+  // the end the last photon is loaded again and never stored)
+  const uint4* src = reinterpret_cast<const uint4*>(tmp);
+  uint4* dst = reinterpret_cast<uint4*>(out);
+  const int64_t step = blockDim.x;
+  if constexpr (sizeof(BinRecord<T>) == 32) {
+    for (int64_t i0 = start + threadIdx.x; i0 < end; i0 += step * kUnroll) {
+      const int64_t i1 = i0 + step, i2 = i0 + 2 * step, i3 = i0 + 3 * step;
+      const int64_t j1 = i1 < end ? i1 : end - 1, j2 = i2 < end ? i2 : end - 1, j3 = i3 < end ? i3 : end - 1;
+      const uint32_t k0 = tkey[i0], k1 = tkey[j1], k2 = tkey[j2], k3 = tkey[j3];
+      const uint4 a0 = src[2 * i0], a1 = src[2 * i0 + 1], b0 = src[2 * j1], b1 = src[2 * j1 + 1];
+      const uint4 c0 = src[2 * j2], c1 = src[2 * j2 + 1], d0 = src[2 * j3], d1 = src[2 * j3 + 1];
+      const int64_t p0 = start + atomicAdd(fine + (k0 & mask), 1u);
+      dst[2 * p0] = a0;
+      dst[2 * p0 + 1] = a1;
+      if (i1 < end) {
+        const int64_t p = start + atomicAdd(fine + (k1 & mask), 1u);
+        dst[2 * p] = b0;
+        dst[2 * p + 1] = b1;
+      }
+      if (i2 < end) {
+        const int64_t p = start + atomicAdd(fine + (k2 & mask), 1u);
+        dst[2 * p] = c0;
+        dst[2 * p + 1] = c1;
+      }
+      if (i3 < end) {
+        const int64_t p = start + atomicAdd(fine + (k3 & mask), 1u);
+        dst[2 * p] = d0;
+        dst[2 * p + 1] = d1;
+      }
+    }
+  } else {
+    constexpr int W = (int)(sizeof(BinRecord<T>) / 16);
+    for (int64_t i = start + threadIdx.x; i < end; i += step) {
+      const int64_t p = start + atomicAdd(fine + (tkey[i] & mask), 1u);
 #pragma unroll
-    for (int w = 0; w < (int)(sizeof(BinRecord<T>) / 16); ++w) to[w] = from[w];
+      for (int q = 0; q < W; ++q) dst[p * W + q] = src[i * W + q];
+    }
   }
 }
 
-// Exclusive scan of the bin counts in place, in three passes: tiles of
-// kScanTile bins scanned in LDS (tile totals to `part`), the tile totals
-// scanned by one workgroup, the tile offsets added back.
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t& total) {
+// Exclusive scan across a workgroup of NT threads (sh: NT words of LDS).
+template <int NT> __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t& total) {
   const int t = threadIdx.x;
   sh[t] = v;
   __syncthreads();
-  for (int o = 1; o < kBinBlock; o <<= 1) {
+  for (int o = 1; o < NT; o <<= 1) {
     uint32_t add = t >= o ? sh[t - o] : 0u;
     __syncthreads();
     sh[t] += add;
     __syncthreads();
   }
-  total = sh[kBinBlock - 1];
+  total = sh[NT - 1];
   const uint32_t incl = sh[t];
   __syncthreads();
   return incl - v;
 }
 
+// Exclusive scan of the bin counts in place, in three passes: tiles of
+// kScanTile bins scanned in LDS (tile totals to `part`), the tile totals
+// scanned by one workgroup, the tile offsets added back.
 __global__ void __launch_bounds__(kBinBlock) k_scan_tiles(uint32_t* hist, int64_t bins, uint32_t* part) {
   __shared__ uint32_t sh[kBinBlock];
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPerThread;
@@ -184,7 +250,7 @@ __global__ void __launch_bounds__(kBinBlock) k_scan_tiles(uint32_t* hist, int64_
     s += v[k];
   }
   uint32_t total;
-  uint32_t run = block_exclusive_scan(s, sh, total);
+  uint32_t run = block_exclusive_scan<kBinBlock>(s, sh, total);
 #pragma unroll
   for (int k = 0; k < kScanPerThread; ++k) {
     if (base + k < bins) hist[base + k] = run;
@@ -200,7 +266,7 @@ __global__ void __launch_bounds__(kBinBlock) k_scan_parts(uint32_t* part, int n_
     const int i = base + threadIdx.x;
     const uint32_t v = i < n_parts ? part[i] : 0u;
     uint32_t total;
-    const uint32_t ex = block_exclusive_scan(v, sh, total);
+    const uint32_t ex = block_exclusive_scan<kBinBlock>(v, sh, total);
     if (i < n_parts) part[i] = carry + ex;
     carry += total;
   }
@@ -259,17 +325,17 @@ hipError_t launch_binning(const RaysView<T>& R, int64_t n, const BinGeom& geo, c
   if (p.shift > kMaxFineShift || p.n_coarse > kMaxCoarse) return hipErrorInvalidValue;
   const size_t coarse_lds = (size_t)p.n_coarse * 4, fine_lds = ((size_t)1 << p.shift) * 4;
   if (multi.n_var > 0)
-    hipLaunchKernelGGL((k_bin_keys<T, true>), dim3(p.n_tiles), dim3(kBinBlock), coarse_lds, st, R, n, geo, multi,
+    hipLaunchKernelGGL((k_bin_keys<T, true>), dim3(p.n_tiles), dim3(kCoarseBlock), coarse_lds, st, R, n, geo, multi,
                        p.shift, p.n_coarse, p.n_tiles, p.tile, W.key, W.cnt);
   else
-    hipLaunchKernelGGL((k_bin_keys<T, false>), dim3(p.n_tiles), dim3(kBinBlock), coarse_lds, st, R, n, geo, multi,
+    hipLaunchKernelGGL((k_bin_keys<T, false>), dim3(p.n_tiles), dim3(kCoarseBlock), coarse_lds, st, R, n, geo, multi,
                        p.shift, p.n_coarse, p.n_tiles, p.tile, W.key, W.cnt);
   hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)p.parts), dim3(kBinBlock), 0, st, W.cnt, p.cnt_entries, W.part);
   hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kBinBlock), 0, st, W.part, (int)p.parts);
   hipLaunchKernelGGL(k_scan_add, dim3((unsigned)p.parts), dim3(kBinBlock), 0, st, W.cnt, p.cnt_entries, W.part);
-  hipLaunchKernelGGL(k_bin_coarse<T>, dim3(p.n_tiles), dim3(kBinBlock), coarse_lds, st, R, n, p.shift, p.n_coarse,
+  hipLaunchKernelGGL(k_bin_coarse<T>, dim3(p.n_tiles), dim3(kCoarseBlock), std::max(coarse_lds, kScatterLds), st, R, n, p.shift, p.n_coarse,
                      p.n_tiles, p.tile, W.key, W.cnt, W.tkey, W.tmp);
-  hipLaunchKernelGGL(k_bin_fine<T>, dim3(p.n_coarse), dim3(kBinBlock), fine_lds, st, n, p.shift, p.n_coarse,
+  hipLaunchKernelGGL(k_bin_fine<T>, dim3(p.n_coarse), dim3(kFineBlock), std::max(fine_lds, kScatterLds), st, n, p.shift, p.n_coarse,
                      p.n_tiles, W.cnt, W.tkey, W.tmp, W.out);
   return hipGetLastError();
 }
