@@ -1197,8 +1197,8 @@ int robast_build_batch(robast_scene* const* scenes, int32_t n_scenes, const int6
   // left is traced from global memory rather than lowering the occupancy of
   // every variant
   {
-    const size_t gbytes = (size_t)b->max_params * sizeof(double);
-    const size_t left = gbytes <= 16384 && gbytes < lds_cap ? (lds_cap - gbytes) & ~(size_t)15 : lds_cap;
+    const size_t gbytes = batch_grad_lds_bytes(b->max_params);
+    const size_t left = gbytes < lds_cap ? (lds_cap - gbytes) & ~(size_t)15 : 0;
     b->blob_cap_bwd = (uint32_t)std::min<size_t>(b->blob_cap, left);
   }
   const size_t vbytes = sizeof(BatchVariant<float>);

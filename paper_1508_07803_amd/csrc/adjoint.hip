@@ -130,7 +130,7 @@ k_backward_path(SceneView<T> S, RaysView<T> R, int64_t n, AdjView A, GradLds G, 
       if (is_long) P.list[base + below] = (uint32_t)i;
     }
     if (w.x >= kPathLong) continue;
-    adjoint_photon_path<T>(L, R, i, A, gs, w);
+    adjoint_photon_path<T, true>(L, R, i, A, gs, w);
   }
   grad_end(gacc, G, A);
 }

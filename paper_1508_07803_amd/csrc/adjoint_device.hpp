@@ -14,14 +14,30 @@ struct GradSink {
   }
 };
 
-template <typename T> __device__ __forceinline__ V3<T> qT(const DVol<T>& v, V3<T> a) {
-  return {v.Q[0] * a.x + v.Q[3] * a.y + v.Q[6] * a.z, v.Q[1] * a.x + v.Q[4] * a.y + v.Q[7] * a.z,
-          v.Q[2] * a.x + v.Q[5] * a.y + v.Q[8] * a.z};
-}
-template <typename T> __device__ __forceinline__ V3<T> qm(const DVol<T>& v, V3<T> a) {
-  return {v.Q[0] * a.x + v.Q[1] * a.y + v.Q[2] * a.z, v.Q[3] * a.x + v.Q[4] * a.y + v.Q[5] * a.z,
-          v.Q[6] * a.x + v.Q[7] * a.y + v.Q[8] * a.z};
-}
+// A volume's local frame (rotation Q, origin c) converted once to the
+// compute type C; Q^T a, Q a and local coordinates of a world point held in
+// double (offset from the origin formed in double).
+template <typename C> struct FrameC {
+  C q[9];
+  double c[3];
+  template <typename T> __device__ __forceinline__ explicit FrameC(const DVol<T>& v) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) q[i] = (C)v.Q[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) c[i] = (double)v.c[i];
+  }
+  __device__ __forceinline__ V3<C> qT(V3<C> a) const {
+    return {q[0] * a.x + q[3] * a.y + q[6] * a.z, q[1] * a.x + q[4] * a.y + q[7] * a.z,
+            q[2] * a.x + q[5] * a.y + q[8] * a.z};
+  }
+  __device__ __forceinline__ V3<C> qm(V3<C> a) const {
+    return {q[0] * a.x + q[1] * a.y + q[2] * a.z, q[3] * a.x + q[4] * a.y + q[5] * a.z,
+            q[6] * a.x + q[7] * a.y + q[8] * a.z};
+  }
+  __device__ __forceinline__ V3<C> local(V3<double> x) const {
+    return qm({(C)(x.x - c[0]), (C)(x.y - c[1]), (C)(x.z - c[2])});
+  }
+};
 
 // Apply a recorded action at a hit with front normal n (no random draw),
 // in double like the forward interaction.
@@ -57,64 +73,54 @@ __device__ __forceinline__ bool replay_root(const SceneView<T>& S, int vid, int 
   return true;
 }
 
-// Bernstein cubic helpers for the cone walls
-template <typename T> __device__ __forceinline__ void bez2(const T* p, T s, T& rho, T& z, T& dr, T& dz, T& ddr,
-                                                           T& ddz) {
+// Bernstein cubic of the cone walls with its first and second derivatives,
+// in C from the record's control points.
+template <typename C, typename P> __device__ __forceinline__ void bez2(const P* p, C s, C& rho, C& z, C& dr, C& dz, C& ddr,
+                                                                       C& ddz) {
   bez_eval(p, s, rho, z, dr, dz);
-  T b0 = T(6) - T(6) * s, b1 = T(-12) + T(18) * s, b2 = T(6) - T(18) * s, b3 = T(6) * s;
-  ddr = b0 * p[0] + b1 * p[2] + b2 * p[4] + b3 * p[6];
-  ddz = b0 * p[1] + b1 * p[3] + b2 * p[5] + b3 * p[7];
+  C b0 = C(6) - C(6) * s, b1 = C(-12) + C(18) * s, b2 = C(6) - C(18) * s, b3 = C(6) * s;
+  ddr = b0 * (C)p[0] + b1 * (C)p[2] + b2 * (C)p[4] + b3 * (C)p[6];
+  ddz = b0 * (C)p[1] + b1 * (C)p[3] + b2 * (C)p[5] + b3 * (C)p[7];
 }
 
-// Volume record in double (for the FP64 pull-back of FP32 scenes).
-template <typename T> __device__ __forceinline__ DVol<double> promote(const DVol<T>& v) {
-  DVol<double> r;
-  r.role = v.role; r.shape = v.shape; r.outline = v.outline; r.nfaces = v.nfaces;
-  r.sparam = v.sparam; r.tparam = v.tparam; r.always_reflect = v.always_reflect; r.thr = v.thr;
-#pragma unroll
-  for (int i = 0; i < 9; ++i) r.Q[i] = (double)v.Q[i];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) r.c[i] = (double)v.c[i];
-#pragma unroll
-  for (int i = 0; i < 12; ++i) r.p[i] = (double)v.p[i];
-  r.n_in = (double)v.n_in;
-  return r;
-}
-
-// Pull back the cotangents of one event.  In: Xb (cotangent of the hit point,
-// i.e. of the next origin) and db (cotangent of the outgoing direction, or of
-// the entering direction for the terminal event).  Out: cotangents of the
-// entering origin and direction; parameter partials go to the sink.
-template <typename T>
+// Pull back the cotangents of one event, computing in C from the volume
+// record (fields converted as they are read).  In: Xb (cotangent of the hit
+// point, i.e. of the next origin) and db (cotangent of the outgoing
+// direction, or of the entering direction for the terminal event).  Out:
+// cotangents of the entering origin and direction; parameter partials go to
+// the sink.
+template <typename C, typename T>
 __device__ __forceinline__ void event_adjoint(const DVol<T>& v, const DTilt* tilt, int face, int act,
-                                              V3<double> O, V3<T> d, T t, T s, V3<T>& Xb, V3<T>& db,
+                                              V3<double> O, V3<C> d, C t, C s, V3<C>& Xb, V3<C>& db,
                                               GradSink& gs) {
+  const FrameC<C> F(v);
   V3<double> Xw = adv(O, t, d);
-  V3<T> xl = loc_pd(v, Xw);
-  V3<T> Gl = local_grad(v, face, xl, s);
-  V3<T> m = qT(v, Gl);
-  T mn = dsqrt(dot(m, m));
-  V3<T> n = scl(T(1) / mn, m);
+  V3<C> xl = F.local(Xw);
+  V3<C> Gl = local_grad<C, T>(v, face, xl, s);
+  V3<C> m = F.qT(Gl);
+  C mn = dsqrt(dot(m, m));
+  V3<C> n = scl(C(1) / mn, m);
 
   // 1. interaction
-  V3<T> dbar = {T(0), T(0), T(0)}, nbar = {T(0), T(0), T(0)};
+  V3<C> dbar = {C(0), C(0), C(0)}, nbar = {C(0), C(0), C(0)};
   if (act == ACT_REFLECT) {
-    T dn = dot(d, n), bn = dot(db, n);
-    dbar = fma3(T(-2) * bn, n, db);
-    nbar = add(scl(T(-2) * bn, d), scl(T(-2) * dn, db));
+    C dn = dot(d, n), bn = dot(db, n);
+    dbar = fma3(C(-2) * bn, n, db);
+    nbar = add(scl(C(-2) * bn, d), scl(C(-2) * dn, db));
   } else if (act == ACT_REFRACT) {
-    int back = dot(d, n) < T(0) ? 0 : 1;
-    T sg = back ? T(-1) : T(1);
-    V3<T> no = scl(sg, n);
-    T n1 = back ? v.n_in : T(1), n2 = back ? T(1) : v.n_in;
-    T eta = n1 / n2;
-    T cos_i = -dot(d, no);
-    T cos_t = dsqrt(dmax(T(1) - eta * eta * (T(1) - cos_i * cos_i), T(1e-30)));
-    T k = eta * cos_i - cos_t;
+    int back = dot(d, n) < C(0) ? 0 : 1;
+    C sg = back ? C(-1) : C(1);
+    V3<C> no = scl(sg, n);
+    const C nin = (C)v.n_in;
+    C n1 = back ? nin : C(1), n2 = back ? C(1) : nin;
+    C eta = n1 / n2;
+    C cos_i = -dot(d, no);
+    C cos_t = dsqrt(dmax(C(1) - eta * eta * (C(1) - cos_i * cos_i), C(1e-30)));
+    C k = eta * cos_i - cos_t;
     dbar = scl(eta, db);
-    T kb = dot(db, no);
-    V3<T> nob = scl(k, db);
-    T cib = kb * (eta - eta * eta * cos_i / cos_t);
+    C kb = dot(db, no);
+    V3<C> nob = scl(k, db);
+    C cib = kb * (eta - eta * eta * cos_i / cos_t);
     dbar = fma3(-cib, no, dbar);
     nob = fma3(-cib, d, nob);
     nbar = scl(sg, nob);
@@ -123,54 +129,54 @@ __device__ __forceinline__ void event_adjoint(const DVol<T>& v, const DTilt* til
   }
 
   // 2. normal n = m / |m|, m = Q^T G(x_l)
-  V3<T> mbar = scl(T(1) / mn, fma3(-dot(nbar, n), n, nbar));
-  V3<T> Gb = qm(v, mbar);
-  V3<T> xlb = {T(0), T(0), T(0)};
-  T sbar = T(0);
+  V3<C> mbar = scl(C(1) / mn, fma3(-dot(nbar, n), n, nbar));
+  V3<C> Gb = F.qm(mbar);
+  V3<C> xlb = {C(0), C(0), C(0)};
+  C sbar = C(0);
   const int sp = v.sparam;
   switch (v.shape) {
     case SPHERE: {
-      T c = v.p[0];
+      C c = (C)v.p[0];
       xlb = scl(-c, Gb);                                   // Hessian -c I
       if (sp >= 0) {
-        T cbar = -dot(Gb, xl);                             // dG/dc = -x_l
+        C cbar = -dot(Gb, xl);                             // dG/dc = -x_l
         // root term added below; radius R = 1/c
         gs.add(sp, (double)(cbar * (-c * c)));
       }
       break;
     }
     case ASPHERE: {
-      T ir = v.p[9];
-      T u = (xl.x * xl.x + xl.y * xl.y) * ir;
-      T S, dS;
+      C ir = (C)v.p[9];
+      C u = (xl.x * xl.x + xl.y * xl.y) * ir;
+      C S, dS;
       sag_eval(v.p, u, S, dS);
-      T d2 = T(56) * v.p[8];
-      for (int i = 7; i >= 2; --i) d2 = d2 * u + T(i * (i - 1)) * v.p[i];
-      T k = T(2) * ir * dS;
-      T proj = xl.x * Gb.x + xl.y * Gb.y;
-      T h = T(4) * ir * ir * d2 * proj;
-      xlb = {-k * Gb.x - h * xl.x, -k * Gb.y - h * xl.y, T(0)};
+      C d2 = C(56) * (C)v.p[8];
+      for (int i = 7; i >= 2; --i) d2 = d2 * u + C(i * (i - 1)) * (C)v.p[i];
+      C k = C(2) * ir * dS;
+      C proj = xl.x * Gb.x + xl.y * Gb.y;
+      C h = C(4) * ir * ir * d2 * proj;
+      xlb = {-k * Gb.x - h * xl.x, -k * Gb.y - h * xl.y, C(0)};
       if (sp >= 0) {
         // dG/db_i = -2 ir i u^{i-1} (x, y, 0)
-        T up = T(1);
+        C up = C(1);
         for (int i = 1; i <= 8; ++i) {
-          gs.add(sp + i - 1, (double)(T(-2) * ir * T(i) * up * proj));
+          gs.add(sp + i - 1, (double)(C(-2) * ir * C(i) * up * proj));
           up *= u;
         }
       }
       break;
     }
-    case CYLINDER: xlb = {Gb.x, Gb.y, T(0)}; break;
+    case CYLINDER: xlb = {Gb.x, Gb.y, C(0)}; break;
     case HEXCONE: {
-      T rho, z, dr, dz, ddr, ddz;
+      C rho, z, dr, dz, ddr, ddz;
       bez2(v.p, s, rho, z, dr, dz, ddr, ddz);
-      T nx, ny;
+      C nx, ny;
       wall_dir(face, nx, ny);
       sbar = -ddz * (Gb.x * nx + Gb.y * ny) + ddr * Gb.z;
       if (sp >= 0) {
-        T a = T(1) - s;
-        T B1p = T(3) * a * a - T(6) * a * s, B2p = T(6) * a * s - T(3) * s * s;
-        T gxy = Gb.x * nx + Gb.y * ny;
+        C a = C(1) - s;
+        C B1p = C(3) * a * a - C(6) * a * s, B2p = C(6) * a * s - C(3) * s * s;
+        C gxy = Gb.x * nx + Gb.y * ny;
         gs.add(sp + 0, (double)(Gb.z * B1p));   // rho1: dG/drho1 = (0, 0, B1')
         gs.add(sp + 1, (double)(-gxy * B1p));   // z1:   dG/dz1 = (-B1' n, 0)
         gs.add(sp + 2, (double)(Gb.z * B2p));
@@ -181,62 +187,62 @@ __device__ __forceinline__ void event_adjoint(const DVol<T>& v, const DTilt* til
     default: break;
   }
   const bool tilted = v.tparam >= 0;
-  V3<T> a1 = {T(0), T(0), T(0)}, a2 = a1, Xp = a1;
+  V3<C> a1 = {C(0), C(0), C(0)}, a2 = a1, Xp = a1;
   if (tilted) {
     const DTilt& tl = tilt[0];
-    a1 = {(T)tl.a1[0], (T)tl.a1[1], (T)tl.a1[2]};
-    a2 = {(T)tl.a2[0], (T)tl.a2[1], (T)tl.a2[2]};
-    Xp = {(T)(Xw.x - tl.pivot[0]), (T)(Xw.y - tl.pivot[1]), (T)(Xw.z - tl.pivot[2])};
+    a1 = {(C)tl.a1[0], (C)tl.a1[1], (C)tl.a1[2]};
+    a2 = {(C)tl.a2[0], (C)tl.a2[1], (C)tl.a2[2]};
+    Xp = {(C)(Xw.x - tl.pivot[0]), (C)(Xw.y - tl.pivot[1]), (C)(Xw.z - tl.pivot[2])};
   }
-  T tb1 = T(0), tb2 = T(0);
+  C tb1 = C(0), tb2 = C(0);
   if (tilted) {
     // explicit rotation of m, and the frame dependence of x_l at fixed X
-    V3<T> qx = qT(v, xlb);
+    V3<C> qx = F.qT(xlb);
     tb1 += dot(mbar, cross(a1, m)) - dot(qx, cross(a1, Xp));
     tb2 += dot(mbar, cross(a2, m)) - dot(qx, cross(a2, Xp));
   }
 
   // 3. hit point X = O + t d (x_l = Q (X - c))
-  V3<T> Xt = add(Xb, qT(v, xlb));
-  V3<T> obar = Xt;
+  V3<C> Xt = add(Xb, F.qT(xlb));
+  V3<C> obar = Xt;
   dbar = fma3(t, Xt, dbar);
-  T tbar = dot(Xt, d);
+  C tbar = dot(Xt, d);
 
   // 4. implicit root
   if (v.shape == HEXCONE) {
-    T rho, z, dr, dz, ddr, ddz;
+    C rho, z, dr, dz, ddr, ddz;
     bez2(v.p, s, rho, z, dr, dz, ddr, ddz);
-    T nx, ny;
+    C nx, ny;
     wall_dir(face, nx, ny);
-    V3<T> dl = loc_d(v, d);
-    T du = dl.x * nx + dl.y * ny, dzl = dl.z;
-    T det = du * dz - dr * dzl;
-    T mu1 = (sbar * dzl + dz * tbar) / det;
-    T mu2 = (-dr * tbar - du * sbar) / det;
-    V3<T> olb = {-mu1 * nx, -mu1 * ny, -mu2};
-    V3<T> ow = qT(v, olb);
+    V3<C> dl = F.qm(d);
+    C du = dl.x * nx + dl.y * ny, dzl = dl.z;
+    C det = du * dz - dr * dzl;
+    C mu1 = (sbar * dzl + dz * tbar) / det;
+    C mu2 = (-dr * tbar - du * sbar) / det;
+    V3<C> olb = {-mu1 * nx, -mu1 * ny, -mu2};
+    V3<C> ow = F.qT(olb);
     obar = add(obar, ow);
     dbar = fma3(t, ow, dbar);
     if (sp >= 0) {
-      T a = T(1) - s;
-      T B1 = T(3) * a * a * s, B2 = T(3) * a * s * s;
+      C a = C(1) - s;
+      C B1 = C(3) * a * a * s, B2 = C(3) * a * s * s;
       gs.add(sp + 0, (double)(mu1 * B1));
       gs.add(sp + 1, (double)(mu2 * B1));
       gs.add(sp + 2, (double)(mu1 * B2));
       gs.add(sp + 3, (double)(mu2 * B2));
     }
   } else {
-    T gt = dot(m, d);
-    T lam = gt != T(0) ? -tbar / gt : T(0);
+    C gt = dot(m, d);
+    C lam = gt != C(0) ? -tbar / gt : C(0);
     obar = fma3(lam, m, obar);
     dbar = fma3(lam * t, m, dbar);
     if (sp >= 0) {
       if (v.shape == SPHERE) {
-        T c = v.p[0];
-        gs.add(sp, (double)(lam * (T(-0.5) * dot(xl, xl)) * (-c * c)));
+        C c = (C)v.p[0];
+        gs.add(sp, (double)(lam * (C(-0.5) * dot(xl, xl)) * (-c * c)));
       } else if (v.shape == ASPHERE) {
-        T u = (xl.x * xl.x + xl.y * xl.y) * v.p[9];
-        T up = u;
+        C u = (xl.x * xl.x + xl.y * xl.y) * (C)v.p[9];
+        C up = u;
         for (int i = 1; i <= 8; ++i) {
           gs.add(sp + i - 1, (double)(-lam * up));
           up *= u;
@@ -303,8 +309,7 @@ __device__ __forceinline__ bool reverse_sweep(const SceneView<T>& L, const AdjVi
     // the pull-back runs in FP64 from the replayed state: the per-photon
     // partials are summed with cancellation (centroid-subtracted
     // cotangents), which FP32 arithmetic would not resolve
-    DVol<double> vd = promote(L.vol[vid]);
-    event_adjoint<double>(vd, A.tilt + vid, face, act, O, d, t, s, Xb, db, gs);
+    event_adjoint<double, T>(L.vol[vid], A.tilt + vid, face, act, O, d, t, s, Xb, db, gs);
   }
   return true;
 }
@@ -330,10 +335,6 @@ __device__ __forceinline__ void adjoint_photon(const SceneView<T>& L, const Rays
   (void)reverse_sweep<T>(L, A, gs, cf, o0, d0, codes, r.nev);
 }
 
-#ifndef ROBAST_PATH_SWEEP
-#define ROBAST_PATH_SWEEP 1
-#endif
-
 // State entering an event of a recorded path: origin, direction, and the
 // root (distance, cone wall parameter) of the event's intersection.
 struct PathState {
@@ -341,10 +342,28 @@ struct PathState {
   double t, s;
 };
 
+// Volume record in double (the pull-back then reads no FP32 field).
+template <typename T> __device__ __forceinline__ DVol<double> promote(const DVol<T>& v) {
+  DVol<double> r;
+  r.role = v.role; r.shape = v.shape; r.outline = v.outline; r.nfaces = v.nfaces;
+  r.sparam = v.sparam; r.tparam = v.tparam; r.always_reflect = v.always_reflect; r.thr = v.thr;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) r.Q[i] = (double)v.Q[i];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) r.c[i] = (double)v.c[i];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) r.p[i] = (double)v.p[i];
+  r.n_in = (double)v.n_in;
+  return r;
+}
+
 // Adjoint of one photon from its path record (see kPathSlots): no search.
 // The states entering the (at most kPathSlots) events are replayed once,
 // forward, and kept in registers; the reverse sweep then reads them back.
-template <typename T>
+// PROMOTE: convert each event's volume record to double once (fewer
+// instructions) rather than field by field as read (fewer registers); which
+// is faster depends on the register pressure of the calling kernel.
+template <typename T, bool PROMOTE>
 __device__ __forceinline__ void adjoint_photon_path(const SceneView<T>& L, const RaysView<T>& R, int64_t i,
                                                     const AdjView& A, GradSink& gs, uint4 w) {
   const int g = R.grp(i);
@@ -355,9 +374,6 @@ __device__ __forceinline__ void adjoint_photon_path(const SceneView<T>& L, const
   R.load(i, oa, da);
   const uint32_t codes[kPathSlots] = {w.x, w.y, w.z, w.w};
   const int nev = w.y == kPathEnd ? 1 : w.z == kPathEnd ? 2 : w.w == kPathEnd ? 3 : 4;
-#if ROBAST_PATH_SWEEP == 0
-  (void)reverse_sweep<T>(L, A, gs, cf, V3<T>{oa[0], oa[1], oa[2]}, V3<T>{da[0], da[1], da[2]}, codes, nev);
-#else
   PathState st[kPathSlots];
   V3<double> O = {(double)oa[0], (double)oa[1], (double)oa[2]};
   V3<double> d = {(double)da[0], (double)da[1], (double)da[2]};
@@ -387,28 +403,19 @@ __device__ __forceinline__ void adjoint_photon_path(const SceneView<T>& L, const
   // and of the sign of the final direction
   V3<double> Xb = {cf[0] * ((double)(T)O.x - cf[1]), cf[0] * ((double)(T)O.y - cf[2]), 0.0};
   V3<double> db = {0.0, 0.0, (T)d.z >= T(0) ? cf[3] : -cf[3]};
-#if ROBAST_PATH_SWEEP == 1
 #pragma unroll
   for (int e = kPathSlots - 1; e >= 0; --e) {
     if (e < nev) {
       const int vid = (int)(codes[e] >> 8), face = (int)((codes[e] >> 4) & 15u), act = (int)(codes[e] & 15u);
-      DVol<double> vd = promote(L.vol[vid]);
-      event_adjoint<double>(vd, A.tilt + vid, face, act, st[e].O, st[e].d, st[e].t, st[e].s, Xb, db, gs);
+      if constexpr (PROMOTE) {
+        const DVol<double> vd = promote(L.vol[vid]);
+        event_adjoint<double, double>(vd, A.tilt + vid, face, act, st[e].O, st[e].d, st[e].t, st[e].s, Xb, db, gs);
+      } else {
+        event_adjoint<double, T>(L.vol[vid], A.tilt + vid, face, act, st[e].O, st[e].d, st[e].t, st[e].s, Xb, db,
+                                 gs);
+      }
     }
   }
-#else
-  for (int e = nev - 1; e >= 0; --e) {
-    PathState c = st[0];
-#pragma unroll
-    for (int k = 1; k < kPathSlots; ++k)
-      if (e == k) c = st[k];
-    const uint32_t code = e == 0 ? codes[0] : e == 1 ? codes[1] : e == 2 ? codes[2] : codes[3];
-    const int vid = (int)(code >> 8), face = (int)((code >> 4) & 15u), act = (int)(code & 15u);
-    DVol<double> vd = promote(L.vol[vid]);
-    event_adjoint<double>(vd, A.tilt + vid, face, act, c.O, c.d, c.t, c.s, Xb, db, gs);
-  }
-#endif
-#endif
 }
 
 }  // namespace robast

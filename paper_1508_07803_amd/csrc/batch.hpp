@@ -54,6 +54,9 @@ hipError_t launch_trace_batch(const BatchView<float>& B, const RaysView<float>& 
 // With `path` (the forward launch's path records, non-null) the sequences
 // are replayed from the records; photons whose record is too long are
 // found again by a search.
+// LDS bytes the batched adjoint keeps for gradient sums (0: they go
+// straight to global memory), from the largest parameter count.
+uint32_t batch_grad_lds_bytes(int max_params);
 hipError_t launch_backward_batch(const BatchView<float>& B, const RaysView<float>& R, const double* coef,
                                  double* grad, hipStream_t st, const uint32_t* path = nullptr);
 

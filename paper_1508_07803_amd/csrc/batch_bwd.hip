@@ -19,7 +19,21 @@
 
 namespace robast {
 
-constexpr uint32_t kGradLdsMax = 16384;   // gradient sums kept in LDS up to this size
+constexpr uint32_t kGradLdsMax = 16384;   // LDS bytes for the gradient sums of a workgroup
+
+// Gradient sums of variant v in LDS: `copies` interleaved copies of its
+// parameter vector (a power of two, as many as fit in grad_bytes, at most
+// 16), `pstride` doubles apart (odd: the copies start in different banks);
+// lane l adds to copy l mod copies, so lanes of a wave that hit the same
+// surface contend for one address copies times less.
+struct GradCopies {
+  int copies, pstride;
+  __device__ __forceinline__ GradCopies(int n_params, uint32_t grad_bytes) {
+    pstride = n_params | 1;
+    copies = 1;
+    while (copies < 16 && (uint32_t)(2 * copies * pstride) * 8u <= grad_bytes) copies *= 2;
+  }
+};
 
 // Photon selection of a batched adjoint launch: every photon, searched
 // again (kSearchAll); only the photons whose path record is kPathLong,
@@ -34,7 +48,7 @@ constexpr int kSearchAll = 0, kSearchLong = 1, kReplay = 2;
 template <bool USE_LDS, int MAXE, int MODE>
 __global__ void __launch_bounds__(kBlockB) __attribute__((amdgpu_waves_per_eu(MAXE <= 16 ? 3 : 1, 8)))
 k_backward_batch(const BatchVariant<float>* vars, const BatchItem* items, int n_items, uint32_t* queue,
-                 uint32_t blob_cap, int grad_in_lds, RaysView<float> R, const double* coef, double* grad,
+                 uint32_t blob_cap, uint32_t grad_bytes, RaysView<float> R, const double* coef, double* grad,
                  const uint32_t* path) {
   extern __shared__ __align__(16) char lds[];
   __shared__ int s_item;
@@ -47,10 +61,14 @@ k_backward_batch(const BatchVariant<float>* vars, const BatchItem* items, int n_
     const int item = next_item(counter, &s_item);
     const BatchItem it = item < n_items ? load_uniform(items + item) : BatchItem{0, 0, -1};
     if (it.v != cur_v) {
-      if (grad_in_lds && cur_v >= 0) {
+      if (grad_bytes && cur_v >= 0) {
         const BatchVariant<float> pv = load_uniform(vars + cur_v);
-        for (int i = threadIdx.x; i < pv.n_params; i += blockDim.x)
-          if (gacc[i] != 0.0) atomicAdd(grad + pv.poff + i, gacc[i]);
+        const GradCopies gc(pv.n_params, grad_bytes);
+        for (int i = threadIdx.x; i < pv.n_params; i += blockDim.x) {
+          double sum = 0.0;
+          for (int c = 0; c < gc.copies; ++c) sum += gacc[c * gc.pstride + i];
+          if (sum != 0.0) atomicAdd(grad + pv.poff + i, sum);
+        }
       }
       __syncthreads();
       cur_v = -1;
@@ -61,17 +79,18 @@ k_backward_batch(const BatchVariant<float>* vars, const BatchItem* items, int n_
     if (fits_lds(S, blob_cap) != USE_LDS) continue;
     SceneView<float> L;
     if (USE_LDS) lds_view(L, lds);
+    const GradCopies gc(bv.n_params, grad_bytes);
     if (it.v != cur_v) {
       if (USE_LDS) stage_variant<float>(S, L, lds);
-      if (grad_in_lds)
-        for (int i = threadIdx.x; i < bv.n_params; i += blockDim.x) gacc[i] = 0.0;
+      if (grad_bytes)
+        for (int i = threadIdx.x; i < gc.copies * gc.pstride; i += blockDim.x) gacc[i] = 0.0;
       cur_v = it.v;
       __syncthreads();
     } else if (USE_LDS) {
       stage_variant_view<float>(S, L, lds);   // tables already in LDS: rebuild the view only
     }
     const AdjView A{coef + (int64_t)bv.goff * 4, grad + bv.poff, bv.tilt, bv.n_params};
-    GradSink gs{grad_in_lds ? gacc : grad + bv.poff};
+    GradSink gs{grad_bytes ? gacc + (threadIdx.x & (gc.copies - 1)) * gc.pstride : grad + bv.poff};
     // the variant's photons, indexed and numbered from its first photon;
     // binned photons carry their index in the whole bundle
     const int64_t off = bv.off;
@@ -89,7 +108,7 @@ k_backward_batch(const BatchVariant<float>* vars, const BatchItem* items, int n_
       // path records are indexed by position in the whole bundle
       if (MODE == kReplay) {
         const uint4 w = reinterpret_cast<const uint4*>(path)[off + i];
-        if (w.x < kPathLong) adjoint_photon_path<float>(USE_LDS ? L : S, Rv, i, A, gs, w);
+        if (w.x < kPathLong) adjoint_photon_path<float, false>(USE_LDS ? L : S, Rv, i, A, gs, w);
       } else if (MODE == kSearchAll || path[(off + i) * kPathSlots] == kPathLong) {
         adjoint_photon<float, MAXE>(USE_LDS ? L : S, Rv, i, A, gs);
       }
@@ -100,19 +119,23 @@ k_backward_batch(const BatchVariant<float>* vars, const BatchItem* items, int n_
 }
 
 // ------------------------------------------------------------------ launcher
+uint32_t batch_grad_lds_bytes(int max_params) {
+  const uint32_t one = (uint32_t)(max_params | 1) * 8u;
+  return one <= kGradLdsMax ? std::min<uint32_t>(kGradLdsMax, 16u * one) : 0u;
+}
+
 template <bool USE_LDS, int MAXE, int MODE>
 static hipError_t backward_batch_k(const BatchView<float>& B, const RaysView<float>& R, const double* coef,
                                    double* grad, int ncu, hipStream_t st, const uint32_t* path) {
-  const size_t gbytes = (size_t)B.max_params * sizeof(double);
-  const bool grad_lds = gbytes <= kGradLdsMax;
-  const size_t shmem = (USE_LDS ? B.blob_cap_bwd : 0) + (grad_lds ? gbytes : 0);
+  const uint32_t gbytes = batch_grad_lds_bytes(B.max_params);
+  const size_t shmem = (USE_LDS ? B.blob_cap_bwd : 0) + gbytes;
   int per_cu = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_backward_batch<USE_LDS, MAXE, MODE>,
                                                               kBlockB, shmem);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
   const int blocks = std::max(1, std::min(B.n_items, ncu * per_cu));
   hipLaunchKernelGGL((k_backward_batch<USE_LDS, MAXE, MODE>), dim3(blocks), dim3(kBlockB), shmem, st, B.vars,
-                     B.items, B.n_items, B.queue, B.blob_cap_bwd, grad_lds ? 1 : 0, R, coef, grad, path);
+                     B.items, B.n_items, B.queue, B.blob_cap_bwd, gbytes, R, coef, grad, path);
   return hipGetLastError();
 }
 
