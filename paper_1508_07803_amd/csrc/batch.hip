@@ -68,19 +68,23 @@ __device__ __forceinline__ void trace_item(const SceneView<float>& L, int64_t st
     PhotonState ps;
     photon_init(ps, V3<float>{oa[0], oa[1], oa[2]}, V3<float>{da[0], da[1], da[2]},
                 R.id_base + (uint64_t)(R.src(cur) - off));
+    uint4 rec = {kPathEnd, kPathEnd, kPathEnd, kPathEnd};   // path record, written once
     while (!ps.fate) {
       const int k = ps.k;
       const uint32_t code = photon_step(L, ps);
-      if (H.path && k < kPathSlots) H.path[cur * kPathSlots + k] = code;
+      if (H.path) {
+        rec.x = k == 0 ? code : rec.x;
+        rec.y = k == 1 ? code : rec.y;
+        rec.z = k == 2 ? code : rec.z;
+        rec.w = k == 3 ? code : rec.w;
+      }
     }
     PhotonOut<float> r = photon_out<float>(ps);
     if (H.path) {
-      uint32_t* w = H.path + cur * kPathSlots;
       const bool is_long = r.fate == FOCUSED && r.nev > kPathSlots;
-      if (r.fate != FOCUSED) w[0] = kPathSkip;
-      else if (is_long) w[0] = kPathLong;
-      else
-        for (int k = r.nev; k < kPathSlots; ++k) w[k] = kPathEnd;
+      if (r.fate != FOCUSED) rec.x = kPathSkip;
+      else if (is_long) rec.x = kPathLong;
+      reinterpret_cast<uint4*>(H.path)[cur] = rec;
       const unsigned long long m = __ballot(is_long);
       if (m && (int)__lane_id() == __ffsll(m) - 1) atomicOr(long_flag, 1u);
     }

@@ -74,18 +74,24 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
     if ((unsigned)g >= (unsigned)S.n_groups) g = -1;
     PhotonState ps;
     photon_init(ps, V3<T>{oa[0], oa[1], oa[2]}, V3<T>{da[0], da[1], da[2]}, R.id_base + (uint64_t)R.src(cur));
+    // the path record is built in registers and written once, as one 16-byte
+    // store (the records of a wave's photons are contiguous)
+    uint4 rec = {kPathEnd, kPathEnd, kPathEnd, kPathEnd};
     while (!ps.fate) {
       const int k = ps.k;
       const uint32_t code = photon_step(L, ps);
-      if (H.path && k < kPathSlots) H.path[cur * kPathSlots + k] = code;
+      if (H.path) {
+        rec.x = k == 0 ? code : rec.x;
+        rec.y = k == 1 ? code : rec.y;
+        rec.z = k == 2 ? code : rec.z;
+        rec.w = k == 3 ? code : rec.w;
+      }
     }
     PhotonOut<T> r = photon_out<T>(ps);
     if (H.path) {
-      uint32_t* w = H.path + cur * kPathSlots;
-      if (r.fate != FOCUSED) w[0] = kPathSkip;
-      else if (r.nev > kPathSlots) w[0] = kPathLong;
-      else
-        for (int k = r.nev; k < kPathSlots; ++k) w[k] = kPathEnd;
+      if (r.fate != FOCUSED) rec.x = kPathSkip;
+      else if (r.nev > kPathSlots) rec.x = kPathLong;
+      reinterpret_cast<uint4*>(H.path)[cur] = rec;
     }
     if (RECORD) {
       const int64_t o = R.src(cur);
