@@ -163,6 +163,7 @@ struct robast_scene {
   size_t blob_bytes = 0;
   DTilt* d_tilt = nullptr;
   double* d_coef = nullptr;    // n_groups * 4 backward coefficients
+  int cell_choice = 0;         // index into kCellFactors chosen by the last upload
   void* d_view = nullptr;      // device copy of sf / sd, read by batched launches
   SceneView<float> sf{};
   SceneView<double> sd{};
@@ -188,7 +189,8 @@ struct robast_scene {
 
 // LDS a workgroup may use for a scene's tables: three workgroups of four
 // waves (the trace kernel's occupancy) share the 160 KiB of a CU.
-constexpr int kLdsCap = (160 * 1024 / 3) & ~15;
+constexpr int kLdsCu = 160 * 1024;
+constexpr int kLdsCap = (kLdsCu / 3) & ~15;
 
 struct robast_batch {
   int precision = 32;
@@ -475,7 +477,7 @@ void to_group(const GroupBuild& g, const double* w, double* x) {
 // Partition the volumes into the always-list and candidate groups and
 // rasterise each group's members onto its grid.
 void build_groups(const robast_scene& s, const std::vector<Box3>& wb, std::vector<uint16_t>& always,
-                  std::vector<GroupBuild>& groups) {
+                  std::vector<GroupBuild>& groups, double cell_factor) {
   int nv = s.n_vol;
   always.clear();
   groups.clear();
@@ -569,15 +571,16 @@ void build_groups(const robast_scene& s, const std::vector<Box3>& wb, std::vecto
     g.zmin -= zp; g.zmax += zp;
     double xp = 1e-5 * (g.x1 - g.x0 + g.y1 - g.y0 + s.l_ref);
     g.x0 -= xp; g.y0 -= xp; g.x1 += xp; g.y1 += xp;
-    // cell from the median footprint of the members that have one (walls
-    // seen edge-on have none), at least 1/256 of the group's extent
+    // cell: cell_factor x the side of the median footprint of the members
+    // that have one (walls seen edge-on have none), at least 1/256 of the
+    // group's extent
     double W = g.x1 - g.x0, H = g.y1 - g.y0;
     std::vector<double> real;
     for (double a : areas)
       if (a > 1e-4 * W * H) real.push_back(a);
     if (real.empty()) real.push_back(W * H / 16.0);
     std::nth_element(real.begin(), real.begin() + real.size() / 2, real.end());
-    g.cell = 0.5 * std::sqrt(real[real.size() / 2]);
+    g.cell = cell_factor * std::sqrt(real[real.size() / 2]);
     g.cell = std::max(g.cell, std::max(W, H) / 256.0);
     g.nx = std::max(1, (int)std::ceil((g.x1 - g.x0) / g.cell));
     g.ny = std::max(1, (int)std::ceil((g.y1 - g.y0) / g.cell));
@@ -633,7 +636,8 @@ void set_bin_frame(robast_scene& s, const std::vector<Box3>& wb) {
 }
 
 template <typename T>
-void compile_blob(robast_scene& s, std::vector<char>& blob, SceneView<T>& V, std::vector<size_t>& offs) {
+void compile_blob(robast_scene& s, std::vector<char>& blob, SceneView<T>& V, std::vector<size_t>& offs,
+                  double cell_factor) {
   int nv = s.n_vol;
   std::vector<DVol<T>> recs(nv);
   std::vector<Box3> wb(nv);
@@ -641,7 +645,7 @@ void compile_blob(robast_scene& s, std::vector<char>& blob, SceneView<T>& V, std
   set_bin_frame(s, wb);
   std::vector<uint16_t> always;
   std::vector<GroupBuild> groups;
-  build_groups(s, wb, always, groups);
+  build_groups(s, wb, always, groups, cell_factor);
   std::vector<GroupRec<T>> grecs(groups.size());
   std::vector<uint32_t> starts;
   std::vector<uint16_t> items;
@@ -717,11 +721,30 @@ std::vector<DTilt> tilt_table(const robast_scene& s) {
   return t;
 }
 
+// Candidate-grid cells of the scene compiler: the finest of these factors
+// (cell side = factor x the side of the median member footprint) whose blob
+// still lets the trace kernel keep four workgroups per CU with the tables in
+// LDS.  Finer cells list fewer candidates per cell, so a search makes fewer
+// box tests and exact tests of neighbouring panels (Schwarzschild-Couder:
+// trace 21.7 ms at 0.5, 19.0 ms at 0.14); the coarsest is used when none fits.
+constexpr double kCellFactors[] = {0.14, 0.18, 0.25, 0.35, 0.5};
+
 int upload(robast_scene* s) {
   std::vector<char> blob;
   std::vector<size_t> offs;
-  if (s->precision == 32) compile_blob<float>(*s, blob, s->sf, offs);
-  else compile_blob<double>(*s, blob, s->sd, offs);
+  const size_t sums_lds = (size_t)s->n_groups * 64 <= 16384 ? (size_t)s->n_groups * 64 : 0;
+  const size_t budget = ((size_t)kLdsCu / 4 - sums_lds) & ~(size_t)15;
+  // a parameter update starts from the previous choice (the tables change
+  // little), a new scene from the finest
+  const int n_f = (int)(sizeof(kCellFactors) / sizeof(kCellFactors[0]));
+  for (int k = s->cell_choice; k < n_f; ++k) {
+    blob.clear();
+    offs.clear();
+    if (s->precision == 32) compile_blob<float>(*s, blob, s->sf, offs, kCellFactors[k]);
+    else compile_blob<double>(*s, blob, s->sd, offs, kCellFactors[k]);
+    s->cell_choice = k;
+    if (blob.size() <= budget) break;
+  }
   std::vector<DTilt> tilt = tilt_table(*s);
   if (blob.size() > s->blob_bytes || !s->d_blob) {
     if (s->d_blob) (void)hipFree(s->d_blob);
