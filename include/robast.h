@@ -159,7 +159,7 @@ int robast_build_scene(const robast_scene_desc* desc, const double* params, int6
  * and is dropped by any other call that bins, by a backward call that used
  * it, by a parameter update and by the autotuner.
  * The call also records each photon's path (its surface sequence, when
- * FOCUSED with at most 4 events; 20 bytes per photon of scene-owned memory,
+ * FOCUSED with at most 4 events; 24 bytes per photon of scene-owned memory,
  * grown by hipMalloc like the binning workspace, n < 2^32).  The next
  * backward call, if it is the next call on the scene after this trace and is
  * given the same arrays, id_base and n, replays the recorded sequences

@@ -882,16 +882,18 @@ int binned_view(robast_scene* s, const robast_rays* rays, int64_t n, hipStream_t
   return ROBAST_OK;
 }
 
-// Path-record buffer for n photons: records, long-record list, count.
+// Path-record buffer for n photons: records, long-record list, the list of
+// four-event records, their two counts.
 size_t path_bytes(int64_t n) {
-  return align256((size_t)n * kPathSlots * 4) + align256((size_t)n * 4) + 256;
+  return align256((size_t)n * kPathSlots * 4) + 2 * align256((size_t)n * 4) + 256;
 }
 
 PathView path_view(const robast_scene* s) {
   char* base = (char*)s->d_path;
   const size_t rec = align256((size_t)s->path_cap * kPathSlots * 4);
   const size_t list = align256((size_t)s->path_cap * 4);
-  return PathView{(const uint32_t*)base, (uint32_t*)(base + rec), (uint32_t*)(base + rec + list)};
+  return PathView{(const uint32_t*)base, (uint32_t*)(base + rec), (uint32_t*)(base + rec + 2 * list),
+                  (uint32_t*)(base + rec + list)};
 }
 
 int ensure_path(robast_scene* s, int64_t n) {

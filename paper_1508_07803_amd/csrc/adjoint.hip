@@ -103,9 +103,24 @@ k_backward(SceneView<T> S, RaysView<T> R, int64_t n, AdjView A, GradLds G, const
   grad_end(gacc, G, A);
 }
 
-// Adjoint from the forward trace's path records: photons with a record of
-// their sequence are swept without a search; those whose record is too long
-// are appended to a list (one atomic per wave) for k_backward.
+// Appends position i of the lanes where `take` holds to list / *count, one
+// atomic per wave.  Reached by every active lane.
+__device__ __forceinline__ void wave_append(bool take, uint32_t i, uint32_t* list, uint32_t* count) {
+  const uint64_t mask = __ballot(take);
+  if (!mask) return;
+  const int leader = __ffsll((unsigned long long)mask) - 1;
+  uint32_t base = 0;
+  if ((int)__lane_id() == leader) base = atomicAdd(count, (uint32_t)__popcll(mask));
+  base = __shfl(base, leader);
+  const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+  if (take) list[base + below] = i;
+}
+
+// Adjoint from the forward trace's path records, main pass: photons with at
+// most kPathSlots - 1 recorded events are swept here without a search (a
+// sweep over three slots fits the registers without spills); those with
+// exactly kPathSlots events go to list4 for k_backward_path4, those whose
+// record is too long to the list for k_backward.
 template <typename T, bool USE_LDS>
 __global__ void __launch_bounds__(kBlockAdj)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1, 8)))
@@ -119,23 +134,39 @@ k_backward_path(SceneView<T> S, RaysView<T> R, int64_t n, AdjView A, GradLds G, 
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     const uint4 w = rec[i];
-    const bool is_long = w.x == kPathLong;
-    const uint64_t mask = __ballot(is_long);
-    if (mask) {
-      const int leader = __ffsll((unsigned long long)mask) - 1;
-      uint32_t base = 0;
-      if ((int)__lane_id() == leader) base = atomicAdd(P.count, (uint32_t)__popcll(mask));
-      base = __shfl(base, leader);
-      const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-      if (is_long) P.list[base + below] = (uint32_t)i;
-    }
-    if (w.x >= kPathLong) continue;
-    adjoint_photon_path<T, true>(L, R, i, A, gs, w);
+    const bool full = w.x < kPathLong && w.w != kPathEnd;
+    wave_append(w.x == kPathLong, (uint32_t)i, P.list, P.count);
+    wave_append(full, (uint32_t)i, P.list4, P.count + 1);
+    if (w.x >= kPathLong || full) continue;
+    adjoint_photon_path<T, true, kPathSlots - 1>(L, R, i, A, gs, w);
   }
   grad_end(gacc, G, A);
 }
 
-__global__ void k_clear_u32(uint32_t* p) { *p = 0u; }
+// The photons of list4 (records of exactly kPathSlots events), swept from
+// their records like the main pass.
+template <typename T, bool USE_LDS>
+__global__ void __launch_bounds__(kBlockAdj)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1, 8)))
+k_backward_path4(SceneView<T> S, RaysView<T> R, AdjView A, GradLds G, PathView P) {
+  extern __shared__ __align__(16) char lds[];
+  SceneView<T> L;
+  stage_adj_scene<T, USE_LDS>(S, L, lds);
+  double* gacc = reinterpret_cast<double*>(lds + (USE_LDS ? ((S.blob_bytes + 15u) & ~15u) : 0u));
+  GradSink gs = grad_begin(gacc, G, A);
+  const uint4* rec = reinterpret_cast<const uint4*>(P.rec);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t m = (int64_t)P.count[1];
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) {
+    const int64_t i = (int64_t)P.list4[j];
+    adjoint_photon_path<T, true, kPathSlots>(L, R, i, A, gs, rec[i]);
+  }
+  grad_end(gacc, G, A);
+}
+
+__global__ void k_clear_u32(uint32_t* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
 
 hipError_t launch_adj_coef(const double* sums, const double* cot, double* coef, int n_groups, hipStream_t st) {
   hipLaunchKernelGGL(k_adj_coef, dim3((n_groups + 63) / 64), dim3(64), 0, st, sums, cot, coef, n_groups);
@@ -180,10 +211,15 @@ static hipError_t launch_bwd_l(const SceneView<T>& S, const RaysView<T>& R, int6
   int blocks = 0;
   hipError_t e;
   if (P) {
-    hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(1), 0, st, P->count);
+    hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(64), 0, st, P->count, 2);
     e = grid_for(k_backward_path<T, USE_LDS>, shmem, n, cfg, blocks);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_backward_path<T, USE_LDS>), dim3(blocks), dim3(kBlockAdj), shmem, st, S, R, n, A, G, *P);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = grid_for(k_backward_path4<T, USE_LDS>, shmem, n, cfg, blocks);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_backward_path4<T, USE_LDS>), dim3(blocks), dim3(kBlockAdj), shmem, st, S, R, A, G, *P);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -358,14 +358,17 @@ template <typename T> __device__ __forceinline__ DVol<double> promote(const DVol
 }
 
 // Adjoint of one photon from its path record (see kPathSlots): no search.
-// The states entering the (at most kPathSlots) events are replayed once,
-// forward, and kept in registers; the reverse sweep then reads them back.
+// The states entering its events (at most NS <= kPathSlots of them: the
+// caller passes only records that short) are replayed once, forward, and
+// kept in registers; the reverse sweep then reads them back.  NS sizes the
+// register arrays: a sweep over 3 slots needs no spills, over 4 it does.
 // PROMOTE: convert each event's volume record to double once (fewer
 // instructions) rather than field by field as read (fewer registers); which
 // is faster depends on the register pressure of the calling kernel.
-template <typename T, bool PROMOTE>
+template <typename T, bool PROMOTE, int NS = kPathSlots>
 __device__ __forceinline__ void adjoint_photon_path(const SceneView<T>& L, const RaysView<T>& R, int64_t i,
                                                     const AdjView& A, GradSink& gs, uint4 w) {
+  static_assert(NS >= 1 && NS <= kPathSlots, "slots of a path record");
   const int g = R.grp(i);
   if ((unsigned)g >= (unsigned)L.n_groups) return;
   const double* cf = A.coef + 4 * g;
@@ -374,12 +377,12 @@ __device__ __forceinline__ void adjoint_photon_path(const SceneView<T>& L, const
   R.load(i, oa, da);
   const uint32_t codes[kPathSlots] = {w.x, w.y, w.z, w.w};
   const int nev = w.y == kPathEnd ? 1 : w.z == kPathEnd ? 2 : w.w == kPathEnd ? 3 : 4;
-  PathState st[kPathSlots];
+  PathState st[NS];
   V3<double> O = {(double)oa[0], (double)oa[1], (double)oa[2]};
   V3<double> d = {(double)da[0], (double)da[1], (double)da[2]};
   int pv = -1, pf = -1, ps = 0;
 #pragma unroll
-  for (int e = 0; e < kPathSlots; ++e) {
+  for (int e = 0; e < NS; ++e) {
     if (e < nev) {
       const int vid = (int)(codes[e] >> 8), face = (int)((codes[e] >> 4) & 15u), act = (int)(codes[e] & 15u);
       double t, s;
@@ -404,7 +407,7 @@ __device__ __forceinline__ void adjoint_photon_path(const SceneView<T>& L, const
   V3<double> Xb = {cf[0] * ((double)(T)O.x - cf[1]), cf[0] * ((double)(T)O.y - cf[2]), 0.0};
   V3<double> db = {0.0, 0.0, (T)d.z >= T(0) ? cf[3] : -cf[3]};
 #pragma unroll
-  for (int e = kPathSlots - 1; e >= 0; --e) {
+  for (int e = NS - 1; e >= 0; --e) {
     if (e < nev) {
       const int vid = (int)(codes[e] >> 8), face = (int)((codes[e] >> 4) & 15u), act = (int)(codes[e] & 15u);
       if constexpr (PROMOTE) {

@@ -65,13 +65,16 @@ struct AdjView {
   int n_params;
 };
 
-// Path records of the forward trace for the adjoint, and the list of the
-// photons whose record is kPathLong (positions in the traced order, with
-// their count; the count is cleared by the backward launch).
+// Path records of the forward trace for the adjoint, and two lists filled
+// by the adjoint's main pass (positions in the traced order, with their
+// counts, cleared by the backward launch): the photons whose record holds
+// exactly kPathSlots events (list4, count[1]) and those whose record is
+// kPathLong (list, count[0]).
 struct PathView {
   const uint32_t* rec;
   uint32_t* list;
-  uint32_t* count;
+  uint32_t* count;   // 2 counters
+  uint32_t* list4;
 };
 
 template <typename T>
