@@ -143,3 +143,67 @@ def test_kept_order_reused_by_backward(rb):
     dev.backward(other, s2, cot, g2)
     torch.cuda.synchronize()
     assert torch.allclose(g1, g2, rtol=1e-9, atol=1e-12 * float(g2.abs().max()))
+
+
+def test_path_records_dropped_when_stale(rb):
+    """The path records of a trace that kept its order are used only by the
+    next backward call on the same photons and scene; a parameter update, a
+    different count or id_base, or an intervening call makes the backward
+    call search again, with the gradient of an independent computation."""
+    sc = scenes.schwarzschild_couder()
+    r = sc.rays(2500)
+    rays_host = r
+    cot = torch.zeros(sc.n_groups, 2, dtype=torch.float64, device="cuda")
+    cot[:, 0] = 1.0 / sc.n_groups
+
+    def fresh(params, n=None, id_base=0):
+        d = rb.Scene(sc)
+        d.update_params(params)
+        rays = d.upload_rays(rays_host)
+        s = d.new_sums()
+        d.trace(rays, sums=s, n=n, id_base=id_base)
+        g = torch.zeros(len(sc.params), dtype=torch.float64, device="cuda")
+        d.backward(rays, s, cot, g, n=n, id_base=id_base)
+        torch.cuda.synchronize()
+        return s, g
+
+    def close(a, b):
+        return torch.allclose(a, b, rtol=1e-9, atol=1e-12 * float(b.abs().max()))
+
+    dev = rb.Scene(sc)
+    rays = dev.upload_rays(r)
+    n = int(rays["ox"].numel())
+    # parameter update between the trace and the backward call
+    p2 = np.array(sc.params) * (1 + 1e-4)
+    s = dev.new_sums()
+    dev.trace(rays, sums=s, keep_order=True)
+    dev.update_params(p2)
+    s2 = dev.new_sums()
+    dev.trace(rays, sums=s2)                 # sums of the updated scene, order not kept
+    g = torch.zeros(len(sc.params), dtype=torch.float64, device="cuda")
+    dev.backward(rays, s2, cot, g)
+    torch.cuda.synchronize()
+    ref_s, ref_g = fresh(p2)
+    assert close(s2, ref_s) and close(g, ref_g)
+    # a backward call on fewer photons than the kept trace (another binned
+    # order): it must search, as after a trace that kept nothing
+    m = n - 777
+    s = dev.new_sums()
+    dev.trace(rays, sums=s, keep_order=True)
+    ga = torch.zeros(len(sc.params), dtype=torch.float64, device="cuda")
+    dev.backward(rays, s, cot, ga, n=m)
+    sp = dev.new_sums()
+    dev.trace(rays, sums=sp)
+    gb = torch.zeros_like(ga)
+    dev.backward(rays, sp, cot, gb, n=m)
+    torch.cuda.synchronize()
+    assert close(s, sp) and close(ga, gb)
+    # the records are one-shot: a second backward call searches again
+    s = dev.new_sums()
+    dev.trace(rays, sums=s, keep_order=True)
+    g1 = torch.zeros(len(sc.params), dtype=torch.float64, device="cuda")
+    g2 = torch.zeros_like(g1)
+    dev.backward(rays, s, cot, g1)
+    dev.backward(rays, s, cot, g2)
+    torch.cuda.synchronize()
+    assert close(g1, g2)
