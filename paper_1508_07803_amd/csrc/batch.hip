@@ -85,7 +85,9 @@ __device__ __forceinline__ void trace_item(const SceneView<float>& L, int64_t st
       if (r.fate != FOCUSED) rec.x = kPathSkip;
       else if (is_long) rec.x = kPathLong;
       reinterpret_cast<uint4*>(H.path)[cur] = rec;
-      const unsigned long long m = __ballot(is_long);
+      // the batched adjoint replays records of up to kPathSlots - 1 events;
+      // the rest are found again by its search pass, which this flag enables
+      const unsigned long long m = __ballot(r.fate == FOCUSED && r.nev >= kPathSlots);
       if (m && (int)__lane_id() == __ffsll(m) - 1) atomicOr(long_flag, 1u);
     }
     if (RECORD) {

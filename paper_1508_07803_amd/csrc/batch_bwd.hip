@@ -36,11 +36,18 @@ struct GradCopies {
 };
 
 // Photon selection of a batched adjoint launch: every photon, searched
-// again (kSearchAll); only the photons whose path record is kPathLong,
-// searched again (kSearchLong; the launch ends at once when the forward
-// launch flagged none); every photon with a path record, replayed from it
-// (kReplay).
+// again (kSearchAll); only the photons whose path record the replay leaves
+// (searched_again), searched again (kSearchLong; the launch ends at once
+// when the forward launch flagged none); every photon whose record holds
+// at most kPathSlots - 1 events, replayed from it (kReplay).
 constexpr int kSearchAll = 0, kSearchLong = 1, kReplay = 2;
+
+// Records the replay pass leaves to the search pass: too long, or holding
+// all kPathSlots events (the replay keeps at most kPathSlots - 1 states in
+// registers, which fits without spills).
+__device__ __forceinline__ bool searched_again(uint4 w) {
+  return w.x == kPathLong || (w.x < kPathLong && w.w != kPathEnd);
+}
 
 // Per-variant state (view, tilt table, slices) is re-derived from the
 // variant table for every item rather than carried across items, which
@@ -108,8 +115,9 @@ k_backward_batch(const BatchVariant<float>* vars, const BatchItem* items, int n_
       // path records are indexed by position in the whole bundle
       if (MODE == kReplay) {
         const uint4 w = reinterpret_cast<const uint4*>(path)[off + i];
-        if (w.x < kPathLong) adjoint_photon_path<float, false>(USE_LDS ? L : S, Rv, i, A, gs, w);
-      } else if (MODE == kSearchAll || path[(off + i) * kPathSlots] == kPathLong) {
+        if (w.x < kPathLong && w.w == kPathEnd)
+          adjoint_photon_path<float, false, kPathSlots - 1>(USE_LDS ? L : S, Rv, i, A, gs, w);
+      } else if (MODE == kSearchAll || searched_again(reinterpret_cast<const uint4*>(path)[off + i])) {
         adjoint_photon<float, MAXE>(USE_LDS ? L : S, Rv, i, A, gs);
       }
     }
