@@ -61,10 +61,12 @@ COST = {
 PULLBACK = {"plane": 150, "sphere": 300, "asphere": 420, "cylinder": 250, "box": 200, "hexcone": 600}
 SHAPE_NAME = {1: "plane", 2: "sphere", 3: "asphere", 4: "cylinder", 5: "box", 6: "hexcone"}
 
-# sources each kernel is built from (its counters go stale when they change)
+# sources each kernel is built from, and the scene compiler that lays out
+# its tables (its counters go stale when any of them changes)
 KERNEL_SOURCES = {
-    "k_trace": ["device_trace.hpp", "kernels.hip", "kernels.hpp", "scene_layout.hpp"],
-    "k_backward_path": ["device_trace.hpp", "adjoint_device.hpp", "adjoint.hip", "kernels.hpp", "scene_layout.hpp"],
+    "k_trace": ["device_trace.hpp", "kernels.hip", "kernels.hpp", "scene_layout.hpp", "abi.cpp"],
+    "k_backward_path": ["device_trace.hpp", "adjoint_device.hpp", "adjoint.hip", "kernels.hpp", "scene_layout.hpp",
+                        "abi.cpp"],
 }
 TRAFFIC_SUMMARY = os.path.join("profiles", "k_trace_k_backward_sc_16x1e7_hbm_traffic.md")
 
