@@ -184,6 +184,21 @@ int robast_trace(robast_scene* scene, const robast_rays* rays, int64_t n, const 
 int robast_figures(robast_scene* scene, const double* d_group_sums, double* d_figures,
                    void* hip_stream);
 
+/* Arrival-time spread (isochronicity) per group, from the per-photon
+ * records of a trace of photons [0, n): over the FOCUSED photons of group g
+ * (rays->group, or group 0 when NULL), d_out[4 g .. 4 g + 3] = {count, mean
+ * optical path length from the start point to the focal surface, RMS
+ * spread of that length, 0} (FP64, metres; arrival time x c).  The optical
+ * path is the one the trace records per photon (sum of n x distance over
+ * the events; the paper's segmented-dish models, section on CTA
+ * telescopes, differ in it: a parabolic dish is isochronous on axis, a
+ * Davies-Cotton dish is not).  Reads hits->fate and hits->opl (the scene's
+ * precision), indexed like the rays; d_out [device] n_groups * 4 doubles,
+ * overwritten.  EINVAL on NULL scene, rays, hits, fate, opl or d_out, n < 0.
+ * Two passes over the records (mean, then squared deviations). */
+int robast_arrival_figures(robast_scene* scene, const robast_rays* rays, const robast_hits* hits, int64_t n,
+                           double* d_out, void* hip_stream);
+
 /* Reverse mode along each photon's fixed surface sequence (pathwise
  * gradient; fates and sequences are re-derived with the same draws, so they
  * equal the forward ones, or read from the path record of the preceding

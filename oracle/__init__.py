@@ -216,6 +216,23 @@ def figures(rec, n_groups):
     return out
 
 
+def arrival_figures(rec, n_groups):
+    """Per group: FOCUSED photons, the mean and the RMS spread of their
+    optical path length from the start point to the focal surface (arrival
+    time x c): the spread is the isochronicity of the optics.  Two passes
+    (mean, then mean squared deviation), in FP64."""
+    g = rec["group"].astype(np.int64)
+    foc = rec["fate"] == FATE_FOCUSED
+    out = []
+    for k in range(n_groups):
+        p = np.asarray(rec["opl"], dtype=np.float64)[foc & (g == k)]
+        nf = len(p)
+        mean = float(p.mean()) if nf else 0.0
+        rms = float(np.sqrt(np.mean((p - mean) ** 2))) if nf else 0.0
+        out.append(dict(focused=nf, mean=mean, rms=rms))
+    return out
+
+
 def rms_cotangent(rec, n_groups, dL_drms):
     """dL/d(x, y) per photon for L = sum_g dL_drms[g] * RMS_g (zero for non-FOCUSED)."""
     fig = figures(rec, n_groups)

@@ -29,7 +29,8 @@ SYMBOLS = ["robast_build_scene", "robast_trace", "robast_figures", "robast_trace
            "robast_update_params", "robast_destroy_scene", "robast_status_string",
            "robast_last_error", "robast_abi_version", "robast_build_batch", "robast_trace_batch",
            "robast_figures_batch", "robast_trace_backward_batch", "robast_batch_sizes", "robast_destroy_batch",
-           "robast_get_tuning", "robast_set_tuning", "robast_autotune", "robast_bin_photons"]
+           "robast_get_tuning", "robast_set_tuning", "robast_autotune", "robast_bin_photons",
+           "robast_arrival_figures"]
 
 
 class VolumeDesc(ctypes.Structure):
@@ -96,12 +97,14 @@ _lib.robast_set_tuning.argtypes = [ctypes.c_void_p, ctypes.POINTER(Tuning)]
 _lib.robast_autotune.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ctypes.c_int64, ctypes.POINTER(Tuning),
                                  ctypes.c_void_p]
 _lib.robast_bin_photons.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ctypes.c_int64, ctypes.c_void_p]
+_lib.robast_arrival_figures.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ctypes.POINTER(Hits), ctypes.c_int64,
+                                        ctypes.c_void_p, ctypes.c_void_p]
 _lib.robast_destroy_batch.argtypes = [ctypes.c_void_p]
 _lib.robast_destroy_batch.restype = None
 for _name in ("robast_build_scene", "robast_trace", "robast_figures", "robast_trace_backward",
               "robast_update_params", "robast_abi_version", "robast_build_batch", "robast_trace_batch",
               "robast_figures_batch", "robast_trace_backward_batch", "robast_batch_sizes", "robast_get_tuning",
-              "robast_set_tuning", "robast_autotune", "robast_bin_photons"):
+              "robast_set_tuning", "robast_autotune", "robast_bin_photons", "robast_arrival_figures"):
     getattr(_lib, _name).restype = ctypes.c_int
 
 
@@ -299,6 +302,21 @@ class Scene:
                                      ("fig", fig, self.n_groups * FIGURE_STRIDE)])
         _check(_lib.robast_figures(self._h, _ptr(sums), _ptr(fig), _stream(stream)), "robast_figures")
         return fig.view(self.n_groups, FIGURE_STRIDE)
+
+    def arrival_figures(self, rays, hits, n=None, out=None, stream=None):
+        """Per group (count, mean optical path, RMS optical path spread, 0) of
+        the FOCUSED photons in the per-photon records `hits` (fate, opl) of a
+        trace of these photons; returns an (n_groups, 4) FP64 tensor."""
+        import torch
+        n = int(rays["ox"].numel()) if n is None else int(n)
+        if out is None:
+            out = torch.zeros(self.n_groups * 4, dtype=torch.float64, device=hits["fate"].device)
+        _check_extents(n, self.dtype, rays, {k: hits[k] for k in ("fate", "opl")}, [("out", out, self.n_groups * 4)])
+        H = _hits_struct(hits, None)
+        R = self._rays_struct(rays, 0)
+        _check(_lib.robast_arrival_figures(self._h, ctypes.byref(R), ctypes.byref(H), n, _ptr(out), _stream(stream)),
+               "robast_arrival_figures")
+        return out.view(self.n_groups, 4)
 
     def backward(self, rays, sums, cot, grad, n=None, id_base=0, stream=None):
         """Accumulate dL/dparams into grad for L = sum_g cot[g,0] RMS_g + cot[g,1] effw_g."""

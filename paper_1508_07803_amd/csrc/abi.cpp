@@ -1077,6 +1077,20 @@ int robast_figures(robast_scene* s, const double* sums, double* fig, void* strea
   return ROBAST_OK;
 }
 
+int robast_arrival_figures(robast_scene* s, const robast_rays* rays, const robast_hits* hits, int64_t n,
+                           double* out, void* stream) {
+  if (!s || !rays || !hits || !out) return fail(ROBAST_EINVAL, "NULL scene, rays, hits or out");
+  if (!hits->fate || !hits->opl) return fail(ROBAST_EINVAL, "hits need fate and opl");
+  if (n < 0) return fail(ROBAST_EINVAL, "n < 0");
+  hipError_t e = s->precision == 32
+                     ? launch_arrival<float>(hits->fate, (const float*)hits->opl, rays->group, n, s->n_groups, out,
+                                             (hipStream_t)stream)
+                     : launch_arrival<double>(hits->fate, (const double*)hits->opl, rays->group, n, s->n_groups,
+                                              out, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "arrival figures launch");
+  return ROBAST_OK;
+}
+
 int robast_trace_backward(robast_scene* s, const robast_rays* rays, int64_t n, const double* sums,
                           const double* cot, double* grad, void* stream) {
   if (!s || !rays || !sums || !cot || !grad) return fail(ROBAST_EINVAL, "NULL scene, rays, sums, cot or grad");

@@ -144,6 +144,82 @@ __global__ void k_figures(const double* sums, double* fig, int n_groups) {
   f[7] = 0.0;
 }
 
+// Arrival-time spread (isochronicity) of the FOCUSED photons of each group
+// from the per-photon records, in two passes over them: PASS 0 sums the
+// count and the optical path lengths, PASS 1 the squared deviations from
+// the group's mean (kept apart so that a spread of millimetres over paths
+// of tens of metres is not lost to cancellation).  Each lane sums the
+// photons it visits for one group at a time and adds them to LDS when its
+// group changes; LDS is added to out once per workgroup.
+template <typename T, int PASS>
+__global__ void __launch_bounds__(kBlock) k_arrival(const uint8_t* fate, const T* opl, const uint32_t* group,
+                                                    int64_t n, int n_groups, double* out, int in_lds) {
+  extern __shared__ __align__(16) char lds[];
+  double* acc = reinterpret_cast<double*>(lds);
+  if (in_lds)
+    for (int i = threadIdx.x; i < 2 * n_groups; i += blockDim.x) acc[i] = 0.0;
+  __syncthreads();
+  double* target = in_lds ? acc : nullptr;
+  int ag = -1;
+  double c = 0.0, v = 0.0;
+  auto flush = [&]() {
+    if (ag < 0) return;
+    if (in_lds) {
+      if (PASS == 0) atomicAdd(target + 2 * ag, c);
+      atomicAdd(target + 2 * ag + 1, v);
+    } else {
+      if (PASS == 0) atomicAdd(out + 4 * ag, c);
+      atomicAdd(out + 4 * ag + 1 + PASS, v);
+    }
+    c = 0.0;
+    v = 0.0;
+  };
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    if (fate[i] != FOCUSED) continue;
+    const int g = group ? (int)group[i] : 0;
+    if (g < 0 || g >= n_groups) continue;
+    if (g != ag) {
+      flush();
+      ag = g;
+    }
+    const double p = (double)opl[i];
+    if (PASS == 0) {
+      c += 1.0;
+      v += p;
+    } else {
+      const double dv = p - out[4 * g + 1];
+      v += dv * dv;
+    }
+  }
+  flush();
+  if (in_lds) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 * n_groups; i += blockDim.x) {
+      const int g = i >> 1, k = i & 1;
+      if (acc[i] == 0.0) continue;
+      if (k == 0 && PASS == 0) atomicAdd(out + 4 * g, acc[i]);
+      if (k == 1) atomicAdd(out + 4 * g + 1 + PASS, acc[i]);
+    }
+  }
+}
+
+// Clears out (a kernel, so that a captured graph can replay it), or turns
+// the pass sums into the mean (PASS 0) and the RMS spread (PASS 1).
+template <int PASS>
+__global__ void k_arrival_step(double* out, int n_groups) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_groups) return;
+  double* o = out + 4 * g;
+  if (PASS < 0) {
+    o[0] = o[1] = o[2] = o[3] = 0.0;
+  } else if (PASS == 0) {
+    o[1] = o[0] > 0.0 ? o[1] / o[0] : 0.0;
+  } else {
+    o[2] = o[0] > 0.0 ? sqrt(o[2] / o[0]) : 0.0;
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 static int g_num_cu = 0;
 
@@ -204,6 +280,31 @@ hipError_t launch_figures(const double* sums, double* fig, int n_groups, hipStre
   hipLaunchKernelGGL(k_figures, dim3((n_groups + 63) / 64), dim3(64), 0, st, sums, fig, n_groups);
   return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_arrival(const uint8_t* fate, const T* opl, const uint32_t* group, int64_t n, int n_groups,
+                          double* out, hipStream_t st) {
+  int ncu = 0;
+  hipError_t e = device_cus(ncu);
+  if (e != hipSuccess) return e;
+  const size_t lds = (size_t)n_groups * 2 * sizeof(double);
+  const int in_lds = lds <= 16384 ? 1 : 0;
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, (int64_t)ncu * 8));
+  const dim3 gsteps((n_groups + 63) / 64);
+  hipLaunchKernelGGL(k_arrival_step<-1>, gsteps, dim3(64), 0, st, out, n_groups);
+  hipLaunchKernelGGL((k_arrival<T, 0>), dim3(blocks), dim3(kBlock), in_lds ? lds : 0, st, fate, opl, group, n,
+                     n_groups, out, in_lds);
+  hipLaunchKernelGGL(k_arrival_step<0>, gsteps, dim3(64), 0, st, out, n_groups);
+  hipLaunchKernelGGL((k_arrival<T, 1>), dim3(blocks), dim3(kBlock), in_lds ? lds : 0, st, fate, opl, group, n,
+                     n_groups, out, in_lds);
+  hipLaunchKernelGGL(k_arrival_step<1>, gsteps, dim3(64), 0, st, out, n_groups);
+  return hipGetLastError();
+}
+
+template hipError_t launch_arrival<float>(const uint8_t*, const float*, const uint32_t*, int64_t, int, double*,
+                                          hipStream_t);
+template hipError_t launch_arrival<double>(const uint8_t*, const double*, const uint32_t*, int64_t, int, double*,
+                                           hipStream_t);
 
 template hipError_t launch_trace<float>(const SceneView<float>&, const RaysView<float>&, int64_t,
                                         const HitsView<float>&, const LaunchCfg&, hipStream_t);

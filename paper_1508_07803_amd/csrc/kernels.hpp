@@ -81,6 +81,12 @@ template <typename T>
 hipError_t launch_trace(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const HitsView<T>& H,
                         const LaunchCfg& cfg, hipStream_t st);
 hipError_t launch_figures(const double* sums, double* fig, int n_groups, hipStream_t st);
+// Arrival-time spread per group from per-photon records (see
+// robast_arrival_figures): out[4 g .. 4 g + 3] = {FOCUSED photons, mean
+// optical path, RMS optical path spread, 0}.
+template <typename T>
+hipError_t launch_arrival(const uint8_t* fate, const T* opl, const uint32_t* group, int64_t n, int n_groups,
+                          double* out, hipStream_t st);
 hipError_t launch_adj_coef(const double* sums, const double* cot, double* coef, int n_groups,
                            hipStream_t st);
 // With `P` (non-null) the photons' sequences are read from the forward

@@ -193,6 +193,92 @@ def single_mirror(seed=SEED_BASE + 0):
 
 
 # ================================================================ C2
+def _hex_lattice(pitch, rmax):
+    """Centres of a hexagonal lattice of pitch `pitch` inside radius rmax,
+    origin removed, sorted by (r, phi): tuples (r, phi, x, y)."""
+    centres = []
+    for i in range(-10, 11):
+        for j in range(-10, 11):
+            x = pitch * (i + 0.5 * j)
+            y = pitch * (math.sqrt(3.0) / 2.0) * j
+            r = math.hypot(x, y)
+            if r <= rmax and (i, j) != (0, 0):
+                centres.append((r, math.atan2(y, x), x, y))
+    centres.sort()
+    return centres
+
+
+def _facet_volumes(centres, surface_z, axis_of, radii, tilts, half_flat, reflectivity):
+    """Hexagonal spherical facets: facet k centred on the dish surface at
+    centre k, with optical axis axis_of(centre), radius radii[k] and a
+    hexagonal outline in the plane normal to its axis, tilted by tilts[k]
+    about its local x then y axes.  Parameters: radii, then 2 tilts each."""
+    nf = len(centres)
+    vols, params, names = [], [], []
+    params.extend(radii); names.extend([f"facet{k}_R" for k in range(nf)])
+    for k in range(nf):
+        params.extend(tilts[k]); names.extend([f"facet{k}_tilt_x", f"facet{k}_tilt_y"])
+    for k, (r, _, x, y) in enumerate(centres):
+        cen = np.array([x, y, surface_z(r)])
+        Q0 = frame_from_axes(axis_of(cen))
+        e1, e2 = Q0[0].copy(), Q0[1].copy()
+        Q, c = tilted_frame(Q0, cen, cen, e1, e2, tilts[k][0], tilts[k][1])
+        v = new_volume(ROLE_MIRROR, SHAPE_SPHERE, OUTLINE_HEX, Q=Q, c=c, p=[1.0 / radii[k]],
+                       o=[half_flat], reflectivity=reflectivity, shape_param=k, tilt_param=nf + 2 * k)
+        v["Q0"], v["c0"], v["pivot"], v["e1"], v["e2"] = Q0.reshape(9), cen, cen, e1, e2
+        vols.append(v)
+    return vols, params, names
+
+
+def _dish_camera_and_masts(f, rmax, zrim):
+    """A 3 m x 3 m focal plane at z = f facing the dish, closed by 5
+    absorbing rectangles (1 m deep), and four absorbing masts (r = 0.1 m)
+    from the dish rim at z = zrim to the camera corners."""
+    vols = []
+    flip = np.diag([1.0, -1.0, -1.0])
+    vols.append(new_volume(ROLE_FOCAL, SHAPE_PLANE, OUTLINE_RECT, Q=flip, c=(0, 0, f), o=[1.5, 1.5]))
+    vols.append(new_volume(ROLE_OBSCURATION, SHAPE_PLANE, OUTLINE_RECT, c=(0, 0, f + 1.0), o=[1.5, 1.5]))
+    for sx in (1.0, -1.0):
+        Q = frame_from_axes((sx, 0, 0), x_hint=(0, 0, 1))
+        vols.append(new_volume(ROLE_OBSCURATION, SHAPE_PLANE, OUTLINE_RECT, Q=Q,
+                               c=(1.5 * sx, 0, f + 0.5), o=[0.5, 1.5]))
+    for sy in (1.0, -1.0):
+        Q = frame_from_axes((0, sy, 0), x_hint=(0, 0, 1))
+        vols.append(new_volume(ROLE_OBSCURATION, SHAPE_PLANE, OUTLINE_RECT, Q=Q,
+                               c=(0, 1.5 * sy, f + 0.5), o=[0.5, 1.5]))
+    for kk in range(4):
+        ph = math.radians(45.0 + 90.0 * kk)
+        base = np.array([rmax * math.cos(ph), rmax * math.sin(ph), zrim])
+        top = np.array([1.5 * np.sign(math.cos(ph)), 1.5 * np.sign(math.sin(ph)), f])
+        ax = top - base
+        vols.append(new_volume(ROLE_OBSCURATION, SHAPE_CYLINDER, Q=frame_from_axes(ax), c=base,
+                               p=[0.1, float(np.linalg.norm(ax))]))
+    return vols
+
+
+def _dish_rays(r_beam, back):
+    """Parallel beams at the groups' field angles (in the x-z plane), uniform
+    over a disc of radius r_beam normal to the beam, starting `back` metres
+    before the origin."""
+    def rays(scene, n, s, gsel):
+        rng2 = np.random.default_rng(s)
+        out = []
+        for g in gsel:
+            th = scene.groups[g]
+            d = np.array([math.sin(th), 0.0, -math.cos(th)])
+            e1v = np.array([math.cos(th), 0.0, math.sin(th)])
+            e2v = np.array([0.0, 1.0, 0.0])
+            u1, u2 = rng2.random(n), rng2.random(n)
+            r, ph = r_beam * np.sqrt(u1), 2.0 * np.pi * u2
+            px, py = r * np.cos(ph), r * np.sin(ph)
+            o = -back * d[None, :] + px[:, None] * e1v[None, :] + py[:, None] * e2v[None, :]
+            out.append((o[:, 0], o[:, 1], o[:, 2], np.full(n, d[0]), np.full(n, d[1]),
+                        np.full(n, d[2]), np.full(n, g)))
+        cols = [np.concatenate(c) for c in zip(*out)]
+        return _pack_rays(scene.precision, *cols)
+    return rays
+
+
 def davies_cotton(seed=SEED_BASE + 1, sigma_tilt=1e-4, fields_deg=(0.0, 0.5, 1.0, 1.5, 2.0),
                   radius_scale=None, tilts=None, precision=32):
     """Davies-Cotton dish, f = 28 m, 198 hexagonal spherical facets.
@@ -209,75 +295,58 @@ def davies_cotton(seed=SEED_BASE + 1, sigma_tilt=1e-4, fields_deg=(0.0, 0.5, 1.0
     """
     f, pitch, rmax, half_flat = 28.0, 1.55, 11.5, 0.755
     rng = np.random.default_rng(seed)
-    centres = []
-    for i in range(-10, 11):
-        for j in range(-10, 11):
-            x = pitch * (i + 0.5 * j)
-            y = pitch * (math.sqrt(3.0) / 2.0) * j
-            r = math.hypot(x, y)
-            if r <= rmax and (i, j) != (0, 0):
-                centres.append((r, math.atan2(y, x), x, y))
-    centres.sort()
+    centres = _hex_lattice(pitch, rmax)
     assert len(centres) == 198
     nf = len(centres)
     if tilts is None:
         tilts = rng.normal(0.0, sigma_tilt, size=(nf, 2))
     radii = np.full(nf, 2.0 * f) if radius_scale is None else 2.0 * f * np.asarray(radius_scale)
-    vols, params, names = [], [], []
-    params.extend(radii); names.extend([f"facet{k}_R" for k in range(nf)])
-    for k in range(nf):
-        params.extend(tilts[k]); names.extend([f"facet{k}_tilt_x", f"facet{k}_tilt_y"])
-    for k, (r, _, x, y) in enumerate(centres):
-        cz = f - math.sqrt(f * f - r * r)
-        cen = np.array([x, y, cz])
-        axis = np.array([0.0, 0.0, 2.0 * f]) - cen
-        Q0 = frame_from_axes(axis)
-        e1, e2 = Q0[0].copy(), Q0[1].copy()
-        Q, c = tilted_frame(Q0, cen, cen, e1, e2, tilts[k][0], tilts[k][1])
-        v = new_volume(ROLE_MIRROR, SHAPE_SPHERE, OUTLINE_HEX, Q=Q, c=c, p=[1.0 / radii[k]],
-                       o=[half_flat], reflectivity=0.9, shape_param=k, tilt_param=nf + 2 * k)
-        v["Q0"], v["c0"], v["pivot"], v["e1"], v["e2"] = Q0.reshape(9), cen, cen, e1, e2
-        vols.append(v)
-    flip = np.diag([1.0, -1.0, -1.0])
-    # camera: focal plane (front towards the dish) + absorbing walls and lid
-    vols.append(new_volume(ROLE_FOCAL, SHAPE_PLANE, OUTLINE_RECT, Q=flip, c=(0, 0, f), o=[1.5, 1.5]))
-    vols.append(new_volume(ROLE_OBSCURATION, SHAPE_PLANE, OUTLINE_RECT, c=(0, 0, f + 1.0), o=[1.5, 1.5]))
-    for sx in (1.0, -1.0):
-        Q = frame_from_axes((sx, 0, 0), x_hint=(0, 0, 1))
-        vols.append(new_volume(ROLE_OBSCURATION, SHAPE_PLANE, OUTLINE_RECT, Q=Q,
-                               c=(1.5 * sx, 0, f + 0.5), o=[0.5, 1.5]))
-    for sy in (1.0, -1.0):
-        Q = frame_from_axes((0, sy, 0), x_hint=(0, 0, 1))
-        vols.append(new_volume(ROLE_OBSCURATION, SHAPE_PLANE, OUTLINE_RECT, Q=Q,
-                               c=(0, 1.5 * sy, f + 0.5), o=[0.5, 1.5]))
-    zrim = f - math.sqrt(f * f - rmax * rmax)
-    for kk in range(4):
-        ph = math.radians(45.0 + 90.0 * kk)
-        base = np.array([rmax * math.cos(ph), rmax * math.sin(ph), zrim])
-        top = np.array([1.5 * np.sign(math.cos(ph)), 1.5 * np.sign(math.sin(ph)), f])
-        ax = top - base
-        vols.append(new_volume(ROLE_OBSCURATION, SHAPE_CYLINDER, Q=frame_from_axes(ax), c=base,
-                               p=[0.1, float(np.linalg.norm(ax))]))
+    vols, params, names = _facet_volumes(centres, lambda r: f - math.sqrt(f * f - r * r),
+                                         lambda cen: np.array([0.0, 0.0, 2.0 * f]) - cen, radii, tilts,
+                                         half_flat, 0.9)
+    vols += _dish_camera_and_masts(f, rmax, f - math.sqrt(f * f - rmax * rmax))
     groups = np.radians(np.asarray(fields_deg, dtype=np.float64))
+    return _finish("davies_cotton", vols, params, names, precision, 16, seed, 28.0, groups, _dish_rays(12.0, 40.0),
+                   n_facets=nf, focal_length=f, beam=dict(kind="disc_perp", r_in=0.0, r_out=12.0, back=40.0))
 
-    def rays(scene, n, s, gsel):
-        rng2 = np.random.default_rng(s)
-        out = []
-        for g in gsel:
-            th = scene.groups[g]
-            d = np.array([math.sin(th), 0.0, -math.cos(th)])
-            e1v = np.array([math.cos(th), 0.0, math.sin(th)])
-            e2v = np.array([0.0, 1.0, 0.0])
-            u1, u2 = rng2.random(n), rng2.random(n)
-            r, ph = 12.0 * np.sqrt(u1), 2.0 * np.pi * u2
-            px, py = r * np.cos(ph), r * np.sin(ph)
-            o = -40.0 * d[None, :] + px[:, None] * e1v[None, :] + py[:, None] * e2v[None, :]
-            out.append((o[:, 0], o[:, 1], o[:, 2], np.full(n, d[0]), np.full(n, d[1]),
-                        np.full(n, d[2]), np.full(n, g)))
-        cols = [np.concatenate(c) for c in zip(*out)]
-        return _pack_rays(scene.precision, *cols)
 
-    return _finish("davies_cotton", vols, params, names, precision, 16, seed, 28.0, groups, rays,
+def lst_parabolic(seed=SEED_BASE + 8, sigma_tilt=1e-4, fields_deg=(0.0, 0.5, 1.0, 1.5, 2.0),
+                  radius_scale=None, tilts=None, precision=32):
+    """Segmented parabolic dish (the LST layout: 198 mirrors aligned on a
+    parabola), f = 28 m, on the Davies-Cotton lattice and camera.
+
+    Facet centres: the same hexagonal lattice (pitch 1.55 m, 1.51 m flat to
+    flat, inside 11.5 m, 198 facets) on the paraboloid z = r^2 / (4 f).
+    Each facet is a sphere whose axis is the paraboloid's normal at its
+    centre (so on-axis light reflected at the centre goes to the focus
+    (0, 0, f)) and whose radius is twice its centre's distance to the focus
+    (its focal length equals that distance); hexagonal outline, Gaussian
+    tilts (sigma 0.1 mrad) as for the Davies-Cotton dish.  Unlike a
+    Davies-Cotton dish, the paraboloid makes every on-axis path from a
+    wavefront to the focus equally long (an isochronous dish).  Camera and
+    masts as for the Davies-Cotton dish.  Parameters: 198 facet radii, then
+    2 tilts per facet.
+    """
+    f, pitch, rmax, half_flat = 28.0, 1.55, 11.5, 0.755
+    rng = np.random.default_rng(seed)
+    centres = _hex_lattice(pitch, rmax)
+    nf = len(centres)
+    if tilts is None:
+        tilts = rng.normal(0.0, sigma_tilt, size=(nf, 2))
+    foc = np.array([0.0, 0.0, f])
+
+    def surface_z(r):
+        return r * r / (4.0 * f)
+
+    def axis_of(cen):
+        return np.array([-cen[0] / (2.0 * f), -cen[1] / (2.0 * f), 1.0])
+
+    base = np.array([2.0 * np.linalg.norm(foc - np.array([x, y, surface_z(r)])) for (r, _, x, y) in centres])
+    radii = base if radius_scale is None else base * np.asarray(radius_scale)
+    vols, params, names = _facet_volumes(centres, surface_z, axis_of, radii, tilts, half_flat, 0.9)
+    vols += _dish_camera_and_masts(f, rmax, surface_z(rmax))
+    groups = np.radians(np.asarray(fields_deg, dtype=np.float64))
+    return _finish("lst_parabolic", vols, params, names, precision, 16, seed, 28.0, groups, _dish_rays(12.0, 40.0),
                    n_facets=nf, focal_length=f, beam=dict(kind="disc_perp", r_in=0.0, r_out=12.0, back=40.0))
 
 
@@ -591,4 +660,5 @@ ALL = {
     "davies_cotton": davies_cotton,
     "schwarzschild_couder": schwarzschild_couder,
     "hex_concentrator": hex_concentrator,
+    "lst_parabolic": lst_parabolic,
 }

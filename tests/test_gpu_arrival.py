@@ -1,0 +1,88 @@
+"""Arrival-time spread (isochronicity) figures of the HIP library.
+
+robast_arrival_figures reduces the per-photon records of a trace to, per
+group, the FOCUSED count and the mean and RMS spread of the optical path
+length.  Checked (1) against the oracle's definition applied to the same GPU
+records (the reduction alone: FP64 summation order, 1e-12 relative), and
+(2) the optical paths photon by photon against the oracle's own trace of
+the same photons, where both call them FOCUSED: each event's distance may
+differ by the parity tests' bar on positions (1e-5 L_ref in FP32, 1e-11
+L_ref in FP64), so a path of k events by k times that; fates may differ
+only at the grazing rate the parity tests allow.  The paper's segmented parabolic dish is
+isochronous on axis and the Davies-Cotton dish is not: the spread of the
+first is checked to be under 2% of the second on the GPU as on the oracle.
+"""
+import numpy as np
+import pytest
+
+import scenes
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rb():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1508_07803_amd as rb
+    return rb
+
+
+def gpu_records(rb, sc, r):
+    dev = rb.Scene(sc)
+    rays = dev.upload_rays(r)
+    hits = dev.alloc_hits(len(r["ox"]))
+    dev.trace(rays, hits=hits)
+    arr = dev.arrival_figures(rays, hits)
+    torch.cuda.synchronize()
+    rec = dict(fate=hits["fate"].cpu().numpy(), opl=hits["opl"].double().cpu().numpy(),
+               group=np.asarray(r["group"]))
+    return rec, arr.cpu().numpy()
+
+
+@pytest.mark.parametrize("name,precision,n_per", [("lst_parabolic", 32, 20000), ("lst_parabolic", 64, 3000),
+                                                  ("davies_cotton", 32, 20000), ("schwarzschild_couder", 32, 2000),
+                                                  ("hex_concentrator", 32, 300)])
+def test_arrival_figures(rb, name, precision, n_per):
+    import oracle
+    sc = scenes.ALL[name](precision=precision)
+    r = sc.rays(n_per)
+    rec, arr = gpu_records(rb, sc, r)
+    # (1) the reduction, on the GPU's own records
+    same = oracle.arrival_figures(rec, sc.n_groups)
+    for g, f in enumerate(same):
+        assert arr[g, 0] == f["focused"]
+        assert abs(arr[g, 1] - f["mean"]) <= 1e-12 * max(abs(f["mean"]), 1.0)
+        assert abs(arr[g, 2] - f["rms"]) <= 1e-9 * max(f["rms"], 1e-6) + 1e-12 * abs(f["mean"])
+        assert arr[g, 3] == 0.0
+    # (2) the optical paths themselves, photon by photon, against the
+    # oracle's trace of the same photons (FOCUSED in both; fates may differ
+    # only for the grazing photons the parity tests bound, at most `rate`)
+    ref = oracle.trace(sc, r)
+    both = (rec["fate"] == scenes.FATE_FOCUSED) & (ref["fate"] == scenes.FATE_FOCUSED)
+    differ = int((rec["fate"] != ref["fate"]).sum())
+    rate = 5e-4 if name == "hex_concentrator" and precision == 32 else 1e-5
+    assert differ <= max(3, rate * len(rec["fate"])), differ
+    # each event's distance may differ by the parity bar on positions
+    # (1e-5 L_ref in FP32, 1e-11 L_ref in FP64)
+    per_event = (1e-5 if precision == 32 else 1e-11) * sc.l_ref
+    dp = np.abs(rec["opl"][both] - ref["opl"][both]) / (per_event * ref["n_events"][both])
+    assert dp.max() <= 1.0, dp.max()
+    print(f"{name} fp{precision}: arrival spread per group {np.round(arr[:, 2], 6).tolist()} m")
+
+
+def test_parabolic_dish_isochronous_on_gpu(rb):
+    lst, dc = scenes.lst_parabolic(), scenes.davies_cotton()
+    _, a_lst = gpu_records(rb, lst, lst.rays(20000, groups=[0]))
+    _, a_dc = gpu_records(rb, dc, dc.rays(20000, groups=[0]))
+    assert a_lst[0, 2] < 0.02 * a_dc[0, 2]
+
+
+def test_arrival_figures_rejects_missing_records(rb):
+    sc = scenes.lst_parabolic()
+    dev = rb.Scene(sc)
+    rays = dev.upload_rays(sc.rays(10))
+    hits = dev.alloc_hits(50)
+    with pytest.raises(ValueError):
+        dev.arrival_figures(rays, {"fate": hits["fate"][:10], "opl": hits["opl"][:5]})

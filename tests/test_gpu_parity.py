@@ -145,7 +145,8 @@ def test_single_mirror_fp64_full(rb):
 # FP64 cone test below holds the 1e-5 bar.
 @pytest.mark.parametrize("name,n_per,rate", [("davies_cotton", 20000, 1e-5),
                                              ("schwarzschild_couder", 3000, 1e-5),
-                                             ("hex_concentrator", 600, 5e-4)])
+                                             ("hex_concentrator", 600, 5e-4),
+                                             ("lst_parabolic", 20000, 1e-5)])
 def test_fp32_scene_parity(rb, name, n_per, rate):
     import oracle
     sc = scenes.ALL[name]()

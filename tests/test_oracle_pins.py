@@ -11,6 +11,9 @@ status:
 * Fresnel / Snell / TIR .......... pinned (sine/tangent laws, reciprocity, slab)
 * Bezier hexagonal cone .......... pinned (ideal 2D CPC acceptance step)
 * hex facets, tilts, cylinders ... pinned (Davies-Cotton vertex focusing, occlusion)
+* optical path / arrival figures . pinned (ideal paraboloid: stigmatic and isochronous,
+                                    path = start height + f; Davies-Cotton spread = the
+                                    spread of its sphere's sag over the hit radii)
 * non-sequential search .......... pinned (brute force vs culled, symmetry, conservation)
 * forced sequences / duals ....... pinned (closed-form derivative of C1; FD vs duals)
 * full-scene figures (DC PSF, SC RMS, cone efficiency curves): parity unpinned
@@ -401,7 +404,7 @@ def test_dc_shadowing_is_exact_occlusion(orc):
 
 # ------------------------------------------------------------------ search invariants
 @pytest.mark.parametrize("name,n", [("davies_cotton", 300), ("schwarzschild_couder", 100),
-                                    ("hex_concentrator", 20)])
+                                    ("hex_concentrator", 20), ("lst_parabolic", 300)])
 def test_brute_force_equals_culled(orc, name, n):
     sc = scenes.ALL[name]()
     r = sc.rays(n)
@@ -413,7 +416,7 @@ def test_brute_force_equals_culled(orc, name, n):
 
 
 @pytest.mark.parametrize("name", ["single_mirror", "davies_cotton", "schwarzschild_couder",
-                                  "hex_concentrator"])
+                                  "hex_concentrator", "lst_parabolic"])
 def test_photon_conservation(orc, name):
     sc = scenes.ALL[name]()
     r = sc.rays(200)
@@ -525,3 +528,49 @@ def test_duals_match_forced_fd(orc, name, n, idx):
         assert np.max(np.abs(dpos[m, :, 0] - fd[m])) <= 1e-4 * scale + 1e-9, sc.param_names[j]
         scd = max(np.max(np.abs(fdd[m])), 1e-12)
         assert np.max(np.abs(ddir[m, :, 0] - fdd[m])) <= 1e-4 * scd + 1e-9, sc.param_names[j]
+
+
+# ------------------------------------------------------------------ optical path, arrival figures
+def test_ideal_paraboloid_is_stigmatic_and_isochronous(orc):
+    """A paraboloid z = r^2 / (4 f) (an asphere with b1 only) sends every
+    on-axis ray to its focus, and every path from the start plane z0 to the
+    focus has the length z0 + f (the distance to the focus equals the
+    distance to the directrix z = -f)."""
+    f, rn, a, z0 = 8.0, 2.0, 2.0, 20.0
+    b = np.zeros(8)
+    b[0] = rn * rn / (4.0 * f)
+    sc = _asphere_scene(b, rn, a)
+    foc = scenes.new_volume(scenes.ROLE_FOCAL, scenes.SHAPE_PLANE, scenes.OUTLINE_DISC,
+                            Q=np.diag([1.0, -1.0, -1.0]), c=(0.0, 0.0, f), o=[0.05])
+    sc.volumes = np.concatenate([sc.volumes, np.array([foc], dtype=scenes.VOLUME_DTYPE)])
+    rng = np.random.default_rng(11)
+    n = 2000
+    r, ph = np.sqrt(0.01 + (a * a - 0.01) * rng.random(n)), 2 * np.pi * rng.random(n)
+    rays = scenes.make_rays(64, r * np.cos(ph), r * np.sin(ph), np.full(n, z0), np.zeros(n), np.zeros(n),
+                            -np.ones(n), np.zeros(n))
+    rec = orc.trace(sc, rays)
+    assert np.all(rec["fate"] == scenes.FATE_FOCUSED)
+    assert np.abs(rec["pos"][:, :2]).max() < 1e-9
+    assert np.abs(rec["opl"] - (z0 + f)).max() < 1e-9
+    arr = orc.arrival_figures(rec, 1)[0]
+    assert arr["focused"] == n and abs(arr["mean"] - (z0 + f)) < 1e-9 and arr["rms"] < 1e-9
+
+
+def test_parabolic_dish_is_isochronous_davies_cotton_is_not(orc):
+    """On axis, a Davies-Cotton dish (facets on a sphere of radius f about the
+    focus) delays a ray at radius r by about the sphere's sag f - sqrt(f^2 -
+    r^2) less than the ray at the centre: its arrival spread is the spread of
+    that sag over the hit radii.  The segmented paraboloid removes it up to
+    the facets' own curvature."""
+    f = 28.0
+    dc, lst = scenes.davies_cotton(precision=64, sigma_tilt=0.0), scenes.lst_parabolic(precision=64, sigma_tilt=0.0)
+    r_dc, r_lst = dc.rays(3000, groups=[0]), lst.rays(3000, groups=[0])
+    rd, rl = orc.trace(dc, r_dc), orc.trace(lst, r_lst)
+    ad, al = orc.arrival_figures(rd, 1)[0], orc.arrival_figures(rl, 1)[0]
+    m = rd["fate"] == scenes.FATE_FOCUSED
+    rr = np.hypot(r_dc["ox"][m], r_dc["oy"][m])
+    sag = f - np.sqrt(f * f - rr * rr)
+    print(f"on-axis arrival spread: DC {ad['rms']:.4e} m (sag spread {sag.std():.4e} m), "
+          f"parabolic {al['rms']:.4e} m")
+    assert abs(ad["rms"] - sag.std()) < 0.03 * sag.std()
+    assert al["rms"] < 0.02 * ad["rms"]
