@@ -259,6 +259,45 @@ def run_sweep(args, torch, rb, scenes):
     }
 
 
+def run_lst(args, torch, rb, scenes):
+    """The segmented parabolic dish (198 facets on a parabola, 5 fields x
+    1e7 photons): a binned trace writing fates and optical paths, then the
+    arrival-time spread figures from those records."""
+    sc = scenes.lst_parabolic()
+    dev = rb.Scene(sc)
+    npf = args.lst_photons_per_field
+    parts = [scenes.device_rays(sc, npf, seed=sc.seed + 1000 * g, group=g) for g in range(sc.n_groups)]
+    rays = {k: torch.cat([p[k] for p in parts]) for k in parts[0]}
+    del parts
+    n = int(rays["ox"].numel())
+    hits = {"fate": torch.empty(n, dtype=torch.uint8, device="cuda"),
+            "opl": torch.empty(n, dtype=torch.float32, device="cuda")}
+    sums = dev.new_sums()
+    out = torch.zeros(sc.n_groups * 4, dtype=torch.float64, device="cuda")
+    t_tr, t_ar = [], []
+    for rep in range(4):
+        sums.zero_()
+        e = [ev(torch) for _ in range(3)]
+        e[0].record()
+        dev.trace(rays, hits=hits, sums=sums)
+        e[1].record()
+        dev.arrival_figures(rays, hits, out=out)
+        e[2].record()
+        torch.cuda.synchronize()
+        if rep:
+            t_tr.append(e[0].elapsed_time(e[1]))
+            t_ar.append(e[1].elapsed_time(e[2]))
+    fig = dev.figures(sums).cpu().numpy()
+    arr = out.view(sc.n_groups, 4).cpu().numpy()
+    tt, ta = float(np.mean(t_tr)), float(np.mean(t_ar))
+    print(f"[bench] lst: trace {tt:.2f} ms ({n / (tt / 1e3):.3e} photons/s), arrival figures {ta:.3f} ms",
+          file=sys.stderr, flush=True)
+    return {"workload": f"lst_parabolic: {sc.n_groups} fields (0-2 deg) x {npf:.0e} photons, 198 spherical facets on "
+                        "a parabola; binning + trace writing fate and optical path, then arrival-time figures",
+            "photons": n, "trace_ms": tt, "trace_photons_per_s": n / (tt / 1e3), "arrival_figures_ms": ta,
+            "rms_spot_m": fig[:, 4].tolist(), "arrival_rms_path_m": arr[:, 2].tolist()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,6 +310,8 @@ def main():
     ap.add_argument("--sweep-steps", type=int, default=4)
     ap.add_argument("--sweep-chunk", type=int, default=8192)
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--lst-photons-per-field", type=int, default=10_000_000)
+    ap.add_argument("--no-lst", action="store_true")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="copy this many GiB device to device first (a known-size kernel for HBM counters)")
     args = ap.parse_args()
@@ -345,6 +386,7 @@ def main():
           f"{np.mean(k_trace):.2f} ms, adjoint {np.mean(k_bwd):.2f} ms per step", file=sys.stderr, flush=True)
 
     sweep = None if args.no_sweep else run_sweep(args, torch, rb, scenes)
+    lst = None if args.no_lst else run_lst(args, torch, rb, scenes)
 
     # algorithmic op tallies from the reference tracer's event log
     import oracle
@@ -394,6 +436,7 @@ def main():
         "roofline": dict(rk[dominant], kernel=dominant),
         "roofline_kernels": rk,
         "sweep": sweep,
+        "lst": lst,
         "cpu_baseline": cpu,
         "figures": {"rms_mean_m": float(np.mean(figs[:, 4])), "efficiency_mean": float(np.mean(figs[:, 5]))},
     }
