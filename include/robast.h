@@ -230,18 +230,18 @@ typedef struct robast_tuning {
    * workspace, so that the photons of one wave take similar paths */
   uint32_t bin_photons;
   uint32_t bin_target;   /* photons per cell aimed at when sizing that grid, 1..65536 */
-  uint32_t waves_mult;   /* workgroups launched per resident workgroup slot, 1..8 */
+  uint32_t waves_mult;   /* workgroups launched per resident workgroup slot, 1..64 */
   uint32_t reserved;     /* 0 */
 } robast_tuning;
 
-/* Defaults: bin_photons 1, bin_target 128, waves_mult 1. */
+/* Defaults: bin_photons 1, bin_target 128, waves_mult 4. */
 int robast_get_tuning(const robast_scene* scene, robast_tuning* out);
 /* EINVAL on NULL arguments or a field out of range. */
 int robast_set_tuning(robast_scene* scene, const robast_tuning* tuning);
 
 /* Autotuner: traces photons [0, n) of `rays` (group sums only, into its own
  * scratch) under candidate tunings (binning off; binning with 32, 128 or 512
- * photons per cell; grid multiplier 1 or 2), times each with HIP events on
+ * photons per cell; grid multiplier 1, 4 or 8), times each with HIP events on
  * the stream, keeps the fastest in the scene and returns it in *best (may be
  * NULL).  Synchronous; allocates; EINVAL as robast_trace or n < 1. */
 int robast_autotune(robast_scene* scene, const robast_rays* rays, int64_t n, robast_tuning* best,

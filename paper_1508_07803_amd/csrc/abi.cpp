@@ -824,7 +824,7 @@ constexpr int64_t kBinMin = 32768;
 void apply_tuning(robast_scene* s) { s->cfg.waves_mult = (int)s->tuning.waves_mult; }
 
 int tuning_valid(const robast_tuning& t) {
-  return t.bin_target >= 1 && t.bin_target <= 65536 && t.waves_mult >= 1 && t.waves_mult <= 8;
+  return t.bin_target >= 1 && t.bin_target <= 65536 && t.waves_mult >= 1 && t.waves_mult <= 64;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -1022,7 +1022,7 @@ int robast_build_scene(const robast_scene_desc* desc, const double* params, int6
   s->params.assign(params, params + n_params);
   s->cfg.lds_cap = kLdsCap;
   s->cfg.max_blocks = 0;
-  s->tuning = robast_tuning{1u, 128u, 1u, 0u};
+  s->tuning = robast_tuning{1u, 128u, 4u, 0u};
   apply_tuning(s);
   rc = upload(s);
   if (rc) {
@@ -1159,7 +1159,7 @@ int robast_autotune(robast_scene* s, const robast_rays* rays, int64_t n, robast_
   hits.group_sums = sums;
   for (uint32_t bin = 0; bin < 2 && e == hipSuccess && !rc; ++bin)
     for (uint32_t target : {32u, 128u, 512u})
-      for (uint32_t mult : {1u, 2u}) {
+      for (uint32_t mult : {1u, 4u, 8u}) {
         if (e != hipSuccess || rc || (!bin && target != 128u)) continue;
         s->tuning = robast_tuning{bin, target, mult, 0u};
         apply_tuning(s);

@@ -18,7 +18,8 @@ torch = pytest.importorskip("torch")
 TUNINGS = [dict(bin_photons=0, waves_mult=1),
            dict(bin_photons=1, waves_mult=1),
            dict(bin_photons=1, waves_mult=2, bin_target=512),
-           dict(bin_photons=1, waves_mult=1, bin_target=16)]
+           dict(bin_photons=1, waves_mult=1, bin_target=16),
+           dict(bin_photons=1, waves_mult=16)]
 
 
 @pytest.fixture(scope="module")
@@ -93,10 +94,10 @@ def test_autotune_keeps_results(rb):
 
 def test_tuning_rejects_out_of_range(rb):
     dev = rb.Scene(scenes.single_mirror())
-    for bad in (dict(bin_target=1 << 20), dict(waves_mult=0), dict(waves_mult=9), dict(bin_target=0)):
+    for bad in (dict(bin_target=1 << 20), dict(waves_mult=0), dict(waves_mult=65), dict(bin_target=0)):
         with pytest.raises(rb.RobastError):
             dev.set_tuning(**bad)
-    assert dev.tuning == dict(bin_photons=1, bin_target=128, waves_mult=1)
+    assert dev.tuning == dict(bin_photons=1, bin_target=128, waves_mult=4)
 
 
 def test_kept_order_reused_by_backward(rb):
