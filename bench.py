@@ -298,6 +298,58 @@ def run_lst(args, torch, rb, scenes):
             "rms_spot_m": fig[:, 4].tolist(), "arrival_rms_path_m": arr[:, 2].tolist()}
 
 
+def run_gct(args, torch, rb, scenes):
+    """The small Schwarzschild-Couder telescope (6-petal primary, monolithic
+    secondary, masts, trusses and camera body; 16 fields x 1e7 photons): the
+    step of the main workload (binning + trace + figures + adjoint of the
+    mean RMS over the 30 mirror parameters), then one trace writing fates and
+    last volumes for the fraction of photons the structure absorbs."""
+    sc = scenes.gct_sc()
+    dev = rb.Scene(sc)
+    npf = args.gct_photons_per_field
+    parts = [scenes.device_rays(sc, npf, seed=sc.seed + 1000 * g, group=g) for g in range(sc.n_groups)]
+    rays = {k: torch.cat([p[k] for p in parts]) for k in parts[0]}
+    del parts
+    n = int(rays["ox"].numel())
+    cot = torch.zeros(sc.n_groups, 2, dtype=torch.float64, device="cuda")
+    cot[:, 0] = 1.0 / sc.n_groups
+    grad = torch.zeros(len(sc.params), dtype=torch.float64, device="cuda")
+    t = {"binning": [], "trace": [], "adjoint": []}
+    for rep in range(4):
+        sums = dev.new_sums()
+        grad.zero_()
+        e = [ev(torch) for _ in range(4)]
+        e[0].record()
+        dev.bin_photons(rays)
+        e[1].record()
+        dev.trace(rays, sums=sums, keep_order=True)
+        e[2].record()
+        dev.backward(rays, sums, cot, grad)
+        e[3].record()
+        torch.cuda.synchronize()
+        if rep:
+            for k, (a, b) in zip(t, ((0, 1), (1, 2), (2, 3))):
+                t[k].append(e[a].elapsed_time(e[b]))
+    fig = dev.figures(sums).cpu().numpy()
+    hits = {"fate": torch.empty(n, dtype=torch.uint8, device="cuda"),
+            "last_vol": torch.empty(n, dtype=torch.int32, device="cuda")}
+    dev.trace(rays, hits=hits)
+    st = torch.tensor(sc.meta["structure"], dtype=torch.int32, device="cuda")
+    shadow = (hits["fate"] == scenes.FATE_ABSORBED) & torch.isin(hits["last_vol"], st)
+    per_field = shadow.view(sc.n_groups, npf).double().mean(1).cpu().numpy()
+    ms = {k: float(np.mean(v)) for k, v in t.items()}
+    tot = sum(ms.values())
+    print(f"[bench] gct: step {tot:.2f} ms (binning {ms['binning']:.2f}, trace {ms['trace']:.2f}, "
+          f"adjoint {ms['adjoint']:.2f}; {n / (tot / 1e3):.3e} photons/s), structure shadow "
+          f"{per_field.mean():.4f}", file=sys.stderr, flush=True)
+    return {"workload": f"gct_sc: {sc.n_groups} fields (0-4.4 deg) x {npf:.0e} photons, small SC (6 aspheric "
+                        "petals, monolithic aspheric secondary, 4 masts, 4 trusses, camera body); binning + "
+                        f"trace + figures + adjoint ({len(sc.params)} params)",
+            "photons": n, "ms_per_step": tot, "photons_per_s": n / (tot / 1e3),
+            "binning_ms": ms["binning"], "trace_ms": ms["trace"], "adjoint_ms": ms["adjoint"],
+            "rms_spot_m": fig[:, 4].tolist(), "structure_shadow_fraction": per_field.tolist()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -312,6 +364,8 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--lst-photons-per-field", type=int, default=10_000_000)
     ap.add_argument("--no-lst", action="store_true")
+    ap.add_argument("--gct-photons-per-field", type=int, default=10_000_000)
+    ap.add_argument("--no-gct", action="store_true")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="copy this many GiB device to device first (a known-size kernel for HBM counters)")
     args = ap.parse_args()
@@ -387,6 +441,7 @@ def main():
 
     sweep = None if args.no_sweep else run_sweep(args, torch, rb, scenes)
     lst = None if args.no_lst else run_lst(args, torch, rb, scenes)
+    gct = None if args.no_gct else run_gct(args, torch, rb, scenes)
 
     # algorithmic op tallies from the reference tracer's event log
     import oracle
@@ -437,6 +492,7 @@ def main():
         "roofline_kernels": rk,
         "sweep": sweep,
         "lst": lst,
+        "gct": gct,
         "cpu_baseline": cpu,
         "figures": {"rms_mean_m": float(np.mean(figs[:, 4])), "efficiency_mean": float(np.mean(figs[:, 5]))},
     }

@@ -372,6 +372,71 @@ def _ring_panels(r_in, r_out, r_split, n_inner, n_outer):
     return out
 
 
+def _sc_two_mirror(name, scale, pan_p, pan_s, tilts, bp, bs, groups, precision, seed, extra_vols=()):
+    """The two-mirror Schwarzschild-Couder optics at `scale` times the
+    dimensions of SC_PRIMARY / SC_SECONDARY / SC_FOCAL_Z: aspheric mirrors
+    cut into the (r_a, r_b, phi_a, phi_b) sectors pan_p / pan_s (radii
+    already scaled), each rotated about its sector-centroid point by its
+    two tilts (radial, tangential axes), the spherical focal cap, and the
+    beam filling the primary's annulus from `12 scale` m above it."""
+    pri = dict(SC_PRIMARY, rn=SC_PRIMARY["rn"] * scale, r_in=SC_PRIMARY["r_in"] * scale,
+               r_out=SC_PRIMARY["r_out"] * scale, z=SC_PRIMARY["z"] * scale)
+    sec = dict(SC_SECONDARY, rn=SC_SECONDARY["rn"] * scale, r_in=SC_SECONDARY["r_in"] * scale,
+               r_out=SC_SECONDARY["r_out"] * scale, z=SC_SECONDARY["z"] * scale)
+    npan = len(pan_p) + len(pan_s)
+    params = list(bp) + list(bs)
+    names = [f"primary_b{i}" for i in range(1, 9)] + [f"secondary_b{i}" for i in range(1, 9)]
+    for k in range(npan):
+        params.extend(tilts[k]); names.extend([f"panel{k}_tilt_r", f"panel{k}_tilt_t"])
+    vols = []
+    k = 0
+    for mirror, pans, b, off, Q0 in ((pri, pan_p, bp, 0, np.eye(3)),
+                                     (sec, pan_s, bs, 8, np.diag([1.0, -1.0, -1.0]))):
+        c0 = np.array([0.0, 0.0, mirror["z"]])
+        for (ra, rb, pa, pb) in pans:
+            phm = 0.5 * (pa + pb)
+            half = 0.5 * (pb - pa)
+            rc = (2.0 / 3.0) * (rb ** 3 - ra ** 3) / (rb ** 2 - ra ** 2) * math.sin(half) / half
+            u = (rc / mirror["rn"]) ** 2
+            zc = sum(b[i] * u ** (i + 1) for i in range(8))
+            piv_l = np.array([rc * math.cos(phm), rc * math.sin(phm), zc])
+            pivot = c0 + Q0.T @ piv_l
+            e1 = Q0.T @ np.array([math.cos(phm), math.sin(phm), 0.0])
+            e2 = Q0.T @ np.array([-math.sin(phm), math.cos(phm), 0.0])
+            Q, c = tilted_frame(Q0, c0, pivot, e1, e2, tilts[k][0], tilts[k][1])
+            # a one-piece mirror is a disc: 2 pi rounded to FP32 exceeds a sector's range
+            whole = ra == 0.0 and pb - pa == 2.0 * math.pi
+            v = new_volume(ROLE_MIRROR, SHAPE_ASPHERE, OUTLINE_DISC if whole else OUTLINE_SECTOR, Q=Q, c=c,
+                           p=[mirror["rn"]] + list(b), o=[rb] if whole else [ra, rb, pa, pb],
+                           reflectivity=1.0, shape_param=off, tilt_param=16 + 2 * k)
+            v["Q0"], v["c0"], v["pivot"], v["e1"], v["e2"] = Q0.reshape(9), c0, pivot, e1, e2
+            vols.append(v)
+            k += 1
+    vols.append(new_volume(ROLE_FOCAL, SHAPE_SPHERE, OUTLINE_DISC, c=(0.0, 0.0, SC_FOCAL_Z * scale),
+                           p=[-1.0 / scale], o=[0.6 * scale]))
+    vols += list(extra_vols)
+    back = 12.0 * scale
+
+    def rays(scene, n, s, gsel):
+        rng2 = np.random.default_rng(s)
+        out = []
+        for g in gsel:
+            th = scene.groups[g]
+            d = np.array([math.sin(th), 0.0, -math.cos(th)])
+            u1, u2 = rng2.random(n), rng2.random(n)
+            r = np.sqrt(pri["r_in"] ** 2 + u1 * (pri["r_out"] ** 2 - pri["r_in"] ** 2))
+            ph = 2.0 * np.pi * u2
+            o = np.stack([r * np.cos(ph), r * np.sin(ph), np.zeros(n)], 1) - back * d[None, :]
+            out.append((o[:, 0], o[:, 1], o[:, 2], np.full(n, d[0]), np.full(n, d[1]),
+                        np.full(n, d[2]), np.full(n, g)))
+        cols = [np.concatenate(c) for c in zip(*out)]
+        return _pack_rays(scene.precision, *cols)
+
+    return _finish(name, vols, params, names, precision, 16, seed, 5.6 * scale, groups, rays,
+                   n_panels=npan, focal_z=SC_FOCAL_Z * scale, scale=scale,
+                   beam=dict(kind="annulus_z0", r_in=pri["r_in"], r_out=pri["r_out"], back=back))
+
+
 def schwarzschild_couder(seed=SEED_BASE + 2, sigma_tilt=5e-5, n_fields=16, max_field_deg=4.0,
                          coeff_scale=None, tilts=None, precision=32, fields_deg=None):
     """Two-mirror Schwarzschild-Couder telescope with segmented aspheric mirrors.
@@ -402,57 +467,86 @@ def schwarzschild_couder(seed=SEED_BASE + 2, sigma_tilt=5e-5, n_fields=16, max_f
     npan = len(pan_p) + len(pan_s)
     if tilts is None:
         tilts = rng.normal(0.0, sigma_tilt, size=(npan, 2))
-    params = list(bp) + list(bs)
-    names = [f"primary_b{i}" for i in range(1, 9)] + [f"secondary_b{i}" for i in range(1, 9)]
-    for k in range(npan):
-        params.extend(tilts[k]); names.extend([f"panel{k}_tilt_r", f"panel{k}_tilt_t"])
-    vols = []
-    k = 0
-    for mirror, pans, b, off, Q0 in ((pri, pan_p, bp, 0, np.eye(3)),
-                                     (sec, pan_s, bs, 8, np.diag([1.0, -1.0, -1.0]))):
-        c0 = np.array([0.0, 0.0, mirror["z"]])
-        for (ra, rb, pa, pb) in pans:
-            phm = 0.5 * (pa + pb)
-            half = 0.5 * (pb - pa)
-            rc = (2.0 / 3.0) * (rb ** 3 - ra ** 3) / (rb ** 2 - ra ** 2) * math.sin(half) / half
-            u = (rc / mirror["rn"]) ** 2
-            zc = sum(b[i] * u ** (i + 1) for i in range(8))
-            piv_l = np.array([rc * math.cos(phm), rc * math.sin(phm), zc])
-            pivot = c0 + Q0.T @ piv_l
-            e1 = Q0.T @ np.array([math.cos(phm), math.sin(phm), 0.0])
-            e2 = Q0.T @ np.array([-math.sin(phm), math.cos(phm), 0.0])
-            Q, c = tilted_frame(Q0, c0, pivot, e1, e2, tilts[k][0], tilts[k][1])
-            v = new_volume(ROLE_MIRROR, SHAPE_ASPHERE, OUTLINE_SECTOR, Q=Q, c=c,
-                           p=[mirror["rn"]] + list(b), o=[ra, rb, pa, pb], reflectivity=1.0,
-                           shape_param=off, tilt_param=16 + 2 * k)
-            v["Q0"], v["c0"], v["pivot"], v["e1"], v["e2"] = Q0.reshape(9), c0, pivot, e1, e2
-            vols.append(v)
-            k += 1
-    vols.append(new_volume(ROLE_FOCAL, SHAPE_SPHERE, OUTLINE_DISC, c=(0.0, 0.0, SC_FOCAL_Z),
-                           p=[-1.0], o=[0.6]))
     if fields_deg is None:
         groups = np.radians(np.linspace(0.0, max_field_deg, n_fields))
     else:
         groups = np.radians(np.asarray(fields_deg, dtype=np.float64))
+    return _sc_two_mirror("schwarzschild_couder", 1.0, pan_p, pan_s, tilts, bp, bs, groups,
+                          precision, seed)
 
-    def rays(scene, n, s, gsel):
-        rng2 = np.random.default_rng(s)
-        out = []
-        for g in gsel:
-            th = scene.groups[g]
-            d = np.array([math.sin(th), 0.0, -math.cos(th)])
-            u1, u2 = rng2.random(n), rng2.random(n)
-            r = np.sqrt(pri["r_in"] ** 2 + u1 * (pri["r_out"] ** 2 - pri["r_in"] ** 2))
-            ph = 2.0 * np.pi * u2
-            o = np.stack([r * np.cos(ph), r * np.sin(ph), np.zeros(n)], 1) - 12.0 * d[None, :]
-            out.append((o[:, 0], o[:, 1], o[:, 2], np.full(n, d[0]), np.full(n, d[1]),
-                        np.full(n, d[2]), np.full(n, g)))
-        cols = [np.concatenate(c) for c in zip(*out)]
-        return _pack_rays(scene.precision, *cols)
 
-    return _finish("schwarzschild_couder", vols, params, names, precision, 16, seed, 5.6, groups, rays,
-                   n_panels=npan, focal_z=SC_FOCAL_Z,
-                   beam=dict(kind="annulus_z0", r_in=pri["r_in"], r_out=pri["r_out"], back=12.0))
+GCT_SCALE = 2.283 / 5.6   # effective focal length of the small SC over that of SC_PRIMARY / SC_SECONDARY
+
+
+def _sc_structure(scale, pri_rim_r, sec_rim_r, sec_z, focal_z, focal_ap):
+    """Absorbing telescope structure of the small SC (§3, Figure 1 c, f, i:
+    its spot diagram shows mast and truss shadows): four masts (r = 5 cm)
+    from outside the primary's rim at z = 0 to just outside and above the
+    secondary's rim, a ring of four trusses (r = 3 cm) joining the masts at
+    half height, and a camera body (an absorbing box) under the focal cap."""
+    vols = []
+    r0, z0 = pri_rim_r + 0.13, 0.0
+    r1, z1 = sec_rim_r + 0.08, sec_z + 0.1
+    mid = []
+    for kk in range(4):
+        ph = math.radians(45.0 + 90.0 * kk)
+        e = np.array([math.cos(ph), math.sin(ph), 0.0])
+        base = r0 * e + np.array([0.0, 0.0, z0])
+        top = r1 * e + np.array([0.0, 0.0, z1])
+        ax = top - base
+        vols.append(new_volume(ROLE_OBSCURATION, SHAPE_CYLINDER, Q=frame_from_axes(ax), c=base,
+                               p=[0.05, float(np.linalg.norm(ax))]))
+        mid.append(0.5 * (base + top))
+    for kk in range(4):
+        a, b = mid[kk], mid[(kk + 1) % 4]
+        ax = b - a
+        vols.append(new_volume(ROLE_OBSCURATION, SHAPE_CYLINDER, Q=frame_from_axes(ax), c=a,
+                               p=[0.03, float(np.linalg.norm(ax))]))
+    # the focal cap reaches down to focal_z - (1 - sqrt(1 - (ap/R)^2)) R, R = scale
+    cap_depth = scale * (1.0 - math.sqrt(1.0 - (focal_ap / scale) ** 2))
+    top_z = focal_z - cap_depth - 0.02
+    vols.append(new_volume(ROLE_OBSCURATION, SHAPE_BOX, c=(0.0, 0.0, top_z - 0.18),
+                           p=[focal_ap + 0.015, focal_ap + 0.015, 0.18]))
+    return vols
+
+
+def gct_sc(seed=SEED_BASE + 9, sigma_tilt=5e-5, n_fields=16, max_field_deg=4.4, tilts=None,
+           precision=32, fields_deg=None, structure=True):
+    """A second Schwarzschild-Couder scale, of the small-sized telescope the
+    paper models beside the SCT (§3, Figure 1 c, f, i): the two-mirror
+    design of schwarzschild_couder scaled by GCT_SCALE (effective focal
+    length 2.283 m; every length, including each sag coefficient b_i of the
+    normalised form, times the scale; primary 3.94 m across, secondary
+    2.20 m, 3.42 m above it), the primary cut into six petals and the
+    secondary in one piece, each rotated about its sector-centroid point by
+    two Gaussian angles (sigma_tilt) about the radial and tangential axes,
+    plus the absorbing masts, trusses and camera body of _sc_structure
+    (structure=False leaves them out).  Parameters: 8 primary b_i, 8
+    secondary b_i, 2 tilts per panel (7 panels).  Fields: n_fields angles
+    evenly spaced in [0, max_field_deg], or the explicit list fields_deg.
+    """
+    rng = np.random.default_rng(seed)
+    s = GCT_SCALE
+    pri, sec = SC_PRIMARY, SC_SECONDARY
+    bp = s * conic_taylor(pri["R"], pri["k"], pri["rn"])
+    bs = s * conic_taylor(sec["R"], sec["k"], sec["rn"])
+    pan_p = [(pri["r_in"] * s, pri["r_out"] * s, k * math.pi / 3.0, (k + 1) * math.pi / 3.0)
+             for k in range(6)]
+    pan_s = [(0.0, sec["r_out"] * s, 0.0, 2.0 * math.pi)]
+    npan = len(pan_p) + len(pan_s)
+    if tilts is None:
+        tilts = rng.normal(0.0, sigma_tilt, size=(npan, 2))
+    if fields_deg is None:
+        groups = np.radians(np.linspace(0.0, max_field_deg, n_fields))
+    else:
+        groups = np.radians(np.asarray(fields_deg, dtype=np.float64))
+    extra = []
+    if structure:
+        extra = _sc_structure(s, pri["r_out"] * s, sec["r_out"] * s, sec["z"] * s, SC_FOCAL_Z * s,
+                              0.6 * s)
+    sc = _sc_two_mirror("gct_sc", s, pan_p, pan_s, tilts, bp, bs, groups, precision, seed, extra)
+    sc.meta["structure"] = list(range(sc.n_volumes - len(extra), sc.n_volumes))
+    return sc
 
 
 # ================================================================ C5
@@ -661,4 +755,5 @@ ALL = {
     "schwarzschild_couder": schwarzschild_couder,
     "hex_concentrator": hex_concentrator,
     "lst_parabolic": lst_parabolic,
+    "gct_sc": gct_sc,
 }

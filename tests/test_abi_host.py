@@ -41,6 +41,17 @@ def _try(rb, sc, **over):
     return st
 
 
+@pytest.mark.parametrize("precision", [32, 64])
+@pytest.mark.parametrize("name", sorted(scenes.ALL))
+def test_every_scene_passes_validation(rb, name, precision):
+    """Each stand-in scene, rounded to either precision, gets past the
+    library's checks of volumes and parameters (without a device the build
+    then stops at its first HIP call)."""
+    f = scenes.ALL[name]
+    sc = f() if name == "single_mirror" else f(precision=precision)
+    assert _try(rb, sc) in (rb.OK, rb.EHIP)
+
+
 @pytest.mark.parametrize("field,value", [
     ("role", 9), ("shape", 0), ("outline", 7), ("shape_param", 5), ("tilt_param", 0),
     ("reflectivity", 1.5), ("reflectivity", np.nan)])

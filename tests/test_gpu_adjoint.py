@@ -110,6 +110,21 @@ def test_lst_rms_gradient(rb, precision, n_per, floor):
     print(f"LST fp{precision}: 594 params, worst rel {e:.2e}")
 
 
+@pytest.mark.parametrize("precision,n_per,floor", [(32, 5000, 1e-2), (64, 1000, 1e-3)])
+def test_small_sc_rms_gradient(rb, precision, n_per, floor):
+    """The small SC: petal and secondary coefficients and tilts, with the
+    structure's shadows removing photons from the figures."""
+    import oracle
+    sc = scenes.gct_sc(precision=precision)
+    r = sc.rays(n_per)
+    w = np.full(sc.n_groups, 1.0 / sc.n_groups)
+    g = gpu_grad(rb, sc, r, w_rms=w)
+    rec = oracle.trace(sc, r, log=True)
+    ref = oracle.gradient_rms(sc, r, rec, w)
+    e = check(g, ref, floor, sc.param_names)
+    print(f"GCT fp{precision}: 30 params, worst rel {e:.2e}")
+
+
 @pytest.mark.parametrize("precision", [32, 64])
 def test_concentrator_weighted_collection_gradient(rb, precision):
     import oracle

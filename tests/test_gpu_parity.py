@@ -146,7 +146,8 @@ def test_single_mirror_fp64_full(rb):
 @pytest.mark.parametrize("name,n_per,rate", [("davies_cotton", 20000, 1e-5),
                                              ("schwarzschild_couder", 3000, 1e-5),
                                              ("hex_concentrator", 600, 5e-4),
-                                             ("lst_parabolic", 20000, 1e-5)])
+                                             ("lst_parabolic", 20000, 1e-5),
+                                             ("gct_sc", 5000, 1e-5)])
 def test_fp32_scene_parity(rb, name, n_per, rate):
     import oracle
     sc = scenes.ALL[name]()
@@ -165,6 +166,20 @@ def test_fp64_concentrator_parity(rb):
     ref = oracle.trace(sc, r, log=True)
     nbad, dp, dd = compare(sc, r, got, ref, 1e-9 * sc.l_ref, 1e-9)
     print(f"hex_concentrator fp64: N={len(r['ox'])} mismatches={nbad} max|dpos|={dp:.3e}")
+
+
+def test_fp64_small_sc_parity(rb):
+    """The small SC with its masts, trusses and camera body, in FP64."""
+    import oracle
+    sc = scenes.gct_sc(precision=64)
+    r = sc.rays(1000)
+    got = gpu_trace(rb, sc, r)
+    ref = oracle.trace(sc, r, log=True)
+    nbad, dp, dd = compare(sc, r, got, ref, 1e-9 * sc.l_ref, 1e-9)
+    st = sc.meta["structure"]
+    shadow = (ref["fate"] == scenes.FATE_ABSORBED) & np.isin(ref["last_vol"], st)
+    assert shadow.sum() > 0.05 * len(r["ox"])
+    print(f"gct_sc fp64: N={len(r['ox'])} mismatches={nbad} max|dpos|={dp:.3e} shadowed={shadow.mean():.3f}")
 
 
 def test_ragged_sizes_and_launch_shape(rb):

@@ -402,9 +402,60 @@ def test_dc_shadowing_is_exact_occlusion(orc):
             assert rec["last_vol"][i] in masts
 
 
+def test_gct_is_the_sc_design_scaled(orc):
+    """Geometric optics has no length scale: the small SC (every length of
+    the SC design times s, the primary cut into other panels) with its
+    structure removed and no tilts images the launch points s*o exactly
+    where the SC images o, times s, with the same exit directions and fates
+    (panel boundaries aside, which have measure zero)."""
+    s = scenes.GCT_SCALE
+    big = scenes.schwarzschild_couder(precision=64, sigma_tilt=0.0)
+    small = scenes.gct_sc(precision=64, sigma_tilt=0.0, structure=False)
+    r = big.rays(300, groups=[0, 4, 9, 15])
+    r2 = {k: (v * s if k in ("ox", "oy", "oz") else v) for k, v in r.items()}
+    a, b = orc.trace(big, r), orc.trace(small, r2)
+    assert np.array_equal(a["fate"], b["fate"])
+    assert np.array_equal(a["n_events"], b["n_events"])
+    ok = a["fate"] == scenes.FATE_FOCUSED
+    assert ok.sum() > 600
+    assert np.abs(b["pos"][ok] - s * a["pos"][ok]).max() < 1e-12 * small.l_ref
+    assert np.abs(b["dir"][ok] - a["dir"][ok]).max() < 1e-12
+    assert np.abs(b["opl"][ok] - s * a["opl"][ok]).max() < 1e-11 * small.l_ref
+
+
+def test_gct_structure_shadow_is_exact_occlusion(orc):
+    """On-axis photons launched outside the secondary's radius can meet only
+    the masts and trusses before the primary: a photon whose line crosses a
+    mast or truss (independent ray / cylinder test) is absorbed there at its
+    first event, at the nearest one, and no other photon is."""
+    sc = scenes.gct_sc(precision=64)
+    r = sc.rays(3000, groups=[0])
+    rec = orc.trace(sc, r)
+    st = sc.meta["structure"]
+    cyl = [m for m in st if sc.volumes["shape"][m] == scenes.SHAPE_CYLINDER]
+    assert len(cyl) == 8
+    sec_r = scenes.SC_SECONDARY["r_out"] * scenes.GCT_SCALE
+    rad = np.hypot(r["ox"], r["oy"])
+    n_hit = 0
+    for i in np.nonzero(rad > sec_r + 1e-6)[0]:
+        o = np.array([r["ox"][i], r["oy"][i], r["oz"][i]])
+        d = np.array([r["dx"][i], r["dy"][i], r["dz"][i]])
+        ts = [_ray_cyl_first_t(o, d, sc.volumes["c"][m], sc.volumes["Q"][m][6:9],
+                               sc.volumes["p"][m][0], sc.volumes["p"][m][1]) for m in cyl]
+        first_struct = rec["fate"][i] == scenes.FATE_ABSORBED and rec["n_events"][i] == 1 \
+            and rec["last_vol"][i] in st
+        if np.isfinite(min(ts)):
+            n_hit += 1
+            assert first_struct and rec["last_vol"][i] == cyl[int(np.argmin(ts))], i
+        else:
+            assert not first_struct, i
+    assert n_hit > 100
+
+
 # ------------------------------------------------------------------ search invariants
 @pytest.mark.parametrize("name,n", [("davies_cotton", 300), ("schwarzschild_couder", 100),
-                                    ("hex_concentrator", 20), ("lst_parabolic", 300)])
+                                    ("hex_concentrator", 20), ("lst_parabolic", 300),
+                                    ("gct_sc", 200)])
 def test_brute_force_equals_culled(orc, name, n):
     sc = scenes.ALL[name]()
     r = sc.rays(n)
@@ -416,7 +467,7 @@ def test_brute_force_equals_culled(orc, name, n):
 
 
 @pytest.mark.parametrize("name", ["single_mirror", "davies_cotton", "schwarzschild_couder",
-                                  "hex_concentrator", "lst_parabolic"])
+                                  "hex_concentrator", "lst_parabolic", "gct_sc"])
 def test_photon_conservation(orc, name):
     sc = scenes.ALL[name]()
     r = sc.rays(200)
