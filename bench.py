@@ -350,6 +350,72 @@ def run_gct(args, torch, rb, scenes):
             "rms_spot_m": fig[:, 4].tolist(), "structure_shadow_fraction": per_field.tolist()}
 
 
+def run_chromatic(args, torch, rb, scenes):
+    """Wavelength as the batch axis: the aspheric singlet at 16 wavelengths
+    (300-600 nm; the same surfaces, the index of each wavelength), 4 fields
+    x 2.5e6 photons each.  One step = binning + forward + figures + adjoint
+    of every wavelength's RMS, batched (one forward and one adjoint launch)
+    against per-wavelength calls."""
+    lams = np.linspace(300e-9, 600e-9, 16)
+    variants = scenes.lens_wavelengths(lams)
+    devs = [rb.Scene(v) for v in variants]
+    npf = args.chromatic_photons_per_field
+    parts = [scenes.device_rays(v, npf, seed=v.seed + 100 * i + g, group=g)
+             for i, v in enumerate(variants) for g in range(v.n_groups)]
+    rays = {k: torch.cat([p[k] for p in parts]) for k in parts[0]}
+    del parts
+    counts = [npf * v.n_groups for v in variants]
+    n = int(sum(counts))
+    offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    batch = rb.Batch(devs, counts, chunk=args.sweep_chunk)
+    sums = batch.new_sums()
+    fig = torch.zeros(batch.n_groups * rb.FIGURE_STRIDE, dtype=torch.float64, device="cuda")
+    cot = torch.zeros(batch.n_groups, 2, dtype=torch.float64, device="cuda")
+    cot[:, 0] = 1.0
+    grad = torch.zeros(batch.n_params, dtype=torch.float64, device="cuda")
+    go, po = batch.goff, batch.poff
+    sub = [{k: t[offs[v]:offs[v + 1]] for k, t in rays.items()} for v in range(len(devs))]
+
+    def batched_step():
+        sums.zero_()
+        grad.zero_()
+        batch.trace(rays, sums=sums, keep_order=True)
+        batch.figures(sums, fig=fig)
+        batch.backward(rays, sums, cot, grad)
+
+    def plain_step():
+        sums.zero_()
+        grad.zero_()
+        for v, d in enumerate(devs):
+            s_v = sums[go[v] * 8:go[v + 1] * 8]
+            d.trace(sub[v], sums=s_v, keep_order=True)
+            d.figures(s_v, fig=fig[go[v] * 8:go[v + 1] * 8])
+            d.backward(sub[v], s_v, cot[go[v]:go[v + 1]], grad[po[v]:po[v + 1]])
+
+    t_b, t_p = [], []
+    for rep in range(4):
+        for step, out in ((batched_step, t_b), (plain_step, t_p)):
+            a, b = ev(torch), ev(torch)
+            a.record()
+            step()
+            b.record()
+            torch.cuda.synchronize()
+            if rep:
+                out.append(a.elapsed_time(b))
+    batched_step()
+    rms = fig.view(-1, rb.FIGURE_STRIDE)[:, 4].cpu().numpy()
+    on_axis = [float(rms[go[v]]) for v in range(len(devs))]
+    tb, tp = float(np.mean(t_b)), float(np.mean(t_p))
+    print(f"[bench] chromatic: batched {tb:.2f} ms, plain {tp:.2f} ms ({n / (tb / 1e3):.3e} photons/s); "
+          f"on-axis RMS {min(on_axis) * 1e3:.2f}-{max(on_axis) * 1e3:.2f} mm", file=sys.stderr, flush=True)
+    return {"workload": f"aspheric_lens at 16 wavelengths (300-600 nm, Cauchy index) x 4 fields (0-3 deg) x "
+                        f"{npf:.1e} photons; one step = binning + forward + figures + adjoint (8 front-face "
+                        "coefficients per wavelength)",
+            "photons_per_step": n, "batched_ms_per_step": tb, "plain_ms_per_step": tp,
+            "batched_photons_per_s": n / (tb / 1e3), "speedup": tp / tb,
+            "wavelengths_nm": (lams * 1e9).tolist(), "on_axis_rms_m": on_axis}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -366,6 +432,8 @@ def main():
     ap.add_argument("--no-lst", action="store_true")
     ap.add_argument("--gct-photons-per-field", type=int, default=10_000_000)
     ap.add_argument("--no-gct", action="store_true")
+    ap.add_argument("--chromatic-photons-per-field", type=int, default=2_500_000)
+    ap.add_argument("--no-chromatic", action="store_true")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="copy this many GiB device to device first (a known-size kernel for HBM counters)")
     args = ap.parse_args()
@@ -442,6 +510,7 @@ def main():
     sweep = None if args.no_sweep else run_sweep(args, torch, rb, scenes)
     lst = None if args.no_lst else run_lst(args, torch, rb, scenes)
     gct = None if args.no_gct else run_gct(args, torch, rb, scenes)
+    chromatic = None if args.no_chromatic else run_chromatic(args, torch, rb, scenes)
 
     # algorithmic op tallies from the reference tracer's event log
     import oracle
@@ -493,6 +562,7 @@ def main():
         "sweep": sweep,
         "lst": lst,
         "gct": gct,
+        "chromatic": chromatic,
         "cpu_baseline": cpu,
         "figures": {"rms_mean_m": float(np.mean(figs[:, 4])), "efficiency_mean": float(np.mean(figs[:, 5]))},
     }

@@ -89,7 +89,13 @@ typedef struct {
   double Q[9], c[3];
   double p[16], o[4];
   double reflectivity; /* mirrors: absorb iff Philox word >= floor(R 2^32) */
-  double n_inside;     /* lenses: refractive index inside, 1 outside */
+  double n_inside;     /* lenses: refractive index on the back side of each face
+                        * (inside a BOX), 1 on the front side.  A lens PLANE,
+                        * SPHERE or ASPHERE is one refracting face of a solid
+                        * that the caller closes with its other faces (e.g. an
+                        * aspheric front, a plane back with its front side
+                        * facing out, an absorbing CYLINDER rim); CYLINDER and
+                        * HEXCONE lenses are EUNSUPPORTED. */
   double Q0[9], c0[3], pivot[3], e1[3], e2[3];
 } robast_volume_desc;
 

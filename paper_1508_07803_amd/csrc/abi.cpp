@@ -140,8 +140,9 @@ int validate(const robast_scene_desc* d, const double* params, int64_t n_params)
     if (v.role == ROBAST_MIRROR && !(v.reflectivity >= 0.0 && v.reflectivity <= 1.0))
       return fail(ROBAST_EINVAL, "reflectivity outside [0, 1]" + at);
     if (v.role == ROBAST_LENS && !(v.n_inside > 0.0)) return fail(ROBAST_EINVAL, "lens index must be > 0" + at);
-    if (v.role == ROBAST_LENS && v.shape != ROBAST_BOX)
-      return fail(ROBAST_EUNSUPPORTED, "lenses must be closed solids (BOX)" + at);
+    if (v.role == ROBAST_LENS && v.shape != ROBAST_BOX && v.shape != ROBAST_PLANE && v.shape != ROBAST_SPHERE &&
+        v.shape != ROBAST_ASPHERE)
+      return fail(ROBAST_EUNSUPPORTED, "lens faces must be planes, spheres, aspheres or boxes" + at);
     int ns = v.shape == ROBAST_SPHERE ? 1 : v.shape == ROBAST_ASPHERE ? 8 : v.shape == ROBAST_HEXCONE ? 4 : 0;
     if (v.shape_param >= 0 && (ns == 0 || v.shape_param + ns > n_params))
       return fail(ROBAST_EINVAL, "shape_param out of range" + at);

@@ -351,7 +351,9 @@ template <typename T> __device__ __forceinline__ void nf_asphere(const DVol<T>& 
     if (g == T(0)) break;
     if ((g > T(0)) == (ga_ > T(0))) { a = t; ga_ = g; } else { bnd = t; }
     T tn = gp != T(0) ? t - fdiv(g, gp) : T(0.5) * (a + bnd);
-    if (!(tn > dmin(a, bnd) && tn < dmax(a, bnd))) tn = T(0.5) * (a + bnd);
+    // t is now an end of the bracket: at Newton's fixed point tn == t, which
+    // must count as inside (a zero step ends the loop), not send it bisecting
+    if (!(tn >= dmin(a, bnd) && tn <= dmax(a, bnd))) tn = T(0.5) * (a + bnd);
     T dt = tn - t;
     t = tn;
     if (dabs(dt) <= tol * (dabs(t) + dabs(t0) + T(1e-30))) break;
@@ -442,7 +444,7 @@ template <typename T> __device__ __forceinline__ T cubic_root_piece(const T* w, 
     if (f == T(0)) break;
     if ((f > T(0)) == (fa > T(0))) { a = s; fa = f; } else { b = s; }
     T sn = fp != T(0) ? s - fdiv(f, fp) : T(0.5) * (a + b);
-    if (!(sn > a && sn < b)) sn = T(0.5) * (a + b);
+    if (!(sn >= a && sn <= b)) sn = T(0.5) * (a + b);   // s is an end: a fixed point stays put
     T ds = sn - s;
     s = sn;
     if (dabs(ds) <= (sizeof(T) == 4 ? T(1e-7) : T(1e-16))) break;

@@ -749,6 +749,59 @@ def window_slab(n_index=1.49, thickness=2.0, precision=64, seed=SEED_BASE + 7):
     return _finish("window_slab", vols, [], [], precision, 64, seed, thickness, [0.0], rays)
 
 
+# ================================================================ refractive optics
+CAUCHY_PMMA = (1.4720, 3.2e-15)   # n(lam) = A + B / lam^2, lam in m: a PMMA-like synthetic law
+
+
+def cauchy_index(lam, A=CAUCHY_PMMA[0], B=CAUCHY_PMMA[1]):
+    """Refractive index of the lens material at wavelength lam (m)."""
+    return A + B / (lam * lam)
+
+
+def aspheric_lens(seed=SEED_BASE + 10, lam=400e-9, a=0.25, R=-0.5, k=None, edge=0.01,
+                  fields_deg=(0.0, 1.0, 2.0, 3.0), design_lam=400e-9, coeffs=None, precision=32):
+    """A plano-aspheric singlet of the kind used as refracting optics for
+    Cherenkov and fluorescence light (§1, §2.1: lenses and refractions), at
+    wavelength lam: index cauchy_index(lam); everything else is fixed by the
+    design wavelength, so scenes at several wavelengths differ only in the
+    index.  Front face: the asphere z = T + S(r), r <= a, with S the Taylor
+    coefficients b_1..b_8 (normalised form, rn = a) of the conic of vertex
+    radius R (< 0: convex towards the sky) and conic constant
+    k = -1/n_design^2 unless given; a refracting lens face whose front side
+    (air) faces +z.  Back face: the plane z = 0, r <= a, front side facing
+    -z.  Rim: an absorbing cylinder r = a, 0 <= z <= edge.  Centre
+    thickness T = edge - S(a).  Focal plane: a disc of radius 0.08 m at the
+    paraxial back focus of the design wavelength, z = -(f - T/n) with
+    f = |R| / (n - 1).  Parameters: the 8 front-face coefficients.
+    Photons: parallel beams at the field angles over a disc of radius a
+    normal to the beam, launched 1 m before the origin."""
+    n_design = cauchy_index(design_lam)
+    if k is None:
+        k = -1.0 / n_design ** 2
+    b = conic_taylor(R, k, a) if coeffs is None else np.asarray(coeffs, dtype=np.float64)
+    T = edge - float(np.sum(b))
+    f = abs(R) / (n_design - 1.0)
+    z_focal = -(f - T / n_design)
+    n = cauchy_index(lam)
+    vols = [new_volume(ROLE_LENS, SHAPE_ASPHERE, OUTLINE_DISC, c=(0.0, 0.0, T), p=[a] + list(b), o=[a],
+                       n_inside=n, shape_param=0),
+            new_volume(ROLE_LENS, SHAPE_PLANE, OUTLINE_DISC, Q=np.diag([1.0, -1.0, -1.0]), c=(0.0, 0.0, 0.0),
+                       o=[a], n_inside=n),
+            new_volume(ROLE_OBSCURATION, SHAPE_CYLINDER, c=(0.0, 0.0, 0.0), p=[a, edge]),
+            new_volume(ROLE_FOCAL, SHAPE_PLANE, OUTLINE_DISC, c=(0.0, 0.0, z_focal), o=[0.08])]
+    names = [f"front_b{i}" for i in range(1, 9)]
+    return _finish("aspheric_lens", vols, list(b), names, precision, 16, seed, f,
+                   np.radians(np.asarray(fields_deg, dtype=np.float64)), _dish_rays(a, 1.0),
+                   lam=lam, n_index=n, thickness=T, design_focus=f, focal_z=z_focal,
+                   beam=dict(kind="disc_perp", r_out=a, back=1.0))
+
+
+def lens_wavelengths(lams=tuple(np.linspace(300e-9, 600e-9, 16)), **kw):
+    """The aspheric singlet at each wavelength of lams (one scene per
+    wavelength; the same surfaces, the index of that wavelength)."""
+    return [aspheric_lens(lam=float(l), **kw) for l in lams]
+
+
 ALL = {
     "single_mirror": single_mirror,
     "davies_cotton": davies_cotton,
@@ -756,4 +809,5 @@ ALL = {
     "hex_concentrator": hex_concentrator,
     "lst_parabolic": lst_parabolic,
     "gct_sc": gct_sc,
+    "aspheric_lens": aspheric_lens,
 }

@@ -125,6 +125,22 @@ def test_small_sc_rms_gradient(rb, precision, n_per, floor):
     print(f"GCT fp{precision}: 30 params, worst rel {e:.2e}")
 
 
+@pytest.mark.parametrize("precision,n_per,floor,lam", [(32, 20000, 1e-2, 400e-9), (64, 3000, 1e-3, 400e-9),
+                                                      (64, 3000, 1e-3, 300e-9)])
+def test_lens_rms_gradient(rb, precision, n_per, floor, lam):
+    """The aspheric singlet: d(mean RMS)/d(front-face coefficients) through
+    two refractions of a curved face (normal and Hessian terms)."""
+    import oracle
+    sc = scenes.aspheric_lens(precision=precision, lam=lam)
+    r = sc.rays(n_per)
+    w = np.full(sc.n_groups, 1.0 / sc.n_groups)
+    g = gpu_grad(rb, sc, r, w_rms=w)
+    rec = oracle.trace(sc, r, log=True)
+    ref = oracle.gradient_rms(sc, r, rec, w)
+    e = check(g, ref, floor, sc.param_names)
+    print(f"lens fp{precision} {lam * 1e9:.0f} nm: 8 params, worst rel {e:.2e}")
+
+
 @pytest.mark.parametrize("precision", [32, 64])
 def test_concentrator_weighted_collection_gradient(rb, precision):
     import oracle

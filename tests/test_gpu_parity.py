@@ -147,7 +147,8 @@ def test_single_mirror_fp64_full(rb):
                                              ("schwarzschild_couder", 3000, 1e-5),
                                              ("hex_concentrator", 600, 5e-4),
                                              ("lst_parabolic", 20000, 1e-5),
-                                             ("gct_sc", 5000, 1e-5)])
+                                             ("gct_sc", 5000, 1e-5),
+                                             ("aspheric_lens", 20000, 1e-5)])
 def test_fp32_scene_parity(rb, name, n_per, rate):
     import oracle
     sc = scenes.ALL[name]()
@@ -180,6 +181,30 @@ def test_fp64_small_sc_parity(rb):
     shadow = (ref["fate"] == scenes.FATE_ABSORBED) & np.isin(ref["last_vol"], st)
     assert shadow.sum() > 0.05 * len(r["ox"])
     print(f"gct_sc fp64: N={len(r['ox'])} mismatches={nbad} max|dpos|={dp:.3e} shadowed={shadow.mean():.3f}")
+
+
+@pytest.mark.parametrize("lam", [300e-9, 600e-9])
+def test_fp64_lens_parity(rb, lam):
+    """The aspheric singlet (refracting asphere and plane faces, Fresnel
+    reflection draws, absorbing rim) in FP64 at two wavelengths."""
+    import oracle
+    sc = scenes.aspheric_lens(precision=64, lam=lam)
+    r = sc.rays(3000)
+    got = gpu_trace(rb, sc, r)
+    ref = oracle.trace(sc, r, log=True)
+    nbad, dp, dd = compare(sc, r, got, ref, 1e-9 * sc.l_ref, 1e-9)
+    # optical paths under the bar of the positions: glancing paths (|d.n| < 0.05
+    # at an event) carry 100x the tolerance, as in compare()
+    same = (got["fate"] == ref["fate"]) & (got["seq_hash"] == ref["seq_hash"])
+    foc = same & (ref["fate"] == scenes.FATE_FOCUSED)
+    glance = (ref["log"]["diag"][:, :, 3] < 0.05).any(axis=1)
+    dl = np.abs(got["opl"].astype(np.float64) - ref["opl"])
+    w = int(np.argmax(np.where(foc, dl, 0.0)))
+    print(f"aspheric_lens fp64 {lam * 1e9:.0f} nm: N={len(r['ox'])} mismatches={nbad} max|dpos|={dp:.3e} "
+          f"worst |dopl| {dl[w]:.3e} (photon {w}, {int(ref['n_events'][w])} events, glancing {bool(glance[w])})")
+    assert dl[foc & ~glance].max() < 1e-9 * sc.l_ref
+    if (foc & glance).any():
+        assert dl[foc & glance].max() < 1e-7 * sc.l_ref
 
 
 def test_ragged_sizes_and_launch_shape(rb):

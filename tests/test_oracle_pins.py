@@ -452,10 +452,54 @@ def test_gct_structure_shadow_is_exact_occlusion(orc):
     assert n_hit > 100
 
 
+@pytest.mark.parametrize("lam", [300e-9, 400e-9, 600e-9])
+def test_lens_paraxial_back_focus_is_the_thick_lens_value(orc, lam):
+    """Plano-convex thick lens, curved face (vertex radius |R| = 0.5 m)
+    towards a beam parallel to the axis: paraxial rays cross the axis at the
+    back focal distance f - T/n behind the plane face, f = |R| / (n - 1), with
+    n = A + B / lam^2 (A = 1.4720, B = 3.2e-15 m^2).  The crossing of rays at
+    heights h and 2h, extrapolated to h = 0 (error O(h^4)), meets it to 1e-9 m;
+    the conic constant changes only the higher orders."""
+    sc = scenes.aspheric_lens(precision=64, lam=lam)
+    T = sc.volumes["c"][0][2]
+    n = 1.4720 + 3.2e-15 / lam ** 2
+    expect = -(0.5 / (n - 1.0) - T / n)
+    zs = []
+    for h in (0.002, 0.004):
+        m = 16   # the same ray under 16 ids: keep one that Fresnel reflection spared
+        r = scenes.make_rays(64, np.full(m, h), np.zeros(m), np.full(m, 1.0), np.zeros(m), np.zeros(m),
+                             -np.ones(m), np.zeros(m))
+        rec = orc.trace(sc, r)
+        ok = np.nonzero((rec["fate"] == scenes.FATE_FOCUSED) & (rec["n_events"] == 3))[0]
+        assert len(ok) > 8
+        i = ok[0]
+        x, z = rec["pos"][i, 0], rec["pos"][i, 2]
+        zs.append(z - x * rec["dir"][i, 2] / rec["dir"][i, 0])
+    assert abs((4 * zs[0] - zs[1]) / 3 - expect) < 1e-9
+    assert abs(zs[0] - expect) > 1e-7          # the extrapolation is needed: aberration is resolved
+
+
+def test_lens_spot_grows_away_from_the_design_wavelength(orc):
+    """Longitudinal chromatic aberration of the singlet: the focal plane sits
+    at the paraxial focus of 400 nm, and the index rises towards the blue, so
+    the focus moves away from the plane and the on-axis spot grows
+    monotonically from 400 to 300 nm (the focal shift itself is pinned by the
+    paraxial test above)."""
+    rms = []
+    for lam in (400e-9, 375e-9, 350e-9, 325e-9, 300e-9):
+        sc = scenes.aspheric_lens(precision=64, lam=lam, fields_deg=(0.0,))
+        r = sc.rays(4000)
+        rec = orc.trace(sc, r)
+        m = rec["fate"] == scenes.FATE_FOCUSED
+        x, y = rec["pos"][m, 0], rec["pos"][m, 1]
+        rms.append(np.sqrt(np.mean((x - x.mean()) ** 2 + (y - y.mean()) ** 2)))
+    assert all(b > a for a, b in zip(rms, rms[1:])), rms
+
+
 # ------------------------------------------------------------------ search invariants
 @pytest.mark.parametrize("name,n", [("davies_cotton", 300), ("schwarzschild_couder", 100),
                                     ("hex_concentrator", 20), ("lst_parabolic", 300),
-                                    ("gct_sc", 200)])
+                                    ("gct_sc", 200), ("aspheric_lens", 300)])
 def test_brute_force_equals_culled(orc, name, n):
     sc = scenes.ALL[name]()
     r = sc.rays(n)
@@ -467,7 +511,7 @@ def test_brute_force_equals_culled(orc, name, n):
 
 
 @pytest.mark.parametrize("name", ["single_mirror", "davies_cotton", "schwarzschild_couder",
-                                  "hex_concentrator", "lst_parabolic", "gct_sc"])
+                                  "hex_concentrator", "lst_parabolic", "gct_sc", "aspheric_lens"])
 def test_photon_conservation(orc, name):
     sc = scenes.ALL[name]()
     r = sc.rays(200)
