@@ -4,7 +4,7 @@
 // single-scene kernel and numbers them from the variant's first photon, so
 // every photon's result (and path record) equals that of a single-scene call
 // on its variant.  Per-lane FP64 figure sums are reduced across the wave per group
-// before one atomic per wave and sum.
+// after every work item, before one atomic per wave and sum.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -53,13 +53,15 @@ __device__ __forceinline__ void wave_flush(double* target, int& ag, double* a) {
 
 // Traces photons [start, end) of one variant whose first photon is `off`, a
 // whole photon per lane (consecutive lanes, consecutive binned photons).
-// The lanes' sums stay in registers across items of one group; a lane whose
-// next photon is of another group adds its sums directly.  Reached by the
-// whole workgroup.
+// The lanes' sums stay in registers within the item; a lane whose next
+// photon is of another group (an item across a group boundary) adds its
+// sums directly.  Reached by the whole workgroup.  long_seen (uniform across the wave) records that some
+// photon needs the adjoint's search pass; the kernel publishes it once per
+// wave at its end, not once per photon on one contended address.
 template <bool RECORD>
 __device__ __forceinline__ void trace_item(const SceneView<float>& L, int64_t start, int64_t end, int64_t off,
                                            const RaysView<float>& R, const HitsView<float>& H, double* target,
-                                           int& ag, double* a, uint32_t* long_flag) {
+                                           int& ag, double* a, bool& long_seen) {
   for (int64_t cur = start + threadIdx.x; cur < end; cur += blockDim.x) {
     float oa[3], da[3];
     R.load(cur, oa, da);
@@ -86,9 +88,8 @@ __device__ __forceinline__ void trace_item(const SceneView<float>& L, int64_t st
       else if (is_long) rec.x = kPathLong;
       reinterpret_cast<uint4*>(H.path)[cur] = rec;
       // the batched adjoint replays records of up to kPathSlots - 1 events;
-      // the rest are found again by its search pass, which this flag enables
-      const unsigned long long m = __ballot(r.fate == FOCUSED && r.nev >= kPathSlots);
-      if (m && (int)__lane_id() == __ffsll(m) - 1) atomicOr(long_flag, 1u);
+      // the rest are found again by its search pass, which the flag enables
+      long_seen = long_seen || __ballot(r.fate == FOCUSED && r.nev >= kPathSlots) != 0ull;
     }
     if (RECORD) {
       const int64_t q = R.src(cur);
@@ -131,19 +132,15 @@ k_trace_batch(const BatchVariant<float>* vars, const BatchItem* items, int n_ite
   extern __shared__ __align__(16) char lds[];
   __shared__ int s_item;
   int staged_v = -1;   // variant whose tables are in LDS
-  int acc_v = -1;      // variant whose sums the lanes hold
   double a[kNSumB];
 #pragma unroll
   for (int k = 0; k < kNSumB; ++k) a[k] = 0.0;
   int ag = -1;
+  bool long_seen = false;
   uint32_t* counter = queue + (USE_LDS ? kQFwdLds : kQFwdGlobal);
   while (true) {
     const int item = next_item(counter, &s_item);
     const BatchItem it = item < n_items ? load_uniform(items + item) : BatchItem{0, 0, -1};
-    if (acc_v >= 0 && it.v != acc_v) {
-      wave_flush(H.sums + (int64_t)load_uniform(vars + acc_v).goff * 8, ag, a);
-      acc_v = -1;
-    }
     if (item >= n_items) break;
     const BatchVariant<float> bv = load_uniform(vars + it.v);
     const SceneView<float> S = load_uniform(bv.S);
@@ -161,11 +158,15 @@ k_trace_batch(const BatchVariant<float>* vars, const BatchItem* items, int n_ite
     }
     double* target = H.sums ? H.sums + (int64_t)bv.goff * 8 : nullptr;
     trace_item<RECORD>(USE_LDS ? L : S, it.start, it.start + it.count, bv.off, R, H, target, ag, a,
-                       queue + kQLongFlag);
-    if (target) acc_v = it.v;
+                       long_seen);
+    // a workgroup's next item is usually far along the bundle (another group
+    // or variant): reduce the lanes' sums now, one atomic per wave and sum,
+    // rather than per lane later on a few contended addresses
+    if (target) wave_flush(target, ag, a);
     // a change of variant overwrites LDS: every wave must be done with it
     __syncthreads();
   }
+  if (long_seen && __lane_id() == 0) atomicOr(queue + kQLongFlag, 1u);
 }
 
 // ------------------------------------------------------------------ launcher
