@@ -350,14 +350,15 @@ def run_gct(args, torch, rb, scenes):
             "rms_spot_m": fig[:, 4].tolist(), "structure_shadow_fraction": per_field.tolist()}
 
 
-def run_chromatic(args, torch, rb, scenes):
-    """Wavelength as the batch axis: the aspheric singlet at 16 wavelengths
-    (300-600 nm; the same surfaces, the index of each wavelength), 4 fields
-    x 2.5e6 photons each.  One step = binning + forward + figures + adjoint
-    of every wavelength's RMS, batched (one forward and one adjoint launch)
-    against per-wavelength calls."""
+def run_chromatic(args, torch, rb, scenes, name="aspheric_lens"):
+    """Wavelength as the batch axis: a refracting lens (the aspheric singlet
+    or the Fresnel lens) at 16 wavelengths (300-600 nm; the same surfaces,
+    the index of each wavelength), 4 fields x 2.5e6 photons each.  One step
+    = binning + forward + figures + adjoint of every wavelength's RMS,
+    batched (one forward and one adjoint launch) against per-wavelength
+    calls."""
     lams = np.linspace(300e-9, 600e-9, 16)
-    variants = scenes.lens_wavelengths(lams)
+    variants = [scenes.ALL[name](lam=float(l)) for l in lams]
     devs = [rb.Scene(v) for v in variants]
     npf = args.chromatic_photons_per_field
     parts = [scenes.device_rays(v, npf, seed=v.seed + 100 * i + g, group=g)
@@ -406,11 +407,12 @@ def run_chromatic(args, torch, rb, scenes):
     rms = fig.view(-1, rb.FIGURE_STRIDE)[:, 4].cpu().numpy()
     on_axis = [float(rms[go[v]]) for v in range(len(devs))]
     tb, tp = float(np.mean(t_b)), float(np.mean(t_p))
-    print(f"[bench] chromatic: batched {tb:.2f} ms, plain {tp:.2f} ms ({n / (tb / 1e3):.3e} photons/s); "
+    print(f"[bench] chromatic {name}: batched {tb:.2f} ms, plain {tp:.2f} ms ({n / (tb / 1e3):.3e} photons/s); "
           f"on-axis RMS {min(on_axis) * 1e3:.2f}-{max(on_axis) * 1e3:.2f} mm", file=sys.stderr, flush=True)
-    return {"workload": f"aspheric_lens at 16 wavelengths (300-600 nm, Cauchy index) x 4 fields (0-3 deg) x "
-                        f"{npf:.1e} photons; one step = binning + forward + figures + adjoint (8 front-face "
-                        "coefficients per wavelength)",
+    fields = ", ".join(f"{np.degrees(g):g}" for g in variants[0].groups)
+    return {"workload": f"{name} at 16 wavelengths (300-600 nm, Cauchy index) x 4 fields ({fields} deg) x "
+                        f"{npf:.1e} photons; one step = binning + forward + figures + adjoint "
+                        f"({len(variants[0].params)} surface coefficients per wavelength)",
             "photons_per_step": n, "batched_ms_per_step": tb, "plain_ms_per_step": tp,
             "batched_photons_per_s": n / (tb / 1e3), "speedup": tp / tb,
             "wavelengths_nm": (lams * 1e9).tolist(), "on_axis_rms_m": on_axis}
@@ -510,7 +512,8 @@ def main():
     sweep = None if args.no_sweep else run_sweep(args, torch, rb, scenes)
     lst = None if args.no_lst else run_lst(args, torch, rb, scenes)
     gct = None if args.no_gct else run_gct(args, torch, rb, scenes)
-    chromatic = None if args.no_chromatic else run_chromatic(args, torch, rb, scenes)
+    chromatic = None if args.no_chromatic else {
+        nm: run_chromatic(args, torch, rb, scenes, nm) for nm in ("aspheric_lens", "fresnel_lens")}
 
     # algorithmic op tallies from the reference tracer's event log
     import oracle

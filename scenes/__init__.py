@@ -802,6 +802,68 @@ def lens_wavelengths(lams=tuple(np.linspace(300e-9, 600e-9, 16)), **kw):
     return [aspheric_lens(lam=float(l), **kw) for l in lams]
 
 
+def fresnel_lens(seed=SEED_BASE + 11, lam=400e-9, a=0.25, n_zones=10, bfl=2.0, t_base=0.01,
+                 fields_deg=(0.0, 0.5, 1.0, 1.5), design_lam=400e-9, precision=32):
+    """A flat Fresnel lens of the kind proposed for fluorescence and
+    Cherenkov telescopes (§1), at wavelength lam (index cauchy_index(lam);
+    the surfaces are fixed by the design wavelength).  Front: the plane
+    z = 0, r <= a, refracting, air above.  Back: n_zones annular zones of
+    equal width; zone j (r_j <= r <= r_j+1) is a refracting facet starting
+    at the groove bottom z = -t_base at r_j and shaped so that light
+    parallel to the axis inside the glass meets the focus F = (0, 0, z_F),
+    z_F = -t_base - bfl, with one optical path: n (-z) + |P - F| = const_j,
+    i.e. the hyperboloid of eccentricity n (k = -n^2) with vertex radius
+    (n - 1) w_j, w_j the height of its virtual vertex above F, given as the
+    Taylor coefficients b_1..b_8 (normalised form, rn = a) in a frame whose
+    +z faces the air below.  Between zones (and at the rim) absorbing
+    cylinders close the glass: the risers (draft facets) and the rim.
+    Focal plane: a disc of radius 0.08 m at z_F.  Parameters: the 8
+    coefficients of each zone."""
+    n0 = cauchy_index(design_lam)
+    k = -n0 * n0
+    z_F = -t_base - bfl
+    edges = np.linspace(0.0, a, n_zones + 1)
+
+    def delta(R, r):   # sag of the hyperboloid (k = -n0^2) of vertex radius R, >= 0
+        return r * r / (R + math.sqrt(R * R - (1.0 + k) * r * r))
+
+    vols = [new_volume(ROLE_LENS, SHAPE_PLANE, OUTLINE_DISC, c=(0.0, 0.0, 0.0), o=[a],
+                       n_inside=cauchy_index(lam))]
+    params, names, tops = [], [], []
+    for j in range(n_zones):
+        r0, r1 = edges[j], edges[j + 1]
+        # w: virtual vertex height above F with z_F + w + delta((n0 - 1) w, r0) = -t_base
+        w = -t_base - z_F
+        for _ in range(200):
+            f = z_F + w + delta((n0 - 1.0) * w, r0) + t_base
+            h = 1e-7 * w
+            fp = (z_F + w + h + delta((n0 - 1.0) * (w + h), r0) + t_base - f) / h
+            w_new = w - f / fp
+            if abs(w_new - w) < 1e-15 * w:
+                w = w_new
+                break
+            w = w_new
+        R = (n0 - 1.0) * w
+        b = conic_taylor(-R, k, a)            # sag -delta in the frame facing down
+        off = len(params)
+        params.extend(b)
+        names.extend(f"zone{j}_b{i}" for i in range(1, 9))
+        outline, o = (OUTLINE_DISC, [r1]) if r0 == 0.0 else (OUTLINE_ANNULUS, [r0, r1])
+        vols.append(new_volume(ROLE_LENS, SHAPE_ASPHERE, outline, Q=np.diag([1.0, -1.0, -1.0]),
+                               c=(0.0, 0.0, z_F + w), p=[a] + list(b), o=o, n_inside=cauchy_index(lam),
+                               shape_param=off))
+        tops.append(z_F + w + delta(R, r1))
+    for j in range(n_zones):
+        r1 = edges[j + 1]
+        top = tops[j] if j < n_zones - 1 else 0.0    # riser up to the zone's outer height; the rim to z = 0
+        vols.append(new_volume(ROLE_OBSCURATION, SHAPE_CYLINDER, c=(0.0, 0.0, -t_base), p=[r1, top + t_base]))
+    vols.append(new_volume(ROLE_FOCAL, SHAPE_PLANE, OUTLINE_DISC, c=(0.0, 0.0, z_F), o=[0.08]))
+    return _finish("fresnel_lens", vols, params, names, precision, 16, seed, bfl,
+                   np.radians(np.asarray(fields_deg, dtype=np.float64)), _dish_rays(a, 1.0),
+                   lam=lam, n_index=cauchy_index(lam), focal_z=z_F, zone_edges=edges.tolist(),
+                   groove_tops=tops, beam=dict(kind="disc_perp", r_out=a, back=1.0))
+
+
 ALL = {
     "single_mirror": single_mirror,
     "davies_cotton": davies_cotton,
@@ -810,4 +872,5 @@ ALL = {
     "lst_parabolic": lst_parabolic,
     "gct_sc": gct_sc,
     "aspheric_lens": aspheric_lens,
+    "fresnel_lens": fresnel_lens,
 }

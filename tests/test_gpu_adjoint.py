@@ -141,6 +141,21 @@ def test_lens_rms_gradient(rb, precision, n_per, floor, lam):
     print(f"lens fp{precision} {lam * 1e9:.0f} nm: 8 params, worst rel {e:.2e}")
 
 
+@pytest.mark.parametrize("precision,n_per,floor", [(32, 20000, 1e-2), (64, 3000, 1e-3)])
+def test_fresnel_rms_gradient(rb, precision, n_per, floor):
+    """The Fresnel lens at 350 nm (off its design wavelength): d(mean RMS)
+    / d(the 8 coefficients of each of its 10 zones)."""
+    import oracle
+    sc = scenes.fresnel_lens(precision=precision, lam=350e-9)
+    r = sc.rays(n_per)
+    w = np.full(sc.n_groups, 1.0 / sc.n_groups)
+    g = gpu_grad(rb, sc, r, w_rms=w)
+    rec = oracle.trace(sc, r, log=True)
+    ref = oracle.gradient_rms(sc, r, rec, w)
+    e = check(g, ref, floor, sc.param_names)
+    print(f"fresnel fp{precision}: 80 params, worst rel {e:.2e}")
+
+
 @pytest.mark.parametrize("precision", [32, 64])
 def test_concentrator_weighted_collection_gradient(rb, precision):
     import oracle

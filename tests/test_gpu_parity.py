@@ -148,7 +148,8 @@ def test_single_mirror_fp64_full(rb):
                                              ("hex_concentrator", 600, 5e-4),
                                              ("lst_parabolic", 20000, 1e-5),
                                              ("gct_sc", 5000, 1e-5),
-                                             ("aspheric_lens", 20000, 1e-5)])
+                                             ("aspheric_lens", 20000, 1e-5),
+                                             ("fresnel_lens", 20000, 1e-5)])
 def test_fp32_scene_parity(rb, name, n_per, rate):
     import oracle
     sc = scenes.ALL[name]()
@@ -183,12 +184,14 @@ def test_fp64_small_sc_parity(rb):
     print(f"gct_sc fp64: N={len(r['ox'])} mismatches={nbad} max|dpos|={dp:.3e} shadowed={shadow.mean():.3f}")
 
 
-@pytest.mark.parametrize("lam", [300e-9, 600e-9])
-def test_fp64_lens_parity(rb, lam):
-    """The aspheric singlet (refracting asphere and plane faces, Fresnel
-    reflection draws, absorbing rim) in FP64 at two wavelengths."""
+@pytest.mark.parametrize("name,lam", [("aspheric_lens", 300e-9), ("aspheric_lens", 600e-9),
+                                      ("fresnel_lens", 400e-9), ("fresnel_lens", 300e-9)])
+def test_fp64_lens_parity(rb, name, lam):
+    """The aspheric singlet and the Fresnel lens (refracting asphere and
+    plane faces, Fresnel reflection draws, absorbing rim and risers) in FP64
+    at two wavelengths."""
     import oracle
-    sc = scenes.aspheric_lens(precision=64, lam=lam)
+    sc = scenes.ALL[name](precision=64, lam=lam)
     r = sc.rays(3000)
     got = gpu_trace(rb, sc, r)
     ref = oracle.trace(sc, r, log=True)
@@ -200,7 +203,7 @@ def test_fp64_lens_parity(rb, lam):
     glance = (ref["log"]["diag"][:, :, 3] < 0.05).any(axis=1)
     dl = np.abs(got["opl"].astype(np.float64) - ref["opl"])
     w = int(np.argmax(np.where(foc, dl, 0.0)))
-    print(f"aspheric_lens fp64 {lam * 1e9:.0f} nm: N={len(r['ox'])} mismatches={nbad} max|dpos|={dp:.3e} "
+    print(f"{name} fp64 {lam * 1e9:.0f} nm: N={len(r['ox'])} mismatches={nbad} max|dpos|={dp:.3e} "
           f"worst |dopl| {dl[w]:.3e} (photon {w}, {int(ref['n_events'][w])} events, glancing {bool(glance[w])})")
     assert dl[foc & ~glance].max() < 1e-9 * sc.l_ref
     if (foc & glance).any():

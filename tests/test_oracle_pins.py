@@ -496,10 +496,51 @@ def test_lens_spot_grows_away_from_the_design_wavelength(orc):
     assert all(b > a for a, b in zip(rms, rms[1:])), rms
 
 
+def test_fresnel_zones_are_stigmatic_and_isochronous(orc):
+    """Each zone of the Fresnel lens is a surface of one optical path
+    n (-z) + |P - F| from the plane to the focus F, so at the design
+    wavelength every on-axis photon that crosses the plane and one facet
+    lands on F (to the 8-term Taylor truncation of its hyperboloid, far
+    below 1e-9 m here), every zone carries light, and within a zone all such
+    paths from the launch plane z = 1 m have one optical length."""
+    sc = scenes.fresnel_lens(precision=64, fields_deg=(0.0,))
+    r = sc.rays(6000)
+    rec = orc.trace(sc, r, log=True)
+    ok = (rec["fate"] == scenes.FATE_FOCUSED) & (rec["n_events"] == 3)
+    assert ok.mean() > 0.85
+    zF = sc.meta["focal_z"]
+    assert np.abs(rec["pos"][ok, 0]).max() < 1e-9 and np.abs(rec["pos"][ok, 1]).max() < 1e-9
+    assert np.allclose(rec["pos"][ok, 2], zF, atol=1e-12)
+    zone = rec["log"]["vol"][ok, 1]
+    nz = len(sc.meta["zone_edges"]) - 1
+    assert set(np.unique(zone)) == set(range(1, nz + 1))
+    opl = rec["opl"][ok]
+    means = []
+    for j in range(1, nz + 1):
+        o = opl[zone == j]
+        assert o.max() - o.min() < 1e-9
+        means.append(o.mean())
+    assert np.ptp(means) > 1e-4          # zones differ: each has its own constant
+
+
+def test_fresnel_spot_grows_away_from_the_design_wavelength(orc):
+    """Off the design wavelength the zones no longer meet one focus: the
+    on-axis spot grows monotonically from 400 nm towards the blue."""
+    rms = []
+    for lam in (400e-9, 375e-9, 350e-9, 325e-9, 300e-9):
+        sc = scenes.fresnel_lens(precision=64, lam=lam, fields_deg=(0.0,))
+        r = sc.rays(3000)
+        rec = orc.trace(sc, r)
+        m = rec["fate"] == scenes.FATE_FOCUSED
+        x, y = rec["pos"][m, 0], rec["pos"][m, 1]
+        rms.append(np.sqrt(np.mean((x - x.mean()) ** 2 + (y - y.mean()) ** 2)))
+    assert rms[0] < 1e-8 and all(b > a for a, b in zip(rms, rms[1:])), rms
+
+
 # ------------------------------------------------------------------ search invariants
 @pytest.mark.parametrize("name,n", [("davies_cotton", 300), ("schwarzschild_couder", 100),
                                     ("hex_concentrator", 20), ("lst_parabolic", 300),
-                                    ("gct_sc", 200), ("aspheric_lens", 300)])
+                                    ("gct_sc", 200), ("aspheric_lens", 300), ("fresnel_lens", 300)])
 def test_brute_force_equals_culled(orc, name, n):
     sc = scenes.ALL[name]()
     r = sc.rays(n)
@@ -511,7 +552,8 @@ def test_brute_force_equals_culled(orc, name, n):
 
 
 @pytest.mark.parametrize("name", ["single_mirror", "davies_cotton", "schwarzschild_couder",
-                                  "hex_concentrator", "lst_parabolic", "gct_sc", "aspheric_lens"])
+                                  "hex_concentrator", "lst_parabolic", "gct_sc", "aspheric_lens",
+                                  "fresnel_lens"])
 def test_photon_conservation(orc, name):
     sc = scenes.ALL[name]()
     r = sc.rays(200)
