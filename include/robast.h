@@ -95,7 +95,12 @@ typedef struct {
                         * that the caller closes with its other faces (e.g. an
                         * aspheric front, a plane back with its front side
                         * facing out, an absorbing CYLINDER rim); CYLINDER and
-                        * HEXCONE lenses are EUNSUPPORTED. */
+                        * HEXCONE lenses are EUNSUPPORTED.  p[15] of a lens
+                        * volume: absorption length (m, >= 0; 0 = none) of
+                        * the medium on its back side: a photon that reaches
+                        * the face from that side after a segment of length
+                        * t is absorbed iff its bulk draw (Philox tag 2, see
+                        * robast_rays) w / 2^32 >= exp(-t / p[15]). */
   double Q0[9], c0[3], pivot[3], e1[3], e2[3];
 } robast_volume_desc;
 
@@ -111,8 +116,9 @@ typedef struct {
 
 /* Structure-of-arrays photon bundle.  Photon i has id id_base + i: its
  * random draws are Philox4x32-10 with key = seed and counter =
- * (id lo, id hi, event >> 2, 1), word event & 3 -- so a photon's result never
- * depends on launch shape or on which other photons share the launch. */
+ * (id lo, id hi, event >> 2, tag), word event & 3, tag 1 for the draw of an
+ * interaction and tag 2 for bulk absorption in a lens -- so a photon's result
+ * never depends on launch shape or on which other photons share the launch. */
 typedef struct {
   const void *ox, *oy, *oz, *dx, *dy, *dz; /* [device] n each, float or double */
   const uint32_t* group;                   /* [device] n, < n_groups; NULL = all group 0 */

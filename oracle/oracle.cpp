@@ -73,8 +73,11 @@ void philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t 
   for (int i = 0; i < 4; ++i) out[i] = c[i];
 }
 
-uint32_t draw(uint64_t seed, uint64_t id, int event) {
-  uint32_t ctr[4] = {(uint32_t)id, (uint32_t)(id >> 32), (uint32_t)(event >> 2), 1u};
+// Word event & 3 of the block with counter (id lo, id hi, event >> 2, tag):
+// tag 1 for the draw of an interaction (mirror absorption, Fresnel
+// reflection), tag 2 for bulk absorption in a lens.
+uint32_t draw(uint64_t seed, uint64_t id, int event, uint32_t tag = 1u) {
+  uint32_t ctr[4] = {(uint32_t)id, (uint32_t)(id >> 32), (uint32_t)(event >> 2), tag};
   uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
   uint32_t out[4];
   philox4x32_10(ctr, key, out);
@@ -706,7 +709,18 @@ Rec trace_one(const Scn& S, V3<double> o, V3<double> d, uint64_t id, int culled,
       double R = fresnel(cos_i, n1, n2, cos_t);
       uint32_t u = draw(S.seed, id, k);
       if (ldiag) ldiag[NDIAG * k + 4] = std::fabs((double)(u >> 8) * (1.0 / 16777216.0) - R);
-      if ((double)(u >> 8) * (1.0 / 16777216.0) < R) { d = d - (2.0 * dot(d, no)) * no; act = ACT_REFLECT; }
+      // bulk absorption (p[15] = absorption length L of the lens medium, 0 =
+      // none): the segment of length bt just crossed inside the glass is
+      // survived with probability exp(-bt / L)
+      bool absorbed = false;
+      if (back && v.p[15] > 0.0) {
+        double surv = std::exp(-bt / v.p[15]);
+        double w = (double)draw(S.seed, id, k, 2u) * (1.0 / 4294967296.0);
+        if (ldiag) ldiag[NDIAG * k + 4] = std::min(ldiag[NDIAG * k + 4], std::fabs(w - surv));
+        absorbed = w >= surv;
+      }
+      if (absorbed) r.fate = F_ABSORBED;
+      else if ((double)(u >> 8) * (1.0 / 16777216.0) < R) { d = d - (2.0 * dot(d, no)) * no; act = ACT_REFLECT; }
       else {
         double eta = n1 / n2;
         d = eta * d + (eta * cos_i - cos_t) * no;

@@ -140,6 +140,8 @@ int validate(const robast_scene_desc* d, const double* params, int64_t n_params)
     if (v.role == ROBAST_MIRROR && !(v.reflectivity >= 0.0 && v.reflectivity <= 1.0))
       return fail(ROBAST_EINVAL, "reflectivity outside [0, 1]" + at);
     if (v.role == ROBAST_LENS && !(v.n_inside > 0.0)) return fail(ROBAST_EINVAL, "lens index must be > 0" + at);
+    if (v.role == ROBAST_LENS && !(v.p[15] >= 0.0 && std::isfinite(v.p[15])))
+      return fail(ROBAST_EINVAL, "lens absorption length p[15] must be finite and >= 0" + at);
     if (v.role == ROBAST_LENS && v.shape != ROBAST_BOX && v.shape != ROBAST_PLANE && v.shape != ROBAST_SPHERE &&
         v.shape != ROBAST_ASPHERE)
       return fail(ROBAST_EUNSUPPORTED, "lens faces must be planes, spheres, aspheres or boxes" + at);
@@ -367,6 +369,7 @@ template <typename T> void fill_record(DVol<T>& r, const robast_volume_desc& v, 
   r.slope = q<T>(slope);
   r.rout = q<T>(outline_rmax(v) * (1.0 + 1e-6));
   r.n_in = q<T>(v.n_inside);
+  r.absl = v.role == ROBAST_LENS ? q<T>(v.p[15]) : T(0);
   // world AABB of the 8 corners, x = c + Q^{-1} x_l
   double I[9];
   inv3(v.Q, I);

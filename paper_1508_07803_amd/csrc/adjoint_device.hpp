@@ -354,6 +354,7 @@ template <typename T> __device__ __forceinline__ DVol<double> promote(const DVol
 #pragma unroll
   for (int i = 0; i < 12; ++i) r.p[i] = (double)v.p[i];
   r.n_in = (double)v.n_in;
+  r.absl = (double)v.absl;
   return r;
 }
 

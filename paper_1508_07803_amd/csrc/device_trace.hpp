@@ -54,15 +54,41 @@ __device__ __forceinline__ double rsqrt_d(double x) {
   y = y * (1.5 - 0.5 * x * y * y);
   return y;
 }
+// exp(-x) in double for x >= 0, inline and light on registers: x = n ln2 - r
+// with ln 2 split into a head exact in 32 bits and a tail (Cody and Waite's
+// reduction), |r| <= ln2 / 2, e^r by its Taylor series to degree 13 (the
+// remainder is below 1e-17), times 2^n assembled in the exponent field.
+__device__ __forceinline__ double exp_neg(double x) {
+  if (!(x < 700.0)) return 0.0;
+  const double n = __builtin_rint(x * 1.4426950408889634);   // x / ln 2
+  const double r = (n * 0.6931471803691238 - x) + n * 1.9082149292705877e-10;
+  double e = 1.0 / 6227020800.0;                                // 1/13!, then Horner
+  e = e * r + 1.0 / 479001600.0;
+  e = e * r + 1.0 / 39916800.0;
+  e = e * r + 1.0 / 3628800.0;
+  e = e * r + 1.0 / 362880.0;
+  e = e * r + 1.0 / 40320.0;
+  e = e * r + 1.0 / 5040.0;
+  e = e * r + 1.0 / 720.0;
+  e = e * r + 1.0 / 120.0;
+  e = e * r + 1.0 / 24.0;
+  e = e * r + 1.0 / 6.0;
+  e = e * r + 0.5;
+  e = e * r + 1.0;
+  e = e * r + 1.0;
+  return e * __builtin_bit_cast(double, (uint64_t)(1023 - (int64_t)n) << 52);
+}
+
 template <typename T> __device__ __forceinline__ bool finite3(V3<T> a) {
   return __builtin_isfinite(a.x) && __builtin_isfinite(a.y) && __builtin_isfinite(a.z);
 }
 
 // ------------------------------------------------------------------ Philox4x32-10
 // Salmon, Moraes, Dror, Shaw (SC'11): 10 rounds of two 32x32->64 multiplies
-// with Weyl-sequence key bumps.  Counter (id lo, id hi, event>>2, tag=1).
-__device__ __forceinline__ uint32_t philox_word(uint64_t seed, uint64_t id, int event) {
-  uint32_t c0 = (uint32_t)id, c1 = (uint32_t)(id >> 32), c2 = (uint32_t)(event >> 2), c3 = 1u;
+// with Weyl-sequence key bumps.  Counter (id lo, id hi, event>>2, tag): tag 1
+// for the draw of an interaction, tag 2 for bulk absorption in a lens.
+__device__ __forceinline__ uint32_t philox_word(uint64_t seed, uint64_t id, int event, uint32_t tag = 1u) {
+  uint32_t c0 = (uint32_t)id, c1 = (uint32_t)(id >> 32), c2 = (uint32_t)(event >> 2), c3 = tag;
   uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
@@ -74,6 +100,14 @@ __device__ __forceinline__ uint32_t philox_word(uint64_t seed, uint64_t id, int 
   }
   int w = event & 3;
   return w == 0 ? c0 : w == 1 ? c1 : w == 2 ? c2 : c3;
+}
+
+// Bulk absorption over a segment of length seg in a medium of absorption
+// length absl: absorbed iff the photon's tag-2 draw w / 2^32 >= exp(-seg/absl).
+// Kept out of line: only photons leaving absorbing glass call it, and its
+// registers then stay out of the allocation of the tracing loop.
+__device__ __noinline__ bool bulk_absorbed(uint64_t seed, uint64_t id, int k, double seg, double absl) {
+  return (double)philox_word(seed, id, k, 2u) * (1.0 / 4294967296.0) >= exp_neg(seg / absl);
 }
 
 // ------------------------------------------------------------------ frames and outlines
@@ -736,10 +770,12 @@ template <typename T> __device__ __forceinline__ T fresnel_R(T cos_i, T n1, T n2
 enum { ACT_REFLECT = 0, ACT_REFRACT = 1, ACT_STOP = 2 };
 
 // Apply the interaction of the event at X on (vol, face).  Updates d, ncur,
-// fate; returns the action.  `back` is set from the side the photon came from.
+// fate; returns the action.  `back` is set from the side the photon came from;
+// seg is the length of the segment that ends at this event.
 template <typename C, typename T> __device__ __forceinline__ int interact(const DVol<T>& v, V3<C> n, V3<C>& d,
                                                                           C& ncur, int& fate, int& back,
-                                                                          uint64_t seed, uint64_t id, int k) {
+                                                                          uint64_t seed, uint64_t id, int k,
+                                                                          double seg) {
   C dn = dot(d, n);
   back = dn < C(0) ? 0 : 1;
   switch (v.role) {
@@ -755,6 +791,12 @@ template <typename C, typename T> __device__ __forceinline__ int interact(const 
       return ACT_REFLECT;
     }
     case LENS: {
+      // bulk absorption: a photon reaching the face from inside survived the
+      // segment through the glass with probability exp(-seg / absl)
+      if (back && v.absl > T(0) && bulk_absorbed(seed, id, k, seg, (double)v.absl)) {
+        fate = ABSORBED;
+        return ACT_STOP;
+      }
       C nin = (C)v.n_in;
       C n1 = back ? nin : C(1), n2 = back ? C(1) : nin;
       V3<C> no = back ? scl(C(-1), n) : n;
@@ -812,7 +854,7 @@ template <typename T> __device__ __forceinline__ uint32_t photon_step(const Scen
   p.opl += p.ncur * b.tp;
   V3<double> n = front_normal(v, b.face, X, (double)b.s);
   int back, fate = 0;
-  int act = interact<double>(v, n, p.d, p.ncur, fate, back, S.seed, p.id, p.k);
+  int act = interact<double>(v, n, p.d, p.ncur, fate, back, S.seed, p.id, p.k, b.tp);
   p.hash = (p.hash ^ (((uint64_t)b.vol << 4) | ((uint64_t)b.face << 1) | (uint64_t)back)) * 0x100000001b3ull;
   p.last_vol = b.vol;
   uint32_t code = ((uint32_t)b.vol << 8) | ((uint32_t)b.face << 4) | (uint32_t)act;

@@ -24,6 +24,7 @@ enum Fate { FOCUSED = 1, ABSORBED = 2, EXITED = 3, SUSPENDED = 4, FAILED = 5 };
 //     HEX {a}; SECTOR {rin^2, rout^2, cos phi0, sin phi0, cos phi1, sin phi1, wide}
 //   lo/hi: local-frame box of the surface (asphere z-slab for bracketing)
 //   bmin/bmax: world AABB; slope: max |grad sag| of a sag surface on its outline
+//   absl: lenses: absorption length of the medium on the back side (0: none)
 template <typename T> struct alignas(16) DVol {
   T bmin[3], bmax[3];    // world AABB first: the candidate test reads only these and `shape`
   int32_t shape, role;
@@ -34,7 +35,7 @@ template <typename T> struct alignas(16) DVol {
   T p[12];
   T o[8];
   T lo[3], hi[3];
-  T n_in, slope, rout, pad;
+  T n_in, slope, rout, absl;
 };
 
 // Tilt data used only by the adjoint: pivot and the two world rotation axes

@@ -736,10 +736,12 @@ def empty_scene(precision=64):
                  SEED_BASE, 1.0, np.array([0.0]), rays)
 
 
-def window_slab(n_index=1.49, thickness=2.0, precision=64, seed=SEED_BASE + 7):
-    """A lone lens slab with normal-incidence photons (Fresnel statistics)."""
+def window_slab(n_index=1.49, thickness=2.0, precision=64, seed=SEED_BASE + 7, absorption_length=0.0):
+    """A lone lens slab with normal-incidence photons (Fresnel statistics;
+    bulk absorption with the given absorption length, 0 = none)."""
     vols = [new_volume(ROLE_LENS, SHAPE_BOX, c=(0, 0, 0), p=[100.0, 100.0, thickness / 2],
                        n_inside=n_index)]
+    vols[0]["p"][15] = absorption_length
 
     def rays(scene, n, s, groups):
         rng = np.random.default_rng(s)
@@ -759,7 +761,8 @@ def cauchy_index(lam, A=CAUCHY_PMMA[0], B=CAUCHY_PMMA[1]):
 
 
 def aspheric_lens(seed=SEED_BASE + 10, lam=400e-9, a=0.25, R=-0.5, k=None, edge=0.01,
-                  fields_deg=(0.0, 1.0, 2.0, 3.0), design_lam=400e-9, coeffs=None, precision=32):
+                  fields_deg=(0.0, 1.0, 2.0, 3.0), design_lam=400e-9, coeffs=None, precision=32,
+                  absorption_length=0.0):
     """A plano-aspheric singlet of the kind used as refracting optics for
     Cherenkov and fluorescence light (§1, §2.1: lenses and refractions), at
     wavelength lam: index cauchy_index(lam); everything else is fixed by the
@@ -772,7 +775,8 @@ def aspheric_lens(seed=SEED_BASE + 10, lam=400e-9, a=0.25, R=-0.5, k=None, edge=
     -z.  Rim: an absorbing cylinder r = a, 0 <= z <= edge.  Centre
     thickness T = edge - S(a).  Focal plane: a disc of radius 0.08 m at the
     paraxial back focus of the design wavelength, z = -(f - T/n) with
-    f = |R| / (n - 1).  Parameters: the 8 front-face coefficients.
+    f = |R| / (n - 1).  absorption_length (m, 0 = none): bulk absorption
+    of the glass, on both faces.  Parameters: the 8 front-face coefficients.
     Photons: parallel beams at the field angles over a disc of radius a
     normal to the beam, launched 1 m before the origin."""
     n_design = cauchy_index(design_lam)
@@ -789,6 +793,8 @@ def aspheric_lens(seed=SEED_BASE + 10, lam=400e-9, a=0.25, R=-0.5, k=None, edge=
                        o=[a], n_inside=n),
             new_volume(ROLE_OBSCURATION, SHAPE_CYLINDER, c=(0.0, 0.0, 0.0), p=[a, edge]),
             new_volume(ROLE_FOCAL, SHAPE_PLANE, OUTLINE_DISC, c=(0.0, 0.0, z_focal), o=[0.08])]
+    for v in vols[:2]:
+        v["p"][15] = absorption_length
     names = [f"front_b{i}" for i in range(1, 9)]
     return _finish("aspheric_lens", vols, list(b), names, precision, 16, seed, f,
                    np.radians(np.asarray(fields_deg, dtype=np.float64)), _dish_rays(a, 1.0),
@@ -803,7 +809,7 @@ def lens_wavelengths(lams=tuple(np.linspace(300e-9, 600e-9, 16)), **kw):
 
 
 def fresnel_lens(seed=SEED_BASE + 11, lam=400e-9, a=0.25, n_zones=10, bfl=2.0, t_base=0.01,
-                 fields_deg=(0.0, 0.5, 1.0, 1.5), design_lam=400e-9, precision=32):
+                 fields_deg=(0.0, 0.5, 1.0, 1.5), design_lam=400e-9, precision=32, absorption_length=0.0):
     """A flat Fresnel lens of the kind proposed for fluorescence and
     Cherenkov telescopes (§1), at wavelength lam (index cauchy_index(lam);
     the surfaces are fixed by the design wavelength).  Front: the plane
@@ -817,7 +823,8 @@ def fresnel_lens(seed=SEED_BASE + 11, lam=400e-9, a=0.25, n_zones=10, bfl=2.0, t
     Taylor coefficients b_1..b_8 (normalised form, rn = a) in a frame whose
     +z faces the air below.  Between zones (and at the rim) absorbing
     cylinders close the glass: the risers (draft facets) and the rim.
-    Focal plane: a disc of radius 0.08 m at z_F.  Parameters: the 8
+    Focal plane: a disc of radius 0.08 m at z_F.  absorption_length (m,
+    0 = none): bulk absorption of the glass.  Parameters: the 8
     coefficients of each zone."""
     n0 = cauchy_index(design_lam)
     k = -n0 * n0
@@ -858,6 +865,9 @@ def fresnel_lens(seed=SEED_BASE + 11, lam=400e-9, a=0.25, n_zones=10, bfl=2.0, t
         top = tops[j] if j < n_zones - 1 else 0.0    # riser up to the zone's outer height; the rim to z = 0
         vols.append(new_volume(ROLE_OBSCURATION, SHAPE_CYLINDER, c=(0.0, 0.0, -t_base), p=[r1, top + t_base]))
     vols.append(new_volume(ROLE_FOCAL, SHAPE_PLANE, OUTLINE_DISC, c=(0.0, 0.0, z_F), o=[0.08]))
+    for v in vols:
+        if v["role"] == ROLE_LENS:
+            v["p"][15] = absorption_length
     return _finish("fresnel_lens", vols, params, names, precision, 16, seed, bfl,
                    np.radians(np.asarray(fields_deg, dtype=np.float64)), _dish_rays(a, 1.0),
                    lam=lam, n_index=cauchy_index(lam), focal_z=z_F, zone_edges=edges.tolist(),

@@ -210,6 +210,28 @@ def test_fp64_lens_parity(rb, name, lam):
         assert dl[foc & glance].max() < 1e-7 * sc.l_ref
 
 
+@pytest.mark.parametrize("name,precision,L", [("aspheric_lens", 32, 0.3), ("aspheric_lens", 64, 0.3),
+                                              ("fresnel_lens", 64, 0.05), ("window_slab", 64, 1.0)])
+def test_absorbing_glass_parity(rb, name, precision, L):
+    """Bulk absorption in lens glass (a second Philox draw per segment
+    inside, tag 2): the same photons are absorbed, at the same event, as in
+    the oracle; the rest keep the positions bar."""
+    import oracle
+    kw = dict(absorption_length=L)
+    if name != "window_slab":
+        kw["precision"] = precision
+    sc = scenes.ALL[name](**kw) if name in scenes.ALL else scenes.window_slab(**kw)
+    r = sc.rays(20000 if name == "window_slab" else 4000)
+    got = gpu_trace(rb, sc, r)
+    ref = oracle.trace(sc, r, log=True)
+    tol = 1e-5 if precision == 32 else 1e-9
+    nbad, dp, dd = compare(sc, r, got, ref, tol * sc.l_ref, tol, require_focused=name != "window_slab")
+    absorbed = (ref["fate"] == scenes.FATE_ABSORBED) & (got["fate"] == ref["fate"])
+    assert absorbed.mean() > 0.02
+    print(f"{name} fp{precision} L={L}: N={len(r['ox'])} mismatches={nbad} absorbed={absorbed.mean():.3f} "
+          f"max|dpos|={dp:.3e}")
+
+
 def test_ragged_sizes_and_launch_shape(rb):
     """n not a multiple of the block; the same photons split over launches with
     id offsets give bit-identical records (draws keyed by photon id)."""

@@ -200,6 +200,28 @@ def test_slab_transmission_statistics(orc):
     assert np.allclose(np.abs(rec["dir"][:, 2]), 1.0, atol=1e-15)
 
 
+@pytest.mark.parametrize("L", [1.0, 4.0])
+def test_absorbing_slab_transmission_statistics(orc, L):
+    """Slab of thickness d = 2 and absorption length L at normal incidence,
+    all internal reflections incoherent: each crossing survives with
+    q = exp(-d / L), so transmission (1 - R0)^2 q / (1 - R0^2 q^2),
+    reflection R0 + (1 - R0)^2 R0 q^2 / (1 - R0^2 q^2), the rest absorbed."""
+    sc = scenes.window_slab(absorption_length=L)
+    r = sc.rays(200000)
+    rec = orc.trace(sc, r)
+    R0 = ((1.49 - 1) / 2.49) ** 2
+    q = math.exp(-2.0 / L)
+    T = (1 - R0) ** 2 * q / (1 - R0 ** 2 * q ** 2)
+    Rf = R0 + (1 - R0) ** 2 * R0 * q ** 2 / (1 - R0 ** 2 * q ** 2)
+    n = len(r["ox"])
+    ex = rec["fate"] == scenes.FATE_EXITED
+    down = ex & (rec["dir"][:, 2] < 0)
+    up = ex & (rec["dir"][:, 2] > 0)
+    for frac, p in ((down.mean(), T), (up.mean(), Rf), ((rec["fate"] == scenes.FATE_ABSORBED).mean(), 1 - T - Rf)):
+        assert abs(frac - p) < 5 * math.sqrt(p * (1 - p) / n), (frac, p)
+    assert np.all(ex | (rec["fate"] == scenes.FATE_ABSORBED))
+
+
 def test_slab_oblique_snell_displacement(orc):
     sc = scenes.window_slab()
     n, half = 1.49, 1.0
