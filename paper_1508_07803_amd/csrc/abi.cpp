@@ -200,6 +200,7 @@ struct robast_batch {
   std::vector<robast_scene*> scenes;
   int64_t n_photons = 0, n_groups = 0, n_params = 0;
   int max_events = 0, max_params = 0, n_items = 0;
+  int shapes = 0;                  // bit 1 << shape of every shape in any variant
   uint32_t blob_cap = 0, blob_cap_bwd = 0;
   void* d_vars = nullptr;          // BatchVariant<T>[n_scenes]
   BatchItem* d_items = nullptr;    // n_items
@@ -690,6 +691,8 @@ void compile_blob(robast_scene& s, std::vector<char>& blob, SceneView<T>& V, std
   for (uint16_t a : items) { blob.push_back((char)(a & 0xff)); blob.push_back((char)(a >> 8)); }
   align_to<T>(blob, 16);
   V.n_vol = nv;
+  V.shapes = 0;
+  for (const auto& v : s.desc) V.shapes |= 1 << v.shape;
   V.n_always = (int)always.size();
   V.n_grp = (int)grecs.size();
   V.max_events = s.max_events;
@@ -807,7 +810,7 @@ int check_hits(const robast_hits* hits) {
 
 template <typename T> BatchView<T> batch_view(const robast_batch* b) {
   return BatchView<T>{(const BatchVariant<T>*)b->d_vars, b->d_items, b->d_queue, b->n_items, b->max_events,
-                      b->max_params, b->blob_cap, b->blob_cap_bwd};
+                      b->max_params, b->blob_cap, b->blob_cap_bwd, b->shapes};
 }
 
 template <typename T> std::vector<BatchVariant<T>> variant_table(const robast_batch& b, const int64_t* offsets) {
@@ -1225,6 +1228,7 @@ int robast_build_batch(robast_scene* const* scenes, int32_t n_scenes, const int6
     b->max_events = std::max(b->max_events, s->max_events);
     b->max_params = std::max(b->max_params, (int)s->params.size());
     max_blob = std::max(max_blob, s->blob_bytes);
+    for (const auto& v : s->desc) b->shapes |= 1 << v.shape;
   }
   if (b->n_groups > INT32_MAX || b->n_params > INT32_MAX) {
     free_batch(b);

@@ -58,7 +58,7 @@ __device__ __forceinline__ void wave_flush(double* target, int& ag, double* a) {
 // sums directly.  Reached by the whole workgroup.  long_seen (uniform across the wave) records that some
 // photon needs the adjoint's search pass; the kernel publishes it once per
 // wave at its end, not once per photon on one contended address.
-template <bool RECORD>
+template <bool RECORD, int SH>
 __device__ __forceinline__ void trace_item(const SceneView<float>& L, int64_t start, int64_t end, int64_t off,
                                            const RaysView<float>& R, const HitsView<float>& H, double* target,
                                            int& ag, double* a, bool& long_seen) {
@@ -73,7 +73,7 @@ __device__ __forceinline__ void trace_item(const SceneView<float>& L, int64_t st
     uint4 rec = {kPathEnd, kPathEnd, kPathEnd, kPathEnd};   // path record, written once
     while (!ps.fate) {
       const int k = ps.k;
-      const uint32_t code = photon_step(L, ps);
+      const uint32_t code = photon_step<float, SH>(L, ps);
       if (H.path) {
         rec.x = k == 0 ? code : rec.x;
         rec.y = k == 1 ? code : rec.y;
@@ -125,7 +125,8 @@ __device__ __forceinline__ void trace_item(const SceneView<float>& L, int64_t st
 // table for every item rather than carried across items (only the staged
 // variant and the lanes' sums are).  The LDS form is held to 3 waves per SIMD
 // (<= 168 VGPRs); 4 measured slower.
-template <bool USE_LDS, bool RECORD>
+// SH: the shape set compiled in (the union over the variants).
+template <bool USE_LDS, bool RECORD, int SH>
 __global__ void __launch_bounds__(kBlockB) __attribute__((amdgpu_waves_per_eu(USE_LDS ? 3 : 1, USE_LDS ? 3 : 8)))
 k_trace_batch(const BatchVariant<float>* vars, const BatchItem* items, int n_items, uint32_t* queue,
               uint32_t blob_cap, RaysView<float> R, HitsView<float> H) {
@@ -157,7 +158,7 @@ k_trace_batch(const BatchVariant<float>* vars, const BatchItem* items, int n_ite
       }
     }
     double* target = H.sums ? H.sums + (int64_t)bv.goff * 8 : nullptr;
-    trace_item<RECORD>(USE_LDS ? L : S, it.start, it.start + it.count, bv.off, R, H, target, ag, a,
+    trace_item<RECORD, SH>(USE_LDS ? L : S, it.start, it.start + it.count, bv.off, R, H, target, ag, a,
                        long_seen);
     // a workgroup's next item is usually far along the bundle (another group
     // or variant): reduce the lanes' sums now, one atomic per wave and sum,
@@ -177,27 +178,34 @@ static hipError_t cu_count(int& ncu) {
   return hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
 }
 
-template <bool USE_LDS, bool RECORD>
+template <bool USE_LDS, bool RECORD, int SH>
 static hipError_t trace_batch_k(const BatchView<float>& B, const RaysView<float>& R, const HitsView<float>& H,
                                 int ncu, hipStream_t st) {
   const size_t shmem = USE_LDS ? B.blob_cap : 0;
   int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace_batch<USE_LDS, RECORD>, kBlockB,
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace_batch<USE_LDS, RECORD, SH>, kBlockB,
                                                               shmem);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
   const int blocks = std::max(1, std::min(B.n_items, ncu * per_cu));
-  hipLaunchKernelGGL((k_trace_batch<USE_LDS, RECORD>), dim3(blocks), dim3(kBlockB), shmem, st, B.vars, B.items,
+  hipLaunchKernelGGL((k_trace_batch<USE_LDS, RECORD, SH>), dim3(blocks), dim3(kBlockB), shmem, st, B.vars, B.items,
                      B.n_items, B.queue, B.blob_cap, R, H);
   return hipGetLastError();
+}
+
+template <bool RECORD, int SH>
+static hipError_t trace_batch_s(const BatchView<float>& B, const RaysView<float>& R, const HitsView<float>& H,
+                                int ncu, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  if (B.blob_cap > 0) e = trace_batch_k<true, RECORD, SH>(B, R, H, ncu, st);
+  if (e == hipSuccess) e = trace_batch_k<false, RECORD, SH>(B, R, H, ncu, st);
+  return e;
 }
 
 template <bool RECORD>
 static hipError_t trace_batch_r(const BatchView<float>& B, const RaysView<float>& R, const HitsView<float>& H,
                                 int ncu, hipStream_t st) {
-  hipError_t e = hipSuccess;
-  if (B.blob_cap > 0) e = trace_batch_k<true, RECORD>(B, R, H, ncu, st);
-  if (e == hipSuccess) e = trace_batch_k<false, RECORD>(B, R, H, ncu, st);
-  return e;
+  if (B.shapes & ~kShapesSurfaces) return trace_batch_s<RECORD, kShapesAll>(B, R, H, ncu, st);
+  return trace_batch_s<RECORD, kShapesSurfaces>(B, R, H, ncu, st);
 }
 
 hipError_t launch_trace_batch(const BatchView<float>& B, const RaysView<float>& R, const HitsView<float>& H,

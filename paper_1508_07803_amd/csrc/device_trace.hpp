@@ -223,34 +223,51 @@ template <typename C, typename P> __device__ __forceinline__ void bez_eval(const
 
 // Gradient of the face's implicit function at local point x, computed in C
 // from the record's parameters: it points to the front side (un-normalised).
-template <typename C, typename T> __device__ __forceinline__ V3<C> local_grad(const DVol<T>& v, int face, V3<C> x, C s) {
+// local_grad_of<SH> is the one of shape SH (known where a shape's own root
+// solver calls it, which keeps the other shapes' code out of that solver);
+// local_grad dispatches on the record's shape.
+template <int SH, typename C, typename T>
+__device__ __forceinline__ V3<C> local_grad_of(const DVol<T>& v, int face, V3<C> x, C s) {
+  if constexpr (SH == PLANE) {
+    return {C(0), C(0), C(1)};
+  } else if constexpr (SH == SPHERE) {
+    C c = (C)v.p[0];
+    return {-c * x.x, -c * x.y, C(1) - c * x.z};
+  } else if constexpr (SH == ASPHERE) {
+    C ir = (C)v.p[9];
+    C u = (x.x * x.x + x.y * x.y) * ir;
+    C S, dS;
+    sag_eval(v.p, u, S, dS);
+    C k = dS * C(2) * ir;
+    return {-k * x.x, -k * x.y, C(1)};
+  } else if constexpr (SH == CYLINDER) {
+    return {x.x, x.y, C(0)};
+  } else if constexpr (SH == BOX) {
+    int ax = face >> 1;
+    C sg = (face & 1) ? C(-1) : C(1);
+    return {ax == 0 ? sg : C(0), ax == 1 ? sg : C(0), ax == 2 ? sg : C(0)};
+  } else {
+    C rho, z, dr, dz;
+    bez_eval(v.p, s, rho, z, dr, dz);
+    C nx, ny;
+    wall_dir(face, nx, ny);
+    return {-dz * nx, -dz * ny, dr};
+  }
+}
+
+template <typename C, typename T, int SH = kShapesAll>
+__device__ __forceinline__ V3<C> local_grad(const DVol<T>& v, int face, V3<C> x, C s) {
   switch (v.shape) {
-    case PLANE: return {C(0), C(0), C(1)};
-    case SPHERE: {
-      C c = (C)v.p[0];
-      return {-c * x.x, -c * x.y, C(1) - c * x.z};
-    }
-    case ASPHERE: {
-      C ir = (C)v.p[9];
-      C u = (x.x * x.x + x.y * x.y) * ir;
-      C S, dS;
-      sag_eval(v.p, u, S, dS);
-      C k = dS * C(2) * ir;
-      return {-k * x.x, -k * x.y, C(1)};
-    }
-    case CYLINDER: return {x.x, x.y, C(0)};
-    case BOX: {
-      int ax = face >> 1;
-      C sg = (face & 1) ? C(-1) : C(1);
-      return {ax == 0 ? sg : C(0), ax == 1 ? sg : C(0), ax == 2 ? sg : C(0)};
-    }
-    default: {
-      C rho, z, dr, dz;
-      bez_eval(v.p, s, rho, z, dr, dz);
-      C nx, ny;
-      wall_dir(face, nx, ny);
-      return {-dz * nx, -dz * ny, dr};
-    }
+    case PLANE: return local_grad_of<PLANE, C>(v, face, x, s);
+    case SPHERE: return local_grad_of<SPHERE, C>(v, face, x, s);
+    case ASPHERE: return local_grad_of<ASPHERE, C>(v, face, x, s);
+    case CYLINDER: return local_grad_of<CYLINDER, C>(v, face, x, s);
+    case BOX:
+      if constexpr ((SH >> BOX) & 1) return local_grad_of<BOX, C>(v, face, x, s);
+      else return {C(0), C(0), C(1)};
+    default:
+      if constexpr ((SH >> HEXCONE) & 1) return local_grad_of<HEXCONE, C>(v, face, x, s);
+      else return {C(0), C(0), C(1)};
   }
 }
 
@@ -261,11 +278,12 @@ struct SelfRule {
   int face;   // face of this volume the photon just left, or -1
   int side;   // side of that face the photon is on
 };
-template <typename T> __device__ __forceinline__ bool self_ok(const DVol<T>& v, const SelfRule& sr, int face,
-                                                             T tt, T eps, V3<T> x, V3<T> d, T s) {
+template <int SH, typename T>
+__device__ __forceinline__ bool self_ok(const DVol<T>& v, const SelfRule& sr, int face, T tt, T eps, V3<T> x, V3<T> d,
+                                        T s) {
   if (face != sr.face) return tt > T(0);
   if (!(tt > eps)) return false;
-  T sd = dot(d, local_grad(v, face, x, s));
+  T sd = dot(d, local_grad_of<SH, T>(v, face, x, s));
   return (sd < T(0)) == (sr.side == 0);
 }
 
@@ -293,7 +311,7 @@ template <typename T> __device__ __forceinline__ void nf_plane(const DVol<T>& v,
   T tt = t + t0;
   if (tt > b.t) return;
   V3<T> x = fma3(t, d, o);
-  if (!self_ok(v, sr, 0, tt, eps, x, d, T(0))) return;
+  if (!self_ok<PLANE>(v, sr, 0, tt, eps, x, d, T(0))) return;
   if (inside_outline(v, x.x, x.y)) offer(b, tt, vid, 0, T(0), (double)t0 + (double)t);
 }
 
@@ -308,7 +326,7 @@ template <typename T> __device__ __forceinline__ void nf_sphere(const DVol<T>& v
     if (tt > b.t) continue;
     V3<T> x = fma3(r[i], d, o);
     if (T(1) - cv * x.z < T(0)) continue;
-    if (!self_ok(v, sr, 0, tt, eps, x, d, T(0))) continue;
+    if (!self_ok<SPHERE>(v, sr, 0, tt, eps, x, d, T(0))) continue;
     if (inside_outline(v, x.x, x.y)) offer(b, tt, vid, 0, T(0), (double)t0 + (double)r[i]);
   }
 }
@@ -395,7 +413,7 @@ template <typename T> __device__ __forceinline__ void nf_asphere(const DVol<T>& 
   T tt = t + t0;
   if (tt > b.t) return;
   V3<T> x = fma3(t, d, o);
-  if (!self_ok(v, sr, 0, tt, eps, x, d, T(0))) return;
+  if (!self_ok<ASPHERE>(v, sr, 0, tt, eps, x, d, T(0))) return;
   if (inside_outline(v, x.x, x.y)) offer(b, tt, vid, 0, T(0), (double)t0 + (double)t);
 }
 
@@ -410,7 +428,7 @@ template <typename T> __device__ __forceinline__ void nf_cylinder(const DVol<T>&
     T tt = r[i] + t0;
     if (tt > b.t) continue;
     V3<T> x = fma3(r[i], d, o);
-    if (!self_ok(v, sr, 0, tt, eps, x, d, T(0))) continue;
+    if (!self_ok<CYLINDER>(v, sr, 0, tt, eps, x, d, T(0))) continue;
     if (x.z >= T(0) && x.z <= v.p[1]) offer(b, tt, vid, 0, T(0), (double)t0 + (double)r[i]);
   }
 }
@@ -425,7 +443,7 @@ template <typename T> __device__ __forceinline__ void nf_box(const DVol<T>& v, i
     T t = fdiv(sgn * v.p[ax] - oa[ax], da[ax]);
     T tt = t + t0;
     if (tt > b.t) continue;
-    if (!self_ok(v, sr, f, tt, eps, fma3(t, d, o), d, T(0))) continue;
+    if (!self_ok<BOX>(v, sr, f, tt, eps, fma3(t, d, o), d, T(0))) continue;
     bool ok = true;
 #pragma unroll
     for (int k = 0; k < 3; ++k)
@@ -555,7 +573,7 @@ template <typename T> __device__ __forceinline__ void nf_hexcone(const DVol<T>& 
       T tt = t + t0;
       if (tt > b.t) continue;
       V3<T> xh = fma3(t, d, o);
-      if (!self_ok(v, sr, f, tt, eps, xh, d, s)) continue;
+      if (!self_ok<HEXCONE>(v, sr, f, tt, eps, xh, d, s)) continue;
       T vt = -xh.x * ny + xh.y * nx;
       if (dabs(vt) <= rho * inv_sqrt3) offer(b, tt, vid, f, s, (double)t0 + (double)t);
     }
@@ -577,7 +595,8 @@ template <typename T> __device__ __forceinline__ bool aabb(const DVol<T>& v, V3<
 // Exact test of one volume; offers its nearest valid face root to b.
 // The photon position O is kept in double (world scale); of and inv are its
 // rounding and the inverse direction in T for the box tests.
-template <typename T> __device__ __forceinline__ void narrow(const DVol<T>& v, int vid, V3<double> O, V3<T> d,
+template <typename T, int SH = kShapesAll>
+__device__ __forceinline__ void narrow(const DVol<T>& v, int vid, V3<double> O, V3<T> d,
                                                              T tin, int prev_vol, int prev_face, int prev_side,
                                                              T eps, Best<T>& b) {
   // advance to the box entry to keep the local quadratic well conditioned;
@@ -591,8 +610,12 @@ template <typename T> __device__ __forceinline__ void narrow(const DVol<T>& v, i
     case SPHERE: nf_sphere(v, vid, ol, dl, t0, eps, sr, b); break;
     case ASPHERE: nf_asphere(v, vid, ol, dl, t0, eps, sr, b); break;
     case CYLINDER: nf_cylinder(v, vid, ol, dl, t0, eps, sr, b); break;
-    case BOX: nf_box(v, vid, ol, dl, t0, eps, sr, b); break;
-    case HEXCONE: nf_hexcone(v, vid, ol, dl, t0, eps, sr, b); break;
+    case BOX:
+      if constexpr ((SH >> BOX) & 1) nf_box(v, vid, ol, dl, t0, eps, sr, b);
+      break;
+    case HEXCONE:
+      if constexpr ((SH >> HEXCONE) & 1) nf_hexcone(v, vid, ol, dl, t0, eps, sr, b);
+      break;
   }
 }
 
@@ -629,7 +652,7 @@ template <typename T> struct Cands {
   int n;
 };
 
-template <typename T>
+template <typename T, int SH = kShapesAll>
 __device__ __forceinline__ void run_cands(const SceneView<T>& S, Cands<T>& c, V3<double> O, V3<T> d, int prev_vol,
                                           int prev_face, int prev_side, Best<T>& b) {
 #pragma unroll 1
@@ -643,17 +666,17 @@ __device__ __forceinline__ void run_cands(const SceneView<T>& S, Cands<T>& c, V3
     for (int j = 0; j < Cands<T>::K; ++j)
       if (j == sel) c.tin[j] = tinf<T>();
     if (vid < 0 || tin > b.t) break;
-    narrow(S.vol[vid], vid, O, d, tin, prev_vol, prev_face, prev_side, S.eps_self, b);
+    narrow<T, SH>(S.vol[vid], vid, O, d, tin, prev_vol, prev_face, prev_side, S.eps_self, b);
   }
   c.n = 0;
 }
 
-template <typename T>
+template <typename T, int SH = kShapesAll>
 __device__ __forceinline__ void gather(const SceneView<T>& S, Cands<T>& c, int vid, V3<T> o, V3<T> inv, V3<double> O,
                                        V3<T> d, int prev_vol, int prev_face, int prev_side, Best<T>& b) {
   T tin;
   if (!aabb(S.vol[vid], o, inv, b.t, tin)) return;
-  if (c.n == Cands<T>::K) run_cands(S, c, O, d, prev_vol, prev_face, prev_side, b);
+  if (c.n == Cands<T>::K) run_cands<T, SH>(S, c, O, d, prev_vol, prev_face, prev_side, b);
 #pragma unroll
   for (int j = 0; j < Cands<T>::K; ++j)
     if (j == c.n) { c.vid[j] = vid; c.tin[j] = tin; }
@@ -662,7 +685,8 @@ __device__ __forceinline__ void gather(const SceneView<T>& S, Cands<T>& c, int v
 
 // Non-sequential search: nearest face over the volume just left, the
 // always-list and the candidate groups crossed by the ray.
-template <typename T> __device__ void find_nearest(const SceneView<T>& S, V3<double> O, V3<T> d, int prev_vol,
+template <typename T, int SH = kShapesAll>
+__device__ void find_nearest(const SceneView<T>& S, V3<double> O, V3<T> d, int prev_vol,
                                                    int prev_face, int prev_side, Best<T>& b) {
   b.t = tinf<T>(); b.vol = -1; b.face = -1; b.s = T(0); b.tp = 0.0;
   Mailbox mb{prev_vol, -1, -1, -1};
@@ -672,10 +696,10 @@ template <typename T> __device__ void find_nearest(const SceneView<T>& S, V3<dou
   c.n = 0;
   // the volume just left first: photons bouncing inside a cone or between
   // facets usually meet it (or its neighbour) next
-  if (prev_vol >= 0) gather(S, c, prev_vol, o, inv, O, d, prev_vol, prev_face, prev_side, b);
+  if (prev_vol >= 0) gather<T, SH>(S, c, prev_vol, o, inv, O, d, prev_vol, prev_face, prev_side, b);
   for (int i = 0; i < S.n_always; ++i) {
     int vid = S.always[i];
-    if (vid != prev_vol) gather(S, c, vid, o, inv, O, d, prev_vol, prev_face, prev_side, b);
+    if (vid != prev_vol) gather<T, SH>(S, c, vid, o, inv, O, d, prev_vol, prev_face, prev_side, b);
   }
   // candidate groups: walk each group's grid over the stretch of the ray that
   // lies inside the group's z-slab (in the group frame)
@@ -729,7 +753,7 @@ template <typename T> __device__ void find_nearest(const SceneView<T>& S, V3<dou
         int vid = S.items[k];
         if (!mb.seen(vid)) {
           mb.put(vid);
-          gather(S, c, vid, o, inv, O, d, prev_vol, prev_face, prev_side, b);
+          gather<T, SH>(S, c, vid, o, inv, O, d, prev_vol, prev_face, prev_side, b);
         }
       }
       T tn = dmin(tmx, tmy);
@@ -738,12 +762,13 @@ template <typename T> __device__ void find_nearest(const SceneView<T>& S, V3<dou
       else { iy += sy; tmy += tdy; if (iy < 0 || iy >= G.ny) break; }
     }
   }
-  run_cands(S, c, O, d, prev_vol, prev_face, prev_side, b);
+  run_cands<T, SH>(S, c, O, d, prev_vol, prev_face, prev_side, b);
 }
 
 // Front normal (world, double) of the face hit at world point X (double):
 // local point, gradient and normalisation in double from the record.
-template <typename T> __device__ __forceinline__ V3<double> front_normal(const DVol<T>& v, int face, V3<double> X,
+template <typename T, int SH = kShapesAll>
+__device__ __forceinline__ V3<double> front_normal(const DVol<T>& v, int face, V3<double> X,
                                                                         double s) {
   double rx = X.x - (double)v.c[0], ry = X.y - (double)v.c[1], rz = X.z - (double)v.c[2];
   double Q[9];
@@ -751,7 +776,7 @@ template <typename T> __device__ __forceinline__ V3<double> front_normal(const D
   for (int i = 0; i < 9; ++i) Q[i] = (double)v.Q[i];
   V3<double> x = {Q[0] * rx + Q[1] * ry + Q[2] * rz, Q[3] * rx + Q[4] * ry + Q[5] * rz,
                   Q[6] * rx + Q[7] * ry + Q[8] * rz};
-  V3<double> g = local_grad<double>(v, face, x, s);
+  V3<double> g = local_grad<double, T, SH>(v, face, x, s);
   V3<double> w = {Q[0] * g.x + Q[3] * g.y + Q[6] * g.z, Q[1] * g.x + Q[4] * g.y + Q[7] * g.z,
                   Q[2] * g.x + Q[5] * g.y + Q[8] * g.z};
   return scl(rsqrt_d(dot(w, w)), w);
@@ -844,15 +869,17 @@ template <typename T> __device__ __forceinline__ void photon_init(PhotonState& p
 // One interaction of the non-sequential transport: nearest surface, then the
 // role of its volume.  Returns the event code (vol << 8 | face << 4 | action)
 // of the interaction, or 0xffffffff when the photon ends without one.
-template <typename T> __device__ __forceinline__ uint32_t photon_step(const SceneView<T>& S, PhotonState& p) {
+// SH: the shape set of the calling kernel (a scene holding only those shapes).
+template <typename T, int SH = kShapesAll>
+__device__ __forceinline__ uint32_t photon_step(const SceneView<T>& S, PhotonState& p) {
   if (p.k == S.max_events) { p.fate = SUSPENDED; return 0xffffffffu; }
   Best<T> b;
-  find_nearest(S, p.o, to_t<T>(p.d), p.prev_v, p.prev_f, p.prev_side, b);
+  find_nearest<T, SH>(S, p.o, to_t<T>(p.d), p.prev_v, p.prev_f, p.prev_side, b);
   if (b.vol < 0) { p.fate = EXITED; return 0xffffffffu; }
   const DVol<T>& v = S.vol[b.vol];
   V3<double> X = {p.o.x + b.tp * p.d.x, p.o.y + b.tp * p.d.y, p.o.z + b.tp * p.d.z};
   p.opl += p.ncur * b.tp;
-  V3<double> n = front_normal(v, b.face, X, (double)b.s);
+  V3<double> n = front_normal<T, SH>(v, b.face, X, (double)b.s);
   int back, fate = 0;
   int act = interact<double>(v, n, p.d, p.ncur, fate, back, S.seed, p.id, p.k, b.tp);
   p.hash = (p.hash ^ (((uint64_t)b.vol << 4) | ((uint64_t)b.face << 1) | (uint64_t)back)) * 0x100000001b3ull;

@@ -44,7 +44,9 @@ __device__ __forceinline__ void flush_lane(double* acc_lds, int g, const double*
 // FP32 kernels are held to 4 waves per SIMD (<= 128 VGPRs, a few spills):
 // measured faster than the 3 waves the unconstrained allocation gives, as
 // the extra wave hides LDS and memory latency of the search.
-template <typename T, bool RECORD, bool SUMS, bool USE_LDS>
+// SH: the shape set compiled in (kShapesSurfaces for scenes without boxes and
+// hex cones, else kShapesAll).
+template <typename T, bool RECORD, bool SUMS, bool USE_LDS, int SH>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1, 8))) k_trace(SceneView<T> S, RaysView<T> R, int64_t n, HitsView<T> H,
                                                   int sums_in_lds) {
   extern __shared__ __align__(16) char lds[];
@@ -79,7 +81,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
     uint4 rec = {kPathEnd, kPathEnd, kPathEnd, kPathEnd};
     while (!ps.fate) {
       const int k = ps.k;
-      const uint32_t code = photon_step(L, ps);
+      const uint32_t code = photon_step<T, SH>(L, ps);
       if (H.path) {
         rec.x = k == 0 ? code : rec.x;
         rec.y = k == 1 ? code : rec.y;
@@ -235,8 +237,8 @@ static hipError_t device_cus(int& ncu) {
   return hipSuccess;
 }
 
-template <typename T, bool RECORD, bool SUMS, bool USE_LDS>
-static hipError_t launch_one_l(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const HitsView<T>& H,
+template <typename T, bool RECORD, bool SUMS, bool USE_LDS, int SH>
+static hipError_t launch_one_s(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const HitsView<T>& H,
                              const LaunchCfg& cfg, hipStream_t st) {
   int ncu = 0;
   hipError_t e = device_cus(ncu);
@@ -246,15 +248,22 @@ static hipError_t launch_one_l(const SceneView<T>& S, const RaysView<T>& R, int6
   bool sums_lds = SUMS && sums_bytes <= 16384;
   size_t shmem = (use_lds ? ((S.blob_bytes + 15u) & ~15u) : 0u) + (sums_lds ? sums_bytes : 0);
   int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace<T, RECORD, SUMS, USE_LDS>, kBlock, shmem);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace<T, RECORD, SUMS, USE_LDS, SH>, kBlock, shmem);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
   int64_t want = (n + kBlock - 1) / kBlock;
   int64_t cap = (int64_t)ncu * per_cu * (cfg.waves_mult > 0 ? cfg.waves_mult : 1);
   if (cfg.max_blocks > 0) cap = std::min<int64_t>(cap, cfg.max_blocks);
   int blocks = (int)std::max<int64_t>(1, std::min(want, cap));
-  hipLaunchKernelGGL((k_trace<T, RECORD, SUMS, USE_LDS>), dim3(blocks), dim3(kBlock), shmem, st, S, R, n, H,
+  hipLaunchKernelGGL((k_trace<T, RECORD, SUMS, USE_LDS, SH>), dim3(blocks), dim3(kBlock), shmem, st, S, R, n, H,
                      sums_lds ? 1 : 0);
   return hipGetLastError();
+}
+
+template <typename T, bool RECORD, bool SUMS, bool USE_LDS>
+static hipError_t launch_one_l(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const HitsView<T>& H,
+                               const LaunchCfg& cfg, hipStream_t st) {
+  if (S.shapes & ~kShapesSurfaces) return launch_one_s<T, RECORD, SUMS, USE_LDS, kShapesAll>(S, R, n, H, cfg, st);
+  return launch_one_s<T, RECORD, SUMS, USE_LDS, kShapesSurfaces>(S, R, n, H, cfg, st);
 }
 
 template <typename T, bool RECORD, bool SUMS>

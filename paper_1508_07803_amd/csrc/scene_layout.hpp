@@ -17,6 +17,12 @@ enum Shape { PLANE = 1, SPHERE = 2, ASPHERE = 3, CYLINDER = 4, BOX = 5, HEXCONE 
 enum Outline { OL_NONE = 0, OL_DISC = 1, OL_ANNULUS = 2, OL_RECT = 3, OL_HEX = 4, OL_SECTOR = 5 };
 enum Fate { FOCUSED = 1, ABSORBED = 2, EXITED = 3, SUSPENDED = 4, FAILED = 5 };
 
+// Shape sets the tracing kernels are compiled for (bit 1 << shape): every
+// shape, or the surfaces only, for scenes without boxes and hex cones (their
+// root solvers then stay out of the kernel and its register allocation).
+constexpr int kShapesAll = (1 << PLANE) | (1 << SPHERE) | (1 << ASPHERE) | (1 << CYLINDER) | (1 << BOX) | (1 << HEXCONE);
+constexpr int kShapesSurfaces = (1 << PLANE) | (1 << SPHERE) | (1 << ASPHERE) | (1 << CYLINDER);
+
 // Per-volume record, precision T.
 //   p (shape, derived): SPHERE {c}; ASPHERE {rn, b1..b8, 1/rn^2}; CYLINDER {rho, h};
 //     BOX {hx, hy, hz}; HEXCONE {rho0 z0 rho1 z1 rho2 z2 rho3 z3}
@@ -65,7 +71,7 @@ template <typename T> struct SceneView {
   const uint32_t* cell_start;
   const uint16_t* items;
   const GroupRec<T>* groups;
-  int32_t n_vol, n_always, n_grp, pad0;
+  int32_t n_vol, n_always, n_grp, shapes;   // shapes: bit 1 << shape of every shape present
   int32_t max_events, n_groups;
   uint64_t seed;
   T eps_self;                      // self-intersection guard for the face just left
