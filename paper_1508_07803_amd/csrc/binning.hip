@@ -42,6 +42,12 @@ constexpr int kMaxFineShift = 13;                       // LDS counters of the f
 constexpr int64_t kTileMax = int64_t(1) << 21;          // photons per tile of the coarse pass, at most
 constexpr int64_t kTileMin = 4096;                      // and at least
 constexpr int64_t kTilesWanted = 256;                   // one workgroup per CU
+// staged fine scatter (FP32 records): buckets of at most kStagedMaxFine bins,
+// kChunk photons at a time through LDS (fits the kScatterLds request)
+constexpr int kStagedMaxFine = 1024;
+constexpr int kChunk = 2 * kFineBlock;
+static_assert((3 * kStagedMaxFine + kChunk + 4) * 4 + kChunk * 32 <= (int)kScatterLds,
+              "staged fine scatter exceeds its LDS");
 
 // bundle of photon i: the last v with offsets[v] <= i (offsets ascending)
 __device__ __forceinline__ int bundle_of(const int64_t* offsets, int n_var, int64_t i) {
@@ -137,12 +143,41 @@ __global__ void __launch_bounds__(kCoarseBlock) k_bin_coarse(RaysView<T> R, int6
 
 template <int NT> __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t& total);
 
+// Inclusive scan across the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
+  const int lane = (int)__lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// Exclusive scan across a workgroup of NT threads (NT / 64 <= 64 waves) with
+// two barriers: each wave scans its lanes, one wave scans the wave totals
+// (sh: NT / 64 words of LDS, free again after the second barrier's readers).
+template <int NT> __device__ __forceinline__ uint32_t block_exclusive_scan_waves(uint32_t v, uint32_t* sh) {
+  static_assert(NT % 64 == 0 && NT / 64 <= 64, "one wave scans the wave totals");
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t incl = wave_inclusive_scan(v);
+  if (lane == 63) sh[w] = incl;
+  __syncthreads();
+  if (w == 0) {
+    const uint32_t x = lane < NT / 64 ? sh[lane] : 0u;
+    const uint32_t xi = wave_inclusive_scan(x);
+    if (lane < NT / 64) sh[lane] = xi - x;
+  }
+  __syncthreads();
+  return incl - v + sh[w];
+}
+
 // (3) one workgroup per coarse bucket: fine counting sort into key order
 template <typename T>
 __global__ void __launch_bounds__(kFineBlock) k_bin_fine(int64_t n, int shift, int n_coarse, int n_tiles,
                                                          const uint32_t* offs, const uint32_t* tkey,
                                                          const BinRecord<T>* tmp, BinRecord<T>* out) {
-  extern __shared__ uint32_t fine[];
+  extern __shared__ __align__(16) uint32_t fine[];
   __shared__ uint32_t sh[kFineBlock];
   const int c = blockIdx.x;
   const int nf = 1 << shift;
@@ -184,6 +219,48 @@ __global__ void __launch_bounds__(kFineBlock) k_bin_fine(int64_t n, int shift, i
   uint4* dst = reinterpret_cast<uint4*>(out);
   const int64_t step = blockDim.x;
   if constexpr (sizeof(BinRecord<T>) == 32) {
+    if (nf <= kStagedMaxFine) {
+      // staged: chunks of kChunk photons are put in fine-digit order in LDS,
+      // then written out slot by slot, so that consecutive lanes write
+      // consecutive records of one bin (runs of whole lines) instead of
+      // 32-byte pieces scattered over all the bins
+      uint32_t* lc = fine + nf;   // the chunk's count per digit
+      uint32_t* ls = fine + 2 * nf;   // and its exclusive scan
+      uint32_t* dig = fine + 3 * nf;   // digit of each LDS slot
+      uint4* rec = reinterpret_cast<uint4*>(fine + ((3 * nf + kChunk + 3) & ~3));
+      const int tid = threadIdx.x;
+      for (int64_t cb = start; cb < end; cb += kChunk) {
+        const int cnt = (int)std::min<int64_t>(kChunk, end - cb);
+        for (int f = tid; f < nf; f += kFineBlock) lc[f] = 0u;
+        __syncthreads();
+        const int s0 = tid, s1 = tid + kFineBlock;
+        const bool h0 = s0 < cnt, h1 = s1 < cnt;
+        uint32_t f0 = 0u, f1 = 0u, r0 = 0u, r1 = 0u;
+        uint4 a0 = {}, a1 = {}, b0 = {}, b1 = {};
+        if (h0) { f0 = tkey[cb + s0] & mask; a0 = src[2 * (cb + s0)]; a1 = src[2 * (cb + s0) + 1]; }
+        if (h1) { f1 = tkey[cb + s1] & mask; b0 = src[2 * (cb + s1)]; b1 = src[2 * (cb + s1) + 1]; }
+        if (h0) r0 = atomicAdd(lc + f0, 1u);
+        if (h1) r1 = atomicAdd(lc + f1, 1u);
+        __syncthreads();
+        const uint32_t ex = block_exclusive_scan_waves<kFineBlock>(tid < nf ? lc[tid] : 0u, sh);
+        if (tid < nf) ls[tid] = ex;
+        __syncthreads();
+        // slots: ls[f] + rank covers [0, cnt) once
+        if (h0) { const uint32_t q = ls[f0] + r0; rec[2 * q] = a0; rec[2 * q + 1] = a1; dig[q] = f0; }
+        if (h1) { const uint32_t q = ls[f1] + r1; rec[2 * q] = b0; rec[2 * q + 1] = b1; dig[q] = f1; }
+        __syncthreads();
+        for (int q = tid; q < cnt; q += kFineBlock) {
+          const uint32_t f = dig[q];
+          const int64_t p = start + (int64_t)fine[f] + (int64_t)(q - (int)ls[f]);
+          dst[2 * p] = rec[2 * q];
+          dst[2 * p + 1] = rec[2 * q + 1];
+        }
+        __syncthreads();
+        for (int f = tid; f < nf; f += kFineBlock) fine[f] += lc[f];
+        __syncthreads();
+      }
+      return;
+    }
     for (int64_t i0 = start + threadIdx.x; i0 < end; i0 += step * kUnroll) {
       const int64_t i1 = i0 + step, i2 = i0 + 2 * step, i3 = i0 + 3 * step;
       const int64_t j1 = i1 < end ? i1 : end - 1, j2 = i2 < end ? i2 : end - 1, j3 = i3 < end ? i3 : end - 1;
