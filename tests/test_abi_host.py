@@ -82,6 +82,25 @@ def test_invalid_geometry_rejected(rb):
     assert _try(rb, sc, params=np.array([np.nan])) == rb.EINVAL
 
 
+def test_lens_face_rules(rb):
+    """Lens faces: planes, spheres, aspheres and boxes pass the checks; a
+    cylinder lens has no kernel; the absorption length p[15] must be finite
+    and >= 0."""
+    sc = scenes.aspheric_lens(precision=64)
+    assert _try(rb, sc) in (rb.OK, rb.EHIP)                  # asphere + plane lens faces
+    v = sc.volumes.copy()
+    v[2]["role"] = scenes.ROLE_LENS                          # the absorbing rim cylinder as a lens
+    v[2]["n_inside"] = 1.49
+    assert _try(rb, sc, volumes=v) == rb.EUNSUPPORTED
+    for bad in (-1.0, np.nan, np.inf):
+        v = sc.volumes.copy()
+        v[0]["p"][15] = bad
+        assert _try(rb, sc, volumes=v) == rb.EINVAL, bad
+    v = sc.volumes.copy()
+    v[0]["p"][15] = 0.3
+    assert _try(rb, sc, volumes=v) in (rb.OK, rb.EHIP)
+
+
 def test_null_arguments_rejected(rb):
     import ctypes
     lib = rb.lib()
