@@ -204,8 +204,8 @@ static hipError_t trace_batch_s(const BatchView<float>& B, const RaysView<float>
 template <bool RECORD>
 static hipError_t trace_batch_r(const BatchView<float>& B, const RaysView<float>& R, const HitsView<float>& H,
                                 int ncu, hipStream_t st) {
-  if (B.shapes & ~kShapesSurfaces) return trace_batch_s<RECORD, kShapesAll>(B, R, H, ncu, st);
-  return trace_batch_s<RECORD, kShapesSurfaces>(B, R, H, ncu, st);
+  if (B.shapes & ~kShapesNoCone) return trace_batch_s<RECORD, kShapesAll>(B, R, H, ncu, st);
+  return trace_batch_s<RECORD, kShapesNoCone>(B, R, H, ncu, st);
 }
 
 hipError_t launch_trace_batch(const BatchView<float>& B, const RaysView<float>& R, const HitsView<float>& H,

@@ -44,8 +44,8 @@ __device__ __forceinline__ void flush_lane(double* acc_lds, int g, const double*
 // FP32 kernels are held to 4 waves per SIMD (<= 128 VGPRs, a few spills):
 // measured faster than the 3 waves the unconstrained allocation gives, as
 // the extra wave hides LDS and memory latency of the search.
-// SH: the shape set compiled in (kShapesSurfaces for scenes without boxes and
-// hex cones, else kShapesAll).
+// SH: the shape set compiled in (kShapesNoCone for scenes without hex cones,
+// else kShapesAll).
 template <typename T, bool RECORD, bool SUMS, bool USE_LDS, int SH>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1, 8))) k_trace(SceneView<T> S, RaysView<T> R, int64_t n, HitsView<T> H,
                                                   int sums_in_lds) {
@@ -262,8 +262,8 @@ static hipError_t launch_one_s(const SceneView<T>& S, const RaysView<T>& R, int6
 template <typename T, bool RECORD, bool SUMS, bool USE_LDS>
 static hipError_t launch_one_l(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const HitsView<T>& H,
                                const LaunchCfg& cfg, hipStream_t st) {
-  if (S.shapes & ~kShapesSurfaces) return launch_one_s<T, RECORD, SUMS, USE_LDS, kShapesAll>(S, R, n, H, cfg, st);
-  return launch_one_s<T, RECORD, SUMS, USE_LDS, kShapesSurfaces>(S, R, n, H, cfg, st);
+  if (S.shapes & ~kShapesNoCone) return launch_one_s<T, RECORD, SUMS, USE_LDS, kShapesAll>(S, R, n, H, cfg, st);
+  return launch_one_s<T, RECORD, SUMS, USE_LDS, kShapesNoCone>(S, R, n, H, cfg, st);
 }
 
 template <typename T, bool RECORD, bool SUMS>

@@ -18,10 +18,11 @@ enum Outline { OL_NONE = 0, OL_DISC = 1, OL_ANNULUS = 2, OL_RECT = 3, OL_HEX = 4
 enum Fate { FOCUSED = 1, ABSORBED = 2, EXITED = 3, SUSPENDED = 4, FAILED = 5 };
 
 // Shape sets the tracing kernels are compiled for (bit 1 << shape): every
-// shape, or the surfaces only, for scenes without boxes and hex cones (their
-// root solvers then stay out of the kernel and its register allocation).
+// shape, or every shape but the hex cone, for scenes without hex cones (the
+// cone's root solver, the largest, then stays out of the kernel and its
+// register allocation).
 constexpr int kShapesAll = (1 << PLANE) | (1 << SPHERE) | (1 << ASPHERE) | (1 << CYLINDER) | (1 << BOX) | (1 << HEXCONE);
-constexpr int kShapesSurfaces = (1 << PLANE) | (1 << SPHERE) | (1 << ASPHERE) | (1 << CYLINDER);
+constexpr int kShapesNoCone = kShapesAll & ~(1 << HEXCONE);
 
 // Per-volume record, precision T.
 //   p (shape, derived): SPHERE {c}; ASPHERE {rn, b1..b8, 1/rn^2}; CYLINDER {rho, h};
