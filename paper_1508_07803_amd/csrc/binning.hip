@@ -59,10 +59,8 @@ __device__ __forceinline__ int bundle_of(const int64_t* offsets, int n_var, int6
   return lo;
 }
 
-template <typename T, bool MULTI>
-__device__ __forceinline__ uint32_t photon_key(const RaysView<T>& R, int64_t i, const BinGeom& geo1,
-                                               const BinMulti& multi) {
-  const BinGeom geo = MULTI ? multi.geo[bundle_of(multi.offsets, multi.n_var, i)] : geo1;
+template <typename T>
+__device__ __forceinline__ uint32_t photon_key(const RaysView<T>& R, int64_t i, const BinGeom& geo) {
   T o[3], d[3];
   R.load(i, o, d);
   double ox = (double)o[0], oy = (double)o[1];
@@ -91,10 +89,31 @@ __global__ void __launch_bounds__(kCoarseBlock) k_bin_keys(RaysView<T> R, int64_
   for (int c = threadIdx.x; c < n_coarse; c += blockDim.x) hist[c] = 0u;
   __syncthreads();
   const int64_t lo = (int64_t)blockIdx.x * tile, hi = lo + tile < n ? lo + tile : n;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    const uint32_t k = photon_key<T, MULTI>(R, i, geo1, multi);
-    key[i] = k;
-    atomicAdd(hist + (k >> shift), 1u);
+  if constexpr (MULTI) {
+    // a thread's photons only move forward through the bundles: find its
+    // first bundle once, then step past bundle ends (offsets[n_var] = n ends
+    // every step) and load a bundle's geometry only when it changes
+    int64_t i = lo + threadIdx.x;
+    if (i < hi) {
+      int v = bundle_of(multi.offsets, multi.n_var, i);
+      int64_t v_end = multi.offsets[v + 1];
+      BinGeom geo = multi.geo[v];
+      for (; i < hi; i += blockDim.x) {
+        if (i >= v_end) {
+          while (i >= v_end) v_end = multi.offsets[++v + 1];
+          geo = multi.geo[v];
+        }
+        const uint32_t k = photon_key<T>(R, i, geo);
+        key[i] = k;
+        atomicAdd(hist + (k >> shift), 1u);
+      }
+    }
+  } else {
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+      const uint32_t k = photon_key<T>(R, i, geo1);
+      key[i] = k;
+      atomicAdd(hist + (k >> shift), 1u);
+    }
   }
   __syncthreads();
   for (int c = threadIdx.x; c < n_coarse; c += blockDim.x) cnt[(int64_t)c * n_tiles + blockIdx.x] = hist[c];
