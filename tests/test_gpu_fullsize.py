@@ -1,8 +1,10 @@
 """Full benchmark sizes, in the launch configuration bench.py times.
 
 The workloads at their real sizes (Schwarzschild-Couder 16 fields x 1e7,
-Davies-Cotton 5 x 1e7, hex-cone array 91 x 1e6) are traced with binning on,
-exactly as the benchmark does.  The oracle cannot trace them whole, so:
+Davies-Cotton 5 x 1e7, hex-cone array 91 x 1e6, the segmented parabolic
+dish 5 x 1e7, the small SC 16 x 1e7, the aspheric singlet batched over 16
+wavelengths x 4 fields x 2.5e6) are traced with binning on, exactly as the
+benchmark does.  The oracle cannot trace them whole, so:
   * blocks of consecutive photons (start, middle, end of every field) are
     recomputed by the oracle with their photon ids and compared photon by
     photon (the parity bar of test_gpu_parity);
@@ -190,3 +192,83 @@ def test_sc_full_size_adjoint(rb):
     big = np.abs(g_ref).max()
     err = np.abs(got - g_ref) / np.maximum(np.abs(g_ref), 1e-2 * big)
     assert err.max() <= 1e-3, (int(np.argmax(err)), got[np.argmax(err)], g_ref[np.argmax(err)])
+
+
+def test_lst_full_size(rb):
+    """The segmented parabolic dish, 5 fields x 1e7 photons (the benchmark's
+    section), and its arrival figures against a reduction of the same
+    full-size records."""
+    sc = scenes.lst_parabolic()
+    npf = 10_000_000
+    rays = device_bundle(sc, npf)
+    dev, hits, sums = full_trace(rb, sc, rays)
+    check_sums_against_records(sc, rays, hits, sums, npf)
+    sampled_parity(sc, rays, hits, npf, 1e-5)
+    n = int(rays["ox"].numel())
+    rec = {"fate": hits["fate"], "opl": torch.empty(n, dtype=torch.float32, device="cuda")}
+    dev.trace(rays, hits=rec)
+    out = dev.arrival_figures(rays, rec).cpu().numpy()
+    foc = rec["fate"] == scenes.FATE_FOCUSED
+    g = rays["group"].long()
+    for k in range(sc.n_groups):
+        o = rec["opl"][foc & (g == k)].double()
+        assert out[k, 0] == o.numel()
+        assert out[k, 1] == pytest.approx(float(o.mean()), rel=1e-12)
+        assert out[k, 2] == pytest.approx(float(((o - o.mean()) ** 2).mean().sqrt()), rel=1e-6)
+
+
+def test_gct_full_size(rb):
+    """The small SC with masts, trusses and camera body, 16 fields x 1e7."""
+    sc = scenes.gct_sc()
+    npf = 10_000_000
+    rays = device_bundle(sc, npf)
+    dev, hits, sums = full_trace(rb, sc, rays)
+    check_sums_against_records(sc, rays, hits, sums, npf)
+    sampled_parity(sc, rays, hits, npf, 1e-5)
+
+
+def test_chromatic_batch_full_size(rb):
+    """The aspheric singlet at 16 wavelengths x 4 fields x 2.5e6 photons in
+    one batch (the benchmark's chromatic section): group sums against the
+    per-photon records, and blocks of three variants against the oracle of
+    their wavelength (photons numbered from 0 within each variant)."""
+    import oracle
+    from test_gpu_parity import compare
+    lams = np.linspace(300e-9, 600e-9, 16)
+    variants = [scenes.aspheric_lens(lam=float(l)) for l in lams]
+    devs = [rb.Scene(v) for v in variants]
+    npf = 2_500_000
+    parts = [scenes.device_rays(v, npf, seed=v.seed + 100 * i + g, group=g)
+             for i, v in enumerate(variants) for g in range(v.n_groups)]
+    rays = {k: torch.cat([p[k] for p in parts]) for k in parts[0]}
+    del parts
+    counts = [npf * v.n_groups for v in variants]
+    batch = rb.Batch(devs, counts, chunk=8192)
+    n = batch.n_photons
+    hits = {k: torch.empty(n, dtype=torch.float32, device="cuda") for k in ("x", "y", "z", "ux", "uy", "uz")}
+    hits["fate"] = torch.empty(n, dtype=torch.uint8, device="cuda")
+    hits["n_events"] = torch.empty(n, dtype=torch.uint8, device="cuda")
+    hits["last_vol"] = torch.empty(n, dtype=torch.int32, device="cuda")
+    hits["seq_hash"] = torch.empty(n, dtype=torch.int64, device="cuda")
+    sums = batch.new_sums()
+    batch.trace(rays, hits=hits, sums=sums)
+    torch.cuda.synchronize()
+    off = 0
+    total_bad = total = 0
+    for v, (sc, c) in enumerate(zip(variants, counts)):
+        sl = slice(off, off + c)
+        sub_r = {k: t[sl] for k, t in rays.items()}
+        sub_h = {k: t[sl] for k, t in hits.items()}
+        check_sums_against_records(sc, sub_r, sub_h, sums[batch.goff[v] * 8:batch.goff[v + 1] * 8], npf)
+        if v in (0, 7, 15):
+            for g in range(sc.n_groups):
+                for local in (g * npf, g * npf + npf // 2, (g + 1) * npf - 1000):
+                    host = host_block(sub_r, local, 1000)
+                    rec = oracle.trace(sc, host, id_base=local, log=True)
+                    nbad, _, _ = compare(sc, host, as_numpy(sub_h, slice(local, local + 1000)), rec,
+                                         1e-5 * sc.l_ref, 1e-5, max_rate=1.0, id_base=local)
+                    total_bad += nbad
+                    total += 1000
+        off += c
+    print(f"chromatic batch: sampled {total} photons, {total_bad} grazing mismatches")
+    assert total_bad <= max(3, 1e-5 * total)
