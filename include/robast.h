@@ -10,12 +10,18 @@
  *   - the trace is non-sequential: no surface order is fixed in advance, so
  *     multiple reflections on segmented mirrors and inside concentrators
  *     arise by themselves (§1, §2.1, §3);
+ *   - mirrors reflect (or absorb, by their reflectivity); lenses refract
+ *     with Fresnel reflection and total internal reflection, and may absorb
+ *     in their bulk (§2.1: refraction by lenses);
  *   - each photon leaves with an exit state: detected on a focal surface,
- *     absorbed, or escaped, plus its exit position and direction.
- * On top of the paper's forward trace the library returns gradients of the
- * focal-plane figures of §3 (spot RMS per field angle, cosine-weighted
- * collection per incidence angle) with respect to the scene's parameters,
- * by reverse mode along each photon's fixed surface sequence.
+ *     absorbed, or escaped, plus its exit position and direction and its
+ *     optical path (the arrival time of §3's timing-sensitive telescopes).
+ * On top of the paper's forward trace the library returns the focal-plane
+ * figures of §3 (spot RMS per field angle, cosine-weighted collection per
+ * incidence angle, arrival-time spread) and their gradients with respect to
+ * the scene's parameters, by reverse mode along each photon's fixed surface
+ * sequence, and traces many scene variants (a design sweep, a spectrum of
+ * wavelengths) in one batched launch.
  *
  * Conventions
  *   - Every function returns robast_status (0 = OK, < 0 = error) and never
