@@ -84,7 +84,8 @@ __device__ __forceinline__ void grad_end(const double* gacc, const GradLds& G, c
 // VGPRs, no spills; the unconstrained allocation gives 2).  With `list` the
 // kernel takes only the photons at the positions list[0 .. *count) (those
 // whose path record was too long); otherwise every photon of the bundle.
-template <typename T, int MAXE, bool USE_LDS>
+// SH (all kernels here): the shape set compiled in, as for the trace.
+template <typename T, int MAXE, bool USE_LDS, int SH>
 __global__ void __launch_bounds__(kBlockAdj)
 __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && MAXE <= 16) ? 3 : 1, 8)))
 k_backward(SceneView<T> S, RaysView<T> R, int64_t n, AdjView A, GradLds G, const uint32_t* list,
@@ -98,7 +99,7 @@ k_backward(SceneView<T> S, RaysView<T> R, int64_t n, AdjView A, GradLds G, const
   const int64_t m = list ? (int64_t)*count : n;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) {
     const int64_t i = list ? (int64_t)list[j] : j;
-    adjoint_photon<T, MAXE>(L, R, i, A, gs);
+    adjoint_photon<T, MAXE, SH>(L, R, i, A, gs);
   }
   grad_end(gacc, G, A);
 }
@@ -121,7 +122,7 @@ __device__ __forceinline__ void wave_append(bool take, uint32_t i, uint32_t* lis
 // sweep over three slots fits the registers without spills); those with
 // exactly kPathSlots events go to list4 for k_backward_path4, those whose
 // record is too long to the list for k_backward.
-template <typename T, bool USE_LDS>
+template <typename T, bool USE_LDS, int SH>
 __global__ void __launch_bounds__(kBlockAdj)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1, 8)))
 k_backward_path(SceneView<T> S, RaysView<T> R, int64_t n, AdjView A, GradLds G, PathView P) {
@@ -138,14 +139,14 @@ k_backward_path(SceneView<T> S, RaysView<T> R, int64_t n, AdjView A, GradLds G, 
     wave_append(w.x == kPathLong, (uint32_t)i, P.list, P.count);
     wave_append(full, (uint32_t)i, P.list4, P.count + 1);
     if (w.x >= kPathLong || full) continue;
-    adjoint_photon_path<T, true, kPathSlots - 1>(L, R, i, A, gs, w);
+    adjoint_photon_path<T, true, kPathSlots - 1, SH>(L, R, i, A, gs, w);
   }
   grad_end(gacc, G, A);
 }
 
 // The photons of list4 (records of exactly kPathSlots events), swept from
 // their records like the main pass.
-template <typename T, bool USE_LDS>
+template <typename T, bool USE_LDS, int SH>
 __global__ void __launch_bounds__(kBlockAdj)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1, 8)))
 k_backward_path4(SceneView<T> S, RaysView<T> R, AdjView A, GradLds G, PathView P) {
@@ -159,7 +160,7 @@ k_backward_path4(SceneView<T> S, RaysView<T> R, AdjView A, GradLds G, PathView P
   const int64_t m = (int64_t)P.count[1];
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) {
     const int64_t i = (int64_t)P.list4[j];
-    adjoint_photon_path<T, true, kPathSlots>(L, R, i, A, gs, rec[i]);
+    adjoint_photon_path<T, true, kPathSlots, SH>(L, R, i, A, gs, rec[i]);
   }
   grad_end(gacc, G, A);
 }
@@ -203,8 +204,8 @@ static hipError_t grid_for(K kernel, size_t shmem, int64_t n, const LaunchCfg& c
   return hipSuccess;
 }
 
-template <typename T, int MAXE, bool USE_LDS>
-static hipError_t launch_bwd_l(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const AdjView& A,
+template <typename T, int MAXE, bool USE_LDS, int SH>
+static hipError_t launch_bwd_s(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const AdjView& A,
                                const LaunchCfg& cfg, hipStream_t st, const PathView* P) {
   GradLds G;
   const size_t shmem = grad_layout(USE_LDS ? ((S.blob_bytes + 15u) & ~15u) : 0u, A.n_params, cfg.lds_cap, G);
@@ -212,22 +213,29 @@ static hipError_t launch_bwd_l(const SceneView<T>& S, const RaysView<T>& R, int6
   hipError_t e;
   if (P) {
     hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(64), 0, st, P->count, 2);
-    e = grid_for(k_backward_path<T, USE_LDS>, shmem, n, cfg, blocks);
+    e = grid_for(k_backward_path<T, USE_LDS, SH>, shmem, n, cfg, blocks);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_backward_path<T, USE_LDS>), dim3(blocks), dim3(kBlockAdj), shmem, st, S, R, n, A, G, *P);
+    hipLaunchKernelGGL((k_backward_path<T, USE_LDS, SH>), dim3(blocks), dim3(kBlockAdj), shmem, st, S, R, n, A, G, *P);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = grid_for(k_backward_path4<T, USE_LDS>, shmem, n, cfg, blocks);
+    e = grid_for(k_backward_path4<T, USE_LDS, SH>, shmem, n, cfg, blocks);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_backward_path4<T, USE_LDS>), dim3(blocks), dim3(kBlockAdj), shmem, st, S, R, A, G, *P);
+    hipLaunchKernelGGL((k_backward_path4<T, USE_LDS, SH>), dim3(blocks), dim3(kBlockAdj), shmem, st, S, R, A, G, *P);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  e = grid_for(k_backward<T, MAXE, USE_LDS>, shmem, n, cfg, blocks);
+  e = grid_for(k_backward<T, MAXE, USE_LDS, SH>, shmem, n, cfg, blocks);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_backward<T, MAXE, USE_LDS>), dim3(blocks), dim3(kBlockAdj), shmem, st, S, R, n, A, G,
+  hipLaunchKernelGGL((k_backward<T, MAXE, USE_LDS, SH>), dim3(blocks), dim3(kBlockAdj), shmem, st, S, R, n, A, G,
                      P ? P->list : nullptr, P ? P->count : nullptr);
   return hipGetLastError();
+}
+
+template <typename T, int MAXE, bool USE_LDS>
+static hipError_t launch_bwd_l(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const AdjView& A,
+                               const LaunchCfg& cfg, hipStream_t st, const PathView* P) {
+  if (S.shapes & ~kShapesNoCone) return launch_bwd_s<T, MAXE, USE_LDS, kShapesAll>(S, R, n, A, cfg, st, P);
+  return launch_bwd_s<T, MAXE, USE_LDS, kShapesNoCone>(S, R, n, A, cfg, st, P);
 }
 
 template <typename T, int MAXE>

@@ -61,13 +61,13 @@ template <typename T> __device__ __forceinline__ void apply_action(const DVol<T>
 
 // Exact root of the recorded (vol, face) from state (O, d); false if the
 // volume no longer yields that face (cannot happen for an unchanged scene).
-template <typename T>
+template <typename T, int SH = kShapesAll>
 __device__ __forceinline__ bool replay_root(const SceneView<T>& S, int vid, int face, V3<double> O, V3<double> dd,
                                             int pv, int pf, int ps, double& t, double& s) {
   Best<T> b;
   b.t = tinf<T>(); b.vol = -1; b.face = -1; b.s = T(0); b.tp = 0.0;
   V3<T> d = to_t<T>(dd);
-  test_volume(S.vol[vid], vid, O, to_t<T>(O), d, inv_dir(d), pv, pf, ps, S.eps_self, b);
+  test_volume<T, SH>(S.vol[vid], vid, O, to_t<T>(O), d, inv_dir(d), pv, pf, ps, S.eps_self, b);
   if (b.vol != vid || b.face != face) return false;
   t = b.tp; s = (double)b.s;
   return true;
@@ -89,14 +89,14 @@ template <typename C, typename P> __device__ __forceinline__ void bez2(const P* 
 // direction, or of the entering direction for the terminal event).  Out:
 // cotangents of the entering origin and direction; parameter partials go to
 // the sink.
-template <typename C, typename T>
+template <typename C, typename T, int SH = kShapesAll>
 __device__ __forceinline__ void event_adjoint(const DVol<T>& v, const DTilt* tilt, int face, int act,
                                               V3<double> O, V3<C> d, C t, C s, V3<C>& Xb, V3<C>& db,
                                               GradSink& gs) {
   const FrameC<C> F(v);
   V3<double> Xw = adv(O, t, d);
   V3<C> xl = F.local(Xw);
-  V3<C> Gl = local_grad<C, T>(v, face, xl, s);
+  V3<C> Gl = local_grad<C, T, SH>(v, face, xl, s);
   V3<C> m = F.qT(Gl);
   C mn = dsqrt(dot(m, m));
   V3<C> n = scl(C(1) / mn, m);
@@ -168,6 +168,7 @@ __device__ __forceinline__ void event_adjoint(const DVol<T>& v, const DTilt* til
     }
     case CYLINDER: xlb = {Gb.x, Gb.y, C(0)}; break;
     case HEXCONE: {
+      if constexpr (!((SH >> HEXCONE) & 1)) break;
       C rho, z, dr, dz, ddr, ddz;
       bez2(v.p, s, rho, z, dr, dz, ddr, ddz);
       C nx, ny;
@@ -270,7 +271,7 @@ __device__ __forceinline__ void event_adjoint(const DVol<T>& v, const DTilt* til
 // the sign of its final direction.  Returns false if a replayed intersection
 // no longer yields the recorded (volume, face), which an unchanged scene
 // cannot produce; the photon then adds nothing further.
-template <typename T>
+template <typename T, int SH = kShapesAll>
 __device__ __forceinline__ bool reverse_sweep(const SceneView<T>& L, const AdjView& A, GradSink& gs,
                                               const double* cf, V3<T> o0, V3<T> d0, const uint32_t* codes,
                                               int nev) {
@@ -285,23 +286,23 @@ __device__ __forceinline__ bool reverse_sweep(const SceneView<T>& L, const AdjVi
     for (int j = 0; j < e; ++j) {
       const int vid = (int)(codes[j] >> 8), face = (int)((codes[j] >> 4) & 15u), act = (int)(codes[j] & 15u);
       double t, s;
-      if (!replay_root(L, vid, face, O, d, pv, pf, ps, t, s)) return false;
+      if (!replay_root<T, SH>(L, vid, face, O, d, pv, pf, ps, t, s)) return false;
       const DVol<T>& v = L.vol[vid];
       V3<double> X = {O.x + t * d.x, O.y + t * d.y, O.z + t * d.z};
-      V3<double> nrm = front_normal(v, face, X, s);
+      V3<double> nrm = front_normal<T, SH>(v, face, X, s);
       int back;
       apply_action(v, nrm, act, d, back);
       O = X; pv = vid; pf = face; ps = back ^ (act == ACT_REFRACT ? 1 : 0);
     }
     const int vid = (int)(codes[e] >> 8), face = (int)((codes[e] >> 4) & 15u), act = (int)(codes[e] & 15u);
     double t, s;
-    if (!replay_root(L, vid, face, O, d, pv, pf, ps, t, s)) return false;
+    if (!replay_root<T, SH>(L, vid, face, O, d, pv, pf, ps, t, s)) return false;
     if (e == nev - 1) {
       const V3<double> X = {O.x + t * d.x, O.y + t * d.y, O.z + t * d.z};
       V3<double> dout = d;
       if (act == ACT_REFLECT || act == ACT_REFRACT) {
         int back;
-        apply_action(L.vol[vid], front_normal(L.vol[vid], face, X, s), act, dout, back);
+        apply_action(L.vol[vid], front_normal<T, SH>(L.vol[vid], face, X, s), act, dout, back);
       }
       Xb = {cf[0] * ((double)(T)X.x - cf[1]), cf[0] * ((double)(T)X.y - cf[2]), 0.0};
       db = {0.0, 0.0, (T)dout.z >= T(0) ? cf[3] : -cf[3]};
@@ -309,7 +310,7 @@ __device__ __forceinline__ bool reverse_sweep(const SceneView<T>& L, const AdjVi
     // the pull-back runs in FP64 from the replayed state: the per-photon
     // partials are summed with cancellation (centroid-subtracted
     // cotangents), which FP32 arithmetic would not resolve
-    event_adjoint<double, T>(L.vol[vid], A.tilt + vid, face, act, O, d, t, s, Xb, db, gs);
+    event_adjoint<double, T, SH>(L.vol[vid], A.tilt + vid, face, act, O, d, t, s, Xb, db, gs);
   }
   return true;
 }
@@ -318,7 +319,7 @@ __device__ __forceinline__ bool reverse_sweep(const SceneView<T>& L, const AdjVi
 // is run again with the same draws (so its fate and sequence equal the
 // forward ones) and the sequence is swept in reverse.  Photons that are not
 // FOCUSED add nothing.
-template <typename T, int MAXE>
+template <typename T, int MAXE, int SH = kShapesAll>
 __device__ __forceinline__ void adjoint_photon(const SceneView<T>& L, const RaysView<T>& R, int64_t i,
                                                const AdjView& A, GradSink& gs) {
   const int g = R.grp(i);
@@ -330,9 +331,9 @@ __device__ __forceinline__ void adjoint_photon(const SceneView<T>& L, const Rays
   const V3<T> o0 = {oa[0], oa[1], oa[2]};
   const V3<T> d0 = {da[0], da[1], da[2]};
   uint32_t codes[MAXE];
-  PhotonOut<T> r = trace_photon<T, MAXE>(L, o0, d0, R.id_base + (uint64_t)R.src(i), codes);
+  PhotonOut<T> r = trace_photon<T, MAXE, SH>(L, o0, d0, R.id_base + (uint64_t)R.src(i), codes);
   if (r.fate != FOCUSED || r.nev > MAXE) return;
-  (void)reverse_sweep<T>(L, A, gs, cf, o0, d0, codes, r.nev);
+  (void)reverse_sweep<T, SH>(L, A, gs, cf, o0, d0, codes, r.nev);
 }
 
 // State entering an event of a recorded path: origin, direction, and the
@@ -366,7 +367,7 @@ template <typename T> __device__ __forceinline__ DVol<double> promote(const DVol
 // PROMOTE: convert each event's volume record to double once (fewer
 // instructions) rather than field by field as read (fewer registers); which
 // is faster depends on the register pressure of the calling kernel.
-template <typename T, bool PROMOTE, int NS = kPathSlots>
+template <typename T, bool PROMOTE, int NS = kPathSlots, int SH = kShapesAll>
 __device__ __forceinline__ void adjoint_photon_path(const SceneView<T>& L, const RaysView<T>& R, int64_t i,
                                                     const AdjView& A, GradSink& gs, uint4 w) {
   static_assert(NS >= 1 && NS <= kPathSlots, "slots of a path record");
@@ -389,16 +390,16 @@ __device__ __forceinline__ void adjoint_photon_path(const SceneView<T>& L, const
       double t, s;
       // a replayed intersection that no longer yields the recorded face
       // (impossible for an unchanged scene): the photon adds nothing
-      if (!replay_root(L, vid, face, O, d, pv, pf, ps, t, s)) return;
+      if (!replay_root<T, SH>(L, vid, face, O, d, pv, pf, ps, t, s)) return;
       st[e] = PathState{O, d, t, s};
       const DVol<T>& v = L.vol[vid];
       const V3<double> X = {O.x + t * d.x, O.y + t * d.y, O.z + t * d.z};
       if (act == ACT_REFLECT || act == ACT_REFRACT) {
         int back;
-        apply_action(v, front_normal(v, face, X, s), act, d, back);
+        apply_action(v, front_normal<T, SH>(v, face, X, s), act, d, back);
         ps = back ^ (act == ACT_REFRACT ? 1 : 0);
       } else {
-        ps = dot(d, front_normal(v, face, X, s)) < 0.0 ? 0 : 1;
+        ps = dot(d, front_normal<T, SH>(v, face, X, s)) < 0.0 ? 0 : 1;
       }
       O = X; pv = vid; pf = face;
     }
@@ -413,9 +414,9 @@ __device__ __forceinline__ void adjoint_photon_path(const SceneView<T>& L, const
       const int vid = (int)(codes[e] >> 8), face = (int)((codes[e] >> 4) & 15u), act = (int)(codes[e] & 15u);
       if constexpr (PROMOTE) {
         const DVol<double> vd = promote(L.vol[vid]);
-        event_adjoint<double, double>(vd, A.tilt + vid, face, act, st[e].O, st[e].d, st[e].t, st[e].s, Xb, db, gs);
+        event_adjoint<double, double, SH>(vd, A.tilt + vid, face, act, st[e].O, st[e].d, st[e].t, st[e].s, Xb, db, gs);
       } else {
-        event_adjoint<double, T>(L.vol[vid], A.tilt + vid, face, act, st[e].O, st[e].d, st[e].t, st[e].s, Xb, db,
+        event_adjoint<double, T, SH>(L.vol[vid], A.tilt + vid, face, act, st[e].O, st[e].d, st[e].t, st[e].s, Xb, db,
                                  gs);
       }
     }

@@ -52,7 +52,8 @@ __device__ __forceinline__ bool searched_again(uint4 w) {
 // Per-variant state (view, tilt table, slices) is re-derived from the
 // variant table for every item rather than carried across items, which
 // keeps it out of the registers the adjoint itself needs.
-template <bool USE_LDS, int MAXE, int MODE>
+// SH: the shape set compiled in (the union over the variants).
+template <bool USE_LDS, int MAXE, int MODE, int SH>
 __global__ void __launch_bounds__(kBlockB) __attribute__((amdgpu_waves_per_eu(MAXE <= 16 ? 3 : 1, 8)))
 k_backward_batch(const BatchVariant<float>* vars, const BatchItem* items, int n_items, uint32_t* queue,
                  uint32_t blob_cap, uint32_t grad_bytes, RaysView<float> R, const double* coef, double* grad,
@@ -116,9 +117,9 @@ k_backward_batch(const BatchVariant<float>* vars, const BatchItem* items, int n_
       if (MODE == kReplay) {
         const uint4 w = reinterpret_cast<const uint4*>(path)[off + i];
         if (w.x < kPathLong && w.w == kPathEnd)
-          adjoint_photon_path<float, false, kPathSlots - 1>(USE_LDS ? L : S, Rv, i, A, gs, w);
+          adjoint_photon_path<float, false, kPathSlots - 1, SH>(USE_LDS ? L : S, Rv, i, A, gs, w);
       } else if (MODE == kSearchAll || searched_again(reinterpret_cast<const uint4*>(path)[off + i])) {
-        adjoint_photon<float, MAXE>(USE_LDS ? L : S, Rv, i, A, gs);
+        adjoint_photon<float, MAXE, SH>(USE_LDS ? L : S, Rv, i, A, gs);
       }
     }
     // a change of variant overwrites LDS: every wave must be done with it
@@ -132,37 +133,44 @@ uint32_t batch_grad_lds_bytes(int max_params) {
   return one <= kGradLdsMax ? std::min<uint32_t>(kGradLdsMax, 16u * one) : 0u;
 }
 
-template <bool USE_LDS, int MAXE, int MODE>
+template <bool USE_LDS, int MAXE, int MODE, int SH>
 static hipError_t backward_batch_k(const BatchView<float>& B, const RaysView<float>& R, const double* coef,
                                    double* grad, int ncu, hipStream_t st, const uint32_t* path) {
   const uint32_t gbytes = batch_grad_lds_bytes(B.max_params);
   const size_t shmem = (USE_LDS ? B.blob_cap_bwd : 0) + gbytes;
   int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_backward_batch<USE_LDS, MAXE, MODE>,
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_backward_batch<USE_LDS, MAXE, MODE, SH>,
                                                               kBlockB, shmem);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
   const int blocks = std::max(1, std::min(B.n_items, ncu * per_cu));
-  hipLaunchKernelGGL((k_backward_batch<USE_LDS, MAXE, MODE>), dim3(blocks), dim3(kBlockB), shmem, st, B.vars,
+  hipLaunchKernelGGL((k_backward_batch<USE_LDS, MAXE, MODE, SH>), dim3(blocks), dim3(kBlockB), shmem, st, B.vars,
                      B.items, B.n_items, B.queue, B.blob_cap_bwd, gbytes, R, coef, grad, path);
   return hipGetLastError();
 }
 
-template <int MAXE, int MODE>
+template <int MAXE, int MODE, int SH>
 static hipError_t backward_batch_e(const BatchView<float>& B, const RaysView<float>& R, const double* coef,
                                    double* grad, int ncu, hipStream_t st, const uint32_t* path) {
   hipError_t e = hipSuccess;
-  if (B.blob_cap_bwd > 0) e = backward_batch_k<true, MAXE, MODE>(B, R, coef, grad, ncu, st, path);
-  if (e == hipSuccess) e = backward_batch_k<false, MAXE, MODE>(B, R, coef, grad, ncu, st, path);
+  if (B.blob_cap_bwd > 0) e = backward_batch_k<true, MAXE, MODE, SH>(B, R, coef, grad, ncu, st, path);
+  if (e == hipSuccess) e = backward_batch_k<false, MAXE, MODE, SH>(B, R, coef, grad, ncu, st, path);
+  return e;
+}
+
+template <int MAXE, int SH>
+static hipError_t backward_batch_s(const BatchView<float>& B, const RaysView<float>& R, const double* coef,
+                                   double* grad, int ncu, hipStream_t st, const uint32_t* path) {
+  if (!path) return backward_batch_e<MAXE, kSearchAll, SH>(B, R, coef, grad, ncu, st, nullptr);
+  hipError_t e = backward_batch_e<16, kReplay, SH>(B, R, coef, grad, ncu, st, path);
+  if (e == hipSuccess) e = backward_batch_e<MAXE, kSearchLong, SH>(B, R, coef, grad, ncu, st, path);
   return e;
 }
 
 template <int MAXE>
 static hipError_t backward_batch_m(const BatchView<float>& B, const RaysView<float>& R, const double* coef,
                                    double* grad, int ncu, hipStream_t st, const uint32_t* path) {
-  if (!path) return backward_batch_e<MAXE, kSearchAll>(B, R, coef, grad, ncu, st, nullptr);
-  hipError_t e = backward_batch_e<16, kReplay>(B, R, coef, grad, ncu, st, path);
-  if (e == hipSuccess) e = backward_batch_e<MAXE, kSearchLong>(B, R, coef, grad, ncu, st, path);
-  return e;
+  if (B.shapes & ~kShapesNoCone) return backward_batch_s<MAXE, kShapesAll>(B, R, coef, grad, ncu, st, path);
+  return backward_batch_s<MAXE, kShapesNoCone>(B, R, coef, grad, ncu, st, path);
 }
 
 hipError_t launch_backward_batch(const BatchView<float>& B, const RaysView<float>& R, const double* coef,

@@ -619,12 +619,12 @@ __device__ __forceinline__ void narrow(const DVol<T>& v, int vid, V3<double> O, 
   }
 }
 
-template <typename T> __device__ __forceinline__ void test_volume(const DVol<T>& v, int vid, V3<double> O, V3<T> of,
+template <typename T, int SH = kShapesAll> __device__ __forceinline__ void test_volume(const DVol<T>& v, int vid, V3<double> O, V3<T> of,
                                                                   V3<T> d, V3<T> inv, int prev_vol, int prev_face,
                                                                   int prev_side, T eps, Best<T>& b) {
   T tin;
   if (!aabb(v, of, inv, b.t, tin)) return;
-  narrow(v, vid, O, d, tin, prev_vol, prev_face, prev_side, eps, b);
+  narrow<T, SH>(v, vid, O, d, tin, prev_vol, prev_face, prev_side, eps, b);
 }
 
 template <typename T> __device__ __forceinline__ V3<T> inv_dir(V3<T> d) {
@@ -905,14 +905,14 @@ template <typename T> __device__ __forceinline__ PhotonOut<T> photon_out(const P
 
 // Full non-sequential transport of one photon.  If `codes` is non-null the
 // event codes are written to it (at most MAXLOG).
-template <typename T, int MAXLOG>
+template <typename T, int MAXLOG, int SH = kShapesAll>
 __device__ __forceinline__ PhotonOut<T> trace_photon(const SceneView<T>& S, V3<T> o, V3<T> d, uint64_t id,
                                                      uint32_t* codes) {
   PhotonState p;
   photon_init(p, o, d, id);
   while (!p.fate) {
     int k = p.k;
-    uint32_t code = photon_step(S, p);
+    uint32_t code = photon_step<T, SH>(S, p);
     if (codes && code != 0xffffffffu && k < MAXLOG) codes[k] = code;
   }
   return photon_out<T>(p);
