@@ -353,10 +353,10 @@ def run_gct(args, torch, rb, scenes):
 def run_chromatic(args, torch, rb, scenes, name="aspheric_lens"):
     """Wavelength as the batch axis: a refracting lens (the aspheric singlet
     or the Fresnel lens) at 16 wavelengths (300-600 nm; the same surfaces,
-    the index of each wavelength), 4 fields x 2.5e6 photons each.  One step
-    = binning + forward + figures + adjoint of every wavelength's RMS,
-    batched (one forward and one adjoint launch) against per-wavelength
-    calls."""
+    the index of each wavelength), 4 fields x 2.5e6 photons each, with the
+    launch tuning the autotuner picks.  One step = binning (if kept) +
+    forward + figures + adjoint of every wavelength's RMS, batched (one
+    forward and one adjoint launch) against per-wavelength calls."""
     lams = np.linspace(300e-9, 600e-9, 16)
     variants = [scenes.ALL[name](lam=float(l)) for l in lams]
     devs = [rb.Scene(v) for v in variants]
@@ -368,6 +368,12 @@ def run_chromatic(args, torch, rb, scenes, name="aspheric_lens"):
     counts = [npf * v.n_groups for v in variants]
     n = int(sum(counts))
     offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    # launch tuning from the autotuner on the first wavelength's photons (the
+    # surfaces are the same at every wavelength), applied to every variant
+    # and so to both the batched and the plain path
+    tuning = devs[0].autotune({k: t[offs[0]:offs[1]] for k, t in rays.items()})
+    for d in devs:
+        d.set_tuning(**tuning)
     batch = rb.Batch(devs, counts, chunk=args.sweep_chunk)
     sums = batch.new_sums()
     fig = torch.zeros(batch.n_groups * rb.FIGURE_STRIDE, dtype=torch.float64, device="cuda")
@@ -407,14 +413,14 @@ def run_chromatic(args, torch, rb, scenes, name="aspheric_lens"):
     rms = fig.view(-1, rb.FIGURE_STRIDE)[:, 4].cpu().numpy()
     on_axis = [float(rms[go[v]]) for v in range(len(devs))]
     tb, tp = float(np.mean(t_b)), float(np.mean(t_p))
-    print(f"[bench] chromatic {name}: batched {tb:.2f} ms, plain {tp:.2f} ms ({n / (tb / 1e3):.3e} photons/s); "
+    print(f"[bench] chromatic {name} ({tuning}): batched {tb:.2f} ms, plain {tp:.2f} ms ({n / (tb / 1e3):.3e} photons/s); "
           f"on-axis RMS {min(on_axis) * 1e3:.2f}-{max(on_axis) * 1e3:.2f} mm", file=sys.stderr, flush=True)
     fields = ", ".join(f"{np.degrees(g):g}" for g in variants[0].groups)
     return {"workload": f"{name} at 16 wavelengths (300-600 nm, Cauchy index) x 4 fields ({fields} deg) x "
                         f"{npf:.1e} photons; one step = binning + forward + figures + adjoint "
                         f"({len(variants[0].params)} surface coefficients per wavelength)",
             "photons_per_step": n, "batched_ms_per_step": tb, "plain_ms_per_step": tp,
-            "batched_photons_per_s": n / (tb / 1e3), "speedup": tp / tb,
+            "batched_photons_per_s": n / (tb / 1e3), "speedup": tp / tb, "tuning": tuning,
             "wavelengths_nm": (lams * 1e9).tolist(), "on_axis_rms_m": on_axis}
 
 
