@@ -93,6 +93,18 @@ def fresnel(cos_i, n1, n2):
     return float(lib().oracle_fresnel(cos_i, n1, n2))
 
 
+def outline(volume, x, y):
+    """(inside, boundary distance) of the outline of one volume descriptor
+    at local points (x, y): the trace's bounds test and its diagnostic."""
+    vi, vd = pack_volumes(np.array([volume]))
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    inside = np.zeros(len(x), np.uint8)
+    bd = np.zeros(len(x))
+    lib().oracle_outline(_p(vi), _p(vd), ctypes.c_int64(len(x)), _p(x), _p(y), _p(inside), _p(bd))
+    return inside.astype(bool), bd
+
+
 def _rays64(rays):
     return [np.ascontiguousarray(rays[k], dtype=np.float64) for k in ("ox", "oy", "oz", "dx", "dy", "dz")]
 

@@ -879,6 +879,20 @@ int oracle_trace(int nv, const int32_t* vi, const double* vd, int max_events, ui
   return 0;
 }
 
+// Outline membership and boundary distance of volume 0 at local points
+// (x[i], y[i]): the bounds test and the diagnostic distance used by the
+// trace, exposed so that tests can pin them against closed forms.
+int oracle_outline(const int32_t* vi, const double* vd, int64_t n, const double* x, const double* y,
+                   uint8_t* inside, double* bdist) {
+  if (n < 0) return -1;
+  std::vector<Vol> vs = unpack(1, vi, vd);
+  for (int64_t i = 0; i < n; ++i) {
+    inside[i] = inside_outline(vs[0], x[i], y[i]) ? 1 : 0;
+    bdist[i] = outline_bdist(vs[0], x[i], y[i]);
+  }
+  return 0;
+}
+
 // Forced-sequence evaluation in double with parameters P (FD driver).
 int oracle_forced(int nv, const int32_t* vi, const double* vd, const double* P, int64_t n,
                   const double* ox, const double* oy, const double* oz, const double* dx,

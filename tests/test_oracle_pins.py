@@ -16,6 +16,9 @@ status:
                                     spread of its sphere's sag over the hit radii)
 * non-sequential search .......... pinned (brute force vs culled, symmetry, conservation)
 * forced sequences / duals ....... pinned (closed-form derivative of C1; FD vs duals)
+* segment outlines, boundary distances, grazing(), the mirror draw, tilted
+  geometry(P), gradient_eff_w, the self-hit rule: pinned in
+  test_oracle_pins_segments.py
 * full-scene figures (DC PSF, SC RMS, cone efficiency curves): parity unpinned
   (the paper prints no values and its figures are not reproducible here).
 """
