@@ -61,6 +61,16 @@ def lib():
     return _lib
 
 
+def default_threads():
+    """Host threads the oracle uses by default: the cores this process may
+    run on, at most 16 (a GPU machine's share of its host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def _p(a):
     return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
 
@@ -125,7 +135,7 @@ def trace(scene, rays, id_base=0, log=False, nthreads=None, culled=True, volumes
         lg = dict(vol=np.full((n, me), -1, np.int32), face=np.full((n, me), -1, np.int32),
                   act=np.full((n, me), -1, np.int32), t=np.zeros((n, me)), s=np.zeros((n, me)),
                   diag=np.full((n, me, 5), np.inf))
-    nth = nthreads or os.cpu_count() or 1
+    nth = nthreads or default_threads()
     rc = L.oracle_trace(ctypes.c_int(len(vols)), _p(vi), _p(vd), ctypes.c_int(me),
                         ctypes.c_uint64(scene.seed), ctypes.c_double(scene.l_ref),
                         ctypes.c_int64(n), *[_p(c) for c in cols], ctypes.c_uint64(id_base),
@@ -177,7 +187,7 @@ def forced(scene, rays, rec, params, nthreads=None):
     L.oracle_forced(ctypes.c_int(len(scene.volumes)), _p(vi), _p(vd), _p(P), ctypes.c_int64(n),
                     *[_p(c) for c in cols], ctypes.c_int(scene.max_events), _p(rec["n_events"]),
                     _p(lg["vol"]), _p(lg["face"]), _p(lg["act"]), _p(lg["t"]), _p(lg["s"]),
-                    _p(pos), _p(dirv), _p(st), ctypes.c_int(nthreads or os.cpu_count() or 1))
+                    _p(pos), _p(dirv), _p(st), ctypes.c_int(nthreads or default_threads()))
     return pos, dirv, st
 
 
@@ -196,7 +206,7 @@ def forced_jac(scene, rays, rec, params, p0, cnt, nthreads=None):
                              ctypes.c_int64(n), *[_p(c) for c in cols], ctypes.c_int(scene.max_events),
                              _p(rec["n_events"]), _p(lg["vol"]), _p(lg["face"]), _p(lg["act"]),
                              _p(lg["t"]), _p(lg["s"]), _p(dpos), _p(ddir), _p(st),
-                             ctypes.c_int(nthreads or os.cpu_count() or 1))
+                             ctypes.c_int(nthreads or default_threads()))
     if rc != 0:
         raise ValueError("oracle_forced_jac rejected its input")
     return dpos, ddir, st

@@ -699,6 +699,7 @@ void compile_blob(robast_scene& s, std::vector<char>& blob, SceneView<T>& V, std
   V.n_groups = s.n_groups;
   V.seed = s.seed;
   V.eps_self = q<T>(s.l_ref * (sizeof(T) == 4 ? 1e-5 : 1e-9));
+  V.eps_tie = 1e-12 * s.l_ref;
   V.blob_bytes = (uint32_t)blob.size();
 }
 

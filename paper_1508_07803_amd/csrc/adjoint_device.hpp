@@ -65,11 +65,11 @@ template <typename T, int SH = kShapesAll>
 __device__ __forceinline__ bool replay_root(const SceneView<T>& S, int vid, int face, V3<double> O, V3<double> dd,
                                             int pv, int pf, int ps, double& t, double& s) {
   Best<T> b;
-  b.t = tinf<T>(); b.vol = -1; b.face = -1; b.s = T(0); b.tp = 0.0;
+  b.t = tinf<T>(); b.vol = -1; b.face = -1; b.s = 0.0; b.tp = tinf<double>(); b.tie = S.eps_tie;
   V3<T> d = to_t<T>(dd);
-  test_volume<T, SH>(S.vol[vid], vid, O, to_t<T>(O), d, inv_dir(d), pv, pf, ps, S.eps_self, b);
+  test_volume<T, SH>(S.vol[vid], vid, O, dd, to_t<T>(O), d, inv_dir(d), pv, pf, ps, S.eps_self, b);
   if (b.vol != vid || b.face != face) return false;
-  t = b.tp; s = (double)b.s;
+  t = b.tp; s = b.s;
   return true;
 }
 

@@ -128,6 +128,18 @@ template <typename T> __device__ __forceinline__ V3<T> loc_pd(const DVol<T>& v, 
   return {v.Q[0] * rx + v.Q[1] * ry + v.Q[2] * rz, v.Q[3] * rx + v.Q[4] * ry + v.Q[5] * rz,
           v.Q[6] * rx + v.Q[7] * ry + v.Q[8] * rz};
 }
+// The same in double throughout (frame promoted from the record).
+template <typename T> __device__ __forceinline__ V3<double> loc_dd(const DVol<T>& v, V3<double> x) {
+  double rx = x.x - (double)v.c[0], ry = x.y - (double)v.c[1], rz = x.z - (double)v.c[2];
+  return {(double)v.Q[0] * rx + (double)v.Q[1] * ry + (double)v.Q[2] * rz,
+          (double)v.Q[3] * rx + (double)v.Q[4] * ry + (double)v.Q[5] * rz,
+          (double)v.Q[6] * rx + (double)v.Q[7] * ry + (double)v.Q[8] * rz};
+}
+template <typename T> __device__ __forceinline__ V3<double> loc_dir_d(const DVol<T>& v, V3<double> d) {
+  return {(double)v.Q[0] * d.x + (double)v.Q[1] * d.y + (double)v.Q[2] * d.z,
+          (double)v.Q[3] * d.x + (double)v.Q[4] * d.y + (double)v.Q[5] * d.z,
+          (double)v.Q[6] * d.x + (double)v.Q[7] * d.y + (double)v.Q[8] * d.z};
+}
 template <typename T> __device__ __forceinline__ V3<double> adv(V3<double> o, T t, V3<T> d) {
   return {o.x + (double)t * (double)d.x, o.y + (double)t * (double)d.y, o.z + (double)t * (double)d.z};
 }
@@ -202,18 +214,24 @@ __device__ __forceinline__ bool segment_may_meet_outline(const DVol<T>& v, T xa,
 }
 
 // ------------------------------------------------------------------ candidate bookkeeping
-// Nearest candidate so far: t (precision T) orders the candidates; tp is the
-// same parameter formed in double from the box-entry shift and the local
-// root, used for the hit point.
+// Nearest candidate so far: tp, the ray parameter formed in double from the
+// box-entry shift and the local root, orders the candidates and places the
+// hit point; t is its rounding to T, which the searches in precision T use
+// to skip farther candidates (it includes the tie margin).  Candidates
+// within `tie` of each other are tied and go to the lower volume, then the
+// lower face.
 template <typename T> struct Best {
-  T t, s;
-  double tp;
+  T t;
+  double s;   // cone wall parameter of the hit (its normal depends on it)
+  double tp, tie;
   int vol, face;
 };
 
-template <typename T> __device__ __forceinline__ void offer(Best<T>& b, T t, int vol, int face, T s, double tp) {
-  bool better = t < b.t || (t == b.t && (vol < b.vol || (vol == b.vol && face < b.face)));
-  if (better) { b.t = t; b.vol = vol; b.face = face; b.s = s; b.tp = tp; }
+template <typename T> __device__ __forceinline__ void offer(Best<T>& b, T t, int vol, int face, double s, double tp) {
+  const double dt = tp - b.tp;
+  bool better = dt < -b.tie || (!(dt > b.tie) && (vol < b.vol || (vol == b.vol && face < b.face)));
+  // the bound for skipping farther candidates keeps those still tied
+  if (better) { b.t = t + (T)b.tie; b.vol = vol; b.face = face; b.s = s; b.tp = tp; }
 }
 
 __device__ __forceinline__ void wall_dir(int k, float& nx, float& ny);
@@ -278,13 +296,13 @@ struct SelfRule {
   int face;   // face of this volume the photon just left, or -1
   int side;   // side of that face the photon is on
 };
-template <int SH, typename T>
-__device__ __forceinline__ bool self_ok(const DVol<T>& v, const SelfRule& sr, int face, T tt, T eps, V3<T> x, V3<T> d,
-                                        T s) {
-  if (face != sr.face) return tt > T(0);
+template <int SH, typename C, typename T>
+__device__ __forceinline__ bool self_ok(const DVol<T>& v, const SelfRule& sr, int face, C tt, C eps, V3<C> x, V3<C> d,
+                                        C s) {
+  if (face != sr.face) return tt > C(0);
   if (!(tt > eps)) return false;
-  T sd = dot(d, local_grad_of<SH, T>(v, face, x, s));
-  return (sd < T(0)) == (sr.side == 0);
+  C sd = dot(d, local_grad_of<SH, C>(v, face, x, s));
+  return (sd < C(0)) == (sr.side == 0);
 }
 
 // ------------------------------------------------------------------ narrow phase
@@ -417,19 +435,26 @@ template <typename T> __device__ __forceinline__ void nf_asphere(const DVol<T>& 
   if (inside_outline(v, x.x, x.y)) offer(b, tt, vid, 0, T(0), (double)t0 + (double)t);
 }
 
-template <typename T> __device__ __forceinline__ void nf_cylinder(const DVol<T>& v, int vid, V3<T> o, V3<T> d,
-                                                                  T t0, T eps, SelfRule sr, Best<T>& b) {
-  T A = d.x * d.x + d.y * d.y;
-  if (A == T(0)) return;
-  T B = T(2) * (o.x * d.x + o.y * d.y), C = o.x * o.x + o.y * o.y - v.p[0] * v.p[0];
-  T r[2]; int n;
-  quad2(A, B, C, r[0], r[1], n);
+// Cylinders (masts, trusses) are solved in double for every scene
+// precision: a ray running nearly along a long strut meets it at glancing
+// incidence, where the hit point along the axis carries the rounding of the
+// local coordinates (metres from the strut's base) divided by |d . n|.
+template <typename C, typename T> __device__ __forceinline__ void nf_cylinder(const DVol<T>& v, int vid, V3<C> o,
+                                                                              V3<C> d, C t0, C eps, SelfRule sr,
+                                                                              Best<T>& b) {
+  C A = d.x * d.x + d.y * d.y;
+  if (A == C(0)) return;
+  const C rho = (C)v.p[0];
+  C B = C(2) * (o.x * d.x + o.y * d.y), Cq = o.x * o.x + o.y * o.y - rho * rho;
+  C r[2]; int n;
+  quad2(A, B, Cq, r[0], r[1], n);
+  const C tbest = (C)(b.tp + b.tie);
   for (int i = 0; i < n; ++i) {
-    T tt = r[i] + t0;
-    if (tt > b.t) continue;
-    V3<T> x = fma3(r[i], d, o);
-    if (!self_ok<CYLINDER>(v, sr, 0, tt, eps, x, d, T(0))) continue;
-    if (x.z >= T(0) && x.z <= v.p[1]) offer(b, tt, vid, 0, T(0), (double)t0 + (double)r[i]);
+    C tt = r[i] + t0;
+    if (tt > tbest) continue;
+    V3<C> x = fma3(r[i], d, o);
+    if (!self_ok<CYLINDER>(v, sr, 0, tt, eps, x, d, C(0))) continue;
+    if (x.z >= C(0) && x.z <= (C)v.p[1]) offer(b, (T)tt, vid, 0, T(0), (double)tt);
   }
 }
 
@@ -504,78 +529,85 @@ template <typename T> __device__ __forceinline__ T cubic_root_piece(const T* w, 
   return s;
 }
 
-template <typename T> __device__ __forceinline__ void nf_hexcone(const DVol<T>& v, int vid, V3<T> o, V3<T> d,
-                                                                 T t0, T eps, SelfRule sr, Best<T>& b) {
+// The walls are solved in double for every scene precision: neighbouring
+// cones of an array share their entrance rims, where one cone's wall and the
+// next one's meet tangentially, so near a rim the two candidate roots differ
+// by the square of the depth below it -- below what single precision can
+// order at the cones' size.  Local coordinates come from the photon position
+// in double; the record's parameters are promoted as they are read.
+template <typename C, typename T> __device__ __forceinline__ void nf_hexcone(const DVol<T>& v, int vid, V3<C> o, V3<C> d,
+                                                                             C t0, C eps, SelfRule sr, Best<T>& b) {
   const T* p = v.p;
-  const T inv_sqrt3 = T(0.5773502691896258);
+  const C inv_sqrt3 = C(0.5773502691896258);
+  const C tbest = (C)(b.tp + b.tie);
   {
     // the walls lie inside the hexagonal prism |x . n_k| <= rho_max,
-    // z in [lo, hi]: skip the cone unless the ray crosses it before b.t
-    T rm = dmax(dmax(p[0], p[2]), dmax(p[4], p[6]));
-    T ta = -t0, tb = b.t - t0;
+    // z in [lo, hi]: skip the cone unless the ray crosses it before the best
+    C rm = (C)dmax(dmax(p[0], p[2]), dmax(p[4], p[6]));
+    C ta = -t0, tb = tbest - t0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      T nx, ny;
+      C nx, ny;
       wall_dir(k, nx, ny);
-      T u0 = o.x * nx + o.y * ny, du = d.x * nx + d.y * ny;
-      if (du != T(0)) {
-        T iu = frcp(du);
-        T t1 = (-rm - u0) * iu, t2 = (rm - u0) * iu;
+      C u0 = o.x * nx + o.y * ny, du = d.x * nx + d.y * ny;
+      if (du != C(0)) {
+        C iu = frcp(du);
+        C t1 = (-rm - u0) * iu, t2 = (rm - u0) * iu;
         ta = dmax(ta, dmin(t1, t2)); tb = dmin(tb, dmax(t1, t2));
       } else if (dabs(u0) > rm) {
         return;
       }
     }
-    if (d.z != T(0)) {
-      T iz = frcp(d.z);
-      T t1 = (v.lo[2] - o.z) * iz, t2 = (v.hi[2] - o.z) * iz;
+    if (d.z != C(0)) {
+      C iz = frcp(d.z);
+      C t1 = ((C)v.lo[2] - o.z) * iz, t2 = ((C)v.hi[2] - o.z) * iz;
       ta = dmax(ta, dmin(t1, t2)); tb = dmin(tb, dmax(t1, t2));
-    } else if (o.z < v.lo[2] || o.z > v.hi[2]) {
+    } else if (o.z < (C)v.lo[2] || o.z > (C)v.hi[2]) {
       return;
     }
     if (!(ta <= tb)) return;
   }
   for (int f = 0; f < 6; ++f) {
-    T nx, ny;
+    C nx, ny;
     wall_dir(f, nx, ny);
-    T u0 = o.x * nx + o.y * ny, du = d.x * nx + d.y * ny;
-    T w0 = (p[0] - u0) * d.z - (p[1] - o.z) * du;
-    T w1 = (p[2] - u0) * d.z - (p[3] - o.z) * du;
-    T w2 = (p[4] - u0) * d.z - (p[5] - o.z) * du;
-    T w3 = (p[6] - u0) * d.z - (p[7] - o.z) * du;
-    if (w0 == T(0) && w1 == T(0) && w2 == T(0) && w3 == T(0)) continue;
-    const T wv[4] = {w0, w1, w2, w3};
+    C u0 = o.x * nx + o.y * ny, du = d.x * nx + d.y * ny;
+    C w0 = ((C)p[0] - u0) * d.z - ((C)p[1] - o.z) * du;
+    C w1 = ((C)p[2] - u0) * d.z - ((C)p[3] - o.z) * du;
+    C w2 = ((C)p[4] - u0) * d.z - ((C)p[5] - o.z) * du;
+    C w3 = ((C)p[6] - u0) * d.z - ((C)p[7] - o.z) * du;
+    if (w0 == C(0) && w1 == C(0) && w2 == C(0) && w3 == C(0)) continue;
+    const C wv[4] = {w0, w1, w2, w3};
     // power-basis coefficients, used only to split [0, 1] at the critical points
-    T c[4] = {w0, T(3) * (w1 - w0), T(3) * (w0 - T(2) * w1 + w2), w3 - T(3) * w2 + T(3) * w1 - w0};
+    C c[4] = {w0, C(3) * (w1 - w0), C(3) * (w0 - C(2) * w1 + w2), w3 - C(3) * w2 + C(3) * w1 - w0};
     // monotone pieces split at the critical points in (0, 1)
-    T br[4]; int nb = 0;
-    br[nb++] = T(0);
-    T q0, q1; int nq;
-    quad2(T(3) * c[3], T(2) * c[2], c[1], q0, q1, nq);
-    if (nq == 2 && q0 > q1) { T tq = q0; q0 = q1; q1 = tq; }
-    if (nq >= 1 && q0 > T(0) && q0 < T(1)) br[nb++] = q0;
-    if (nq == 2 && q1 > T(0) && q1 < T(1)) br[nb++] = q1;
-    br[nb++] = T(1);
-    T fa = c[0];
+    C br[4]; int nb = 0;
+    br[nb++] = C(0);
+    C q0, q1; int nq;
+    quad2(C(3) * c[3], C(2) * c[2], c[1], q0, q1, nq);
+    if (nq == 2 && q0 > q1) { C tq = q0; q0 = q1; q1 = tq; }
+    if (nq >= 1 && q0 > C(0) && q0 < C(1)) br[nb++] = q0;
+    if (nq == 2 && q1 > C(0) && q1 < C(1)) br[nb++] = q1;
+    br[nb++] = C(1);
+    C fa = c[0];
     for (int i = 0; i + 1 < nb; ++i) {
-      T a = br[i], bb = br[i + 1];
-      T fb, fpb;
+      C a = br[i], bb = br[i + 1];
+      C fb, fpb;
       bern3(wv, bb, fb, fpb);
-      T s;
-      if (fa == T(0)) s = a;
-      else if (fb == T(0) && i + 2 == nb) s = bb;
-      else if ((fa > T(0)) != (fb > T(0))) s = cubic_root_piece(wv, a, bb, fa);
+      C s;
+      if (fa == C(0)) s = a;
+      else if (fb == C(0) && i + 2 == nb) s = bb;
+      else if ((fa > C(0)) != (fb > C(0))) s = cubic_root_piece(wv, a, bb, fa);
       else { fa = fb; continue; }
       fa = fb;
-      T rho, z, dr, dzs;
+      C rho, z, dr, dzs;
       bez_eval(p, s, rho, z, dr, dzs);
-      T t = dabs(d.z) >= dabs(du) ? fdiv(z - o.z, d.z) : fdiv(rho - u0, du);
-      T tt = t + t0;
-      if (tt > b.t) continue;
-      V3<T> xh = fma3(t, d, o);
+      C t = dabs(d.z) >= dabs(du) ? fdiv(z - o.z, d.z) : fdiv(rho - u0, du);
+      C tt = t + t0;
+      if (tt > tbest) continue;
+      V3<C> xh = fma3(t, d, o);
       if (!self_ok<HEXCONE>(v, sr, f, tt, eps, xh, d, s)) continue;
-      T vt = -xh.x * ny + xh.y * nx;
-      if (dabs(vt) <= rho * inv_sqrt3) offer(b, tt, vid, f, s, (double)t0 + (double)t);
+      C vt = -xh.x * ny + xh.y * nx;
+      if (dabs(vt) <= rho * inv_sqrt3) offer(b, (T)tt, vid, f, (double)s, (double)tt);
     }
   }
 }
@@ -596,7 +628,7 @@ template <typename T> __device__ __forceinline__ bool aabb(const DVol<T>& v, V3<
 // The photon position O is kept in double (world scale); of and inv are its
 // rounding and the inverse direction in T for the box tests.
 template <typename T, int SH = kShapesAll>
-__device__ __forceinline__ void narrow(const DVol<T>& v, int vid, V3<double> O, V3<T> d,
+__device__ __forceinline__ void narrow(const DVol<T>& v, int vid, V3<double> O, V3<double> D, V3<T> d,
                                                              T tin, int prev_vol, int prev_face, int prev_side,
                                                              T eps, Best<T>& b) {
   // advance to the box entry to keep the local quadratic well conditioned;
@@ -609,22 +641,33 @@ __device__ __forceinline__ void narrow(const DVol<T>& v, int vid, V3<double> O, 
     case PLANE: nf_plane(v, vid, ol, dl, t0, eps, sr, b); break;
     case SPHERE: nf_sphere(v, vid, ol, dl, t0, eps, sr, b); break;
     case ASPHERE: nf_asphere(v, vid, ol, dl, t0, eps, sr, b); break;
-    case CYLINDER: nf_cylinder(v, vid, ol, dl, t0, eps, sr, b); break;
+    case CYLINDER: {
+      const V3<double> Ot = {O.x + (double)t0 * D.x, O.y + (double)t0 * D.y, O.z + (double)t0 * D.z};
+      nf_cylinder<double>(v, vid, loc_dd(v, Ot), loc_dir_d(v, D), (double)t0, (double)eps, sr, b);
+      break;
+    }
     case BOX:
       if constexpr ((SH >> BOX) & 1) nf_box(v, vid, ol, dl, t0, eps, sr, b);
       break;
     case HEXCONE:
-      if constexpr ((SH >> HEXCONE) & 1) nf_hexcone(v, vid, ol, dl, t0, eps, sr, b);
+      if constexpr ((SH >> HEXCONE) & 1) {
+        // the photon's direction in double too: near a shared rim the two
+        // walls' order depends on where the ray passes to well below the
+        // rounding of the direction to T over a cone's length
+        const V3<double> Ot = {O.x + (double)t0 * D.x, O.y + (double)t0 * D.y, O.z + (double)t0 * D.z};
+        nf_hexcone<double>(v, vid, loc_dd(v, Ot), loc_dir_d(v, D), (double)t0, (double)eps, sr, b);
+      }
       break;
   }
 }
 
-template <typename T, int SH = kShapesAll> __device__ __forceinline__ void test_volume(const DVol<T>& v, int vid, V3<double> O, V3<T> of,
-                                                                  V3<T> d, V3<T> inv, int prev_vol, int prev_face,
-                                                                  int prev_side, T eps, Best<T>& b) {
+template <typename T, int SH = kShapesAll> __device__ __forceinline__ void test_volume(const DVol<T>& v, int vid, V3<double> O,
+                                                                  V3<double> D, V3<T> of, V3<T> d, V3<T> inv,
+                                                                  int prev_vol, int prev_face, int prev_side, T eps,
+                                                                  Best<T>& b) {
   T tin;
   if (!aabb(v, of, inv, b.t, tin)) return;
-  narrow<T, SH>(v, vid, O, d, tin, prev_vol, prev_face, prev_side, eps, b);
+  narrow<T, SH>(v, vid, O, D, d, tin, prev_vol, prev_face, prev_side, eps, b);
 }
 
 template <typename T> __device__ __forceinline__ V3<T> inv_dir(V3<T> d) {
@@ -653,7 +696,8 @@ template <typename T> struct Cands {
 };
 
 template <typename T, int SH = kShapesAll>
-__device__ __forceinline__ void run_cands(const SceneView<T>& S, Cands<T>& c, V3<double> O, V3<T> d, int prev_vol,
+__device__ __forceinline__ void run_cands(const SceneView<T>& S, Cands<T>& c, V3<double> O, V3<double> D, V3<T> d,
+                                          int prev_vol,
                                           int prev_face, int prev_side, Best<T>& b) {
 #pragma unroll 1
   for (int it = 0; it < c.n; ++it) {
@@ -666,17 +710,17 @@ __device__ __forceinline__ void run_cands(const SceneView<T>& S, Cands<T>& c, V3
     for (int j = 0; j < Cands<T>::K; ++j)
       if (j == sel) c.tin[j] = tinf<T>();
     if (vid < 0 || tin > b.t) break;
-    narrow<T, SH>(S.vol[vid], vid, O, d, tin, prev_vol, prev_face, prev_side, S.eps_self, b);
+    narrow<T, SH>(S.vol[vid], vid, O, D, d, tin, prev_vol, prev_face, prev_side, S.eps_self, b);
   }
   c.n = 0;
 }
 
 template <typename T, int SH = kShapesAll>
 __device__ __forceinline__ void gather(const SceneView<T>& S, Cands<T>& c, int vid, V3<T> o, V3<T> inv, V3<double> O,
-                                       V3<T> d, int prev_vol, int prev_face, int prev_side, Best<T>& b) {
+                                       V3<double> D, V3<T> d, int prev_vol, int prev_face, int prev_side, Best<T>& b) {
   T tin;
   if (!aabb(S.vol[vid], o, inv, b.t, tin)) return;
-  if (c.n == Cands<T>::K) run_cands<T, SH>(S, c, O, d, prev_vol, prev_face, prev_side, b);
+  if (c.n == Cands<T>::K) run_cands<T, SH>(S, c, O, D, d, prev_vol, prev_face, prev_side, b);
 #pragma unroll
   for (int j = 0; j < Cands<T>::K; ++j)
     if (j == c.n) { c.vid[j] = vid; c.tin[j] = tin; }
@@ -686,9 +730,10 @@ __device__ __forceinline__ void gather(const SceneView<T>& S, Cands<T>& c, int v
 // Non-sequential search: nearest face over the volume just left, the
 // always-list and the candidate groups crossed by the ray.
 template <typename T, int SH = kShapesAll>
-__device__ void find_nearest(const SceneView<T>& S, V3<double> O, V3<T> d, int prev_vol,
+__device__ void find_nearest(const SceneView<T>& S, V3<double> O, V3<double> D, int prev_vol,
                                                    int prev_face, int prev_side, Best<T>& b) {
-  b.t = tinf<T>(); b.vol = -1; b.face = -1; b.s = T(0); b.tp = 0.0;
+  b.t = tinf<T>(); b.vol = -1; b.face = -1; b.s = 0.0; b.tp = tinf<double>(); b.tie = S.eps_tie;
+  const V3<T> d = to_t<T>(D);
   Mailbox mb{prev_vol, -1, -1, -1};
   V3<T> inv = inv_dir(d);
   const V3<T> o = to_t<T>(O);
@@ -696,10 +741,10 @@ __device__ void find_nearest(const SceneView<T>& S, V3<double> O, V3<T> d, int p
   c.n = 0;
   // the volume just left first: photons bouncing inside a cone or between
   // facets usually meet it (or its neighbour) next
-  if (prev_vol >= 0) gather<T, SH>(S, c, prev_vol, o, inv, O, d, prev_vol, prev_face, prev_side, b);
+  if (prev_vol >= 0) gather<T, SH>(S, c, prev_vol, o, inv, O, D, d, prev_vol, prev_face, prev_side, b);
   for (int i = 0; i < S.n_always; ++i) {
     int vid = S.always[i];
-    if (vid != prev_vol) gather<T, SH>(S, c, vid, o, inv, O, d, prev_vol, prev_face, prev_side, b);
+    if (vid != prev_vol) gather<T, SH>(S, c, vid, o, inv, O, D, d, prev_vol, prev_face, prev_side, b);
   }
   // candidate groups: walk each group's grid over the stretch of the ray that
   // lies inside the group's z-slab (in the group frame)
@@ -753,7 +798,7 @@ __device__ void find_nearest(const SceneView<T>& S, V3<double> O, V3<T> d, int p
         int vid = S.items[k];
         if (!mb.seen(vid)) {
           mb.put(vid);
-          gather<T, SH>(S, c, vid, o, inv, O, d, prev_vol, prev_face, prev_side, b);
+          gather<T, SH>(S, c, vid, o, inv, O, D, d, prev_vol, prev_face, prev_side, b);
         }
       }
       T tn = dmin(tmx, tmy);
@@ -762,7 +807,7 @@ __device__ void find_nearest(const SceneView<T>& S, V3<double> O, V3<T> d, int p
       else { iy += sy; tmy += tdy; if (iy < 0 || iy >= G.ny) break; }
     }
   }
-  run_cands<T, SH>(S, c, O, d, prev_vol, prev_face, prev_side, b);
+  run_cands<T, SH>(S, c, O, D, d, prev_vol, prev_face, prev_side, b);
 }
 
 // Front normal (world, double) of the face hit at world point X (double):
@@ -874,12 +919,12 @@ template <typename T, int SH = kShapesAll>
 __device__ __forceinline__ uint32_t photon_step(const SceneView<T>& S, PhotonState& p) {
   if (p.k == S.max_events) { p.fate = SUSPENDED; return 0xffffffffu; }
   Best<T> b;
-  find_nearest<T, SH>(S, p.o, to_t<T>(p.d), p.prev_v, p.prev_f, p.prev_side, b);
+  find_nearest<T, SH>(S, p.o, p.d, p.prev_v, p.prev_f, p.prev_side, b);
   if (b.vol < 0) { p.fate = EXITED; return 0xffffffffu; }
   const DVol<T>& v = S.vol[b.vol];
   V3<double> X = {p.o.x + b.tp * p.d.x, p.o.y + b.tp * p.d.y, p.o.z + b.tp * p.d.z};
   p.opl += p.ncur * b.tp;
-  V3<double> n = front_normal<T, SH>(v, b.face, X, (double)b.s);
+  V3<double> n = front_normal<T, SH>(v, b.face, X, b.s);
   int back, fate = 0;
   int act = interact<double>(v, n, p.d, p.ncur, fate, back, S.seed, p.id, p.k, b.tp);
   p.hash = (p.hash ^ (((uint64_t)b.vol << 4) | ((uint64_t)b.face << 1) | (uint64_t)back)) * 0x100000001b3ull;

@@ -76,6 +76,7 @@ template <typename T> struct SceneView {
   int32_t max_events, n_groups;
   uint64_t seed;
   T eps_self;                      // self-intersection guard for the face just left
+  double eps_tie;                  // candidates this close are tied (lower volume, then face, wins)
   uint32_t blob_bytes;             // size of the blob (for LDS staging)
   const char* blob;                // start of the blob (== vol)
 };

@@ -62,8 +62,7 @@ def test_arrival_figures(rb, name, precision, n_per):
     ref = oracle.trace(sc, r)
     both = (rec["fate"] == scenes.FATE_FOCUSED) & (ref["fate"] == scenes.FATE_FOCUSED)
     differ = int((rec["fate"] != ref["fate"]).sum())
-    rate = 5e-4 if name == "hex_concentrator" and precision == 32 else 1e-5
-    assert differ <= max(3, rate * len(rec["fate"])), differ
+    assert differ <= max(3, 1e-5 * len(rec["fate"])), differ
     # each event's distance may differ by the parity bar on positions
     # (1e-5 L_ref in FP32, 1e-11 L_ref in FP64)
     per_event = (1e-5 if precision == 32 else 1e-11) * sc.l_ref

@@ -236,7 +236,7 @@ def test_batch_photons_match_oracle(rb):
     off = 0
     for v, (sc, c) in enumerate(zip(variants, counts)):
         rec = oracle.trace(sc, host[v], log=True)
-        nbad, dp, dd = compare(sc, host[v], as_numpy(hits, slice(off, off + c)), rec, 1e-5 * sc.l_ref, 1e-5)
+        nbad, dp, dd, _ = compare(sc, host[v], as_numpy(hits, slice(off, off + c)), rec, 1e-5 * sc.l_ref, 1e-5)
         print(f"{sc.name}: N={c} mismatches={nbad} max|dpos|={dp:.3e} max|ddir|={dd:.3e}")
         off += c
 

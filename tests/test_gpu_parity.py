@@ -91,37 +91,35 @@ def grazing(sc, r, idx, ref_hash, id_base=0):
     return g
 
 
-def compare(sc, r, got, ref, pos_tol, dir_tol, max_rate=1e-5, id_base=0, require_focused=True):
+def compare(sc, r, got, ref, pos_tol, dir_tol, max_rate=1e-5, id_base=0, require_focused=True, floor=3):
+    """Photon-by-photon comparison; returns (mismatches, max |dpos|, max |ddir|,
+    photons with a glancing event).  At most max(floor, max_rate N)
+    mismatches, all grazing (floor 3 is the 1.4 % Poisson tail of a 1e-5
+    rate over 5e4 photons; the million-photon tests use floor 0).  Every
+    other photon that did not fail is held to the tolerances at its exit
+    point and direction, whatever its fate."""
     n = len(r["ox"])
     same = ((got["fate"] == ref["fate"]) & (got["n_events"] == ref["n_events"]) &
             (got["last_vol"] == ref["last_vol"]) & (got["seq_hash"] == ref["seq_hash"]))
     bad = np.nonzero(~same)[0]
-    assert len(bad) <= max(3, max_rate * n), f"{len(bad)} mismatches of {n}"
+    assert len(bad) <= max(floor, max_rate * n), f"{len(bad)} mismatches of {n}"
     if len(bad):
         import oracle
         g = oracle.grazing(ref, sc.l_ref)[bad] if "log" in ref else np.zeros(len(bad), bool)
         if not g.all():
             g[~g] = grazing(sc, r, bad[~g], ref["seq_hash"][bad[~g]], id_base)
         assert g.all(), f"non-grazing mismatches at {bad[~g][:10]}"
-    foc = same & (ref["fate"] == scenes.FATE_FOCUSED)
-    assert foc.sum() > 0 or not require_focused
-    # A reflection at incidence |d.n| multiplies the effect of a hit-point
-    # error on the exit direction by ~1/|d.n|: paths with a glancing
-    # interaction (|d.n| < 0.05) are held to 100x the tolerance.
-    glance = np.zeros(n, bool)
-    if "log" in ref:
-        cosn = ref["log"]["diag"][:, :, 3]
-        glance = (cosn < 0.05).any(axis=1)
-    ok = foc & ~glance
+    ok = same & (ref["fate"] != scenes.FATE_FAILED)
+    assert (same & (ref["fate"] == scenes.FATE_FOCUSED)).sum() > 0 or not require_focused
     dp = np.abs(got["pos"][ok] - ref["pos"][ok]).max() if ok.any() else 0.0
     dd = np.abs(got["dir"][ok] - ref["dir"][ok]).max() if ok.any() else 0.0
     assert dp <= pos_tol, f"max |dpos| {dp}"
     assert dd <= dir_tol, f"max |ddir| {dd}"
-    gl = foc & glance
-    if gl.any():
-        assert np.abs(got["pos"][gl] - ref["pos"][gl]).max() <= 100 * pos_tol
-        assert np.abs(got["dir"][gl] - ref["dir"][gl]).max() <= 100 * dir_tol
-    return len(bad), dp, dd
+    # photons with a glancing interaction (|d.n| < 0.05), where a hit-point
+    # error is magnified ~1/|d.n| in the exit direction: counted, held to the
+    # same tolerance
+    n_glance = int((ref["log"]["diag"][:, :, 3] < 0.05).any(axis=1).sum()) if "log" in ref else -1
+    return len(bad), dp, dd, n_glance
 
 
 def test_single_mirror_fp64_full(rb):
@@ -130,34 +128,23 @@ def test_single_mirror_fp64_full(rb):
     r = sc.rays(100000)
     got = gpu_trace(rb, sc, r)
     ref = oracle.trace(sc, r)
-    nbad, dp, dd = compare(sc, r, got, ref, 1e-11 * sc.l_ref, 1e-11)
+    nbad, dp, dd, _ = compare(sc, r, got, ref, 1e-11 * sc.l_ref, 1e-11)
     assert nbad == 0
     assert np.array_equal(got["fate"], ref["fate"])
     assert np.abs(got["opl"] - ref["opl"]).max() < 1e-10 * sc.l_ref
 
 
-# The cone array has zero-thickness walls meeting at tangent rims: just below
-# a shared rim the front of one cone's wall and the back of its neighbour's are
-# a quadratically thin wedge apart, and FP32 cannot order two candidates
-# closer than ~1e-5 mm (ulp at 65 mm).  Those photons are grazing by the
-# near-tie criterion (candidates within 1e-5 L_ref); in FP32 they occur at a
-# rate of about 2.5e-4, so the FP32 cone bound is 5e-4 (all grazing), and the
-# FP64 cone test below holds the 1e-5 bar.
-@pytest.mark.parametrize("name,n_per,rate", [("davies_cotton", 20000, 1e-5),
-                                             ("schwarzschild_couder", 3000, 1e-5),
-                                             ("hex_concentrator", 600, 5e-4),
-                                             ("lst_parabolic", 20000, 1e-5),
-                                             ("gct_sc", 5000, 1e-5),
-                                             ("aspheric_lens", 20000, 1e-5),
-                                             ("fresnel_lens", 20000, 1e-5)])
-def test_fp32_scene_parity(rb, name, n_per, rate):
+@pytest.mark.parametrize("name,n_per", [("davies_cotton", 20000), ("schwarzschild_couder", 3000),
+                                        ("hex_concentrator", 600), ("lst_parabolic", 20000), ("gct_sc", 5000),
+                                        ("aspheric_lens", 20000), ("fresnel_lens", 20000)])
+def test_fp32_scene_parity(rb, name, n_per):
     import oracle
     sc = scenes.ALL[name]()
     r = sc.rays(n_per)
     got = gpu_trace(rb, sc, r)
     ref = oracle.trace(sc, r, log=True)
-    nbad, dp, dd = compare(sc, r, got, ref, 1e-5 * sc.l_ref, 1e-5, max_rate=rate)
-    print(f"{name}: N={len(r['ox'])} mismatches={nbad} max|dpos|={dp:.3e} max|ddir|={dd:.3e}")
+    nbad, dp, dd, ng = compare(sc, r, got, ref, 1e-5 * sc.l_ref, 1e-5)
+    print(f"{name}: N={len(r['ox'])} mismatches={nbad} max|dpos|={dp:.3e} max|ddir|={dd:.3e} glancing={ng}")
 
 
 def test_fp64_concentrator_parity(rb):
@@ -166,7 +153,7 @@ def test_fp64_concentrator_parity(rb):
     r = sc.rays(600)
     got = gpu_trace(rb, sc, r)
     ref = oracle.trace(sc, r, log=True)
-    nbad, dp, dd = compare(sc, r, got, ref, 1e-9 * sc.l_ref, 1e-9)
+    nbad, dp, dd, _ = compare(sc, r, got, ref, 1e-9 * sc.l_ref, 1e-9)
     print(f"hex_concentrator fp64: N={len(r['ox'])} mismatches={nbad} max|dpos|={dp:.3e}")
 
 
@@ -177,7 +164,7 @@ def test_fp64_small_sc_parity(rb):
     r = sc.rays(1000)
     got = gpu_trace(rb, sc, r)
     ref = oracle.trace(sc, r, log=True)
-    nbad, dp, dd = compare(sc, r, got, ref, 1e-9 * sc.l_ref, 1e-9)
+    nbad, dp, dd, _ = compare(sc, r, got, ref, 1e-9 * sc.l_ref, 1e-9)
     st = sc.meta["structure"]
     shadow = (ref["fate"] == scenes.FATE_ABSORBED) & np.isin(ref["last_vol"], st)
     assert shadow.sum() > 0.05 * len(r["ox"])
@@ -195,9 +182,10 @@ def test_fp64_lens_parity(rb, name, lam):
     r = sc.rays(3000)
     got = gpu_trace(rb, sc, r)
     ref = oracle.trace(sc, r, log=True)
-    nbad, dp, dd = compare(sc, r, got, ref, 1e-9 * sc.l_ref, 1e-9)
-    # optical paths under the bar of the positions: glancing paths (|d.n| < 0.05
-    # at an event) carry 100x the tolerance, as in compare()
+    nbad, dp, dd, _ = compare(sc, r, got, ref, 1e-9 * sc.l_ref, 1e-9)
+    # optical paths under the bar of the positions; a path with a glancing
+    # event (|d.n| < 0.05) sums segments whose lengths are ill-conditioned in
+    # the hit points and is held to 1e-7 L_ref
     same = (got["fate"] == ref["fate"]) & (got["seq_hash"] == ref["seq_hash"])
     foc = same & (ref["fate"] == scenes.FATE_FOCUSED)
     glance = (ref["log"]["diag"][:, :, 3] < 0.05).any(axis=1)
@@ -225,7 +213,7 @@ def test_absorbing_glass_parity(rb, name, precision, L):
     got = gpu_trace(rb, sc, r)
     ref = oracle.trace(sc, r, log=True)
     tol = 1e-5 if precision == 32 else 1e-9
-    nbad, dp, dd = compare(sc, r, got, ref, tol * sc.l_ref, tol, require_focused=name != "window_slab")
+    nbad, dp, dd, _ = compare(sc, r, got, ref, tol * sc.l_ref, tol, require_focused=name != "window_slab")
     absorbed = (ref["fate"] == scenes.FATE_ABSORBED) & (got["fate"] == ref["fate"])
     assert absorbed.mean() > 0.02
     print(f"{name} fp{precision} L={L}: N={len(r['ox'])} mismatches={nbad} absorbed={absorbed.mean():.3f} "
