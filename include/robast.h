@@ -198,6 +198,23 @@ int robast_build_scene(const robast_scene_desc* desc, const double* params, int6
 int robast_trace(robast_scene* scene, const robast_rays* rays, int64_t n, const robast_hits* hits,
                  uint32_t flags, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the trace
+ * of robast_trace with flags 0, whose photon binning (when the scene's
+ * tuning bins photons and 32768 <= n <= 2^32 - 1) runs in a fixed 64 MiB
+ * workspace in device memory that the library holds per GPU until the
+ * process ends, instead of the scene's own growable one.  Calls no hipMalloc
+ * or hipFree (the workspace's device address is looked up once per GPU, on
+ * the first call there).  Results equal those of robast_trace.  Binning
+ * needs 72 bytes per photon in FP32 (136 in FP64) plus per-bin counts:
+ * EINVAL, before any launch, when that exceeds the workspace (about 9e5
+ * FP32 photons) -- binning off (robast_set_tuning) lifts the limit.  Keeps
+ * no binned order and no path records, and drops those of earlier calls on
+ * the scene.  Every call on one GPU shares the workspace: calls that overlap
+ * in time on one GPU (two streams) race.  Other errors as robast_trace. */
+int robast_trace_static(robast_scene* scene, const robast_rays* rays, int64_t n, const robast_hits* hits,
+                        void* hip_stream);
+
 /* Figures from accumulated group sums (device -> device, n_groups * 8 doubles). */
 int robast_figures(robast_scene* scene, const double* d_group_sums, double* d_figures,
                    void* hip_stream);

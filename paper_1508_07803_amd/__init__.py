@@ -30,7 +30,7 @@ SYMBOLS = ["robast_build_scene", "robast_trace", "robast_figures", "robast_trace
            "robast_last_error", "robast_abi_version", "robast_build_batch", "robast_trace_batch",
            "robast_figures_batch", "robast_trace_backward_batch", "robast_batch_sizes", "robast_destroy_batch",
            "robast_get_tuning", "robast_set_tuning", "robast_autotune", "robast_bin_photons",
-           "robast_arrival_figures"]
+           "robast_arrival_figures", "robast_trace_static"]
 
 
 class VolumeDesc(ctypes.Structure):
@@ -75,6 +75,8 @@ _lib.robast_build_scene.argtypes = [ctypes.POINTER(SceneDesc), ctypes.c_void_p, 
                                     ctypes.POINTER(ctypes.c_void_p)]
 _lib.robast_trace.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ctypes.c_int64, ctypes.POINTER(Hits),
                               ctypes.c_uint32, ctypes.c_void_p]
+_lib.robast_trace_static.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ctypes.c_int64, ctypes.POINTER(Hits),
+                                     ctypes.c_void_p]
 _lib.robast_figures.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
 _lib.robast_trace_backward.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ctypes.c_int64, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
@@ -104,7 +106,8 @@ _lib.robast_destroy_batch.restype = None
 for _name in ("robast_build_scene", "robast_trace", "robast_figures", "robast_trace_backward",
               "robast_update_params", "robast_abi_version", "robast_build_batch", "robast_trace_batch",
               "robast_figures_batch", "robast_trace_backward_batch", "robast_batch_sizes", "robast_get_tuning",
-              "robast_set_tuning", "robast_autotune", "robast_bin_photons", "robast_arrival_figures"):
+              "robast_set_tuning", "robast_autotune", "robast_bin_photons", "robast_arrival_figures",
+              "robast_trace_static"):
     getattr(_lib, _name).restype = ctypes.c_int
 
 
@@ -285,6 +288,18 @@ class Scene:
         flags = TRACE_KEEP_ORDER if keep_order else 0
         _check(_lib.robast_trace(self._h, ctypes.byref(R), n, ctypes.byref(H), flags, _stream(stream)),
                "robast_trace")
+        return hits
+
+    def trace_static(self, rays, n=None, hits=None, sums=None, id_base=0, stream=None):
+        """robast_trace_static: the trace of `trace`, binning in the library's
+        fixed per-GPU workspace (no device allocation)."""
+        n = int(rays["ox"].numel()) if n is None else int(n)
+        hits = hits or {}
+        _check_extents(n, self.dtype, rays, hits, [("sums", sums, self.n_groups * GROUP_STRIDE)])
+        H = _hits_struct(hits, sums)
+        R = self._rays_struct(rays, id_base)
+        _check(_lib.robast_trace_static(self._h, ctypes.byref(R), n, ctypes.byref(H), _stream(stream)),
+               "robast_trace_static")
         return hits
 
     def bin_photons(self, rays, n=None, id_base=0, stream=None):

@@ -11,6 +11,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -22,7 +23,20 @@
 
 using namespace robast;
 
+// Binning workspace of robast_trace_static, for callers that cannot
+// allocate: a fixed array in device memory.  Each GPU the library runs on
+// holds its own copy, at its own address, until the process ends; calls on
+// one GPU share it.  Host code must not pass `scratch` itself to a kernel
+// (the name is a host-side stand-in): it uses the device address found by
+// hipGetSymbolAddress on each device.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+void* g_scratch_dev[kMaxDevices] = {};
+std::mutex g_scratch_mu;
 
 thread_local std::string g_err;
 
@@ -33,6 +47,24 @@ int fail(int code, const std::string& msg) {
 int hip_fail(hipError_t e, const char* what) {
   g_err = std::string(what) + ": " + hipGetErrorString(e);
   return ROBAST_EHIP;
+}
+
+// Device address of the static workspace on the current device, looked up
+// once per device (with that device current) on the first call there.
+int static_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(ROBAST_EUNSUPPORTED, "device index beyond the static workspace table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return ROBAST_OK;
 }
 
 bool finite_all(const double* a, int n) {
@@ -846,14 +878,16 @@ bool same_rays(const robast_rays& a, const robast_rays& b) {
 
 // The kept binned order is used by any call given the same arrays and n;
 // afterwards it stays kept only if `keep` (a backward call passes false).
+// With `ext` (a workspace of ext_bytes the caller supplies) the binning uses
+// it instead of the scene's own, keeps nothing and allocates nothing.
 template <typename T>
 int binned_view(robast_scene* s, const robast_rays* rays, int64_t n, hipStream_t st, RaysView<T>& out,
-                bool keep, bool* reused = nullptr) {
+                bool keep, bool* reused = nullptr, void* ext = nullptr, size_t ext_bytes = 0) {
   const RaysView<T> R = rays_view<T>(rays);
   out = R;
   if (reused) *reused = false;
   if (!s->tuning.bin_photons || n < kBinMin || n > (int64_t)UINT32_MAX) return ROBAST_OK;
-  if (s->kept && s->kept_n == n && same_rays(s->kept_rays, *rays)) {
+  if (!ext && s->kept && s->kept_n == n && same_rays(s->kept_rays, *rays)) {
     s->kept = keep;
     if (reused) *reused = true;
     out = binned_rays<T>((const BinRecord<T>*)s->kept_records, rays->group != nullptr, rays->id_base);
@@ -867,6 +901,19 @@ int binned_view(robast_scene* s, const robast_rays* rays, int64_t n, hipStream_t
   nc = std::max(1, std::min({nc, 1024, nc_max}));
   const int64_t bins = (int64_t)G * nc * nc;
   const BinPlan plan = bin_plan<T>(n, bins);
+  if (ext) {
+    if (plan.bytes > ext_bytes)
+      return fail(ROBAST_EINVAL, "binning " + std::to_string(n) + " photons needs " + std::to_string(plan.bytes) +
+                                     " bytes of workspace, more than the " + std::to_string(ext_bytes) +
+                                     " bytes of the static workspace (about " +
+                                     std::to_string(ext_bytes / (2 * sizeof(BinRecord<T>) + 8)) + " photons)");
+    const BinWork<T> W = bin_carve<T>(plan, ext);
+    const BinGeom geo{s->bin_z, s->bin_x0, s->bin_y0, (double)nc / s->bin_side, nc, G, 0u, 0u};
+    hipError_t e = launch_binning<T>(R, n, geo, BinMulti{nullptr, nullptr, 0}, plan, W, st);
+    if (e != hipSuccess) return hip_fail(e, "binning launch");
+    out = binned_rays<T>(W.out, rays->group != nullptr, rays->id_base);
+    return ROBAST_OK;
+  }
   if (plan.bytes > s->work_bytes) {
     if (s->d_work) (void)hipFree(s->d_work);
     s->d_work = nullptr;
@@ -937,6 +984,21 @@ int trace_t(robast_scene* s, const SceneView<T>& V, const robast_rays* rays, int
     s->path_rays = *rays;
     s->path_n = n;
   }
+  return ROBAST_OK;
+}
+
+// The trace of robast_trace_static: binning (if the tuning asks for it) in
+// the static workspace, no path records, nothing kept.
+template <typename T>
+int trace_static_t(robast_scene* s, const SceneView<T>& V, const robast_rays* rays, int64_t n,
+                   const robast_hits* hits, void* work, hipStream_t st) {
+  s->path_ok = false;
+  s->kept = false;
+  RaysView<T> R;
+  int rc = binned_view<T>(s, rays, n, st, R, false, nullptr, work, kStaticScratchBytes);
+  if (rc) return rc;
+  hipError_t e = launch_trace<T>(V, R, n, hits_view<T>(hits), s->cfg, st);
+  if (e != hipSuccess) return hip_fail(e, "trace launch");
   return ROBAST_OK;
 }
 
@@ -1076,6 +1138,22 @@ int robast_trace(robast_scene* s, const robast_rays* rays, int64_t n, const roba
   const bool keep = (flags & ROBAST_TRACE_KEEP_ORDER) != 0;
   if (s->precision == 32) return trace_t<float>(s, s->sf, rays, n, hits, keep, st);
   return trace_t<double>(s, s->sd, rays, n, hits, keep, st);
+}
+
+int robast_trace_static(robast_scene* s, const robast_rays* rays, int64_t n, const robast_hits* hits,
+                        void* stream) {
+  if (!s || !rays || !hits) return fail(ROBAST_EINVAL, "NULL scene, rays or hits");
+  if (n < 0) return fail(ROBAST_EINVAL, "n < 0");
+  if (n == 0) return ROBAST_OK;
+  int rc = check_rays(rays);
+  if (!rc) rc = check_hits(hits);
+  if (rc) return rc;
+  void* work = nullptr;
+  rc = static_scratch(&work);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  if (s->precision == 32) return trace_static_t<float>(s, s->sf, rays, n, hits, work, st);
+  return trace_static_t<double>(s, s->sd, rays, n, hits, work, st);
 }
 
 int robast_figures(robast_scene* s, const double* sums, double* fig, void* stream) {
