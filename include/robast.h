@@ -148,6 +148,10 @@ typedef struct {
                         0xcbf29ce484222325, h = (h ^ (vol<<4 | face<<1 | back)) *
                         0x100000001b3 per interaction */
   double* group_sums;
+  uint32_t* seq_log; /* [device] n * max_events event codes (vol << 8 | face << 4 |
+                        action; action 0 reflect, 1 refract, 2 stop), photon i's
+                        at [i * max_events, i * max_events + n_events[i]), the
+                        rest untouched; robast_trace only (a debug log) */
 } robast_hits;
 
 /* Figures per group (§3: spot diagrams, collection efficiency), 8 doubles:
@@ -234,17 +238,38 @@ int robast_figures(robast_scene* scene, const double* d_group_sums, double* d_fi
 int robast_arrival_figures(robast_scene* scene, const robast_rays* rays, const robast_hits* hits, int64_t n,
                            double* d_out, void* hip_stream);
 
-/* Reverse mode along each photon's fixed surface sequence (pathwise
- * gradient; fates and sequences are re-derived with the same draws, so they
- * equal the forward ones, or read from the path record of the preceding
+/* robast_trace_backward flag: debug check that the backward pass follows
+ * the forward surface sequences.  Every photon is traced again by the
+ * search (no path record replay) and its sequence hash compared with
+ * fwd->seq_hash; the call then synchronises the stream and returns
+ * ROBAST_EMISMATCH (gradient still accumulated) if any photon differs. */
+#define ROBAST_BACKWARD_CHECK_SEQ 1u
+
+/* Reverse mode along each photon's fixed surface sequence: the pathwise
+ * gradient of the paper's focal-plane figures (§3: spot size of the
+ * segmented telescopes, collection of the concentrators) with respect to
+ * the scene parameters, each photon's fate and (volume, face) sequence held
+ * fixed.  Sequences are re-derived with the same draws (so they equal the
+ * forward ones) or read from the path record of the preceding
  * ROBAST_TRACE_KEEP_ORDER trace; the gradient is the same either way up to
- * FP64 summation order).  The objective is
- *   L = sum_g ( w_rms[g] * RMS_g + w_eff[g] * effw_g )
- * with d_cot [device] n_groups * 2 doubles {w_rms, w_eff} per group and
- * d_group_sums [device] the forward sums of the same photons.
- * d_grad [device] n_params doubles, ACCUMULATED (+=). */
-int robast_trace_backward(robast_scene* scene, const robast_rays* rays, int64_t n,
-                          const double* d_group_sums, const double* d_cot, double* d_grad,
+ * FP64 summation order.  The objective is
+ *   L = sum_g ( w_rms[g] RMS_g + w_eff[g] effw_g )
+ *       + sum_{FOCUSED p} c_p . (x_p, y_p, z_p, ux_p, uy_p, uz_p)
+ * with (x, y, z) a photon's focal-surface hit and u its exit direction.
+ *   fwd          [device pointers] the forward records of the same photons:
+ *                group_sums (needed with d_group_cot) and seq_hash (needed
+ *                with ROBAST_BACKWARD_CHECK_SEQ); other fields unused; may
+ *                be NULL when neither is needed
+ *   d_group_cot  [device] n_groups * 2 doubles {w_rms, w_eff}, or NULL
+ *   d_photon_cot [device] n * 6 doubles, c_p of photon p (caller's order),
+ *                or NULL; photons that are not FOCUSED contribute nothing
+ *   d_grad       [device] n_params doubles, ACCUMULATED (+=)
+ *   flags        0 or ROBAST_BACKWARD_CHECK_SEQ
+ * EINVAL on NULL scene / rays / grad, n < 0, an unknown flag, a group
+ * cotangent without fwd->group_sums, the check without fwd->seq_hash;
+ * EUNSUPPORTED when max_events > 64; EMISMATCH as described above. */
+int robast_trace_backward(robast_scene* scene, const robast_rays* rays, int64_t n, const robast_hits* fwd,
+                          const double* d_group_cot, const double* d_photon_cot, double* d_grad, uint32_t flags,
                           void* hip_stream);
 
 /* Bin photons [0, n) now and keep the order, as a trace call with

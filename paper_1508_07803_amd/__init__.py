@@ -24,6 +24,7 @@ OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, EMISMATCH = 0, -1, -2, -3, -4, -5
 GROUP_STRIDE = 8
 FIGURE_STRIDE = 8
 TRACE_KEEP_ORDER = 1
+BACKWARD_CHECK_SEQ = 1
 
 SYMBOLS = ["robast_build_scene", "robast_trace", "robast_figures", "robast_trace_backward",
            "robast_update_params", "robast_destroy_scene", "robast_status_string",
@@ -58,7 +59,8 @@ class Hits(ctypes.Structure):
     _fields_ = [("fate", ctypes.c_void_p), ("n_events", ctypes.c_void_p), ("last_vol", ctypes.c_void_p),
                 ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
                 ("ux", ctypes.c_void_p), ("uy", ctypes.c_void_p), ("uz", ctypes.c_void_p),
-                ("opl", ctypes.c_void_p), ("seq_hash", ctypes.c_void_p), ("group_sums", ctypes.c_void_p)]
+                ("opl", ctypes.c_void_p), ("seq_hash", ctypes.c_void_p), ("group_sums", ctypes.c_void_p),
+                ("seq_log", ctypes.c_void_p)]
 
 
 class Tuning(ctypes.Structure):
@@ -78,8 +80,9 @@ _lib.robast_trace.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ctypes.c_in
 _lib.robast_trace_static.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ctypes.c_int64, ctypes.POINTER(Hits),
                                      ctypes.c_void_p]
 _lib.robast_figures.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
-_lib.robast_trace_backward.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ctypes.c_int64, ctypes.c_void_p,
-                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+_lib.robast_trace_backward.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ctypes.c_int64, ctypes.POINTER(Hits),
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                       ctypes.c_void_p]
 _lib.robast_update_params.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
 _lib.robast_destroy_scene.argtypes = [ctypes.c_void_p]
 _lib.robast_destroy_scene.restype = None
@@ -203,8 +206,9 @@ def _check_extents(n, dtype, rays=None, hits=None, f64=()):
 
 def _hits_struct(hits, sums):
     hits = hits or {}
+    log = hits.get("seq_log")
     return Hits(*[(hits[k].data_ptr() if hits.get(k) is not None else None) for k in _HIT_KEYS],
-                sums.data_ptr() if sums is not None else None)
+                sums.data_ptr() if sums is not None else None, log.data_ptr() if log is not None else None)
 
 
 class Scene:
@@ -333,14 +337,24 @@ class Scene:
                "robast_arrival_figures")
         return out.view(self.n_groups, 4)
 
-    def backward(self, rays, sums, cot, grad, n=None, id_base=0, stream=None):
-        """Accumulate dL/dparams into grad for L = sum_g cot[g,0] RMS_g + cot[g,1] effw_g."""
+    def backward(self, rays, sums, cot, grad, n=None, id_base=0, stream=None, photon_cot=None, fwd_hash=None,
+                 check=False):
+        """Accumulate dL/dparams into grad for L = sum_g cot[g,0] RMS_g + cot[g,1] effw_g
+        (sums: the forward group sums; cot may be None) plus, per FOCUSED
+        photon, photon_cot[p] . (x, y, z, ux, uy, uz) of its exit state
+        (an (n, 6) float64 tensor, or None).  check: compare every photon's
+        re-derived surface sequence with fwd_hash (the forward seq_hash);
+        raises RobastError(EMISMATCH) if any differs."""
         n = int(rays["ox"].numel()) if n is None else int(n)
-        _check_extents(n, self.dtype, rays, f64=[("sums", sums, self.n_groups * GROUP_STRIDE),
-                                                 ("cot", cot, self.n_groups * 2), ("grad", grad, self.n_params)])
+        f64 = [("grad", grad, self.n_params), ("photon_cot", photon_cot, 6 * n)]
+        if cot is not None:
+            f64 += [("sums", sums, self.n_groups * GROUP_STRIDE), ("cot", cot, self.n_groups * 2)]
+        _check_extents(n, self.dtype, rays, {"seq_hash": fwd_hash} if fwd_hash is not None else None, f64)
         R = self._rays_struct(rays, id_base)
-        _check(_lib.robast_trace_backward(self._h, ctypes.byref(R), n, _ptr(sums), _ptr(cot), _ptr(grad),
-                                          _stream(stream)), "robast_trace_backward")
+        H = _hits_struct({"seq_hash": fwd_hash} if fwd_hash is not None else None, sums)
+        flags = BACKWARD_CHECK_SEQ if check else 0
+        _check(_lib.robast_trace_backward(self._h, ctypes.byref(R), n, ctypes.byref(H), _ptr(cot), _ptr(photon_cot),
+                                          _ptr(grad), flags, _stream(stream)), "robast_trace_backward")
         return grad
 
     @property
@@ -470,13 +484,15 @@ def _autograd():
 
         @staticmethod
         def forward(ctx, params, scene, rays):
-            p = params.detach().cpu().numpy()
+            p = params.detach().to("cpu", torch.float64).numpy()
             if not np.array_equal(p, scene.params):
                 scene.update_params(p)
             sums = scene.new_sums(rays["ox"].device)
             scene.trace(rays, sums=sums, keep_order=True)
             fig = scene.figures(sums)
             ctx.scene, ctx.rays = scene, rays
+            ctx.params = p.copy()
+            ctx.pdev, ctx.pdtype = params.device, params.dtype
             ctx.save_for_backward(sums)
             return fig
 
@@ -484,10 +500,14 @@ def _autograd():
         def backward(ctx, gfig):
             (sums,) = ctx.saved_tensors
             scene = ctx.scene
+            # the scene may have moved on (another forward call since): the
+            # gradient is taken at this forward call's parameters
+            if not np.array_equal(ctx.params, scene.params):
+                scene.update_params(ctx.params)
             cot = torch.stack([gfig[:, 4], gfig[:, 6]], 1).contiguous().to(torch.float64)
             grad = torch.zeros(scene.n_params, dtype=torch.float64, device=sums.device)
             scene.backward(ctx.rays, sums, cot, grad)
-            return grad.to("cpu"), None, None
+            return grad.to(device=ctx.pdev, dtype=ctx.pdtype), None, None
 
     return RobastTrace
 

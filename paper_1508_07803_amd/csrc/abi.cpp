@@ -200,6 +200,7 @@ struct robast_scene {
   double* d_coef = nullptr;    // n_groups * 4 backward coefficients
   int cell_choice = 0;         // index into kCellFactors chosen by the last upload
   void* d_view = nullptr;      // device copy of sf / sd, read by batched launches
+  void* d_check = nullptr;     // sequence-check counter of the backward debug mode
   SceneView<float> sf{};
   SceneView<double> sd{};
   LaunchCfg cfg{};
@@ -825,8 +826,10 @@ template <typename T> RaysView<T> rays_view(const robast_rays* r) {
 }
 
 template <typename T> HitsView<T> hits_view(const robast_hits* h) {
-  return HitsView<T>{h->fate, h->n_events, h->last_vol, (T*)h->x, (T*)h->y, (T*)h->z, (T*)h->ux, (T*)h->uy,
-                     (T*)h->uz, (T*)h->opl, h->seq_hash, h->group_sums};
+  HitsView<T> H{h->fate, h->n_events, h->last_vol, (T*)h->x, (T*)h->y, (T*)h->z, (T*)h->ux, (T*)h->uy,
+                (T*)h->uz, (T*)h->opl, h->seq_hash, h->group_sums};
+  H.seq_log = h->seq_log;
+  return H;
 }
 
 int check_rays(const robast_rays* rays) {
@@ -1122,6 +1125,7 @@ void robast_destroy_scene(robast_scene* s) {
   if (s->d_view) (void)hipFree(s->d_view);
   if (s->d_work) (void)hipFree(s->d_work);
   if (s->d_path) (void)hipFree(s->d_path);
+  if (s->d_check) (void)hipFree(s->d_check);
   delete s;
 }
 
@@ -1177,20 +1181,50 @@ int robast_arrival_figures(robast_scene* s, const robast_rays* rays, const robas
   return ROBAST_OK;
 }
 
-int robast_trace_backward(robast_scene* s, const robast_rays* rays, int64_t n, const double* sums,
-                          const double* cot, double* grad, void* stream) {
-  if (!s || !rays || !sums || !cot || !grad) return fail(ROBAST_EINVAL, "NULL scene, rays, sums, cot or grad");
+int robast_trace_backward(robast_scene* s, const robast_rays* rays, int64_t n, const robast_hits* fwd,
+                          const double* group_cot, const double* photon_cot, double* grad, uint32_t flags,
+                          void* stream) {
+  if (!s || !rays || !grad) return fail(ROBAST_EINVAL, "NULL scene, rays or grad");
+  if (flags & ~(uint32_t)ROBAST_BACKWARD_CHECK_SEQ) return fail(ROBAST_EINVAL, "unknown backward flag");
+  const bool check = (flags & ROBAST_BACKWARD_CHECK_SEQ) != 0;
+  if (group_cot && (!fwd || !fwd->group_sums))
+    return fail(ROBAST_EINVAL, "a group cotangent needs the forward group sums (fwd->group_sums)");
+  if (check && (!fwd || !fwd->seq_hash))
+    return fail(ROBAST_EINVAL, "the sequence check needs the forward hashes (fwd->seq_hash)");
   if (n < 0) return fail(ROBAST_EINVAL, "n < 0");
   if (n == 0) return ROBAST_OK;
   int rc = check_rays(rays);
   if (rc) return rc;
   if (s->max_events > 64) return fail(ROBAST_EUNSUPPORTED, "backward supports max_events <= 64");
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = launch_adj_coef(sums, cot, s->d_coef, s->n_groups, st);
-  if (e != hipSuccess) return hip_fail(e, "coefficient launch");
-  AdjView A{s->d_coef, grad, s->d_tilt, (int)s->params.size()};
-  if (s->precision == 32) return backward_t<float>(s, s->sf, rays, n, A, st);
-  return backward_t<double>(s, s->sd, rays, n, A, st);
+  AdjView A{nullptr, grad, s->d_tilt, (int)s->params.size()};
+  if (group_cot) {
+    hipError_t e = launch_adj_coef(fwd->group_sums, group_cot, s->d_coef, s->n_groups, st);
+    if (e != hipSuccess) return hip_fail(e, "coefficient launch");
+    A.coef = s->d_coef;
+  }
+  A.pcot = photon_cot;
+  if (check) {
+    // debug mode: every photon is searched again (no path record replay) and
+    // its sequence hash compared with the forward one; synchronous
+    if (!s->d_check) {
+      hipError_t e = hipMalloc(&s->d_check, 256);
+      if (e != hipSuccess) return hip_fail(e, "hipMalloc check counter");
+    }
+    hipError_t e = hipMemsetAsync(s->d_check, 0, sizeof(uint32_t), st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync check counter");
+    A.check_hash = fwd->seq_hash;
+    A.mismatch = (uint32_t*)s->d_check;
+    s->path_ok = false;
+  }
+  rc = s->precision == 32 ? backward_t<float>(s, s->sf, rays, n, A, st) : backward_t<double>(s, s->sd, rays, n, A, st);
+  if (rc || !check) return rc;
+  uint32_t bad = 0;
+  hipError_t e = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = hipMemcpy(&bad, s->d_check, sizeof(bad), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "sequence check readback");
+  if (bad) return fail(ROBAST_EMISMATCH, std::to_string(bad) + " photons' surface sequences differ from the forward pass");
+  return ROBAST_OK;
 }
 
 int robast_bin_photons(robast_scene* s, const robast_rays* rays, int64_t n, void* stream) {
@@ -1387,6 +1421,7 @@ int robast_trace_batch(robast_batch* b, const robast_rays* rays, const robast_hi
                        void* stream) {
   if (!b || !rays || !hits) return fail(ROBAST_EINVAL, "NULL batch, rays or hits");
   if (flags & ~(uint32_t)ROBAST_TRACE_KEEP_ORDER) return fail(ROBAST_EINVAL, "unknown trace flag");
+  if (hits->seq_log) return fail(ROBAST_EINVAL, "seq_log is written by robast_trace only");
   if (b->n_photons == 0) return ROBAST_OK;
   int rc = check_rays(rays);
   if (!rc) rc = check_hits(hits);

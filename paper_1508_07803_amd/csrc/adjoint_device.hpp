@@ -7,6 +7,35 @@
 
 namespace robast {
 
+// Group coefficients of a photon outside every group (or of a call without
+// a figure objective): no figure term.
+static __device__ const double kNoCoef[4] = {0.0, 0.0, 0.0, 0.0};
+
+// The cotangent coefficients of photon i's group, and its own cotangent of
+// the exit state (or null).
+template <typename T>
+__device__ __forceinline__ void photon_cots(const SceneView<T>& L, const RaysView<T>& R, int64_t i, const AdjView& A,
+                                            const double*& cf, const double*& pc) {
+  const int g = R.grp(i);
+  cf = (A.coef && (unsigned)g < (unsigned)L.n_groups) ? A.coef + 4 * g : kNoCoef;
+  pc = A.pcot ? A.pcot + 6 * R.src(i) : nullptr;
+}
+
+// Cotangents of a FOCUSED photon's exit state (position X rounded to T like
+// its record, direction d): the figure terms of its group -- RMS about the
+// group centroid, a (x - xbar, y - ybar, 0); weighted collection, b sign(u_z)
+// on u_z -- plus its own cotangent.
+template <typename T>
+__device__ __forceinline__ void seed_cots(const double* cf, const double* pc, V3<double> X, V3<double> d,
+                                          V3<double>& Xb, V3<double>& db) {
+  Xb = {cf[0] * ((double)(T)X.x - cf[1]), cf[0] * ((double)(T)X.y - cf[2]), 0.0};
+  db = {0.0, 0.0, (T)d.z >= T(0) ? cf[3] : -cf[3]};
+  if (pc) {
+    Xb.x += pc[0]; Xb.y += pc[1]; Xb.z += pc[2];
+    db.x += pc[3]; db.y += pc[4]; db.z += pc[5];
+  }
+}
+
 struct GradSink {
   double* acc;   // LDS or global
   __device__ __forceinline__ void add(int i, double v) {
@@ -273,8 +302,8 @@ __device__ __forceinline__ void event_adjoint(const DVol<T>& v, const DTilt* til
 // cannot produce; the photon then adds nothing further.
 template <typename T, int SH = kShapesAll>
 __device__ __forceinline__ bool reverse_sweep(const SceneView<T>& L, const AdjView& A, GradSink& gs,
-                                              const double* cf, V3<T> o0, V3<T> d0, const uint32_t* codes,
-                                              int nev) {
+                                              const double* cf, const double* pc, V3<T> o0, V3<T> d0,
+                                              const uint32_t* codes, int nev) {
   const V3<double> O0 = {(double)o0.x, (double)o0.y, (double)o0.z};
   const V3<double> D0 = {(double)d0.x, (double)d0.y, (double)d0.z};
   V3<double> Xb = {0.0, 0.0, 0.0}, db = {0.0, 0.0, 0.0};
@@ -304,8 +333,7 @@ __device__ __forceinline__ bool reverse_sweep(const SceneView<T>& L, const AdjVi
         int back;
         apply_action(L.vol[vid], front_normal<T, SH>(L.vol[vid], face, X, s), act, dout, back);
       }
-      Xb = {cf[0] * ((double)(T)X.x - cf[1]), cf[0] * ((double)(T)X.y - cf[2]), 0.0};
-      db = {0.0, 0.0, (T)dout.z >= T(0) ? cf[3] : -cf[3]};
+      seed_cots<T>(cf, pc, X, dout, Xb, db);
     }
     // the pull-back runs in FP64 from the replayed state: the per-photon
     // partials are summed with cancellation (centroid-subtracted
@@ -318,22 +346,24 @@ __device__ __forceinline__ bool reverse_sweep(const SceneView<T>& L, const AdjVi
 // Adjoint of one photon whose sequence is not recorded: its forward search
 // is run again with the same draws (so its fate and sequence equal the
 // forward ones) and the sequence is swept in reverse.  Photons that are not
-// FOCUSED add nothing.
+// FOCUSED add nothing.  With A.check_hash every photon's sequence hash is
+// compared with the forward one (a count of differences in A.mismatch).
 template <typename T, int MAXE, int SH = kShapesAll>
 __device__ __forceinline__ void adjoint_photon(const SceneView<T>& L, const RaysView<T>& R, int64_t i,
                                                const AdjView& A, GradSink& gs) {
-  const int g = R.grp(i);
-  if ((unsigned)g >= (unsigned)L.n_groups) return;
-  const double* cf = A.coef + 4 * g;
-  if ((T)cf[0] == T(0) && (T)cf[3] == T(0)) return;
+  const double *cf, *pc;
+  photon_cots(L, R, i, A, cf, pc);
+  const bool want = cf[0] != 0.0 || cf[3] != 0.0 || pc;
+  if (!want && !A.check_hash) return;
   T oa[3], da[3];
   R.load(i, oa, da);
   const V3<T> o0 = {oa[0], oa[1], oa[2]};
   const V3<T> d0 = {da[0], da[1], da[2]};
   uint32_t codes[MAXE];
   PhotonOut<T> r = trace_photon<T, MAXE, SH>(L, o0, d0, R.id_base + (uint64_t)R.src(i), codes);
-  if (r.fate != FOCUSED || r.nev > MAXE) return;
-  (void)reverse_sweep<T, SH>(L, A, gs, cf, o0, d0, codes, r.nev);
+  if (A.check_hash && A.check_hash[R.src(i)] != r.hash) atomicAdd(A.mismatch, 1u);
+  if (!want || r.fate != FOCUSED || r.nev > MAXE) return;
+  (void)reverse_sweep<T, SH>(L, A, gs, cf, pc, o0, d0, codes, r.nev);
 }
 
 // State entering an event of a recorded path: origin, direction, and the
@@ -371,10 +401,9 @@ template <typename T, bool PROMOTE, int NS = kPathSlots, int SH = kShapesAll>
 __device__ __forceinline__ void adjoint_photon_path(const SceneView<T>& L, const RaysView<T>& R, int64_t i,
                                                     const AdjView& A, GradSink& gs, uint4 w) {
   static_assert(NS >= 1 && NS <= kPathSlots, "slots of a path record");
-  const int g = R.grp(i);
-  if ((unsigned)g >= (unsigned)L.n_groups) return;
-  const double* cf = A.coef + 4 * g;
-  if ((T)cf[0] == T(0) && (T)cf[3] == T(0)) return;
+  const double *cf, *pc;
+  photon_cots(L, R, i, A, cf, pc);
+  if (cf[0] == 0.0 && cf[3] == 0.0 && !pc) return;
   T oa[3], da[3];
   R.load(i, oa, da);
   const uint32_t codes[kPathSlots] = {w.x, w.y, w.z, w.w};
@@ -404,10 +433,8 @@ __device__ __forceinline__ void adjoint_photon_path(const SceneView<T>& L, const
       O = X; pv = vid; pf = face;
     }
   }
-  // cotangents of the final position (rounded to T like the photon's record)
-  // and of the sign of the final direction
-  V3<double> Xb = {cf[0] * ((double)(T)O.x - cf[1]), cf[0] * ((double)(T)O.y - cf[2]), 0.0};
-  V3<double> db = {0.0, 0.0, (T)d.z >= T(0) ? cf[3] : -cf[3]};
+  V3<double> Xb, db;
+  seed_cots<T>(cf, pc, O, d, Xb, db);
 #pragma unroll
   for (int e = NS - 1; e >= 0; --e) {
     if (e < nev) {

@@ -82,6 +82,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
     while (!ps.fate) {
       const int k = ps.k;
       const uint32_t code = photon_step<T, SH>(L, ps);
+      if (RECORD && H.seq_log && code != 0xffffffffu) H.seq_log[R.src(cur) * S.max_events + k] = code;
       if (H.path) {
         rec.x = k == 0 ? code : rec.x;
         rec.y = k == 1 ? code : rec.y;
@@ -277,7 +278,7 @@ static hipError_t launch_one(const SceneView<T>& S, const RaysView<T>& R, int64_
 template <typename T>
 hipError_t launch_trace(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const HitsView<T>& H,
                         const LaunchCfg& cfg, hipStream_t st) {
-  bool rec = H.fate || H.nev || H.last_vol || H.x || H.ux || H.opl || H.hash;
+  bool rec = H.fate || H.nev || H.last_vol || H.x || H.ux || H.opl || H.hash || H.seq_log;
   bool sums = H.sums != nullptr;
   if (rec && sums) return launch_one<T, true, true>(S, R, n, H, cfg, st);
   if (rec) return launch_one<T, true, false>(S, R, n, H, cfg, st);

@@ -47,7 +47,8 @@ template <typename T> struct HitsView {
   T *x, *y, *z, *ux, *uy, *uz, *opl;
   uint64_t* hash;
   double* sums;
-  uint32_t* path;   // kPathSlots words per photon, or null
+  uint32_t* path = nullptr;      // kPathSlots words per photon, or null
+  uint32_t* seq_log = nullptr;   // max_events event codes per photon (caller's order), or null
 };
 
 struct LaunchCfg {
@@ -57,12 +58,16 @@ struct LaunchCfg {
 };
 
 // Backward-pass inputs: per-group cotangent coefficients of the objective
-// (a_g, xbar_g, ybar_g, b_g) and the output gradient.
+// (a_g, xbar_g, ybar_g, b_g), per-photon cotangents of the exit state, and
+// the output gradient; optionally the forward sequence hashes to check.
 struct AdjView {
-  const double* coef;     // n_groups * 4
+  const double* coef;     // n_groups * 4, or null (no figure term)
   double* grad;           // n_params, accumulated
   const DTilt* tilt;      // n_vol (valid where tparam >= 0)
   int n_params;
+  const double* pcot = nullptr;          // 6 per photon (caller's order): dL/d(exit x, y, z, ux, uy, uz), or null
+  const uint64_t* check_hash = nullptr;  // forward sequence hash per photon (caller's order), or null
+  uint32_t* mismatch = nullptr;          // photons whose sequence hash differs from check_hash
 };
 
 // Path records of the forward trace for the adjoint, and two lists filled

@@ -107,10 +107,33 @@ def test_null_arguments_rejected(rb):
     h = ctypes.c_void_p()
     assert lib.robast_build_scene(None, None, 0, ctypes.byref(h)) == rb.EINVAL
     assert lib.robast_trace(None, None, 10, None, 0, None) == rb.EINVAL
-    assert lib.robast_trace_backward(None, None, 10, None, None, None, None) == rb.EINVAL
+    assert lib.robast_trace_backward(None, None, 10, None, None, None, None, 0, None) == rb.EINVAL
     assert lib.robast_figures(None, None, None, None) == rb.EINVAL
     assert b"NULL" in lib.robast_last_error()
     assert lib.robast_status_string(rb.EINVAL) == b"invalid argument"
+
+
+def test_backward_arguments_rejected(rb):
+    """robast_trace_backward rejects an unknown flag, a group cotangent
+    without the forward sums and the sequence check without the forward
+    hashes, before it reads the scene (a stand-in handle is never touched)."""
+    import ctypes
+    lib = rb.lib()
+    fake = ctypes.create_string_buffer(64)
+    scene = ctypes.cast(fake, ctypes.c_void_p)
+    rays = rb.Rays()
+    grad = ctypes.cast(ctypes.create_string_buffer(64), ctypes.c_void_p)
+    cot = ctypes.cast(ctypes.create_string_buffer(64), ctypes.c_void_p)
+    no_sums = rb.Hits()
+    assert lib.robast_trace_backward(scene, ctypes.byref(rays), 10, None, None, None, grad, 2, None) == rb.EINVAL
+    assert b"flag" in lib.robast_last_error()
+    assert lib.robast_trace_backward(scene, ctypes.byref(rays), 10, None, cot, None, grad, 0, None) == rb.EINVAL
+    assert lib.robast_trace_backward(scene, ctypes.byref(rays), 10, ctypes.byref(no_sums), cot, None, grad, 0,
+                                     None) == rb.EINVAL
+    assert b"group_sums" in lib.robast_last_error()
+    assert lib.robast_trace_backward(scene, ctypes.byref(rays), 10, ctypes.byref(no_sums), None, None, grad,
+                                     rb.BACKWARD_CHECK_SEQ, None) == rb.EINVAL
+    assert b"seq_hash" in lib.robast_last_error()
 
 
 def test_batch_arguments_rejected(rb):

@@ -231,3 +231,134 @@ def test_autograd_function(rb):
     loss.backward()
     ref = gpu_grad(rb, sc, r, w_rms=np.full(sc.n_groups, 1.0 / sc.n_groups))
     assert np.allclose(params.grad.numpy(), ref, rtol=1e-9, atol=1e-12 * np.abs(ref).max())
+
+
+def test_autograd_two_forwards_then_backward_and_cuda_params(rb):
+    """backward of the first of two forward calls with different parameters
+    is the gradient at the first call's parameters; CUDA params get a CUDA
+    gradient of their own dtype."""
+    sc = scenes.schwarzschild_couder()
+    r = sc.rays(800)
+    dev = rb.Scene(sc)
+    rays = dev.upload_rays(r)
+    p1 = torch.tensor(sc.params, dtype=torch.float64, device="cuda", requires_grad=True)
+    p2 = (p1.detach() * (1 + 1e-3)).requires_grad_(True)
+    loss1 = rb.RobastTrace.apply(p1, dev, rays)[:, 4].mean()
+    loss2 = rb.RobastTrace.apply(p2, dev, rays)[:, 4].mean()
+    loss1.backward()
+    assert p1.grad.device.type == "cuda" and p1.grad.dtype == torch.float64
+    loss2.backward()
+    ref = gpu_grad(rb, sc, r, w_rms=np.full(sc.n_groups, 1.0 / sc.n_groups))
+    # the scene restored to p1 rebuilds its frames from the tilt parameters,
+    # which round to FP32 tables a little differently from the scene built
+    # from the descriptors: agreement to FP32 table rounding, and far closer
+    # than the gradient at p2
+    e1 = np.abs(p1.grad.cpu().numpy() - ref).max()
+    e2 = np.abs(p2.grad.cpu().numpy() - ref).max()
+    assert e1 <= 1e-3 * np.abs(ref).max(), e1
+    assert e1 < 0.1 * e2, (e1, e2)
+
+
+@pytest.mark.parametrize("name,precision,n_per,tol", [("schwarzschild_couder", 64, 300, 1e-9),
+                                                      ("schwarzschild_couder", 32, 1500, 1e-3),
+                                                      ("hex_concentrator", 64, 8, 1e-9)])
+def test_photon_cotangent_gradient(rb, name, precision, n_per, tol):
+    """A per-photon loss sum_p c_p . (exit x, y, z, ux, uy, uz) of the FOCUSED
+    photons, c_p random: the gradient against the oracle's dual numbers along
+    the same sequences."""
+    import oracle
+    sc = scenes.ALL[name](precision=precision)
+    r = sc.rays(n_per)
+    n = len(r["ox"])
+    rng = np.random.default_rng(17)
+    c = rng.normal(size=(n, 6))
+    dev = rb.Scene(sc)
+    rays = dev.upload_rays(r)
+    rec = oracle.trace(sc, r, log=True)
+    # photons whose fate or sequence differ from the oracle's (grazing an
+    # edge: at most the parity tests' rate) carry no cotangent, so both
+    # sides sum over the same photons
+    hits = dev.alloc_hits(n)
+    dev.trace(rays, hits=hits)
+    torch.cuda.synchronize()
+    same = (hits["fate"].cpu().numpy() == rec["fate"]) & \
+        (hits["seq_hash"].cpu().numpy().view(np.uint64) == rec["seq_hash"])
+    assert same.sum() >= n - max(3, 1e-5 * n)
+    c[~same] = 0.0
+    pc = torch.from_numpy(c).cuda()
+    for keep in (False, True):
+        dev.trace(rays, sums=dev.new_sums(), keep_order=keep)
+        g = torch.zeros(len(sc.params), dtype=torch.float64, device="cuda")
+        dev.backward(rays, None, None, g, photon_cot=pc)
+        torch.cuda.synchronize()
+        g = g.cpu().numpy()
+        if keep:
+            assert np.allclose(g, g_search, rtol=1e-9, atol=1e-12 * np.abs(g).max())
+        g_search = g
+    foc = rec["fate"] == scenes.FATE_FOCUSED
+    ref = np.zeros(len(sc.params))
+    for p0 in range(0, len(sc.params), 8):
+        cnt = min(8, len(sc.params) - p0)
+        dpos, ddir, st = oracle.forced_jac(sc, r, rec, sc.params, p0, cnt)
+        m = foc & (st == 0)
+        ref[p0:p0 + cnt] = np.einsum("nk,nkj->j", c[m, :3], dpos[m]) + np.einsum("nk,nkj->j", c[m, 3:], ddir[m])
+    scale = np.abs(ref).max()
+    err = np.abs(g - ref) / np.maximum(np.abs(ref), 1e-2 * scale)
+    print(f"{name} fp{precision}: per-photon cotangent gradient, worst rel {err.max():.2e}")
+    assert err.max() <= tol
+
+
+def test_backward_sequence_check(rb):
+    """The debug check: sequences re-derived by the backward pass equal the
+    forward ones (OK); a forward hash changed by hand is reported
+    (EMISMATCH), the gradient still accumulated."""
+    sc = scenes.hex_concentrator()
+    r = sc.rays(60)
+    dev = rb.Scene(sc)
+    rays = dev.upload_rays(r)
+    n = len(r["ox"])
+    hits = dev.alloc_hits(n)
+    sums = dev.new_sums()
+    dev.trace(rays, hits=hits, sums=sums)
+    cot = torch.zeros(sc.n_groups, 2, dtype=torch.float64, device="cuda")
+    cot[:, 1] = 1.0
+    g1 = torch.zeros(len(sc.params), dtype=torch.float64, device="cuda")
+    dev.backward(rays, sums, cot, g1, fwd_hash=hits["seq_hash"], check=True)
+    g0 = torch.zeros_like(g1)
+    dev.backward(rays, sums, cot, g0)
+    torch.cuda.synchronize()
+    assert torch.allclose(g1, g0, rtol=1e-9, atol=0)
+    bad = hits["seq_hash"].clone()
+    bad[[3, 77]] ^= 1
+    g2 = torch.zeros_like(g1)
+    with pytest.raises(rb.RobastError) as ei:
+        dev.backward(rays, sums, cot, g2, fwd_hash=bad, check=True)
+    assert ei.value.status == rb.EMISMATCH and "2 photons" in str(ei.value)
+    assert torch.allclose(g2, g0, rtol=1e-9, atol=0)
+
+
+@pytest.mark.parametrize("name,n_per", [("hex_concentrator", 30), ("davies_cotton", 2000)])
+def test_sequence_log_matches_oracle(rb, name, n_per):
+    """seq_log holds each photon's event codes (volume << 8 | face << 4 |
+    action): equal to the oracle's log wherever the fates agree."""
+    import oracle
+    sc = scenes.ALL[name]()
+    r = sc.rays(n_per)
+    n = len(r["ox"])
+    dev = rb.Scene(sc)
+    rays = dev.upload_rays(r)
+    hits = dev.alloc_hits(n)
+    hits["seq_log"] = torch.full((n * sc.max_events,), 0x7fffffff, dtype=torch.int32, device="cuda")
+    dev.trace(rays, hits=hits)
+    torch.cuda.synchronize()
+    log = hits["seq_log"].cpu().numpy().view(np.uint32).reshape(n, sc.max_events)
+    rec = oracle.trace(sc, r, log=True)
+    same = (hits["seq_hash"].cpu().numpy().view(np.uint64) == rec["seq_hash"])
+    assert same.mean() > 0.999
+    lg = rec["log"]
+    codes = (lg["vol"].astype(np.int64) << 8) | (lg["face"].astype(np.int64) << 4) | lg["act"].astype(np.int64)
+    ne = rec["n_events"].astype(np.int64)
+    k = np.arange(sc.max_events)[None, :]
+    live = k < ne[:, None]
+    assert np.array_equal(log[same][live[same]], codes[same][live[same]].astype(np.uint32))
+    assert np.all(log[~live] == 0x7fffffff)
