@@ -106,7 +106,9 @@ typedef struct {
                         * the medium on its back side: a photon that reaches
                         * the face from that side after a segment of length
                         * t is absorbed iff its bulk draw (Philox tag 2, see
-                        * robast_rays) w / 2^32 >= exp(-t / p[15]). */
+                        * robast_rays) w / 2^32 >= exp(-t / p[15]).
+                        * p[13], p[14] of a lens volume: its dispersion law
+                        * (see robast_rays.lambda; both 0 = none). */
   double Q0[9], c0[3], pivot[3], e1[3], e2[3];
 } robast_volume_desc;
 
@@ -129,6 +131,13 @@ typedef struct {
   const void *ox, *oy, *oz, *dx, *dy, *dz; /* [device] n each, float or double */
   const uint32_t* group;                   /* [device] n, < n_groups; NULL = all group 0 */
   uint64_t id_base;
+  const void* lambda;  /* [device] n wavelengths (metres, float or double), or NULL.  A
+                        * lens volume whose descriptor gives a dispersion law
+                        * (p[13] = A > 0, p[14] = B > 0: n = A + B / lambda^2)
+                        * refracts each photon with its own n(lambda); without
+                        * wavelengths, or for a lens without the law, n_inside.
+                        * EUNSUPPORTED in batches and in scenes with HEXCONE
+                        * volumes. */
 } robast_rays;
 
 /* Per-photon exit records; any pointer may be NULL (not written).

@@ -119,12 +119,24 @@ def _rays64(rays):
     return [np.ascontiguousarray(rays[k], dtype=np.float64) for k in ("ox", "oy", "oz", "dx", "dy", "dz")]
 
 
-def trace(scene, rays, id_base=0, log=False, nthreads=None, culled=True, volumes=None):
-    """Trace every photon; returns a dict of per-photon exit records (and the event log)."""
+def _lam(rays, wavelengths):
+    if not wavelengths:
+        return None
+    return np.ascontiguousarray(rays["lam"], dtype=np.float64)
+
+
+def trace(scene, rays, id_base=0, log=False, nthreads=None, culled=True, volumes=None, wavelengths=False):
+    """Trace every photon; returns a dict of per-photon exit records (and the event log).
+
+    wavelengths: each photon carries its wavelength rays["lam"] (m), and a
+    lens with a dispersion law refracts it with n(lam) (§2.1: lenses; the
+    law is the Cauchy form A + B / lam^2 of the lens descriptor); otherwise
+    every lens has its fixed index."""
     L = lib()
     vols = scene.volumes if volumes is None else volumes
     vi, vd = pack_volumes(vols)
     cols = _rays64(rays)
+    lam = _lam(rays, wavelengths)
     n = len(cols[0])
     me = scene.max_events
     out = dict(fate=np.zeros(n, np.uint8), n_events=np.zeros(n, np.uint8),
@@ -138,7 +150,7 @@ def trace(scene, rays, id_base=0, log=False, nthreads=None, culled=True, volumes
     nth = nthreads or default_threads()
     rc = L.oracle_trace(ctypes.c_int(len(vols)), _p(vi), _p(vd), ctypes.c_int(me),
                         ctypes.c_uint64(scene.seed), ctypes.c_double(scene.l_ref),
-                        ctypes.c_int64(n), *[_p(c) for c in cols], ctypes.c_uint64(id_base),
+                        ctypes.c_int64(n), *[_p(c) for c in cols], _p(lam), ctypes.c_uint64(id_base),
                         _p(out["fate"]), _p(out["n_events"]), _p(out["last_vol"]), _p(out["pos"]),
                         _p(out["dir"]), _p(out["opl"]), _p(out["seq_hash"]),
                         _p(lg["vol"]) if lg else None, _p(lg["face"]) if lg else None,
@@ -148,6 +160,7 @@ def trace(scene, rays, id_base=0, log=False, nthreads=None, culled=True, volumes
     if rc != 0:
         raise ValueError("oracle_trace rejected its input")
     out["group"] = np.asarray(rays["group"])
+    out["lam"] = lam
     if log:
         out["log"] = lg
     return out
@@ -185,7 +198,7 @@ def forced(scene, rays, rec, params, nthreads=None):
     pos, dirv = np.zeros((n, 3)), np.zeros((n, 3))
     st = np.zeros(n, np.int32)
     L.oracle_forced(ctypes.c_int(len(scene.volumes)), _p(vi), _p(vd), _p(P), ctypes.c_int64(n),
-                    *[_p(c) for c in cols], ctypes.c_int(scene.max_events), _p(rec["n_events"]),
+                    *[_p(c) for c in cols], _p(rec.get("lam")), ctypes.c_int(scene.max_events), _p(rec["n_events"]),
                     _p(lg["vol"]), _p(lg["face"]), _p(lg["act"]), _p(lg["t"]), _p(lg["s"]),
                     _p(pos), _p(dirv), _p(st), ctypes.c_int(nthreads or default_threads()))
     return pos, dirv, st
@@ -203,7 +216,8 @@ def forced_jac(scene, rays, rec, params, p0, cnt, nthreads=None):
     st = np.zeros(n, np.int32)
     rc = L.oracle_forced_jac(ctypes.c_int(len(scene.volumes)), _p(vi), _p(vd), _p(P),
                              ctypes.c_int(len(P)), ctypes.c_int(p0), ctypes.c_int(cnt),
-                             ctypes.c_int64(n), *[_p(c) for c in cols], ctypes.c_int(scene.max_events),
+                             ctypes.c_int64(n), *[_p(c) for c in cols], _p(rec.get("lam")),
+                             ctypes.c_int(scene.max_events),
                              _p(rec["n_events"]), _p(lg["vol"]), _p(lg["face"]), _p(lg["act"]),
                              _p(lg["t"]), _p(lg["s"]), _p(dpos), _p(ddir), _p(st),
                              ctypes.c_int(nthreads or default_threads()))

@@ -598,6 +598,15 @@ double fresnel(double cos_i, double n1, double n2, double& cos_t) {
   return 0.5 * (rs * rs + rp * rp);
 }
 
+// Refractive index of a lens volume's medium for a photon of wavelength lam
+// (metres; 0 = the photon carries none).  A lens whose descriptor gives a
+// Cauchy law (p[13] = A, p[14] = B != 0) has n = A + B / lam^2 for photons
+// with a wavelength; otherwise its fixed index n_inside.
+double lens_index(const Vol& v, double lam) {
+  if (lam > 0.0 && v.p[14] != 0.0) return v.p[13] + v.p[14] / (lam * lam);
+  return v.n_in;
+}
+
 constexpr uint64_t HASH0 = 0xcbf29ce484222325ull, HASHP = 0x100000001b3ull;
 
 struct Rec {
@@ -618,7 +627,7 @@ struct Scn {
 // from its reflect / absorb threshold.
 constexpr int NDIAG = 5;
 
-Rec trace_one(const Scn& S, V3<double> o, V3<double> d, uint64_t id, int culled,
+Rec trace_one(const Scn& S, V3<double> o, V3<double> d, double lam, uint64_t id, int culled,
               int32_t* lv, int32_t* lf, int32_t* la, double* lt, double* ls, double* ldiag) {
   Rec r{};
   r.hash = HASH0; r.last_vol = -1;
@@ -703,7 +712,8 @@ Rec trace_one(const Scn& S, V3<double> o, V3<double> d, uint64_t id, int culled,
         else { d = d - (2.0 * dn) * n; act = ACT_REFLECT; }
       }
     } else if (v.role == ROLE_LENS) {
-      double n1 = back ? v.n_in : 1.0, n2 = back ? 1.0 : v.n_in;
+      const double nl = lens_index(v, lam);
+      double n1 = back ? nl : 1.0, n2 = back ? 1.0 : nl;
       V3<double> no = back ? (-1.0) * n : n;          // oriented against d
       double cos_i = -dot(d, no), cos_t;
       double R = fresnel(cos_i, n1, n2, cos_t);
@@ -759,7 +769,7 @@ template <class F> void parallel_for(int64_t n, int nthreads, F f) {
 // Newton in double, then a last Newton step is taken in T so derivatives
 // follow the implicit-function theorem.
 template <class T>
-int forced_one(const std::vector<Vol>& vs, const T* P, V3<T> o, V3<T> d, int nev,
+int forced_one(const std::vector<Vol>& vs, const T* P, V3<T> o, V3<T> d, double lam, int nev,
                const int32_t* lv, const int32_t* lf, const int32_t* la, const double* lt,
                const double* ls, V3<T>& pos, V3<T>& dir) {
   for (int e = 0; e < nev; ++e) {
@@ -824,7 +834,8 @@ int forced_one(const std::vector<Vol>& vs, const T* P, V3<T> o, V3<T> d, int nev
       d = d - (2.0 * dn) * n;
     } else {
       bool back = val(dn) >= 0.0;
-      double n1 = back ? v.n_in : 1.0, n2 = back ? 1.0 : v.n_in;
+      const double nl = lens_index(v, lam);
+      double n1 = back ? nl : 1.0, n2 = back ? 1.0 : nl;
       V3<T> no = back ? (-1.0) * n : n;
       T cos_i = T(0.0) - dot(d, no);
       double eta = n1 / n2;
@@ -852,10 +863,11 @@ uint32_t oracle_draw(uint64_t seed, uint64_t id, int event) { return draw(seed, 
 
 double oracle_fresnel(double cos_i, double n1, double n2) { double ct; return fresnel(cos_i, n1, n2, ct); }
 
-// Brute-force trace.  Rays and outputs are SoA float64; log arrays (n * max_events) may be NULL.
+// Brute-force trace.  Rays and outputs are SoA float64; lam (wavelengths, m)
+// and the log arrays (n * max_events) may be NULL.
 int oracle_trace(int nv, const int32_t* vi, const double* vd, int max_events, uint64_t seed,
                  double l_ref, int64_t n, const double* ox, const double* oy, const double* oz,
-                 const double* dx, const double* dy, const double* dz, uint64_t id_base,
+                 const double* dx, const double* dy, const double* dz, const double* lam, uint64_t id_base,
                  uint8_t* fate, uint8_t* nev, int32_t* last_vol, double* pos, double* dir,
                  double* opl, uint64_t* hash, int32_t* log_vol, int32_t* log_face,
                  int32_t* log_act, double* log_t, double* log_s, double* log_diag, int nthreads,
@@ -867,7 +879,8 @@ int oracle_trace(int nv, const int32_t* vi, const double* vd, int max_events, ui
   parallel_for(n, nthreads, [&](int64_t a, int64_t b) {
     for (int64_t i = a; i < b; ++i) {
       int64_t lo = i * (int64_t)max_events;
-      Rec r = trace_one(S, mk(ox[i], oy[i], oz[i]), mk(dx[i], dy[i], dz[i]), id_base + (uint64_t)i,
+      Rec r = trace_one(S, mk(ox[i], oy[i], oz[i]), mk(dx[i], dy[i], dz[i]), lam ? lam[i] : 0.0,
+                        id_base + (uint64_t)i,
                         culled, log_vol ? log_vol + lo : nullptr, log_face ? log_face + lo : nullptr,
                         log_act ? log_act + lo : nullptr, log_t ? log_t + lo : nullptr,
                         log_s ? log_s + lo : nullptr, log_diag ? log_diag + lo * NDIAG : nullptr);
@@ -896,7 +909,7 @@ int oracle_outline(const int32_t* vi, const double* vd, int64_t n, const double*
 // Forced-sequence evaluation in double with parameters P (FD driver).
 int oracle_forced(int nv, const int32_t* vi, const double* vd, const double* P, int64_t n,
                   const double* ox, const double* oy, const double* oz, const double* dx,
-                  const double* dy, const double* dz, int max_events, const uint8_t* nev,
+                  const double* dy, const double* dz, const double* lam, int max_events, const uint8_t* nev,
                   const int32_t* log_vol, const int32_t* log_face, const int32_t* log_act,
                   const double* log_t, const double* log_s, double* pos, double* dir,
                   int32_t* status, int nthreads) {
@@ -906,7 +919,8 @@ int oracle_forced(int nv, const int32_t* vi, const double* vd, const double* P, 
       int64_t lo = i * (int64_t)max_events;
       const double nan = std::numeric_limits<double>::quiet_NaN();
       V3<double> p = mk(nan, nan, nan), q = p;
-      status[i] = forced_one<double>(vs, P, mk(ox[i], oy[i], oz[i]), mk(dx[i], dy[i], dz[i]), nev[i],
+      status[i] = forced_one<double>(vs, P, mk(ox[i], oy[i], oz[i]), mk(dx[i], dy[i], dz[i]), lam ? lam[i] : 0.0,
+                                     nev[i],
                                      log_vol + lo, log_face + lo, log_act + lo, log_t + lo,
                                      log_s + lo, p, q);
       pos[3 * i] = p.x; pos[3 * i + 1] = p.y; pos[3 * i + 2] = p.z;
@@ -921,7 +935,7 @@ int oracle_forced(int nv, const int32_t* vi, const double* vd, const double* P, 
 int oracle_forced_jac(int nv, const int32_t* vi, const double* vd, const double* P, int np,
                       int p0, int cnt, int64_t n, const double* ox, const double* oy,
                       const double* oz, const double* dx, const double* dy, const double* dz,
-                      int max_events, const uint8_t* nev, const int32_t* log_vol,
+                      const double* lam, int max_events, const uint8_t* nev, const int32_t* log_vol,
                       const int32_t* log_face, const int32_t* log_act, const double* log_t,
                       const double* log_s, double* dpos, double* ddir, int32_t* status,
                       int nthreads) {
@@ -935,7 +949,8 @@ int oracle_forced_jac(int nv, const int32_t* vi, const double* vd, const double*
       int64_t lo = i * (int64_t)max_events;
       V3<Dual> p, q;
       status[i] = forced_one<Dual>(vs, PD.data(), mk(Dual(ox[i]), Dual(oy[i]), Dual(oz[i])),
-                                   mk(Dual(dx[i]), Dual(dy[i]), Dual(dz[i])), nev[i], log_vol + lo,
+                                   mk(Dual(dx[i]), Dual(dy[i]), Dual(dz[i])), lam ? lam[i] : 0.0, nev[i],
+                                   log_vol + lo,
                                    log_face + lo, log_act + lo, log_t + lo, log_s + lo, p, q);
       const Dual* pc[3] = {&p.x, &p.y, &p.z};
       const Dual* qc[3] = {&q.x, &q.y, &q.z};

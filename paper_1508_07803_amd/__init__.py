@@ -52,7 +52,7 @@ class SceneDesc(ctypes.Structure):
 class Rays(ctypes.Structure):
     _fields_ = [("ox", ctypes.c_void_p), ("oy", ctypes.c_void_p), ("oz", ctypes.c_void_p),
                 ("dx", ctypes.c_void_p), ("dy", ctypes.c_void_p), ("dz", ctypes.c_void_p),
-                ("group", ctypes.c_void_p), ("id_base", ctypes.c_uint64)]
+                ("group", ctypes.c_void_p), ("id_base", ctypes.c_uint64), ("lam", ctypes.c_void_p)]
 
 
 class Hits(ctypes.Structure):
@@ -164,8 +164,10 @@ def _rays_struct(rays, id_base=0, offset=0):
         t = rays[k]
         return t.data_ptr() + offset * t.element_size()
     g = rays.get("group")
+    lam = rays.get("lam")
     return Rays(p("ox"), p("oy"), p("oz"), p("dx"), p("dy"), p("dz"),
-                (g.data_ptr() + offset * g.element_size()) if g is not None else None, id_base + offset)
+                (g.data_ptr() + offset * g.element_size()) if g is not None else None, id_base + offset,
+                p("lam") if lam is not None else None)
 
 
 _HIT_ITEM = {"fate": 1, "n_events": 1, "last_vol": 4, "seq_hash": 8}
@@ -176,8 +178,10 @@ def _check_extents(n, dtype, rays=None, hits=None, f64=()):
     tensors a call reads or writes are checked here, before any launch."""
     import torch
     if rays is not None:
-        for k in ("ox", "oy", "oz", "dx", "dy", "dz"):
-            t = rays[k]
+        for k in ("ox", "oy", "oz", "dx", "dy", "dz", "lam"):
+            t = rays.get(k)
+            if t is None and k == "lam":
+                continue
             if t.dtype != dtype:
                 raise ValueError(f"rays[{k!r}] is {t.dtype}, the scene computes in {dtype}")
             if t.numel() < n:
@@ -246,11 +250,13 @@ class Scene:
         import torch
         return torch.float32 if self.precision == 32 else torch.float64
 
-    def upload_rays(self, rays, device="cuda"):
-        """Host ray dict (numpy, from `scenes`) -> dict of device tensors."""
+    def upload_rays(self, rays, device="cuda", wavelengths=False):
+        """Host ray dict (numpy, from `scenes`) -> dict of device tensors;
+        with wavelengths, each photon's rays["lam"] goes along as "lam"."""
         import torch
+        keys = ("ox", "oy", "oz", "dx", "dy", "dz") + (("lam",) if wavelengths else ())
         out = {k: torch.from_numpy(np.ascontiguousarray(rays[k])).to(device=device, dtype=self.dtype)
-               for k in ("ox", "oy", "oz", "dx", "dy", "dz")}
+               for k in keys}
         out["group"] = torch.from_numpy(np.ascontiguousarray(rays["group"]).astype(np.int32)).to(device)
         return out
 

@@ -174,6 +174,10 @@ int validate(const robast_scene_desc* d, const double* params, int64_t n_params)
     if (v.role == ROBAST_LENS && !(v.n_inside > 0.0)) return fail(ROBAST_EINVAL, "lens index must be > 0" + at);
     if (v.role == ROBAST_LENS && !(v.p[15] >= 0.0 && std::isfinite(v.p[15])))
       return fail(ROBAST_EINVAL, "lens absorption length p[15] must be finite and >= 0" + at);
+    if (v.role == ROBAST_LENS && v.p[14] != 0.0 && !(v.p[13] > 0.0 && v.p[14] > 0.0))
+      return fail(ROBAST_EINVAL, "lens dispersion law needs A = p[13] > 0 and B = p[14] > 0" + at);
+    if (v.role == ROBAST_LENS && v.p[14] != 0.0 && v.shape == ROBAST_HEXCONE)
+      return fail(ROBAST_EUNSUPPORTED, "dispersive lens faces must not be cones" + at);
     if (v.role == ROBAST_LENS && v.shape != ROBAST_BOX && v.shape != ROBAST_PLANE && v.shape != ROBAST_SPHERE &&
         v.shape != ROBAST_ASPHERE)
       return fail(ROBAST_EUNSUPPORTED, "lens faces must be planes, spheres, aspheres or boxes" + at);
@@ -404,6 +408,7 @@ template <typename T> void fill_record(DVol<T>& r, const robast_volume_desc& v, 
   r.rout = q<T>(outline_rmax(v) * (1.0 + 1e-6));
   r.n_in = q<T>(v.n_inside);
   r.absl = v.role == ROBAST_LENS ? q<T>(v.p[15]) : T(0);
+  if (v.role == ROBAST_LENS && v.p[14] != 0.0) { r.p[10] = q<T>(v.p[13]); r.p[11] = q<T>(v.p[14]); }
   // world AABB of the 8 corners, x = c + Q^{-1} x_l
   double I[9];
   inv3(v.Q, I);
@@ -725,7 +730,11 @@ void compile_blob(robast_scene& s, std::vector<char>& blob, SceneView<T>& V, std
   align_to<T>(blob, 16);
   V.n_vol = nv;
   V.shapes = 0;
-  for (const auto& v : s.desc) V.shapes |= 1 << v.shape;
+  V.dispersive = 0;
+  for (const auto& v : s.desc) {
+    V.shapes |= 1 << v.shape;
+    if (v.role == ROBAST_LENS && v.p[14] != 0.0) V.dispersive = 1;
+  }
   V.n_always = (int)always.size();
   V.n_grp = (int)grecs.size();
   V.max_events = s.max_events;
@@ -821,8 +830,10 @@ int upload(robast_scene* s) {
 }
 
 template <typename T> RaysView<T> rays_view(const robast_rays* r) {
-  return RaysView<T>{(const T*)r->ox, (const T*)r->oy, (const T*)r->oz, (const T*)r->dx, (const T*)r->dy,
-                     (const T*)r->dz, r->group, r->id_base};
+  RaysView<T> R{(const T*)r->ox, (const T*)r->oy, (const T*)r->oz, (const T*)r->dx, (const T*)r->dy,
+                (const T*)r->dz, r->group, r->id_base};
+  R.lam = (const T*)r->lambda;
+  return R;
 }
 
 template <typename T> HitsView<T> hits_view(const robast_hits* h) {
@@ -835,6 +846,16 @@ template <typename T> HitsView<T> hits_view(const robast_hits* h) {
 int check_rays(const robast_rays* rays) {
   if (!rays->ox || !rays->oy || !rays->oz || !rays->dx || !rays->dy || !rays->dz)
     return fail(ROBAST_EINVAL, "NULL ray coordinate array");
+  return ROBAST_OK;
+}
+
+// Wavelengths are traced for scenes whose dispersive lenses sit beside
+// shapes other than cones (the kernels carry them in those instances only).
+int check_lambda(const robast_scene* s, const robast_rays* rays) {
+  if (!rays->lambda) return ROBAST_OK;
+  const int shapes = s->precision == 32 ? s->sf.shapes : s->sd.shapes;
+  if (shapes & ~kShapesNoCone)
+    return fail(ROBAST_EUNSUPPORTED, "per-photon wavelengths are not traced in scenes with hexagonal cones");
   return ROBAST_OK;
 }
 
@@ -894,6 +915,7 @@ int binned_view(robast_scene* s, const robast_rays* rays, int64_t n, hipStream_t
     s->kept = keep;
     if (reused) *reused = true;
     out = binned_rays<T>((const BinRecord<T>*)s->kept_records, rays->group != nullptr, rays->id_base);
+    out.lam = R.lam;
     return ROBAST_OK;
   }
   s->kept = false;   // the workspace is about to be overwritten
@@ -915,6 +937,7 @@ int binned_view(robast_scene* s, const robast_rays* rays, int64_t n, hipStream_t
     hipError_t e = launch_binning<T>(R, n, geo, BinMulti{nullptr, nullptr, 0}, plan, W, st);
     if (e != hipSuccess) return hip_fail(e, "binning launch");
     out = binned_rays<T>(W.out, rays->group != nullptr, rays->id_base);
+    out.lam = R.lam;
     return ROBAST_OK;
   }
   if (plan.bytes > s->work_bytes) {
@@ -931,6 +954,7 @@ int binned_view(robast_scene* s, const robast_rays* rays, int64_t n, hipStream_t
   hipError_t e = launch_binning<T>(R, n, geo, BinMulti{nullptr, nullptr, 0}, plan, W, st);
   if (e != hipSuccess) return hip_fail(e, "binning launch");
   out = binned_rays<T>(W.out, rays->group != nullptr, rays->id_base);
+  out.lam = R.lam;
   if (keep) {
     s->kept = true;
     s->kept_rays = *rays;
@@ -1136,6 +1160,7 @@ int robast_trace(robast_scene* s, const robast_rays* rays, int64_t n, const roba
   if (n < 0) return fail(ROBAST_EINVAL, "n < 0");
   if (n == 0) return ROBAST_OK;
   int rc = check_rays(rays);
+  if (!rc) rc = check_lambda(s, rays);
   if (!rc) rc = check_hits(hits);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
@@ -1150,6 +1175,7 @@ int robast_trace_static(robast_scene* s, const robast_rays* rays, int64_t n, con
   if (n < 0) return fail(ROBAST_EINVAL, "n < 0");
   if (n == 0) return ROBAST_OK;
   int rc = check_rays(rays);
+  if (!rc) rc = check_lambda(s, rays);
   if (!rc) rc = check_hits(hits);
   if (rc) return rc;
   void* work = nullptr;
@@ -1194,6 +1220,7 @@ int robast_trace_backward(robast_scene* s, const robast_rays* rays, int64_t n, c
   if (n < 0) return fail(ROBAST_EINVAL, "n < 0");
   if (n == 0) return ROBAST_OK;
   int rc = check_rays(rays);
+  if (!rc) rc = check_lambda(s, rays);
   if (rc) return rc;
   if (s->max_events > 64) return fail(ROBAST_EUNSUPPORTED, "backward supports max_events <= 64");
   hipStream_t st = (hipStream_t)stream;
@@ -1232,6 +1259,7 @@ int robast_bin_photons(robast_scene* s, const robast_rays* rays, int64_t n, void
   if (n < 0) return fail(ROBAST_EINVAL, "n < 0");
   if (n == 0) return ROBAST_OK;
   int rc = check_rays(rays);
+  if (!rc) rc = check_lambda(s, rays);
   if (rc) return rc;
   s->kept = false;
   s->path_ok = false;
@@ -1263,6 +1291,7 @@ int robast_autotune(robast_scene* s, const robast_rays* rays, int64_t n, robast_
   if (!s || !rays) return fail(ROBAST_EINVAL, "NULL scene or rays");
   if (n < 1) return fail(ROBAST_EINVAL, "n < 1");
   int rc = check_rays(rays);
+  if (!rc) rc = check_lambda(s, rays);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   s->kept = false;
@@ -1424,6 +1453,7 @@ int robast_trace_batch(robast_batch* b, const robast_rays* rays, const robast_hi
   if (hits->seq_log) return fail(ROBAST_EINVAL, "seq_log is written by robast_trace only");
   if (b->n_photons == 0) return ROBAST_OK;
   int rc = check_rays(rays);
+  if (!rc && rays->lambda) rc = fail(ROBAST_EUNSUPPORTED, "batches trace no per-photon wavelengths");
   if (!rc) rc = check_hits(hits);
   if (rc) return rc;
   const bool keep = (flags & ROBAST_TRACE_KEEP_ORDER) != 0;
@@ -1454,6 +1484,7 @@ int robast_trace_backward_batch(robast_batch* b, const robast_rays* rays, const 
   if (!b || !rays || !sums || !cot || !grad) return fail(ROBAST_EINVAL, "NULL batch, rays, sums, cot or grad");
   if (b->n_photons == 0) return ROBAST_OK;
   int rc = check_rays(rays);
+  if (!rc && rays->lambda) rc = fail(ROBAST_EUNSUPPORTED, "batches trace no per-photon wavelengths");
   if (rc) return rc;
   if (b->max_events > 32) return fail(ROBAST_EUNSUPPORTED, "batched backward supports max_events <= 32");
   hipStream_t st = (hipStream_t)stream;

@@ -234,6 +234,7 @@ static hipError_t launch_bwd_s(const SceneView<T>& S, const RaysView<T>& R, int6
 template <typename T, int MAXE, bool USE_LDS>
 static hipError_t launch_bwd_l(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const AdjView& A,
                                const LaunchCfg& cfg, hipStream_t st, const PathView* P) {
+  if (R.lam && S.dispersive) return launch_bwd_s<T, MAXE, USE_LDS, kShapesNoCone | kLambda>(S, R, n, A, cfg, st, P);
   if (S.shapes & ~kShapesNoCone) return launch_bwd_s<T, MAXE, USE_LDS, kShapesAll>(S, R, n, A, cfg, st, P);
   return launch_bwd_s<T, MAXE, USE_LDS, kShapesNoCone>(S, R, n, A, cfg, st, P);
 }

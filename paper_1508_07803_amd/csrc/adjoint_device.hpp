@@ -69,15 +69,15 @@ template <typename C> struct FrameC {
 };
 
 // Apply a recorded action at a hit with front normal n (no random draw),
-// in double like the forward interaction.
+// in double like the forward interaction; nin: the lens medium's index for
+// this photon.
 template <typename T> __device__ __forceinline__ void apply_action(const DVol<T>& v, V3<double> n, int act,
-                                                                   V3<double>& d, int& back) {
+                                                                   V3<double>& d, int& back, double nin) {
   double dn = dot(d, n);
   back = dn < 0.0 ? 0 : 1;
   if (act == ACT_REFLECT) {
     d = fma3(-2.0 * dn, n, d);
   } else if (act == ACT_REFRACT) {
-    double nin = (double)v.n_in;
     double n1 = back ? nin : 1.0, n2 = back ? 1.0 : nin;
     V3<double> no = back ? scl(-1.0, n) : n;
     double cos_i = -dot(d, no);
@@ -121,7 +121,7 @@ template <typename C, typename P> __device__ __forceinline__ void bez2(const P* 
 template <typename C, typename T, int SH = kShapesAll>
 __device__ __forceinline__ void event_adjoint(const DVol<T>& v, const DTilt* tilt, int face, int act,
                                               V3<double> O, V3<C> d, C t, C s, V3<C>& Xb, V3<C>& db,
-                                              GradSink& gs) {
+                                              GradSink& gs, C nin) {
   const FrameC<C> F(v);
   V3<double> Xw = adv(O, t, d);
   V3<C> xl = F.local(Xw);
@@ -140,7 +140,6 @@ __device__ __forceinline__ void event_adjoint(const DVol<T>& v, const DTilt* til
     int back = dot(d, n) < C(0) ? 0 : 1;
     C sg = back ? C(-1) : C(1);
     V3<C> no = scl(sg, n);
-    const C nin = (C)v.n_in;
     C n1 = back ? nin : C(1), n2 = back ? C(1) : nin;
     C eta = n1 / n2;
     C cos_i = -dot(d, no);
@@ -303,7 +302,7 @@ __device__ __forceinline__ void event_adjoint(const DVol<T>& v, const DTilt* til
 template <typename T, int SH = kShapesAll>
 __device__ __forceinline__ bool reverse_sweep(const SceneView<T>& L, const AdjView& A, GradSink& gs,
                                               const double* cf, const double* pc, V3<T> o0, V3<T> d0,
-                                              const uint32_t* codes, int nev) {
+                                              const uint32_t* codes, int nev, double lam) {
   const V3<double> O0 = {(double)o0.x, (double)o0.y, (double)o0.z};
   const V3<double> D0 = {(double)d0.x, (double)d0.y, (double)d0.z};
   V3<double> Xb = {0.0, 0.0, 0.0}, db = {0.0, 0.0, 0.0};
@@ -320,7 +319,7 @@ __device__ __forceinline__ bool reverse_sweep(const SceneView<T>& L, const AdjVi
       V3<double> X = {O.x + t * d.x, O.y + t * d.y, O.z + t * d.z};
       V3<double> nrm = front_normal<T, SH>(v, face, X, s);
       int back;
-      apply_action(v, nrm, act, d, back);
+      apply_action(v, nrm, act, d, back, lens_index<SH>(v, lam));
       O = X; pv = vid; pf = face; ps = back ^ (act == ACT_REFRACT ? 1 : 0);
     }
     const int vid = (int)(codes[e] >> 8), face = (int)((codes[e] >> 4) & 15u), act = (int)(codes[e] & 15u);
@@ -331,14 +330,16 @@ __device__ __forceinline__ bool reverse_sweep(const SceneView<T>& L, const AdjVi
       V3<double> dout = d;
       if (act == ACT_REFLECT || act == ACT_REFRACT) {
         int back;
-        apply_action(L.vol[vid], front_normal<T, SH>(L.vol[vid], face, X, s), act, dout, back);
+        apply_action(L.vol[vid], front_normal<T, SH>(L.vol[vid], face, X, s), act, dout, back,
+                     lens_index<SH>(L.vol[vid], lam));
       }
       seed_cots<T>(cf, pc, X, dout, Xb, db);
     }
     // the pull-back runs in FP64 from the replayed state: the per-photon
     // partials are summed with cancellation (centroid-subtracted
     // cotangents), which FP32 arithmetic would not resolve
-    event_adjoint<double, T, SH>(L.vol[vid], A.tilt + vid, face, act, O, d, t, s, Xb, db, gs);
+    event_adjoint<double, T, SH>(L.vol[vid], A.tilt + vid, face, act, O, d, t, s, Xb, db, gs,
+                                 lens_index<SH>(L.vol[vid], lam));
   }
   return true;
 }
@@ -360,10 +361,11 @@ __device__ __forceinline__ void adjoint_photon(const SceneView<T>& L, const Rays
   const V3<T> o0 = {oa[0], oa[1], oa[2]};
   const V3<T> d0 = {da[0], da[1], da[2]};
   uint32_t codes[MAXE];
-  PhotonOut<T> r = trace_photon<T, MAXE, SH>(L, o0, d0, R.id_base + (uint64_t)R.src(i), codes);
+  const double lam = R.template wavelength<SH>(i);
+  PhotonOut<T> r = trace_photon<T, MAXE, SH>(L, o0, d0, R.id_base + (uint64_t)R.src(i), codes, lam);
   if (A.check_hash && A.check_hash[R.src(i)] != r.hash) atomicAdd(A.mismatch, 1u);
   if (!want || r.fate != FOCUSED || r.nev > MAXE) return;
-  (void)reverse_sweep<T, SH>(L, A, gs, cf, pc, o0, d0, codes, r.nev);
+  (void)reverse_sweep<T, SH>(L, A, gs, cf, pc, o0, d0, codes, r.nev, lam);
 }
 
 // State entering an event of a recorded path: origin, direction, and the
@@ -407,6 +409,7 @@ __device__ __forceinline__ void adjoint_photon_path(const SceneView<T>& L, const
   T oa[3], da[3];
   R.load(i, oa, da);
   const uint32_t codes[kPathSlots] = {w.x, w.y, w.z, w.w};
+  const double lam = R.template wavelength<SH>(i);
   const int nev = w.y == kPathEnd ? 1 : w.z == kPathEnd ? 2 : w.w == kPathEnd ? 3 : 4;
   PathState st[NS];
   V3<double> O = {(double)oa[0], (double)oa[1], (double)oa[2]};
@@ -425,7 +428,7 @@ __device__ __forceinline__ void adjoint_photon_path(const SceneView<T>& L, const
       const V3<double> X = {O.x + t * d.x, O.y + t * d.y, O.z + t * d.z};
       if (act == ACT_REFLECT || act == ACT_REFRACT) {
         int back;
-        apply_action(v, front_normal<T, SH>(v, face, X, s), act, d, back);
+        apply_action(v, front_normal<T, SH>(v, face, X, s), act, d, back, lens_index<SH>(v, lam));
         ps = back ^ (act == ACT_REFRACT ? 1 : 0);
       } else {
         ps = dot(d, front_normal<T, SH>(v, face, X, s)) < 0.0 ? 0 : 1;
@@ -441,10 +444,11 @@ __device__ __forceinline__ void adjoint_photon_path(const SceneView<T>& L, const
       const int vid = (int)(codes[e] >> 8), face = (int)((codes[e] >> 4) & 15u), act = (int)(codes[e] & 15u);
       if constexpr (PROMOTE) {
         const DVol<double> vd = promote(L.vol[vid]);
-        event_adjoint<double, double, SH>(vd, A.tilt + vid, face, act, st[e].O, st[e].d, st[e].t, st[e].s, Xb, db, gs);
+        event_adjoint<double, double, SH>(vd, A.tilt + vid, face, act, st[e].O, st[e].d, st[e].t, st[e].s, Xb, db, gs,
+                                          lens_index<SH>(L.vol[vid], lam));
       } else {
         event_adjoint<double, T, SH>(L.vol[vid], A.tilt + vid, face, act, st[e].O, st[e].d, st[e].t, st[e].s, Xb, db,
-                                 gs);
+                                 gs, lens_index<SH>(L.vol[vid], lam));
       }
     }
   }

@@ -839,13 +839,23 @@ template <typename T> __device__ __forceinline__ T fresnel_R(T cos_i, T n1, T n2
 
 enum { ACT_REFLECT = 0, ACT_REFRACT = 1, ACT_STOP = 2 };
 
+// Index of a lens volume's medium for a photon of wavelength lam (metres;
+// 0: the photon carries none): the lens's dispersion law A + B / lam^2 when
+// it has one and the kernel carries wavelengths, else its fixed index.
+template <int SH, typename T> __device__ __forceinline__ double lens_index(const DVol<T>& v, double lam) {
+  if constexpr ((SH & kLambda) != 0) {
+    if (lam > 0.0 && v.p[11] != T(0)) return (double)v.p[10] + (double)v.p[11] / (lam * lam);
+  }
+  return (double)v.n_in;
+}
+
 // Apply the interaction of the event at X on (vol, face).  Updates d, ncur,
 // fate; returns the action.  `back` is set from the side the photon came from;
 // seg is the length of the segment that ends at this event.
 template <typename C, typename T> __device__ __forceinline__ int interact(const DVol<T>& v, V3<C> n, V3<C>& d,
                                                                           C& ncur, int& fate, int& back,
                                                                           uint64_t seed, uint64_t id, int k,
-                                                                          double seg) {
+                                                                          double seg, C nlens) {
   C dn = dot(d, n);
   back = dn < C(0) ? 0 : 1;
   switch (v.role) {
@@ -867,8 +877,7 @@ template <typename C, typename T> __device__ __forceinline__ int interact(const 
         fate = ABSORBED;
         return ACT_STOP;
       }
-      C nin = (C)v.n_in;
-      C n1 = back ? nin : C(1), n2 = back ? C(1) : nin;
+      C n1 = back ? nlens : C(1), n2 = back ? C(1) : nlens;
       V3<C> no = back ? scl(C(-1), n) : n;
       C cos_i = -dot(d, no), cos_t;
       C R = fresnel_R(cos_i, n1, n2, cos_t);
@@ -898,15 +907,16 @@ template <typename T> struct PhotonOut {
 // in double; every search uses their rounding to T.
 struct PhotonState {
   V3<double> o, d;
-  double ncur, opl;
+  double ncur, opl, lam;   // lam: the photon's wavelength (0: none)
   uint64_t hash, id;
   int k, prev_v, prev_f, prev_side, fate, last_vol;
 };
 
-template <typename T> __device__ __forceinline__ void photon_init(PhotonState& p, V3<T> o, V3<T> d, uint64_t id) {
+template <typename T> __device__ __forceinline__ void photon_init(PhotonState& p, V3<T> o, V3<T> d, uint64_t id,
+                                                                  double lam = 0.0) {
   p.o = {(double)o.x, (double)o.y, (double)o.z};
   p.d = {(double)d.x, (double)d.y, (double)d.z};
-  p.ncur = 1.0; p.opl = 0.0; p.hash = 0xcbf29ce484222325ull; p.id = id;
+  p.ncur = 1.0; p.opl = 0.0; p.lam = lam; p.hash = 0xcbf29ce484222325ull; p.id = id;
   p.k = 0; p.prev_v = -1; p.prev_f = -1; p.prev_side = 0; p.fate = 0; p.last_vol = -1;
   if (!finite3(o) || !finite3(d) || dot(d, d) == T(0)) p.fate = FAILED;
 }
@@ -926,7 +936,7 @@ __device__ __forceinline__ uint32_t photon_step(const SceneView<T>& S, PhotonSta
   p.opl += p.ncur * b.tp;
   V3<double> n = front_normal<T, SH>(v, b.face, X, b.s);
   int back, fate = 0;
-  int act = interact<double>(v, n, p.d, p.ncur, fate, back, S.seed, p.id, p.k, b.tp);
+  int act = interact<double>(v, n, p.d, p.ncur, fate, back, S.seed, p.id, p.k, b.tp, lens_index<SH>(v, p.lam));
   p.hash = (p.hash ^ (((uint64_t)b.vol << 4) | ((uint64_t)b.face << 1) | (uint64_t)back)) * 0x100000001b3ull;
   p.last_vol = b.vol;
   uint32_t code = ((uint32_t)b.vol << 8) | ((uint32_t)b.face << 4) | (uint32_t)act;
@@ -952,9 +962,9 @@ template <typename T> __device__ __forceinline__ PhotonOut<T> photon_out(const P
 // event codes are written to it (at most MAXLOG).
 template <typename T, int MAXLOG, int SH = kShapesAll>
 __device__ __forceinline__ PhotonOut<T> trace_photon(const SceneView<T>& S, V3<T> o, V3<T> d, uint64_t id,
-                                                     uint32_t* codes) {
+                                                     uint32_t* codes, double lam = 0.0) {
   PhotonState p;
-  photon_init(p, o, d, id);
+  photon_init(p, o, d, id, lam);
   while (!p.fate) {
     int k = p.k;
     uint32_t code = photon_step<T, SH>(S, p);

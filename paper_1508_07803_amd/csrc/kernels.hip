@@ -75,7 +75,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
     int g = R.grp(cur);
     if ((unsigned)g >= (unsigned)S.n_groups) g = -1;
     PhotonState ps;
-    photon_init(ps, V3<T>{oa[0], oa[1], oa[2]}, V3<T>{da[0], da[1], da[2]}, R.id_base + (uint64_t)R.src(cur));
+    photon_init(ps, V3<T>{oa[0], oa[1], oa[2]}, V3<T>{da[0], da[1], da[2]}, R.id_base + (uint64_t)R.src(cur),
+                R.template wavelength<SH>(cur));
     // the path record is built in registers and written once, as one 16-byte
     // store (the records of a wave's photons are contiguous)
     uint4 rec = {kPathEnd, kPathEnd, kPathEnd, kPathEnd};
@@ -263,6 +264,10 @@ static hipError_t launch_one_s(const SceneView<T>& S, const RaysView<T>& R, int6
 template <typename T, bool RECORD, bool SUMS, bool USE_LDS>
 static hipError_t launch_one_l(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const HitsView<T>& H,
                                const LaunchCfg& cfg, hipStream_t st) {
+  // wavelengths matter only for dispersive lenses (the caller rejects them
+  // for scenes with cones)
+  if (R.lam && S.dispersive)
+    return launch_one_s<T, RECORD, SUMS, USE_LDS, kShapesNoCone | kLambda>(S, R, n, H, cfg, st);
   if (S.shapes & ~kShapesNoCone) return launch_one_s<T, RECORD, SUMS, USE_LDS, kShapesAll>(S, R, n, H, cfg, st);
   return launch_one_s<T, RECORD, SUMS, USE_LDS, kShapesNoCone>(S, R, n, H, cfg, st);
 }

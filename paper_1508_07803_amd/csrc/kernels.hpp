@@ -18,6 +18,9 @@ template <typename T> struct RaysView {
   // arrays; binned copies interleave each photon into one record.
   int64_t stride = 1;    // in T
   int64_t ustride = 1;   // in uint32_t (group, perm)
+  // Wavelength of each photon (metres), in the caller's order (indexed by
+  // src(i), also for binned copies), or null.
+  const T* lam = nullptr;
 
   __device__ __forceinline__ void load(int64_t i, T o[3], T d[3]) const {
     const int64_t k = i * stride;
@@ -27,6 +30,11 @@ template <typename T> struct RaysView {
   __device__ __forceinline__ int grp(int64_t i) const { return group ? (int)group[i * ustride] : 0; }
   // index of photon i in the caller's bundle
   __device__ __forceinline__ int64_t src(int64_t i) const { return perm ? (int64_t)perm[i * ustride] : i; }
+  // wavelength of photon i when the kernel carries wavelengths (SH has kLambda), else 0
+  template <int SH> __device__ __forceinline__ double wavelength(int64_t i) const {
+    if constexpr ((SH & kLambda) != 0) return (double)lam[src(i)];
+    else return 0.0;
+  }
 };
 
 // Path record of a photon, written by a forward trace for the adjoint that

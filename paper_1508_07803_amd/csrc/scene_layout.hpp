@@ -23,6 +23,9 @@ enum Fate { FOCUSED = 1, ABSORBED = 2, EXITED = 3, SUSPENDED = 4, FAILED = 5 };
 // register allocation).
 constexpr int kShapesAll = (1 << PLANE) | (1 << SPHERE) | (1 << ASPHERE) | (1 << CYLINDER) | (1 << BOX) | (1 << HEXCONE);
 constexpr int kShapesNoCone = kShapesAll & ~(1 << HEXCONE);
+// Kernel option joined to a shape set: photons carry their own wavelengths
+// and dispersive lenses refract them with n(lambda).
+constexpr int kLambda = 1 << 16;
 
 // Per-volume record, precision T.
 //   p (shape, derived): SPHERE {c}; ASPHERE {rn, b1..b8, 1/rn^2}; CYLINDER {rho, h};
@@ -32,6 +35,7 @@ constexpr int kShapesNoCone = kShapesAll & ~(1 << HEXCONE);
 //   lo/hi: local-frame box of the surface (asphere z-slab for bracketing)
 //   bmin/bmax: world AABB; slope: max |grad sag| of a sag surface on its outline
 //   absl: lenses: absorption length of the medium on the back side (0: none)
+//   lenses also keep their dispersion law in p[10] = A, p[11] = B (n = A + B / lambda^2; B = 0: none)
 template <typename T> struct alignas(16) DVol {
   T bmin[3], bmax[3];    // world AABB first: the candidate test reads only these and `shape`
   int32_t shape, role;
@@ -73,6 +77,7 @@ template <typename T> struct SceneView {
   const uint16_t* items;
   const GroupRec<T>* groups;
   int32_t n_vol, n_always, n_grp, shapes;   // shapes: bit 1 << shape of every shape present
+  int32_t dispersive;                       // some lens has a dispersion law
   int32_t max_events, n_groups;
   uint64_t seed;
   T eps_self;                      // self-intersection guard for the face just left

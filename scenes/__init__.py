@@ -760,6 +760,25 @@ def cauchy_index(lam, A=CAUCHY_PMMA[0], B=CAUCHY_PMMA[1]):
     return A + B / (lam * lam)
 
 
+def _dispersive(v):
+    """Give a lens volume the material's dispersion law (p[13] = A,
+    p[14] = B of n = A + B / lam^2): photons that carry their own wavelength
+    are refracted with n(lam); n_inside stays the index at the scene's
+    wavelength for photons that carry none."""
+    v["p"][13], v["p"][14] = CAUCHY_PMMA
+    return v
+
+
+def with_wavelengths(scene, rays, lam_min=300e-9, lam_max=600e-9, seed=None):
+    """The same photons, each given a wavelength drawn uniformly from
+    [lam_min, lam_max] (a continuous spectrum traced in one bundle; rounded
+    to the scene precision)."""
+    rng = np.random.default_rng(scene.seed + 77 if seed is None else seed)
+    out = dict(rays)
+    out["lam"] = _q(rng.uniform(lam_min, lam_max, len(rays["ox"])), scene.precision)
+    return out
+
+
 def aspheric_lens(seed=SEED_BASE + 10, lam=400e-9, a=0.25, R=-0.5, k=None, edge=0.01,
                   fields_deg=(0.0, 1.0, 2.0, 3.0), design_lam=400e-9, coeffs=None, precision=32,
                   absorption_length=0.0):
@@ -795,6 +814,7 @@ def aspheric_lens(seed=SEED_BASE + 10, lam=400e-9, a=0.25, R=-0.5, k=None, edge=
             new_volume(ROLE_FOCAL, SHAPE_PLANE, OUTLINE_DISC, c=(0.0, 0.0, z_focal), o=[0.08])]
     for v in vols[:2]:
         v["p"][15] = absorption_length
+        _dispersive(v)
     names = [f"front_b{i}" for i in range(1, 9)]
     return _finish("aspheric_lens", vols, list(b), names, precision, 16, seed, f,
                    np.radians(np.asarray(fields_deg, dtype=np.float64)), _dish_rays(a, 1.0),
@@ -868,6 +888,7 @@ def fresnel_lens(seed=SEED_BASE + 11, lam=400e-9, a=0.25, n_zones=10, bfl=2.0, t
     for v in vols:
         if v["role"] == ROLE_LENS:
             v["p"][15] = absorption_length
+            _dispersive(v)
     return _finish("fresnel_lens", vols, params, names, precision, 16, seed, bfl,
                    np.radians(np.asarray(fields_deg, dtype=np.float64)), _dish_rays(a, 1.0),
                    lam=lam, n_index=cauchy_index(lam), focal_z=z_F, zone_edges=edges.tolist(),

@@ -362,3 +362,31 @@ def test_sequence_log_matches_oracle(rb, name, n_per):
     live = k < ne[:, None]
     assert np.array_equal(log[same][live[same]], codes[same][live[same]].astype(np.uint32))
     assert np.all(log[~live] == 0x7fffffff)
+
+
+@pytest.mark.parametrize("precision,n_per,floor", [(32, 10000, 1e-2), (64, 2000, 1e-3)])
+def test_lens_rms_gradient_with_wavelengths(rb, precision, n_per, floor):
+    """The singlet traced over a spectrum (a wavelength per photon): the RMS
+    gradient against the oracle's dual numbers along the same sequences,
+    with each photon's own index."""
+    import oracle
+    sc = scenes.aspheric_lens(precision=precision)
+    r = scenes.with_wavelengths(sc, sc.rays(n_per))
+    dev = rb.Scene(sc)
+    rays = dev.upload_rays(r, wavelengths=True)
+    w = np.full(sc.n_groups, 1.0 / sc.n_groups)
+    cot = torch.zeros(sc.n_groups, 2, dtype=torch.float64, device="cuda")
+    cot[:, 0] = torch.as_tensor(w)
+    out = []
+    for keep in (False, True):
+        sums = dev.new_sums()
+        dev.trace(rays, sums=sums, keep_order=keep)
+        g = torch.zeros(len(sc.params), dtype=torch.float64, device="cuda")
+        dev.backward(rays, sums, cot, g)
+        torch.cuda.synchronize()
+        out.append(g.cpu().numpy())
+    assert np.allclose(out[1], out[0], rtol=1e-9, atol=1e-12 * np.abs(out[0]).max())
+    rec = oracle.trace(sc, r, log=True, wavelengths=True)
+    ref = oracle.gradient_rms(sc, r, rec, w)
+    e = check(out[1], ref, floor, sc.param_names)
+    print(f"lens spectrum fp{precision}: {len(sc.params)} params, worst rel {e:.2e}")

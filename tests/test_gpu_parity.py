@@ -297,3 +297,51 @@ def test_group_sums_match_records(rb):
         rms = np.sqrt(np.mean((x[f] - cx) ** 2 + (y[f] - cy) ** 2))
         assert fig[k, 4] == pytest.approx(rms, rel=1e-9)
         assert fig[k, 5] == pytest.approx(f.sum() / m.sum(), rel=1e-12)
+
+
+@pytest.mark.parametrize("name,precision,n_per", [("aspheric_lens", 32, 10000), ("aspheric_lens", 64, 3000),
+                                                  ("fresnel_lens", 32, 10000), ("fresnel_lens", 64, 3000)])
+def test_per_photon_wavelength_parity(rb, name, precision, n_per):
+    """A continuous spectrum in one bundle: each photon carries its own
+    wavelength (uniform over 300-600 nm) and the lenses refract it with
+    n(lambda) from their dispersion law (photon-by-photon against the oracle
+    tracing the same wavelengths; the FP32 bundles are large enough to be
+    binned)."""
+    import oracle
+    sc = scenes.ALL[name](precision=precision)
+    r = scenes.with_wavelengths(sc, sc.rays(n_per))
+    dev = rb.Scene(sc)
+    rays = dev.upload_rays(r, wavelengths=True)
+    n = len(r["ox"])
+    hits = dev.alloc_hits(n)
+    dev.trace(rays, hits=hits)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in hits.items()}
+    got["seq_hash"] = got["seq_hash"].view(np.uint64)
+    got["pos"] = np.stack([got["x"], got["y"], got["z"]], 1).astype(np.float64)
+    got["dir"] = np.stack([got["ux"], got["uy"], got["uz"]], 1).astype(np.float64)
+    ref = oracle.trace(sc, r, log=True, wavelengths=True)
+    tol = 1e-5 if precision == 32 else 1e-9
+    nbad, dp, dd, ng = compare(sc, r, got, ref, tol * sc.l_ref, tol)
+    # the wavelengths matter: the fixed-index trace differs
+    fixed = oracle.trace(sc, r)
+    assert (fixed["seq_hash"] != ref["seq_hash"]).mean() > 0.05 or np.abs(fixed["pos"] - ref["pos"]).max() > 1e-3
+    print(f"{name} fp{precision} spectrum: N={n} mismatches={nbad} max|dpos|={dp:.3e} max|ddir|={dd:.3e}")
+
+
+def test_wavelengths_rejected_where_unsupported(rb):
+    """Per-photon wavelengths in a scene with cones, or in a batch: EUNSUPPORTED."""
+    sc = scenes.hex_concentrator()
+    r = sc.rays(2)
+    dev = rb.Scene(sc)
+    rays = dev.upload_rays(r, wavelengths=True)
+    with pytest.raises(rb.RobastError) as ei:
+        dev.trace(rays, hits=dev.alloc_hits(len(r["ox"])))
+    assert ei.value.status == rb.EUNSUPPORTED
+    lens = scenes.aspheric_lens()
+    d2 = rb.Scene(lens)
+    r2 = lens.rays(100)
+    batch = rb.Batch([d2], [len(r2["ox"])])
+    with pytest.raises(rb.RobastError) as ei:
+        batch.trace(d2.upload_rays(r2, wavelengths=True), sums=batch.new_sums())
+    assert ei.value.status == rb.EUNSUPPORTED

@@ -504,6 +504,44 @@ def test_lens_paraxial_back_focus_is_the_thick_lens_value(orc, lam):
     assert abs(zs[0] - expect) > 1e-7          # the extrapolation is needed: aberration is resolved
 
 
+def test_per_photon_wavelength_back_focus(orc):
+    """One bundle, each photon with its own wavelength (300, 400, 600 nm) in
+    a singlet built for 500 nm (its fixed index is that of 500 nm): each
+    photon crosses the axis at the thick-lens back focus of its own index
+    n = A + B / lam^2, not of the scene's, and photons without wavelengths
+    use the fixed index."""
+    sc = scenes.aspheric_lens(precision=64, lam=500e-9)
+    T = sc.volumes["c"][0][2]
+    lams = (300e-9, 400e-9, 600e-9)
+    m = 16
+    zs = {l: [] for l in lams}
+    for h in (0.002, 0.004):
+        k = m * len(lams)
+        r = scenes.make_rays(64, np.full(k, h), np.zeros(k), np.full(k, 1.0), np.zeros(k), np.zeros(k),
+                             -np.ones(k), np.zeros(k))
+        r["lam"] = np.repeat(lams, m)
+        rec = orc.trace(sc, r, wavelengths=True)
+        for j, l in enumerate(lams):
+            sel = np.arange(j * m, (j + 1) * m)
+            ok = sel[(rec["fate"][sel] == scenes.FATE_FOCUSED) & (rec["n_events"][sel] == 3)]
+            assert len(ok) > 8
+            i = ok[0]
+            x, z = rec["pos"][i, 0], rec["pos"][i, 2]
+            zs[l].append(z - x * rec["dir"][i, 2] / rec["dir"][i, 0])
+    for l in lams:
+        n = 1.4720 + 3.2e-15 / l ** 2
+        expect = -(0.5 / (n - 1.0) - T / n)
+        assert abs((4 * zs[l][0] - zs[l][1]) / 3 - expect) < 1e-9, l
+    # without wavelengths every photon sees the scene's fixed (500 nm) index
+    r = scenes.make_rays(64, np.full(m, 0.002), np.zeros(m), np.full(m, 1.0), np.zeros(m), np.zeros(m),
+                         -np.ones(m), np.zeros(m))
+    r["lam"] = np.full(m, 300e-9)
+    a, b = orc.trace(sc, r), orc.trace(sc, r, wavelengths=True)
+    assert not np.allclose(a["pos"], b["pos"], atol=1e-6)
+    c = orc.trace(scenes.aspheric_lens(precision=64, lam=300e-9), r)
+    assert np.abs(c["pos"] - b["pos"]).max() < 1e-12
+
+
 def test_lens_spot_grows_away_from_the_design_wavelength(orc):
     """Longitudinal chromatic aberration of the singlet: the focal plane sits
     at the paraxial focus of 400 nm, and the index rises towards the blue, so
