@@ -316,9 +316,36 @@ int robast_set_tuning(robast_scene* scene, const robast_tuning* tuning);
 int robast_autotune(robast_scene* scene, const robast_rays* rays, int64_t n, robast_tuning* best,
                     void* hip_stream);
 
-/* Replace the differentiable parameters (host vector, n_params) and rebuild
- * the affected device records.  Synchronous. */
-int robast_update_params(robast_scene* scene, const double* params, int64_t n_params);
+/* Gradient-descent steps on the device (a design optimised as in §3):
+ * replace the differentiable parameters with d_params [device, n_params
+ * doubles], in stream order, without the host.  A kernel rebuilds every
+ * volume record (tilted frames, sphere curvature, asphere coefficients,
+ * cone control points, their bounds) and the candidate groups' slabs into
+ * the scene's second table slot and then switches the scene's device view
+ * to it, so launches queued after it on the stream (and replays of a HIP
+ * graph that captured it) trace the new geometry, while kernels still
+ * running on the old slot are never given half-written tables.  The
+ * candidate grid is kept: the update is applied only if no surface moves,
+ * across its group's grid, by more than a quarter of the sampling step the
+ * grid was built with (ample for optimisation steps; large changes need
+ * robast_set_params).  *d_status [device, may be NULL] becomes 0 when the
+ * update is applied, ROBAST_EINVAL when the new parameters make a surface
+ * invalid (non-finite value, a sphere whose aperture reaches its equator,
+ * a non-positive cone radius), ROBAST_EUNSUPPORTED when a surface would
+ * leave its grid cells; in both cases the scene keeps its previous tables.
+ * Updates on one scene must not overlap in time with other calls on it from
+ * another stream.  Drops the kept binned order and path records.  EINVAL on
+ * NULL scene or d_params (host-side, nothing launched). */
+int robast_update_params(robast_scene* scene, const double* d_params, int32_t* d_status, void* hip_stream);
+
+/* Replace the differentiable parameters from the host [host, n_params] and
+ * rebuild the scene's tables on the host, grid included (any change).  The
+ * new geometry is checked first (the checks of robast_build_scene): EINVAL
+ * and nothing changed on failure; EMISMATCH when n_params differs from the
+ * build.  Synchronous: waits for the device to be idle before it rewrites
+ * the tables.  The tables may grow: re-capture HIP graphs that launch on the
+ * scene after this call. */
+int robast_set_params(robast_scene* scene, const double* params, int64_t n_params);
 
 void robast_destroy_scene(robast_scene* scene);
 
@@ -372,6 +399,13 @@ int robast_figures_batch(robast_batch* batch, const double* d_group_sums, double
  * (+=).  EUNSUPPORTED when a variant has max_events > 32. */
 int robast_trace_backward_batch(robast_batch* batch, const robast_rays* rays, const double* d_group_sums,
                                 const double* d_cot, double* d_grad, void* hip_stream);
+
+/* robast_update_params for every variant of the batch in one launch (one
+ * workgroup per variant): d_params [device] the concatenated parameters,
+ * d_status [device, n_scenes int32, may be NULL] one status per variant as
+ * for robast_update_params.  Graph-capturable.  EUNSUPPORTED when a scene
+ * appears more than once in the batch. */
+int robast_update_params_batch(robast_batch* batch, const double* d_params, int32_t* d_status, void* hip_stream);
 
 /* Totals of the concatenated layouts: photons, groups, parameters. */
 int robast_batch_sizes(const robast_batch* batch, int64_t* n_photons, int64_t* n_groups, int64_t* n_params);

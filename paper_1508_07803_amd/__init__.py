@@ -31,7 +31,7 @@ SYMBOLS = ["robast_build_scene", "robast_trace", "robast_figures", "robast_trace
            "robast_last_error", "robast_abi_version", "robast_build_batch", "robast_trace_batch",
            "robast_figures_batch", "robast_trace_backward_batch", "robast_batch_sizes", "robast_destroy_batch",
            "robast_get_tuning", "robast_set_tuning", "robast_autotune", "robast_bin_photons",
-           "robast_arrival_figures", "robast_trace_static"]
+           "robast_arrival_figures", "robast_trace_static", "robast_set_params", "robast_update_params_batch"]
 
 
 class VolumeDesc(ctypes.Structure):
@@ -83,7 +83,9 @@ _lib.robast_figures.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_
 _lib.robast_trace_backward.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ctypes.c_int64, ctypes.POINTER(Hits),
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
                                        ctypes.c_void_p]
-_lib.robast_update_params.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+_lib.robast_update_params.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+_lib.robast_set_params.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+_lib.robast_update_params_batch.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
 _lib.robast_destroy_scene.argtypes = [ctypes.c_void_p]
 _lib.robast_destroy_scene.restype = None
 _lib.robast_status_string.argtypes = [ctypes.c_int]
@@ -110,7 +112,7 @@ for _name in ("robast_build_scene", "robast_trace", "robast_figures", "robast_tr
               "robast_update_params", "robast_abi_version", "robast_build_batch", "robast_trace_batch",
               "robast_figures_batch", "robast_trace_backward_batch", "robast_batch_sizes", "robast_get_tuning",
               "robast_set_tuning", "robast_autotune", "robast_bin_photons", "robast_arrival_figures",
-              "robast_trace_static"):
+              "robast_trace_static", "robast_set_params", "robast_update_params_batch"):
     getattr(_lib, _name).restype = ctypes.c_int
 
 
@@ -391,10 +393,25 @@ class Scene:
         return t.as_dict()
 
     def update_params(self, params):
+        """New parameters from the host: robast_set_params (checked first,
+        tables rebuilt on the host, synchronous)."""
         P = np.ascontiguousarray(params, dtype=np.float64)
-        _check(_lib.robast_update_params(self._h, P.ctypes.data if len(P) else None, len(P)),
-               "robast_update_params")
+        _check(_lib.robast_set_params(self._h, P.ctypes.data if len(P) else None, len(P)),
+               "robast_set_params")
         self.params = P.copy()
+
+    def update_params_device(self, params, status=None, stream=None):
+        """New parameters already on the device (float64 tensor of n_params):
+        robast_update_params, in stream order (graph-capturable).  status: an
+        int32 device tensor that receives 0 or the rejection code.  The
+        host copy self.params no longer describes the scene afterwards."""
+        import torch
+        _check_extents(0, None, f64=[("params", params, self.n_params)])
+        if status is not None and (status.dtype != torch.int32 or status.numel() < 1):
+            raise ValueError("status must hold an int32")
+        _check(_lib.robast_update_params(self._h, _ptr(params), _ptr(status), _stream(stream)),
+               "robast_update_params")
+        self.params = None
 
 
 class Batch:
@@ -468,6 +485,18 @@ class Batch:
                                      ("fig", fig, self.n_groups * FIGURE_STRIDE)])
         _check(_lib.robast_figures_batch(self._h, _ptr(sums), _ptr(fig), _stream(stream)), "robast_figures_batch")
         return fig.view(self.n_groups, FIGURE_STRIDE)
+
+    def update_params(self, params, status=None, stream=None):
+        """robast_update_params_batch: every variant's parameters from the
+        concatenated float64 device tensor (status: int32 per variant)."""
+        import torch
+        _check_extents(0, None, f64=[("params", params, self.n_params)])
+        if status is not None and (status.dtype != torch.int32 or status.numel() < len(self.scenes)):
+            raise ValueError("status must hold one int32 per variant")
+        _check(_lib.robast_update_params_batch(self._h, _ptr(params), _ptr(status), _stream(stream)),
+               "robast_update_params_batch")
+        for s in self.scenes:
+            s.params = None
 
     def backward(self, rays, sums, cot, grad, id_base=0, stream=None):
         self._check_sizes(rays, None, sums, grad, cot)

@@ -20,6 +20,7 @@
 #include "binning.hpp"
 #include "kernels.hpp"
 #include "scene_layout.hpp"
+#include "update.hpp"
 
 using namespace robast;
 
@@ -124,6 +125,62 @@ double outline_rmax(const robast_volume_desc& v) {
 }
 
 // ------------------------------------------------------------------ validation
+// Checks of one volume descriptor (shape, outline, role, sizes, the
+// geometry its parameters give, parameter indices).
+int validate_volume(const robast_volume_desc& v, int i, int64_t n_params) {
+  std::string at = " (volume " + std::to_string(i) + ")";
+  if (v.role < ROBAST_MIRROR || v.role > ROBAST_OBSCURATION) return fail(ROBAST_EINVAL, "unknown role" + at);
+  if (v.shape < ROBAST_PLANE || v.shape > ROBAST_HEXCONE) return fail(ROBAST_EINVAL, "unknown shape" + at);
+  if (v.outline < 0 || v.outline > ROBAST_SECTOR) return fail(ROBAST_EINVAL, "unknown outline" + at);
+  if (!finite_all(v.Q, 9) || !finite_all(v.c, 3) || !finite_all(v.p, 16) || !finite_all(v.o, 4) ||
+      !std::isfinite(v.reflectivity) || !std::isfinite(v.n_inside) || !finite_all(v.Q0, 9) ||
+      !finite_all(v.c0, 3) || !finite_all(v.pivot, 3) || !finite_all(v.e1, 3) || !finite_all(v.e2, 3))
+    return fail(ROBAST_EINVAL, "non-finite descriptor value" + at);
+  double I[9];
+  if (!inv3(v.Q, I)) return fail(ROBAST_EINVAL, "singular frame Q" + at);
+  bool sagged = v.shape == ROBAST_PLANE || v.shape == ROBAST_SPHERE || v.shape == ROBAST_ASPHERE;
+  if (sagged) {
+    if (v.outline == ROBAST_OUTLINE_NONE) return fail(ROBAST_EINVAL, "sag surface needs an outline" + at);
+    const double* o = v.o;
+    bool ok = true;
+    switch (v.outline) {
+      case ROBAST_DISC: ok = o[0] > 0; break;
+      case ROBAST_ANNULUS: ok = o[0] >= 0 && o[1] > o[0]; break;
+      case ROBAST_RECT: ok = o[0] > 0 && o[1] > 0; break;
+      case ROBAST_HEX: ok = o[0] > 0; break;
+      case ROBAST_SECTOR: ok = o[0] >= 0 && o[1] > o[0] && o[3] > o[2] && o[3] - o[2] <= 2 * M_PI + 1e-12; break;
+    }
+    if (!ok) return fail(ROBAST_EINVAL, "degenerate outline" + at);
+  }
+  if (v.shape == ROBAST_SPHERE && std::fabs(v.p[0]) * outline_rmax(v) >= 1.0)
+    return fail(ROBAST_EINVAL, "sphere aperture reaches its equator" + at);
+  if (v.shape == ROBAST_ASPHERE && !(v.p[0] > 0)) return fail(ROBAST_EINVAL, "asphere rn must be > 0" + at);
+  if (v.shape == ROBAST_CYLINDER && !(v.p[0] > 0 && v.p[1] > 0)) return fail(ROBAST_EINVAL, "cylinder size" + at);
+  if (v.shape == ROBAST_BOX && !(v.p[0] > 0 && v.p[1] > 0 && v.p[2] > 0)) return fail(ROBAST_EINVAL, "box size" + at);
+  if (v.shape == ROBAST_HEXCONE) {
+    for (int k = 0; k < 4; ++k)
+      if (!(v.p[2 * k] > 0)) return fail(ROBAST_EINVAL, "cone profile radius must be > 0" + at);
+  }
+  if (v.role == ROBAST_MIRROR && !(v.reflectivity >= 0.0 && v.reflectivity <= 1.0))
+    return fail(ROBAST_EINVAL, "reflectivity outside [0, 1]" + at);
+  if (v.role == ROBAST_LENS && !(v.n_inside > 0.0)) return fail(ROBAST_EINVAL, "lens index must be > 0" + at);
+  if (v.role == ROBAST_LENS && !(v.p[15] >= 0.0 && std::isfinite(v.p[15])))
+    return fail(ROBAST_EINVAL, "lens absorption length p[15] must be finite and >= 0" + at);
+  if (v.role == ROBAST_LENS && v.p[14] != 0.0 && !(v.p[13] > 0.0 && v.p[14] > 0.0))
+    return fail(ROBAST_EINVAL, "lens dispersion law needs A = p[13] > 0 and B = p[14] > 0" + at);
+  if (v.role == ROBAST_LENS && v.p[14] != 0.0 && v.shape == ROBAST_HEXCONE)
+    return fail(ROBAST_EUNSUPPORTED, "dispersive lens faces must not be cones" + at);
+  if (v.role == ROBAST_LENS && v.shape != ROBAST_BOX && v.shape != ROBAST_PLANE && v.shape != ROBAST_SPHERE &&
+      v.shape != ROBAST_ASPHERE)
+    return fail(ROBAST_EUNSUPPORTED, "lens faces must be planes, spheres, aspheres or boxes" + at);
+  int ns = v.shape == ROBAST_SPHERE ? 1 : v.shape == ROBAST_ASPHERE ? 8 : v.shape == ROBAST_HEXCONE ? 4 : 0;
+  if (v.shape_param >= 0 && (ns == 0 || v.shape_param + ns > n_params))
+    return fail(ROBAST_EINVAL, "shape_param out of range" + at);
+  if (v.tilt_param >= 0 && v.tilt_param + 2 > n_params) return fail(ROBAST_EINVAL, "tilt_param out of range" + at);
+  if (v.shape_param < -1 || v.tilt_param < -1) return fail(ROBAST_EINVAL, "negative parameter index" + at);
+  return ROBAST_OK;
+}
+
 int validate(const robast_scene_desc* d, const double* params, int64_t n_params) {
   if (!d) return fail(ROBAST_EINVAL, "desc is NULL");
   if (d->n_volumes < 0 || d->n_volumes > 65535) return fail(ROBAST_EINVAL, "n_volumes out of range 0..65535");
@@ -135,57 +192,8 @@ int validate(const robast_scene_desc* d, const double* params, int64_t n_params)
   if (n_params < 0 || (n_params > 0 && !params)) return fail(ROBAST_EINVAL, "params NULL or n_params < 0");
   if (n_params > 0 && !finite_all(params, (int)n_params)) return fail(ROBAST_EINVAL, "non-finite parameter");
   for (int i = 0; i < d->n_volumes; ++i) {
-    const robast_volume_desc& v = d->volumes[i];
-    std::string at = " (volume " + std::to_string(i) + ")";
-    if (v.role < ROBAST_MIRROR || v.role > ROBAST_OBSCURATION) return fail(ROBAST_EINVAL, "unknown role" + at);
-    if (v.shape < ROBAST_PLANE || v.shape > ROBAST_HEXCONE) return fail(ROBAST_EINVAL, "unknown shape" + at);
-    if (v.outline < 0 || v.outline > ROBAST_SECTOR) return fail(ROBAST_EINVAL, "unknown outline" + at);
-    if (!finite_all(v.Q, 9) || !finite_all(v.c, 3) || !finite_all(v.p, 16) || !finite_all(v.o, 4) ||
-        !std::isfinite(v.reflectivity) || !std::isfinite(v.n_inside) || !finite_all(v.Q0, 9) ||
-        !finite_all(v.c0, 3) || !finite_all(v.pivot, 3) || !finite_all(v.e1, 3) || !finite_all(v.e2, 3))
-      return fail(ROBAST_EINVAL, "non-finite descriptor value" + at);
-    double I[9];
-    if (!inv3(v.Q, I)) return fail(ROBAST_EINVAL, "singular frame Q" + at);
-    bool sagged = v.shape == ROBAST_PLANE || v.shape == ROBAST_SPHERE || v.shape == ROBAST_ASPHERE;
-    if (sagged) {
-      if (v.outline == ROBAST_OUTLINE_NONE) return fail(ROBAST_EINVAL, "sag surface needs an outline" + at);
-      const double* o = v.o;
-      bool ok = true;
-      switch (v.outline) {
-        case ROBAST_DISC: ok = o[0] > 0; break;
-        case ROBAST_ANNULUS: ok = o[0] >= 0 && o[1] > o[0]; break;
-        case ROBAST_RECT: ok = o[0] > 0 && o[1] > 0; break;
-        case ROBAST_HEX: ok = o[0] > 0; break;
-        case ROBAST_SECTOR: ok = o[0] >= 0 && o[1] > o[0] && o[3] > o[2] && o[3] - o[2] <= 2 * M_PI + 1e-12; break;
-      }
-      if (!ok) return fail(ROBAST_EINVAL, "degenerate outline" + at);
-    }
-    if (v.shape == ROBAST_SPHERE && std::fabs(v.p[0]) * outline_rmax(v) >= 1.0)
-      return fail(ROBAST_EINVAL, "sphere aperture reaches its equator" + at);
-    if (v.shape == ROBAST_ASPHERE && !(v.p[0] > 0)) return fail(ROBAST_EINVAL, "asphere rn must be > 0" + at);
-    if (v.shape == ROBAST_CYLINDER && !(v.p[0] > 0 && v.p[1] > 0)) return fail(ROBAST_EINVAL, "cylinder size" + at);
-    if (v.shape == ROBAST_BOX && !(v.p[0] > 0 && v.p[1] > 0 && v.p[2] > 0)) return fail(ROBAST_EINVAL, "box size" + at);
-    if (v.shape == ROBAST_HEXCONE) {
-      for (int k = 0; k < 4; ++k)
-        if (!(v.p[2 * k] > 0)) return fail(ROBAST_EINVAL, "cone profile radius must be > 0" + at);
-    }
-    if (v.role == ROBAST_MIRROR && !(v.reflectivity >= 0.0 && v.reflectivity <= 1.0))
-      return fail(ROBAST_EINVAL, "reflectivity outside [0, 1]" + at);
-    if (v.role == ROBAST_LENS && !(v.n_inside > 0.0)) return fail(ROBAST_EINVAL, "lens index must be > 0" + at);
-    if (v.role == ROBAST_LENS && !(v.p[15] >= 0.0 && std::isfinite(v.p[15])))
-      return fail(ROBAST_EINVAL, "lens absorption length p[15] must be finite and >= 0" + at);
-    if (v.role == ROBAST_LENS && v.p[14] != 0.0 && !(v.p[13] > 0.0 && v.p[14] > 0.0))
-      return fail(ROBAST_EINVAL, "lens dispersion law needs A = p[13] > 0 and B = p[14] > 0" + at);
-    if (v.role == ROBAST_LENS && v.p[14] != 0.0 && v.shape == ROBAST_HEXCONE)
-      return fail(ROBAST_EUNSUPPORTED, "dispersive lens faces must not be cones" + at);
-    if (v.role == ROBAST_LENS && v.shape != ROBAST_BOX && v.shape != ROBAST_PLANE && v.shape != ROBAST_SPHERE &&
-        v.shape != ROBAST_ASPHERE)
-      return fail(ROBAST_EUNSUPPORTED, "lens faces must be planes, spheres, aspheres or boxes" + at);
-    int ns = v.shape == ROBAST_SPHERE ? 1 : v.shape == ROBAST_ASPHERE ? 8 : v.shape == ROBAST_HEXCONE ? 4 : 0;
-    if (v.shape_param >= 0 && (ns == 0 || v.shape_param + ns > n_params))
-      return fail(ROBAST_EINVAL, "shape_param out of range" + at);
-    if (v.tilt_param >= 0 && v.tilt_param + 2 > n_params) return fail(ROBAST_EINVAL, "tilt_param out of range" + at);
-    if (v.shape_param < -1 || v.tilt_param < -1) return fail(ROBAST_EINVAL, "negative parameter index" + at);
+    int rc = validate_volume(d->volumes[i], i, n_params);
+    if (rc) return rc;
   }
   return ROBAST_OK;
 }
@@ -197,13 +205,24 @@ struct robast_scene {
   uint64_t seed = 0;
   double l_ref = 1.0;
   std::vector<robast_volume_desc> desc;
-  std::vector<double> params;
-  void* d_blob = nullptr;
-  size_t blob_bytes = 0;
-  DTilt* d_tilt = nullptr;
+  std::vector<double> params;  // parameters of the last host build (device updates leave them)
+  void* d_blob = nullptr;      // two table slots of slot_cap bytes; the view points at the live one
+  size_t blob_bytes = 0, slot_cap = 0;
+  DTilt* d_tilt = nullptr;     // two tilt-table slots of n_vol records
   double* d_coef = nullptr;    // n_groups * 4 backward coefficients
   int cell_choice = 0;         // index into kCellFactors chosen by the last upload
-  void* d_view = nullptr;      // device copy of sf / sd, read by batched launches
+  void* d_view = nullptr;      // the live view (sf / sd with device pointers), read by every kernel
+  // device parameter updates: per-volume and per-group tables of the last
+  // host build (UpdVol[n_vol] | UpdGroup[n_grp] | members | z-range scratch),
+  // the job record and a one-entry array pointing at it
+  void* d_upd = nullptr;
+  size_t upd_bytes = 0;
+  void* d_job = nullptr;
+  void* d_jobptr = nullptr;
+  std::vector<int> upd_group;          // filled by the scene compiler
+  std::vector<double> upd_gpad;
+  std::vector<UpdGroup> upd_groups;
+  std::vector<uint16_t> upd_members;
   void* d_check = nullptr;     // sequence-check counter of the backward debug mode
   SceneView<float> sf{};
   SceneView<double> sd{};
@@ -255,6 +274,10 @@ struct robast_batch {
   uint32_t* d_path = nullptr;
   bool path_ok = false;
   robast_rays path_rays{};
+  // parameter updates of the variants: their update jobs and parameter offsets
+  void* d_jobs = nullptr;          // n_scenes job pointers
+  int64_t* d_poff = nullptr;       // n_scenes offsets into the concatenated parameters
+  bool repeated = false;           // a scene appears more than once
 };
 
 namespace {
@@ -508,8 +531,10 @@ struct GroupBuild {
   double Q[9], c[3];
   std::vector<int> members;
   double zmin = 1e300, zmax = -1e300, x0 = 1e300, y0 = 1e300, x1 = -1e300, y1 = -1e300, cell = 1.0;
+  double zpad = 0.0;          // padding of the z-slab
   int nx = 0, ny = 0;
   std::vector<std::vector<uint16_t>> cells;
+  std::vector<double> step;   // surface sampling step of each member's rasterisation
 };
 
 void to_group(const GroupBuild& g, const double* w, double* x) {
@@ -611,6 +636,7 @@ void build_groups(const robast_scene& s, const std::vector<Box3>& wb, std::vecto
       areas.push_back(std::max((mx1 - mx0) * (my1 - my0), 1e-30));
     }
     double zp = 1e-5 * (g.zmax - g.zmin + s.l_ref);
+    g.zpad = zp;
     g.zmin -= zp; g.zmax += zp;
     double xp = 1e-5 * (g.x1 - g.x0 + g.y1 - g.y0 + s.l_ref);
     g.x0 -= xp; g.y0 -= xp; g.x1 += xp; g.y1 += xp;
@@ -635,6 +661,7 @@ void build_groups(const robast_scene& s, const std::vector<Box3>& wb, std::vecto
       Box3 lb = local_bounds(s.desc[m], slope);
       double ext = std::max(std::max(lb.hi[0] - lb.lo[0], lb.hi[1] - lb.lo[1]), lb.hi[2] - lb.lo[2]);
       double h = std::max(g.cell / 6.0, ext / 256.0);
+      g.step.push_back(h);
       pts.clear();
       surface_samples(s.desc[m], h, pts);
       double pad = h + 1e-5 * s.l_ref;
@@ -689,6 +716,30 @@ void compile_blob(robast_scene& s, std::vector<char>& blob, SceneView<T>& V, std
   std::vector<uint16_t> always;
   std::vector<GroupBuild> groups;
   build_groups(s, wb, always, groups, cell_factor);
+  // what device parameter updates need of the groups: frames, slab padding,
+  // members, and how far a member's surface may move across its group before
+  // it could leave the cells it is listed in (samples every h, each padded by
+  // h + 1e-5 L_ref: a quarter of h is covered)
+  s.upd_group.assign(nv, -1);
+  s.upd_gpad.assign(nv, -1.0);
+  s.upd_groups.clear();
+  s.upd_members.clear();
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const GroupBuild& g = groups[gi];
+    UpdGroup ug{};
+    std::memcpy(ug.Q, g.Q, sizeof ug.Q);
+    std::memcpy(ug.c, g.c, sizeof ug.c);
+    ug.zpad = g.zpad;
+    ug.first = (int32_t)s.upd_members.size();
+    ug.count = (int32_t)g.members.size();
+    for (size_t k = 0; k < g.members.size(); ++k) {
+      const int m = g.members[k];
+      s.upd_members.push_back((uint16_t)m);
+      s.upd_group[m] = (int)gi;
+      s.upd_gpad[m] = 0.25 * g.step[k];
+    }
+    s.upd_groups.push_back(ug);
+  }
   std::vector<GroupRec<T>> grecs(groups.size());
   std::vector<uint32_t> starts;
   std::vector<uint16_t> items;
@@ -779,6 +830,59 @@ std::vector<DTilt> tilt_table(const robast_scene& s) {
 // trace 21.7 ms at 0.5, 19.0 ms at 0.14); the coarsest is used when none fits.
 constexpr double kCellFactors[] = {0.14, 0.18, 0.25, 0.35, 0.5};
 
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// The device tables of a volume for parameter updates (its descriptor with
+// the current parameters applied).
+UpdVol upd_vol(const robast_scene& s, int i) {
+  const robast_volume_desc& v = s.desc[i];
+  UpdVol u{};
+  std::memcpy(u.Q, v.Q, sizeof u.Q);
+  std::memcpy(u.c, v.c, sizeof u.c);
+  std::memcpy(u.Q0, v.Q0, sizeof u.Q0);
+  std::memcpy(u.c0, v.c0, sizeof u.c0);
+  std::memcpy(u.pivot, v.pivot, sizeof u.pivot);
+  std::memcpy(u.e1, v.e1, sizeof u.e1);
+  std::memcpy(u.e2, v.e2, sizeof u.e2);
+  std::memcpy(u.p, v.p, sizeof u.p);
+  double slope;
+  const Box3 lb = local_bounds(v, slope);
+  for (int k = 0; k < 3; ++k) { u.lb_lo[k] = lb.lo[k]; u.lb_hi[k] = lb.hi[k]; }
+  u.rmin = outline_rmin(v);
+  u.rmax = outline_rmax(v);
+  u.gpad = s.upd_gpad.empty() ? -1.0 : s.upd_gpad[i];
+  u.shape = v.shape; u.outline = v.outline; u.sparam = v.shape_param; u.tparam = v.tilt_param;
+  u.group = s.upd_group.empty() ? -1 : s.upd_group[i];
+  u.role = v.role;
+  return u;
+}
+
+template <typename T> int set_job(robast_scene* s, const SceneView<T>& V) {
+  char* base = (char*)s->d_upd;
+  const size_t ov = 0, og = align256(sizeof(UpdVol) * s->n_vol), om = og + align256(sizeof(UpdGroup) * V.n_grp),
+               oz = om + align256(sizeof(uint16_t) * s->upd_members.size());
+  UpdJob<T> j{};
+  j.view = (SceneView<T>*)s->d_view;
+  j.slot[0] = (char*)s->d_blob;
+  j.slot[1] = (char*)s->d_blob + s->slot_cap;
+  j.tilt[0] = s->d_tilt;
+  j.tilt[1] = s->d_tilt + std::max(1, s->n_vol);
+  j.vols = (const UpdVol*)(base + ov);
+  j.groups = (const UpdGroup*)(base + og);
+  j.members = (const uint16_t*)(base + om);
+  j.zr = (double*)(base + oz);
+  j.n_vol = s->n_vol;
+  j.n_grp = V.n_grp;
+  j.blob_bytes = (uint32_t)s->blob_bytes;
+  j.l_ref = s->l_ref;
+  hipError_t e = hipMemcpy(s->d_job, &j, sizeof j, hipMemcpyHostToDevice);
+  return e == hipSuccess ? ROBAST_OK : hip_fail(e, "hipMemcpy update job");
+}
+
+// Host build of the scene's device tables (a new scene, or new parameters
+// by robast_set_params): compile, then write slot 0, the tilt table, the
+// view and the tables of device updates.  Called with no kernel of the
+// scene in flight (robast_set_params synchronises the device first).
 int upload(robast_scene* s) {
   std::vector<char> blob;
   std::vector<size_t> offs;
@@ -796,17 +900,22 @@ int upload(robast_scene* s) {
     if (blob.size() <= budget) break;
   }
   std::vector<DTilt> tilt = tilt_table(*s);
-  if (blob.size() > s->blob_bytes || !s->d_blob) {
+  const size_t need = align256(std::max<size_t>(blob.size(), 16));
+  hipError_t e = hipSuccess;
+  if (need > s->slot_cap || !s->d_blob) {
     if (s->d_blob) (void)hipFree(s->d_blob);
     s->d_blob = nullptr;
-    hipError_t e = hipMalloc(&s->d_blob, std::max<size_t>(blob.size(), 16));
+    s->slot_cap = 0;
+    e = hipMalloc(&s->d_blob, 2 * need);
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(ROBAST_ENOMEM, "hipMalloc blob") : hip_fail(e, "hipMalloc blob");
+    s->slot_cap = need;
   }
   s->blob_bytes = blob.size();
-  hipError_t e = hipMemcpy(s->d_blob, blob.data(), blob.size(), hipMemcpyHostToDevice);
+  e = hipMemcpy(s->d_blob, blob.data(), blob.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy blob");
+  const int nt = std::max(1, s->n_vol);
   if (!s->d_tilt) {
-    e = hipMalloc(&s->d_tilt, sizeof(DTilt) * std::max(1, s->n_vol));
+    e = hipMalloc(&s->d_tilt, 2 * sizeof(DTilt) * nt);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc tilt");
   }
   if (s->n_vol) {
@@ -817,16 +926,51 @@ int upload(robast_scene* s) {
     e = hipMalloc(&s->d_coef, sizeof(double) * 4 * s->n_groups);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc coef");
   }
-  if (s->precision == 32) rebase(s->sf, offs, (const char*)s->d_blob);
-  else rebase(s->sd, offs, (const char*)s->d_blob);
   if (!s->d_view) {
     e = hipMalloc(&s->d_view, sizeof(SceneView<double>));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc view");
   }
-  if (s->precision == 32) e = hipMemcpy(s->d_view, &s->sf, sizeof(SceneView<float>), hipMemcpyHostToDevice);
-  else e = hipMemcpy(s->d_view, &s->sd, sizeof(SceneView<double>), hipMemcpyHostToDevice);
+  if (s->precision == 32) {
+    rebase(s->sf, offs, (const char*)s->d_blob);
+    s->sf.self = (const SceneView<float>*)s->d_view;
+    s->sf.tilt = s->d_tilt;
+    e = hipMemcpy(s->d_view, &s->sf, sizeof(SceneView<float>), hipMemcpyHostToDevice);
+  } else {
+    rebase(s->sd, offs, (const char*)s->d_blob);
+    s->sd.self = (const SceneView<double>*)s->d_view;
+    s->sd.tilt = s->d_tilt;
+    e = hipMemcpy(s->d_view, &s->sd, sizeof(SceneView<double>), hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy view");
-  return ROBAST_OK;
+  // tables of device parameter updates
+  const int n_grp = (int)s->upd_groups.size();
+  std::vector<char> upd(align256(sizeof(UpdVol) * s->n_vol) + align256(sizeof(UpdGroup) * n_grp) +
+                        align256(sizeof(uint16_t) * s->upd_members.size()) + align256(sizeof(double) * 2 * nt));
+  for (int i = 0; i < s->n_vol; ++i) {
+    const UpdVol u = upd_vol(*s, i);
+    std::memcpy(upd.data() + sizeof(UpdVol) * i, &u, sizeof u);
+  }
+  const size_t og = align256(sizeof(UpdVol) * s->n_vol), om = og + align256(sizeof(UpdGroup) * n_grp);
+  if (n_grp) std::memcpy(upd.data() + og, s->upd_groups.data(), sizeof(UpdGroup) * n_grp);
+  if (!s->upd_members.empty())
+    std::memcpy(upd.data() + om, s->upd_members.data(), sizeof(uint16_t) * s->upd_members.size());
+  if (upd.size() > s->upd_bytes || !s->d_upd) {
+    if (s->d_upd) (void)hipFree(s->d_upd);
+    s->d_upd = nullptr;
+    s->upd_bytes = 0;
+    e = hipMalloc(&s->d_upd, std::max<size_t>(upd.size(), 256));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc update tables");
+    s->upd_bytes = upd.size();
+  }
+  e = hipMemcpy(s->d_upd, upd.data(), upd.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy update tables");
+  if (!s->d_job) {
+    e = hipMalloc(&s->d_job, std::max(sizeof(UpdJob<float>), sizeof(UpdJob<double>)));
+    if (e == hipSuccess) e = hipMalloc(&s->d_jobptr, sizeof(void*));
+    if (e == hipSuccess) e = hipMemcpy(s->d_jobptr, &s->d_job, sizeof(void*), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc update job");
+  }
+  return s->precision == 32 ? set_job<float>(s, s->sf) : set_job<double>(s, s->sd);
 }
 
 template <typename T> RaysView<T> rays_view(const robast_rays* r) {
@@ -875,7 +1019,7 @@ template <typename T> std::vector<BatchVariant<T>> variant_table(const robast_ba
   int64_t goff = 0, poff = 0;
   for (size_t v = 0; v < b.scenes.size(); ++v) {
     const robast_scene* s = b.scenes[v];
-    t[v] = BatchVariant<T>{(const SceneView<T>*)s->d_view, s->d_tilt, offsets[v], (int32_t)goff, (int32_t)poff,
+    t[v] = BatchVariant<T>{(const SceneView<T>*)s->d_view, offsets[v], (int32_t)goff, (int32_t)poff,
                            (int32_t)s->params.size(), 0};
     goff += s->n_groups;
     poff += (int64_t)s->params.size();
@@ -891,7 +1035,6 @@ int tuning_valid(const robast_tuning& t) {
   return t.bin_target >= 1 && t.bin_target <= 65536 && t.waves_mult >= 1 && t.waves_mult <= 64;
 }
 
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // The view of the photons a launch reads: the caller's arrays, or their
 // binned copy (with the permutation back to the caller's order).
@@ -1079,6 +1222,8 @@ void free_batch(robast_batch* b) {
   if (b->d_geo) (void)hipFree(b->d_geo);
   if (b->d_work) (void)hipFree(b->d_work);
   if (b->d_path) (void)hipFree(b->d_path);
+  if (b->d_jobs) (void)hipFree(b->d_jobs);
+  if (b->d_poff) (void)hipFree(b->d_poff);
   delete b;
 }
 
@@ -1130,15 +1275,40 @@ int robast_build_scene(const robast_scene_desc* desc, const double* params, int6
   return ROBAST_OK;
 }
 
-int robast_update_params(robast_scene* s, const double* params, int64_t n_params) {
+int robast_set_params(robast_scene* s, const double* params, int64_t n_params) {
   if (!s || (!params && n_params > 0)) return fail(ROBAST_EINVAL, "NULL scene or params");
   if (n_params != (int64_t)s->params.size()) return fail(ROBAST_EMISMATCH, "parameter count differs from build");
   if (!finite_all(params, (int)n_params)) return fail(ROBAST_EINVAL, "non-finite parameter");
-  s->params.assign(params, params + n_params);
-  for (auto& v : s->desc) apply_params(v, s->params);
+  // the new geometry is checked before anything changes: on failure the
+  // scene keeps its parameters and tables
+  std::vector<double> P(params, params + n_params);
+  std::vector<robast_volume_desc> nd = s->desc;
+  for (auto& v : nd) apply_params(v, P);
+  for (int i = 0; i < (int)nd.size(); ++i) {
+    int rc = validate_volume(nd[i], i, n_params);
+    if (rc) return rc;
+  }
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize before a rebuild");
+  s->params.swap(P);
+  s->desc.swap(nd);
   s->kept = false;
   s->path_ok = false;
   return upload(s);
+}
+
+int robast_update_params(robast_scene* s, const double* d_params, int32_t* d_status, void* stream) {
+  if (!s || !d_params) return fail(ROBAST_EINVAL, "NULL scene or params");
+  s->kept = false;
+  s->path_ok = false;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = s->precision == 32
+                     ? launch_update_params<float>((const UpdJob<float>* const*)s->d_jobptr, 1, d_params, nullptr,
+                                                   d_status, st)
+                     : launch_update_params<double>((const UpdJob<double>* const*)s->d_jobptr, 1, d_params, nullptr,
+                                                    d_status, st);
+  if (e != hipSuccess) return hip_fail(e, "parameter update launch");
+  return ROBAST_OK;
 }
 
 void robast_destroy_scene(robast_scene* s) {
@@ -1150,6 +1320,9 @@ void robast_destroy_scene(robast_scene* s) {
   if (s->d_work) (void)hipFree(s->d_work);
   if (s->d_path) (void)hipFree(s->d_path);
   if (s->d_check) (void)hipFree(s->d_check);
+  if (s->d_upd) (void)hipFree(s->d_upd);
+  if (s->d_job) (void)hipFree(s->d_job);
+  if (s->d_jobptr) (void)hipFree(s->d_jobptr);
   delete s;
 }
 
@@ -1405,6 +1578,22 @@ int robast_build_batch(robast_scene* const* scenes, int32_t n_scenes, const int6
     auto t = variant_table<float>(*b, offsets);
     e = hipMemcpy(b->d_vars, t.data(), vbytes * n_scenes, hipMemcpyHostToDevice);
   }
+  // the variants' update jobs and parameter offsets (for robast_update_params_batch)
+  if (e == hipSuccess) {
+    std::vector<void*> jobs(n_scenes);
+    std::vector<int64_t> poff(n_scenes);
+    int64_t acc = 0;
+    for (int v = 0; v < n_scenes; ++v) {
+      jobs[v] = scenes[v]->d_job;
+      poff[v] = acc;
+      acc += (int64_t)scenes[v]->params.size();
+      for (int u = 0; u < v; ++u) b->repeated = b->repeated || scenes[u] == scenes[v];
+    }
+    e = hipMalloc(&b->d_jobs, sizeof(void*) * n_scenes);
+    if (e == hipSuccess) e = hipMalloc(&b->d_poff, sizeof(int64_t) * n_scenes);
+    if (e == hipSuccess) e = hipMemcpy(b->d_jobs, jobs.data(), sizeof(void*) * n_scenes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->d_poff, poff.data(), sizeof(int64_t) * n_scenes, hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess && !items.empty())
     e = hipMemcpy(b->d_items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
@@ -1500,6 +1689,20 @@ int robast_trace_backward_batch(robast_batch* b, const robast_rays* rays, const 
   b->path_ok = false;
   e = launch_backward_batch(batch_view<float>(b), R, b->d_coef, grad, st, use_path ? b->d_path : nullptr);
   if (e != hipSuccess) return hip_fail(e, "batched backward launch");
+  return ROBAST_OK;
+}
+
+int robast_update_params_batch(robast_batch* b, const double* d_params, int32_t* d_status, void* stream) {
+  if (!b || !d_params) return fail(ROBAST_EINVAL, "NULL batch or params");
+  if (b->repeated) return fail(ROBAST_EUNSUPPORTED, "a scene appears more than once in the batch");
+  for (robast_scene* s : b->scenes) {
+    s->kept = false;
+    s->path_ok = false;
+  }
+  b->path_ok = false;
+  hipError_t e = launch_update_params<float>((const UpdJob<float>* const*)b->d_jobs, (int)b->scenes.size(), d_params,
+                                             b->d_poff, d_status, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "batched parameter update launch");
   return ROBAST_OK;
 }
 

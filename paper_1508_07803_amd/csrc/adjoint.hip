@@ -88,9 +88,11 @@ __device__ __forceinline__ void grad_end(const double* gacc, const GradLds& G, c
 template <typename T, int MAXE, bool USE_LDS, int SH>
 __global__ void __launch_bounds__(kBlockAdj)
 __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && MAXE <= 16) ? 3 : 1, 8)))
-k_backward(SceneView<T> S, RaysView<T> R, int64_t n, AdjView A, GradLds G, const uint32_t* list,
+k_backward(const SceneView<T>* Sp, RaysView<T> R, int64_t n, AdjView A, GradLds G, const uint32_t* list,
            const uint32_t* count) {
   extern __shared__ __align__(16) char lds[];
+  const SceneView<T> S = *Sp;
+  A.tilt = S.tilt;
   SceneView<T> L;
   stage_adj_scene<T, USE_LDS>(S, L, lds);
   double* gacc = reinterpret_cast<double*>(lds + (USE_LDS ? ((S.blob_bytes + 15u) & ~15u) : 0u));
@@ -125,8 +127,10 @@ __device__ __forceinline__ void wave_append(bool take, uint32_t i, uint32_t* lis
 template <typename T, bool USE_LDS, int SH>
 __global__ void __launch_bounds__(kBlockAdj)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1, 8)))
-k_backward_path(SceneView<T> S, RaysView<T> R, int64_t n, AdjView A, GradLds G, PathView P) {
+k_backward_path(const SceneView<T>* Sp, RaysView<T> R, int64_t n, AdjView A, GradLds G, PathView P) {
   extern __shared__ __align__(16) char lds[];
+  const SceneView<T> S = *Sp;
+  A.tilt = S.tilt;
   SceneView<T> L;
   stage_adj_scene<T, USE_LDS>(S, L, lds);
   double* gacc = reinterpret_cast<double*>(lds + (USE_LDS ? ((S.blob_bytes + 15u) & ~15u) : 0u));
@@ -149,8 +153,10 @@ k_backward_path(SceneView<T> S, RaysView<T> R, int64_t n, AdjView A, GradLds G, 
 template <typename T, bool USE_LDS, int SH>
 __global__ void __launch_bounds__(kBlockAdj)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1, 8)))
-k_backward_path4(SceneView<T> S, RaysView<T> R, AdjView A, GradLds G, PathView P) {
+k_backward_path4(const SceneView<T>* Sp, RaysView<T> R, AdjView A, GradLds G, PathView P) {
   extern __shared__ __align__(16) char lds[];
+  const SceneView<T> S = *Sp;
+  A.tilt = S.tilt;
   SceneView<T> L;
   stage_adj_scene<T, USE_LDS>(S, L, lds);
   double* gacc = reinterpret_cast<double*>(lds + (USE_LDS ? ((S.blob_bytes + 15u) & ~15u) : 0u));
@@ -215,18 +221,20 @@ static hipError_t launch_bwd_s(const SceneView<T>& S, const RaysView<T>& R, int6
     hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(64), 0, st, P->count, 2);
     e = grid_for(k_backward_path<T, USE_LDS, SH>, shmem, n, cfg, blocks);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_backward_path<T, USE_LDS, SH>), dim3(blocks), dim3(kBlockAdj), shmem, st, S, R, n, A, G, *P);
+    hipLaunchKernelGGL((k_backward_path<T, USE_LDS, SH>), dim3(blocks), dim3(kBlockAdj), shmem, st, S.self, R, n, A, G,
+                       *P);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = grid_for(k_backward_path4<T, USE_LDS, SH>, shmem, n, cfg, blocks);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_backward_path4<T, USE_LDS, SH>), dim3(blocks), dim3(kBlockAdj), shmem, st, S, R, A, G, *P);
+    hipLaunchKernelGGL((k_backward_path4<T, USE_LDS, SH>), dim3(blocks), dim3(kBlockAdj), shmem, st, S.self, R, A, G,
+                       *P);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   e = grid_for(k_backward<T, MAXE, USE_LDS, SH>, shmem, n, cfg, blocks);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_backward<T, MAXE, USE_LDS, SH>), dim3(blocks), dim3(kBlockAdj), shmem, st, S, R, n, A, G,
+  hipLaunchKernelGGL((k_backward<T, MAXE, USE_LDS, SH>), dim3(blocks), dim3(kBlockAdj), shmem, st, S.self, R, n, A, G,
                      P ? P->list : nullptr, P ? P->count : nullptr);
   return hipGetLastError();
 }

@@ -12,8 +12,7 @@ namespace robast {
 // scene's own device copy, so parameter updates of the scene (which rewrite
 // that copy) are seen by later launches, including graph replays.
 template <typename T> struct BatchVariant {
-  const SceneView<T>* S;   // device
-  const DTilt* tilt;       // device, n_vol entries
+  const SceneView<T>* S;   // device (its tilt table: S->tilt)
   int64_t off;             // first photon of the variant in the concatenated bundle
   int32_t goff;            // first group of the variant in the concatenated sums
   int32_t poff;            // first parameter of the variant in the concatenated gradient

@@ -97,7 +97,7 @@ k_backward_batch(const BatchVariant<float>* vars, const BatchItem* items, int n_
     } else if (USE_LDS) {
       stage_variant_view<float>(S, L, lds);   // tables already in LDS: rebuild the view only
     }
-    const AdjView A{coef + (int64_t)bv.goff * 4, grad + bv.poff, bv.tilt, bv.n_params};
+    const AdjView A{coef + (int64_t)bv.goff * 4, grad + bv.poff, S.tilt, bv.n_params};
     GradSink gs{grad_bytes ? gacc + (threadIdx.x & (gc.copies - 1)) * gc.pstride : grad + bv.poff};
     // the variant's photons, indexed and numbered from its first photon;
     // binned photons carry their index in the whole bundle

@@ -47,9 +47,10 @@ __device__ __forceinline__ void flush_lane(double* acc_lds, int g, const double*
 // SH: the shape set compiled in (kShapesNoCone for scenes without hex cones,
 // else kShapesAll).
 template <typename T, bool RECORD, bool SUMS, bool USE_LDS, int SH>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1, 8))) k_trace(SceneView<T> S, RaysView<T> R, int64_t n, HitsView<T> H,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1, 8))) k_trace(const SceneView<T>* Sp, RaysView<T> R, int64_t n, HitsView<T> H,
                                                   int sums_in_lds) {
   extern __shared__ __align__(16) char lds[];
+  const SceneView<T> S = *Sp;
   SceneView<T> L;
   stage_scene<T, USE_LDS>(S, L, lds);
   double* acc = reinterpret_cast<double*>(lds + (USE_LDS ? ((S.blob_bytes + 15u) & ~15u) : 0u));
@@ -256,7 +257,7 @@ static hipError_t launch_one_s(const SceneView<T>& S, const RaysView<T>& R, int6
   int64_t cap = (int64_t)ncu * per_cu * (cfg.waves_mult > 0 ? cfg.waves_mult : 1);
   if (cfg.max_blocks > 0) cap = std::min<int64_t>(cap, cfg.max_blocks);
   int blocks = (int)std::max<int64_t>(1, std::min(want, cap));
-  hipLaunchKernelGGL((k_trace<T, RECORD, SUMS, USE_LDS, SH>), dim3(blocks), dim3(kBlock), shmem, st, S, R, n, H,
+  hipLaunchKernelGGL((k_trace<T, RECORD, SUMS, USE_LDS, SH>), dim3(blocks), dim3(kBlock), shmem, st, S.self, R, n, H,
                      sums_lds ? 1 : 0);
   return hipGetLastError();
 }

@@ -71,6 +71,10 @@ template <typename T> struct alignas(16) GroupRec {
 };
 
 template <typename T> struct SceneView {
+  // device address of the scene's live view: kernels read the view through
+  // it, so parameter updates (which rewrite it) reach later launches and
+  // graph replays
+  const SceneView<T>* self;
   const DVol<T>* vol;
   const uint16_t* always;
   const uint32_t* cell_start;
@@ -84,6 +88,7 @@ template <typename T> struct SceneView {
   double eps_tie;                  // candidates this close are tied (lower volume, then face, wins)
   uint32_t blob_bytes;             // size of the blob (for LDS staging)
   const char* blob;                // start of the blob (== vol)
+  const DTilt* tilt;               // n_vol tilt records of the adjoint (beside the blob)
 };
 
 }  // namespace robast

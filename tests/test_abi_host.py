@@ -109,6 +109,9 @@ def test_null_arguments_rejected(rb):
     assert lib.robast_trace(None, None, 10, None, 0, None) == rb.EINVAL
     assert lib.robast_trace_backward(None, None, 10, None, None, None, None, 0, None) == rb.EINVAL
     assert lib.robast_figures(None, None, None, None) == rb.EINVAL
+    assert lib.robast_update_params(None, None, None, None) == rb.EINVAL
+    assert lib.robast_set_params(None, None, 0) == rb.EINVAL
+    assert lib.robast_update_params_batch(None, None, None, None) == rb.EINVAL
     assert b"NULL" in lib.robast_last_error()
     assert lib.robast_status_string(rb.EINVAL) == b"invalid argument"
 
