@@ -642,8 +642,11 @@ __device__ __forceinline__ void narrow(const DVol<T>& v, int vid, V3<double> O, 
     case SPHERE: nf_sphere(v, vid, ol, dl, t0, eps, sr, b); break;
     case ASPHERE: nf_asphere(v, vid, ol, dl, t0, eps, sr, b); break;
     case CYLINDER: {
-      const V3<double> Ot = {O.x + (double)t0 * D.x, O.y + (double)t0 * D.y, O.z + (double)t0 * D.z};
-      nf_cylinder<double>(v, vid, loc_dd(v, Ot), loc_dir_d(v, D), (double)t0, (double)eps, sr, b);
+      // the origin in double carries the precision; the direction rounded to
+      // T is enough here (kernels without cones then keep no double direction)
+      const V3<double> Dc = ((SH >> HEXCONE) & 1) ? D : V3<double>{(double)d.x, (double)d.y, (double)d.z};
+      const V3<double> Ot = {O.x + (double)t0 * Dc.x, O.y + (double)t0 * Dc.y, O.z + (double)t0 * Dc.z};
+      nf_cylinder<double>(v, vid, loc_dd(v, Ot), loc_dir_d(v, Dc), (double)t0, (double)eps, sr, b);
       break;
     }
     case BOX:
