@@ -15,9 +15,9 @@ Prints one JSON line.  Besides the contract fields:
                 against the MI355X VALU issue rate (256 CU x 64 lanes x
                 2.4 GHz); roofline_kernels gives it for both kernels;
   sweep         256 Davies-Cotton / Schwarzschild-Couder variants with
-                log-uniform photon counts: one batched forward + adjoint step
-                (captured in a HIP graph) against 256 plain per-variant calls,
-                over a few gradient-descent steps;
+                log-uniform photon counts, 20 gradient-descent steps: the
+                batched step (forward + adjoint + device update, one HIP
+                graph) against plain per-variant calls from the same start;
   cpu_baseline  the FP64 reference tracer on a bounded sample on the host.
 """
 import argparse
@@ -154,8 +154,12 @@ def c3_bundle(scenes, torch, sc, npf):
 
 
 def run_sweep(args, torch, rb, scenes):
-    """Batched (one persistent forward + adjoint launch, HIP graph) against
-    plain per-variant calls on 256 variants, over a few GD steps."""
+    """The design sweep as an optimisation: 256 variants, each step a
+    forward trace + figures + adjoint of each variant's RMS + a gradient
+    step on the device.  Batched (one forward, one adjoint and one update
+    launch, the whole step replayed from a HIP graph, launch shape from the
+    batch autotuner) against plain per-variant calls, each over the same
+    number of steps from the same start."""
     t0 = time.time()
     variants, counts = scenes.sweep()
     devs = [rb.Scene(v) for v in variants]
@@ -165,24 +169,28 @@ def run_sweep(args, torch, rb, scenes):
     n = int(counts.sum())
     offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
     batch = rb.Batch(devs, counts, chunk=args.sweep_chunk)
+    tuned = batch.autotune(rays)
     sums = batch.new_sums()
     fig = torch.zeros(batch.n_groups * rb.FIGURE_STRIDE, dtype=torch.float64, device="cuda")
     cot = torch.zeros(batch.n_groups, 2, dtype=torch.float64, device="cuda")
     cot[:, 0] = 1.0                                    # each variant: its own RMS at 1 deg
     grad = torch.zeros(batch.n_params, dtype=torch.float64, device="cuda")
     go, po = batch.goff, batch.poff
+    P0 = torch.from_numpy(np.concatenate([d.params for d in devs])).cuda()
+    P = P0.clone()
+    status = torch.zeros(len(devs), dtype=torch.int32, device="cuda")
     sub = [{k: t[offs[v]:offs[v + 1]] for k, t in rays.items()} for v in range(len(devs))]
-    print(f"[bench] sweep: {len(devs)} variants, {n:.3e} photons, ready in {time.time() - t0:.1f}s",
-          file=sys.stderr, flush=True)
+    print(f"[bench] sweep: {len(devs)} variants, {n:.3e} photons, ready in {time.time() - t0:.1f}s; "
+          f"autotuned {tuned}", file=sys.stderr, flush=True)
 
-    def batched_step():
+    def batched_fb():
         sums.zero_()
         grad.zero_()
         batch.trace(rays, sums=sums, keep_order=True)
         batch.figures(sums, fig=fig)
         batch.backward(rays, sums, cot, grad)
 
-    def plain_step():
+    def plain_fb():
         sums.zero_()
         grad.zero_()
         for v, d in enumerate(devs):
@@ -191,72 +199,209 @@ def run_sweep(args, torch, rb, scenes):
             d.figures(s_v, fig=fig[go[v] * 8:go[v + 1] * 8])
             d.backward(sub[v], s_v, cot[go[v]:go[v + 1]], grad[po[v]:po[v + 1]])
 
-    # warm both paths, then capture the batched step
-    batched_step()
-    plain_step()
+    # the same photons and parameters through both paths give the same sums
+    # and gradients (up to FP64 summation order)
+    batched_fb()
     torch.cuda.synchronize()
+    sums_b, grad_b = sums.clone(), grad.clone()
+    plain_fb()
+    torch.cuda.synchronize()
+    rel_s = float(((sums - sums_b).abs() / sums_b.abs().clamp_min(1e-300)).max())
+    rel_g = float((grad - grad_b).abs().max() / grad_b.abs().max().clamp_min(1e-300))
+    # fixed GD step per family and parameter class, set from the first gradient
+    g = grad_b.cpu().numpy()
+    lr = []
+    for v, d in enumerate(devs):
+        gv = g[po[v]:po[v + 1]]
+        tilt = np.array(["tilt" in nm for nm in d.src.param_names])
+        sig = 1e-4 if d.src.name == "davies_cotton" else 5e-5
+        lt = 0.2 * sig / max(np.abs(gv[tilt]).max(), 1e-300)
+        ls = 2e-4 * np.abs(d.params[~tilt]).max() / max(np.abs(gv[~tilt]).max(), 1e-300)
+        lr.append(np.where(tilt, lt, ls))
+    LR = torch.from_numpy(np.concatenate(lr)).cuda()
+
+    def plain_step():
+        plain_fb()
+        for v, d in enumerate(devs):
+            d.gd_step(P[po[v]:po[v + 1]], grad[po[v]:po[v + 1]], LR[po[v]:po[v + 1]], status=status[v:v + 1])
+
+    def batched_step():
+        batched_fb()
+        batch.gd_step(P, grad, LR, status=status)
+
+    def run(step_fn):
+        times, losses, rejected = [], [], 0
+        for k in range(args.sweep_steps):
+            a, b = ev(torch), ev(torch)
+            a.record()
+            step_fn()
+            b.record()
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b))
+            losses.append(float(fig.view(-1, rb.FIGURE_STRIDE)[:, 4].mean()))
+            rejected += int((status != 0).sum())
+        return times, losses, rejected
+
+    # plain trajectory from the start parameters
+    plain_step()                                   # warm-up step, then back to the start
+    P.copy_(P0)
+    batch.update_params(P)
+    torch.cuda.synchronize()
+    t_p, loss_p, rej_p = run(plain_step)
+    P_plain = P.clone()
+    # batched trajectory from the same start, the whole step from a HIP graph
+    P.copy_(P0)
+    batch.update_params(P)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
         batched_step()
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
+    P.copy_(P0)
+    batch.update_params(P)
+    torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         batched_step()
     torch.cuda.synchronize()
-
-    # fixed GD step per family and parameter class, set from the first gradient
-    lr = None
-    t_b, t_p, losses, diffs = [], [], [], []
-    for step in range(args.sweep_steps):
-        a, b = ev(torch), ev(torch)
-        a.record()
-        graph.replay()
-        b.record()
-        torch.cuda.synchronize()
-        t_b.append(a.elapsed_time(b))
-        sums_b, grad_b = sums.clone(), grad.clone()
-        rms = fig.view(-1, rb.FIGURE_STRIDE)[:, 4].cpu().numpy()
-        losses.append(float(rms.mean()))
-        a, b = ev(torch), ev(torch)
-        a.record()
-        plain_step()
-        b.record()
-        torch.cuda.synchronize()
-        t_p.append(a.elapsed_time(b))
-        # same photons, same results: sums and gradients equal up to FP64 order
-        rel_s = float(((sums - sums_b).abs() / sums_b.abs().clamp_min(1e-300)).max())
-        rel_g = float((grad - grad_b).abs().max() / grad_b.abs().max().clamp_min(1e-300))
-        diffs.append(max(rel_s, rel_g))
-        g = grad_b.cpu().numpy()
-        if lr is None:
-            lr = []
-            for v, d in enumerate(devs):
-                gv = g[po[v]:po[v + 1]]
-                names = d.src.param_names
-                tilt = np.array(["tilt" in nm for nm in names])
-                sig = 1e-4 if d.src.name == "davies_cotton" else 5e-5
-                lt = 0.2 * sig / max(np.abs(gv[tilt]).max(), 1e-300)
-                ls = 2e-4 * np.abs(d.params[~tilt]).max() / max(np.abs(gv[~tilt]).max(), 1e-300)
-                lr.append(np.where(tilt, lt, ls))
-        for v, d in enumerate(devs):
-            d.update_params(d.params - lr[v] * g[po[v]:po[v + 1]])
-        print(f"[bench] sweep step {step}: batched {t_b[-1]:.1f} ms, plain {t_p[-1]:.1f} ms, "
-              f"mean RMS {losses[-1] * 1e3:.4f} mm", file=sys.stderr, flush=True)
+    t_b, loss_b, rej_b = run(graph.replay)
+    dp = float(((P - P_plain).abs() / P_plain.abs().clamp_min(1e-300)).max())
+    dl = max(abs(a - b) / abs(b) for a, b in zip(loss_b, loss_p))
     tb, tp = float(np.mean(t_b)), float(np.mean(t_p))
+    print(f"[bench] sweep: {args.sweep_steps} GD steps, batched {tb:.1f} ms, plain {tp:.1f} ms per step; "
+          f"mean RMS {loss_b[0] * 1e3:.4f} -> {loss_b[-1] * 1e3:.4f} mm; rejected updates {rej_b}/{rej_p}",
+          file=sys.stderr, flush=True)
     return {
         "workload": "256 variants (128 Davies-Cotton, 128 Schwarzschild-Couder) at 1 deg, perturbed radii / "
                     "coefficients / tilts, photons per variant round(10^U(5,7)); one step = forward trace + "
-                    "figures + adjoint of each variant's RMS, then a gradient-descent update",
-        "photons_per_step": n, "variants": len(devs), "steps": args.sweep_steps, "chunk": args.sweep_chunk,
+                    "figures + adjoint of each variant's RMS + a gradient-descent update on the device",
+        "photons_per_step": n, "variants": len(devs), "steps": args.sweep_steps, "tuning": tuned,
         "batched_ms_per_step": tb, "plain_ms_per_step": tp, "speedup": tp / tb,
         "batched_photons_per_s": n / (tb / 1e3), "plain_photons_per_s": n / (tp / 1e3),
-        "batched": "one binning + forward launch and one adjoint launch, replayed from a HIP graph",
-        "plain": f"{len(devs)} x (binning + trace + figures + coefficients + adjoint) launches",
-        "max_rel_diff_batched_vs_plain": float(max(diffs)),
-        "mean_rms_m_per_step": losses,
+        "batched": "one binning + forward launch, one adjoint launch and one update launch per step, "
+                   "replayed from a HIP graph",
+        "plain": f"{len(devs)} x (binning + trace + figures + coefficients + adjoint + update) launches",
+        "max_rel_diff_batched_vs_plain": max(rel_s, rel_g),
+        "trajectory_max_rel_diff": {"params": dp, "mean_rms": dl},
+        "rejected_updates": {"batched": rej_b, "plain": rej_p},
+        "mean_rms_m_per_step": loss_b,
     }
+
+
+def cpu_baseline(scenes, sc, per_group, what):
+    """The reference tracer on a bounded sample of a config's photons, on the
+    host's cores (at most 16 threads, the host share of one GPU)."""
+    import oracle
+    cores = host_cores()
+    sample = sc.rays(per_group, seed=sc.seed + 99)
+    rec, dt = oracle.timed_trace(sc, sample, nthreads=cores)
+    ncpu = len(sample["ox"])
+    print(f"[bench] cpu baseline {sc.name}: {ncpu / dt:.3e} photons/s on {cores} threads ({ncpu} photons, "
+          f"{dt:.1f} s)", file=sys.stderr, flush=True)
+    return {"value": ncpu / dt, "unit": "photons/s", "cores": cores, "kind": "oracle",
+            "sample": f"{ncpu} photons ({per_group} per group x {sc.n_groups} groups) of the same scene, "
+                      f"{what}, FP64 brute-force search, {dt:.1f} s"}
+
+
+def roofline(ops, n, ms, traffic=None):
+    achieved = ops * n / (ms / 1e3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
+            "frac": achieved * 1e12 / VALU_PEAK_OPS, "traffic": traffic, "ops_per_photon": ops,
+            "kernel_ms": ms}
+
+
+def run_config(args, torch, rb, scenes, sc, npf, objective, cpu_per_group, describe):
+    """One config's step on the device: binning + forward trace with group
+    sums + figures + adjoint of the objective (objective: "rms" or "eff",
+    the mean over the groups), per-phase times from HIP events, the roofline
+    of both kernels from the reference tracer's event log, and the CPU
+    baseline."""
+    import oracle
+    dev = rb.Scene(sc)
+    t0 = time.time()
+    parts = [scenes.device_rays(sc, npf, seed=sc.seed + 1000 * g, group=g) for g in range(sc.n_groups)]
+    rays = {k: torch.cat([p[k] for p in parts]) for k in parts[0]}
+    del parts
+    n = int(rays["ox"].numel())
+    torch.cuda.synchronize()
+    print(f"[bench] {sc.name}: {n:.3e} photons generated on the device in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    sums = dev.new_sums()
+    fig = torch.zeros(sc.n_groups * rb.FIGURE_STRIDE, dtype=torch.float64, device="cuda")
+    grad = torch.zeros(len(sc.params), dtype=torch.float64, device="cuda")
+    cot = torch.zeros(sc.n_groups, 2, dtype=torch.float64, device="cuda")
+    cot[:, 0 if objective == "rms" else 1] = 1.0 / sc.n_groups
+    evs = [ev(torch) for _ in range(5)]
+    t = {"binning": [], "trace": [], "adjoint": [], "step": []}
+    for rep in range(args.config_steps + 1):
+        sums.zero_()
+        grad.zero_()
+        evs[0].record()
+        dev.bin_photons(rays)
+        evs[1].record()
+        dev.trace(rays, sums=sums, keep_order=True)
+        evs[2].record()
+        dev.figures(sums, fig=fig)
+        evs[3].record()
+        dev.backward(rays, sums, cot, grad)
+        evs[4].record()
+        torch.cuda.synchronize()
+        if rep:   # the first step warms up
+            t["binning"].append(evs[0].elapsed_time(evs[1]))
+            t["trace"].append(evs[1].elapsed_time(evs[2]))
+            t["adjoint"].append(evs[3].elapsed_time(evs[4]))
+            t["step"].append(evs[0].elapsed_time(evs[4]))
+    ms = {k: float(np.mean(v)) for k, v in t.items()}
+    figs = fig.view(sc.n_groups, rb.FIGURE_STRIDE).cpu().numpy()
+    tally = oracle.trace(sc, sc.rays(max(1, 40000 // sc.n_groups), seed=sc.seed + 77), log=True)
+    ops_fwd, ops_adj = ops_per_photon(sc, tally)
+    rk = {"k_trace": roofline(ops_fwd, n, ms["trace"]), "k_backward_path": roofline(ops_adj, n, ms["adjoint"])}
+    dominant = "k_backward_path" if ms["adjoint"] > ms["trace"] else "k_trace"
+    cpu = None if args.no_cpu_baseline else cpu_baseline(scenes, sc, cpu_per_group, "forward trace only")
+    print(f"[bench] {sc.name}: step {ms['step']:.2f} ms (binning {ms['binning']:.2f}, trace {ms['trace']:.2f}, "
+          f"adjoint {ms['adjoint']:.2f}); {n / (ms['step'] / 1e3):.3e} photons/s; trace frac "
+          f"{rk['k_trace']['frac']:.3f}", file=sys.stderr, flush=True)
+    col = 4 if objective == "rms" else 5
+    return {"workload": describe, "photons": n, "ms_per_step": ms["step"],
+            "photons_per_s": n / (ms["step"] / 1e3), "binning_ms": ms["binning"], "trace_ms": ms["trace"],
+            "adjoint_ms": ms["adjoint"], "trace_photons_per_s": n / (ms["trace"] / 1e3),
+            "roofline": dict(rk[dominant], kernel=dominant), "roofline_kernels": rk, "cpu_baseline": cpu,
+            ("rms_spot" if objective == "rms" else "efficiency"): figs[:, col].tolist(),
+            "gradient_norm": float(grad.norm())}
+
+
+def run_single_mirror(args, torch, rb, scenes):
+    """The single spherical mirror (FP64, 1e5 on-axis photons): trace with
+    per-photon hit records and the RMS spot; launch-bound at this size."""
+    sc = scenes.single_mirror()
+    dev = rb.Scene(sc)
+    rays = dev.upload_rays(sc.rays(100000))
+    n = int(rays["ox"].numel())
+    hits = {"fate": torch.empty(n, dtype=torch.uint8, device="cuda"),
+            "x": torch.empty(n, dtype=torch.float64, device="cuda"),
+            "y": torch.empty(n, dtype=torch.float64, device="cuda"),
+            "z": torch.empty(n, dtype=torch.float64, device="cuda")}
+    sums = dev.new_sums()
+    fig = torch.zeros(sc.n_groups * rb.FIGURE_STRIDE, dtype=torch.float64, device="cuda")
+    ts = []
+    for rep in range(6):
+        sums.zero_()
+        a, b = ev(torch), ev(torch)
+        a.record()
+        dev.trace(rays, hits=hits, sums=sums)
+        dev.figures(sums, fig=fig)
+        b.record()
+        torch.cuda.synchronize()
+        if rep:
+            ts.append(a.elapsed_time(b))
+    ms = float(np.mean(ts))
+    cpu = None if args.no_cpu_baseline else cpu_baseline(scenes, sc, 1_000_000, "forward trace only")
+    print(f"[bench] single_mirror: {ms:.3f} ms per trace + figures ({n / (ms / 1e3):.3e} photons/s)",
+          file=sys.stderr, flush=True)
+    return {"workload": "single_mirror: R = 16 m, 4 m aperture, 1e5 on-axis photons, FP64; trace writing fate "
+                        "and focal-plane hits + RMS spot", "photons": n, "ms_per_step": ms,
+            "photons_per_s": n / (ms / 1e3), "rms_spot_m": float(fig[4].item()), "cpu_baseline": cpu}
 
 
 def run_lst(args, torch, rb, scenes):
@@ -430,10 +575,13 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--photons-per-field", type=int, default=10_000_000)
-    ap.add_argument("--cpu-sample-per-field", type=int, default=60_000)
+    ap.add_argument("--cpu-sample-per-field", type=int, default=62_500)
+    ap.add_argument("--config-steps", type=int, default=3)
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the single-mirror, Davies-Cotton and concentrator sections")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
-    ap.add_argument("--sweep-steps", type=int, default=4)
+    ap.add_argument("--sweep-steps", type=int, default=20)
     ap.add_argument("--sweep-chunk", type=int, default=8192)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--lst-photons-per-field", type=int, default=10_000_000)
@@ -520,33 +668,32 @@ def main():
     gct = None if args.no_gct else run_gct(args, torch, rb, scenes)
     chromatic = None if args.no_chromatic else {
         nm: run_chromatic(args, torch, rb, scenes, nm) for nm in ("aspheric_lens", "fresnel_lens")}
+    configs = None
+    if not args.no_configs:
+        configs = {
+            "single_mirror": run_single_mirror(args, torch, rb, scenes),
+            "davies_cotton": run_config(
+                args, torch, rb, scenes, scenes.davies_cotton(), 10_000_000, "rms", 1_000_000,
+                "davies_cotton: 5 fields (0-2 deg) x 1e7 photons, 198 spherical facets, camera box and masts; "
+                "binning + trace + figures + adjoint of the mean RMS (594 params: radii, tilts)"),
+            "hex_concentrator": run_config(
+                args, torch, rb, scenes, scenes.hex_concentrator(), 1_000_000, "eff", 11_000,
+                "hex_concentrator: 91 incidence angles (0-45 deg) x 1e6 photons, 8x8 Bezier hex cones under a "
+                "PMMA window, up to 32 events; binning + trace + figures + adjoint of the mean weighted "
+                "collection efficiency (4 control-point coordinates)"),
+        }
 
     # algorithmic op tallies from the reference tracer's event log
     import oracle
     tally = oracle.trace(sc, sc.rays(400, seed=sc.seed + 77), log=True)
     ops_fwd, ops_adj = ops_per_photon(sc, tally)
-    cpu = None
-    if not args.no_cpu_baseline:
-        cores = host_cores()
-        sample = sc.rays(args.cpu_sample_per_field, seed=sc.seed + 99)
-        rec, dt = oracle.timed_trace(sc, sample, nthreads=cores)
-        ncpu = len(sample["ox"])
-        cpu = {"value": ncpu / dt, "unit": "photons/s", "cores": cores, "kind": "oracle",
-               "sample": f"{ncpu} photons ({args.cpu_sample_per_field} per field x {sc.n_groups} fields) "
-                         f"of the same scene, forward trace only, FP64 brute-force search, {dt:.1f} s"}
-        print(f"[bench] cpu baseline {ncpu / dt:.3e} photons/s on {cores} threads", file=sys.stderr,
-              flush=True)
-
-    def roof(ops, ms, traffic=None):
-        achieved = ops * n / (ms / 1e3) / 1e12
-        return {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
-                "frac": achieved * 1e12 / VALU_PEAK_OPS, "traffic": traffic, "ops_per_photon": ops,
-                "kernel_ms": ms}
+    cpu = None if args.no_cpu_baseline else cpu_baseline(scenes, sc, args.cpu_sample_per_field,
+                                                          "forward trace only")
 
     t_trace, t_bwd = float(np.mean(k_trace)), float(np.mean(k_bwd))
-    rk = {"k_trace": roof(ops_fwd, t_trace, measured_traffic("k_trace"))}
+    rk = {"k_trace": roofline(ops_fwd, n, t_trace, measured_traffic("k_trace"))}
     if do_bwd:
-        rk["k_backward_path"] = roof(ops_adj, t_bwd, measured_traffic("k_backward_path"))
+        rk["k_backward_path"] = roofline(ops_adj, n, t_bwd, measured_traffic("k_backward_path"))
     dominant = "k_backward_path" if do_bwd and t_bwd > t_trace else "k_trace"
     out = {
         "metric": "traced photons/s (2-mirror SC, 1e7 rays); batched fwd+adjoint vs plain, 1 GPU",
@@ -572,6 +719,7 @@ def main():
         "lst": lst,
         "gct": gct,
         "chromatic": chromatic,
+        "configs": configs,
         "cpu_baseline": cpu,
         "figures": {"rms_mean_m": float(np.mean(figs[:, 4])), "efficiency_mean": float(np.mean(figs[:, 5]))},
     }

@@ -300,19 +300,23 @@ typedef struct robast_tuning {
   uint32_t bin_photons;
   uint32_t bin_target;   /* photons per cell aimed at when sizing that grid, 1..65536 */
   uint32_t waves_mult;   /* workgroups launched per resident workgroup slot, 1..64 */
-  uint32_t reserved;     /* 0 */
+  uint32_t block;        /* threads per workgroup of the forward trace: 64, 128, 192 or 256
+                            (0 reads as 256); each workgroup stages the scene's tables into
+                            LDS once, so smaller workgroups stage more often */
 } robast_tuning;
 
-/* Defaults: bin_photons 1, bin_target 128, waves_mult 4. */
+/* Defaults: bin_photons 1, bin_target 128, waves_mult 4, block 256. */
 int robast_get_tuning(const robast_scene* scene, robast_tuning* out);
 /* EINVAL on NULL arguments or a field out of range. */
 int robast_set_tuning(robast_scene* scene, const robast_tuning* tuning);
 
 /* Autotuner: traces photons [0, n) of `rays` (group sums only, into its own
  * scratch) under candidate tunings (binning off; binning with 32, 128 or 512
- * photons per cell; grid multiplier 1, 4 or 8), times each with HIP events on
- * the stream, keeps the fastest in the scene and returns it in *best (may be
- * NULL).  Synchronous; allocates; EINVAL as robast_trace or n < 1. */
+ * photons per cell; grid multiplier 1, 4 or 8; workgroups of 128 or 256
+ * threads), times each with HIP events on the stream, keeps the fastest in
+ * the scene and returns it in *best (may be NULL).  Synchronous; allocates;
+ * EINVAL as robast_trace or n < 1.  Iteration caps of the root solvers are
+ * not tuned: they decide results, which no tuning may change. */
 int robast_autotune(robast_scene* scene, const robast_rays* rays, int64_t n, robast_tuning* best,
                     void* hip_stream);
 
@@ -337,6 +341,21 @@ int robast_autotune(robast_scene* scene, const robast_rays* rays, int64_t n, rob
  * another stream.  Drops the kept binned order and path records.  EINVAL on
  * NULL scene or d_params (host-side, nothing launched). */
 int robast_update_params(robast_scene* scene, const double* d_params, int32_t* d_status, void* hip_stream);
+
+/* One gradient-descent step on the device (the optimisation of §3, with
+ * the gradient of robast_trace_backward): the candidate parameters
+ * p - lr * g (elementwise, FP64) are applied as by robast_update_params.
+ *   d_params [device, n_params doubles] the current parameters p; where the
+ *            update is applied they are overwritten with the new ones, else
+ *            they keep their values (so they always describe the scene)
+ *   d_grad   [device, n_params] the gradient g
+ *   d_lr     [device, n_params] the step per parameter
+ *   d_status [device, may be NULL] as for robast_update_params
+ * Stream-ordered and graph-capturable (no host work, no allocation), so a
+ * whole optimisation step -- trace, figures, backward, this step -- can be
+ * replayed from one HIP graph.  EINVAL on NULL arguments. */
+int robast_gd_step(robast_scene* scene, double* d_params, const double* d_grad, const double* d_lr,
+                   int32_t* d_status, void* hip_stream);
 
 /* Replace the differentiable parameters from the host [host, n_params] and
  * rebuild the scene's tables on the host, grid included (any change).  The
@@ -406,6 +425,25 @@ int robast_trace_backward_batch(robast_batch* batch, const robast_rays* rays, co
  * for robast_update_params.  Graph-capturable.  EUNSUPPORTED when a scene
  * appears more than once in the batch. */
 int robast_update_params_batch(robast_batch* batch, const double* d_params, int32_t* d_status, void* hip_stream);
+
+/* robast_gd_step for every variant of the batch in one launch: d_params,
+ * d_grad and d_lr concatenated in variant order (n_params doubles each),
+ * d_status [device, n_scenes int32, may be NULL].  Graph-capturable.
+ * EINVAL on NULL arguments; EUNSUPPORTED when a scene appears more than once
+ * in the batch. */
+int robast_gd_step_batch(robast_batch* batch, double* d_params, const double* d_grad, const double* d_lr,
+                         int32_t* d_status, void* hip_stream);
+
+/* Autotuner of a batch's forward launch: traces the whole bundle (group
+ * sums only, into its own scratch) with work items of 2048, 8192, 32768 or
+ * 131072 photons and workgroups of 128 or 256 threads, times each with HIP
+ * events, keeps the fastest in the batch (the work list is rebuilt for it)
+ * and returns it in *best_chunk / *best_block (may be NULL).  Results do not
+ * depend on either (only FP64 summation order does).  Synchronous;
+ * allocates; re-capture graphs of the batch afterwards.  EINVAL as
+ * robast_trace_batch. */
+int robast_autotune_batch(robast_batch* batch, const robast_rays* rays, uint32_t* best_chunk, uint32_t* best_block,
+                          void* hip_stream);
 
 /* Totals of the concatenated layouts: photons, groups, parameters. */
 int robast_batch_sizes(const robast_batch* batch, int64_t* n_photons, int64_t* n_groups, int64_t* n_params);

@@ -31,7 +31,8 @@ SYMBOLS = ["robast_build_scene", "robast_trace", "robast_figures", "robast_trace
            "robast_last_error", "robast_abi_version", "robast_build_batch", "robast_trace_batch",
            "robast_figures_batch", "robast_trace_backward_batch", "robast_batch_sizes", "robast_destroy_batch",
            "robast_get_tuning", "robast_set_tuning", "robast_autotune", "robast_bin_photons",
-           "robast_arrival_figures", "robast_trace_static", "robast_set_params", "robast_update_params_batch"]
+           "robast_arrival_figures", "robast_trace_static", "robast_set_params", "robast_update_params_batch",
+           "robast_gd_step", "robast_gd_step_batch", "robast_autotune_batch"]
 
 
 class VolumeDesc(ctypes.Structure):
@@ -65,10 +66,10 @@ class Hits(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("bin_photons", ctypes.c_uint32), ("bin_target", ctypes.c_uint32),
-                ("waves_mult", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("waves_mult", ctypes.c_uint32), ("block", ctypes.c_uint32)]
 
     def as_dict(self):
-        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 assert ctypes.sizeof(VolumeDesc) == 464
@@ -86,6 +87,10 @@ _lib.robast_trace_backward.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ct
 _lib.robast_update_params.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
 _lib.robast_set_params.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
 _lib.robast_update_params_batch.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+_lib.robast_gd_step.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 5
+_lib.robast_gd_step_batch.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 5
+_lib.robast_autotune_batch.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ctypes.POINTER(ctypes.c_uint32),
+                                       ctypes.POINTER(ctypes.c_uint32), ctypes.c_void_p]
 _lib.robast_destroy_scene.argtypes = [ctypes.c_void_p]
 _lib.robast_destroy_scene.restype = None
 _lib.robast_status_string.argtypes = [ctypes.c_int]
@@ -112,7 +117,8 @@ for _name in ("robast_build_scene", "robast_trace", "robast_figures", "robast_tr
               "robast_update_params", "robast_abi_version", "robast_build_batch", "robast_trace_batch",
               "robast_figures_batch", "robast_trace_backward_batch", "robast_batch_sizes", "robast_get_tuning",
               "robast_set_tuning", "robast_autotune", "robast_bin_photons", "robast_arrival_figures",
-              "robast_trace_static", "robast_set_params", "robast_update_params_batch"):
+              "robast_trace_static", "robast_set_params", "robast_update_params_batch", "robast_gd_step",
+              "robast_gd_step_batch", "robast_autotune_batch"):
     getattr(_lib, _name).restype = ctypes.c_int
 
 
@@ -372,7 +378,7 @@ class Scene:
         return t.as_dict()
 
     def set_tuning(self, **fields):
-        """Change launch parameters (bin_photons, bin_target, waves_mult)."""
+        """Change launch parameters (bin_photons, bin_target, waves_mult, block)."""
         cur = self.tuning
         unknown = set(fields) - set(cur)
         if unknown:
@@ -411,6 +417,19 @@ class Scene:
             raise ValueError("status must hold an int32")
         _check(_lib.robast_update_params(self._h, _ptr(params), _ptr(status), _stream(stream)),
                "robast_update_params")
+        self.params = None
+
+    def gd_step(self, params, grad, lr, status=None, stream=None):
+        """robast_gd_step: params <- params - lr * grad on the device, applied
+        to the scene in stream order (graph-capturable); params (float64
+        device tensor) is overwritten where the update is applied."""
+        import torch
+        _check_extents(0, None, f64=[("params", params, self.n_params), ("grad", grad, self.n_params),
+                                     ("lr", lr, self.n_params)])
+        if status is not None and (status.dtype != torch.int32 or status.numel() < 1):
+            raise ValueError("status must hold an int32")
+        _check(_lib.robast_gd_step(self._h, _ptr(params), _ptr(grad), _ptr(lr), _ptr(status), _stream(stream)),
+               "robast_gd_step")
         self.params = None
 
 
@@ -497,6 +516,29 @@ class Batch:
                "robast_update_params_batch")
         for s in self.scenes:
             s.params = None
+
+    def gd_step(self, params, grad, lr, status=None, stream=None):
+        """robast_gd_step_batch: one gradient-descent step of every variant
+        (concatenated float64 device tensors; status: int32 per variant)."""
+        import torch
+        _check_extents(0, None, f64=[("params", params, self.n_params), ("grad", grad, self.n_params),
+                                     ("lr", lr, self.n_params)])
+        if status is not None and (status.dtype != torch.int32 or status.numel() < len(self.scenes)):
+            raise ValueError("status must hold one int32 per variant")
+        _check(_lib.robast_gd_step_batch(self._h, _ptr(params), _ptr(grad), _ptr(lr), _ptr(status),
+                                         _stream(stream)), "robast_gd_step_batch")
+        for s in self.scenes:
+            s.params = None
+
+    def autotune(self, rays, id_base=0, stream=None):
+        """robast_autotune_batch: the fastest work-item size and workgroup
+        size of the forward launch, kept in the batch; returns both."""
+        self._check_sizes(rays)
+        R = _rays_struct(rays, id_base)
+        c, b = ctypes.c_uint32(), ctypes.c_uint32()
+        _check(_lib.robast_autotune_batch(self._h, ctypes.byref(R), ctypes.byref(c), ctypes.byref(b),
+                                          _stream(stream)), "robast_autotune_batch")
+        return {"chunk": int(c.value), "block": int(b.value)}
 
     def backward(self, rays, sums, cot, grad, id_base=0, stream=None):
         self._check_sizes(rays, None, sums, grad, cot)

@@ -278,6 +278,10 @@ struct robast_batch {
   void* d_jobs = nullptr;          // n_scenes job pointers
   int64_t* d_poff = nullptr;       // n_scenes offsets into the concatenated parameters
   bool repeated = false;           // a scene appears more than once
+  // launch shape of the forward launch (robast_autotune_batch may change it)
+  std::vector<int64_t> offsets;    // n_scenes + 1 photon offsets
+  uint32_t chunk = 0, block = 256;
+  size_t items_cap = 0;            // BatchItem slots allocated at d_items
 };
 
 namespace {
@@ -860,7 +864,8 @@ UpdVol upd_vol(const robast_scene& s, int i) {
 template <typename T> int set_job(robast_scene* s, const SceneView<T>& V) {
   char* base = (char*)s->d_upd;
   const size_t ov = 0, og = align256(sizeof(UpdVol) * s->n_vol), om = og + align256(sizeof(UpdGroup) * V.n_grp),
-               oz = om + align256(sizeof(uint16_t) * s->upd_members.size());
+               oz = om + align256(sizeof(uint16_t) * s->upd_members.size()),
+               op = oz + align256(sizeof(double) * 2 * std::max(1, s->n_vol));
   UpdJob<T> j{};
   j.view = (SceneView<T>*)s->d_view;
   j.slot[0] = (char*)s->d_blob;
@@ -871,8 +876,10 @@ template <typename T> int set_job(robast_scene* s, const SceneView<T>& V) {
   j.groups = (const UpdGroup*)(base + og);
   j.members = (const uint16_t*)(base + om);
   j.zr = (double*)(base + oz);
+  j.pn = (double*)(base + op);
   j.n_vol = s->n_vol;
   j.n_grp = V.n_grp;
+  j.n_params = (int32_t)s->params.size();
   j.blob_bytes = (uint32_t)s->blob_bytes;
   j.l_ref = s->l_ref;
   hipError_t e = hipMemcpy(s->d_job, &j, sizeof j, hipMemcpyHostToDevice);
@@ -945,7 +952,8 @@ int upload(robast_scene* s) {
   // tables of device parameter updates
   const int n_grp = (int)s->upd_groups.size();
   std::vector<char> upd(align256(sizeof(UpdVol) * s->n_vol) + align256(sizeof(UpdGroup) * n_grp) +
-                        align256(sizeof(uint16_t) * s->upd_members.size()) + align256(sizeof(double) * 2 * nt));
+                        align256(sizeof(uint16_t) * s->upd_members.size()) + align256(sizeof(double) * 2 * nt) +
+                        align256(sizeof(double) * std::max<size_t>(1, s->params.size())));
   for (int i = 0; i < s->n_vol; ++i) {
     const UpdVol u = upd_vol(*s, i);
     std::memcpy(upd.data() + sizeof(UpdVol) * i, &u, sizeof u);
@@ -1011,7 +1019,7 @@ int check_hits(const robast_hits* hits) {
 
 template <typename T> BatchView<T> batch_view(const robast_batch* b) {
   return BatchView<T>{(const BatchVariant<T>*)b->d_vars, b->d_items, b->d_queue, b->n_items, b->max_events,
-                      b->max_params, b->blob_cap, b->blob_cap_bwd, b->shapes};
+                      b->max_params, b->blob_cap, b->blob_cap_bwd, b->shapes, (int)b->block};
 }
 
 template <typename T> std::vector<BatchVariant<T>> variant_table(const robast_batch& b, const int64_t* offsets) {
@@ -1029,10 +1037,16 @@ template <typename T> std::vector<BatchVariant<T>> variant_table(const robast_ba
 
 constexpr int64_t kBinMin = 32768;
 
-void apply_tuning(robast_scene* s) { s->cfg.waves_mult = (int)s->tuning.waves_mult; }
+void apply_tuning(robast_scene* s) {
+  s->cfg.waves_mult = (int)s->tuning.waves_mult;
+  s->cfg.block = s->tuning.block ? (int)s->tuning.block : 256;
+}
+
+bool block_valid(uint32_t b) { return b == 0 || b == 64 || b == 128 || b == 192 || b == 256; }
 
 int tuning_valid(const robast_tuning& t) {
-  return t.bin_target >= 1 && t.bin_target <= 65536 && t.waves_mult >= 1 && t.waves_mult <= 64;
+  return t.bin_target >= 1 && t.bin_target <= 65536 && t.waves_mult >= 1 && t.waves_mult <= 64 &&
+         block_valid(t.block);
 }
 
 
@@ -1264,7 +1278,8 @@ int robast_build_scene(const robast_scene_desc* desc, const double* params, int6
   s->params.assign(params, params + n_params);
   s->cfg.lds_cap = kLdsCap;
   s->cfg.max_blocks = 0;
-  s->tuning = robast_tuning{1u, 128u, 4u, 0u};
+  s->cfg.block = 256;
+  s->tuning = robast_tuning{1u, 128u, 4u, 256u};
   apply_tuning(s);
   rc = upload(s);
   if (rc) {
@@ -1302,12 +1317,28 @@ int robast_update_params(robast_scene* s, const double* d_params, int32_t* d_sta
   s->kept = false;
   s->path_ok = false;
   hipStream_t st = (hipStream_t)stream;
+  // the kernel writes params only in its gradient-step form (not this one)
+  double* P = const_cast<double*>(d_params);
+  hipError_t e = s->precision == 32
+                     ? launch_update_params<float>((const UpdJob<float>* const*)s->d_jobptr, 1, P, nullptr, d_status, st)
+                     : launch_update_params<double>((const UpdJob<double>* const*)s->d_jobptr, 1, P, nullptr, d_status,
+                                                    st);
+  if (e != hipSuccess) return hip_fail(e, "parameter update launch");
+  return ROBAST_OK;
+}
+
+int robast_gd_step(robast_scene* s, double* d_params, const double* d_grad, const double* d_lr, int32_t* d_status,
+                   void* stream) {
+  if (!s || !d_params || !d_grad || !d_lr) return fail(ROBAST_EINVAL, "NULL scene, params, grad or lr");
+  s->kept = false;
+  s->path_ok = false;
+  hipStream_t st = (hipStream_t)stream;
   hipError_t e = s->precision == 32
                      ? launch_update_params<float>((const UpdJob<float>* const*)s->d_jobptr, 1, d_params, nullptr,
-                                                   d_status, st)
+                                                   d_status, st, d_grad, d_lr)
                      : launch_update_params<double>((const UpdJob<double>* const*)s->d_jobptr, 1, d_params, nullptr,
-                                                    d_status, st);
-  if (e != hipSuccess) return hip_fail(e, "parameter update launch");
+                                                    d_status, st, d_grad, d_lr);
+  if (e != hipSuccess) return hip_fail(e, "gradient step launch");
   return ROBAST_OK;
 }
 
@@ -1481,9 +1512,10 @@ int robast_autotune(robast_scene* s, const robast_rays* rays, int64_t n, robast_
   hits.group_sums = sums;
   for (uint32_t bin = 0; bin < 2 && e == hipSuccess && !rc; ++bin)
     for (uint32_t target : {32u, 128u, 512u})
-      for (uint32_t mult : {1u, 4u, 8u}) {
+      for (uint32_t mult : {1u, 4u, 8u})
+        for (uint32_t block : {128u, 256u}) {
         if (e != hipSuccess || rc || (!bin && target != 128u)) continue;
-        s->tuning = robast_tuning{bin, target, mult, 0u};
+        s->tuning = robast_tuning{bin, target, mult, block};
         apply_tuning(s);
         float ms = 0.0f;
         for (int rep = 0; rep < 2 && e == hipSuccess && !rc; ++rep) {   // first run warms up
@@ -1498,7 +1530,7 @@ int robast_autotune(robast_scene* s, const robast_rays* rays, int64_t n, robast_
           win_ms = ms;
           win = s->tuning;
         }
-      }
+        }
   s->tuning = (e == hipSuccess && !rc) ? win : saved;
   apply_tuning(s);
   if (e0) (void)hipEventDestroy(e0);
@@ -1536,6 +1568,9 @@ int robast_build_batch(robast_scene* const* scenes, int32_t n_scenes, const int6
   b->scenes.assign(scenes, scenes + n_scenes);
   b->n_photons = offsets[n_scenes];
   b->n_items = (int)items.size();
+  b->offsets.assign(offsets, offsets + n_scenes + 1);
+  b->chunk = chunk;
+  b->items_cap = std::max<size_t>(1, items.size());
   size_t max_blob = 0;
   for (robast_scene* s : b->scenes) {
     b->n_groups += s->n_groups;
@@ -1700,9 +1735,111 @@ int robast_update_params_batch(robast_batch* b, const double* d_params, int32_t*
     s->path_ok = false;
   }
   b->path_ok = false;
-  hipError_t e = launch_update_params<float>((const UpdJob<float>* const*)b->d_jobs, (int)b->scenes.size(), d_params,
-                                             b->d_poff, d_status, (hipStream_t)stream);
+  hipError_t e = launch_update_params<float>((const UpdJob<float>* const*)b->d_jobs, (int)b->scenes.size(),
+                                             const_cast<double*>(d_params), b->d_poff, d_status, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "batched parameter update launch");
+  return ROBAST_OK;
+}
+
+int robast_gd_step_batch(robast_batch* b, double* d_params, const double* d_grad, const double* d_lr,
+                         int32_t* d_status, void* stream) {
+  if (!b || !d_params || !d_grad || !d_lr) return fail(ROBAST_EINVAL, "NULL batch, params, grad or lr");
+  if (b->repeated) return fail(ROBAST_EUNSUPPORTED, "a scene appears more than once in the batch");
+  for (robast_scene* s : b->scenes) {
+    s->kept = false;
+    s->path_ok = false;
+  }
+  b->path_ok = false;
+  hipError_t e = launch_update_params<float>((const UpdJob<float>* const*)b->d_jobs, (int)b->scenes.size(), d_params,
+                                             b->d_poff, d_status, (hipStream_t)stream, d_grad, d_lr);
+  if (e != hipSuccess) return hip_fail(e, "batched gradient step launch");
+  return ROBAST_OK;
+}
+
+namespace {
+// The batch's work items for another chunk size, into d_items (grown when
+// needed).  Called with no launch of the batch in flight.
+int set_batch_chunk(robast_batch* b, uint32_t chunk) {
+  std::vector<BatchItem> items;
+  const int nv = (int)b->scenes.size();
+  for (int v = 0; v < nv; ++v)
+    for (int64_t st = b->offsets[v]; st < b->offsets[v + 1]; st += chunk)
+      items.push_back(BatchItem{st, (int32_t)std::min<int64_t>(chunk, b->offsets[v + 1] - st), v});
+  if (items.size() > (size_t)INT32_MAX - 65536) return fail(ROBAST_EINVAL, "too many work items: raise chunk");
+  hipError_t e = hipSuccess;
+  if (items.size() > b->items_cap) {
+    BatchItem* d = nullptr;
+    e = hipMalloc(&d, sizeof(BatchItem) * items.size());
+    if (e != hipSuccess) return fail(ROBAST_ENOMEM, "hipMalloc batch items");
+    (void)hipFree(b->d_items);
+    b->d_items = d;
+    b->items_cap = items.size();
+  }
+  if (!items.empty()) e = hipMemcpy(b->d_items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy batch items");
+  b->n_items = (int)items.size();
+  b->chunk = chunk;
+  return ROBAST_OK;
+}
+}  // namespace
+
+int robast_autotune_batch(robast_batch* b, const robast_rays* rays, uint32_t* best_chunk, uint32_t* best_block,
+                          void* stream) {
+  if (!b || !rays) return fail(ROBAST_EINVAL, "NULL batch or rays");
+  if (b->n_photons == 0) return ROBAST_OK;
+  int rc = check_rays(rays);
+  if (rc) return rc;
+  if (rays->lambda) return fail(ROBAST_EUNSUPPORTED, "batched launches take no per-photon wavelengths");
+  hipStream_t st = (hipStream_t)stream;
+  (void)hipStreamSynchronize(st);
+  b->kept = false;
+  b->path_ok = false;
+  double* sums = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc(&sums, sizeof(double) * 8 * std::max<int64_t>(1, b->n_groups));
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  const uint32_t saved_chunk = b->chunk, saved_block = b->block;
+  uint32_t win_chunk = saved_chunk, win_block = saved_block;
+  float win_ms = INFINITY;
+  robast_hits hits{};
+  hits.group_sums = sums;
+  for (uint32_t chunk : {2048u, 8192u, 32768u, 131072u})
+    for (uint32_t block : {128u, 256u}) {
+      if (e != hipSuccess || rc) continue;
+      rc = set_batch_chunk(b, chunk);
+      b->block = block;
+      float ms = 0.0f;
+      for (int rep = 0; rep < 2 && e == hipSuccess && !rc; ++rep) {   // first run warms up
+        e = hipMemsetAsync(sums, 0, sizeof(double) * 8 * b->n_groups, st);
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        if (e == hipSuccess) rc = robast_trace_batch(b, rays, &hits, 0, stream);
+        if (e == hipSuccess && !rc) e = hipEventRecord(e1, st);
+        if (e == hipSuccess && !rc) e = hipEventSynchronize(e1);
+        if (e == hipSuccess && !rc) e = hipEventElapsedTime(&ms, e0, e1);
+      }
+      if (e == hipSuccess && !rc && ms < win_ms) {
+        win_ms = ms;
+        win_chunk = chunk;
+        win_block = block;
+      }
+    }
+  if (e == hipSuccess && !rc) {
+    rc = set_batch_chunk(b, win_chunk);
+    b->block = win_block;
+  } else {
+    (void)set_batch_chunk(b, saved_chunk);
+    b->block = saved_block;
+  }
+  b->kept = false;
+  b->path_ok = false;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (sums) (void)hipFree(sums);
+  if (rc) return rc;
+  if (e != hipSuccess) return hip_fail(e, "batch autotune");
+  if (best_chunk) *best_chunk = win_chunk;
+  if (best_block) *best_block = win_block;
   return ROBAST_OK;
 }
 

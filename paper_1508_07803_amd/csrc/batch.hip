@@ -182,12 +182,13 @@ template <bool USE_LDS, bool RECORD, int SH>
 static hipError_t trace_batch_k(const BatchView<float>& B, const RaysView<float>& R, const HitsView<float>& H,
                                 int ncu, hipStream_t st) {
   const size_t shmem = USE_LDS ? B.blob_cap : 0;
+  const int blk = B.block > 0 ? B.block : kBlockB;
   int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace_batch<USE_LDS, RECORD, SH>, kBlockB,
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace_batch<USE_LDS, RECORD, SH>, blk,
                                                               shmem);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
   const int blocks = std::max(1, std::min(B.n_items, ncu * per_cu));
-  hipLaunchKernelGGL((k_trace_batch<USE_LDS, RECORD, SH>), dim3(blocks), dim3(kBlockB), shmem, st, B.vars, B.items,
+  hipLaunchKernelGGL((k_trace_batch<USE_LDS, RECORD, SH>), dim3(blocks), dim3(blk), shmem, st, B.vars, B.items,
                      B.n_items, B.queue, B.blob_cap, R, H);
   return hipGetLastError();
 }

@@ -46,6 +46,7 @@ template <typename T> struct BatchView {
   uint32_t blob_cap;             // LDS bytes reserved for a variant's tables (0: read from global memory)
   uint32_t blob_cap_bwd;         // the same for the adjoint, whose LDS also holds the gradient sums
   int shapes;                    // bit 1 << shape of every shape in any variant
+  int block;                     // threads per workgroup of the forward launch (64..256)
 };
 
 // Batched launches are built for FP32 scenes (the sweep precision).

@@ -524,9 +524,63 @@ template <typename T> __device__ __forceinline__ T cubic_root_piece(const T* w, 
     if (!(sn >= a && sn <= b)) sn = T(0.5) * (a + b);   // s is an end: a fixed point stays put
     T ds = sn - s;
     s = sn;
-    if (dabs(ds) <= (sizeof(T) == 4 ? T(1e-7) : T(1e-16))) break;
+    // s lies in [0, 1]: a double step below 1e-14 leaves an error far under
+    // the tie margin of the search (a tolerance at the rounding unit would
+    // never be met by an iteration that alternates between neighbours)
+    if (dabs(ds) <= (sizeof(T) == 4 ? T(1e-7) : T(1e-14))) break;
   }
   return s;
+}
+
+// One wall of a hex cone against the local ray: the wall's cubic in Bernstein
+// form (zero where the ray meets the wall's surface of revolution cut by the
+// wall plane) and its monotone pieces, split at the critical points in
+// (0, 1).  False when the cubic vanishes identically.
+template <typename C> struct ConeWall {
+  C nx, ny, u0, du;
+  C w[4];
+  C br[4];
+  int nb;
+};
+
+template <typename C, typename P>
+__device__ __forceinline__ bool cone_wall(const P* p, int f, V3<C> o, V3<C> d, ConeWall<C>& W) {
+  wall_dir(f, W.nx, W.ny);
+  W.u0 = o.x * W.nx + o.y * W.ny;
+  W.du = d.x * W.nx + d.y * W.ny;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) W.w[k] = ((C)p[2 * k] - W.u0) * d.z - ((C)p[2 * k + 1] - o.z) * W.du;
+  if (W.w[0] == C(0) && W.w[1] == C(0) && W.w[2] == C(0) && W.w[3] == C(0)) return false;
+  // power-basis coefficients, used only to find the critical points
+  const C c1 = C(3) * (W.w[1] - W.w[0]), c2 = C(3) * (W.w[0] - C(2) * W.w[1] + W.w[2]);
+  const C c3 = W.w[3] - C(3) * W.w[2] + C(3) * W.w[1] - W.w[0];
+  W.nb = 0;
+  W.br[W.nb++] = C(0);
+  C q0, q1;
+  int nq;
+  quad2(C(3) * c3, C(2) * c2, c1, q0, q1, nq);
+  if (nq == 2 && q0 > q1) { C tq = q0; q0 = q1; q1 = tq; }
+  if (nq >= 1 && q0 > C(0) && q0 < C(1)) W.br[W.nb++] = q0;
+  if (nq == 2 && q1 > C(0) && q1 < C(1)) W.br[W.nb++] = q1;
+  W.br[W.nb++] = C(1);
+  return true;
+}
+
+// The wall point at parameter s: offered if it lies ahead within the current
+// best, passes the self rule and lies within the wall's hexagon sector.
+template <typename C, typename T>
+__device__ __forceinline__ void cone_hit(const DVol<T>& v, int vid, const ConeWall<C>& W, int f, C s, V3<C> o,
+                                         V3<C> d, C t0, C eps, C tbest, SelfRule sr, Best<T>& b) {
+  const C inv_sqrt3 = C(0.5773502691896258);
+  C rho, z, dr, dzs;
+  bez_eval(v.p, s, rho, z, dr, dzs);
+  C t = dabs(d.z) >= dabs(W.du) ? fdiv(z - o.z, d.z) : fdiv(rho - W.u0, W.du);
+  C tt = t + t0;
+  if (tt > tbest) return;
+  V3<C> xh = fma3(t, d, o);
+  if (!self_ok<HEXCONE>(v, sr, f, tt, eps, xh, d, s)) return;
+  C vt = -xh.x * W.ny + xh.y * W.nx;
+  if (dabs(vt) <= rho * inv_sqrt3) offer(b, (T)tt, vid, f, (double)s, (double)tt);
 }
 
 // The walls are solved in double for every scene precision: neighbouring
@@ -538,7 +592,6 @@ template <typename T> __device__ __forceinline__ T cubic_root_piece(const T* w, 
 template <typename C, typename T> __device__ __forceinline__ void nf_hexcone(const DVol<T>& v, int vid, V3<C> o, V3<C> d,
                                                                              C t0, C eps, SelfRule sr, Best<T>& b) {
   const T* p = v.p;
-  const C inv_sqrt3 = C(0.5773502691896258);
   const C tbest = (C)(b.tp + b.tie);
   {
     // the walls lie inside the hexagonal prism |x . n_k| <= rho_max,
@@ -567,48 +620,35 @@ template <typename C, typename T> __device__ __forceinline__ void nf_hexcone(con
     }
     if (!(ta <= tb)) return;
   }
+  // Every wall's monotone pieces first: a root at a piece's end is taken at
+  // once, a piece with a sign change inside is listed (bit 3 f + i) and all
+  // listed pieces are solved afterwards in one loop, so that the lanes of a
+  // wave run their Newton iterations side by side rather than one wall and
+  // one piece at a time.
+  uint32_t todo = 0;
   for (int f = 0; f < 6; ++f) {
-    C nx, ny;
-    wall_dir(f, nx, ny);
-    C u0 = o.x * nx + o.y * ny, du = d.x * nx + d.y * ny;
-    C w0 = ((C)p[0] - u0) * d.z - ((C)p[1] - o.z) * du;
-    C w1 = ((C)p[2] - u0) * d.z - ((C)p[3] - o.z) * du;
-    C w2 = ((C)p[4] - u0) * d.z - ((C)p[5] - o.z) * du;
-    C w3 = ((C)p[6] - u0) * d.z - ((C)p[7] - o.z) * du;
-    if (w0 == C(0) && w1 == C(0) && w2 == C(0) && w3 == C(0)) continue;
-    const C wv[4] = {w0, w1, w2, w3};
-    // power-basis coefficients, used only to split [0, 1] at the critical points
-    C c[4] = {w0, C(3) * (w1 - w0), C(3) * (w0 - C(2) * w1 + w2), w3 - C(3) * w2 + C(3) * w1 - w0};
-    // monotone pieces split at the critical points in (0, 1)
-    C br[4]; int nb = 0;
-    br[nb++] = C(0);
-    C q0, q1; int nq;
-    quad2(C(3) * c[3], C(2) * c[2], c[1], q0, q1, nq);
-    if (nq == 2 && q0 > q1) { C tq = q0; q0 = q1; q1 = tq; }
-    if (nq >= 1 && q0 > C(0) && q0 < C(1)) br[nb++] = q0;
-    if (nq == 2 && q1 > C(0) && q1 < C(1)) br[nb++] = q1;
-    br[nb++] = C(1);
-    C fa = c[0];
-    for (int i = 0; i + 1 < nb; ++i) {
-      C a = br[i], bb = br[i + 1];
+    ConeWall<C> W;
+    if (!cone_wall(p, f, o, d, W)) continue;
+    C fa = W.w[0];
+    for (int i = 0; i + 1 < W.nb; ++i) {
       C fb, fpb;
-      bern3(wv, bb, fb, fpb);
-      C s;
-      if (fa == C(0)) s = a;
-      else if (fb == C(0) && i + 2 == nb) s = bb;
-      else if ((fa > C(0)) != (fb > C(0))) s = cubic_root_piece(wv, a, bb, fa);
-      else { fa = fb; continue; }
+      bern3(W.w, W.br[i + 1], fb, fpb);
+      if (fa == C(0)) cone_hit(v, vid, W, f, W.br[i], o, d, t0, eps, tbest, sr, b);
+      else if (fb == C(0) && i + 2 == W.nb) cone_hit(v, vid, W, f, W.br[i + 1], o, d, t0, eps, tbest, sr, b);
+      else if ((fa > C(0)) != (fb > C(0))) todo |= 1u << (3 * f + i);
       fa = fb;
-      C rho, z, dr, dzs;
-      bez_eval(p, s, rho, z, dr, dzs);
-      C t = dabs(d.z) >= dabs(du) ? fdiv(z - o.z, d.z) : fdiv(rho - u0, du);
-      C tt = t + t0;
-      if (tt > tbest) continue;
-      V3<C> xh = fma3(t, d, o);
-      if (!self_ok<HEXCONE>(v, sr, f, tt, eps, xh, d, s)) continue;
-      C vt = -xh.x * ny + xh.y * nx;
-      if (dabs(vt) <= rho * inv_sqrt3) offer(b, (T)tt, vid, f, (double)s, (double)tt);
     }
+  }
+  while (todo) {
+    const int j = __builtin_ctz(todo);
+    todo &= todo - 1u;
+    const int f = j / 3, i = j - 3 * f;
+    ConeWall<C> W;
+    cone_wall(p, f, o, d, W);
+    C fa, fpa;
+    bern3(W.w, W.br[i], fa, fpa);
+    const C s = cubic_root_piece(W.w, W.br[i], W.br[i + 1], fa);
+    cone_hit(v, vid, W, f, s, o, d, t0, eps, tbest, sr, b);
   }
 }
 
@@ -718,11 +758,56 @@ __device__ __forceinline__ void run_cands(const SceneView<T>& S, Cands<T>& c, V3
   c.n = 0;
 }
 
+// Conservative cull of a hex cone before its exact test: its walls lie
+// inside the hexagonal prism |x . n_k| <= rho_max over its local z range.
+// Narrows tin (the box entry) to the ray's entry into that prism, padded by
+// 1e-4 of the cone's size so that rounding to T cannot cull a wall hit;
+// false when the ray misses the prism before tmax.  Run for every gathered
+// cone, it keeps neighbouring cones (whose boxes overlap the one the photon
+// is in) out of the candidate list, so that the lanes of a wave run few
+// exact cone tests.
+template <typename T>
+__device__ __forceinline__ bool cone_prism(const DVol<T>& v, V3<double> O, V3<T> d, T tmax, T& tin) {
+  const T* p = v.p;
+  const T rm = dmax(dmax(p[0], p[2]), dmax(p[4], p[6]));
+  const T pad = T(1e-4) * (rm + v.hi[2] - v.lo[2]);
+  const V3<T> ol = loc_pd(v, O), dl = loc_d(v, d);
+  T ta = tin, tb = tmax;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    T nx, ny;
+    wall_dir(k, nx, ny);
+    const T u0 = ol.x * nx + ol.y * ny, du = dl.x * nx + dl.y * ny;
+    if (du != T(0)) {
+      const T iu = frcp(du);
+      const T t1 = (-rm - pad - u0) * iu, t2 = (rm + pad - u0) * iu;
+      ta = dmax(ta, dmin(t1, t2));
+      tb = dmin(tb, dmax(t1, t2));
+    } else if (dabs(u0) > rm + pad) {
+      return false;
+    }
+  }
+  if (dl.z != T(0)) {
+    const T iz = frcp(dl.z);
+    const T t1 = (v.lo[2] - pad - ol.z) * iz, t2 = (v.hi[2] + pad - ol.z) * iz;
+    ta = dmax(ta, dmin(t1, t2));
+    tb = dmin(tb, dmax(t1, t2));
+  } else if (ol.z < v.lo[2] - pad || ol.z > v.hi[2] + pad) {
+    return false;
+  }
+  if (!(ta <= tb)) return false;
+  tin = ta;
+  return true;
+}
+
 template <typename T, int SH = kShapesAll>
 __device__ __forceinline__ void gather(const SceneView<T>& S, Cands<T>& c, int vid, V3<T> o, V3<T> inv, V3<double> O,
                                        V3<double> D, V3<T> d, int prev_vol, int prev_face, int prev_side, Best<T>& b) {
   T tin;
   if (!aabb(S.vol[vid], o, inv, b.t, tin)) return;
+  if constexpr (((SH >> HEXCONE) & 1) != 0) {
+    if (S.vol[vid].shape == HEXCONE && !cone_prism(S.vol[vid], O, d, b.t, tin)) return;
+  }
   if (c.n == Cands<T>::K) run_cands<T, SH>(S, c, O, D, d, prev_vol, prev_face, prev_side, b);
 #pragma unroll
   for (int j = 0; j < Cands<T>::K; ++j)
@@ -732,8 +817,11 @@ __device__ __forceinline__ void gather(const SceneView<T>& S, Cands<T>& c, int v
 
 // Non-sequential search: nearest face over the volume just left, the
 // always-list and the candidate groups crossed by the ray.
+// Inlined into its callers on purpose: as a called function it would take
+// the scene view and the best hit through the stack (scratch memory), which
+// the compiler does for the all-shape kernels if left to decide.
 template <typename T, int SH = kShapesAll>
-__device__ void find_nearest(const SceneView<T>& S, V3<double> O, V3<double> D, int prev_vol,
+__device__ __forceinline__ void find_nearest(const SceneView<T>& S, V3<double> O, V3<double> D, int prev_vol,
                                                    int prev_face, int prev_side, Best<T>& b) {
   b.t = tinf<T>(); b.vol = -1; b.face = -1; b.s = 0.0; b.tp = tinf<double>(); b.tie = S.eps_tie;
   const V3<T> d = to_t<T>(D);

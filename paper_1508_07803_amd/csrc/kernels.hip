@@ -41,6 +41,73 @@ __device__ __forceinline__ void flush_lane(double* acc_lds, int g, const double*
     if (a[k] != 0.0) atomicAdd(acc_lds + g * 8 + k, a[k]);
 }
 
+// Per-photon results of a finished photon: its records (RECORD), its path
+// record, and its share of the group sums, added to the lane's running sums
+// (flushed when the lane moves on to another group).
+template <typename T, bool RECORD, bool SUMS>
+__device__ __forceinline__ void finish_photon(const RaysView<T>& R, const HitsView<T>& H, int64_t cur, int g,
+                                              const PhotonState& ps, uint4 rec, double* a, int& ag,
+                                              double* acc_target) {
+  PhotonOut<T> r = photon_out<T>(ps);
+  if (H.path) {
+    if (r.fate != FOCUSED) rec.x = kPathSkip;
+    else if (r.nev > kPathSlots) rec.x = kPathLong;
+    reinterpret_cast<uint4*>(H.path)[cur] = rec;
+  }
+  if (RECORD) {
+    const int64_t o = R.src(cur);
+    if (H.fate) H.fate[o] = (uint8_t)r.fate;
+    if (H.nev) H.nev[o] = (uint8_t)r.nev;
+    if (H.last_vol) H.last_vol[o] = r.last_vol;
+    if (H.x) { H.x[o] = r.pos.x; H.y[o] = r.pos.y; H.z[o] = r.pos.z; }
+    if (H.ux) { H.ux[o] = r.dir.x; H.uy[o] = r.dir.y; H.uz[o] = r.dir.z; }
+    if (H.opl) H.opl[o] = r.opl;
+    if (H.hash) H.hash[o] = r.hash;
+  }
+  if (SUMS && g >= 0) {
+    if (g != ag && ag >= 0) {
+      flush_lane(acc_target, ag, a);
+#pragma unroll
+      for (int k = 0; k < kNSum; ++k) a[k] = 0.0;
+    }
+    ag = g;
+    a[0] += 1.0;
+    if (r.fate == FOCUSED) {
+      double x = (double)r.pos.x, y = (double)r.pos.y;
+      a[1] += 1.0; a[2] += x; a[3] += y; a[4] += x * x; a[5] += y * y;
+      a[6] += (double)dabs(r.dir.z);
+    }
+  }
+}
+
+// One interaction of the lane's photon, logged (seq_log) and kept in the
+// photon's path record (its first kPathSlots event codes).
+template <typename T, bool RECORD, int SH>
+__device__ __forceinline__ void step_photon(const SceneView<T>& L, const RaysView<T>& R, const HitsView<T>& H,
+                                            int64_t cur, PhotonState& ps, uint4& rec) {
+  const int k = ps.k;
+  const uint32_t code = photon_step<T, SH>(L, ps);
+  if (RECORD && H.seq_log && code != 0xffffffffu) H.seq_log[R.src(cur) * L.max_events + k] = code;
+  if (H.path) {
+    rec.x = k == 0 ? code : rec.x;
+    rec.y = k == 1 ? code : rec.y;
+    rec.z = k == 2 ? code : rec.z;
+    rec.w = k == 3 ? code : rec.w;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ int start_photon(const SceneView<T>& L, const RaysView<T>& R, int64_t cur,
+                                            PhotonState& ps, uint4& rec) {
+  T oa[3], da[3];
+  R.load(cur, oa, da);
+  int g = R.grp(cur);
+  if ((unsigned)g >= (unsigned)L.n_groups) g = -1;
+  photon_init(ps, V3<T>{oa[0], oa[1], oa[2]}, V3<T>{da[0], da[1], da[2]}, R.id_base + (uint64_t)R.src(cur), 0.0);
+  rec = uint4{kPathEnd, kPathEnd, kPathEnd, kPathEnd};
+  return g;
+}
+
 // FP32 kernels are held to 4 waves per SIMD (<= 128 VGPRs, a few spills):
 // measured faster than the 3 waves the unconstrained allocation gives, as
 // the extra wave hides LDS and memory latency of the search.
@@ -68,60 +135,18 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
   // One lane traces one photon start to finish (the event loop, §2.1), over
   // a persistent grid-stride walk of the (binned) bundle: consecutive lanes
   // take consecutive photons, which binning makes spatially close, so a
-  // wave's photons follow similar paths and finish at similar times.
+  // wave's photons follow similar paths event by event.  (Handing a lane the
+  // wave's next photon as soon as its own ends was measured slower, on the
+  // telescopes and on the many-bounce concentrator alike: lanes then sit at
+  // different events of their photons and diverge within each event.)
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t cur = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; cur < n; cur += stride) {
-    T oa[3], da[3];
-    R.load(cur, oa, da);
-    int g = R.grp(cur);
-    if ((unsigned)g >= (unsigned)S.n_groups) g = -1;
     PhotonState ps;
-    photon_init(ps, V3<T>{oa[0], oa[1], oa[2]}, V3<T>{da[0], da[1], da[2]}, R.id_base + (uint64_t)R.src(cur),
-                R.template wavelength<SH>(cur));
-    // the path record is built in registers and written once, as one 16-byte
-    // store (the records of a wave's photons are contiguous)
-    uint4 rec = {kPathEnd, kPathEnd, kPathEnd, kPathEnd};
-    while (!ps.fate) {
-      const int k = ps.k;
-      const uint32_t code = photon_step<T, SH>(L, ps);
-      if (RECORD && H.seq_log && code != 0xffffffffu) H.seq_log[R.src(cur) * S.max_events + k] = code;
-      if (H.path) {
-        rec.x = k == 0 ? code : rec.x;
-        rec.y = k == 1 ? code : rec.y;
-        rec.z = k == 2 ? code : rec.z;
-        rec.w = k == 3 ? code : rec.w;
-      }
-    }
-    PhotonOut<T> r = photon_out<T>(ps);
-    if (H.path) {
-      if (r.fate != FOCUSED) rec.x = kPathSkip;
-      else if (r.nev > kPathSlots) rec.x = kPathLong;
-      reinterpret_cast<uint4*>(H.path)[cur] = rec;
-    }
-    if (RECORD) {
-      const int64_t o = R.src(cur);
-      if (H.fate) H.fate[o] = (uint8_t)r.fate;
-      if (H.nev) H.nev[o] = (uint8_t)r.nev;
-      if (H.last_vol) H.last_vol[o] = r.last_vol;
-      if (H.x) { H.x[o] = r.pos.x; H.y[o] = r.pos.y; H.z[o] = r.pos.z; }
-      if (H.ux) { H.ux[o] = r.dir.x; H.uy[o] = r.dir.y; H.uz[o] = r.dir.z; }
-      if (H.opl) H.opl[o] = r.opl;
-      if (H.hash) H.hash[o] = r.hash;
-    }
-    if (SUMS && g >= 0) {
-      if (g != ag && ag >= 0) {
-        flush_lane(acc_target, ag, a);
-#pragma unroll
-        for (int k = 0; k < kNSum; ++k) a[k] = 0.0;
-      }
-      ag = g;
-      a[0] += 1.0;
-      if (r.fate == FOCUSED) {
-        double x = (double)r.pos.x, y = (double)r.pos.y;
-        a[1] += 1.0; a[2] += x; a[3] += y; a[4] += x * x; a[5] += y * y;
-        a[6] += (double)dabs(r.dir.z);
-      }
-    }
+    uint4 rec;
+    const int g = start_photon<T>(L, R, cur, ps, rec);
+    ps.lam = R.template wavelength<SH>(cur);
+    while (!ps.fate) step_photon<T, RECORD, SH>(L, R, H, cur, ps, rec);
+    finish_photon<T, RECORD, SUMS>(R, H, cur, g, ps, rec, a, ag, acc_target);
   }
   if (SUMS) {
     flush_lane(acc_target, ag, a);
@@ -242,7 +267,7 @@ static hipError_t device_cus(int& ncu) {
 
 template <typename T, bool RECORD, bool SUMS, bool USE_LDS, int SH>
 static hipError_t launch_one_s(const SceneView<T>& S, const RaysView<T>& R, int64_t n, const HitsView<T>& H,
-                             const LaunchCfg& cfg, hipStream_t st) {
+                               const LaunchCfg& cfg, hipStream_t st) {
   int ncu = 0;
   hipError_t e = device_cus(ncu);
   if (e != hipSuccess) return e;
@@ -250,14 +275,15 @@ static hipError_t launch_one_s(const SceneView<T>& S, const RaysView<T>& R, int6
   size_t sums_bytes = (size_t)S.n_groups * 8 * sizeof(double);
   bool sums_lds = SUMS && sums_bytes <= 16384;
   size_t shmem = (use_lds ? ((S.blob_bytes + 15u) & ~15u) : 0u) + (sums_lds ? sums_bytes : 0);
+  const int blk = cfg.block > 0 ? cfg.block : kBlock;
   int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace<T, RECORD, SUMS, USE_LDS, SH>, kBlock, shmem);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace<T, RECORD, SUMS, USE_LDS, SH>, blk, shmem);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
-  int64_t want = (n + kBlock - 1) / kBlock;
+  int64_t want = (n + blk - 1) / blk;
   int64_t cap = (int64_t)ncu * per_cu * (cfg.waves_mult > 0 ? cfg.waves_mult : 1);
   if (cfg.max_blocks > 0) cap = std::min<int64_t>(cap, cfg.max_blocks);
   int blocks = (int)std::max<int64_t>(1, std::min(want, cap));
-  hipLaunchKernelGGL((k_trace<T, RECORD, SUMS, USE_LDS, SH>), dim3(blocks), dim3(kBlock), shmem, st, S.self, R, n, H,
+  hipLaunchKernelGGL((k_trace<T, RECORD, SUMS, USE_LDS, SH>), dim3(blocks), dim3(blk), shmem, st, S.self, R, n, H,
                      sums_lds ? 1 : 0);
   return hipGetLastError();
 }

@@ -63,6 +63,7 @@ struct LaunchCfg {
   int lds_cap;      // stage the scene blob in LDS when it is at most this many bytes
   int waves_mult;   // persistent grid = CUs x resident blocks per CU x waves_mult
   int max_blocks;   // 0 = no cap
+  int block;        // threads per workgroup of the forward trace (64..256, a multiple of 64; 0 = 256)
 };
 
 // Backward-pass inputs: per-group cotangent coefficients of the objective

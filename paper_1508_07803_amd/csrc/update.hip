@@ -57,10 +57,19 @@ __device__ __forceinline__ double sag_sphere(double c, double r) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kUpdBlock) k_update_params(const UpdJob<T>* const* jobs, const double* params,
-                                                             const int64_t* poff, int32_t* status) {
+__global__ void __launch_bounds__(kUpdBlock) k_update_params(const UpdJob<T>* const* jobs, double* params,
+                                                             const int64_t* poff, int32_t* status,
+                                                             const double* grad, const double* lr) {
   const UpdJob<T>& J = *jobs[blockIdx.x];
-  const double* P = params + (poff ? poff[blockIdx.x] : 0);
+  const int64_t po = poff ? poff[blockIdx.x] : 0;
+  const double* P = params + po;
+  if (grad) {
+    // gradient-descent step: the candidate parameters go to the job's
+    // scratch; params takes them only if the update is applied
+    for (int i = threadIdx.x; i < J.n_params; i += blockDim.x) J.pn[i] = P[i] - lr[po + i] * grad[po + i];
+    __syncthreads();
+    P = J.pn;
+  }
   __shared__ int s_bad;
   __shared__ const char* s_src;
   if (threadIdx.x == 0) {
@@ -249,6 +258,8 @@ __global__ void __launch_bounds__(kUpdBlock) k_update_params(const UpdJob<T>* co
     grecs[g].zmin = round_down<T>(z0 - G.zpad);
     grecs[g].zmax = round_up<T>(z1 + G.zpad);
   }
+  if (grad)
+    for (int i = threadIdx.x; i < J.n_params; i += blockDim.x) params[po + i] = J.pn[i];
   __syncthreads();
   if (threadIdx.x == 0) {
     SceneView<T> nv = cur;
@@ -266,16 +277,16 @@ __global__ void __launch_bounds__(kUpdBlock) k_update_params(const UpdJob<T>* co
 }
 
 template <typename T>
-hipError_t launch_update_params(const UpdJob<T>* const* jobs, int n_jobs, const double* params, const int64_t* poff,
-                                int32_t* status, hipStream_t st) {
+hipError_t launch_update_params(const UpdJob<T>* const* jobs, int n_jobs, double* params, const int64_t* poff,
+                                int32_t* status, hipStream_t st, const double* grad, const double* lr) {
   if (n_jobs < 1) return hipSuccess;
-  hipLaunchKernelGGL(k_update_params<T>, dim3(n_jobs), dim3(kUpdBlock), 0, st, jobs, params, poff, status);
+  hipLaunchKernelGGL(k_update_params<T>, dim3(n_jobs), dim3(kUpdBlock), 0, st, jobs, params, poff, status, grad, lr);
   return hipGetLastError();
 }
 
-template hipError_t launch_update_params<float>(const UpdJob<float>* const*, int, const double*, const int64_t*,
-                                                int32_t*, hipStream_t);
-template hipError_t launch_update_params<double>(const UpdJob<double>* const*, int, const double*, const int64_t*,
-                                                 int32_t*, hipStream_t);
+template hipError_t launch_update_params<float>(const UpdJob<float>* const*, int, double*, const int64_t*, int32_t*,
+                                                hipStream_t, const double*, const double*);
+template hipError_t launch_update_params<double>(const UpdJob<double>* const*, int, double*, const int64_t*,
+                                                 int32_t*, hipStream_t, const double*, const double*);
 
 }  // namespace robast

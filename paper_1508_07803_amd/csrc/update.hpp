@@ -48,7 +48,8 @@ template <typename T> struct UpdJob {
   const UpdGroup* groups;  // n_grp
   const uint16_t* members;
   double* zr;              // scratch, 2 per volume: group-frame z range
-  int32_t n_vol, n_grp;
+  double* pn;              // scratch, n_params: the parameters of a gradient step
+  int32_t n_vol, n_grp, n_params;
   uint32_t blob_bytes;
   double l_ref;
 };
@@ -57,8 +58,12 @@ template <typename T> struct UpdJob {
 // (if status) becomes 0 when applied, ROBAST_EINVAL for parameters that make
 // a surface invalid, ROBAST_EUNSUPPORTED when a surface would leave its
 // grid cells; in both cases the scene keeps its tables.
+// With grad and lr (same offsets as params), a gradient-descent step: the
+// new parameters are params - lr * grad, and params takes them where the
+// update is applied (and keeps its values where it is not).
 template <typename T>
-hipError_t launch_update_params(const UpdJob<T>* const* jobs, int n_jobs, const double* params, const int64_t* poff,
-                                int32_t* status, hipStream_t st);
+hipError_t launch_update_params(const UpdJob<T>* const* jobs, int n_jobs, double* params, const int64_t* poff,
+                                int32_t* status, hipStream_t st, const double* grad = nullptr,
+                                const double* lr = nullptr);
 
 }  // namespace robast

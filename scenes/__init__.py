@@ -581,6 +581,8 @@ def device_rays(scene, n, seed, group=0, device="cuda"):
     geometry as Scene.rays, a different random stream).  Returns a dict of
     device tensors in the scene precision plus int32 groups."""
     import torch
+    if "beam" not in scene.meta and "cells" in scene.meta:
+        return _device_cone_rays(scene, n, seed, group, device)
     b = scene.meta["beam"]
     gen = torch.Generator(device=device)
     gen.manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
@@ -608,6 +610,42 @@ def device_rays(scene, n, seed, group=0, device="cuda"):
     out = dict(ox=ox.to(dt), oy=oy.to(dt), oz=oz.to(dt))
     for k, val in zip(("dx", "dy", "dz"), d):
         out[k] = torch.full((n,), val, dtype=dt, device=device)
+    out["group"] = torch.full((n,), int(group), dtype=torch.int32, device=device)
+    return out
+
+
+def _device_cone_rays(scene, n, seed, group, device):
+    """The concentrator's photons for one incidence angle on the device: the
+    recipe of its host generator (a uniformly chosen cone, a uniform point
+    of its entrance hexagon, a uniform azimuth), from torch's seeded
+    generator."""
+    import torch
+    m = scene.meta
+    f64 = torch.float64
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
+    cells = torch.as_tensor(np.asarray(m["cells"]), dtype=f64, device=device)
+    a_in, L, zl = float(m["control"][3][0]), float(m["length"]), float(m["z_launch"])
+    k = torch.randint(0, len(cells), (n,), generator=gen, device=device)
+    half = torch.tensor([a_in, a_in * 2.0 / math.sqrt(3.0)], dtype=f64, device=device)
+    pts, need = [], n
+    while need > 0:
+        c = (torch.rand(int(need * 1.4) + 64, 2, generator=gen, device=device, dtype=f64) * 2.0 - 1.0) * half
+        ok = torch.ones(len(c), dtype=torch.bool, device=device)
+        for ang in (0.0, math.pi / 3.0, 2.0 * math.pi / 3.0):
+            ok &= (c[:, 0] * math.cos(ang) + c[:, 1] * math.sin(ang)).abs() <= a_in
+        c = c[ok][:need]
+        pts.append(c)
+        need -= len(c)
+    pts = torch.cat(pts)
+    ph = torch.rand(n, generator=gen, device=device, dtype=f64) * (2.0 * math.pi)
+    th = float(scene.groups[group])
+    dx, dy = math.sin(th) * torch.cos(ph), math.sin(th) * torch.sin(ph)
+    dz = torch.full((n,), -math.cos(th), dtype=f64, device=device)
+    s = (zl - L) / math.cos(th)
+    dt = torch.float32 if scene.precision == 32 else torch.float64
+    out = dict(ox=(cells[k, 0] + pts[:, 0] - s * dx).to(dt), oy=(cells[k, 1] + pts[:, 1] - s * dy).to(dt),
+               oz=(L - s * dz).to(dt), dx=dx.to(dt), dy=dy.to(dt), dz=dz.to(dt))
     out["group"] = torch.full((n,), int(group), dtype=torch.int32, device=device)
     return out
 

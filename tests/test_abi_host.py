@@ -166,6 +166,9 @@ def test_tuning_arguments_rejected(rb):
     assert lib.robast_get_tuning(None, ctypes.byref(t)) == rb.EINVAL
     assert lib.robast_set_tuning(None, ctypes.byref(t)) == rb.EINVAL
     assert lib.robast_autotune(None, None, 10, None, None) == rb.EINVAL
+    assert lib.robast_autotune_batch(None, None, None, None, None) == rb.EINVAL
+    assert lib.robast_gd_step(None, None, None, None, None, None) == rb.EINVAL
+    assert lib.robast_gd_step_batch(None, None, None, None, None, None) == rb.EINVAL
 
 
 def test_binding_checks_extents_before_launch(rb):

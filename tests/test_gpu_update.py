@@ -263,3 +263,190 @@ def test_host_set_params_checks_geometry_first(rb):
     after, _ = _trace(rb, dev, rays, n)
     for k in KEYS:
         assert torch.equal(before[k], after[k]), k
+
+
+def _gd_inputs(sc, seed, scale=1.0):
+    """A gradient-like vector and per-parameter steps that move the SC's
+    coefficients by ~1e-4 relative and its tilts by ~2e-5 rad (x scale)."""
+    rng = np.random.default_rng(seed)
+    g = rng.normal(0.0, 1.0, len(sc.params))
+    lr = np.where(np.arange(len(sc.params)) < 16, 1e-4 * np.abs(sc.params), 2e-5) * scale
+    return g, lr
+
+
+def test_gd_step_applies_the_step(rb):
+    """robast_gd_step: params become p - lr * g (FP64, to rounding), and the
+    scene traces exactly as one updated to those parameters; a step that
+    would move a panel out of its grid cells is rejected and leaves both
+    the parameters and the scene as they were."""
+    sc = scenes.schwarzschild_couder()
+    r = sc.rays(2000)
+    dev = rb.Scene(sc)
+    rays = dev.upload_rays(r)
+    n = len(r["ox"])
+    g, lr = _gd_inputs(sc, 5)
+    P = torch.from_numpy(sc.params.copy()).cuda()
+    G, LR = torch.from_numpy(g).cuda(), torch.from_numpy(lr).cuda()
+    st = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+    dev.gd_step(P, G, LR, status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    want = sc.params - lr * g
+    got = P.cpu().numpy()
+    assert np.allclose(got, want, rtol=1e-15, atol=1e-18)
+    assert not np.array_equal(got, sc.params)
+    h1, s1 = _trace(rb, dev, rays, n)
+    ref = rb.Scene(sc)
+    ref.update_params_device(P.clone())
+    h2, s2 = _trace(rb, ref, rays, n)
+    for k in KEYS:
+        assert torch.equal(h1[k], h2[k]), k
+    assert torch.allclose(s1, s2, rtol=1e-12, atol=1e-12 * float(s2.abs().max()))   # FP64 summation order
+    # a step far beyond the grid's margin: rejected, nothing changes
+    before = P.clone()
+    dev.gd_step(P, G, LR * 1e4, status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == rb.EUNSUPPORTED
+    assert torch.equal(P, before)
+    h3, _ = _trace(rb, dev, rays, n)
+    for k in KEYS:
+        assert torch.equal(h1[k], h3[k]), k
+
+
+def test_gd_steps_in_a_graph_equal_eager_steps(rb):
+    """One optimisation step -- trace, figures, adjoint of the mean RMS,
+    gradient step on the device -- captured once and replayed 3 times
+    equals 3 eager steps on a second copy of the scene (parameters to
+    FP64 summation order of the gradient, RMS per step)."""
+    sc = scenes.schwarzschild_couder()
+    r = sc.rays(3000)
+    cot = torch.zeros(sc.n_groups, 2, dtype=torch.float64, device="cuda")
+    cot[:, 0] = 1.0 / sc.n_groups
+    _, lr = _gd_inputs(sc, 6)
+    # steps sized from the first gradient so that 3 of them stay in the grid margin
+    probe = rb.Scene(sc)
+    rays = probe.upload_rays(r)
+    s0 = probe.new_sums()
+    probe.trace(rays, sums=s0)
+    g0 = torch.zeros(len(sc.params), dtype=torch.float64, device="cuda")
+    probe.backward(rays, s0, cot, g0)
+    torch.cuda.synchronize()
+    g0 = g0.cpu().numpy()
+    lr = lr / np.maximum(np.abs(g0), 1e-300 + np.abs(g0).max() * 1e-3)
+    LR = torch.from_numpy(lr).cuda()
+
+    def make():
+        dev = rb.Scene(sc)
+        state = dict(dev=dev, P=torch.from_numpy(sc.params.copy()).cuda(), sums=dev.new_sums(),
+                     fig=torch.zeros(sc.n_groups * rb.FIGURE_STRIDE, dtype=torch.float64, device="cuda"),
+                     grad=torch.zeros(len(sc.params), dtype=torch.float64, device="cuda"),
+                     st=torch.zeros(1, dtype=torch.int32, device="cuda"))
+        return state
+
+    def step(S, stream=None):
+        S["sums"].zero_()
+        S["grad"].zero_()
+        S["dev"].trace(rays, sums=S["sums"], stream=stream, keep_order=True)
+        S["dev"].figures(S["sums"], fig=S["fig"], stream=stream)
+        S["dev"].backward(rays, S["sums"], cot, S["grad"], stream=stream)
+        S["dev"].gd_step(S["P"], S["grad"], LR, status=S["st"], stream=stream)
+
+    A, B = make(), make()
+    # both copies take their tables from a device update (at the start
+    # parameters), so that the two follow one rounding of the FP32 tables
+    B["dev"].update_params_device(B["P"])
+    # warm A eagerly on a side stream (grows its workspaces), then undo the
+    # step it took, and capture
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step(A, stream=s.cuda_stream)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    A["P"].copy_(torch.from_numpy(sc.params.copy()))
+    A["dev"].update_params_device(A["P"])
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step(A, stream=torch.cuda.current_stream().cuda_stream)
+    for rep in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        step(B)
+        torch.cuda.synchronize()
+        assert int(A["st"].item()) == 0 and int(B["st"].item()) == 0, rep
+        assert torch.equal(A["sums"][0::8], B["sums"][0::8]), rep
+        assert torch.allclose(A["fig"][4::8], B["fig"][4::8], rtol=1e-12), rep
+        assert torch.allclose(A["P"], B["P"], rtol=1e-12, atol=0.0), rep
+        _ = (rays["ox"] * 2.0).sum().item()   # eager work between replays
+    assert not torch.equal(A["P"], torch.from_numpy(sc.params).cuda())
+
+
+def test_batched_gd_step_equals_per_scene_steps(rb):
+    """robast_gd_step_batch equals each variant's robast_gd_step (the same
+    new parameters bit for bit, the same photons)."""
+    variants, _ = scenes.sweep(n_dc=2, n_sc=2, seed=scenes.SEED_BASE + 62)
+    devs = [rb.Scene(v) for v in variants]
+    counts = [2500, 2000, 1500, 3000]
+    host = [v.rays(c, seed=51 + i) for i, (v, c) in enumerate(zip(variants, counts))]
+    rays = {k: torch.cat([d.upload_rays(h)[k] for d, h in zip(devs, host)]) for k in
+            ("ox", "oy", "oz", "dx", "dy", "dz", "group")}
+    batch = rb.Batch(devs, counts, chunk=1000)
+    rng = np.random.default_rng(12)
+    gs, lrs = [], []
+    for v in variants:
+        gs.append(rng.normal(0.0, 1.0, len(v.params)))
+        if v.name.startswith("schwarz"):
+            lrs.append(np.where(np.arange(len(v.params)) < 16, 1e-4 * np.abs(v.params), 2e-5))
+        else:
+            nf = v.meta["n_facets"]
+            lrs.append(np.where(np.arange(len(v.params)) < nf, 1e-3 * np.abs(v.params), 2e-5))
+    P = torch.from_numpy(np.concatenate([v.params for v in variants])).cuda()
+    G = torch.from_numpy(np.concatenate(gs)).cuda()
+    LR = torch.from_numpy(np.concatenate(lrs)).cuda()
+    st = torch.full((len(devs),), 7, dtype=torch.int32, device="cuda")
+    batch.gd_step(P, G, LR, status=st)
+    hits = devs[0].alloc_hits(sum(counts))
+    batch.trace(rays, hits=hits)
+    torch.cuda.synchronize()
+    assert st.tolist() == [0] * len(devs)
+    off = poff = 0
+    for v, (sc, c) in enumerate(zip(variants, counts)):
+        d = rb.Scene(sc)
+        p = torch.from_numpy(sc.params.copy()).cuda()
+        d.gd_step(p, torch.from_numpy(gs[v]).cuda(), torch.from_numpy(lrs[v]).cuda())
+        sub = {k: t[off:off + c] for k, t in rays.items()}
+        h1 = d.alloc_hits(c)
+        d.trace(sub, hits=h1)
+        torch.cuda.synchronize()
+        assert torch.equal(P[poff:poff + len(sc.params)], p), v
+        for k in KEYS:
+            assert torch.equal(hits[k][off:off + c], h1[k]), (v, k)
+        off += c
+        poff += len(sc.params)
+
+
+def test_batch_autotune_keeps_results(rb):
+    """robast_autotune_batch picks a work-item and workgroup size; photons
+    traced with the pick equal those of the default launch bit for bit."""
+    variants, _ = scenes.sweep(n_dc=2, n_sc=2, seed=scenes.SEED_BASE + 63)
+    devs = [rb.Scene(v) for v in variants]
+    counts = [40000, 3000, 60000, 5000]
+    host = [v.rays(c // v.n_groups, seed=61 + i) for i, (v, c) in enumerate(zip(variants, counts))]
+    counts = [len(h["ox"]) for h in host]
+    rays = {k: torch.cat([d.upload_rays(h)[k] for d, h in zip(devs, host)]) for k in
+            ("ox", "oy", "oz", "dx", "dy", "dz", "group")}
+    batch = rb.Batch(devs, counts, chunk=4096)
+    n = sum(counts)
+    ref = devs[0].alloc_hits(n)
+    rs = batch.new_sums()
+    batch.trace(rays, hits=ref, sums=rs)
+    best = batch.autotune(rays)
+    assert best["chunk"] in (2048, 8192, 32768, 131072) and best["block"] in (128, 256)
+    hits = devs[0].alloc_hits(n)
+    s = batch.new_sums()
+    batch.trace(rays, hits=hits, sums=s)
+    torch.cuda.synchronize()
+    for k in KEYS:
+        assert torch.equal(ref[k], hits[k]), k
+    assert torch.allclose(rs, s, rtol=1e-12, atol=1e-12 * float(rs.abs().max()))
