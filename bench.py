@@ -354,6 +354,20 @@ def run_config(args, torch, rb, scenes, sc, npf, objective, cpu_per_group, descr
             t["step"].append(evs[0].elapsed_time(evs[4]))
     ms = {k: float(np.mean(v)) for k, v in t.items()}
     figs = fig.view(sc.n_groups, rb.FIGURE_STRIDE).cpu().numpy()
+    boundary = None
+    if objective == "eff":
+        # the boundary (fate-flip) gradient of the mean collection efficiency,
+        # edge sampling in a band of 0.01, on the same photons
+        gb = torch.zeros(len(sc.params), dtype=torch.float64, device="cuda")
+        ceta = torch.full((sc.n_groups,), 1.0 / sc.n_groups, dtype=torch.float64, device="cuda")
+        a, b = ev(torch), ev(torch)
+        a.record()
+        dev.boundary_grad(rays, sums, ceta, gb, band=0.01)
+        b.record()
+        torch.cuda.synchronize()
+        boundary = {"ms": a.elapsed_time(b), "band": 0.01, "gradient": gb.cpu().numpy().tolist(),
+                    "params": list(sc.param_names)}
+        print(f"[bench] {sc.name}: boundary gradient {boundary['ms']:.1f} ms", file=sys.stderr, flush=True)
     tally = oracle.trace(sc, sc.rays(max(1, 40000 // sc.n_groups), seed=sc.seed + 77), log=True)
     ops_fwd, ops_adj = ops_per_photon(sc, tally)
     rk = {"k_trace": roofline(ops_fwd, n, ms["trace"]), "k_backward_path": roofline(ops_adj, n, ms["adjoint"])}
@@ -368,7 +382,7 @@ def run_config(args, torch, rb, scenes, sc, npf, objective, cpu_per_group, descr
             "adjoint_ms": ms["adjoint"], "trace_photons_per_s": n / (ms["trace"] / 1e3),
             "roofline": dict(rk[dominant], kernel=dominant), "roofline_kernels": rk, "cpu_baseline": cpu,
             ("rms_spot" if objective == "rms" else "efficiency"): figs[:, col].tolist(),
-            "gradient_norm": float(grad.norm())}
+            "gradient_norm": float(grad.norm()), "boundary_gradient": boundary}
 
 
 def run_single_mirror(args, torch, rb, scenes):

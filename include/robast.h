@@ -281,6 +281,35 @@ int robast_trace_backward(robast_scene* scene, const robast_rays* rays, int64_t 
                           const double* d_group_cot, const double* d_photon_cot, double* d_grad, uint32_t flags,
                           void* hip_stream);
 
+/* Boundary (fate-flip) terms of the gradient of the collection efficiency
+ * eta_g = N_FOCUSED,g / N_launched,g (§3: the concentrators' collection;
+ * the count changes only through photons whose fate flips as the geometry
+ * moves, so robast_trace_backward, which holds every fate fixed, gives it no
+ * gradient).  Estimated by edge sampling: every event of a photon's path
+ * that lies within band / 2 of an edge of its face -- a cone wall's seams
+ * with its neighbours, its exit rim and its entrance rim, an exit
+ * aperture's hexagon (focal surfaces with a hexagonal outline), and the
+ * Fresnel decision at a lens face (distance R - u in probability) -- is
+ * moved just across that edge and traced on with the same draws; where the
+ * fate differs, the edge's flux (d delta / dp by a reverse sweep from that
+ * event, plus the edge's own motion) is added.  Objective
+ * L = sum_g cot[g] eta_g; the estimate is unbiased as band -> 0, its noise
+ * grows as 1 / sqrt(N band).  Edges of other faces (telescope facet edges,
+ * shadow edges) are not sampled.
+ *   d_group_sums [device] the forward trace's group sums of the same photons
+ *                (for N_launched,g)
+ *   d_group_cot  [device] n_groups doubles cot[g]
+ *   band         band width in (0, 1), in each edge's own distance units
+ *                (fraction of the wall's lateral half-width at a seam, of
+ *                the wall's parameter at its rims, of the aperture's
+ *                inradius, of probability at a Fresnel decision)
+ *   d_grad       [device] n_params doubles, ACCUMULATED (+=)
+ * Photons are read in the caller's order (no binning).  EINVAL on NULL
+ * arguments, n < 0, band outside (0, 1); EUNSUPPORTED for per-photon
+ * wavelengths or max_events > 32. */
+int robast_boundary_grad(robast_scene* scene, const robast_rays* rays, int64_t n, const double* d_group_sums,
+                         const double* d_group_cot, double band, double* d_grad, void* hip_stream);
+
 /* Bin photons [0, n) now and keep the order, as a trace call with
  * ROBAST_TRACE_KEEP_ORDER would (a no-op when binning is off or n is outside
  * the binning range).  Lets a caller time the binning apart from the trace,

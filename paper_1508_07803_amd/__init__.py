@@ -32,7 +32,7 @@ SYMBOLS = ["robast_build_scene", "robast_trace", "robast_figures", "robast_trace
            "robast_figures_batch", "robast_trace_backward_batch", "robast_batch_sizes", "robast_destroy_batch",
            "robast_get_tuning", "robast_set_tuning", "robast_autotune", "robast_bin_photons",
            "robast_arrival_figures", "robast_trace_static", "robast_set_params", "robast_update_params_batch",
-           "robast_gd_step", "robast_gd_step_batch", "robast_autotune_batch"]
+           "robast_gd_step", "robast_gd_step_batch", "robast_autotune_batch", "robast_boundary_grad"]
 
 
 class VolumeDesc(ctypes.Structure):
@@ -88,6 +88,8 @@ _lib.robast_update_params.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c
 _lib.robast_set_params.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
 _lib.robast_update_params_batch.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
 _lib.robast_gd_step.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 5
+_lib.robast_boundary_grad.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ctypes.c_int64, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
 _lib.robast_gd_step_batch.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 5
 _lib.robast_autotune_batch.argtypes = [ctypes.c_void_p, ctypes.POINTER(Rays), ctypes.POINTER(ctypes.c_uint32),
                                        ctypes.POINTER(ctypes.c_uint32), ctypes.c_void_p]
@@ -118,7 +120,7 @@ for _name in ("robast_build_scene", "robast_trace", "robast_figures", "robast_tr
               "robast_figures_batch", "robast_trace_backward_batch", "robast_batch_sizes", "robast_get_tuning",
               "robast_set_tuning", "robast_autotune", "robast_bin_photons", "robast_arrival_figures",
               "robast_trace_static", "robast_set_params", "robast_update_params_batch", "robast_gd_step",
-              "robast_gd_step_batch", "robast_autotune_batch"):
+              "robast_gd_step_batch", "robast_autotune_batch", "robast_boundary_grad"):
     getattr(_lib, _name).restype = ctypes.c_int
 
 
@@ -369,6 +371,20 @@ class Scene:
         flags = BACKWARD_CHECK_SEQ if check else 0
         _check(_lib.robast_trace_backward(self._h, ctypes.byref(R), n, ctypes.byref(H), _ptr(cot), _ptr(photon_cot),
                                           _ptr(grad), flags, _stream(stream)), "robast_trace_backward")
+        return grad
+
+    def boundary_grad(self, rays, sums, cot, grad, band=0.02, n=None, id_base=0, stream=None):
+        """Accumulate into grad the boundary (fate-flip) terms of
+        d/dparams sum_g cot[g] eta_g, eta_g the collection efficiency of
+        group g (robast_boundary_grad; sums: the forward group sums of the
+        same photons; cot: n_groups float64)."""
+        n = int(rays["ox"].numel()) if n is None else int(n)
+        _check_extents(n, self.dtype, rays, None, [("grad", grad, self.n_params),
+                                                   ("sums", sums, self.n_groups * GROUP_STRIDE),
+                                                   ("cot", cot, self.n_groups)])
+        R = self._rays_struct(rays, id_base)
+        _check(_lib.robast_boundary_grad(self._h, ctypes.byref(R), n, _ptr(sums), _ptr(cot), float(band), _ptr(grad),
+                                         _stream(stream)), "robast_boundary_grad")
         return grad
 
     @property

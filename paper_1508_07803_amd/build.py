@@ -7,7 +7,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librobast.so")
-SOURCES = ["abi.cpp", "kernels.hip", "adjoint.hip", "batch.hip", "batch_bwd.hip", "binning.hip", "update.hip"]
+SOURCES = ["abi.cpp", "kernels.hip", "adjoint.hip", "batch.hip", "batch_bwd.hip", "binning.hip", "update.hip",
+           "boundary.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 (v_pk_*_f32) is disabled: the tracer's arithmetic is scalar

@@ -17,6 +17,7 @@
 
 #include "../../include/robast.h"
 #include "batch.hpp"
+#include "boundary.hpp"
 #include "binning.hpp"
 #include "kernels.hpp"
 #include "scene_layout.hpp"
@@ -1455,6 +1456,26 @@ int robast_trace_backward(robast_scene* s, const robast_rays* rays, int64_t n, c
   if (e == hipSuccess) e = hipMemcpy(&bad, s->d_check, sizeof(bad), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "sequence check readback");
   if (bad) return fail(ROBAST_EMISMATCH, std::to_string(bad) + " photons' surface sequences differ from the forward pass");
+  return ROBAST_OK;
+}
+
+int robast_boundary_grad(robast_scene* s, const robast_rays* rays, int64_t n, const double* group_sums,
+                         const double* group_cot, double band, double* grad, void* stream) {
+  if (!s || !rays || !group_sums || !group_cot || !grad)
+    return fail(ROBAST_EINVAL, "NULL scene, rays, group sums, cotangents or grad");
+  if (n < 0) return fail(ROBAST_EINVAL, "n < 0");
+  if (!(band > 0.0 && band < 1.0)) return fail(ROBAST_EINVAL, "band must lie in (0, 1)");
+  int rc = check_rays(rays);
+  if (rc) return rc;
+  if (rays->lambda) return fail(ROBAST_EUNSUPPORTED, "the boundary gradient takes no per-photon wavelengths");
+  if (s->max_events > kBndMaxEvents) return fail(ROBAST_EUNSUPPORTED, "the boundary gradient supports max_events <= 32");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = s->precision == 32
+                     ? launch_boundary<float>(s->sf, rays_view<float>(rays), n, group_sums, group_cot, s->d_coef, band,
+                                              grad, (int)s->params.size(), s->cfg.lds_cap, st)
+                     : launch_boundary<double>(s->sd, rays_view<double>(rays), n, group_sums, group_cot, s->d_coef,
+                                               band, grad, (int)s->params.size(), s->cfg.lds_cap, st);
+  if (e != hipSuccess) return hip_fail(e, "boundary gradient launch");
   return ROBAST_OK;
 }
 

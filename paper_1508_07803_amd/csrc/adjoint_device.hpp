@@ -37,9 +37,9 @@ __device__ __forceinline__ void seed_cots(const double* cf, const double* pc, V3
 }
 
 struct GradSink {
-  double* acc;   // LDS or global
+  double* acc;   // LDS or global; null: partials are dropped
   __device__ __forceinline__ void add(int i, double v) {
-    if (v != 0.0) atomicAdd(acc + i, v);
+    if (v != 0.0 && acc) atomicAdd(acc + i, v);
   }
 };
 

@@ -169,6 +169,7 @@ def test_tuning_arguments_rejected(rb):
     assert lib.robast_autotune_batch(None, None, None, None, None) == rb.EINVAL
     assert lib.robast_gd_step(None, None, None, None, None, None) == rb.EINVAL
     assert lib.robast_gd_step_batch(None, None, None, None, None, None) == rb.EINVAL
+    assert lib.robast_boundary_grad(None, None, 10, None, None, 0.01, None, None) == rb.EINVAL
 
 
 def test_binding_checks_extents_before_launch(rb):
