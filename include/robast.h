@@ -128,7 +128,10 @@ typedef struct {
  * interaction and tag 2 for bulk absorption in a lens -- so a photon's result
  * never depends on launch shape or on which other photons share the launch. */
 typedef struct {
-  const void *ox, *oy, *oz, *dx, *dy, *dz; /* [device] n each, float or double */
+  const void *ox, *oy, *oz, *dx, *dy, *dz; /* [device] n each, float or double; (dx, dy, dz)
+                                            * a unit vector: a photon whose |d|^2 is off 1
+                                            * by more than 1e-5 (or with a non-finite
+                                            * coordinate) is not traced and ends FAILED */
   const uint32_t* group;                   /* [device] n, < n_groups; NULL = all group 0 */
   uint64_t id_base;
   const void* lambda;  /* [device] n wavelengths (metres, float or double), or NULL.  A

@@ -635,8 +635,10 @@ Rec trace_one(const Scn& S, V3<double> o, V3<double> d, double lam, uint64_t id,
   int prev_v = -1, prev_f = -1, prev_side = 0;
   const double eps_self = 1e-9 * S.l_ref, eps_tie = 1e-12 * S.l_ref;
   std::vector<Hit> hits;
+  // a photon is a position and a unit direction (§2.1); any other input
+  // (non-finite, or |d| off 1 by more than rounding) is refused, not traced
   if (!(std::isfinite(o.x) && std::isfinite(o.y) && std::isfinite(o.z) && std::isfinite(d.x) &&
-        std::isfinite(d.y) && std::isfinite(d.z)) || dot(d, d) == 0.0) {
+        std::isfinite(d.y) && std::isfinite(d.z)) || !(std::fabs(dot(d, d) - 1.0) <= 1e-5)) {
     r.fate = F_FAILED;
   }
   int k = 0;

@@ -1009,7 +1009,9 @@ template <typename T> __device__ __forceinline__ void photon_init(PhotonState& p
   p.d = {(double)d.x, (double)d.y, (double)d.z};
   p.ncur = 1.0; p.opl = 0.0; p.lam = lam; p.hash = 0xcbf29ce484222325ull; p.id = id;
   p.k = 0; p.prev_v = -1; p.prev_f = -1; p.prev_side = 0; p.fate = 0; p.last_vol = -1;
-  if (!finite3(o) || !finite3(d) || dot(d, d) == T(0)) p.fate = FAILED;
+  // directions must be unit vectors (to rounding): a photon with any other
+  // ends FAILED rather than being traced with wrong path lengths and angles
+  if (!finite3(o) || !finite3(d) || !(dabs(dot(d, d) - T(1)) <= T(1e-5))) p.fate = FAILED;
 }
 
 // One interaction of the non-sequential transport: nearest surface, then the

@@ -271,3 +271,56 @@ def test_chromatic_batch_full_size(rb):
         off += c
     print(f"chromatic batch: sampled {total} photons, {total_bad} grazing mismatches")
     assert total_bad <= max(3, 1e-5 * total)
+
+
+def test_concentrator_full_size_adjoint(rb):
+    """Gradient of the mean weighted collection over 91 angles x 1e6 photons
+    (device-generated, binned, path records kept: the benchmark's step):
+    additive over the two halves of the bundle, and restricted to sampled
+    photons against the oracle's dual numbers with the full-size
+    coefficients."""
+    import oracle
+    sc = scenes.hex_concentrator()
+    npf = 1_000_000
+    rays = device_bundle(sc, npf)
+    n = int(rays["ox"].numel())
+    dev = rb.Scene(sc)
+    sums = dev.new_sums()
+    dev.trace(rays, sums=sums, keep_order=True)
+    cot = torch.zeros(sc.n_groups, 2, dtype=torch.float64, device="cuda")
+    cot[:, 1] = 1.0 / sc.n_groups
+    g_full = torch.zeros(len(sc.params), dtype=torch.float64, device="cuda")
+    dev.backward(rays, sums, cot, g_full)
+    h = n // 2 + 4321
+    g_halves = torch.zeros_like(g_full)
+    dev.backward({k: v[:h] for k, v in rays.items()}, sums, cot, g_halves, n=h)
+    dev.backward({k: v[h:] for k, v in rays.items()}, sums, cot, g_halves, n=n - h, id_base=h)
+    torch.cuda.synchronize()
+    scale = float(g_full.abs().max())
+    assert scale > 0
+    assert torch.allclose(g_full, g_halves, rtol=1e-9, atol=1e-12 * scale)
+
+    # sampled photons of every 7th angle, coefficients b_g = cot_g / N_g of
+    # the full-size sums
+    nl = sums.view(sc.n_groups, 8)[:, 0].cpu().numpy()
+    g_gpu = torch.zeros_like(g_full)
+    g_ref = np.zeros(len(sc.params))
+    for g in range(0, sc.n_groups, 7):
+        start = g * npf + npf // 5
+        cnt = 2000
+        sub = {k: v[start:start + cnt] for k, v in rays.items()}
+        dev.backward(sub, sums, cot, g_gpu, n=cnt, id_base=start)
+        host = host_block(rays, start, cnt)
+        rec = oracle.trace(sc, host, id_base=start, log=True)
+        foc = rec["fate"] == scenes.FATE_FOCUSED
+        b = (1.0 / sc.n_groups) / nl[g]
+        _, ddir, st = oracle.forced_jac(sc, host, rec, sc.params, 0, len(sc.params))
+        m = foc & (st == 0)
+        sgn = np.sign(rec["dir"][m, 2])
+        g_ref += b * np.einsum("n,nj->j", sgn, ddir[m][:, 2, :])
+    torch.cuda.synchronize()
+    got = g_gpu.cpu().numpy()
+    big = np.abs(g_ref).max()
+    assert big > 0
+    err = np.abs(got - g_ref) / np.maximum(np.abs(g_ref), 1e-2 * big)
+    assert err.max() <= 1e-3, (int(np.argmax(err)), got, g_ref)

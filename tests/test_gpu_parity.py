@@ -262,10 +262,13 @@ def test_max_events_and_failed(rb):
     sc.max_events = 1
     r = sc.rays(3000)
     r["dz"][5] = np.nan
+    for k in ("dx", "dy", "dz"):
+        r[k][11] *= 1.5     # not a unit direction: refused on both sides
     got = gpu_trace(rb, sc, r)
     ref = oracle.trace(sc, r)
     assert np.array_equal(got["fate"], ref["fate"])
     assert got["fate"][5] == scenes.FATE_FAILED
+    assert got["fate"][11] == scenes.FATE_FAILED
 
 
 def test_group_sums_match_records(rb):

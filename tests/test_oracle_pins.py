@@ -160,6 +160,24 @@ def test_empty_scene_and_failed(orc):
     assert rec["fate"][3] == scenes.FATE_FAILED
 
 
+def test_non_unit_directions_are_refused(orc):
+    """A photon's direction is a unit vector (§2.1): a scaled one is refused
+    (FAILED) rather than traced with wrong path lengths; one off by rounding
+    is traced as usual."""
+    sc = scenes.single_mirror()
+    r = sc.rays(200)
+    base = orc.trace(sc, r)
+    for k in ("dx", "dy", "dz"):
+        r[k][7] *= 2.0
+        r[k][9] *= 1.0 + 2e-7
+    rec = orc.trace(sc, r)
+    assert rec["fate"][7] == scenes.FATE_FAILED
+    assert rec["fate"][9] == base["fate"][9] != scenes.FATE_FAILED
+    keep = np.ones(len(r["ox"]), bool)
+    keep[[7, 9]] = False
+    assert np.array_equal(rec["fate"][keep], base["fate"][keep])
+
+
 # ------------------------------------------------------------------ Fresnel / Snell
 def test_fresnel_closed_forms(orc):
     n = 1.49
