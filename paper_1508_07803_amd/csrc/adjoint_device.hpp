@@ -291,54 +291,56 @@ __device__ __forceinline__ void event_adjoint(const DVol<T>& v, const DTilt* til
   db = dbar;
 }
 
-// Reverse sweep along a photon's recorded sequence of `nev` events (codes
-// vol << 8 | face << 4 | action) from its initial ray.  The state entering
-// event e is recomputed by replaying events 0..e-1 (one exact intersection
-// each, no search).  The objective's cotangents start at the last event:
+// State entering an event of a recorded path: origin, direction, and the
+// root (distance, cone wall parameter) of the event's intersection.
+struct PathState {
+  V3<double> O, d;
+  double t, s;
+};
+
+// Reverse sweep along a photon's recorded sequence of `nev` <= MAXE events
+// (codes vol << 8 | face << 4 | action) from its initial ray.  The sequence
+// is replayed forward once (one exact intersection per event, no search)
+// and the states entering the events are kept in a lane-local array, so the
+// sweep costs one replay per event however long the path (a many-bounce
+// concentrator photon).  The objective's cotangents start at the last event:
 // those of the final position (rounded to T like the photon's record) and of
 // the sign of its final direction.  Returns false if a replayed intersection
 // no longer yields the recorded (volume, face), which an unchanged scene
-// cannot produce; the photon then adds nothing further.
-template <typename T, int SH = kShapesAll>
+// cannot produce; the photon then adds nothing.
+template <typename T, int MAXE, int SH = kShapesAll>
 __device__ __forceinline__ bool reverse_sweep(const SceneView<T>& L, const AdjView& A, GradSink& gs,
                                               const double* cf, const double* pc, V3<T> o0, V3<T> d0,
                                               const uint32_t* codes, int nev, double lam) {
-  const V3<double> O0 = {(double)o0.x, (double)o0.y, (double)o0.z};
-  const V3<double> D0 = {(double)d0.x, (double)d0.y, (double)d0.z};
-  V3<double> Xb = {0.0, 0.0, 0.0}, db = {0.0, 0.0, 0.0};
-  for (int e = nev - 1; e >= 0; --e) {
-    // state entering event e, replayed along the recorded sequence
-    V3<double> O = O0;
-    V3<double> d = D0;
-    int pv = -1, pf = -1, ps = 0;
-    for (int j = 0; j < e; ++j) {
-      const int vid = (int)(codes[j] >> 8), face = (int)((codes[j] >> 4) & 15u), act = (int)(codes[j] & 15u);
-      double t, s;
-      if (!replay_root<T, SH>(L, vid, face, O, d, pv, pf, ps, t, s)) return false;
-      const DVol<T>& v = L.vol[vid];
-      V3<double> X = {O.x + t * d.x, O.y + t * d.y, O.z + t * d.z};
-      V3<double> nrm = front_normal<T, SH>(v, face, X, s);
-      int back;
-      apply_action(v, nrm, act, d, back, lens_index<SH>(v, lam));
-      O = X; pv = vid; pf = face; ps = back ^ (act == ACT_REFRACT ? 1 : 0);
-    }
+  PathState st[MAXE];
+  V3<double> O = {(double)o0.x, (double)o0.y, (double)o0.z};
+  V3<double> d = {(double)d0.x, (double)d0.y, (double)d0.z};
+  int pv = -1, pf = -1, ps = 0;
+  for (int e = 0; e < nev; ++e) {
     const int vid = (int)(codes[e] >> 8), face = (int)((codes[e] >> 4) & 15u), act = (int)(codes[e] & 15u);
     double t, s;
     if (!replay_root<T, SH>(L, vid, face, O, d, pv, pf, ps, t, s)) return false;
-    if (e == nev - 1) {
-      const V3<double> X = {O.x + t * d.x, O.y + t * d.y, O.z + t * d.z};
-      V3<double> dout = d;
-      if (act == ACT_REFLECT || act == ACT_REFRACT) {
-        int back;
-        apply_action(L.vol[vid], front_normal<T, SH>(L.vol[vid], face, X, s), act, dout, back,
-                     lens_index<SH>(L.vol[vid], lam));
-      }
-      seed_cots<T>(cf, pc, X, dout, Xb, db);
+    st[e] = PathState{O, d, t, s};
+    const DVol<T>& v = L.vol[vid];
+    const V3<double> X = {O.x + t * d.x, O.y + t * d.y, O.z + t * d.z};
+    if (act == ACT_REFLECT || act == ACT_REFRACT) {
+      int back;
+      apply_action(v, front_normal<T, SH>(v, face, X, s), act, d, back, lens_index<SH>(v, lam));
+      ps = back ^ (act == ACT_REFRACT ? 1 : 0);
+    } else {
+      ps = dot(d, front_normal<T, SH>(v, face, X, s)) < 0.0 ? 0 : 1;
     }
+    O = X; pv = vid; pf = face;
+  }
+  // the final position and direction: O and d after the last event
+  V3<double> Xb, db;
+  seed_cots<T>(cf, pc, O, d, Xb, db);
+  for (int e = nev - 1; e >= 0; --e) {
+    const int vid = (int)(codes[e] >> 8), face = (int)((codes[e] >> 4) & 15u), act = (int)(codes[e] & 15u);
     // the pull-back runs in FP64 from the replayed state: the per-photon
     // partials are summed with cancellation (centroid-subtracted
     // cotangents), which FP32 arithmetic would not resolve
-    event_adjoint<double, T, SH>(L.vol[vid], A.tilt + vid, face, act, O, d, t, s, Xb, db, gs,
+    event_adjoint<double, T, SH>(L.vol[vid], A.tilt + vid, face, act, st[e].O, st[e].d, st[e].t, st[e].s, Xb, db, gs,
                                  lens_index<SH>(L.vol[vid], lam));
   }
   return true;
@@ -365,15 +367,8 @@ __device__ __forceinline__ void adjoint_photon(const SceneView<T>& L, const Rays
   PhotonOut<T> r = trace_photon<T, MAXE, SH>(L, o0, d0, R.id_base + (uint64_t)R.src(i), codes, lam);
   if (A.check_hash && A.check_hash[R.src(i)] != r.hash) atomicAdd(A.mismatch, 1u);
   if (!want || r.fate != FOCUSED || r.nev > MAXE) return;
-  (void)reverse_sweep<T, SH>(L, A, gs, cf, pc, o0, d0, codes, r.nev, lam);
+  (void)reverse_sweep<T, MAXE, SH>(L, A, gs, cf, pc, o0, d0, codes, r.nev, lam);
 }
-
-// State entering an event of a recorded path: origin, direction, and the
-// root (distance, cone wall parameter) of the event's intersection.
-struct PathState {
-  V3<double> O, d;
-  double t, s;
-};
 
 // Volume record in double (the pull-back then reads no FP32 field).
 template <typename T> __device__ __forceinline__ DVol<double> promote(const DVol<T>& v) {
