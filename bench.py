@@ -593,6 +593,8 @@ def main():
     ap.add_argument("--config-steps", type=int, default=3)
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the single-mirror, Davies-Cotton and concentrator sections")
+    ap.add_argument("--configs", default="single_mirror,davies_cotton,hex_concentrator",
+                    help="which of those sections to run (comma-separated)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--sweep-steps", type=int, default=20)
@@ -684,18 +686,21 @@ def main():
         nm: run_chromatic(args, torch, rb, scenes, nm) for nm in ("aspheric_lens", "fresnel_lens")}
     configs = None
     if not args.no_configs:
-        configs = {
-            "single_mirror": run_single_mirror(args, torch, rb, scenes),
-            "davies_cotton": run_config(
+        want = set(args.configs.split(","))
+        runs = {
+            "single_mirror": lambda: run_single_mirror(args, torch, rb, scenes),
+            "davies_cotton": lambda: run_config(
                 args, torch, rb, scenes, scenes.davies_cotton(), 10_000_000, "rms", 1_000_000,
                 "davies_cotton: 5 fields (0-2 deg) x 1e7 photons, 198 spherical facets, camera box and masts; "
                 "binning + trace + figures + adjoint of the mean RMS (594 params: radii, tilts)"),
-            "hex_concentrator": run_config(
+            "hex_concentrator": lambda: run_config(
                 args, torch, rb, scenes, scenes.hex_concentrator(), 1_000_000, "eff", 11_000,
                 "hex_concentrator: 91 incidence angles (0-45 deg) x 1e6 photons, 8x8 Bezier hex cones under a "
                 "PMMA window, up to 32 events; binning + trace + figures + adjoint of the mean weighted "
-                "collection efficiency (4 control-point coordinates)"),
+                "collection efficiency (4 control-point coordinates), and the boundary gradient of the "
+                "mean collection efficiency"),
         }
+        configs = {k: f() for k, f in runs.items() if k in want}
 
     # algorithmic op tallies from the reference tracer's event log
     import oracle
