@@ -111,7 +111,8 @@ __device__ __forceinline__ int start_photon(const SceneView<T>& L, const RaysVie
 // FP32 kernels are held to 4 waves per SIMD (<= 128 VGPRs, a few spills):
 // measured faster than the 3 waves the unconstrained allocation gives, as
 // the extra wave hides LDS and memory latency of the search.
-// SH: the shape set compiled in (kShapesNoCone for scenes without hex cones,
+// SH: the shape set compiled in (kShapesMirrors for scenes of mirrors and
+// focal surfaces only, kShapesNoCone for other scenes without hex cones,
 // else kShapesAll).
 template <typename T, bool RECORD, bool SUMS, bool USE_LDS, int SH>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1, 8))) k_trace(const SceneView<T>* Sp, RaysView<T> R, int64_t n, HitsView<T> H,
@@ -296,6 +297,7 @@ static hipError_t launch_one_l(const SceneView<T>& S, const RaysView<T>& R, int6
   if (R.lam && S.dispersive)
     return launch_one_s<T, RECORD, SUMS, USE_LDS, kShapesNoCone | kLambda>(S, R, n, H, cfg, st);
   if (S.shapes & ~kShapesNoCone) return launch_one_s<T, RECORD, SUMS, USE_LDS, kShapesAll>(S, R, n, H, cfg, st);
+  if (!(S.shapes & ~kShapesMirrors)) return launch_one_s<T, RECORD, SUMS, USE_LDS, kShapesMirrors>(S, R, n, H, cfg, st);
   return launch_one_s<T, RECORD, SUMS, USE_LDS, kShapesNoCone>(S, R, n, H, cfg, st);
 }
 

@@ -20,9 +20,12 @@ enum Fate { FOCUSED = 1, ABSORBED = 2, EXITED = 3, SUSPENDED = 4, FAILED = 5 };
 // Shape sets the tracing kernels are compiled for (bit 1 << shape): every
 // shape, or every shape but the hex cone, for scenes without hex cones (the
 // cone's root solver, the largest, then stays out of the kernel and its
-// register allocation).
+// register allocation); the forward trace has a third set, mirrors and
+// focal surfaces only (no cylinder or box: telescopes without masts or a
+// camera body), whose search keeps fewer values in scratch.
 constexpr int kShapesAll = (1 << PLANE) | (1 << SPHERE) | (1 << ASPHERE) | (1 << CYLINDER) | (1 << BOX) | (1 << HEXCONE);
 constexpr int kShapesNoCone = kShapesAll & ~(1 << HEXCONE);
+constexpr int kShapesMirrors = (1 << PLANE) | (1 << SPHERE) | (1 << ASPHERE);
 // Kernel option joined to a shape set: photons carry their own wavelengths
 // and dispersive lenses refract them with n(lambda).
 constexpr int kLambda = 1 << 16;

@@ -210,7 +210,7 @@ def test_chromatic_batch(rb, n_per):
             sub = {k: val[:2000] for k, val in host[v].items()}
             got = as_numpy(hits, slice(off, off + 2000))
             ref = oracle.trace(variants[v], sub, log=True)
-            compare(variants[v], sub, got, ref, 1e-5 * variants[v].l_ref, 1e-5, max_rate=1e-3)
+            compare(variants[v], sub, got, ref, 1e-5 * variants[v].l_ref, 1e-5)
         off += c
     # the plane sits at the 400 nm paraxial focus; spherical aberration puts
     # the best focus inside it, where longer wavelengths focus: the blue end
@@ -330,6 +330,6 @@ def test_full_size_variants_sampled_against_oracle(rb):
             host = {k: rays[k][sl].double().cpu().numpy() for k in ("ox", "oy", "oz", "dx", "dy", "dz")}
             host["group"] = rays["group"][sl].cpu().numpy().astype(np.uint32)
             rec = oracle.trace(sc, host, id_base=start, log=True)
-            compare(sc, host, as_numpy(hits, sl), rec, 1e-5 * sc.l_ref, 1e-5, max_rate=1e-3, id_base=start)
+            compare(sc, host, as_numpy(hits, sl), rec, 1e-5 * sc.l_ref, 1e-5, id_base=start)
         assert float(sums[batch.goff[v] * 8]) == c
         off += c
