@@ -314,7 +314,8 @@ def roofline(ops, n, ms, traffic=None):
 def run_config(args, torch, rb, scenes, sc, npf, objective, cpu_per_group, describe):
     """One config's step on the device: binning + forward trace with group
     sums + figures + adjoint of the objective (objective: "rms" or "eff",
-    the mean over the groups), per-phase times from HIP events, the roofline
+    the mean over the groups), under the launch tuning the autotuner picks
+    on a sample of the bundle, per-phase times from HIP events, the roofline
     of both kernels from the reference tracer's event log, and the CPU
     baseline."""
     import oracle
@@ -327,6 +328,10 @@ def run_config(args, torch, rb, scenes, sc, npf, objective, cpu_per_group, descr
     torch.cuda.synchronize()
     print(f"[bench] {sc.name}: {n:.3e} photons generated on the device in {time.time() - t0:.1f}s",
           file=sys.stderr, flush=True)
+    # launch tuning from the autotuner on every 8th photon (all groups)
+    t0 = time.time()
+    tuning = dev.autotune({k: v[::8].contiguous() for k, v in rays.items()})
+    print(f"[bench] {sc.name}: autotuned {tuning} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     sums = dev.new_sums()
     fig = torch.zeros(sc.n_groups * rb.FIGURE_STRIDE, dtype=torch.float64, device="cuda")
     grad = torch.zeros(len(sc.params), dtype=torch.float64, device="cuda")
@@ -379,7 +384,7 @@ def run_config(args, torch, rb, scenes, sc, npf, objective, cpu_per_group, descr
     col = 4 if objective == "rms" else 5
     return {"workload": describe, "photons": n, "ms_per_step": ms["step"],
             "photons_per_s": n / (ms["step"] / 1e3), "binning_ms": ms["binning"], "trace_ms": ms["trace"],
-            "adjoint_ms": ms["adjoint"], "trace_photons_per_s": n / (ms["trace"] / 1e3),
+            "adjoint_ms": ms["adjoint"], "trace_photons_per_s": n / (ms["trace"] / 1e3), "tuning": tuning,
             "roofline": dict(rk[dominant], kernel=dominant), "roofline_kernels": rk, "cpu_baseline": cpu,
             ("rms_spot" if objective == "rms" else "efficiency"): figs[:, col].tolist(),
             "gradient_norm": float(grad.norm()), "boundary_gradient": boundary}

@@ -307,7 +307,10 @@ int robast_trace_backward(robast_scene* scene, const robast_rays* rays, int64_t 
  *                the wall's parameter at its rims, of the aperture's
  *                inradius, of probability at a Fresnel decision)
  *   d_grad       [device] n_params doubles, ACCUMULATED (+=)
- * Photons are read in the caller's order (no binning).  EINVAL on NULL
+ * With binning on (robast_tuning) the photons are processed in binned
+ * order: a kept order of the same arrays is reused and stays kept, else the
+ * bundle is binned into the scene's workspace (allocated on first need) and
+ * kept, and path records of an earlier order are dropped.  EINVAL on NULL
  * arguments, n < 0, band outside (0, 1); EUNSUPPORTED for per-photon
  * wavelengths or max_events > 32. */
 int robast_boundary_grad(robast_scene* scene, const robast_rays* rays, int64_t n, const double* d_group_sums,
@@ -335,9 +338,16 @@ typedef struct robast_tuning {
   uint32_t block;        /* threads per workgroup of the forward trace: 64, 128, 192 or 256
                             (0 reads as 256); each workgroup stages the scene's tables into
                             LDS once, so smaller workgroups stage more often */
+  uint32_t bin_dirs;     /* azimuth sectors of the photon direction in the binning key: 1, 4,
+                            16 or 64 (0 reads as 1).  Above 1, photons of a group are ordered
+                            by the sector of atan2(dy, dx) first, then by cell (the grid then
+                            has bin_dirs times fewer cells per sector, so a cell still aims at
+                            bin_target photons): for bundles whose directions vary within a
+                            group (a concentrator lit from all azimuths), where photons that
+                            start together but leave in different directions diverge */
 } robast_tuning;
 
-/* Defaults: bin_photons 1, bin_target 128, waves_mult 4, block 256. */
+/* Defaults: bin_photons 1, bin_target 128, waves_mult 4, block 256, bin_dirs 1. */
 int robast_get_tuning(const robast_scene* scene, robast_tuning* out);
 /* EINVAL on NULL arguments or a field out of range. */
 int robast_set_tuning(robast_scene* scene, const robast_tuning* tuning);
@@ -345,8 +355,10 @@ int robast_set_tuning(robast_scene* scene, const robast_tuning* tuning);
 /* Autotuner: traces photons [0, n) of `rays` (group sums only, into its own
  * scratch) under candidate tunings (binning off; binning with 32, 128 or 512
  * photons per cell; grid multiplier 1, 4 or 8; workgroups of 128 or 256
- * threads), times each with HIP events on the stream, keeps the fastest in
- * the scene and returns it in *best (may be NULL).  Synchronous; allocates;
+ * threads; then, with the best grid multiplier and workgroup size so far,
+ * 4 or 16 direction sectors at 32 or 128 photons per cell), times each with
+ * HIP events on the stream, keeps the fastest in the scene and returns it in
+ * *best (may be NULL).  Synchronous; allocates;
  * EINVAL as robast_trace or n < 1.  Iteration caps of the root solvers are
  * not tuned: they decide results, which no tuning may change. */
 int robast_autotune(robast_scene* scene, const robast_rays* rays, int64_t n, robast_tuning* best,
@@ -484,6 +496,7 @@ void robast_destroy_batch(robast_batch* batch);
 
 const char* robast_status_string(int status);
 const char* robast_last_error(void);
+/* Version of this interface's layouts: 2 (robast_tuning has bin_dirs). */
 int robast_abi_version(void);
 
 #ifdef __cplusplus

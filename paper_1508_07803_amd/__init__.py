@@ -19,6 +19,10 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'`")
 
 _lib = ctypes.CDLL(LIB_PATH)
+ABI_VERSION = 2   # the layouts below (robast_tuning with bin_dirs)
+if _lib.robast_abi_version() != ABI_VERSION:
+    raise ImportError(f"{LIB_PATH} has ABI version {_lib.robast_abi_version()}, this binding expects "
+                      f"{ABI_VERSION}; rebuild it")
 
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, EMISMATCH = 0, -1, -2, -3, -4, -5
 GROUP_STRIDE = 8
@@ -66,7 +70,7 @@ class Hits(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("bin_photons", ctypes.c_uint32), ("bin_target", ctypes.c_uint32),
-                ("waves_mult", ctypes.c_uint32), ("block", ctypes.c_uint32)]
+                ("waves_mult", ctypes.c_uint32), ("block", ctypes.c_uint32), ("bin_dirs", ctypes.c_uint32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

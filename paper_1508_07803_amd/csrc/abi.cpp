@@ -1044,10 +1044,21 @@ void apply_tuning(robast_scene* s) {
 }
 
 bool block_valid(uint32_t b) { return b == 0 || b == 64 || b == 128 || b == 192 || b == 256; }
+bool dirs_valid(uint32_t d) { return d == 0 || d == 1 || d == 4 || d == 16 || d == 64; }
+uint32_t bin_dirs(const robast_tuning& t) { return t.bin_dirs ? t.bin_dirs : 1u; }
+
+// Cells per side of the binning grid: about `target` photons per cell over
+// G groups x `dirs` direction sectors, within the key range.
+int bin_cells(int64_t n, int G, uint32_t target, uint32_t dirs) {
+  const double per_cell = (double)std::max<int64_t>(n, 1) / ((double)G * (double)dirs * (double)target);
+  const int nc = (int)std::floor(std::sqrt(std::max(1.0, per_cell)));
+  const int nc_max = (int)std::floor(std::sqrt((double)kBinsMax / ((double)G * (double)dirs)));
+  return std::max(1, std::min({nc, 1024, nc_max}));
+}
 
 int tuning_valid(const robast_tuning& t) {
   return t.bin_target >= 1 && t.bin_target <= 65536 && t.waves_mult >= 1 && t.waves_mult <= 64 &&
-         block_valid(t.block);
+         block_valid(t.block) && dirs_valid(t.bin_dirs);
 }
 
 
@@ -1078,11 +1089,9 @@ int binned_view(robast_scene* s, const robast_rays* rays, int64_t n, hipStream_t
   }
   s->kept = false;   // the workspace is about to be overwritten
   const int G = s->n_groups;
-  const double per_cell = (double)n / ((double)G * (double)s->tuning.bin_target);
-  int nc = (int)std::floor(std::sqrt(std::max(1.0, per_cell)));
-  const int nc_max = (int)std::floor(std::sqrt((double)kBinsMax / G));
-  nc = std::max(1, std::min({nc, 1024, nc_max}));
-  const int64_t bins = (int64_t)G * nc * nc;
+  const uint32_t dirs = bin_dirs(s->tuning);
+  const int nc = bin_cells(n, G, s->tuning.bin_target, dirs);
+  const int64_t bins = (int64_t)G * dirs * nc * nc;
   const BinPlan plan = bin_plan<T>(n, bins);
   if (ext) {
     if (plan.bytes > ext_bytes)
@@ -1091,7 +1100,7 @@ int binned_view(robast_scene* s, const robast_rays* rays, int64_t n, hipStream_t
                                      " bytes of the static workspace (about " +
                                      std::to_string(ext_bytes / (2 * sizeof(BinRecord<T>) + 8)) + " photons)");
     const BinWork<T> W = bin_carve<T>(plan, ext);
-    const BinGeom geo{s->bin_z, s->bin_x0, s->bin_y0, (double)nc / s->bin_side, nc, G, 0u, 0u};
+    const BinGeom geo{s->bin_z, s->bin_x0, s->bin_y0, (double)nc / s->bin_side, nc, G, 0u, dirs};
     hipError_t e = launch_binning<T>(R, n, geo, BinMulti{nullptr, nullptr, 0}, plan, W, st);
     if (e != hipSuccess) return hip_fail(e, "binning launch");
     out = binned_rays<T>(W.out, rays->group != nullptr, rays->id_base);
@@ -1108,7 +1117,7 @@ int binned_view(robast_scene* s, const robast_rays* rays, int64_t n, hipStream_t
     s->work_bytes = plan.bytes;
   }
   const BinWork<T> W = bin_carve<T>(plan, s->d_work);
-  const BinGeom geo{s->bin_z, s->bin_x0, s->bin_y0, (double)nc / s->bin_side, nc, G, 0u, 0u};
+  const BinGeom geo{s->bin_z, s->bin_x0, s->bin_y0, (double)nc / s->bin_side, nc, G, 0u, dirs};
   hipError_t e = launch_binning<T>(R, n, geo, BinMulti{nullptr, nullptr, 0}, plan, W, st);
   if (e != hipSuccess) return hip_fail(e, "binning launch");
   out = binned_rays<T>(W.out, rays->group != nullptr, rays->id_base);
@@ -1244,9 +1253,27 @@ void free_batch(robast_batch* b) {
 
 }  // namespace
 
+// The boundary gradient over the binned order (a kept order of the same
+// arrays is reused and stays kept; else the bundle is binned and kept, and
+// path records of an earlier order are dropped): the photons of a wave then
+// replay similar paths, as in the trace.
+template <typename T>
+int boundary_t(robast_scene* s, const SceneView<T>& V, const robast_rays* rays, int64_t n, const double* group_sums,
+               const double* group_cot, double band, double* grad, hipStream_t st) {
+  RaysView<T> R;
+  bool reused = false;
+  int rc = binned_view<T>(s, rays, n, st, R, true, &reused);
+  if (rc) return rc;
+  if (R.perm && !reused) s->path_ok = false;
+  hipError_t e = launch_boundary<T>(V, R, n, group_sums, group_cot, s->d_coef, band, grad, (int)s->params.size(),
+                                    s->cfg.lds_cap, st);
+  if (e != hipSuccess) return hip_fail(e, "boundary gradient launch");
+  return ROBAST_OK;
+}
+
 extern "C" {
 
-int robast_abi_version(void) { return 1; }
+int robast_abi_version(void) { return 2; }
 
 const char* robast_status_string(int st) {
   switch (st) {
@@ -1280,7 +1307,7 @@ int robast_build_scene(const robast_scene_desc* desc, const double* params, int6
   s->cfg.lds_cap = kLdsCap;
   s->cfg.max_blocks = 0;
   s->cfg.block = 256;
-  s->tuning = robast_tuning{1u, 128u, 4u, 256u};
+  s->tuning = robast_tuning{1u, 128u, 4u, 256u, 1u};
   apply_tuning(s);
   rc = upload(s);
   if (rc) {
@@ -1470,13 +1497,8 @@ int robast_boundary_grad(robast_scene* s, const robast_rays* rays, int64_t n, co
   if (rays->lambda) return fail(ROBAST_EUNSUPPORTED, "the boundary gradient takes no per-photon wavelengths");
   if (s->max_events > kBndMaxEvents) return fail(ROBAST_EUNSUPPORTED, "the boundary gradient supports max_events <= 32");
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = s->precision == 32
-                     ? launch_boundary<float>(s->sf, rays_view<float>(rays), n, group_sums, group_cot, s->d_coef, band,
-                                              grad, (int)s->params.size(), s->cfg.lds_cap, st)
-                     : launch_boundary<double>(s->sd, rays_view<double>(rays), n, group_sums, group_cot, s->d_coef,
-                                               band, grad, (int)s->params.size(), s->cfg.lds_cap, st);
-  if (e != hipSuccess) return hip_fail(e, "boundary gradient launch");
-  return ROBAST_OK;
+  return s->precision == 32 ? boundary_t<float>(s, s->sf, rays, n, group_sums, group_cot, band, grad, st)
+                            : boundary_t<double>(s, s->sd, rays, n, group_sums, group_cot, band, grad, st);
 }
 
 int robast_bin_photons(robast_scene* s, const robast_rays* rays, int64_t n, void* stream) {
@@ -1531,27 +1553,34 @@ int robast_autotune(robast_scene* s, const robast_rays* rays, int64_t n, robast_
   float win_ms = INFINITY;
   robast_hits hits{};
   hits.group_sums = sums;
-  for (uint32_t bin = 0; bin < 2 && e == hipSuccess && !rc; ++bin)
+  // times one candidate (the first of two runs warms up) and keeps the fastest
+  auto time_one = [&](const robast_tuning& t) {
+    if (e != hipSuccess || rc) return;
+    s->tuning = t;
+    apply_tuning(s);
+    float ms = 0.0f;
+    for (int rep = 0; rep < 2 && e == hipSuccess && !rc; ++rep) {
+      e = hipMemsetAsync(sums, 0, sizeof(double) * 8 * s->n_groups, st);
+      if (e == hipSuccess) e = hipEventRecord(e0, st);
+      if (e == hipSuccess) rc = robast_trace(s, rays, n, &hits, 0, stream);
+      if (e == hipSuccess && !rc) e = hipEventRecord(e1, st);
+      if (e == hipSuccess && !rc) e = hipEventSynchronize(e1);
+      if (e == hipSuccess && !rc) e = hipEventElapsedTime(&ms, e0, e1);
+    }
+    if (e == hipSuccess && !rc && ms < win_ms) {
+      win_ms = ms;
+      win = s->tuning;
+    }
+  };
+  for (uint32_t bin = 0; bin < 2; ++bin)
     for (uint32_t target : {32u, 128u, 512u})
       for (uint32_t mult : {1u, 4u, 8u})
-        for (uint32_t block : {128u, 256u}) {
-        if (e != hipSuccess || rc || (!bin && target != 128u)) continue;
-        s->tuning = robast_tuning{bin, target, mult, block};
-        apply_tuning(s);
-        float ms = 0.0f;
-        for (int rep = 0; rep < 2 && e == hipSuccess && !rc; ++rep) {   // first run warms up
-          e = hipMemsetAsync(sums, 0, sizeof(double) * 8 * s->n_groups, st);
-          if (e == hipSuccess) e = hipEventRecord(e0, st);
-          if (e == hipSuccess) rc = robast_trace(s, rays, n, &hits, 0, stream);
-          if (e == hipSuccess && !rc) e = hipEventRecord(e1, st);
-          if (e == hipSuccess && !rc) e = hipEventSynchronize(e1);
-          if (e == hipSuccess && !rc) e = hipEventElapsedTime(&ms, e0, e1);
-        }
-        if (e == hipSuccess && !rc && ms < win_ms) {
-          win_ms = ms;
-          win = s->tuning;
-        }
-        }
+        for (uint32_t block : {128u, 256u})
+          if (bin || target == 128u) time_one(robast_tuning{bin, target, mult, block, 1u});
+  // direction sectors, with the launch shape found so far
+  const robast_tuning shape = win;
+  for (uint32_t dirs : {4u, 16u})
+    for (uint32_t target : {32u, 128u}) time_one(robast_tuning{1u, target, shape.waves_mult, shape.block, dirs});
   s->tuning = (e == hipSuccess && !rc) ? win : saved;
   apply_tuning(s);
   if (e0) (void)hipEventDestroy(e0);
@@ -1664,11 +1693,10 @@ int robast_build_batch(robast_scene* const* scenes, int32_t n_scenes, const int6
       const robast_scene* sv = scenes[v];
       const int64_t cnt = offsets[v + 1] - offsets[v];
       const int G = sv->n_groups;
-      const double per_cell = (double)std::max<int64_t>(cnt, 1) / ((double)G * (double)sv->tuning.bin_target);
-      int nc = (int)std::floor(std::sqrt(std::max(1.0, per_cell)));
-      nc = std::max(1, std::min(nc, 1024));
-      geo[v] = BinGeom{sv->bin_z, sv->bin_x0, sv->bin_y0, (double)nc / sv->bin_side, nc, G, (uint32_t)base, 0u};
-      base += (int64_t)G * nc * nc;
+      const uint32_t dirs = bin_dirs(sv->tuning);
+      const int nc = bin_cells(cnt, G, sv->tuning.bin_target, dirs);
+      geo[v] = BinGeom{sv->bin_z, sv->bin_x0, sv->bin_y0, (double)nc / sv->bin_side, nc, G, (uint32_t)base, dirs};
+      base += (int64_t)G * dirs * nc * nc;
     }
     if (base <= kBinsMax) {
       b->bins = base;

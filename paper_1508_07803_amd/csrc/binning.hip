@@ -5,7 +5,9 @@
 // diverges far less than a wave of photons drawn at random over the
 // aperture.  The bundle is ordered by a key made of the photon's group and
 // the cell (row-major in a square grid) where its line crosses a reference
-// plane z = z_ref.  The permutation is kept: the trace numbers each photon by
+// plane z = z_ref, optionally preceded by the sector of the direction's
+// azimuth (photons that enter together but in different directions part at
+// once).  The permutation is kept: the trace numbers each photon by
 // its original index (its random draws and its result do not depend on the
 // order) and writes per-photon results back at that index.
 //
@@ -77,7 +79,15 @@ __device__ __forceinline__ uint32_t photon_key(const RaysView<T>& R, int64_t i, 
   const double fx = (ox - geo.x0) * geo.inv_cell, fy = (oy - geo.y0) * geo.inv_cell;
   const int ix = (int)fmin(fmax(fx, 0.0), (double)(geo.nc - 1));
   const int iy = (int)fmin(fmax(fy, 0.0), (double)(geo.nc - 1));
-  return geo.base + (g * (uint32_t)geo.nc + (uint32_t)iy) * (uint32_t)geo.nc + (uint32_t)ix;
+  uint32_t gs = g;
+  if (geo.dirs > 1u) {
+    // sector of atan2(dy, dx) in [-pi, pi]; single precision is enough, the
+    // order only groups photons
+    const float a = atan2f((float)dy, (float)dx) + 3.14159265f;
+    const int k = (int)(a * (float)geo.dirs * 0.159154943f);
+    gs = g * geo.dirs + (uint32_t)(k < 0 ? 0 : (k >= (int)geo.dirs ? (int)geo.dirs - 1 : k));
+  }
+  return geo.base + (gs * (uint32_t)geo.nc + (uint32_t)iy) * (uint32_t)geo.nc + (uint32_t)ix;
 }
 
 // (1) keys and per-tile coarse counts; cnt is bucket-major: cnt[c * n_tiles + tile]

@@ -8,11 +8,13 @@
 namespace robast {
 
 // Bin geometry: an nc x nc grid of cells of size 1 / inv_cell from (x0, y0)
-// on the plane z = z_ref, per photon group; the bins are numbered from base.
+// on the plane z = z_ref, per photon group and per sector of the direction's
+// azimuth (dirs sectors of 2 pi / dirs; 1: direction not used); the bins
+// are numbered from base.
 struct BinGeom {
   double z_ref, x0, y0, inv_cell;
   int nc, n_groups;
-  uint32_t base, pad;
+  uint32_t base, dirs;
 };
 
 // Photons of several bundles binned together (a batch of scene variants):

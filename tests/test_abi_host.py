@@ -23,7 +23,7 @@ def test_header_symbols_exported(rb):
     assert declared == set(rb.SYMBOLS)
     for name in declared:
         assert hasattr(rb.lib(), name), name
-    assert rb.lib().robast_abi_version() == 1
+    assert rb.lib().robast_abi_version() == rb.ABI_VERSION == 2
 
 
 def test_volume_desc_layout_matches_inputs(rb):

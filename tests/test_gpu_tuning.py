@@ -1,7 +1,7 @@
 """Launch tuning never changes a photon's result.
 
-Photon binning (counting sort by entrance cell), the cell size, the grid
-size and the workgroup size only change which lane traces which photon and
+Photon binning (counting sort by entrance cell, optionally by direction
+sector), the cell size, the grid size and the workgroup size only change which lane traces which photon and
 in which order: every per-photon record must be bit-identical across tunings, group
 sums and gradients equal up to FP64 summation order (1e-12 / 1e-9
 relative).  The binned path is also what the parity tests against the
@@ -21,7 +21,10 @@ TUNINGS = [dict(bin_photons=0, waves_mult=1),
            dict(bin_photons=1, waves_mult=1, bin_target=16),
            dict(bin_photons=1, waves_mult=16),
            dict(bin_photons=1, waves_mult=4, block=64),
-           dict(bin_photons=0, waves_mult=2, block=128),]
+           dict(bin_photons=0, waves_mult=2, block=128),
+           dict(bin_photons=1, waves_mult=4, bin_target=32, bin_dirs=16),
+           dict(bin_photons=1, waves_mult=4, bin_target=8, bin_dirs=64),
+           dict(bin_photons=1, waves_mult=4, bin_dirs=4),]
 
 
 @pytest.fixture(scope="module")
@@ -97,10 +100,10 @@ def test_autotune_keeps_results(rb):
 def test_tuning_rejects_out_of_range(rb):
     dev = rb.Scene(scenes.single_mirror())
     for bad in (dict(bin_target=1 << 20), dict(waves_mult=0), dict(waves_mult=65), dict(bin_target=0),
-                dict(block=96), dict(block=512)):
+                dict(block=96), dict(block=512), dict(bin_dirs=2), dict(bin_dirs=128)):
         with pytest.raises(rb.RobastError):
             dev.set_tuning(**bad)
-    assert dev.tuning == dict(bin_photons=1, bin_target=128, waves_mult=4, block=256)
+    assert dev.tuning == dict(bin_photons=1, bin_target=128, waves_mult=4, block=256, bin_dirs=1)
 
 
 def test_kept_order_reused_by_backward(rb):
