@@ -80,14 +80,16 @@ __device__ __forceinline__ void grad_end(const double* gacc, const GradLds& G, c
   }
 }
 
-// FP32 kernels with up to 16 events are held to 3 waves per SIMD (<= 168
-// VGPRs, no spills; the unconstrained allocation gives 2).  With `list` the
+// FP32 kernels with up to 32 events are held to 3 waves per SIMD (<= 168
+// VGPRs; the unconstrained allocation gives 2): at 16 events this needs no
+// spills, at 32 (the concentrator) the extra wave is worth its spills
+// (adjoint 99 -> 89 ms on 91 x 1e6 photons).  With `list` the
 // kernel takes only the photons at the positions list[0 .. *count) (those
 // whose path record was too long); otherwise every photon of the bundle.
 // SH (all kernels here): the shape set compiled in, as for the trace.
 template <typename T, int MAXE, bool USE_LDS, int SH>
 __global__ void __launch_bounds__(kBlockAdj)
-__attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && MAXE <= 16) ? 3 : 1, 8)))
+__attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && MAXE <= 32) ? 3 : 1, 8)))
 k_backward(const SceneView<T>* Sp, RaysView<T> R, int64_t n, AdjView A, GradLds G, const uint32_t* list,
            const uint32_t* count) {
   extern __shared__ __align__(16) char lds[];
