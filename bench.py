@@ -331,8 +331,11 @@ def run_config(args, torch, rb, scenes, sc, npf, objective, cpu_per_group, descr
     # launch tuning from the autotuner on every photon of every 8th group
     # (each group at its full density, so the binning grid is the same)
     t0 = time.time()
-    sample = (rays["group"] % 8) == 0
-    tuning = dev.autotune({k: v[sample].contiguous() for k, v in rays.items()})
+    if args.config_tuning:
+        tuning = dev.set_tuning(**json.loads(args.config_tuning))
+    else:
+        sample = (rays["group"] % 8) == 0
+        tuning = dev.autotune({k: v[sample].contiguous() for k, v in rays.items()})
     print(f"[bench] {sc.name}: autotuned {tuning} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     sums = dev.new_sums()
     fig = torch.zeros(sc.n_groups * rb.FIGURE_STRIDE, dtype=torch.float64, device="cuda")
@@ -602,6 +605,9 @@ def main():
                     help="skip the single-mirror, Davies-Cotton and concentrator sections")
     ap.add_argument("--configs", default="single_mirror,davies_cotton,hex_concentrator",
                     help="which of those sections to run (comma-separated)")
+    ap.add_argument("--config-tuning", default=None,
+                    help="JSON launch tuning for the config sections instead of the autotuner's "
+                         "(for profiling runs), e.g. '{\"bin_target\": 32, \"bin_dirs\": 4}'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--sweep-steps", type=int, default=20)
