@@ -315,7 +315,7 @@ def run_config(args, torch, rb, scenes, sc, npf, objective, cpu_per_group, descr
     """One config's step on the device: binning + forward trace with group
     sums + figures + adjoint of the objective (objective: "rms" or "eff",
     the mean over the groups), under the launch tuning the autotuner picks
-    on every 8th group of the bundle, per-phase times from HIP events, the roofline
+    on every 4th group of the bundle, per-phase times from HIP events, the roofline
     of both kernels from the reference tracer's event log, and the CPU
     baseline."""
     import oracle
@@ -328,13 +328,13 @@ def run_config(args, torch, rb, scenes, sc, npf, objective, cpu_per_group, descr
     torch.cuda.synchronize()
     print(f"[bench] {sc.name}: {n:.3e} photons generated on the device in {time.time() - t0:.1f}s",
           file=sys.stderr, flush=True)
-    # launch tuning from the autotuner on every photon of every 8th group
+    # launch tuning from the autotuner on every photon of every 4th group
     # (each group at its full density, so the binning grid is the same)
     t0 = time.time()
     if args.config_tuning:
         tuning = dev.set_tuning(**json.loads(args.config_tuning))
     else:
-        sample = (rays["group"] % 8) == 0
+        sample = (rays["group"] % 4) == 0
         tuning = dev.autotune({k: v[sample].contiguous() for k, v in rays.items()})
     print(f"[bench] {sc.name}: autotuned {tuning} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     sums = dev.new_sums()

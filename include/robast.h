@@ -356,7 +356,7 @@ int robast_set_tuning(robast_scene* scene, const robast_tuning* tuning);
  * scratch) under candidate tunings (binning off; binning with 32, 128 or 512
  * photons per cell; grid multiplier 1, 4 or 8; workgroups of 128 or 256
  * threads; then, with the best grid multiplier and workgroup size so far,
- * 4 or 16 direction sectors at 32 or 128 photons per cell), times each with
+ * 4 or 16 direction sectors at 16, 32 or 128 photons per cell), times each with
  * HIP events on the stream, keeps the fastest in the scene and returns it in
  * *best (may be NULL).  Synchronous; allocates;
  * EINVAL as robast_trace or n < 1.  Iteration caps of the root solvers are

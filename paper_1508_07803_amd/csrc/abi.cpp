@@ -1580,7 +1580,7 @@ int robast_autotune(robast_scene* s, const robast_rays* rays, int64_t n, robast_
   // direction sectors, with the launch shape found so far
   const robast_tuning shape = win;
   for (uint32_t dirs : {4u, 16u})
-    for (uint32_t target : {32u, 128u}) time_one(robast_tuning{1u, target, shape.waves_mult, shape.block, dirs});
+    for (uint32_t target : {16u, 32u, 128u}) time_one(robast_tuning{1u, target, shape.waves_mult, shape.block, dirs});
   s->tuning = (e == hipSuccess && !rc) ? win : saved;
   apply_tuning(s);
   if (e0) (void)hipEventDestroy(e0);
