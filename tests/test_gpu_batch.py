@@ -56,15 +56,20 @@ def as_numpy(hits, sl):
 
 
 # small bundles run unbinned; above 32768 photons the batch bins per variant
-COUNTS = {"unbinned": [3001, 0, 1, 2048, 4097], "binned": [40000, 0, 1, 30000, 50001]}
+COUNTS = {"unbinned": [3001, 0, 1, 2048, 4097], "binned": [40000, 0, 1, 30000, 50001],
+          "binned_dirs": [40000, 0, 1, 30000, 50001]}
 
 
 @pytest.mark.parametrize("kind", sorted(COUNTS))
 def test_batch_equals_per_variant_bitwise(rb, kind):
     """Ragged counts (0, 1, chunk multiples and tails), chunk smaller than a
-    variant, mixed DC / SC variants: every photon identical to the plain call."""
+    variant, mixed DC / SC variants, binning by entrance cell or also by
+    direction sector: every photon identical to the plain call."""
     variants = small_sweep()
     devs = [rb.Scene(v) for v in variants]
+    if kind == "binned_dirs":
+        for d in devs:
+            d.set_tuning(bin_dirs=16, bin_target=16)
     counts = COUNTS[kind]
     chunk = 1024
     rays, parts = concat_rays(rb, devs, counts)

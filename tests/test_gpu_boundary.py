@@ -105,3 +105,53 @@ def test_boundary_gradient_arguments(rb):
     lam = torch.full_like(rays["ox"], 400e-9)
     with pytest.raises(rb.RobastError):
         dev.boundary_grad(dict(rays, lam=lam), sums, cot, g)
+
+
+def test_boundary_gradient_binned_and_interleaved_with_backward(rb):
+    """The boundary gradient over the binned order equals the one over the
+    caller's order (up to FP64 summation order), and calling it between a
+    trace that keeps its order and the backward call, with the same photons
+    or with other ones, leaves the backward's gradient unchanged."""
+    sc = scenes.hex_concentrator(angles_deg=ANGLES, control=BASE)
+    dev = rb.Scene(sc)
+    parts = [scenes.device_rays(sc, 40_000, seed=sc.seed + 1000 * g, group=g) for g in range(sc.n_groups)]
+    rays = {k: torch.cat([p[k] for p in parts]) for k in parts[0]}
+    other = {k: v.flip(0).contiguous() for k, v in rays.items()}
+    ceta = torch.full((sc.n_groups,), 1.0 / sc.n_groups, dtype=torch.float64, device="cuda")
+    cot = torch.zeros(sc.n_groups, 2, dtype=torch.float64, device="cuda")
+    cot[:, 1] = 1.0 / sc.n_groups
+    P = len(sc.params)
+
+    def boundary(tuning):
+        dev.set_tuning(**tuning)
+        sums = dev.new_sums()
+        dev.trace(rays, sums=sums)
+        g = torch.zeros(P, dtype=torch.float64, device="cuda")
+        dev.boundary_grad(rays, sums, ceta, g, band=0.02)
+        return g
+
+    g_plain = boundary(dict(bin_photons=0))
+    for t in (dict(bin_photons=1, bin_dirs=1), dict(bin_photons=1, bin_dirs=16, bin_target=16)):
+        g = boundary(t)
+        assert torch.allclose(g, g_plain, rtol=1e-9, atol=1e-12 * float(g_plain.abs().max())), t
+    assert float(g_plain.abs().max()) > 0
+
+    dev.set_tuning(bin_photons=1, bin_dirs=1)
+    grads = []
+    for between in (None, rays, other):
+        sums = dev.new_sums()
+        dev.trace(rays, sums=sums, keep_order=True)
+        if between is not None:
+            s2 = dev.new_sums()
+            if between is other:
+                dev.trace(other, sums=s2)
+            else:
+                s2 = sums
+            gb = torch.zeros(P, dtype=torch.float64, device="cuda")
+            dev.boundary_grad(between, s2, ceta, gb, band=0.02)
+        g = torch.zeros(P, dtype=torch.float64, device="cuda")
+        dev.backward(rays, sums, cot, g)
+        torch.cuda.synchronize()
+        grads.append(g)
+    for g in grads[1:]:
+        assert torch.allclose(g, grads[0], rtol=1e-9, atol=1e-12 * float(grads[0].abs().max()))
