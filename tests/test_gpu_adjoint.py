@@ -6,7 +6,9 @@ themselves pinned to central finite differences of forced sequences and to a
 closed-form derivative (tests/test_oracle_pins.py).  Bar per component:
 |g_gpu - g_ref| <= 1e-3 * max(|g_ref|, floor * max|g_ref|), with floor 1e-3
 for FP64 scenes and 1e-2 for FP32 scenes, whose focal positions carry FP32
-rounding into the centroid-subtracted cotangents of small components.
+rounding into the centroid-subtracted cotangents of small components; FP32
+components down to 1e-3 of the largest are held to 3e-3 relative as well
+(measured worst: 1.4e-3, a primary coefficient of the small SC).
 """
 import numpy as np
 import pytest
@@ -57,6 +59,11 @@ def check(g, ref, floor, names):
     err = np.abs(g - ref) / np.maximum(np.abs(ref), floor * scale)
     worst = int(np.argmax(err))
     assert err.max() <= 1e-3, f"{names[worst]}: gpu {g[worst]:.6e} ref {ref[worst]:.6e} (rel {err.max():.2e})"
+    if floor > 1e-3:
+        # the smaller components of FP32 scenes, to a wider bar
+        err2 = np.abs(g - ref) / np.maximum(np.abs(ref), 1e-3 * scale)
+        w2 = int(np.argmax(err2))
+        assert err2.max() <= 3e-3, f"{names[w2]}: gpu {g[w2]:.6e} ref {ref[w2]:.6e} (rel {err2.max():.2e})"
     return err.max()
 
 
