@@ -24,12 +24,13 @@ __global__ void k_bnd_coef(const double* sums, const double* cot, double* w, int
   w[g] = nl > 0.0 ? cot[g] / (nl * band) : 0.0;
 }
 
-// Held to 3 waves per SIMD (<= 168 VGPRs, the rest spilled): the
-// unconstrained allocation takes 256 registers and runs one wave per SIMD,
-// which leaves the latency of its searches and replays exposed (measured
-// twice as slow on the concentrator; 2 and 4 waves were slower than 3).
+// The FP32 kernel is held to 3 waves per SIMD (<= 168 VGPRs, the rest
+// spilled): the unconstrained allocation takes 256 registers and runs one
+// wave per SIMD, which leaves the latency of its searches and replays
+// exposed (measured twice as slow on the concentrator; 2 and 4 waves were
+// slower than 3).  The FP64 kernel keeps the compiler's allocation.
 template <typename T, bool USE_LDS>
-__global__ void __launch_bounds__(kBlockBnd) __attribute__((amdgpu_waves_per_eu(3, 8))) k_boundary(const SceneView<T>* Sp, RaysView<T> R, int64_t n, BndView B) {
+__global__ void __launch_bounds__(kBlockBnd) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1, 8))) k_boundary(const SceneView<T>* Sp, RaysView<T> R, int64_t n, BndView B) {
   extern __shared__ __align__(16) char lds[];
   const SceneView<T> S = *Sp;
   B.tilt = S.tilt;
