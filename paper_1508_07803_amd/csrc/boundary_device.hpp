@@ -175,23 +175,38 @@ __device__ __forceinline__ bool replay_event(const SceneView<T>& L, uint32_t cod
 }
 
 // Reverse sweep seeded at event e0 (Xb: cotangent of its hit point, db: of
-// its outgoing direction) down to the initial ray; the states entering each
-// event are replayed from the start.  On return Xb and db hold the
-// cotangents of the initial origin and direction.  A sink without an array
-// (acc null) collects no parameter partials.
-template <typename T, int SH>
+// its outgoing direction) down to the initial ray.  One forward replay keeps
+// the state entering each event and its root in a lane-local stack (linear
+// in e0; replaying from the start for every event would be quadratic), then
+// the events are swept in reverse.  On return Xb and db hold the cotangents
+// of the initial origin and direction; if the recorded sequence no longer
+// holds, nothing is changed.  A sink without an array (acc null) collects
+// no parameter partials.
+template <typename T, int MAXE, int SH>
 __device__ __forceinline__ void sweep_from(const SceneView<T>& L, const DTilt* tilt, GradSink& gs, V3<T> o0, V3<T> d0,
                                            const uint32_t* codes, int e0, V3<double>& Xb, V3<double>& db,
                                            double lam) {
-  for (int e = e0; e >= 0; --e) {
-    ReplayState st = {{(double)o0.x, (double)o0.y, (double)o0.z}, {(double)d0.x, (double)d0.y, (double)d0.z}, 1.0,
-                      -1, -1, 0};
+  if (e0 < 0 || e0 >= MAXE) return;
+  V3<double> O[MAXE], D[MAXE];
+  double tr[MAXE], sr[MAXE];
+  ReplayState st = {{(double)o0.x, (double)o0.y, (double)o0.z}, {(double)d0.x, (double)d0.y, (double)d0.z}, 1.0,
+                    -1, -1, 0};
+  for (int e = 0; e <= e0; ++e) {
+    O[e] = st.O;
+    D[e] = st.d;
     double t = 0.0, s = 0.0;
-    for (int j = 0; j < e; ++j)
-      if (!replay_event<T, SH>(L, codes[j], st, lam, t, s)) return;
+    if (e < e0) {
+      if (!replay_event<T, SH>(L, codes[e], st, lam, t, s)) return;
+    } else {
+      const int vid = (int)(codes[e] >> 8), face = (int)((codes[e] >> 4) & 15u);
+      if (!replay_root<T, SH>(L, vid, face, st.O, st.d, st.pv, st.pf, st.ps, t, s)) return;
+    }
+    tr[e] = t;
+    sr[e] = s;
+  }
+  for (int e = e0; e >= 0; --e) {
     const int vid = (int)(codes[e] >> 8), face = (int)((codes[e] >> 4) & 15u), act = (int)(codes[e] & 15u);
-    if (!replay_root<T, SH>(L, vid, face, st.O, st.d, st.pv, st.pf, st.ps, t, s)) return;
-    event_adjoint<double, T, SH>(L.vol[vid], tilt + vid, face, act, st.O, st.d, t, s, Xb, db, gs,
+    event_adjoint<double, T, SH>(L.vol[vid], tilt + vid, face, act, O[e], D[e], tr[e], sr[e], Xb, db, gs,
                                  lens_index<SH>(L.vol[vid], lam));
   }
 }
@@ -268,7 +283,7 @@ __device__ __forceinline__ void boundary_photon(const SceneView<T>& L, const Ray
       // band); the outside one lies 2 push beyond it.
       V3<double> G = E.gX, Gd = {0.0, 0.0, 0.0};
       GradSink none{nullptr};
-      sweep_from<T, SH>(L, B.tilt, none, o0, d0, codes, e, G, Gd, lam);
+      sweep_from<T, MAXE, SH>(L, B.tilt, none, o0, d0, codes, e, G, Gd, lam);
       const double gg = dot(G, G);
       const V3<double> D0 = {(double)d0.x, (double)d0.y, (double)d0.z};
       V3<double> Oin = {(double)o0.x, (double)o0.y, (double)o0.z};
@@ -290,7 +305,7 @@ __device__ __forceinline__ void boundary_photon(const SceneView<T>& L, const Ray
           if (v.sparam >= 0 && v.shape == HEXCONE)
             for (int k = 0; k < 4; ++k) gs.add(v.sparam + k, c * E.gp[k]);
           V3<double> Xb = scl(c, E.gX), db = {0.0, 0.0, 0.0};
-          sweep_from<T, SH>(L, B.tilt, gs, o0, d0, codes, e, Xb, db, lam);
+          sweep_from<T, MAXE, SH>(L, B.tilt, gs, o0, d0, codes, e, Xb, db, lam);
         }
       }
     }
@@ -329,7 +344,7 @@ __device__ __forceinline__ void boundary_photon(const SceneView<T>& L, const Ray
             // d delta / d d_in = +-(dR/dcos_i) (-n_o): seeded on the outgoing
             // direction of the previous event
             V3<double> Xb = {0.0, 0.0, 0.0}, db = scl(-(refl ? 1.0 : -1.0) * c * fresnel_dR(ci, n1, n2), no);
-            sweep_from<T, SH>(L, B.tilt, gs, o0, d0, codes, e - 1, Xb, db, lam);
+            sweep_from<T, MAXE, SH>(L, B.tilt, gs, o0, d0, codes, e - 1, Xb, db, lam);
           }
         }
       }
