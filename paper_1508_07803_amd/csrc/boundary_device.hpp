@@ -16,9 +16,10 @@
 // per launched photon, where f_own - f_other is the jump of the fate at the
 // edge: the fates of the photon moved to just inside and just outside it
 // (its initial origin shifted along the gradient of delta, so that its
-// whole path up to the event moves with it, and traced again with the same
-// draws; comparing two photons a hair apart keeps later, unrelated edges
-// out of the difference), or at a Fresnel decision the photon's own fate
+// whole path up to the event moves with it: replayed along the recorded
+// sequence up to the event and traced on from there with the same draws;
+// comparing two photons a hair apart keeps earlier and later, unrelated
+// edges out of the difference), or at a Fresnel decision the photon's own fate
 // and that of the other decision; sides' is 1 for edges whose other side
 // also produces such events (seams, exit rim and aperture edge, Fresnel
 // decisions) and 2 for an
@@ -243,6 +244,21 @@ __device__ __forceinline__ PhotonState state_at(const ReplayState& st, int k, ui
   return p;
 }
 
+// Fate of the photon started from origin O (direction D): its recorded
+// sequence replayed up to event e (exclusive; no search, the same actions,
+// so the same draws), then traced on from there.  If the sequence no longer
+// holds before e, the photon is traced from its start instead.
+template <typename T, int SH>
+__device__ __forceinline__ int fate_from(const SceneView<T>& L, const uint32_t* codes, int e, V3<double> O,
+                                         V3<double> D, uint64_t id, double lam) {
+  const ReplayState s0 = {O, D, 1.0, -1, -1, 0};
+  ReplayState st = s0;
+  double t = 0.0, s = 0.0;
+  for (int j = 0; j < e; ++j)
+    if (!replay_event<T, SH>(L, codes[j], st, lam, t, s)) return finish_fate<T, SH>(L, state_at<T, SH>(s0, 0, id, lam));
+  return finish_fate<T, SH>(L, state_at<T, SH>(st, e, id, lam));
+}
+
 // Boundary terms of one photon (see the top of this file).  f_own: the
 // photon's own fate, used at Fresnel decisions.
 template <typename T, int MAXE, int SH>
@@ -297,9 +313,8 @@ __device__ __forceinline__ void boundary_photon(const SceneView<T>& L, const Ray
       ok = ok && dabs(dcur - B.push) < 0.5 * B.push;
       if (ok) {
         const V3<double> Oout = fma3(-2.0 * B.push / gg, G, Oin);
-        ReplayState sp = {Oin, D0, 1.0, -1, -1, 0}, sm = {Oout, D0, 1.0, -1, -1, 0};
-        const double f_in = finish_fate<T, SH>(L, state_at<T, SH>(sp, 0, id, lam)) == FOCUSED ? 1.0 : 0.0;
-        const double f_out = finish_fate<T, SH>(L, state_at<T, SH>(sm, 0, id, lam)) == FOCUSED ? 1.0 : 0.0;
+        const double f_in = fate_from<T, SH>(L, codes, e, Oin, D0, id, lam) == FOCUSED ? 1.0 : 0.0;
+        const double f_out = fate_from<T, SH>(L, codes, e, Oout, D0, id, lam) == FOCUSED ? 1.0 : 0.0;
         const double c = (E.sides == 1 ? 2.0 : 1.0) * w * (f_in - f_out);
         if (c != 0.0) {
           if (v.sparam >= 0 && v.shape == HEXCONE)
